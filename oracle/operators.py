@@ -1,0 +1,540 @@
+"""Flux-limited NRD residual, its Jacobian action and its transpose.
+
+Definitions (paper Sec. 3.1-3.3 and 4.1):
+
+* E_t - div(D_E grad E) =  sigma (T^4 - E),  T_t - div(D_T grad T) = -sigma (T^4 - E),
+  sigma = z^3 / T^3, D_T = kappa T^(5/2)                    (eqs. E_td, T_td, sigma)
+* cell balance with face fluxes D (u_b - u_a) / h          (eqs. E_int, diffusion_coeffs)
+* face temperature T_f = (T_a + T_b) / 2; harmonic face coefficient of
+  1/(3 sigma) at T_f; Wilson limiter with the face-normal |dE| / (h E_f)
+* Marshak (Robin) boundary 1/2 n.D grad E + E/4 = R, not flux limited, with
+  D = 1/(3 sigma) of the boundary cell                       (eq. robinbc)
+* zero-flux faces for E elsewhere and for T everywhere       (eq. bcs)
+* coarse-fine flux matching: the coarse flux through a face shared with a
+  finer level is replaced by the mean of the fine fluxes (Sec. 3.2.1)
+* BDF residual F(u) = c0 u - b - dt f(u)                  (eqs. bdf2, be, nonlinearsystem)
+
+Readings (the paper is ambiguous):
+* the printed face pair (D_r, then 2 D_r / (1 + D_r g)) is read as the true
+  harmonic mean D_h = 2 T_f^3 / (3 (z_a^3 + z_b^3)) limited as
+  D_h / (1 + lam D_h g) with lam = 1 (the Wilson form of Sec. 3.1); lam = 1/2
+  reproduces the printed pair literally;
+* face D_T = kappa T_f^(5/2) with the arithmetic face temperature;
+* Robin ghost from the discrete boundary relation, giving the inflow flux
+  q = 2 D_b (4 R - E_c) / (4 D_b + h) into the boundary cell;
+* the analytic derivative of |x| at 0 is taken as 0.
+
+Parity status: the face/residual formulas are pinned by special cases
+(gradient-free limit, equilibrium, textbook Laplacian), the discrete energy
+identity, mirror symmetry and second-order MMS convergence; the JVP by
+brute-force finite differences; the VJP by the dot-product identity and
+finite differences in z.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .hierarchy import Hierarchy
+
+
+# ---------------------------------------------------------------------------
+# slicing helpers: faces of a patch along axis d
+# ---------------------------------------------------------------------------
+
+def face_slices(d, n):
+    """(lower-cell, upper-cell) ghosted slices over the n_d + 1 faces along
+    d, interior in the tangential directions."""
+    lo = [slice(1, -1)] * 3
+    up = [slice(1, -1)] * 3
+    lo[d] = slice(0, int(n[d]) + 1)
+    up[d] = slice(1, int(n[d]) + 2)
+    return tuple(lo), tuple(up)
+
+
+def face_index(d, idx):
+    s = [slice(None)] * 3
+    s[d] = idx
+    return tuple(s)
+
+
+def cell_layer(d, idx):
+    """Ghosted slice of interior layer idx (0-based interior) along d."""
+    s = [slice(1, -1)] * 3
+    s[d] = idx + 1
+    return tuple(s)
+
+
+# ---------------------------------------------------------------------------
+# face formulas
+# ---------------------------------------------------------------------------
+
+def face_coeffs(Ea, Eb, Ta, Tb, z3a, z3b, h, kappa, lam=1.0):
+    """Limited radiation coefficient D_E and conduction coefficient D_T on a
+    face between lower cell a and upper cell b."""
+    Tf = 0.5 * (Ta + Tb)
+    Zf = z3a + z3b
+    Dh = 2.0 * Tf**3 / (3.0 * Zf)
+    g = np.abs(Eb - Ea) / (0.5 * h * (Ea + Eb))
+    DE = Dh / (1.0 + lam * Dh * g)
+    DT = kappa * Tf**2.5
+    return DE, DT
+
+
+def face_flux(Ea, Eb, Ta, Tb, z3a, z3b, h, kappa, lam=1.0):
+    """Flux densities D_E dE/dx and D_T dT/dx through a face (lower a, upper b)."""
+    DE, DT = face_coeffs(Ea, Eb, Ta, Tb, z3a, z3b, h, kappa, lam)
+    return DE * (Eb - Ea) / h, DT * (Tb - Ta) / h
+
+
+def face_flux_tangent(Ea, Eb, Ta, Tb, z3a, z3b, dEa, dEb, dTa, dTb, h, kappa,
+                      lam=1.0):
+    """Directional derivative of face_flux along (dE, dT)."""
+    Tf = 0.5 * (Ta + Tb)
+    dTf = 0.5 * (dTa + dTb)
+    Zf = z3a + z3b
+    Dh = 2.0 * Tf**3 / (3.0 * Zf)
+    dDh = 3.0 * Dh * dTf / Tf
+    dE = Eb - Ea
+    ddE = dEb - dEa
+    S = Ea + Eb
+    dS = dEa + dEb
+    g = np.abs(dE) / (0.5 * h * S)
+    dg = np.sign(dE) * ddE / (0.5 * h * S) - g * dS / S
+    den = 1.0 + lam * Dh * g
+    DE = Dh / den
+    dDE = (dDh - lam * Dh**2 * dg) / den**2
+    DT = kappa * Tf**2.5
+    dDT = 2.5 * DT * dTf / Tf
+    dT = Tb - Ta
+    ddT = dTb - dTa
+    return (dDE * dE + DE * ddE) / h, (dDT * dT + DT * ddT) / h
+
+
+def robin_D(Tc, z3c):
+    """Unlimited boundary coefficient 1/(3 sigma) of the boundary cell."""
+    return Tc**3 / (3.0 * z3c)
+
+
+def robin_q(Ec, Tc, z3c, R, h):
+    """Inflow flux density through a Marshak face into the boundary cell."""
+    Db = robin_D(Tc, z3c)
+    return 2.0 * Db * (4.0 * R - Ec) / (4.0 * Db + h)
+
+
+def robin_q_tangent(Ec, Tc, z3c, dEc, dTc, R, h):
+    Db = robin_D(Tc, z3c)
+    dDb = 3.0 * Db * dTc / Tc
+    den = 4.0 * Db + h
+    return -2.0 * Db / den * dEc + 2.0 * (4.0 * R - Ec) * h / den**2 * dDb
+
+
+# ---------------------------------------------------------------------------
+# generic flux-form operator on the composite grid
+# ---------------------------------------------------------------------------
+
+def is_physical(H, p, d, s):
+    N = H.N(p.level)
+    return (p.lo[d] == 0) if s == 0 else (p.hi[d] == N[d])
+
+
+def cf_faces(H, p, d):
+    """Faces of patch p along d that separate a non-covered interior cell of
+    p from a covered coarse cell.  Returns a list of
+    (face_idx[m], tangential local (m, 2), covered_side) with covered_side 1
+    when the covered cell is the upper one."""
+    if p.level + 1 >= H.nlev:
+        return []
+    n = p.n
+    cov = H.covered[p.pid]
+    t1, t2 = [a for a in range(3) if a != d]
+    out = []
+    # covered status of the cells just outside the patch along d
+    ext = []
+    for s in (0, 1):
+        lo = p.lo.copy()
+        hi = p.hi.copy()
+        if s == 0:
+            lo[d], hi[d] = p.lo[d] - 1, p.lo[d]
+        else:
+            lo[d], hi[d] = p.hi[d], p.hi[d] + 1
+        N = H.N(p.level)
+        shape = [int(v) for v in n]
+        shape[d] = 1
+        if lo[d] < 0 or hi[d] > N[d]:
+            ext.append(np.zeros(shape, dtype=bool))
+        else:
+            from .hierarchy import _box_cells
+            I = _box_cells(lo, hi)
+            ext.append(H.is_covered(p.level, I).reshape(shape, order="F"))
+    full = np.concatenate([ext[0], cov, ext[1]], axis=d)   # n_d + 2 along d
+    lo_sl, up_sl = [slice(None)] * 3, [slice(None)] * 3
+    lo_sl[d] = slice(0, int(n[d]) + 1)
+    up_sl[d] = slice(1, int(n[d]) + 2)
+    cl = full[tuple(lo_sl)]
+    cu = full[tuple(up_sl)]
+    f_idx = np.arange(int(n[d]) + 1)
+    shp = [1, 1, 1]
+    shp[d] = -1
+    fi = np.broadcast_to(f_idx.reshape(shp), cl.shape)
+    lower_interior = fi >= 1
+    upper_interior = fi <= int(n[d]) - 1
+    # covered above, non-covered interior below
+    mA = cu & ~cl & lower_interior
+    mB = cl & ~cu & upper_interior
+    for m, side in ((mA, 1), (mB, 0)):
+        if m.any():
+            idx = np.argwhere(m)
+            out.append((idx[:, d], idx[:, [t1, t2]], side))
+    return out
+
+
+def _fine_face_values(H, p, d, faces, side, fine_flux):
+    """Mean of the four fine fluxes on coarse faces of patch p."""
+    t1, t2 = [a for a in range(3) if a != d]
+    fidx, tloc, _ = faces
+    m = len(fidx)
+    acc = [np.zeros(m) for _ in fine_flux[p.pid][d]]
+    for a in (0, 1):
+        for b in (0, 1):
+            Ic = np.zeros((m, 3), dtype=np.int64)
+            Ic[:, d] = p.lo[d] + fidx - (0 if side == 1 else 1)   # covered cell
+            Ic[:, t1] = p.lo[t1] + tloc[:, 0]
+            Ic[:, t2] = p.lo[t2] + tloc[:, 1]
+            If = 2 * Ic
+            If[:, d] += 0 if side == 1 else 1
+            If[:, t1] += a
+            If[:, t2] += b
+            pid, loc = H.locate(p.level + 1, If)
+            assert np.all(pid >= 0)
+            for q in np.unique(pid):
+                mm = pid == q
+                ll = loc[mm]
+                fd = ll[:, d] + (0 if side == 1 else 1)   # local fine face index
+                for k in range(len(acc)):
+                    arr = fine_flux[q][d][k]
+                    idx = [None] * 3
+                    idx[d] = fd
+                    idx[t1] = ll[:, t1]
+                    idx[t2] = ll[:, t2]
+                    acc[k][mm] += arr[idx[0], idx[1], idx[2]]
+    return [a / 4.0 for a in acc]
+
+
+def composite_divergence(H, nout, flux_fn, robin_fn=None):
+    """Divergence of face fluxes on every patch with boundary handling and
+    coarse-fine flux matching.
+
+    flux_fn(p, d) -> list of nout flux arrays (n_d + 1 faces along d).
+    robin_fn(p, d, s) -> flux of output 0 through a Marshak face (tangential
+    array), or None.  Other physical faces carry zero flux.
+    Returns div[pid][k] (interior arrays).
+    """
+    fl = {}
+    for p in H.patches:
+        fl[p.pid] = []
+        for d in range(3):
+            phis = [np.array(a, dtype=np.float64) for a in flux_fn(p, d)]
+            for s in (0, 1):
+                if not is_physical(H, p, d, s):
+                    continue
+                fs = face_index(d, 0 if s == 0 else int(p.n[d]))
+                for k in range(nout):
+                    phis[k][fs] = 0.0
+                if robin_fn is not None and H.bc_E[2 * d + s] == 1:
+                    phis[0][fs] = robin_fn(p, d, s)
+            fl[p.pid].append(phis)
+    # coarse-fine flux matching
+    for p in H.patches:
+        for d in range(3):
+            for faces in cf_faces(H, p, d):
+                fidx, tloc, side = faces
+                vals = _fine_face_values(H, p, d, faces, side, fl)
+                t1, t2 = [a for a in range(3) if a != d]
+                idx = [None] * 3
+                idx[d] = fidx
+                idx[t1] = tloc[:, 0]
+                idx[t2] = tloc[:, 1]
+                for k in range(nout):
+                    fl[p.pid][d][k][idx[0], idx[1], idx[2]] = vals[k]
+    div = {}
+    for p in H.patches:
+        h = H.h(p.level)
+        out = [np.zeros(tuple(int(v) for v in p.n)) for _ in range(nout)]
+        for d in range(3):
+            n = int(p.n[d])
+            a = [slice(None)] * 3
+            b = [slice(None)] * 3
+            a[d] = slice(0, n)
+            b[d] = slice(1, n + 1)
+            for k in range(nout):
+                phi = fl[p.pid][d][k]
+                out[k] += (phi[tuple(b)] - phi[tuple(a)]) / h[d]
+        div[p.pid] = out
+    return div, fl
+
+
+# ---------------------------------------------------------------------------
+# state preparation
+# ---------------------------------------------------------------------------
+
+def ghosted_state(H: Hierarchy, E, T):
+    """Ghosted copies of per-patch interior E, T with covered cells
+    restricted and face ghosts filled."""
+    Eg = H.from_interior(E)
+    Tg = H.from_interior(T)
+    H.sync([Eg, Tg])
+    H.fill_ghosts([Eg, Tg])
+    return Eg, Tg
+
+
+def ghosted_z3(H: Hierarchy, z):
+    """z is given on every level (covered cells included); ghosts use the
+    same fill rules as the state; the cube is taken after the fill."""
+    zg = H.from_interior(z)
+    H.fill_ghosts([zg])
+    return [a**3 for a in zg]
+
+
+# ---------------------------------------------------------------------------
+# residual
+# ---------------------------------------------------------------------------
+
+def residual(H, E, T, z, bE, bT, dt, c0, lam=1.0, parts=False):
+    """F(u) = c0 u - b - dt f(u) on composite cells; covered cells -> 0."""
+    Eg, Tg = ghosted_state(H, E, T)
+    z3 = ghosted_z3(H, z)
+    kappa = H.kappa
+
+    def flux_fn(p, d):
+        lo, up = face_slices(d, p.n)
+        q = p.pid
+        return face_flux(Eg[q][lo], Eg[q][up], Tg[q][lo], Tg[q][up],
+                         z3[q][lo], z3[q][up], H.h(p.level)[d], kappa, lam)
+
+    def robin_fn(p, d, s):
+        q = p.pid
+        c = cell_layer(d, 0 if s == 0 else int(p.n[d]) - 1)
+        qf = robin_q(Eg[q][c], Tg[q][c], z3[q][c], H.robin_R[2 * d + s],
+                     H.h(p.level)[d])
+        return -qf if s == 0 else qf
+
+    div, fl = composite_divergence(H, 2, flux_fn, robin_fn)
+    FE, FT = [], []
+    for p in H.patches:
+        q = p.pid
+        e = Eg[q][1:-1, 1:-1, 1:-1]
+        t = Tg[q][1:-1, 1:-1, 1:-1]
+        zz = z3[q][1:-1, 1:-1, 1:-1]
+        S = zz / t**3 * (t**4 - e)
+        fe = c0 * e - bE[q] - dt * (div[q][0] + S)
+        ft = c0 * t - bT[q] - dt * (div[q][1] - S)
+        cov = H.covered[q]
+        fe[cov] = 0.0
+        ft[cov] = 0.0
+        FE.append(fe)
+        FT.append(ft)
+    if parts:
+        return FE, FT, dict(Eg=Eg, Tg=Tg, z3=z3, flux=fl, div=div)
+    return FE, FT
+
+
+def residual_scale(H, E, T, z, bE, bT, dt, c0, lam=1.0):
+    """Per-cell sum of magnitudes of the terms entering F (used to judge
+    entries near the T^4 - E cancellation)."""
+    Eg, Tg = ghosted_state(H, E, T)
+    z3 = ghosted_z3(H, z)
+    sE, sT = [], []
+    for p in H.patches:
+        q = p.pid
+        h = H.h(p.level)
+        fl = np.zeros(tuple(int(v) for v in p.n))
+        flT = np.zeros_like(fl)
+        for d in range(3):
+            lo, up = face_slices(d, p.n)
+            pe, pt = face_flux(Eg[q][lo], Eg[q][up], Tg[q][lo], Tg[q][up],
+                               z3[q][lo], z3[q][up], h[d], H.kappa, lam)
+            n = int(p.n[d])
+            a = [slice(None)] * 3
+            b = [slice(None)] * 3
+            a[d] = slice(0, n)
+            b[d] = slice(1, n + 1)
+            fl += (np.abs(pe[tuple(a)]) + np.abs(pe[tuple(b)])) / h[d]
+            flT += (np.abs(pt[tuple(a)]) + np.abs(pt[tuple(b)])) / h[d]
+            # boundary inflow magnitude bound (4R + E) / h
+            fl += 8.0 * max(H.robin_R) / h[d]
+        e = Eg[q][1:-1, 1:-1, 1:-1]
+        t = Tg[q][1:-1, 1:-1, 1:-1]
+        zz = z3[q][1:-1, 1:-1, 1:-1]
+        sig = zz / t**3
+        cpl = sig * (t**4 + np.abs(e))
+        sE.append(np.abs(c0 * e) + np.abs(bE[q]) + dt * (fl + cpl))
+        sT.append(np.abs(c0 * t) + np.abs(bT[q]) + dt * (flT + cpl))
+    return sE, sT
+
+
+# ---------------------------------------------------------------------------
+# analytic Jacobian action
+# ---------------------------------------------------------------------------
+
+def jvp(H, E, T, z, vE, vT, dt, c0, lam=1.0):
+    """J(u) v for F above; covered entries -> 0.  Restriction, ghost fill
+    and flux matching act on v exactly as on u (they are linear)."""
+    Eg, Tg = ghosted_state(H, E, T)
+    dEg, dTg = ghosted_state(H, vE, vT)
+    z3 = ghosted_z3(H, z)
+    kappa = H.kappa
+
+    def flux_fn(p, d):
+        lo, up = face_slices(d, p.n)
+        q = p.pid
+        return face_flux_tangent(Eg[q][lo], Eg[q][up], Tg[q][lo], Tg[q][up],
+                                 z3[q][lo], z3[q][up], dEg[q][lo], dEg[q][up],
+                                 dTg[q][lo], dTg[q][up], H.h(p.level)[d],
+                                 kappa, lam)
+
+    def robin_fn(p, d, s):
+        q = p.pid
+        c = cell_layer(d, 0 if s == 0 else int(p.n[d]) - 1)
+        dq = robin_q_tangent(Eg[q][c], Tg[q][c], z3[q][c], dEg[q][c], dTg[q][c],
+                             H.robin_R[2 * d + s], H.h(p.level)[d])
+        return -dq if s == 0 else dq
+
+    div, _ = composite_divergence(H, 2, flux_fn, robin_fn)
+    JE, JT = [], []
+    for p in H.patches:
+        q = p.pid
+        e = Eg[q][1:-1, 1:-1, 1:-1]
+        t = Tg[q][1:-1, 1:-1, 1:-1]
+        de = dEg[q][1:-1, 1:-1, 1:-1]
+        dtt = dTg[q][1:-1, 1:-1, 1:-1]
+        zz = z3[q][1:-1, 1:-1, 1:-1]
+        dS = zz * ((1.0 + 3.0 * e / t**4) * dtt - de / t**3)
+        je = c0 * de - dt * (div[q][0] + dS)
+        jt = c0 * dtt - dt * (div[q][1] - dS)
+        cov = H.covered[q]
+        je[cov] = 0.0
+        jt[cov] = 0.0
+        JE.append(je)
+        JT.append(jt)
+    return JE, JT
+
+
+# ---------------------------------------------------------------------------
+# transpose (gather over faces); single-level hierarchies
+# ---------------------------------------------------------------------------
+
+def _face_partials(Ea, Eb, Ta, Tb, z3a, z3b, h, kappa, lam):
+    """Partial derivatives of (Phi_E, Phi_T) w.r.t. the 6 face inputs."""
+    Tf = 0.5 * (Ta + Tb)
+    Zf = z3a + z3b
+    Dh = 2.0 * Tf**3 / (3.0 * Zf)
+    dE = Eb - Ea
+    S = Ea + Eb
+    g = np.abs(dE) / (0.5 * h * S)
+    sg = np.sign(dE)
+    den = 1.0 + lam * Dh * g
+    DE = Dh / den
+    dDh_dT = 1.5 * Dh / Tf                      # w.r.t. Ta or Tb
+    dDh_dz = -Dh / Zf                           # w.r.t. z3a or z3b
+    dg_dEb = sg / (0.5 * h * S) - g / S
+    dg_dEa = -sg / (0.5 * h * S) - g / S
+    dDE = lambda dDh, dg: (dDh - lam * Dh**2 * dg) / den**2
+    P = {}
+    P["E_Ea"] = dDE(0.0, dg_dEa) * dE / h - DE / h
+    P["E_Eb"] = dDE(0.0, dg_dEb) * dE / h + DE / h
+    P["E_T"] = dDE(dDh_dT, 0.0) * dE / h        # same for Ta and Tb
+    P["E_z"] = dDE(dDh_dz, 0.0) * dE / h        # same for z3a and z3b
+    DT = kappa * Tf**2.5
+    dT = Tb - Ta
+    c = 1.25 * DT / Tf * dT / h
+    P["T_Ta"] = c - DT / h
+    P["T_Tb"] = c + DT / h
+    return P
+
+
+def vjp(H, E, T, z, lE, lT, dt, c0, lam=1.0):
+    """lambda^T dF/du (E and T parts) and lambda^T dF/dz (per cell) for a
+    single-level hierarchy.  Ghost values are copies (physical or sibling),
+    so their sensitivities are scattered back to the copied cells."""
+    if H.nlev != 1:
+        raise NotImplementedError("transpose on refined hierarchies")
+    Eg, Tg = ghosted_state(H, E, T)
+    zg = H.from_interior(z)
+    H.fill_ghosts([zg])
+    z3 = [a**3 for a in zg]
+    aE = [np.zeros(p.gshape) for p in H.patches]
+    aT = [np.zeros(p.gshape) for p in H.patches]
+    aZ = [np.zeros(p.gshape) for p in H.patches]   # w.r.t. z^3
+    for p in H.patches:
+        q = p.pid
+        h = H.h(p.level)
+        lEg = np.zeros(p.gshape)
+        lTg = np.zeros(p.gshape)
+        lEg[1:-1, 1:-1, 1:-1] = lE[q]
+        lTg[1:-1, 1:-1, 1:-1] = lT[q]
+        for d in range(3):
+            lo, up = face_slices(d, p.n)
+            P = _face_partials(Eg[q][lo], Eg[q][up], Tg[q][lo], Tg[q][up],
+                               z3[q][lo], z3[q][up], h[d], H.kappa, lam)
+            muE = dt * (lEg[up] - lEg[lo]) / h[d]
+            muT = dt * (lTg[up] - lTg[lo]) / h[d]
+            for s in (0, 1):                       # physical faces: no flux
+                if is_physical(H, p, d, s):
+                    fs = face_index(d, 0 if s == 0 else int(p.n[d]))
+                    muE[fs] = 0.0
+                    muT[fs] = 0.0
+            aE[q][lo] += muE * P["E_Ea"]
+            aE[q][up] += muE * P["E_Eb"]
+            aT[q][lo] += muE * P["E_T"] + muT * P["T_Ta"]
+            aT[q][up] += muE * P["E_T"] + muT * P["T_Tb"]
+            aZ[q][lo] += muE * P["E_z"]
+            aZ[q][up] += muE * P["E_z"]
+            for s in (0, 1):                       # Marshak faces
+                if not (is_physical(H, p, d, s) and H.bc_E[2 * d + s] == 1):
+                    continue
+                c = cell_layer(d, 0 if s == 0 else int(p.n[d]) - 1)
+                Ec, Tc, zc = Eg[q][c], Tg[q][c], z3[q][c]
+                Db = robin_D(Tc, zc)
+                den = 4.0 * Db + h[d]
+                R = H.robin_R[2 * d + s]
+                dq_dE = -2.0 * Db / den
+                dq_dDb = 2.0 * (4.0 * R - Ec) * h[d] / den**2
+                # F_c gets -dt * q / h whichever side the face is on
+                w = -dt * lEg[c] / h[d]
+                aE[q][c] += w * dq_dE
+                aT[q][c] += w * dq_dDb * 3.0 * Db / Tc
+                aZ[q][c] += w * dq_dDb * (-Db / zc)
+        # cell terms
+        e = Eg[q][1:-1, 1:-1, 1:-1]
+        t = Tg[q][1:-1, 1:-1, 1:-1]
+        zz = z3[q][1:-1, 1:-1, 1:-1]
+        dS_dE = -zz / t**3
+        dS_dT = zz * (1.0 + 3.0 * e / t**4)
+        dS_dz = t - e / t**3
+        x = lT[q] - lE[q]                          # F_E has -dt S, F_T has +dt S
+        aE[q][1:-1, 1:-1, 1:-1] += c0 * lE[q] + dt * x * dS_dE
+        aT[q][1:-1, 1:-1, 1:-1] += c0 * lT[q] + dt * x * dS_dT
+        aZ[q][1:-1, 1:-1, 1:-1] += dt * x * dS_dz
+    # transpose of the ghost fill: scatter ghost sensitivities to sources
+    for p in H.patches:
+        for d in range(3):
+            for s in range(2):
+                G, gl, il, kind = H.ghost_kinds(p, d, s)
+                for acc in (aE, aT, aZ):
+                    g = acc[p.pid][gl[:, 0], gl[:, 1], gl[:, 2]]
+                    m = kind == 0
+                    np.add.at(acc[p.pid], (il[m, 0], il[m, 1], il[m, 2]), g[m])
+                    m = kind == 1
+                    if m.any():
+                        pid, loc = H.locate(p.level, G[m])
+                        for qq in np.unique(pid):
+                            mm = pid == qq
+                            ll = loc[mm] + 1
+                            np.add.at(acc[qq], (ll[:, 0], ll[:, 1], ll[:, 2]),
+                                      g[m][mm])
+                    acc[p.pid][gl[:, 0], gl[:, 1], gl[:, 2]] = 0.0
+    gE = [a[1:-1, 1:-1, 1:-1].copy() for a in aE]
+    gT = [a[1:-1, 1:-1, 1:-1].copy() for a in aT]
+    gz = [3.0 * zg[p.pid][1:-1, 1:-1, 1:-1]**2 * aZ[p.pid][1:-1, 1:-1, 1:-1]
+          for p in H.patches]
+    return gE, gT, gz

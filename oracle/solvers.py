@@ -1,0 +1,335 @@
+"""Krylov, Newton, time stepping and the discrete adjoint (paper Sec. 3.3-4.1).
+
+* Right-preconditioned GMRES on the Newton equations (Sec. 4.1-4.2), run as
+  flexible GMRES(m) -- it stores z_j = P^-1 v_j, which is the same method for
+  a fixed preconditioner -- with two passes of classical Gram-Schmidt and
+  Givens rotations; x0 = 0; stop when the least-squares residual estimate is
+  at most eta ||F|| (eq. inexactNewtoneqns).
+* Inexact Newton with Eisenstat-Walker forcing terms (Sec. 4.1).  Reading:
+  the book the paper points to is not available; the forcing sequence used
+  is eta_0 = 0.9, eta_k = max(min(eta_max, gamma r^2 [safeguarded by
+  gamma eta_{k-1}^2 when that exceeds 0.1]), 0.5 tau / ||F_k||) with
+  gamma = 0.9, eta_max = 0.9, r = ||F_k|| / ||F_{k-1}||, tau the stopping
+  threshold.
+* Positivity: the step length is halved until E and T stay positive
+  (Sec. 4.1 remark).
+* BDF1 for the first step and variable-step BDF2 afterwards (eqs. be, bdf2);
+  the generalised leapfrog predictor (eq. leapfrog) with the time derivative
+  taken from the previous step's BDF left-hand side (Remark 2) is the Newton
+  initial guess when it is positive.
+* The discrete adjoint of a BDF1 trajectory for J = sum of E over cells.
+
+Norms and inner products are volume weighted over composite (non-covered)
+cells: <x, y> = sum_c V_c (x_E y_E + x_T y_T).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import operators as ops
+from . import precond as pc
+
+
+class System:
+    """One problem: hierarchy, material field, options; compact vectors are
+    [E of all patches (x fastest) | T of all patches]."""
+
+    def __init__(self, H, z, lam=1.0, p2_mode="paper"):
+        self.H = H
+        self.z = [np.asarray(a, dtype=np.float64) for a in z]
+        self.lam = lam
+        self.p2_mode = p2_mode
+        self.nc = H.ncells()
+        w = []
+        for p in H.patches:
+            v = np.full(tuple(int(x) for x in p.n), H.volume(p.level))
+            v[H.covered[p.pid]] = 0.0
+            w.append(v.ravel(order="F"))
+        w = np.concatenate(w)
+        self.weight = np.concatenate([w, w])
+        self.composite = self.weight > 0
+
+    # -- layout -----------------------------------------------------------
+    def split(self, x):
+        n = self.nc
+        out = []
+        for part in (x[:n], x[n:]):
+            lst, o = [], 0
+            for p in self.H.patches:
+                m = int(np.prod(p.n))
+                lst.append(part[o:o + m].reshape(tuple(int(v) for v in p.n),
+                                                 order="F"))
+                o += m
+            out.append(lst)
+        return out
+
+    def join(self, E, T):
+        return np.concatenate([np.concatenate([a.ravel(order="F") for a in E]),
+                               np.concatenate([a.ravel(order="F") for a in T])])
+
+    def dot(self, x, y):
+        return float(np.sum(self.weight * x * y))
+
+    def norm(self, x):
+        return float(np.sqrt(self.dot(x, x)))
+
+    def sync(self, u):
+        E, T = self.split(u)
+        Eg = self.H.from_interior(E)
+        Tg = self.H.from_interior(T)
+        self.H.sync([Eg, Tg])
+        return self.join(self.H.interior(Eg), self.H.interior(Tg))
+
+    # -- operators --------------------------------------------------------
+    def residual(self, u, b, dt, c0):
+        E, T = self.split(u)
+        bE, bT = self.split(b)
+        FE, FT = ops.residual(self.H, E, T, self.z, bE, bT, dt, c0, self.lam)
+        return self.join(FE, FT)
+
+    def jvp(self, u, v, dt, c0):
+        E, T = self.split(u)
+        vE, vT = self.split(v)
+        JE, JT = ops.jvp(self.H, E, T, self.z, vE, vT, dt, c0, self.lam)
+        return self.join(JE, JT)
+
+    def vjp(self, u, lmb, dt, c0):
+        E, T = self.split(u)
+        lE, lT = self.split(lmb)
+        gE, gT, gz = ops.vjp(self.H, E, T, self.z, lE, lT, dt, c0, self.lam)
+        return self.join(gE, gT), np.concatenate([a.ravel(order="F") for a in gz])
+
+    def precond(self, u, beta):
+        E, T = self.split(u)
+        snap = pc.Snapshot(self.H, E, T, self.z, beta, self.lam, self.p2_mode)
+        mg = (pc.build_mg(self.H, snap, 0), pc.build_mg(self.H, snap, 1))
+
+        def apply(w):
+            wE, wT = self.split(w)
+            yE, yT = pc.precond_apply(self.H, snap, wE, wT, mg)
+            return self.join(yE, yT)
+
+        def apply_t(w):
+            wE, wT = self.split(w)
+            yE, yT = pc.precond_apply_transpose(self.H, snap, wE, wT, mg)
+            return self.join(yE, yT)
+
+        return apply, apply_t
+
+
+# ---------------------------------------------------------------------------
+# FGMRES(m) with CGS2
+# ---------------------------------------------------------------------------
+
+def givens(a, b):
+    if b == 0.0:
+        return 1.0, 0.0, a
+    r = np.sqrt(a * a + b * b)
+    return a / r, b / r, r
+
+
+def fgmres(matvec, precond, rhs, tol, dot, m=30, max_restarts=10):
+    """Solve A x = rhs to ||rhs - A x|| <= tol.  Returns (x, its, est)."""
+    x = np.zeros_like(rhs)
+    r = rhs.copy()
+    its = 0
+    est = np.sqrt(dot(r, r))
+    for cycle in range(max_restarts + 1):
+        beta0 = np.sqrt(dot(r, r))
+        est = beta0
+        if beta0 <= tol:
+            break
+        V = [r / beta0]
+        Z = []
+        Hm = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta0
+        k = 0
+        done = False
+        for j in range(m):
+            z = precond(V[j])
+            Z.append(z)
+            w = matvec(z)
+            h1 = np.array([dot(V[i], w) for i in range(j + 1)])
+            w = w - sum(h1[i] * V[i] for i in range(j + 1))
+            h2 = np.array([dot(V[i], w) for i in range(j + 1)])
+            w = w - sum(h2[i] * V[i] for i in range(j + 1))
+            col = np.zeros(m + 1)
+            col[:j + 1] = h1 + h2
+            hn = np.sqrt(dot(w, w))
+            col[j + 1] = hn
+            for i in range(j):
+                t = cs[i] * col[i] + sn[i] * col[i + 1]
+                col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1]
+                col[i] = t
+            cs[j], sn[j], col[j] = givens(col[j], col[j + 1])
+            col[j + 1] = 0.0
+            Hm[:, j] = col
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            its += 1
+            k = j + 1
+            est = abs(g[j + 1])
+            if hn == 0.0 or est <= tol:
+                done = True
+                break
+            V.append(w / hn)
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):
+            y[i] = (g[i] - Hm[i, i + 1:k] @ y[i + 1:k]) / Hm[i, i]
+        x = x + sum(y[i] * Z[i] for i in range(k))
+        if done:
+            break
+        r = rhs - matvec(x)
+    return x, its, est
+
+
+# ---------------------------------------------------------------------------
+# inexact Newton
+# ---------------------------------------------------------------------------
+
+class NewtonResult:
+    def __init__(self, u, converged, iters, krylov, fnorms, cuts):
+        self.u = u
+        self.converged = converged
+        self.iters = iters
+        self.krylov = krylov
+        self.fnorms = fnorms
+        self.cuts = cuts
+
+
+def newton(sys: System, u0, b, dt, c0, beta, rtol=1e-8, atol=1e-14, maxit=20,
+           m=30, max_restarts=10, eta_max=0.9, gamma=0.9):
+    u = u0.copy()
+    F = sys.residual(u, b, dt, c0)
+    fn = sys.norm(F)
+    stop = max(rtol * fn, atol)
+    fnorms = [fn]
+    krylov = []
+    cuts = 0
+    eta = eta_max
+    fn_old = fn
+    k = 0
+    while fn > stop and k < maxit:
+        if k > 0:
+            rat = fn / fn_old
+            enew = gamma * rat * rat
+            if gamma * eta * eta > 0.1:
+                enew = max(enew, gamma * eta * eta)
+            eta = min(enew, eta_max)
+            eta = max(eta, 0.5 * stop / fn)
+        P, _ = sys.precond(u, beta)
+        s, its, _ = fgmres(lambda v: sys.jvp(u, v, dt, c0), P, -F, eta * fn,
+                           sys.dot, m, max_restarts)
+        krylov.append(its)
+        lam = 1.0
+        ok = False
+        for _ in range(31):
+            trial = u + lam * s
+            if np.all(trial[sys.composite] > 0.0):
+                ok = True
+                break
+            lam *= 0.5
+            cuts += 1
+        if not ok:
+            return NewtonResult(u, False, k, krylov, fnorms, cuts)
+        u = sys.sync(trial)
+        fn_old = fn
+        F = sys.residual(u, b, dt, c0)
+        fn = sys.norm(F)
+        fnorms.append(fn)
+        k += 1
+    return NewtonResult(u, fn <= stop, k, krylov, fnorms, cuts)
+
+
+# ---------------------------------------------------------------------------
+# BDF stepping
+# ---------------------------------------------------------------------------
+
+def bdf_coefficients(dt, dt_prev):
+    """(c0, alpha) for BDF1 (dt_prev None) or variable-step BDF2."""
+    if dt_prev is None:
+        return 1.0, 0.0
+    a = dt / dt_prev
+    return (1.0 + 2.0 * a) / (1.0 + a), a
+
+
+class Stepper:
+    """Library-owned state u_n, u_{n-1}, dt_{n-1}, udot_n (eqs. be, bdf2,
+    leapfrog)."""
+
+    def __init__(self, sys: System, u0, bdf1_only=False, **newton_kw):
+        self.sys = sys
+        self.u = sys.sync(u0.copy())
+        self.u_prev = None
+        self.dt_prev = None
+        self.udot = None
+        self.bdf1_only = bdf1_only
+        self.kw = newton_kw
+        self.history = []
+
+    def rhs_and_guess(self, dt):
+        first = self.dt_prev is None or self.bdf1_only
+        if first:
+            c0, a = 1.0, 0.0
+            b = self.u.copy()
+            guess = self.u.copy()
+        else:
+            c0, a = bdf_coefficients(dt, self.dt_prev)
+            b = (1.0 + a) * self.u - (a * a / (1.0 + a)) * self.u_prev
+            guess = (self.u + (1.0 + a) * dt * self.udot
+                     - a * a * (self.u - self.u_prev))
+            if not np.all(guess[self.sys.composite] > 0.0):
+                guess = self.u.copy()
+            guess = self.sys.sync(guess)
+        beta = dt / c0
+        return c0, a, b, guess, beta
+
+    def step(self, dt):
+        c0, a, b, guess, beta = self.rhs_and_guess(dt)
+        res = newton(self.sys, guess, b, dt, c0, beta, **self.kw)
+        if not res.converged:
+            return res
+        self.udot = (c0 * res.u - b) / dt
+        self.u_prev = self.u
+        self.u = res.u
+        self.dt_prev = dt
+        self.history.append(res)
+        return res
+
+
+# ---------------------------------------------------------------------------
+# discrete adjoint of a BDF1 trajectory, J = sum of E over cells
+# ---------------------------------------------------------------------------
+
+def adjoint_gradient(sys: System, u0, dt, nsteps, tol=1e-11, newton_kw=None,
+                     m=30, max_restarts=20):
+    """dJ/dz for J = sum_c E_N(c) after nsteps BDF1 steps of size dt.
+
+    Forward: u_n solves F_n = u_n - u_{n-1} - dt f(u_n; z) = 0.  Reverse:
+    A_N^T l_N = dJ/du_N, A_n^T l_n = l_{n+1}; dJ/dz = -sum_n l_n^T dF_n/dz.
+    Every forward state is kept (the oracle does not checkpoint)."""
+    kw = dict(newton_kw or {})
+    st = Stepper(sys, u0, bdf1_only=True, **kw)
+    states = [st.u.copy()]
+    for _ in range(nsteps):
+        r = st.step(dt)
+        if not r.converged:
+            raise RuntimeError("forward solve failed")
+        states.append(st.u.copy())
+    nc = sys.nc
+    rhs = np.concatenate([np.ones(nc), np.zeros(nc)])
+    grad = np.zeros(nc)
+    euclid = lambda x, y: float(np.dot(x, y))
+    for n in range(nsteps, 0, -1):
+        u = states[n]
+        _, PT = sys.precond(u, dt)
+        mv = lambda v: sys.vjp(u, v, dt, 1.0)[0]
+        tol_abs = tol * np.sqrt(euclid(rhs, rhs))
+        lmb, _, _ = fgmres(mv, PT, rhs, tol_abs, euclid, m, max_restarts)
+        _, gz = sys.vjp(u, lmb, dt, 1.0)
+        grad -= gz
+        rhs = lmb
+    return grad, states
