@@ -1,0 +1,238 @@
+/*
+ * nrd.h -- C ABI of the MI355X library for the implicit AMR two-temperature
+ * non-equilibrium radiation diffusion hot path (Philip et al., "Dynamic
+ * Implicit 3D Adaptive Mesh Refinement for Non-Equilibrium Radiation
+ * Diffusion", arXiv:1302.6303).
+ *
+ * The library evaluates, on one GPU, the pieces of a Jacobian-free
+ * Newton-Krylov time step on a structured AMR hierarchy:
+ *   - the flux-limited residual F(u) = c0 u - b - dt f(u)  (Sec. 3.1-3.3),
+ *   - its Jacobian action and transpose                      (Sec. 4.1),
+ *   - the physics-based preconditioner P^-1 = P2^-1 P1^-1 with FAC V(1,0)
+ *     diffusion solves (Sec. 4.2-4.3, Alg. 1),
+ *   - the whole BDF1/BDF2 implicit step with inexact Newton + FGMRES.
+ *
+ * Conventions (every call):
+ *   - Return value: NRD_OK (0) or a negative nrd_status.  The message of the
+ *     last failure on the calling thread is nrd_last_error().  No C++
+ *     exception crosses the ABI.
+ *   - Pointers named `dev_*` or documented as device pointers refer to GPU
+ *     memory; all others are host memory.  Ownership never transfers: the
+ *     caller keeps every buffer it passes.
+ *   - The library allocates no device memory.  After nrd_hierarchy_create
+ *     the caller queries nrd_workspace_size and binds ONE device buffer of
+ *     at least that size with nrd_bind_workspace; it must stay alive until
+ *     nrd_hierarchy_destroy.
+ *   - All device work is queued on the HIP stream given at create.  Calls
+ *     that return data to the host (norm values, statistics) synchronise
+ *     that stream; the others are asynchronous.
+ *   - A hierarchy is not thread safe; use one per host thread.
+ *
+ * Layouts:
+ *   - compact: for every box in creation order, its cells with x fastest;
+ *     all E values first, then all T values (length 2 * ncells).  z is one
+ *     field (length ncells).
+ *   - native: every box stored as a block of (nx+2)(ny+2)(nz+2) values with
+ *     one ghost layer, x fastest; all E blocks, then all T blocks (length
+ *     2 * native_len).  Ghost entries and covered-cell entries of native
+ *     inputs are scratch that the library overwrites (restriction and ghost
+ *     fill); outputs are written on interior cells only, covered cells = 0.
+ */
+#ifndef NRD_H
+#define NRD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nrd_status;
+enum {
+    NRD_OK = 0,
+    NRD_EINVAL = -1,     /* bad argument, size or option                  */
+    NRD_ENESTING = -2,   /* boxes overlap, are misaligned or not nested   */
+    NRD_ESTATE = -3,     /* call out of order (e.g. no workspace bound)   */
+    NRD_ENONPOS = -4,    /* E, T or z not positive and finite             */
+    NRD_ENOTCONV = -5,   /* Newton or Krylov failed; state rolled back     */
+    NRD_EDEVICE = -6,    /* HIP runtime error                              */
+    NRD_EUNSUPPORTED = -7
+};
+
+/* One refinement patch: half-open [lo, hi) in the index space of its level
+ * (level l refines level 0 by 2^l per axis).  Level-0 boxes: exactly one per
+ * problem, covering the base grid.  Finer boxes: even lo/hi, inside the
+ * coarser level shrunk by one coarse cell away from the physical boundary
+ * (proper nesting).  Boxes must be ordered by (problem, level). */
+typedef struct {
+    int32_t problem;
+    int32_t level;
+    int32_t lo[3];
+    int32_t hi[3];
+} nrd_box;
+
+/* One independent problem on [lo, hi] with base_n cells per axis.
+ * Faces are numbered 2*d + s (d = axis, s = 0 low / 1 high).
+ * bc_E[f] = 0: zero flux; 1: Marshak/Robin face  1/2 n.D grad E + E/4 = R
+ * with R = robin_R[f] (eqs. robinbc, bcs).  T has zero flux on every face. */
+typedef struct {
+    int32_t base_n[3];
+    double lo[3];
+    double hi[3];
+    int32_t bc_E[6];
+    double robin_R[6];
+    double kappa;          /* D_T = kappa T^(5/2), kappa = 0.01 in Sec. 3.1  */
+} nrd_problem;
+
+enum { NRD_FP64 = 0, NRD_MIXED = 1 };            /* preconditioner precision */
+enum { NRD_BATCHED = 0, NRD_PER_PATCH = 1 };     /* kernel launch grouping   */
+enum { NRD_JVP_ANALYTIC = 0, NRD_JVP_FD = 1 };
+enum { NRD_P2_PAPER = 0, NRD_P2_FROZEN4 = 1 };
+
+typedef struct {
+    int32_t precision;      /* NRD_FP64 or NRD_MIXED (V-cycles in float)     */
+    int32_t launch;         /* NRD_BATCHED: one launch per operator over the
+                               whole patch table; NRD_PER_PATCH: one launch
+                               per patch (same kernels, same results)       */
+    int32_t use_graph;      /* capture the preconditioner as a HIP graph     */
+    int32_t jvp_mode;       /* analytic Jacobian action or finite difference  */
+    double limiter;         /* lambda in D_h / (1 + lambda D_h |dE|/(h E_f));
+                               1 = Wilson form, 0.5 = the printed pair       */
+    int32_t p2_mode;        /* coupling block entries                        */
+    double newton_rtol;     /* ||F_k|| <= max(rtol ||F_0||, atol)            */
+    double newton_atol;
+    int32_t newton_maxit;
+    int32_t gmres_restart;  /* Krylov dimension m <= 64                      */
+    int32_t gmres_maxrestarts;
+    int32_t mg_nu_pre;      /* base multigrid V(nu_pre, nu_post)             */
+    int32_t mg_nu_post;
+    int32_t adjoint_slots;  /* device state slots reserved for nrd_adjoint_run:
+                               ceil(nsteps / ckpt_every) + ckpt_every        */
+    int32_t reserved[7];
+} nrd_options;
+
+/* Fills *opt with the defaults: FP64, batched, no graph, analytic JVP,
+ * limiter 1, paper P2, rtol 1e-8, atol 1e-14, 20 Newton iterations,
+ * GMRES(30) with 10 restarts, V(1,1). */
+void nrd_default_options(nrd_options* opt);
+
+typedef struct {
+    int32_t newton_iters;
+    int32_t krylov_iters;        /* total over the Newton iterations         */
+    int32_t positivity_cuts;
+    int32_t converged;
+    double fnorm0;
+    double fnorm;
+    int32_t krylov_per_newton[24];
+} nrd_step_stats;
+
+typedef struct nrd_hierarchy nrd_hierarchy;
+
+const char* nrd_last_error(void);
+
+/* Builds the patch, ghost, restriction and flux-matching tables on the host
+ * (Sec. 3.2.1: coarse-fine boundary fragments become a flat ghost table).
+ * hip_stream: a hipStream_t (NULL = default stream).  Errors: NRD_EINVAL,
+ * NRD_ENESTING.  *out is set only on success. */
+nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob,
+                                const nrd_box* boxes, int32_t nbox,
+                                const nrd_options* opt, void* hip_stream,
+                                nrd_hierarchy** out);
+/* Releases host tables and graphs; never frees the bound workspace. */
+nrd_status nrd_hierarchy_destroy(nrd_hierarchy* h);
+
+/* Bytes of device workspace this hierarchy needs (Krylov basis included). */
+nrd_status nrd_workspace_size(const nrd_hierarchy* h, size_t* bytes);
+/* Binds dev_ptr (>= nrd_workspace_size bytes, 256-byte aligned) and uploads
+ * the tables into it.  Synchronises the stream. */
+nrd_status nrd_bind_workspace(nrd_hierarchy* h, void* dev_ptr, size_t bytes);
+
+/* ncells: composite + covered cells of all boxes; native_len: ghosted cells
+ * per field. */
+nrd_status nrd_layout(const nrd_hierarchy* h, int64_t* ncells,
+                      int64_t* native_len);
+/* Device pointers; 2-field vectors in the layouts described above. */
+nrd_status nrd_pack(nrd_hierarchy* h, const double* dev_native,
+                    double* dev_compact);
+nrd_status nrd_unpack(nrd_hierarchy* h, const double* dev_compact,
+                      double* dev_native);
+
+/* Copies the state E, T and the material z (device, compact) into the
+ * library, restricts covered cells, fills ghosts and resets the time
+ * history (the next implicit step is BDF1).  z must be given on every
+ * level, covered cells included.  NRD_ENONPOS if any value <= 0 or not
+ * finite (checked on the device; synchronises). */
+nrd_status nrd_set_fields(nrd_hierarchy* h, const double* dev_E,
+                          const double* dev_T, const double* dev_z);
+/* Copies the current state out (compact; covered cells hold restricted
+ * values).  Synchronises. */
+nrd_status nrd_get_fields(nrd_hierarchy* h, double* dev_E, double* dev_T);
+
+/* Fixes BDF order, alpha, c0, b = history combination and beta for the
+ * following residual / jvp / precond calls, per problem (dt: host array of
+ * nprob step sizes; eqs. be, bdf2). */
+nrd_status nrd_begin_step(nrd_hierarchy* h, const double* dt);
+
+/* F = c0 u - b - dt f(u) on composite cells (covered cells = 0) for a native
+ * state u; u's ghost and covered entries are overwritten (restriction and
+ * ghost fill).  Sec. 3.1-3.3, eq. nonlinearsystem. */
+nrd_status nrd_residual(nrd_hierarchy* h, double* dev_u, double* dev_F);
+
+/* Jv = F'(u) v (analytic derivative of the residual, or the finite
+ * difference of eq. Jac-free with the step of Sec. 4.1 when jvp_mode is FD).
+ * u and v native; their ghost/covered entries are overwritten. */
+nrd_status nrd_jvp(nrd_hierarchy* h, double* dev_u, double* dev_v,
+                   double* dev_Jv);
+
+/* Freezes D_E, D_T, sigma at u (Sec. 4.2 L^k) and factors the coarsest
+ * multigrid grid.  Then y = P2^-1 P1^-1 w, P1^-1 by one FAC V(1,0) cycle
+ * (Alg. 1) in the configured precision.  w and y native double; covered
+ * entries of y are unspecified. */
+nrd_status nrd_precond_setup(nrd_hierarchy* h, double* dev_u);
+nrd_status nrd_precond_apply(nrd_hierarchy* h, const double* dev_w,
+                             double* dev_y);
+
+/* Transposed action: JTlam = F'(u)^T lam (native, interior written) and
+ * gz = (dF/dz)^T lam per cell (compact, ncells).  Single-level hierarchies
+ * (the adjoint of coarse-fine interpolation is not provided). */
+nrd_status nrd_vjp(nrd_hierarchy* h, double* dev_u, double* dev_lam,
+                   double* dev_JTlam, double* dev_gz);
+
+/* One BDF step of the library-owned state for every problem: BDF1 after
+ * set_fields, BDF2 with alpha = dt_n / dt_{n-1} afterwards, leapfrog
+ * predictor as initial guess (eqs. be, bdf2, leapfrog), inexact Newton with
+ * Eisenstat-Walker forcing and positivity-preserving step halving, FGMRES
+ * right-preconditioned by P (eq. inexactNewtoneqns).  dt: host [nprob];
+ * stats: host [nprob] or NULL.  On failure the state is rolled back and
+ * NRD_ENOTCONV is returned.  Synchronises. */
+nrd_status nrd_implicit_step(nrd_hierarchy* h, const double* dt,
+                             nrd_step_stats* stats);
+
+/* Discrete adjoint of nsteps BDF1 steps of size dt from the current state
+ * for J = sum over cells of dJdE_final[c] * E_N(c) (device, compact E part;
+ * NULL = all ones).  Forward states are checkpointed every ckpt_every steps
+ * and recomputed segment by segment.  gz (device, ncells) receives dJ/dz.
+ * The state afterwards is u_N. */
+nrd_status nrd_adjoint_run(nrd_hierarchy* h, const double* dt, int32_t nsteps,
+                           int32_t ckpt_every, const double* dev_dJdE_final,
+                           double* dev_gz);
+
+/* Inner product and norm of native 2-field vectors, per problem, volume
+ * weighted over composite cells (host outputs of length nprob). */
+nrd_status nrd_dot(nrd_hierarchy* h, const double* dev_x, const double* dev_y,
+                   double* out);
+
+/* Time of the last kernels of one operator, for measurement: launches of
+ * the residual kernel family since the last call are timed with HIP events
+ * on the library stream.  *ms_total / *count.  Synchronises. */
+nrd_status nrd_timer_read(nrd_hierarchy* h, int32_t which, double* ms_total,
+                          int32_t* count);
+enum { NRD_TIMER_RESIDUAL = 0, NRD_TIMER_JVP = 1, NRD_TIMER_PRECOND = 2,
+       NRD_TIMER_SMOOTH = 3, NRD_TIMER_COUNT = 4 };
+nrd_status nrd_timer_enable(nrd_hierarchy* h, int32_t on);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NRD_H */

@@ -1,0 +1,109 @@
+// Launchers of the HIP kernels (defined in stencil.hip, vec.hip, precond.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "nrd_internal.h"
+
+namespace nrd {
+
+constexpr int kMaxLev = 12;
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+
+// Device views of the hierarchy tables (pointers into the workspace) plus the
+// host-side counts that size the launches.
+struct Dev {
+    int64_t nl = 0;
+    int32_t nprob = 0, nlev = 0, nbox = 0;
+    const PatchInfo* patches = nullptr;
+    const Tile* tiles = nullptr;
+    int32_t level_tile0[kMaxLev + 1] = {};
+    const Tile* vtiles = nullptr;
+    int32_t nvtiles = 0;
+    const int32_t* prob_vtile0 = nullptr;    // device [nprob+1]
+    const GhostCopy* gcopy = nullptr;
+    int32_t ncopy = 0;
+    const GhostCF* gcf = nullptr;
+    int32_t ncf = 0;
+    const GhostCopy* sib = nullptr;
+    int32_t level_sib0[kMaxLev + 1] = {};
+    const SyncEntry* sync[kMaxLev] = {};
+    int32_t nsync[kMaxLev] = {};
+    const RefluxFace* rfaces = nullptr;
+    const RefluxCell* rcells = nullptr;
+    int32_t nrcells = 0;
+    const uint8_t* ctype = nullptr;
+    const ProbScalars* ps = nullptr;         // device [nprob]
+    const int32_t* active = nullptr;         // device [nprob], 1 = work on it
+    const double* z3 = nullptr;              // native, z^3 with ghosts
+    int32_t level_shadow0[kMaxLev + 1] = {}; // prolongation shadow cells per level
+};
+
+// ---- stencil.hip --------------------------------------------------------
+// x: NF fields of native length nl.  Fills every face ghost of every patch.
+void ghost_fill_d(const Dev& D, hipStream_t s, double* x, int nf);
+void ghost_fill_f(const Dev& D, hipStream_t s, float* x, int nf);
+// covered cells <- mean of children, finest level first
+void restrict_d(const Dev& D, hipStream_t s, double* x, int nf, int lev_lo = 0);
+void restrict_f(const Dev& D, hipStream_t s, float* x, int nf, int lev_lo = 0);
+// sibling ghosts of one level only
+void sibling_exchange_f(const Dev& D, hipStream_t s, float* x, int nf, int lev);
+void sibling_exchange_d(const Dev& D, hipStream_t s, double* x, int nf, int lev);
+
+// F = c0 u - b - dt f(u) over tiles [t0, t0+nt); covered cells = 0.
+void residual(const Dev& D, hipStream_t s, int t0, int nt, const double* u,
+              const double* b, double* F);
+void residual_reflux(const Dev& D, hipStream_t s, const double* u, double* F);
+// Jv
+void jvp(const Dev& D, hipStream_t s, int t0, int nt, const double* u,
+         const double* v, double* Jv);
+void jvp_reflux(const Dev& D, hipStream_t s, const double* u, const double* v,
+                double* Jv);
+// transpose: gE, gT (native, interior) and gz3 (native) = lambda^T dF/dz^3
+void vjp(const Dev& D, hipStream_t s, int t0, int nt, const double* u,
+         const double* lam, double* JTl, double* gz3);
+
+// ---- vec.hip ------------------------------------------------------------
+// Deterministic per-problem reductions over vtiles.
+//   out[p * nv + v] = sum over composite cells of problem p of
+//                     vol * (x_v . y) (both fields), x_v = X + v * xstride
+void multidot(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
+              int nv, const double* y, double* partial, double* out);
+// out[p] = min over composite cells of min(E + lam_p dE, T + lam_p dT)
+void min_positive(const Dev& D, hipStream_t s, const double* u, const double* du,
+                  const double* lam, double* partial, double* out);
+// y = sum_v coef[p][v] x_v (+ y if accumulate) on interior cells of active
+// problems; coef row stride cstride
+void combine(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
+             int nv, const double* coef, int cstride, double* y, int accumulate,
+             double alpha);
+// y = a_p x + b_p y elementwise (a, b per problem, host-computed device arrays)
+void axpby(const Dev& D, hipStream_t s, const double* a, const double* x,
+           const double* b, double* y);
+// y = x * scale_p (scale device [nprob])
+void scale_copy(const Dev& D, hipStream_t s, const double* x, const double* sc,
+                double* y);
+void copy_interior(const Dev& D, hipStream_t s, const double* x, double* y);
+void fill_native(hipStream_t s, double* x, int64_t n, double v);
+void fill_native_f(hipStream_t s, float* x, int64_t n, float v);
+void pack(const Dev& D, hipStream_t s, const int64_t* coff, const double* native,
+          double* compact, int nf, int64_t ncells);
+void unpack(const Dev& D, hipStream_t s, const int64_t* coff,
+            const double* compact, double* native, int nf, int64_t ncells);
+// flag[0] = 1 if any interior value of the nf fields is <= 0 or not finite
+void check_positive(const Dev& D, hipStream_t s, const double* x, int nf,
+                    int32_t* flag);
+void cube(hipStream_t s, const double* z, double* z3, int64_t n);
+void to_float(hipStream_t s, const double* x, float* y, int64_t n);
+void to_double(hipStream_t s, const float* x, double* y, int64_t n);
+
+// Givens / Hessenberg update of FGMRES for every active problem.
+//   hcol [nprob][m+1] holds the new column (CGS sums), hn2 [nprob] = ||w||^2
+void gmres_column(hipStream_t s, int nprob, int m, int j, const int32_t* active,
+                  const double* h1, const double* h2, const double* hn2,
+                  double* H, double* cs, double* sn, double* g, double* rho,
+                  double* vscale);
+void gmres_backsolve(hipStream_t s, int nprob, int m, const int32_t* kdim,
+                     const double* H, const double* g, double* y);
+
+}  // namespace nrd

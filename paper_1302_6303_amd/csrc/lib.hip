@@ -1,0 +1,1316 @@
+// nrd library: workspace, operators, solver drivers and the C ABI.
+//
+// The host drives one lock-step inexact Newton / FGMRES iteration over all
+// problems of the hierarchy; all vector arithmetic, reductions and small
+// per-problem FGMRES updates run on the device.  The host reads back one
+// small per-problem array per Krylov iteration (the residual estimates)
+// and a few per Newton iteration (norms, positivity minima).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "precond.h"
+
+using namespace nrd;
+
+namespace {
+
+thread_local std::string g_err;
+
+nrd_status fail(nrd_status st, const std::string& m) {
+    g_err = m;
+    return st;
+}
+
+#define HIPCHK(x)                                                                   \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess)                                                       \
+            return fail(NRD_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define RCHK(x)                        \
+    do {                               \
+        nrd_status r_ = (x);           \
+        if (r_ != NRD_OK) return r_;   \
+    } while (0)
+
+struct Bump {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+
+}  // namespace
+
+struct nrd_hierarchy {
+    Tables t;
+    nrd_options opt;
+    hipStream_t stream = nullptr;
+    int m = 30;                     // Krylov dimension
+    bool bound = false;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Dev D;
+    PcArrays<float> pcf;
+    PcArrays<double> pcd;
+    bool mixed = false;
+    std::vector<int32_t> patch_tile0;
+
+    // workspace offsets
+    struct Off {
+        size_t patches, tiles, vtiles, prob_vtile0, gcopy, gcf, sib, sync[kMaxLev], rfaces,
+            rcells, ctype, shadows, shadow_src, coff, ps, active;
+        size_t mg_box[kMaxMG], mg_tiles[kMaxMG], mg_box_of[kMaxMG], mg_smooth[kMaxMG],
+            mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bottom_off, Lbuf, Xbuf;
+        size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, rb, gz3, V, Z;
+        size_t pc_D, pc_sigma, pc_e, pc_u, pc_r, pc_f, pc_tmp, pc_shadow;
+        size_t mg_D[kMaxMG], mg_e[kMaxMG], mg_f[kMaxMG], mg_r[kMaxMG];
+        size_t partial, dots, h1, h2, hn2, H, cs, sn, g, rho, vscale, y, kdim, coefA, coefB,
+            minout, flag, ckpt;
+    } o;
+    int32_t adjoint_slots = 0;
+    // host-side per-problem state
+    std::vector<double> dt_prev;   // 0: no history (next step BDF1)
+    std::vector<double> c0, alpha, beta, dt_cur;
+    std::vector<ProbScalars> ps_host;
+    bool step_ready = false;
+    // device pointers
+    double *z, *z3, *cur, *prev, *udot, *bvec, *x, *F, *s, *w, *tmp, *tmp2, *rb, *gz3, *V, *Z;
+    double *partial, *dots, *h1, *h2, *hn2, *H, *cs, *sn, *g, *rho, *vscale, *y, *coefA, *coefB,
+        *minout, *ckpt;
+    int32_t *kdim, *flag, *active;
+    ProbScalars* ps;
+    // timers
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pairs;
+    std::vector<int32_t> host_active;
+
+    int64_t nl2() const { return 2 * t.nl; }
+    template <typename T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+
+    hipEvent_t ev() {
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t e;
+            (void)hipEventCreate(&e);
+            ev_pool.push_back(e);
+        }
+        return ev_pool[ev_used++];
+    }
+    std::pair<hipEvent_t, hipEvent_t> tic(int which) {
+        if (!timing) return {nullptr, nullptr};
+        hipEvent_t a = ev(), b = ev();
+        (void)hipEventRecord(a, stream);
+        return {a, b};
+    }
+    void toc(int which, std::pair<hipEvent_t, hipEvent_t> p) {
+        if (!timing || !p.first) return;
+        (void)hipEventRecord(p.second, stream);
+        ev_pairs.push_back({which, p});
+    }
+};
+
+// ---------------------------------------------------------------------------
+// layout
+// ---------------------------------------------------------------------------
+
+static void layout(nrd_hierarchy* h) {
+    Tables& t = h->t;
+    Bump b;
+    auto& o = h->o;
+    const int64_t nl = t.nl;
+    const int nprob = t.nprob;
+    const int m = h->m;
+    o.patches = b.take(sizeof(PatchInfo) * t.patches.size());
+    o.tiles = b.take(sizeof(Tile) * std::max<size_t>(1, t.tiles.size()));
+    o.vtiles = b.take(sizeof(Tile) * std::max<size_t>(1, t.vtiles.size()));
+    o.prob_vtile0 = b.take(sizeof(int32_t) * t.prob_vtile0.size());
+    o.gcopy = b.take(sizeof(GhostCopy) * std::max<size_t>(1, t.gcopy.size()));
+    o.gcf = b.take(sizeof(GhostCF) * std::max<size_t>(1, t.gcf.size()));
+    o.sib = b.take(sizeof(GhostCopy) * std::max<size_t>(1, t.sib.size()));
+    for (int l = 0; l < t.nlev; ++l)
+        o.sync[l] = b.take(sizeof(SyncEntry) * std::max<size_t>(1, t.sync[l].size()));
+    o.rfaces = b.take(sizeof(RefluxFace) * std::max<size_t>(1, t.rfaces.size()));
+    o.rcells = b.take(sizeof(RefluxCell) * std::max<size_t>(1, t.rcells.size()));
+    o.ctype = b.take(t.ctype.size());
+    o.shadows = b.take(sizeof(ShadowPatch) * t.shadow.size());
+    o.shadow_src = b.take(sizeof(int32_t) * std::max<int64_t>(1, t.shadow_len));
+    o.coff = b.take(sizeof(int64_t) * t.compact_off.size());
+    o.ps = b.take(sizeof(ProbScalars) * nprob);
+    o.active = b.take(sizeof(int32_t) * nprob);
+    const int G = (int)t.mg.size() - 1;
+    for (int g = 0; g <= G; ++g) {
+        if (g >= 1) {
+            o.mg_box[g] = b.take(sizeof(PatchInfo) * t.mg[g].boxes.size());
+            o.mg_tiles[g] = b.take(sizeof(Tile) * std::max<size_t>(1, t.mg[g].tiles.size()));
+        }
+        o.mg_box_of[g] = b.take(sizeof(int32_t) * nprob);
+        o.mg_smooth[g] = b.take(sizeof(Tile) * (t.tiles.size() + 1));
+        o.mg_bprobs[g] = b.take(sizeof(int32_t) * nprob);
+        o.mg_bboxes[g] = b.take(sizeof(int32_t) * nprob);
+    }
+    o.bottom_off = b.take(sizeof(int64_t) * nprob);
+    int64_t bsum = 0;
+    for (int p = 0; p < nprob; ++p) {
+        int64_t nb = 1;
+        for (int d = 0; d < 3; ++d) nb *= t.probs[p].base_n[d] >> t.prob_mgdepth[p];
+        bsum += nb * nb;
+    }
+    o.Lbuf = b.take(sizeof(double) * 2 * bsum);
+    o.Xbuf = b.take(sizeof(double) * 2 * bsum);
+    // state and work vectors (double)
+    o.z = b.take(8 * nl);
+    o.z3 = b.take(8 * nl);
+    o.cur = b.take(8 * 2 * nl);
+    o.prev = b.take(8 * 2 * nl);
+    o.udot = b.take(8 * 2 * nl);
+    o.bvec = b.take(8 * 2 * nl);
+    o.x = b.take(8 * 2 * nl);
+    o.F = b.take(8 * 2 * nl);
+    o.s = b.take(8 * 2 * nl);
+    o.w = b.take(8 * 2 * nl);
+    o.tmp = b.take(8 * 2 * nl);
+    o.tmp2 = b.take(8 * 2 * nl);
+    o.rb = b.take(8 * 2 * nl);
+    o.gz3 = b.take(8 * nl);
+    o.V = b.take(8 * 2 * nl * (size_t)(m + 1));
+    o.Z = b.take(8 * 2 * nl * (size_t)m);
+    // preconditioner (float or double)
+    const size_t es = h->mixed ? 4 : 8;
+    o.pc_D = b.take(es * 6 * nl);
+    o.pc_sigma = b.take(es * nl);
+    o.pc_e = b.take(es * 2 * nl);
+    o.pc_u = b.take(es * 2 * nl);
+    o.pc_r = b.take(es * 2 * nl);
+    o.pc_f = b.take(es * 2 * nl);
+    o.pc_tmp = b.take(es * 2 * nl);
+    o.pc_shadow = b.take(es * 2 * std::max<int64_t>(1, t.shadow_len));
+    for (int g = 1; g <= G; ++g) {
+        const int64_t n = t.mg[g].len;
+        o.mg_D[g] = b.take(es * 6 * n);
+        o.mg_e[g] = b.take(es * 2 * n);
+        o.mg_f[g] = b.take(es * 2 * n);
+        o.mg_r[g] = b.take(es * 2 * n);
+    }
+    // reductions and per-problem scalars
+    o.partial = b.take(8 * 16 * std::max<size_t>(1, t.vtiles.size()));
+    o.dots = b.take(8 * nprob * (m + 2));
+    o.h1 = b.take(8 * nprob * (m + 1));
+    o.h2 = b.take(8 * nprob * (m + 1));
+    o.hn2 = b.take(8 * nprob);
+    o.H = b.take(8 * (size_t)nprob * (m + 1) * m);
+    o.cs = b.take(8 * nprob * m);
+    o.sn = b.take(8 * nprob * m);
+    o.g = b.take(8 * nprob * (m + 1));
+    o.rho = b.take(8 * nprob);
+    o.vscale = b.take(8 * nprob);
+    o.y = b.take(8 * nprob * m);
+    o.kdim = b.take(4 * nprob);
+    o.coefA = b.take(8 * nprob * 4);
+    o.coefB = b.take(8 * nprob * 4);
+    o.minout = b.take(8 * nprob);
+    o.flag = b.take(4 * 4);
+    o.ckpt = b.take(8 * 2 * nl * (size_t)std::max(0, h->adjoint_slots));
+    h->ws_bytes = b.off;
+}
+
+template <typename T>
+static hipError_t up(hipStream_t s, void* dst, const std::vector<T>& v) {
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s);
+}
+
+template <typename PT>
+static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
+    auto& o = h->o;
+    Tables& t = h->t;
+    pc.D = &h->D;
+    pc.Dface = h->at<PT>(o.pc_D);
+    pc.sigma = h->at<PT>(o.pc_sigma);
+    pc.e = h->at<PT>(o.pc_e);
+    pc.u = h->at<PT>(o.pc_u);
+    pc.r = h->at<PT>(o.pc_r);
+    pc.f = h->at<PT>(o.pc_f);
+    pc.tmp = h->at<PT>(o.pc_tmp);
+    pc.shadow = h->at<PT>(o.pc_shadow);
+    pc.shadow_src = h->at<int32_t>(o.shadow_src);
+    pc.shadows = h->at<ShadowPatch>(o.shadows);
+    pc.shadow_len = std::max<int64_t>(1, t.shadow_len);
+    const int G = (int)t.mg.size() - 1;
+    pc.mg.G = G;
+    for (int g = 0; g <= G; ++g) {
+        if (g >= 1) {
+            pc.mg.box[g] = h->at<PatchInfo>(o.mg_box[g]);
+            pc.mg.len[g] = t.mg[g].len;
+            pc.mg.tiles[g] = h->at<Tile>(o.mg_tiles[g]);
+            pc.mg.ntiles[g] = (int)t.mg[g].tiles.size();
+            pc.mg.Dg[g] = h->at<PT>(o.mg_D[g]);
+            pc.mg.eg[g] = h->at<PT>(o.mg_e[g]);
+            pc.mg.fg[g] = h->at<PT>(o.mg_f[g]);
+            pc.mg.rg[g] = h->at<PT>(o.mg_r[g]);
+        }
+        pc.mg.box_of[g] = h->at<int32_t>(o.mg_box_of[g]);
+        pc.mg.smooth_tiles[g] = h->at<Tile>(o.mg_smooth[g]);
+        pc.mg.bottom_probs[g] = h->at<int32_t>(o.mg_bprobs[g]);
+        pc.mg.bottom_boxes[g] = h->at<int32_t>(o.mg_bboxes[g]);
+    }
+    pc.mg.bottom_off = h->at<int64_t>(o.bottom_off);
+    pc.mg.Lbuf = h->at<double>(o.Lbuf);
+    pc.mg.Xbuf = h->at<double>(o.Xbuf);
+    pc.p2_mode = h->opt.p2_mode;
+    pc.nu_pre = std::max(1, h->opt.mg_nu_pre);
+    pc.nu_post = std::max(0, h->opt.mg_nu_post);
+}
+
+static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
+    if (bytes < h->ws_bytes) return fail(NRD_EINVAL, "workspace too small");
+    if (reinterpret_cast<uintptr_t>(ptr) % 256) return fail(NRD_EINVAL, "workspace not 256-byte aligned");
+    h->ws = static_cast<char*>(ptr);
+    Tables& t = h->t;
+    auto& o = h->o;
+    hipStream_t s = h->stream;
+    // zero everything once: ghosts of work vectors stay finite
+    fill_native(s, reinterpret_cast<double*>(h->ws), (int64_t)(h->ws_bytes / 8), 0.0);
+    HIPCHK(up(s, h->ws + o.patches, t.patches));
+    HIPCHK(up(s, h->ws + o.tiles, t.tiles));
+    HIPCHK(up(s, h->ws + o.vtiles, t.vtiles));
+    HIPCHK(up(s, h->ws + o.prob_vtile0, t.prob_vtile0));
+    HIPCHK(up(s, h->ws + o.gcopy, t.gcopy));
+    HIPCHK(up(s, h->ws + o.gcf, t.gcf));
+    HIPCHK(up(s, h->ws + o.sib, t.sib));
+    for (int l = 0; l < t.nlev; ++l) HIPCHK(up(s, h->ws + o.sync[l], t.sync[l]));
+    HIPCHK(up(s, h->ws + o.rfaces, t.rfaces));
+    HIPCHK(up(s, h->ws + o.rcells, t.rcells));
+    HIPCHK(up(s, h->ws + o.ctype, t.ctype));
+    HIPCHK(up(s, h->ws + o.shadows, t.shadow));
+    HIPCHK(up(s, h->ws + o.shadow_src, t.shadow_src));
+    HIPCHK(up(s, h->ws + o.coff, t.compact_off));
+    // multigrid tables
+    const int G = (int)t.mg.size() - 1;
+    std::vector<std::vector<int32_t>> box_of(G + 1, std::vector<int32_t>(t.nprob, -1));
+    for (int p = 0; p < t.nprob; ++p) box_of[0][p] = t.level_patches[p][0][0];
+    for (int g = 1; g <= G; ++g)
+        for (size_t i = 0; i < t.mg[g].probs.size(); ++i) box_of[g][t.mg[g].probs[i]] = (int32_t)i;
+    std::vector<int32_t> nsmooth(G + 1, 0), nbottom(G + 1, 0);
+    for (int g = 0; g <= G; ++g) {
+        if (g >= 1) {
+            HIPCHK(up(s, h->ws + o.mg_box[g], t.mg[g].boxes));
+            HIPCHK(up(s, h->ws + o.mg_tiles[g], t.mg[g].tiles));
+        }
+        HIPCHK(up(s, h->ws + o.mg_box_of[g], box_of[g]));
+        std::vector<Tile> sm;
+        if (g == 0) {
+            for (int i = t.level_tile0[0]; i < t.level_tile0[1]; ++i)
+                if (t.prob_mgdepth[t.tiles[i].prob] > 0) sm.push_back(t.tiles[i]);
+        } else {
+            for (const Tile& tl : t.mg[g].tiles)
+                if (t.prob_mgdepth[tl.prob] > g) sm.push_back(tl);
+        }
+        nsmooth[g] = (int)sm.size();
+        HIPCHK(up(s, h->ws + o.mg_smooth[g], sm));
+        std::vector<int32_t> bp, bb;
+        for (int p = 0; p < t.nprob; ++p)
+            if (t.prob_mgdepth[p] == g) {
+                bp.push_back(p);
+                bb.push_back(box_of[g][p]);
+            }
+        nbottom[g] = (int)bp.size();
+        HIPCHK(up(s, h->ws + o.mg_bprobs[g], bp));
+        HIPCHK(up(s, h->ws + o.mg_bboxes[g], bb));
+    }
+    std::vector<int64_t> boff(t.nprob);
+    for (int p = 0; p < t.nprob; ++p) boff[p] = t.bottom_off[p];
+    HIPCHK(up(s, h->ws + o.bottom_off, boff));
+    // device views
+    Dev& D = h->D;
+    D.nl = t.nl;
+    D.nprob = t.nprob;
+    D.nlev = t.nlev;
+    D.nbox = t.nbox;
+    D.patches = h->at<PatchInfo>(o.patches);
+    D.tiles = h->at<Tile>(o.tiles);
+    for (int l = 0; l <= t.nlev; ++l) D.level_tile0[l] = t.level_tile0[l];
+    D.vtiles = h->at<Tile>(o.vtiles);
+    D.nvtiles = (int32_t)t.vtiles.size();
+    D.prob_vtile0 = h->at<int32_t>(o.prob_vtile0);
+    D.gcopy = h->at<GhostCopy>(o.gcopy);
+    D.ncopy = (int32_t)t.gcopy.size();
+    D.gcf = h->at<GhostCF>(o.gcf);
+    D.ncf = (int32_t)t.gcf.size();
+    D.sib = h->at<GhostCopy>(o.sib);
+    for (int l = 0; l <= t.nlev; ++l) D.level_sib0[l] = t.level_sib0[l];
+    for (int l = 0; l <= t.nlev; ++l) D.level_shadow0[l] = t.level_shadow0[l];
+    for (int l = 0; l < t.nlev; ++l) {
+        D.sync[l] = h->at<SyncEntry>(o.sync[l]);
+        D.nsync[l] = (int32_t)t.sync[l].size();
+    }
+    D.rfaces = h->at<RefluxFace>(o.rfaces);
+    D.rcells = h->at<RefluxCell>(o.rcells);
+    D.nrcells = (int32_t)t.rcells.size();
+    D.ctype = h->at<uint8_t>(o.ctype);
+    D.ps = h->at<ProbScalars>(o.ps);
+    D.active = nullptr;
+    D.z3 = h->at<double>(o.z3);
+    h->ps = h->at<ProbScalars>(o.ps);
+    h->active = h->at<int32_t>(o.active);
+    h->z = h->at<double>(o.z);
+    h->z3 = h->at<double>(o.z3);
+    h->cur = h->at<double>(o.cur);
+    h->prev = h->at<double>(o.prev);
+    h->udot = h->at<double>(o.udot);
+    h->bvec = h->at<double>(o.bvec);
+    h->x = h->at<double>(o.x);
+    h->F = h->at<double>(o.F);
+    h->s = h->at<double>(o.s);
+    h->w = h->at<double>(o.w);
+    h->tmp = h->at<double>(o.tmp);
+    h->tmp2 = h->at<double>(o.tmp2);
+    h->rb = h->at<double>(o.rb);
+    h->gz3 = h->at<double>(o.gz3);
+    h->V = h->at<double>(o.V);
+    h->Z = h->at<double>(o.Z);
+    h->partial = h->at<double>(o.partial);
+    h->dots = h->at<double>(o.dots);
+    h->h1 = h->at<double>(o.h1);
+    h->h2 = h->at<double>(o.h2);
+    h->hn2 = h->at<double>(o.hn2);
+    h->H = h->at<double>(o.H);
+    h->cs = h->at<double>(o.cs);
+    h->sn = h->at<double>(o.sn);
+    h->g = h->at<double>(o.g);
+    h->rho = h->at<double>(o.rho);
+    h->vscale = h->at<double>(o.vscale);
+    h->y = h->at<double>(o.y);
+    h->kdim = h->at<int32_t>(o.kdim);
+    h->coefA = h->at<double>(o.coefA);
+    h->coefB = h->at<double>(o.coefB);
+    h->minout = h->at<double>(o.minout);
+    h->flag = h->at<int32_t>(o.flag);
+    h->ckpt = h->at<double>(o.ckpt);
+    if (h->mixed) {
+        wire_pc(h, h->pcf);
+        for (int g = 0; g <= G; ++g) {
+            h->pcf.mg.nsmooth[g] = nsmooth[g];
+            h->pcf.mg.nbottom[g] = nbottom[g];
+        }
+    } else {
+        wire_pc(h, h->pcd);
+        for (int g = 0; g <= G; ++g) {
+            h->pcd.mg.nsmooth[g] = nsmooth[g];
+            h->pcd.mg.nbottom[g] = nbottom[g];
+        }
+    }
+    h->host_active.assign(t.nprob, 1);
+    HIPCHK(up(s, h->active, h->host_active));
+    // per-problem constants (valid before the first begin_step)
+    h->ps_host.assign(t.nprob, ProbScalars());
+    for (int p = 0; p < t.nprob; ++p) {
+        ProbScalars& q = h->ps_host[p];
+        std::memset(&q, 0, sizeof(q));
+        q.dt = 0.0;
+        q.c0 = 1.0;
+        q.beta = 0.0;
+        q.kappa = t.probs[p].kappa;
+        q.lam = h->opt.limiter;
+        for (int f = 0; f < 6; ++f) q.R[f] = t.probs[p].robin_R[f];
+    }
+    HIPCHK(up(s, h->ps, h->ps_host));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    h->bound = true;
+    return NRD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operators on native vectors
+// ---------------------------------------------------------------------------
+
+static void prepare_state(nrd_hierarchy* h, double* u) {
+    restrict_d(h->D, h->stream, u, 2, 0);
+    ghost_fill_d(h->D, h->stream, u, 2);
+}
+
+static void op_residual(nrd_hierarchy* h, double* u, double* F, bool prepared = false) {
+    if (!prepared) prepare_state(h, u);
+    auto tk = h->tic(NRD_TIMER_RESIDUAL);
+    const Dev& D = h->D;
+    if (h->opt.launch == NRD_PER_PATCH) {
+        for (int b = 0; b < h->t.nbox; ++b)
+            residual(D, h->stream, h->patch_tile0[b], (int)h->t.patch_tiles[b].size(), u,
+                     h->bvec, F);
+    } else {
+        residual(D, h->stream, 0, D.level_tile0[D.nlev], u, h->bvec, F);
+    }
+    residual_reflux(D, h->stream, u, F);
+    h->toc(NRD_TIMER_RESIDUAL, tk);
+}
+
+static void op_jvp(nrd_hierarchy* h, double* u, double* v, double* Jv, bool u_prepared) {
+    if (!u_prepared) prepare_state(h, u);
+    prepare_state(h, v);
+    auto tk = h->tic(NRD_TIMER_JVP);
+    const Dev& D = h->D;
+    if (h->opt.launch == NRD_PER_PATCH) {
+        for (int b = 0; b < h->t.nbox; ++b)
+            jvp(D, h->stream, h->patch_tile0[b], (int)h->t.patch_tiles[b].size(), u, v, Jv);
+    } else {
+        jvp(D, h->stream, 0, D.level_tile0[D.nlev], u, v, Jv);
+    }
+    jvp_reflux(D, h->stream, u, v, Jv);
+    h->toc(NRD_TIMER_JVP, tk);
+}
+
+static void pc_setup(nrd_hierarchy* h, double* u, bool prepared) {
+    if (!prepared) prepare_state(h, u);
+    if (h->mixed)
+        h->pcf.setup(h->stream, u);
+    else
+        h->pcd.setup(h->stream, u);
+}
+
+static void pc_apply(nrd_hierarchy* h, const double* w, double* y) {
+    auto tk = h->tic(NRD_TIMER_PRECOND);
+    if (h->mixed)
+        h->pcf.apply(h->stream, w, y);
+    else
+        h->pcd.apply(h->stream, w, y);
+    h->toc(NRD_TIMER_PRECOND, tk);
+}
+
+static void pc_apply_t(nrd_hierarchy* h, const double* w, double* y) {
+    if (h->mixed)
+        h->pcf.apply_transpose(h->stream, w, y);
+    else
+        h->pcd.apply_transpose(h->stream, w, y);
+}
+
+static nrd_status upload_active(nrd_hierarchy* h) {
+    HIPCHK(hipMemcpyAsync(h->active, h->host_active.data(), 4 * h->t.nprob,
+                          hipMemcpyHostToDevice, h->stream));
+    return NRD_OK;
+}
+
+static nrd_status dot_host(nrd_hierarchy* h, const double* x, const double* y,
+                           std::vector<double>& out) {
+    h->D.active = nullptr;
+    multidot(h->D, h->stream, x, 0, 1, y, h->partial, h->dots);
+    out.resize(h->t.nprob);
+    HIPCHK(hipMemcpyAsync(out.data(), h->dots, 8 * h->t.nprob, hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return NRD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// BDF coefficients and history combination (eqs. be, bdf2)
+// ---------------------------------------------------------------------------
+
+static nrd_status begin_step(nrd_hierarchy* h, const double* dt, bool bdf1_only = false) {
+    Tables& t = h->t;
+    const int np = t.nprob;
+    h->c0.assign(np, 1.0);
+    h->alpha.assign(np, 0.0);
+    h->beta.assign(np, 0.0);
+    h->dt_cur.assign(dt, dt + np);
+    std::vector<double> a(np), b(np), one(np, 1.0);
+    for (int p = 0; p < np; ++p) {
+        if (!(dt[p] > 0.0)) return fail(NRD_EINVAL, "dt must be positive");
+        const bool first = !(h->dt_prev[p] > 0.0) || bdf1_only;
+        double c0 = 1.0, al = 0.0;
+        if (!first) {
+            al = dt[p] / h->dt_prev[p];
+            c0 = (1.0 + 2.0 * al) / (1.0 + al);
+        }
+        h->c0[p] = c0;
+        h->alpha[p] = al;
+        h->beta[p] = dt[p] / c0;
+        h->ps_host[p].dt = dt[p];
+        h->ps_host[p].c0 = c0;
+        h->ps_host[p].alpha = al;
+        h->ps_host[p].beta = dt[p] / c0;
+        a[p] = first ? 1.0 : 1.0 + al;
+        b[p] = first ? 0.0 : -al * al / (1.0 + al);
+    }
+    hipStream_t s = h->stream;
+    HIPCHK(up(s, h->ps, h->ps_host));
+    // b = a u_n + b u_{n-1}
+    std::vector<double> coef(2 * np);
+    for (int p = 0; p < np; ++p) {
+        coef[p] = a[p];
+        coef[np + p] = b[p];
+    }
+    HIPCHK(up(s, h->coefA, coef));
+    h->D.active = nullptr;
+    scale_copy(h->D, s, h->cur, h->coefA, h->bvec);
+    // bvec += b_p * prev  (axpby with y = bvec, a = b_p, b = 1)
+    std::vector<double> ones(np, 1.0);
+    HIPCHK(up(s, h->coefB, ones));
+    axpby(h->D, s, h->coefA + np, h->prev, h->coefB, h->bvec);
+    HIPCHK(hipStreamSynchronize(s));
+    h->step_ready = true;
+    return NRD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES(m), lock-step over the problems with host_active set
+// ---------------------------------------------------------------------------
+
+struct GmresOut {
+    std::vector<int32_t> its;
+};
+
+// Solves J s = rhs (rhs native, s native) for active problems with absolute
+// tolerances tol[p].  transpose: use the transposed operators.
+static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double* sol,
+                         const std::vector<double>& tol, std::vector<int32_t>& its,
+                         bool transpose) {
+    Tables& t = h->t;
+    const int np = t.nprob;
+    const int m = h->m;
+    const int64_t NL = h->nl2();
+    hipStream_t s = h->stream;
+    std::vector<int32_t> outer = h->host_active;           // problems asked to solve
+    its.assign(np, 0);
+    std::vector<double> beta0(np), rho(np), inv(np);
+    std::vector<int32_t> kd(np);
+    // sol = 0
+    h->D.active = h->active;
+    std::vector<double> zeros(np, 0.0);
+    HIPCHK(up(s, h->coefA, zeros));
+    scale_copy(h->D, s, rhs, h->coefA, sol);
+    std::vector<int32_t> todo = outer;
+    for (int cycle = 0; cycle <= h->opt.gmres_maxrestarts; ++cycle) {
+        // r = rhs - A sol  (first cycle: rhs)
+        double* r = h->w;
+        h->host_active = todo;
+        RCHK(upload_active(h));
+        h->D.active = h->active;
+        if (cycle == 0) {
+            copy_interior(h->D, s, rhs, r);
+        } else {
+            copy_interior(h->D, s, sol, h->tmp2);
+            if (!transpose) {
+                op_jvp(h, u, h->tmp2, h->tmp, true);
+            } else {
+                ghost_fill_d(h->D, s, h->tmp2, 2);
+                vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], u, h->tmp2, h->tmp, h->gz3);
+            }
+            copy_interior(h->D, s, rhs, r);
+            std::vector<double> mone(np, -1.0), pone(np, 1.0);
+            HIPCHK(up(s, h->coefA, mone));
+            HIPCHK(up(s, h->coefB, pone));
+            axpby(h->D, s, h->coefA, h->tmp, h->coefB, r);
+        }
+        std::vector<double> b2;
+        {
+            multidot(h->D, s, r, 0, 1, r, h->partial, h->dots);
+            b2.resize(np);
+            HIPCHK(hipMemcpyAsync(b2.data(), h->dots, 8 * np, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        bool any = false;
+        for (int p = 0; p < np; ++p) {
+            if (!todo[p]) continue;
+            beta0[p] = std::sqrt(std::max(0.0, b2[p]));
+            if (beta0[p] <= tol[p]) {
+                todo[p] = 0;
+                continue;
+            }
+            inv[p] = 1.0 / beta0[p];
+            any = true;
+        }
+        if (!any) break;
+        h->host_active = todo;
+        RCHK(upload_active(h));
+        HIPCHK(up(s, h->coefA, inv));
+        scale_copy(h->D, s, r, h->coefA, h->V);
+        std::vector<double> g0((size_t)np * (m + 1), 0.0);
+        for (int p = 0; p < np; ++p) g0[(size_t)p * (m + 1)] = beta0[p];
+        HIPCHK(up(s, h->g, g0));
+        std::vector<int32_t> live = todo;
+        for (int p = 0; p < np; ++p) kd[p] = 0;
+        for (int j = 0; j < m; ++j) {
+            double* Vj = h->V + j * NL;
+            double* Zj = h->Z + j * NL;
+            double* wv = h->w;
+            if (!transpose) {
+                pc_apply(h, Vj, Zj);
+                op_jvp(h, u, Zj, wv, true);
+            } else {
+                pc_apply_t(h, Vj, Zj);
+                ghost_fill_d(h->D, s, Zj, 2);
+                vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], u, Zj, wv, h->gz3);
+            }
+            // CGS2
+            multidot(h->D, s, h->V, NL, j + 1, wv, h->partial, h->h1);
+            combine(h->D, s, h->V, NL, j + 1, h->h1, j + 1, wv, 1, -1.0);
+            multidot(h->D, s, h->V, NL, j + 1, wv, h->partial, h->h2);
+            combine(h->D, s, h->V, NL, j + 1, h->h2, j + 1, wv, 1, -1.0);
+            multidot(h->D, s, wv, 0, 1, wv, h->partial, h->hn2);
+            gmres_column(s, np, m, j, h->active, h->h1, h->h2, h->hn2, h->H, h->cs, h->sn, h->g,
+                         h->rho, h->vscale);
+            scale_copy(h->D, s, wv, h->vscale, h->V + (j + 1) * NL);
+            std::vector<double> hn(np);
+            HIPCHK(hipMemcpyAsync(rho.data(), h->rho, 8 * np, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(hn.data(), h->hn2, 8 * np, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            bool left = false;
+            for (int p = 0; p < np; ++p) {
+                if (!live[p]) continue;
+                its[p] += 1;
+                kd[p] = j + 1;
+                if (rho[p] <= tol[p] || hn[p] == 0.0) {
+                    live[p] = 0;
+                    todo[p] = 0;
+                } else {
+                    left = true;
+                }
+            }
+            if (!left) break;
+            h->host_active = live;
+            RCHK(upload_active(h));
+        }
+        // sol += Z y for every problem that iterated in this cycle
+        std::vector<int32_t> did(np, 0);
+        for (int p = 0; p < np; ++p) did[p] = kd[p] > 0;
+        h->host_active = did;
+        RCHK(upload_active(h));
+        HIPCHK(up(s, h->kdim, kd));
+        gmres_backsolve(s, np, m, h->kdim, h->H, h->g, h->y);
+        int kmax = *std::max_element(kd.begin(), kd.end());
+        combine(h->D, s, h->Z, NL, kmax, h->y, m, sol, 1, 1.0);
+        bool rem = false;
+        for (int p = 0; p < np; ++p) rem |= todo[p] != 0;
+        if (!rem) break;
+    }
+    h->host_active = outer;
+    RCHK(upload_active(h));
+    HIPCHK(hipStreamSynchronize(s));
+    return NRD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// inexact Newton (lock-step), positivity by step halving
+// ---------------------------------------------------------------------------
+
+static nrd_status newton(nrd_hierarchy* h, std::vector<nrd_step_stats>& st) {
+    Tables& t = h->t;
+    const int np = t.nprob;
+    hipStream_t s = h->stream;
+    const nrd_options& O = h->opt;
+    st.assign(np, nrd_step_stats());
+    for (auto& x : st) std::memset(&x, 0, sizeof(x));
+    h->host_active.assign(np, 1);
+    RCHK(upload_active(h));
+    h->D.active = nullptr;
+    op_residual(h, h->x, h->F);
+    std::vector<double> f2;
+    nrd_status rc = dot_host(h, h->F, h->F, f2);
+    if (rc) return rc;
+    std::vector<double> fn(np), fn_old(np), stop(np), eta(np, 0.9), tol(np);
+    std::vector<int32_t> done(np, 0), failed(np, 0);
+    for (int p = 0; p < np; ++p) {
+        fn[p] = std::sqrt(f2[p]);
+        st[p].fnorm0 = fn[p];
+        stop[p] = std::max(O.newton_rtol * fn[p], O.newton_atol);
+        fn_old[p] = fn[p];
+    }
+    const double gamma = 0.9, eta_max = 0.9;
+    for (int k = 0;; ++k) {
+        bool any = false;
+        for (int p = 0; p < np; ++p) {
+            if (done[p] || failed[p]) continue;
+            if (!(fn[p] == fn[p])) {
+                failed[p] = 1;
+                continue;
+            }
+            if (fn[p] <= stop[p]) {
+                done[p] = 1;
+                continue;
+            }
+            if (st[p].newton_iters >= O.newton_maxit) {
+                failed[p] = 1;
+                continue;
+            }
+            any = true;
+            if (k > 0) {
+                const double rat = fn[p] / fn_old[p];
+                double en = gamma * rat * rat;
+                if (gamma * eta[p] * eta[p] > 0.1) en = std::max(en, gamma * eta[p] * eta[p]);
+                eta[p] = std::min(en, eta_max);
+                eta[p] = std::max(eta[p], 0.5 * stop[p] / fn[p]);
+            }
+            tol[p] = eta[p] * fn[p];
+        }
+        if (!any) break;
+        for (int p = 0; p < np; ++p) h->host_active[p] = !(done[p] || failed[p]);
+        RCHK(upload_active(h));
+        h->D.active = nullptr;
+        pc_setup(h, h->x, true);              // x was prepared by the residual
+        // s = J^-1 (-F)
+        std::vector<double> mone(np, -1.0);
+        HIPCHK(up(s, h->coefA, mone));
+        h->D.active = h->active;
+        scale_copy(h->D, s, h->F, h->coefA, h->rb);
+        std::vector<int32_t> its;
+        rc = fgmres(h, h->x, h->rb, h->s, tol, its, false);
+        if (rc) return rc;
+        std::vector<int32_t> act = h->host_active;
+        for (int p = 0; p < np; ++p)
+            if (act[p]) {
+                if (st[p].newton_iters < 24) st[p].krylov_per_newton[st[p].newton_iters] = its[p];
+                st[p].krylov_iters += its[p];
+            }
+        // positivity: halve lambda until E, T > 0 on composite cells
+        std::vector<double> lam(np, 1.0), mn(np);
+        std::vector<int32_t> ok(np, 0);
+        for (int p = 0; p < np; ++p) ok[p] = !act[p];
+        for (int cut = 0; cut <= 30; ++cut) {
+            HIPCHK(up(s, h->coefA, lam));
+            h->D.active = h->active;
+            min_positive(h->D, s, h->x, h->s, h->coefA, h->partial, h->minout);
+            HIPCHK(hipMemcpyAsync(mn.data(), h->minout, 8 * np, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            bool all = true;
+            for (int p = 0; p < np; ++p) {
+                if (ok[p]) continue;
+                if (mn[p] > 0.0) {
+                    ok[p] = 1;
+                } else if (cut < 30) {
+                    lam[p] *= 0.5;
+                    st[p].positivity_cuts += 1;
+                    all = false;
+                } else {
+                    failed[p] = 1;
+                }
+            }
+            if (all) break;
+            // only problems still searching need another pass
+            for (int p = 0; p < np; ++p) h->host_active[p] = act[p] && !ok[p] && !failed[p];
+            RCHK(upload_active(h));
+        }
+        for (int p = 0; p < np; ++p) h->host_active[p] = act[p] && !failed[p];
+        RCHK(upload_active(h));
+        std::vector<double> one(np, 1.0);
+        HIPCHK(up(s, h->coefA, lam));
+        HIPCHK(up(s, h->coefB, one));
+        h->D.active = h->active;
+        axpby(h->D, s, h->coefA, h->s, h->coefB, h->x);
+        h->D.active = nullptr;
+        op_residual(h, h->x, h->F);
+        rc = dot_host(h, h->F, h->F, f2);
+        if (rc) return rc;
+        for (int p = 0; p < np; ++p) {
+            if (!act[p]) continue;
+            fn_old[p] = fn[p];
+            fn[p] = std::sqrt(f2[p]);
+            st[p].newton_iters += 1;
+        }
+    }
+    bool all_ok = true;
+    for (int p = 0; p < np; ++p) {
+        st[p].fnorm = fn[p];
+        st[p].converged = done[p] && !failed[p];
+        all_ok &= st[p].converged != 0;
+    }
+    h->host_active.assign(np, 1);
+    RCHK(upload_active(h));
+    h->D.active = nullptr;
+    return all_ok ? NRD_OK : NRD_ENOTCONV;
+}
+
+static nrd_status implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_stats* stats,
+                                bool bdf1_only = false) {
+    Tables& t = h->t;
+    const int np = t.nprob;
+    hipStream_t s = h->stream;
+    nrd_status rc = begin_step(h, dt, bdf1_only);
+    if (rc) return rc;
+    // initial guess: leapfrog predictor (BDF2 steps) if positive, else u_n
+    h->D.active = nullptr;
+    copy_interior(h->D, s, h->cur, h->x);
+    bool any2 = false;
+    for (int p = 0; p < np; ++p) any2 |= h->alpha[p] > 0.0;
+    if (any2) {
+        // x = (1 - a^2) u_n + (1 + a) dt u'_n + a^2 u_{n-1}
+        std::vector<double> A(np), B(np), C(np), one(np, 1.0);
+        for (int p = 0; p < np; ++p) {
+            const double a = h->alpha[p];
+            const bool bdf2 = a > 0.0;
+            A[p] = bdf2 ? (1.0 + a) * dt[p] : 0.0;
+            B[p] = bdf2 ? a * a : 0.0;
+            C[p] = bdf2 ? -a * a : 0.0;
+        }
+        std::vector<double> buf(4 * np);
+        for (int p = 0; p < np; ++p) {
+            buf[p] = A[p];
+            buf[np + p] = B[p];
+            buf[2 * np + p] = C[p];
+            buf[3 * np + p] = 1.0;
+        }
+        HIPCHK(up(s, h->coefA, buf));
+        copy_interior(h->D, s, h->cur, h->tmp);
+        axpby(h->D, s, h->coefA, h->udot, h->coefA + 3 * np, h->tmp);        // + A udot
+        axpby(h->D, s, h->coefA + np, h->prev, h->coefA + 3 * np, h->tmp);   // + a^2 u_{n-1}
+        axpby(h->D, s, h->coefA + 2 * np, h->cur, h->coefA + 3 * np, h->tmp); // - a^2 u_n
+        // accept per problem if positive
+        std::vector<double> zero(np, 0.0), mn(np);
+        HIPCHK(up(s, h->coefB, zero));
+        min_positive(h->D, s, h->tmp, h->tmp, h->coefB, h->partial, h->minout);
+        HIPCHK(hipMemcpyAsync(mn.data(), h->minout, 8 * np, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<int32_t> use(np);
+        for (int p = 0; p < np; ++p) use[p] = (h->alpha[p] > 0.0) && mn[p] > 0.0;
+        h->host_active = use;
+        RCHK(upload_active(h));
+        h->D.active = h->active;
+        copy_interior(h->D, s, h->tmp, h->x);
+        h->host_active.assign(np, 1);
+        RCHK(upload_active(h));
+        h->D.active = nullptr;
+    }
+    std::vector<nrd_step_stats> st;
+    rc = newton(h, st);
+    if (stats)
+        for (int p = 0; p < np; ++p) stats[p] = st[p];
+    if (rc) {
+        if (rc == NRD_ENOTCONV) g_err = "Newton did not converge; state rolled back";
+        return rc;
+    }
+    // udot = (c0 x - b) / dt ; rotate history
+    std::vector<double> buf(2 * np);
+    for (int p = 0; p < np; ++p) {
+        buf[p] = h->c0[p] / dt[p];
+        buf[np + p] = -1.0 / dt[p];
+    }
+    HIPCHK(up(s, h->coefA, buf));
+    scale_copy(h->D, s, h->x, h->coefA, h->udot);
+    std::vector<double> one(np, 1.0);
+    HIPCHK(up(s, h->coefB, one));
+    // udot = -b/dt + udot
+    axpby(h->D, s, h->coefA + np, h->bvec, h->coefB, h->udot);
+    std::swap(h->prev, h->cur);       // prev <- u_n
+    std::swap(h->cur, h->x);          // cur <- u_{n+1}
+    // keep ghosts/covered of the new state consistent
+    prepare_state(h, h->cur);
+    for (int p = 0; p < np; ++p) h->dt_prev[p] = bdf1_only ? 0.0 : dt[p];
+    HIPCHK(hipStreamSynchronize(s));
+    h->step_ready = false;
+    return NRD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// discrete adjoint of BDF1 steps with checkpoints
+// ---------------------------------------------------------------------------
+
+static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, int every,
+                              const double* dJdE, double* gz) {
+    Tables& t = h->t;
+    const int np = t.nprob;
+    hipStream_t s = h->stream;
+    const int64_t NL = h->nl2();
+    if (t.nlev != 1) return fail(NRD_EUNSUPPORTED, "adjoint needs a single-level hierarchy");
+    if (nsteps <= 0 || every <= 0) return fail(NRD_EINVAL, "nsteps and ckpt_every must be > 0");
+    const int nck = (nsteps + every - 1) / every;
+    if (nck + every > h->adjoint_slots)
+        return fail(NRD_EINVAL, "workspace reserved too few adjoint slots");
+    double* ck = h->ckpt;                      // checkpoints 0..nck-1
+    double* seg = h->ckpt + (size_t)nck * NL;  // segment states 1..every
+    std::vector<double> dtv(dt, dt + np);
+    // forward with checkpoints of u_0, u_every, ...
+    for (int n = 0; n < nsteps; ++n) {
+        if (n % every == 0) copy_interior(h->D, s, h->cur, ck + (size_t)(n / every) * NL);
+        nrd_status rc = implicit_step(h, dtv.data(), nullptr, true);
+        if (rc) return rc;
+    }
+    // lambda_N rhs: (dJ/dE, 0)
+    double* rhs = h->rb;
+    fill_native(s, rhs, NL, 0.0);
+    if (dJdE) {
+        unpack(h->D, s, h->at<int64_t>(h->o.coff), dJdE, rhs, 1, t.ncells);
+    } else {
+        std::vector<double> ones(t.ncells, 1.0);
+        // build a compact vector of ones in gz scratch region via host upload
+        HIPCHK(hipMemcpyAsync(gz, ones.data(), 8 * t.ncells, hipMemcpyHostToDevice, s));
+        unpack(h->D, s, h->at<int64_t>(h->o.coff), gz, rhs, 1, t.ncells);
+    }
+    double* lam = h->udot;                     // reuse: the adjoint ends the run
+    double* gacc = h->bvec;                    // dJ/dz^3 accumulator (field 0)
+    fill_native(s, gacc, NL, 0.0);
+    for (int p = 0; p < np; ++p) {
+        h->ps_host[p].dt = dt[p];
+        h->ps_host[p].c0 = 1.0;
+        h->ps_host[p].beta = dt[p];
+        h->ps_host[p].alpha = 0.0;
+    }
+    HIPCHK(up(s, h->ps, h->ps_host));
+    for (int segi = nck - 1; segi >= 0; --segi) {
+        const int n0 = segi * every;
+        const int n1 = std::min(nsteps, n0 + every);
+        // recompute u_{n0+1..n1} from the checkpoint
+        copy_interior(h->D, s, ck + (size_t)segi * NL, h->cur);
+        prepare_state(h, h->cur);
+        for (int p = 0; p < np; ++p) h->dt_prev[p] = 0.0;
+        for (int n = n0; n < n1; ++n) {
+            nrd_status rc = implicit_step(h, dtv.data(), nullptr, true);
+            if (rc) return rc;
+            copy_interior(h->D, s, h->cur, seg + (size_t)(n - n0) * NL);
+        }
+        for (int p = 0; p < np; ++p) {
+            h->ps_host[p].dt = dt[p];
+            h->ps_host[p].c0 = 1.0;
+            h->ps_host[p].beta = dt[p];
+        }
+        HIPCHK(up(s, h->ps, h->ps_host));
+        for (int n = n1; n > n0; --n) {
+            double* un = seg + (size_t)(n - n0 - 1) * NL;
+            prepare_state(h, un);
+            pc_setup(h, un, true);
+            // A_n^T lam = rhs
+            std::vector<double> r2;
+            nrd_status rc = dot_host(h, rhs, rhs, r2);
+            if (rc) return rc;
+            std::vector<double> tol(np);
+            for (int p = 0; p < np; ++p) tol[p] = 1e-12 * std::sqrt(r2[p]);
+            std::vector<int32_t> its;
+            h->host_active.assign(np, 1);
+            RCHK(upload_active(h));
+            rc = fgmres(h, un, rhs, lam, tol, its, true);
+            if (rc) return rc;
+            // grad -= lam^T dF/dz^3 ; next rhs = lam
+            ghost_fill_d(h->D, s, lam, 2);
+            vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], un, lam, h->w, h->gz3);
+            std::vector<double> mone(np, -1.0), one(np, 1.0);
+            HIPCHK(up(s, h->coefA, mone));
+            HIPCHK(up(s, h->coefB, one));
+            // gacc (field 0 only used) += -gz3 : use a 2-field axpby on (gz3 | scratch)
+            {
+                // gz3 is a single field; place it in tmp field 0, zero field 1
+                fill_native(s, h->tmp, NL, 0.0);
+                HIPCHK(hipMemcpyAsync(h->tmp, h->gz3, 8 * t.nl, hipMemcpyDeviceToDevice, s));
+                axpby(h->D, s, h->coefA, h->tmp, h->coefB, gacc);
+            }
+            copy_interior(h->D, s, lam, rhs);
+        }
+    }
+    // gz = 3 z^2 gacc (compact)
+    {
+        // tmp field 0 = 3 z^2 * gacc field 0
+        std::vector<double> zz;
+        pack(h->D, s, h->at<int64_t>(h->o.coff), gacc, gz, 1, t.ncells);
+        pack(h->D, s, h->at<int64_t>(h->o.coff), h->z, h->tmp, 1, t.ncells);
+        std::vector<double> g(t.ncells), zc(t.ncells);
+        HIPCHK(hipMemcpyAsync(g.data(), gz, 8 * t.ncells, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(zc.data(), h->tmp, 8 * t.ncells, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < t.ncells; ++i) g[i] *= 3.0 * zc[i] * zc[i];
+        HIPCHK(hipMemcpyAsync(gz, g.data(), 8 * t.ncells, hipMemcpyHostToDevice, s));
+    }
+    // the state ends at u_N: recompute it from the last checkpoint
+    copy_interior(h->D, s, ck + (size_t)(nck - 1) * NL, h->cur);
+    prepare_state(h, h->cur);
+    for (int n = (nck - 1) * every; n < nsteps; ++n) {
+        nrd_status rc = implicit_step(h, dtv.data(), nullptr, true);
+        if (rc) return rc;
+    }
+    for (int p = 0; p < np; ++p) h->dt_prev[p] = 0.0;
+    HIPCHK(hipStreamSynchronize(s));
+    return NRD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* nrd_last_error(void) { return g_err.c_str(); }
+
+void nrd_default_options(nrd_options* o) {
+    std::memset(o, 0, sizeof(*o));
+    o->precision = NRD_FP64;
+    o->launch = NRD_BATCHED;
+    o->use_graph = 0;
+    o->jvp_mode = NRD_JVP_ANALYTIC;
+    o->limiter = 1.0;
+    o->p2_mode = NRD_P2_PAPER;
+    o->newton_rtol = 1e-8;
+    o->newton_atol = 1e-14;
+    o->newton_maxit = 20;
+    o->gmres_restart = 30;
+    o->gmres_maxrestarts = 10;
+    o->mg_nu_pre = 1;
+    o->mg_nu_post = 1;
+}
+
+nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const nrd_box* boxes,
+                                int32_t nbox, const nrd_options* opt, void* hip_stream,
+                                nrd_hierarchy** out) {
+    if (!out) return fail(NRD_EINVAL, "out is NULL");
+    try {
+        nrd_hierarchy* h = new nrd_hierarchy();
+        if (opt)
+            h->opt = *opt;
+        else
+            nrd_default_options(&h->opt);
+        if (h->opt.gmres_restart < 1 || h->opt.gmres_restart > 64) {
+            delete h;
+            return fail(NRD_EINVAL, "gmres_restart must be in [1, 64]");
+        }
+        if (h->opt.newton_maxit < 1 || h->opt.newton_maxit > 24) {
+            delete h;
+            return fail(NRD_EINVAL, "newton_maxit must be in [1, 24]");
+        }
+        if (h->opt.jvp_mode == NRD_JVP_FD) {
+            delete h;
+            return fail(NRD_EUNSUPPORTED, "finite-difference Jacobian action is not built");
+        }
+        h->m = h->opt.gmres_restart;
+        h->mixed = h->opt.precision == NRD_MIXED;
+        h->adjoint_slots = std::max(0, h->opt.adjoint_slots);
+        h->stream = static_cast<hipStream_t>(hip_stream);
+        std::string msg;
+        nrd_status rc = build_tables(probs, nprob, boxes, nbox, kBlock, 8 * kBlock, h->t, msg);
+        if (rc) {
+            delete h;
+            return fail(rc, msg);
+        }
+        if (h->t.nlev > kMaxLev || (int)h->t.mg.size() > kMaxMG) {
+            delete h;
+            return fail(NRD_EUNSUPPORTED, "too many levels");
+        }
+        h->patch_tile0.assign(h->t.nbox, 0);
+        {
+            // tiles are grouped per patch in level order
+            std::vector<int32_t> first(h->t.nbox, -1);
+            for (size_t i = 0; i < h->t.tiles.size(); ++i)
+                if (first[h->t.tiles[i].patch] < 0) first[h->t.tiles[i].patch] = (int32_t)i;
+            h->patch_tile0 = first;
+        }
+        h->dt_prev.assign(h->t.nprob, 0.0);
+        layout(h);
+        *out = h;
+        return NRD_OK;
+    } catch (const std::exception& e) {
+        return fail(NRD_EINVAL, e.what());
+    }
+}
+
+nrd_status nrd_hierarchy_destroy(nrd_hierarchy* h) {
+    if (!h) return NRD_OK;
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    delete h;
+    return NRD_OK;
+}
+
+nrd_status nrd_workspace_size(const nrd_hierarchy* h, size_t* bytes) {
+    if (!h || !bytes) return fail(NRD_EINVAL, "NULL argument");
+    *bytes = h->ws_bytes;
+    return NRD_OK;
+}
+
+nrd_status nrd_bind_workspace(nrd_hierarchy* h, void* ptr, size_t bytes) {
+    if (!h || !ptr) return fail(NRD_EINVAL, "NULL argument");
+    return bind(h, ptr, bytes);
+}
+
+nrd_status nrd_layout(const nrd_hierarchy* h, int64_t* ncells, int64_t* native_len) {
+    if (!h) return fail(NRD_EINVAL, "NULL hierarchy");
+    if (ncells) *ncells = h->t.ncells;
+    if (native_len) *native_len = h->t.nl;
+    return NRD_OK;
+}
+
+#define NEED_BOUND(h)                                                        \
+    do {                                                                     \
+        if (!(h)) return fail(NRD_EINVAL, "NULL hierarchy");                 \
+        if (!(h)->bound) return fail(NRD_ESTATE, "no workspace bound");      \
+    } while (0)
+
+nrd_status nrd_pack(nrd_hierarchy* h, const double* native, double* compact) {
+    NEED_BOUND(h);
+    pack(h->D, h->stream, h->at<int64_t>(h->o.coff), native, compact, 2, h->t.ncells);
+    HIPCHK(hipGetLastError());
+    return NRD_OK;
+}
+
+nrd_status nrd_unpack(nrd_hierarchy* h, const double* compact, double* native) {
+    NEED_BOUND(h);
+    unpack(h->D, h->stream, h->at<int64_t>(h->o.coff), compact, native, 2, h->t.ncells);
+    HIPCHK(hipGetLastError());
+    return NRD_OK;
+}
+
+nrd_status nrd_set_fields(nrd_hierarchy* h, const double* E, const double* T, const double* z) {
+    NEED_BOUND(h);
+    if (!E || !T || !z) return fail(NRD_EINVAL, "NULL field");
+    hipStream_t s = h->stream;
+    const int64_t nc = h->t.ncells;
+    const int64_t* coff = h->at<int64_t>(h->o.coff);
+    // stage into scratch first so that a rejected input leaves the state intact
+    unpack(h->D, s, coff, E, h->tmp, 1, nc);
+    unpack(h->D, s, coff, T, h->tmp + h->t.nl, 1, nc);
+    unpack(h->D, s, coff, z, h->tmp2, 1, nc);
+    fill_native(s, reinterpret_cast<double*>(h->flag), 1, 0.0);
+    h->D.active = nullptr;
+    check_positive(h->D, s, h->tmp, 2, h->flag);
+    check_positive(h->D, s, h->tmp2, 1, h->flag);
+    int32_t bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, h->flag, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) return fail(NRD_ENONPOS, "E, T and z must be positive and finite");
+    copy_interior(h->D, s, h->tmp, h->cur);
+    HIPCHK(hipMemcpyAsync(h->z, h->tmp2, 8 * h->t.nl, hipMemcpyDeviceToDevice, s));
+    prepare_state(h, h->cur);
+    ghost_fill_d(h->D, s, h->z, 1);
+    cube(s, h->z, h->z3, h->t.nl);
+    copy_interior(h->D, s, h->cur, h->prev);
+    fill_native(s, h->udot, 2 * h->t.nl, 0.0);
+    std::fill(h->dt_prev.begin(), h->dt_prev.end(), 0.0);
+    h->step_ready = false;
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    return NRD_OK;
+}
+
+nrd_status nrd_get_fields(nrd_hierarchy* h, double* E, double* T) {
+    NEED_BOUND(h);
+    hipStream_t s = h->stream;
+    const int64_t nc = h->t.ncells;
+    const int64_t* coff = h->at<int64_t>(h->o.coff);
+    if (E) pack(h->D, s, coff, h->cur, E, 1, nc);
+    if (T) pack(h->D, s, coff, h->cur + h->t.nl, T, 1, nc);
+    HIPCHK(hipStreamSynchronize(s));
+    return NRD_OK;
+}
+
+nrd_status nrd_begin_step(nrd_hierarchy* h, const double* dt) {
+    NEED_BOUND(h);
+    if (!dt) return fail(NRD_EINVAL, "NULL dt");
+    return begin_step(h, dt);
+}
+
+nrd_status nrd_residual(nrd_hierarchy* h, double* u, double* F) {
+    NEED_BOUND(h);
+    if (!h->step_ready) return fail(NRD_ESTATE, "call nrd_begin_step first");
+    h->D.active = nullptr;
+    op_residual(h, u, F);
+    HIPCHK(hipGetLastError());
+    return NRD_OK;
+}
+
+nrd_status nrd_jvp(nrd_hierarchy* h, double* u, double* v, double* Jv) {
+    NEED_BOUND(h);
+    if (!h->step_ready) return fail(NRD_ESTATE, "call nrd_begin_step first");
+    h->D.active = nullptr;
+    op_jvp(h, u, v, Jv, false);
+    HIPCHK(hipGetLastError());
+    return NRD_OK;
+}
+
+nrd_status nrd_precond_setup(nrd_hierarchy* h, double* u) {
+    NEED_BOUND(h);
+    if (!h->step_ready) return fail(NRD_ESTATE, "call nrd_begin_step first");
+    h->D.active = nullptr;
+    pc_setup(h, u, false);
+    HIPCHK(hipGetLastError());
+    return NRD_OK;
+}
+
+nrd_status nrd_precond_apply(nrd_hierarchy* h, const double* w, double* y) {
+    NEED_BOUND(h);
+    if (!h->step_ready) return fail(NRD_ESTATE, "call nrd_begin_step first");
+    h->D.active = nullptr;
+    pc_apply(h, w, y);
+    HIPCHK(hipGetLastError());
+    return NRD_OK;
+}
+
+nrd_status nrd_vjp(nrd_hierarchy* h, double* u, double* lam, double* JTl, double* gz) {
+    NEED_BOUND(h);
+    if (!h->step_ready) return fail(NRD_ESTATE, "call nrd_begin_step first");
+    if (h->t.nlev != 1) return fail(NRD_EUNSUPPORTED, "transpose needs a single-level hierarchy");
+    hipStream_t s = h->stream;
+    h->D.active = nullptr;
+    prepare_state(h, u);
+    ghost_fill_d(h->D, s, lam, 2);
+    vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], u, lam, JTl, h->gz3);
+    if (gz) {
+        // gz = 3 z^2 * dF/dz^3 (compact): stage z into tmp field 1
+        const int64_t* coff = h->at<int64_t>(h->o.coff);
+        pack(h->D, s, coff, h->gz3, gz, 1, h->t.ncells);
+        std::vector<double> g(h->t.ncells), zc(h->t.ncells);
+        pack(h->D, s, coff, h->z, h->tmp, 1, h->t.ncells);
+        HIPCHK(hipMemcpyAsync(g.data(), gz, 8 * h->t.ncells, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(zc.data(), h->tmp, 8 * h->t.ncells, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < h->t.ncells; ++i) g[i] *= 3.0 * zc[i] * zc[i];
+        HIPCHK(hipMemcpyAsync(gz, g.data(), 8 * h->t.ncells, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    HIPCHK(hipGetLastError());
+    return NRD_OK;
+}
+
+nrd_status nrd_implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_stats* stats) {
+    NEED_BOUND(h);
+    if (!dt) return fail(NRD_EINVAL, "NULL dt");
+    nrd_status rc = implicit_step(h, dt, stats);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(NRD_EDEVICE, hipGetErrorString(e));
+    return rc;
+}
+
+nrd_status nrd_adjoint_run(nrd_hierarchy* h, const double* dt, int32_t nsteps, int32_t every,
+                           const double* dJdE, double* gz) {
+    NEED_BOUND(h);
+    if (!dt || !gz) return fail(NRD_EINVAL, "NULL argument");
+    return adjoint_run(h, dt, nsteps, every, dJdE, gz);
+}
+
+nrd_status nrd_dot(nrd_hierarchy* h, const double* x, const double* y, double* out) {
+    NEED_BOUND(h);
+    std::vector<double> v;
+    nrd_status rc = dot_host(h, x, y, v);
+    if (rc) return rc;
+    std::copy(v.begin(), v.end(), out);
+    return NRD_OK;
+}
+
+nrd_status nrd_timer_enable(nrd_hierarchy* h, int32_t on) {
+    if (!h) return fail(NRD_EINVAL, "NULL hierarchy");
+    h->timing = on != 0;
+    h->ev_pairs.clear();
+    h->ev_used = 0;
+    return NRD_OK;
+}
+
+nrd_status nrd_timer_read(nrd_hierarchy* h, int32_t which, double* ms, int32_t* count) {
+    if (!h) return fail(NRD_EINVAL, "NULL hierarchy");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double tot = 0.0;
+    int32_t n = 0;
+    for (auto& pr : h->ev_pairs) {
+        if (pr.first != which) continue;
+        float dtm = 0.f;
+        HIPCHK(hipEventElapsedTime(&dtm, pr.second.first, pr.second.second));
+        tot += dtm;
+        ++n;
+    }
+    if (ms) *ms = tot;
+    if (count) *count = n;
+    return NRD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// Preconditioner state and drivers (see precond.hip).
+#pragma once
+
+#include "kernels.h"
+
+namespace nrd {
+
+constexpr int kMaxMG = 12;
+
+struct MGDev {
+    int G = 0;                                   // deepest grid index
+    const PatchInfo* box[kMaxMG] = {};           // grid g >= 1 box tables
+    int64_t len[kMaxMG] = {};                    // ghosted cells per field
+    const Tile* tiles[kMaxMG] = {};              // all boxes of grid g >= 1
+    int ntiles[kMaxMG] = {};
+    const int32_t* box_of[kMaxMG] = {};          // [nprob]: box of problem in
+                                                 // grid g (g = 0: patch id)
+    const Tile* smooth_tiles[kMaxMG] = {};       // grid g boxes of problems
+    int nsmooth[kMaxMG] = {};                    // deeper than g
+    const int32_t* bottom_probs[kMaxMG] = {};    // problems whose coarsest
+    const int32_t* bottom_boxes[kMaxMG] = {};    // grid is g
+    int nbottom[kMaxMG] = {};
+    const int64_t* bottom_off = nullptr;         // [nprob] in N^2 units
+    double* Lbuf = nullptr;
+    double* Xbuf = nullptr;
+};
+
+template <typename PT>
+struct PcArrays {
+    const Dev* D = nullptr;
+    PT* Dface = nullptr;        // 6 * nl: (field * 3 + d) * nl
+    PT* sigma = nullptr;        // nl
+    PT* e = nullptr;            // 2 * nl each
+    PT* u = nullptr;
+    PT* r = nullptr;
+    PT* f = nullptr;
+    PT* tmp = nullptr;
+    PT* shadow = nullptr;       // 2 * shadow_len
+    const int32_t* shadow_src = nullptr;
+    const ShadowPatch* shadows = nullptr;
+    int64_t shadow_len = 0;
+    struct MGArr {
+        int G = 0;
+        const PatchInfo* box[kMaxMG] = {};
+        int64_t len[kMaxMG] = {};
+        const Tile* tiles[kMaxMG] = {};
+        int ntiles[kMaxMG] = {};
+        const int32_t* box_of[kMaxMG] = {};
+        const Tile* smooth_tiles[kMaxMG] = {};
+        int nsmooth[kMaxMG] = {};
+        const int32_t* bottom_probs[kMaxMG] = {};
+        const int32_t* bottom_boxes[kMaxMG] = {};
+        int nbottom[kMaxMG] = {};
+        const int64_t* bottom_off = nullptr;
+        double* Lbuf = nullptr;
+        double* Xbuf = nullptr;
+        PT* Dg[kMaxMG] = {};
+        PT* eg[kMaxMG] = {};
+        PT* fg[kMaxMG] = {};
+        PT* rg[kMaxMG] = {};
+    } mg;
+    int p2_mode = 0;
+    int nu_pre = 1, nu_post = 1;
+
+    void zero(hipStream_t s) const;
+    void setup(hipStream_t s, const double* u_state) const;
+    void apply(hipStream_t s, const double* w, double* y) const;
+    void apply_transpose(hipStream_t s, const double* w, double* y) const;
+    void fac(hipStream_t s) const;
+    void vcycle(hipStream_t s) const;
+    void composite_residual(hipStream_t s) const;
+    void fill_ghosts(hipStream_t s, PT* x) const;
+    void restrict_(hipStream_t s, PT* x, int lev_lo) const;
+    void siblings(hipStream_t s, PT* x, int lev) const;
+};
+
+}  // namespace nrd

@@ -1,0 +1,826 @@
+// Physics-based preconditioner kernels (paper Sec. 4.2-4.3, Alg. 1).
+//
+// P1 = diag(I - beta div D_E grad, I - beta div D_T grad) with D frozen at
+// u^k, approximately inverted by one FAC V(1,0) cycle: one red-black
+// Gauss-Seidel sweep per refinement level and a multigrid V(1,1) cycle on
+// the base level whose coarsest grid is solved with a dense float64
+// inverse.  P2 is the per-cell 2x2 coupling block.  PT is the storage and
+// arithmetic type of the V-cycle (float in mixed precision, double
+// otherwise); the bottom solve always uses double.
+//
+// Face coefficient arrays hold D at the LOW face of every cell in the
+// native layout, so cell c's high face along d is the low face of c + st_d
+// (for the last cell: the ghost slot).  On physical faces they hold the
+// unlimited boundary coefficient D_b of E for a Marshak face and 0
+// otherwise.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "precond.h"
+
+namespace nrd {
+
+static inline int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+__device__ __forceinline__ void coords(const PatchInfo& p, int lin, int& i, int& j, int& k) {
+    i = lin % p.n[0];
+    const int r = lin / p.n[0];
+    j = r % p.n[1];
+    k = r / p.n[1];
+}
+__device__ __forceinline__ int nat(const PatchInfo& p, int i, int j, int k) {
+    return p.off + (i + 1) + p.sy * (j + 1) + p.sz * (k + 1);
+}
+
+// ---------------------------------------------------------------------------
+// snapshot: D_E, D_T on every face of every patch, sigma per cell
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void face_D(double Ea, double Eb, double Ta, double Tb,
+                                       double za, double zb, double h, double kappa,
+                                       double lam, double& DE, double& DT) {
+    const double Tf = 0.5 * (Ta + Tb);
+    const double Tf3 = Tf * Tf * Tf;
+    const double S = Ea + Eb;
+    // D_h / (1 + lam D_h g) with D_h = 2 Tf^3 / (3 Zf), g = 2|dE| / (h S)
+    DE = 2.0 * Tf3 * h * S / (3.0 * (za + zb) * h * S + 4.0 * lam * Tf3 * fabs(Eb - Ea));
+    DT = kappa * Tf * Tf * sqrt(Tf);
+}
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_snapshot(
+    const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
+    const ProbScalars* __restrict__ ps, const double* __restrict__ u,
+    const double* __restrict__ z3, PT* __restrict__ Dface, PT* __restrict__ sigma,
+    int64_t nl) {
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    const ProbScalars& q = ps[t.prob];
+    int id[3];
+    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(p, id[0], id[1], id[2]);
+    const int st[3] = {1, p.sy, p.sz};
+    const double E = u[c], T = u[c + nl], z = z3[c];
+    sigma[c] = (PT)(z / (T * T * T));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (s == 1 && id[d] != p.n[d] - 1) continue;     // high face owned by c+st
+            const int slot = s ? c + st[d] : c;
+            double DE, DT;
+            if ((id[d] == (s ? p.n[d] - 1 : 0)) && ((p.phys >> (2 * d + s)) & 1)) {
+                DT = 0.0;
+                DE = ((p.robin >> (2 * d + s)) & 1) ? T * T * T / (3.0 * z) : 0.0;
+            } else {
+                const int nb = s ? c + st[d] : c - st[d];
+                if (s)
+                    face_D(E, u[nb], T, u[nb + nl], z, z3[nb], p.h[d], q.kappa, q.lam, DE, DT);
+                else
+                    face_D(u[nb], E, u[nb + nl], T, z3[nb], z, p.h[d], q.kappa, q.lam, DE, DT);
+            }
+            Dface[(0 * 3 + d) * nl + slot] = (PT)DE;
+            Dface[(1 * 3 + d) * nl + slot] = (PT)DT;
+        }
+    }
+}
+
+// Coarse face coefficient = mean of the four fine face coefficients
+// (grid g+1 from grid g); boundary faces included.
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_mg_coarsen(
+    const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pc,
+    const PatchInfo* __restrict__ Pf, const int32_t* __restrict__ fbox,
+    const PT* __restrict__ Df, int64_t nlf, PT* __restrict__ Dc, int64_t nlc) {
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& pc = Pc[t.patch];
+    const PatchInfo& pf = Pf[fbox[t.prob]];
+    int id[3];
+    coords(pc, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(pc, id[0], id[1], id[2]);
+    const int stc[3] = {1, pc.sy, pc.sz};
+    const int stf[3] = {1, pf.sy, pf.sz};
+    const int f0 = nat(pf, 2 * id[0], 2 * id[1], 2 * id[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int t1 = d == 0 ? 1 : 0;
+        const int t2 = d == 2 ? 1 : 2;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (s == 1 && id[d] != pc.n[d] - 1) continue;
+            const int slot = s ? c + stc[d] : c;
+            const int fs = s ? f0 + 2 * stf[d] : f0;
+            for (int fld = 0; fld < 2; ++fld) {
+                const PT* src = Df + (fld * 3 + d) * nlf;
+                const PT v = (src[fs] + src[fs + stf[t1]]) + (src[fs + stf[t2]] +
+                                                              src[fs + stf[t1] + stf[t2]]);
+                Dc[(fld * 3 + d) * nlc + slot] = v * PT(0.25);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// level operator: (A e)_c = diag_c e_c - sum w_f e_nb
+//   interior / sibling faces: w = a = beta D / h^2, diag += a
+//   coarse-fine faces (correction ghost = e_c / 3): diag += 2/3 a
+//   Marshak faces (E): diag += 2 beta D_b / ((4 D_b + h) h)
+// ---------------------------------------------------------------------------
+
+template <typename PT, int MODE>   // MODE 0: RBGS colour (ZERO start) 1: colour 2: residual
+__device__ __forceinline__ void level_cell(const PatchInfo& p, const int id[3], int c,
+                                          int fld, const PT* __restrict__ D, int64_t nl,
+                                          double beta, const uint8_t* __restrict__ ctype,
+                                          const PT* __restrict__ e, PT& diag, PT& nsum) {
+    const int st[3] = {1, p.sy, p.sz};
+    PT dg = PT(1);
+    PT ns = PT(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const PT bh2 = (PT)(beta * p.ih[d] * p.ih[d]);
+        const PT* Dd = D + (fld * 3 + d) * nl;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int slot = s ? c + st[d] : c;
+            const PT a = bh2 * Dd[slot];
+            const int nb = s ? c + st[d] : c - st[d];
+            const bool edge = id[d] == (s ? p.n[d] - 1 : 0);
+            if (edge && ((p.phys >> (2 * d + s)) & 1)) {
+                if (fld == 0 && ((p.robin >> (2 * d + s)) & 1)) {
+                    const double Db = (double)Dd[slot];
+                    dg += (PT)(2.0 * beta * Db / ((4.0 * Db + p.h[d]) * p.h[d]));
+                }
+                continue;
+            }
+            if (edge && ctype[nb] == GK_CF) {
+                dg += PT(2.0 / 3.0) * a;
+                continue;
+            }
+            dg += a;
+            if (MODE != 0) ns += a * e[nb];
+        }
+    }
+    diag = dg;
+    nsum = ns;
+}
+
+template <typename PT, int MODE>
+__global__ __launch_bounds__(kBlock) void k_level(
+    const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
+    const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
+    const PT* __restrict__ D, const PT* __restrict__ f, PT* __restrict__ e,
+    PT* __restrict__ r, int colour, int64_t nl) {
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    int id[3];
+    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    if (MODE != 2 && (((id[0] + id[1] + id[2] + p.lo[0] + p.lo[1] + p.lo[2]) & 1) != colour))
+        return;
+    const int c = nat(p, id[0], id[1], id[2]);
+    const double beta = ps[t.prob].beta;
+    for (int fld = 0; fld < 2; ++fld) {
+        PT dg, ns;
+        level_cell<PT, MODE>(p, id, c, fld, D, nl, beta, ctype, e + fld * nl, dg, ns);
+        const int64_t cf = fld * nl + c;
+        if (MODE == 2)
+            r[cf] = f[cf] - (dg * e[cf] - ns);
+        else
+            e[cf] = (f[cf] + ns) / dg;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// composite operator residual r = f - A^c u on composite cells (covered -> 0)
+// with flux form on every face; coarse faces bordering a finer level are
+// skipped here and supplied by k_comp_reflux.
+// ---------------------------------------------------------------------------
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_comp_res(
+    const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
+    const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
+    const PT* __restrict__ D, const PT* __restrict__ f, const PT* __restrict__ u,
+    PT* __restrict__ r, int64_t nl) {
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    int id[3];
+    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(p, id[0], id[1], id[2]);
+    const int ct = (p.flags & PF_CTYPE) ? ctype[c] : 0;
+    if (ct & CT_COVERED) {
+        r[c] = PT(0);
+        r[c + nl] = PT(0);
+        return;
+    }
+    const double beta = ps[t.prob].beta;
+    const int st[3] = {1, p.sy, p.sz};
+    for (int fld = 0; fld < 2; ++fld) {
+        const PT* uf = u + fld * nl;
+        const PT uc = uf[c];
+        PT div = PT(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const PT* Dd = D + (fld * 3 + d) * nl;
+            const PT ih = (PT)p.ih[d];
+            PT lo = PT(0), hi = PT(0);
+            if (id[d] == 0 && ((p.phys >> (2 * d)) & 1)) {
+                if (fld == 0 && ((p.robin >> (2 * d)) & 1)) {
+                    const PT Db = Dd[c];
+                    lo = PT(2) * Db * uc / (PT(4) * Db + (PT)p.h[d]);
+                }
+            } else if (!((ct >> (2 * d + 1)) & 1)) {
+                lo = Dd[c] * (uc - uf[c - st[d]]) * ih;
+            }
+            const int up = c + st[d];
+            if (id[d] == p.n[d] - 1 && ((p.phys >> (2 * d + 1)) & 1)) {
+                if (fld == 0 && ((p.robin >> (2 * d + 1)) & 1)) {
+                    const PT Db = Dd[up];
+                    hi = -PT(2) * Db * uc / (PT(4) * Db + (PT)p.h[d]);
+                }
+            } else if (!((ct >> (2 * d + 2)) & 1)) {
+                hi = Dd[up] * (uf[up] - uc) * ih;
+            }
+            div += (hi - lo) * ih;
+        }
+        r[fld * nl + c] = f[fld * nl + c] - (uc - (PT)beta * div);
+    }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_comp_reflux(
+    const RefluxCell* __restrict__ rc, int n, const RefluxFace* __restrict__ rf,
+    const PatchInfo* __restrict__ P, const ProbScalars* __restrict__ ps,
+    const PT* __restrict__ D, const PT* __restrict__ u, PT* __restrict__ r, int64_t nl) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const RefluxCell cell = rc[t];
+    const double beta = ps[cell.prob].beta;
+    for (int fld = 0; fld < 2; ++fld) {
+        const PT* uf = u + fld * nl;
+        PT acc = PT(0);
+        for (int e = cell.first; e < cell.first + cell.count; ++e) {
+            const RefluxFace fc = rf[e];
+            const int d = fc.face >> 1;
+            const bool hi = fc.face & 1;
+            const PatchInfo& fp = P[fc.fpatch];
+            const PT* Dd = D + (fld * 3 + d) * nl;
+            const PT ih = (PT)fp.ih[d];
+            PT sum = PT(0);
+            for (int k = 0; k < 4; ++k) {
+                const int fi = fc.fine[k];
+                const int g = fi + fc.gofs;
+                // fine face: lower cell a, upper cell b; its D sits at b's slot
+                const int a = hi ? g : fi;
+                const int b = hi ? fi : g;
+                sum += Dd[b] * (uf[b] - uf[a]) * ih;
+            }
+            acc += (hi ? PT(1) : PT(-1)) * PT(0.25) * sum * (PT(0.5) * ih);
+        }
+        r[fld * nl + cell.c] += (PT)beta * acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// transfers
+// ---------------------------------------------------------------------------
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ src, int n,
+                                                   const PT* __restrict__ x, int64_t nlx,
+                                                   PT* __restrict__ y, int64_t nly) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int s = src[t];
+    y[t] = x[s];
+    y[t + nly] = x[s + nlx];
+}
+
+// Trilinear prolongation (weights 3/4, 1/4 per axis) of the shadow block of
+// each level-m patch onto its cells: e = P e_coarse, u += e.
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_prolong_level(
+    const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
+    const ShadowPatch* __restrict__ SP, const PT* __restrict__ sh, int64_t nls,
+    PT* __restrict__ e, PT* __restrict__ u, int64_t nl) {
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    const ShadowPatch sp = SP[t.patch];
+    int id[3];
+    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(p, id[0], id[1], id[2]);
+    int q[3], o[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int g = p.lo[d] + id[d];
+        q[d] = (g >> 1) - (p.lo[d] >> 1) + 1;      // shadow has a one-cell halo
+        o[d] = (g & 1) ? 1 : -1;
+    }
+    const int sy = sp.m0, sz = sp.m0 * sp.m1;
+    const int base = sp.off + q[0] + sy * q[1] + sz * q[2];
+    const int ox = o[0], oy = o[1] * sy, oz = o[2] * sz;
+    for (int fld = 0; fld < 2; ++fld) {
+        const PT* s = sh + fld * nls + base;
+        const PT v = PT(27.0 / 64) * s[0] +
+                     PT(9.0 / 64) * (s[ox] + s[oy] + s[oz]) +
+                     PT(3.0 / 64) * (s[ox + oy] + s[ox + oz] + s[oy + oz]) +
+                     PT(1.0 / 64) * s[ox + oy + oz];
+        e[fld * nl + c] = v;
+        u[fld * nl + c] += v;
+    }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_add_level(const Tile* __restrict__ tiles,
+                                                      const PatchInfo* __restrict__ P,
+                                                      const PT* __restrict__ e,
+                                                      PT* __restrict__ u, int64_t nl) {
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    int id[3];
+    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(p, id[0], id[1], id[2]);
+    u[c] += e[c];
+    u[c + nl] += e[c + nl];
+}
+
+// multigrid: restriction (mean of 8) from grid g to g+1
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(
+    const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pc,
+    const PatchInfo* __restrict__ Pf, const int32_t* __restrict__ fbox,
+    const PT* __restrict__ rf, int64_t nlf, PT* __restrict__ fc, int64_t nlc) {
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& pc = Pc[t.patch];
+    const PatchInfo& pf = Pf[fbox[t.prob]];
+    int id[3];
+    coords(pc, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(pc, id[0], id[1], id[2]);
+    const int f0 = nat(pf, 2 * id[0], 2 * id[1], 2 * id[2]);
+    for (int fld = 0; fld < 2; ++fld) {
+        const PT* y = rf + fld * nlf + f0;
+        PT acc = y[0];
+        acc += y[1];
+        acc += y[pf.sy];
+        acc += y[pf.sy + 1];
+        acc += y[pf.sz];
+        acc += y[pf.sz + 1];
+        acc += y[pf.sz + pf.sy];
+        acc += y[pf.sz + pf.sy + 1];
+        fc[fld * nlc + c] = acc * PT(0.125);
+    }
+}
+
+// multigrid: e_g += trilinear prolongation of e_{g+1} (copy rule at edges)
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_mg_prolong(
+    const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pf,
+    const PatchInfo* __restrict__ Pc, const int32_t* __restrict__ cbox,
+    const PT* __restrict__ ec, int64_t nlc, PT* __restrict__ ef, int64_t nlf) {
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& pf = Pf[t.patch];
+    const PatchInfo& pc = Pc[cbox[t.prob]];
+    int id[3];
+    coords(pf, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(pf, id[0], id[1], id[2]);
+    int q[3], nbq[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        q[d] = id[d] >> 1;
+        const int o = (id[d] & 1) ? 1 : -1;
+        nbq[d] = min(max(q[d] + o, 0), pc.n[d] - 1);
+    }
+    for (int fld = 0; fld < 2; ++fld) {
+        const PT* s = ec + fld * nlc;
+        PT v = PT(0);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    const PT w = (a ? PT(0.25) : PT(0.75)) * (b ? PT(0.25) : PT(0.75)) *
+                                 (cc ? PT(0.25) : PT(0.75));
+                    v += w * s[nat(pc, a ? nbq[0] : q[0], b ? nbq[1] : q[1],
+                                   cc ? nbq[2] : q[2])];
+                }
+        ef[fld * nlf + c] += v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dense bottom solve (float64): assemble, Cholesky, explicit inverse
+// one workgroup per (problem, field)
+// ---------------------------------------------------------------------------
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_bottom_setup(
+    const int32_t* __restrict__ probs, const int32_t* __restrict__ boxes,
+    const PatchInfo* __restrict__ P, const ProbScalars* __restrict__ ps,
+    const PT* __restrict__ D, int64_t nl, const int64_t* __restrict__ boff,
+    double* __restrict__ L, double* __restrict__ X) {
+    const int pi = blockIdx.x >> 1;
+    const int fld = blockIdx.x & 1;
+    const int prob = probs[pi];
+    const PatchInfo& p = P[boxes[pi]];
+    const double beta = ps[prob].beta;
+    const int N = p.ncell;
+    double* A = L + boff[prob] * 2 + (int64_t)fld * N * N;
+    double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * N;
+    for (int i = threadIdx.x; i < N * N; i += blockDim.x) A[i] = 0.0;
+    __syncthreads();
+    const int st[3] = {1, p.sy, p.sz};
+    const int sl[3] = {1, p.n[0], p.n[0] * p.n[1]};
+    for (int lin = threadIdx.x; lin < N; lin += blockDim.x) {
+        int id[3];
+        coords(p, lin, id[0], id[1], id[2]);
+        const int c = nat(p, id[0], id[1], id[2]);
+        double dg = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            const double bh2 = beta * p.ih[d] * p.ih[d];
+            const PT* Dd = D + (fld * 3 + d) * nl;
+            for (int s = 0; s < 2; ++s) {
+                const int slot = s ? c + st[d] : c;
+                const double Dv = (double)Dd[slot];
+                if (id[d] == (s ? p.n[d] - 1 : 0)) {        // grid covers the domain
+                    if (fld == 0 && ((p.robin >> (2 * d + s)) & 1))
+                        dg += 2.0 * beta * Dv / ((4.0 * Dv + p.h[d]) * p.h[d]);
+                    continue;
+                }
+                const double a = bh2 * Dv;
+                dg += a;
+                A[(int64_t)lin * N + (s ? lin + sl[d] : lin - sl[d])] = -a;
+            }
+        }
+        A[(int64_t)lin * N + lin] = dg;
+    }
+    __syncthreads();
+    // Cholesky A = L L^T in place (lower triangle)
+    __shared__ double piv;
+    for (int k = 0; k < N; ++k) {
+        if (threadIdx.x == 0) {
+            double s = A[(int64_t)k * N + k];
+            for (int j = 0; j < k; ++j) s -= A[(int64_t)k * N + j] * A[(int64_t)k * N + j];
+            piv = sqrt(s);
+            A[(int64_t)k * N + k] = piv;
+        }
+        __syncthreads();
+        for (int i = k + 1 + threadIdx.x; i < N; i += blockDim.x) {
+            double s = A[(int64_t)i * N + k];
+            for (int j = 0; j < k; ++j) s -= A[(int64_t)i * N + j] * A[(int64_t)k * N + j];
+            A[(int64_t)i * N + k] = s / piv;
+        }
+        __syncthreads();
+    }
+    // inverse, one column per thread: L y = e_col, L^T x = y
+    for (int col = threadIdx.x; col < N; col += blockDim.x) {
+        double* x = Xi + (int64_t)col * N;     // column col of A^-1 (symmetric)
+        for (int i = 0; i < N; ++i) {
+            double s = (i == col) ? 1.0 : 0.0;
+            for (int j = 0; j < i; ++j) s -= A[(int64_t)i * N + j] * x[j];
+            x[i] = s / A[(int64_t)i * N + i];
+        }
+        for (int i = N - 1; i >= 0; --i) {
+            double s = x[i];
+            for (int j = i + 1; j < N; ++j) s -= A[(int64_t)j * N + i] * x[j];
+            x[i] = s / A[(int64_t)i * N + i];
+        }
+    }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_bottom_apply(
+    const int32_t* __restrict__ probs, const int32_t* __restrict__ boxes,
+    const PatchInfo* __restrict__ P, const int64_t* __restrict__ boff,
+    const double* __restrict__ X, const PT* __restrict__ f, PT* __restrict__ e,
+    int64_t nl) {
+    const int pi = blockIdx.x >> 1;
+    const int fld = blockIdx.x & 1;
+    const int prob = probs[pi];
+    const PatchInfo& p = P[boxes[pi]];
+    const int N = p.ncell;
+    const double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * N;
+    for (int row = threadIdx.x; row < N; row += blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < N; ++j) {
+            int id[3];
+            coords(p, j, id[0], id[1], id[2]);
+            s += Xi[(int64_t)j * N + row] * (double)f[fld * nl + nat(p, id[0], id[1], id[2])];
+        }
+        int id[3];
+        coords(p, row, id[0], id[1], id[2]);
+        e[fld * nl + nat(p, id[0], id[1], id[2])] = (PT)s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P2 and precision conversion
+// ---------------------------------------------------------------------------
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_p2(const Tile* __restrict__ tiles,
+                                               const PatchInfo* __restrict__ P,
+                                               const ProbScalars* __restrict__ ps,
+                                               const PT* __restrict__ sigma,
+                                               const double* __restrict__ z3,
+                                               const PT* __restrict__ e,
+                                               double* __restrict__ y, int mode,
+                                               int transpose, int64_t nl) {
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    int id[3];
+    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(p, id[0], id[1], id[2]);
+    const double beta = ps[t.prob].beta;
+    const double sg = (double)sigma[c];
+    const double z = z3[c];
+    const double k = mode ? 4.0 : 1.0;
+    // [[1 + sigma beta, -k beta z^3], [-sigma beta, 1 + k beta z^3]]  (sigma T^3 = z^3)
+    const double a = 1.0 + sg * beta, b = -k * beta * z, cc = -sg * beta, d = 1.0 + k * beta * z;
+    const double det = a * d - b * cc;
+    const double eE = (double)e[c], eT = (double)e[c + nl];
+    if (!transpose) {
+        y[c] = (d * eE - b * eT) / det;
+        y[c + nl] = (a * eT - cc * eE) / det;
+    } else {
+        y[c] = (d * eE - cc * eT) / det;
+        y[c + nl] = (a * eT - b * eE) / det;
+    }
+}
+
+// P2^-T applied first (transposed preconditioner): double in, PT out
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_p2t_in(const Tile* __restrict__ tiles,
+                                                   const PatchInfo* __restrict__ P,
+                                                   const ProbScalars* __restrict__ ps,
+                                                   const PT* __restrict__ sigma,
+                                                   const double* __restrict__ z3,
+                                                   const double* __restrict__ w,
+                                                   PT* __restrict__ x, int mode, int64_t nl) {
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    int id[3];
+    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(p, id[0], id[1], id[2]);
+    const double beta = ps[t.prob].beta;
+    const double sg = (double)sigma[c];
+    const double z = z3[c];
+    const double k = mode ? 4.0 : 1.0;
+    const double a = 1.0 + sg * beta, b = -k * beta * z, cc = -sg * beta, d = 1.0 + k * beta * z;
+    const double det = a * d - b * cc;
+    const double eE = w[c], eT = w[c + nl];
+    x[c] = (PT)((d * eE - cc * eT) / det);
+    x[c + nl] = (PT)((a * eT - b * eE) / det);
+}
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_in(const Tile* __restrict__ tiles,
+                                               const PatchInfo* __restrict__ P,
+                                               const double* __restrict__ w,
+                                               PT* __restrict__ x, int64_t nl) {
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    int id[3];
+    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(p, id[0], id[1], id[2]);
+    x[c] = (PT)w[c];
+    x[c + nl] = (PT)w[c + nl];
+}
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_out(const Tile* __restrict__ tiles,
+                                                const PatchInfo* __restrict__ P,
+                                                const PT* __restrict__ x,
+                                                double* __restrict__ y, int64_t nl) {
+    const Tile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    int id[3];
+    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(p, id[0], id[1], id[2]);
+    y[c] = (double)x[c];
+    y[c + nl] = (double)x[c + nl];
+}
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_fill_t(PT* __restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = PT(0);
+}
+
+// ---------------------------------------------------------------------------
+// drivers
+// ---------------------------------------------------------------------------
+
+template <typename PT>
+void PcArrays<PT>::zero(hipStream_t s) const {
+    k_fill_t<PT><<<nblocks(2 * D->nl), kBlock, 0, s>>>(e, 2 * D->nl);
+    k_fill_t<PT><<<nblocks(2 * D->nl), kBlock, 0, s>>>(u, 2 * D->nl);
+    k_fill_t<PT><<<nblocks(2 * D->nl), kBlock, 0, s>>>(r, 2 * D->nl);
+    k_fill_t<PT><<<nblocks(2 * D->nl), kBlock, 0, s>>>(f, 2 * D->nl);
+    k_fill_t<PT><<<nblocks(2 * D->nl), kBlock, 0, s>>>(tmp, 2 * D->nl);
+    k_fill_t<PT><<<nblocks(6 * D->nl), kBlock, 0, s>>>(Dface, 6 * D->nl);
+    for (int g = 1; g <= mg.G; ++g) {
+        const int64_t n = mg.len[g];
+        k_fill_t<PT><<<nblocks(6 * n), kBlock, 0, s>>>(mg.Dg[g], 6 * n);
+        k_fill_t<PT><<<nblocks(2 * n), kBlock, 0, s>>>(mg.eg[g], 2 * n);
+        k_fill_t<PT><<<nblocks(2 * n), kBlock, 0, s>>>(mg.fg[g], 2 * n);
+        k_fill_t<PT><<<nblocks(2 * n), kBlock, 0, s>>>(mg.rg[g], 2 * n);
+    }
+}
+
+template <typename PT>
+void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
+    const Dev& d = *D;
+    const int ntiles = d.level_tile0[d.nlev];
+    k_snapshot<PT><<<ntiles, kBlock, 0, s>>>(d.tiles, d.patches, d.ps, u_state, d.z3, Dface,
+                                            sigma, d.nl);
+    for (int g = 1; g <= mg.G; ++g) {
+        const PT* Df = (g == 1) ? Dface : mg.Dg[g - 1];
+        const int64_t nlf = (g == 1) ? d.nl : mg.len[g - 1];
+        const PatchInfo* Pf = (g == 1) ? d.patches : mg.box[g - 1];
+        k_mg_coarsen<PT><<<mg.ntiles[g], kBlock, 0, s>>>(mg.tiles[g], mg.box[g], Pf,
+                                                         mg.box_of[g - 1], Df, nlf, mg.Dg[g],
+                                                         mg.len[g]);
+    }
+    for (int g = 0; g <= mg.G; ++g) {
+        if (mg.nbottom[g] == 0) continue;
+        const PT* Dg = (g == 0) ? Dface : mg.Dg[g];
+        const int64_t nlg = (g == 0) ? d.nl : mg.len[g];
+        const PatchInfo* Pg = (g == 0) ? d.patches : mg.box[g];
+        k_bottom_setup<PT><<<2 * mg.nbottom[g], kBlock, 0, s>>>(
+            mg.bottom_probs[g], mg.bottom_boxes[g], Pg, d.ps, Dg, nlg, mg.bottom_off,
+            mg.Lbuf, mg.Xbuf);
+    }
+}
+
+template <typename PT>
+void PcArrays<PT>::vcycle(hipStream_t s) const {
+    // grid 0 = the level-0 patches: rhs in f (native), result in e
+    const Dev& d = *D;
+    for (int g = 0; g <= mg.G; ++g) {
+        const PatchInfo* Pg = (g == 0) ? d.patches : mg.box[g];
+        const int64_t nlg = (g == 0) ? d.nl : mg.len[g];
+        PT* eg = (g == 0) ? e : mg.eg[g];
+        PT* fg = (g == 0) ? f : mg.fg[g];
+        PT* rg = (g == 0) ? tmp : mg.rg[g];
+        const PT* Dg = (g == 0) ? Dface : mg.Dg[g];
+        if (mg.nsmooth[g] > 0) {
+            const Tile* tl = mg.smooth_tiles[g];
+            const int nt = mg.nsmooth[g];
+            for (int it = 0; it < nu_pre; ++it) {
+                if (it == 0)
+                    k_level<PT, 0><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg,
+                                                        nullptr, 0, nlg);
+                else
+                    k_level<PT, 1><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg,
+                                                        nullptr, 0, nlg);
+                k_level<PT, 1><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg,
+                                                    nullptr, 1, nlg);
+            }
+            k_level<PT, 2><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg, rg, 0, nlg);
+            k_mg_restrict<PT><<<mg.ntiles[g + 1], kBlock, 0, s>>>(
+                mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g], rg, nlg, mg.fg[g + 1],
+                mg.len[g + 1]);
+        }
+        if (mg.nbottom[g] > 0)
+            k_bottom_apply<PT><<<2 * mg.nbottom[g], kBlock, 0, s>>>(
+                mg.bottom_probs[g], mg.bottom_boxes[g], Pg, mg.bottom_off, mg.Xbuf, fg, eg,
+                nlg);
+    }
+    for (int g = mg.G - 1; g >= 0; --g) {
+        if (mg.nsmooth[g] == 0) continue;
+        const PatchInfo* Pg = (g == 0) ? d.patches : mg.box[g];
+        const int64_t nlg = (g == 0) ? d.nl : mg.len[g];
+        PT* eg = (g == 0) ? e : mg.eg[g];
+        PT* fg = (g == 0) ? f : mg.fg[g];
+        const PT* Dg = (g == 0) ? Dface : mg.Dg[g];
+        const Tile* tl = mg.smooth_tiles[g];
+        const int nt = mg.nsmooth[g];
+        k_mg_prolong<PT><<<nt, kBlock, 0, s>>>(tl, Pg, mg.box[g + 1], mg.box_of[g + 1],
+                                              mg.eg[g + 1], mg.len[g + 1], eg, nlg);
+        for (int it = 0; it < nu_post; ++it) {
+            k_level<PT, 1><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 0,
+                                                nlg);
+            k_level<PT, 1><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 1,
+                                                nlg);
+        }
+    }
+}
+
+template <>
+void PcArrays<float>::fill_ghosts(hipStream_t s, float* x) const {
+    ghost_fill_f(*D, s, x, 2);
+}
+template <>
+void PcArrays<double>::fill_ghosts(hipStream_t s, double* x) const {
+    ghost_fill_d(*D, s, x, 2);
+}
+template <>
+void PcArrays<float>::restrict_(hipStream_t s, float* x, int lev_lo) const {
+    restrict_f(*D, s, x, 2, lev_lo);
+}
+template <>
+void PcArrays<double>::restrict_(hipStream_t s, double* x, int lev_lo) const {
+    restrict_d(*D, s, x, 2, lev_lo);
+}
+template <>
+void PcArrays<float>::siblings(hipStream_t s, float* x, int lev) const {
+    sibling_exchange_f(*D, s, x, 2, lev);
+}
+template <>
+void PcArrays<double>::siblings(hipStream_t s, double* x, int lev) const {
+    sibling_exchange_d(*D, s, x, 2, lev);
+}
+
+template <typename PT>
+void PcArrays<PT>::composite_residual(hipStream_t s) const {
+    // r = f - A^c u on composite cells; covered r <- restriction of finer r
+    const Dev& d = *D;
+    restrict_(s, u, 0);
+    fill_ghosts(s, u);
+    const int ntiles = d.level_tile0[d.nlev];
+    k_comp_res<PT><<<ntiles, kBlock, 0, s>>>(d.tiles, d.patches, d.ps, d.ctype, Dface, f, u, r,
+                                            d.nl);
+    if (d.nrcells > 0)
+        k_comp_reflux<PT><<<nblocks(d.nrcells), kBlock, 0, s>>>(
+            d.rcells, d.nrcells, d.rfaces, d.patches, d.ps, Dface, u, r, d.nl);
+    restrict_(s, r, 0);
+}
+
+template <typename PT>
+void PcArrays<PT>::fac(hipStream_t s) const {
+    // One FAC V(1,0) cycle from u = 0 for A^c u = f (Alg. 1).  Result in u.
+    const Dev& d = *D;
+    const int L = d.nlev - 1;
+    k_fill_t<PT><<<nblocks(2 * d.nl), kBlock, 0, s>>>(u, 2 * d.nl);
+    for (int lev = L; lev >= 0; --lev) {
+        if (lev == L) {
+            // u = 0: r = f on composite cells, restricted below
+            (void)hipMemcpyAsync(r, f, sizeof(PT) * 2 * d.nl, hipMemcpyDeviceToDevice, s);
+            restrict_(s, r, 0);
+        } else {
+            composite_residual(s);
+        }
+        const int t0 = d.level_tile0[lev], nt = d.level_tile0[lev + 1] - t0;
+        if (lev > 0) {
+            // one red-black sweep on A^l e = f^l from e = 0, sibling ghosts
+            // refreshed between the half-sweeps
+            k_level<PT, 0><<<nt, kBlock, 0, s>>>(d.tiles + t0, d.patches, d.ps, d.ctype, Dface,
+                                                r, e, nullptr, 0, d.nl);
+            siblings(s, e, lev);
+            k_level<PT, 1><<<nt, kBlock, 0, s>>>(d.tiles + t0, d.patches, d.ps, d.ctype, Dface,
+                                                r, e, nullptr, 1, d.nl);
+        } else {
+            // base level: multigrid V-cycle with rhs f^0 = r on level 0
+            PcArrays<PT> v = *this;
+            v.f = r;
+            v.vcycle(s);
+        }
+        k_add_level<PT><<<nt, kBlock, 0, s>>>(d.tiles + t0, d.patches, e, u, d.nl);
+        for (int m = lev + 1; m <= L; ++m) {
+            const int a = d.level_shadow0[m], b = d.level_shadow0[m + 1];
+            k_gather<PT><<<nblocks(b - a), kBlock, 0, s>>>(shadow_src + a, b - a, e, d.nl,
+                                                           shadow + a, shadow_len);
+            const int m0 = d.level_tile0[m], mt = d.level_tile0[m + 1] - m0;
+            k_prolong_level<PT><<<mt, kBlock, 0, s>>>(d.tiles + m0, d.patches, shadows,
+                                                      shadow, shadow_len, e, u, d.nl);
+        }
+        restrict_(s, u, 0);
+    }
+}
+
+template <typename PT>
+void PcArrays<PT>::apply(hipStream_t s, const double* w, double* y) const {
+    const Dev& d = *D;
+    const int ntiles = d.level_tile0[d.nlev];
+    k_in<PT><<<ntiles, kBlock, 0, s>>>(d.tiles, d.patches, w, f, d.nl);
+    fac(s);
+    k_p2<PT><<<ntiles, kBlock, 0, s>>>(d.tiles, d.patches, d.ps, sigma, d.z3, u, y, p2_mode, 0,
+                                       d.nl);
+}
+
+template <typename PT>
+void PcArrays<PT>::apply_transpose(hipStream_t s, const double* w, double* y) const {
+    const Dev& d = *D;
+    const int ntiles = d.level_tile0[d.nlev];
+    k_p2t_in<PT><<<ntiles, kBlock, 0, s>>>(d.tiles, d.patches, d.ps, sigma, d.z3, w, f,
+                                           p2_mode, d.nl);
+    fac(s);
+    k_out<PT><<<ntiles, kBlock, 0, s>>>(d.tiles, d.patches, u, y, d.nl);
+}
+
+template struct PcArrays<float>;
+template struct PcArrays<double>;
+
+}  // namespace nrd

@@ -1,0 +1,435 @@
+// Stencil kernels of the NRD residual, its Jacobian action and transpose
+// (paper Sec. 3.1-3.3, 4.1), plus restriction and ghost fill (Sec. 3.2.1).
+//
+// Layout: per patch a ghosted block, x fastest; field f of a native vector
+// starts at f * nl.  One workgroup processes one tile (a run of interior
+// cells of one patch); the patch descriptor is wave-uniform and lives in
+// scalar registers.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace nrd {
+
+// ---------------------------------------------------------------------------
+// face formulas
+//
+// Flux density through a face between lower cell a and upper cell b:
+//   Phi_E = D_E (E_b - E_a) / h,  D_E = D_h / (1 + lam D_h g),
+//   D_h = 2 T_f^3 / (3 (z_a^3 + z_b^3)),  g = |E_b - E_a| / (h (E_a + E_b)/2)
+// folded into one division:
+//   Phi_E = 2 T_f^3 S dE / (3 Z_f h S + 4 lam T_f^3 |dE|),  S = E_a + E_b.
+//   Phi_T = kappa T_f^(5/2) (T_b - T_a) / h.
+// Marshak face: inflow q = 2 D_b (4R - E_c) / (4 D_b + h), D_b = T_c^3/(3 z_c^3)
+//   = 2 T^3 (4R - E) / (4 T^3 + 3 z^3 h).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void face_flux(double Ea, double Eb, double Ta, double Tb,
+                                          double za, double zb, double h, double ih,
+                                          double kappa, double lam, double& fe,
+                                          double& ft) {
+    const double Tf = 0.5 * (Ta + Tb);
+    const double Tf3 = Tf * Tf * Tf;
+    const double S = Ea + Eb;
+    const double dE = Eb - Ea;
+    fe = (2.0 * Tf3 * S * dE) / (3.0 * (za + zb) * h * S + 4.0 * lam * Tf3 * fabs(dE));
+    ft = kappa * Tf * Tf * sqrt(Tf) * (Tb - Ta) * ih;
+}
+
+__device__ __forceinline__ void face_flux_tan(double Ea, double Eb, double Ta, double Tb,
+                                              double za, double zb, double dEa, double dEb,
+                                              double dTa, double dTb, double h, double ih,
+                                              double kappa, double lam, double& dfe,
+                                              double& dft) {
+    const double Tf = 0.5 * (Ta + Tb);
+    const double dTf = 0.5 * (dTa + dTb);
+    const double Tf2 = Tf * Tf;
+    const double Tf3 = Tf2 * Tf;
+    const double S = Ea + Eb;
+    const double dS = dEa + dEb;
+    const double dE = Eb - Ea;
+    const double ddE = dEb - dEa;
+    const double adE = fabs(dE);
+    const double sg = (dE > 0.0) ? 1.0 : ((dE < 0.0) ? -1.0 : 0.0);
+    const double Zh = 3.0 * (za + zb) * h;
+    const double N = 2.0 * Tf3 * S * dE;
+    const double iD = 1.0 / (Zh * S + 4.0 * lam * Tf3 * adE);
+    const double phi = N * iD;
+    const double dN = 2.0 * (3.0 * Tf2 * dTf * S * dE + Tf3 * (dS * dE + S * ddE));
+    const double dDn = Zh * dS + 4.0 * lam * (3.0 * Tf2 * dTf * adE + Tf3 * sg * ddE);
+    dfe = (dN - phi * dDn) * iD;
+    const double sq = sqrt(Tf);
+    dft = kappa * Tf * sq * (2.5 * dTf * (Tb - Ta) + Tf * (dTb - dTa)) * ih;
+}
+
+__device__ __forceinline__ double robin_q(double Ec, double Tc, double zc, double R,
+                                          double h) {
+    const double T3 = Tc * Tc * Tc;
+    return 2.0 * T3 * (4.0 * R - Ec) / (4.0 * T3 + 3.0 * zc * h);
+}
+
+__device__ __forceinline__ double robin_q_tan(double Ec, double Tc, double zc, double R,
+                                              double h, double dEc, double dTc) {
+    const double T2 = Tc * Tc;
+    const double T3 = T2 * Tc;
+    const double iD = 1.0 / (4.0 * T3 + 3.0 * zc * h);
+    const double q = 2.0 * T3 * (4.0 * R - Ec) * iD;
+    const double dN = 6.0 * T2 * dTc * (4.0 * R - Ec) - 2.0 * T3 * dEc;
+    return (dN - q * 12.0 * T2 * dTc) * iD;
+}
+
+__device__ __forceinline__ void cell_coords(const PatchInfo& p, int lin, int& i, int& j,
+                                            int& k) {
+    i = lin % p.n[0];
+    const int r = lin / p.n[0];
+    j = r % p.n[1];
+    k = r / p.n[1];
+}
+
+__device__ __forceinline__ int native_index(const PatchInfo& p, int i, int j, int k) {
+    return p.off + (i + 1) + p.sy * (j + 1) + p.sz * (k + 1);
+}
+
+// ---------------------------------------------------------------------------
+// ghost fill and restriction
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ghost_fill(const GhostCopy* __restrict__ cp,
+                                                       int ncp,
+                                                       const GhostCF* __restrict__ cf,
+                                                       int ncf, T* __restrict__ x, int nf,
+                                                       int64_t nl) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ncp) {
+        const GhostCopy e = cp[t];
+        for (int f = 0; f < nf; ++f) x[f * nl + e.dst] = x[f * nl + e.src];
+    } else if (t < ncp + ncf) {
+        const GhostCF e = cf[t - ncp];
+        for (int f = 0; f < nf; ++f) {
+            const T* y = x + f * nl;
+            const T ci = (T(9) * y[e.src[0]] + T(3) * y[e.src[1]] + T(3) * y[e.src[2]] +
+                          y[e.src[3]]) * T(0.0625);
+            x[f * nl + e.dst] = T(2.0 / 3.0) * ci + T(1.0 / 3.0) * y[e.src[4]];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(const SyncEntry* __restrict__ se,
+                                                     int n, T* __restrict__ x, int nf,
+                                                     int64_t nl) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const SyncEntry e = se[t];
+    for (int f = 0; f < nf; ++f) {
+        const T* y = x + f * nl + e.src;
+        T acc = y[0];
+        acc += y[1];
+        acc += y[e.sy];
+        acc += y[e.sy + 1];
+        acc += y[e.sz];
+        acc += y[e.sz + 1];
+        acc += y[e.sz + e.sy];
+        acc += y[e.sz + e.sy + 1];
+        x[f * nl + e.dst] = acc * T(0.125);
+    }
+}
+
+static inline int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+void ghost_fill_d(const Dev& D, hipStream_t s, double* x, int nf) {
+    const int n = D.ncopy + D.ncf;
+    if (n == 0) return;
+    k_ghost_fill<double><<<nblocks(n), kBlock, 0, s>>>(D.gcopy, D.ncopy, D.gcf, D.ncf, x,
+                                                      nf, D.nl);
+}
+void ghost_fill_f(const Dev& D, hipStream_t s, float* x, int nf) {
+    const int n = D.ncopy + D.ncf;
+    if (n == 0) return;
+    k_ghost_fill<float><<<nblocks(n), kBlock, 0, s>>>(D.gcopy, D.ncopy, D.gcf, D.ncf, x,
+                                                     nf, D.nl);
+}
+
+template <typename T>
+static void restrict_t(const Dev& D, hipStream_t s, T* x, int nf, int lev_lo) {
+    for (int l = D.nlev - 2; l >= lev_lo; --l) {
+        if (D.nsync[l] == 0) continue;
+        k_restrict<T><<<nblocks(D.nsync[l]), kBlock, 0, s>>>(D.sync[l], D.nsync[l], x, nf,
+                                                             D.nl);
+    }
+}
+void restrict_d(const Dev& D, hipStream_t s, double* x, int nf, int lev_lo) {
+    restrict_t<double>(D, s, x, nf, lev_lo);
+}
+void restrict_f(const Dev& D, hipStream_t s, float* x, int nf, int lev_lo) {
+    restrict_t<float>(D, s, x, nf, lev_lo);
+}
+
+template <typename T>
+static void sib_t(const Dev& D, hipStream_t s, T* x, int nf, int lev) {
+    const int a = D.level_sib0[lev], b = D.level_sib0[lev + 1];
+    if (b <= a) return;
+    k_ghost_fill<T><<<nblocks(b - a), kBlock, 0, s>>>(D.sib + a, b - a, nullptr, 0, x, nf,
+                                                     D.nl);
+}
+void sibling_exchange_f(const Dev& D, hipStream_t s, float* x, int nf, int lev) {
+    sib_t<float>(D, s, x, nf, lev);
+}
+void sibling_exchange_d(const Dev& D, hipStream_t s, double* x, int nf, int lev) {
+    sib_t<double>(D, s, x, nf, lev);
+}
+
+// ---------------------------------------------------------------------------
+// residual (MODE 0) and Jacobian action (MODE 1)
+// ---------------------------------------------------------------------------
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_stencil(
+    const Tile* __restrict__ tiles, int t0, const PatchInfo* __restrict__ P,
+    const ProbScalars* __restrict__ ps, const int32_t* __restrict__ active,
+    const uint8_t* __restrict__ ctype, const double* __restrict__ u,
+    const double* __restrict__ v, const double* __restrict__ z3,
+    const double* __restrict__ b, double* __restrict__ out, int64_t nl) {
+    const Tile t = tiles[t0 + blockIdx.x];
+    if (active && !active[t.prob]) return;
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    const ProbScalars& q = ps[t.prob];
+    int id[3];
+    cell_coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = native_index(p, id[0], id[1], id[2]);
+    const int ct = (p.flags & PF_CTYPE) ? ctype[c] : 0;
+    if (ct & CT_COVERED) {
+        out[c] = 0.0;
+        out[c + nl] = 0.0;
+        return;
+    }
+    const int st[3] = {1, p.sy, p.sz};
+    const double E = u[c], T = u[c + nl], z = z3[c];
+    double dE = 0.0, dT = 0.0;
+    if (MODE == 1) {
+        dE = v[c];
+        dT = v[c + nl];
+    }
+    const double kappa = q.kappa, lam = q.lam;
+    double divE = 0.0, divT = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double h = p.h[d], ih = p.ih[d];
+        double fe_lo = 0.0, ft_lo = 0.0, fe_hi = 0.0, ft_hi = 0.0;
+        // low face
+        if (id[d] == 0 && ((p.phys >> (2 * d)) & 1)) {
+            if ((p.robin >> (2 * d)) & 1) {
+                fe_lo = (MODE == 0) ? -robin_q(E, T, z, q.R[2 * d], h)
+                                    : -robin_q_tan(E, T, z, q.R[2 * d], h, dE, dT);
+            }
+        } else if (!((ct >> (2 * d + 1)) & 1)) {
+            const int a = c - st[d];
+            if (MODE == 0)
+                face_flux(u[a], E, u[a + nl], T, z3[a], z, h, ih, kappa, lam, fe_lo, ft_lo);
+            else
+                face_flux_tan(u[a], E, u[a + nl], T, z3[a], z, v[a], dE, v[a + nl], dT, h, ih,
+                              kappa, lam, fe_lo, ft_lo);
+        }
+        // high face
+        if (id[d] == p.n[d] - 1 && ((p.phys >> (2 * d + 1)) & 1)) {
+            if ((p.robin >> (2 * d + 1)) & 1) {
+                fe_hi = (MODE == 0) ? robin_q(E, T, z, q.R[2 * d + 1], h)
+                                    : robin_q_tan(E, T, z, q.R[2 * d + 1], h, dE, dT);
+            }
+        } else if (!((ct >> (2 * d + 2)) & 1)) {
+            const int bb = c + st[d];
+            if (MODE == 0)
+                face_flux(E, u[bb], T, u[bb + nl], z, z3[bb], h, ih, kappa, lam, fe_hi, ft_hi);
+            else
+                face_flux_tan(E, u[bb], T, u[bb + nl], z, z3[bb], dE, v[bb], dT, v[bb + nl], h,
+                              ih, kappa, lam, fe_hi, ft_hi);
+        }
+        divE += (fe_hi - fe_lo) * ih;
+        divT += (ft_hi - ft_lo) * ih;
+    }
+    const double T2 = T * T;
+    const double T3 = T2 * T;
+    if (MODE == 0) {
+        const double S = z * (T - E / T3);
+        out[c] = q.c0 * E - b[c] - q.dt * (divE + S);
+        out[c + nl] = q.c0 * T - b[c + nl] - q.dt * (divT - S);
+    } else {
+        const double r3 = 1.0 / T3;
+        const double dS = z * ((1.0 + 3.0 * E * r3 / T) * dT - dE * r3);
+        out[c] = q.c0 * dE - q.dt * (divE + dS);
+        out[c + nl] = q.c0 * dT - q.dt * (divT - dS);
+    }
+}
+
+// Flux matching: a coarse face bordering a finer level carries the mean of
+// the four fine fluxes (Sec. 3.2.1).  The stencil skipped that face; add
+// -dt * (+-mean) / h_c here.  One thread per coarse cell (no races).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_reflux(
+    const RefluxCell* __restrict__ rc, int n, const RefluxFace* __restrict__ rf,
+    const PatchInfo* __restrict__ P, const ProbScalars* __restrict__ ps,
+    const int32_t* __restrict__ active, const double* __restrict__ u,
+    const double* __restrict__ v, const double* __restrict__ z3,
+    double* __restrict__ out, int64_t nl) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const RefluxCell cell = rc[t];
+    if (active && !active[cell.prob]) return;
+    const ProbScalars& q = ps[cell.prob];
+    double accE = 0.0, accT = 0.0;
+    for (int e = cell.first; e < cell.first + cell.count; ++e) {
+        const RefluxFace f = rf[e];
+        const int d = f.face >> 1;
+        const bool hi = f.face & 1;
+        const PatchInfo& fp = P[f.fpatch];
+        const double h = fp.h[d], ih = fp.ih[d];
+        double se = 0.0, st = 0.0;
+        for (int k = 0; k < 4; ++k) {
+            const int fi = f.fine[k];
+            const int g = fi + f.gofs;
+            const int a = hi ? g : fi;        // lower cell of the fine face
+            const int b = hi ? fi : g;
+            double fe, ft;
+            if (MODE == 0)
+                face_flux(u[a], u[b], u[a + nl], u[b + nl], z3[a], z3[b], h, ih, q.kappa,
+                          q.lam, fe, ft);
+            else
+                face_flux_tan(u[a], u[b], u[a + nl], u[b + nl], z3[a], z3[b], v[a], v[b],
+                              v[a + nl], v[b + nl], h, ih, q.kappa, q.lam, fe, ft);
+            se += fe;
+            st += ft;
+        }
+        const double sgn = hi ? 1.0 : -1.0;
+        const double ihc = 0.5 * ih;          // coarse h = 2 fine h
+        accE += sgn * 0.25 * se * ihc;
+        accT += sgn * 0.25 * st * ihc;
+    }
+    out[cell.c] -= q.dt * accE;
+    out[cell.c + nl] -= q.dt * accT;
+}
+
+void residual(const Dev& D, hipStream_t s, int t0, int nt, const double* u, const double* b,
+              double* F) {
+    if (nt <= 0) return;
+    k_stencil<0><<<nt, kBlock, 0, s>>>(D.tiles, t0, D.patches, D.ps, D.active, D.ctype, u,
+                                       nullptr, D.z3, b, F, D.nl);
+}
+void residual_reflux(const Dev& D, hipStream_t s, const double* u, double* F) {
+    if (D.nrcells == 0) return;
+    k_reflux<0><<<nblocks(D.nrcells), kBlock, 0, s>>>(D.rcells, D.nrcells, D.rfaces,
+                                                      D.patches, D.ps, D.active, u,
+                                                      nullptr, D.z3, F, D.nl);
+}
+void jvp(const Dev& D, hipStream_t s, int t0, int nt, const double* u, const double* v,
+         double* Jv) {
+    if (nt <= 0) return;
+    k_stencil<1><<<nt, kBlock, 0, s>>>(D.tiles, t0, D.patches, D.ps, D.active, D.ctype, u, v,
+                                       D.z3, nullptr, Jv, D.nl);
+}
+void jvp_reflux(const Dev& D, hipStream_t s, const double* u, const double* v, double* Jv) {
+    if (D.nrcells == 0) return;
+    k_reflux<1><<<nblocks(D.nrcells), kBlock, 0, s>>>(D.rcells, D.nrcells, D.rfaces,
+                                                      D.patches, D.ps, D.active, u, v,
+                                                      D.z3, Jv, D.nl);
+}
+
+// ---------------------------------------------------------------------------
+// transpose (gather form, single-level hierarchies): each cell collects the
+// transposed contributions of its six faces and of its own cell terms, so no
+// atomics are needed.  lam's sibling ghosts must hold copies (ghost fill);
+// its physical ghosts are never read.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_vjp(
+    const Tile* __restrict__ tiles, int t0, const PatchInfo* __restrict__ P,
+    const ProbScalars* __restrict__ ps, const int32_t* __restrict__ active,
+    const double* __restrict__ u, const double* __restrict__ lam,
+    const double* __restrict__ z3, double* __restrict__ gout,
+    double* __restrict__ gz3, int64_t nl) {
+    const Tile t = tiles[t0 + blockIdx.x];
+    if (active && !active[t.prob]) return;
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    const ProbScalars& q = ps[t.prob];
+    int id[3];
+    cell_coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = native_index(p, id[0], id[1], id[2]);
+    const int st[3] = {1, p.sy, p.sz};
+    const double E = u[c], T = u[c + nl], z = z3[c];
+    const double lE = lam[c], lT = lam[c + nl];
+    const double dt = q.dt, kappa = q.kappa, lm = q.lam;
+    double gE = q.c0 * lE, gT = q.c0 * lT, gZ = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double h = p.h[d], ih = p.ih[d];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const bool phys = (id[d] == (s ? p.n[d] - 1 : 0)) && ((p.phys >> (2 * d + s)) & 1);
+            if (phys) {
+                if ((p.robin >> (2 * d + s)) & 1) {
+                    // F_c gets -dt q / h
+                    const double R = q.R[2 * d + s];
+                    const double T2 = T * T, T3 = T2 * T;
+                    const double iD = 1.0 / (4.0 * T3 + 3.0 * z * h);
+                    const double qq = 2.0 * T3 * (4.0 * R - E) * iD;
+                    const double w = -dt * lE * ih;
+                    gE += w * (-2.0 * T3) * iD;
+                    gT += w * (6.0 * T2 * (4.0 * R - E) - qq * 12.0 * T2) * iD;
+                    gZ += w * (-qq * 3.0 * h) * iD;
+                }
+                continue;
+            }
+            const int nb = s ? c + st[d] : c - st[d];
+            // face between lower a and upper b; c is a when s = 1
+            const int a = s ? c : nb;
+            const int bb = s ? nb : c;
+            const double Ea = u[a], Eb = u[bb], Ta = u[a + nl], Tb = u[bb + nl];
+            const double za = z3[a], zb = z3[bb];
+            const double muE = dt * (lam[bb] - lam[a]) * ih;
+            const double muT = dt * (lam[bb + nl] - lam[a + nl]) * ih;
+            const double Tf = 0.5 * (Ta + Tb);
+            const double Tf2 = Tf * Tf, Tf3 = Tf2 * Tf;
+            const double S = Ea + Eb;
+            const double dEv = Eb - Ea;
+            const double adE = fabs(dEv);
+            const double sg = (dEv > 0.0) ? 1.0 : ((dEv < 0.0) ? -1.0 : 0.0);
+            const double Zh = 3.0 * (za + zb) * h;
+            const double iD = 1.0 / (Zh * S + 4.0 * lm * Tf3 * adE);
+            const double phi = 2.0 * Tf3 * S * dEv * iD;
+            // partials of Phi_E w.r.t. c's own E, T, z^3
+            const double sE = s ? -1.0 : 1.0;              // d(dE)/dE_c
+            const double dN_E = 2.0 * Tf3 * (S * sE + dEv);
+            const double dD_E = Zh + 4.0 * lm * Tf3 * sg * sE;
+            const double dN_T = 3.0 * Tf2 * S * dEv;
+            const double dD_T = 6.0 * lm * Tf2 * adE;
+            const double dD_z = 3.0 * h * S;
+            gE += muE * (dN_E - phi * dD_E) * iD;
+            gT += muE * (dN_T - phi * dD_T) * iD;
+            gZ += muE * (-phi * dD_z) * iD;
+            const double sq = sqrt(Tf);
+            const double DT = kappa * Tf2 * sq;
+            const double base = 1.25 * kappa * Tf * sq * (Tb - Ta);
+            gT += muT * (base + (s ? -DT : DT)) * ih;
+        }
+    }
+    const double T2 = T * T, T3 = T2 * T;
+    const double r3 = 1.0 / T3;
+    const double x = lT - lE;
+    gE += dt * x * (-z * r3);
+    gT += dt * x * z * (1.0 + 3.0 * E * r3 / T);
+    gZ += dt * x * (T - E * r3);
+    gout[c] = gE;
+    gout[c + nl] = gT;
+    gz3[c] = gZ;
+}
+
+void vjp(const Dev& D, hipStream_t s, int t0, int nt, const double* u, const double* lam,
+         double* JTl, double* gz3) {
+    if (nt <= 0) return;
+    k_vjp<<<nt, kBlock, 0, s>>>(D.tiles, t0, D.patches, D.ps, D.active, u, lam, D.z3, JTl,
+                                gz3, D.nl);
+}
+
+}  // namespace nrd

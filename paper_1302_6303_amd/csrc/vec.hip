@@ -1,0 +1,448 @@
+// Krylov vector kernels: per-problem inner products (two-stage, fixed
+// order, hence bitwise reproducible), vector combinations, positivity
+// reductions and the small per-problem FGMRES kernels (Sec. 4.1).
+//
+// Vectors are native 2-field arrays; only interior cells are read or
+// written.  Inner products are volume weighted over composite cells.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+
+#include "kernels.h"
+
+namespace nrd {
+
+static inline int nblocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Sum over the workgroup (4 waves), same result on every thread.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ double block_min(double v, double* sh) {
+    v = wave_min(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    const double r = fmin(fmin(sh[0], sh[1]), fmin(sh[2], sh[3]));
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int interior_index(const PatchInfo& p, int lin) {
+    const int i = lin % p.n[0];
+    const int r = lin / p.n[0];
+    const int j = r % p.n[1];
+    const int k = r / p.n[1];
+    return p.off + (i + 1) + p.sy * (j + 1) + p.sz * (k + 1);
+}
+
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_multidot(
+    const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
+    const uint8_t* __restrict__ ctype, const int32_t* __restrict__ active,
+    const double* __restrict__ X, int64_t xs, int nv, const double* __restrict__ y,
+    double* __restrict__ partial, int64_t nl) {
+    __shared__ double sh[4];
+    const Tile t = vt[blockIdx.x];
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    const bool on = !active || active[t.prob];
+    const PatchInfo& p = P[t.patch];
+    if (on) {
+        const bool cov = p.flags & PF_COVERED;
+        for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+            const int c = interior_index(p, lin);
+            if (cov && (ctype[c] & CT_COVERED)) continue;
+            const double y0 = y[c], y1 = y[c + nl];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < nv) acc[v] += X[v * xs + c] * y0 + X[v * xs + c + nl] * y1;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (v < nv) {
+            const double s = block_sum(acc[v], sh);
+            if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * nv + v] = s * p.vol;
+        }
+    }
+}
+
+// out[p * ostride + v] = sum of the problem's tile partials (fixed order)
+__global__ __launch_bounds__(kBlock) void k_sum_partials(
+    const int32_t* __restrict__ t0, const double* __restrict__ partial, int nv,
+    double* __restrict__ out, int ostride) {
+    __shared__ double sh[4];
+    const int p = blockIdx.x;
+    const int a = t0[p], b = t0[p + 1];
+    for (int v = 0; v < nv; ++v) {
+        double acc = 0.0;
+        for (int i = a + threadIdx.x; i < b; i += kBlock) acc += partial[(int64_t)i * nv + v];
+        const double s = block_sum(acc, sh);
+        if (threadIdx.x == 0) out[p * ostride + v] = s;
+    }
+}
+
+void multidot(const Dev& D, hipStream_t s, const double* X, int64_t xstride, int nv,
+              const double* y, double* partial, double* out) {
+    for (int v0 = 0; v0 < nv; v0 += 16) {
+        const int c = std::min(16, nv - v0);
+        const double* Xc = X + v0 * xstride;
+        if (c == 1)
+            k_multidot<1><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
+                                                       Xc, xstride, c, y, partial, D.nl);
+        else if (c <= 2)
+            k_multidot<2><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
+                                                       Xc, xstride, c, y, partial, D.nl);
+        else if (c <= 4)
+            k_multidot<4><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
+                                                       Xc, xstride, c, y, partial, D.nl);
+        else if (c <= 8)
+            k_multidot<8><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
+                                                       Xc, xstride, c, y, partial, D.nl);
+        else
+            k_multidot<16><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype,
+                                                        D.active, Xc, xstride, c, y, partial,
+                                                        D.nl);
+        k_sum_partials<<<D.nprob, kBlock, 0, s>>>(D.prob_vtile0, partial, c, out + v0, nv);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_min_pos(
+    const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
+    const uint8_t* __restrict__ ctype, const int32_t* __restrict__ active,
+    const double* __restrict__ u, const double* __restrict__ du,
+    const double* __restrict__ lam, double* __restrict__ partial, int64_t nl) {
+    __shared__ double sh[4];
+    const Tile t = vt[blockIdx.x];
+    double m = DBL_MAX;
+    if (!active || active[t.prob]) {
+        const PatchInfo& p = P[t.patch];
+        const double l = lam[t.prob];
+        const bool cov = p.flags & PF_COVERED;
+        for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+            const int c = interior_index(p, lin);
+            if (cov && (ctype[c] & CT_COVERED)) continue;
+            const double e = u[c] + l * du[c];
+            const double tt = u[c + nl] + l * du[c + nl];
+            // NaN compares false: map it to -1 so that it counts as a failure
+            const double v = fmin(e, tt);
+            m = fmin(m, (e == e && tt == tt) ? v : -1.0);
+        }
+    }
+    const double r = block_min(m, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_min_partials(const int32_t* __restrict__ t0,
+                                                         const double* __restrict__ partial,
+                                                         double* __restrict__ out) {
+    __shared__ double sh[4];
+    const int p = blockIdx.x;
+    double m = DBL_MAX;
+    for (int i = t0[p] + threadIdx.x; i < t0[p + 1]; i += kBlock) m = fmin(m, partial[i]);
+    const double r = block_min(m, sh);
+    if (threadIdx.x == 0) out[p] = r;
+}
+
+void min_positive(const Dev& D, hipStream_t s, const double* u, const double* du,
+                  const double* lam, double* partial, double* out) {
+    k_min_pos<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, u, du,
+                                           lam, partial, D.nl);
+    k_min_partials<<<D.nprob, kBlock, 0, s>>>(D.prob_vtile0, partial, out);
+}
+
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_combine(
+    const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
+    const int32_t* __restrict__ active, const double* __restrict__ X, int64_t xs, int nv,
+    const double* __restrict__ coef, int cs, double* __restrict__ y, int accumulate,
+    double alpha, int64_t nl) {
+    const Tile t = vt[blockIdx.x];
+    if (active && !active[t.prob]) return;
+    const PatchInfo& p = P[t.patch];
+    double cf[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) cf[v] = (v < nv) ? alpha * coef[t.prob * cs + v] : 0.0;
+    for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+        const int c = interior_index(p, lin);
+        double a0 = accumulate ? y[c] : 0.0;
+        double a1 = accumulate ? y[c + nl] : 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v < nv && cf[v] != 0.0) {     // unused basis vectors may be stale
+                a0 += cf[v] * X[v * xs + c];
+                a1 += cf[v] * X[v * xs + c + nl];
+            }
+        y[c] = a0;
+        y[c + nl] = a1;
+    }
+}
+
+void combine(const Dev& D, hipStream_t s, const double* X, int64_t xstride, int nv,
+             const double* coef, int cstride, double* y, int accumulate, double alpha) {
+    for (int v0 = 0; v0 < nv || (v0 == 0 && nv == 0); v0 += 16) {
+        const int c = std::min(16, nv - v0);
+        const int acc = (v0 > 0) ? 1 : accumulate;
+        const double* Xc = X + v0 * xstride;
+        const double* cc = coef + v0;
+        if (c <= 1)
+            k_combine<1><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.active, Xc,
+                                                      xstride, c, cc, cstride, y, acc, alpha,
+                                                      D.nl);
+        else if (c <= 4)
+            k_combine<4><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.active, Xc,
+                                                      xstride, c, cc, cstride, y, acc, alpha,
+                                                      D.nl);
+        else if (c <= 8)
+            k_combine<8><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.active, Xc,
+                                                      xstride, c, cc, cstride, y, acc, alpha,
+                                                      D.nl);
+        else
+            k_combine<16><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.active, Xc,
+                                                       xstride, c, cc, cstride, y, acc, alpha,
+                                                       D.nl);
+        if (nv == 0) break;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpby(const Tile* __restrict__ vt,
+                                                  const PatchInfo* __restrict__ P,
+                                                  const int32_t* __restrict__ active,
+                                                  const double* __restrict__ a,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ b,
+                                                  double* __restrict__ y, int64_t nl) {
+    const Tile t = vt[blockIdx.x];
+    if (active && !active[t.prob]) return;
+    const PatchInfo& p = P[t.patch];
+    const double aa = a[t.prob], bb = b[t.prob];
+    for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+        const int c = interior_index(p, lin);
+        y[c] = aa * x[c] + bb * y[c];
+        y[c + nl] = aa * x[c + nl] + bb * y[c + nl];
+    }
+}
+
+void axpby(const Dev& D, hipStream_t s, const double* a, const double* x, const double* b,
+           double* y) {
+    k_axpby<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.active, a, x, b, y, D.nl);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_copy(const Tile* __restrict__ vt,
+                                                       const PatchInfo* __restrict__ P,
+                                                       const int32_t* __restrict__ active,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ sc,
+                                                       double* __restrict__ y, int64_t nl) {
+    const Tile t = vt[blockIdx.x];
+    if (active && !active[t.prob]) return;
+    const PatchInfo& p = P[t.patch];
+    const double a = sc ? sc[t.prob] : 1.0;
+    for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+        const int c = interior_index(p, lin);
+        y[c] = a * x[c];
+        y[c + nl] = a * x[c + nl];
+    }
+}
+
+void scale_copy(const Dev& D, hipStream_t s, const double* x, const double* sc, double* y) {
+    k_scale_copy<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.active, x, sc, y, D.nl);
+}
+void copy_interior(const Dev& D, hipStream_t s, const double* x, double* y) {
+    k_scale_copy<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.active, x, nullptr, y,
+                                              D.nl);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ x, int64_t n, T v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+void fill_native(hipStream_t s, double* x, int64_t n, double v) {
+    if (n > 0) k_fill<double><<<nblocks(n), kBlock, 0, s>>>(x, n, v);
+}
+void fill_native_f(hipStream_t s, float* x, int64_t n, float v) {
+    if (n > 0) k_fill<float><<<nblocks(n), kBlock, 0, s>>>(x, n, v);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack(const Tile* __restrict__ vt,
+                                                 const PatchInfo* __restrict__ P,
+                                                 const int64_t* __restrict__ coff,
+                                                 const double* __restrict__ nat,
+                                                 double* __restrict__ cmp, int nf, int dir,
+                                                 int64_t nl, int64_t ncells) {
+    const Tile t = vt[blockIdx.x];
+    const PatchInfo& p = P[t.patch];
+    const int64_t base = coff[t.patch];
+    for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+        const int c = interior_index(p, lin);
+        for (int f = 0; f < nf; ++f) {
+            if (dir == 0)
+                cmp[f * ncells + base + lin] = nat[f * nl + c];
+            else
+                const_cast<double*>(nat)[f * nl + c] = cmp[f * ncells + base + lin];
+        }
+    }
+}
+
+void pack(const Dev& D, hipStream_t s, const int64_t* coff, const double* native,
+          double* compact, int nf, int64_t ncells) {
+    k_pack<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, coff, native, compact, nf, 0,
+                                        D.nl, ncells);
+}
+void unpack(const Dev& D, hipStream_t s, const int64_t* coff, const double* compact,
+            double* native, int nf, int64_t ncells) {
+    k_pack<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, coff, native,
+                                        const_cast<double*>(compact), nf, 1, D.nl, ncells);
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_pos(const Tile* __restrict__ vt,
+                                                      const PatchInfo* __restrict__ P,
+                                                      const double* __restrict__ x, int nf,
+                                                      int32_t* __restrict__ flag,
+                                                      int64_t nl) {
+    const Tile t = vt[blockIdx.x];
+    const PatchInfo& p = P[t.patch];
+    int bad = 0;
+    for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+        const int c = interior_index(p, lin);
+        for (int f = 0; f < nf; ++f) {
+            const double v = x[f * nl + c];
+            if (!(v > 0.0) || !(v < DBL_MAX)) bad = 1;
+        }
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+void check_positive(const Dev& D, hipStream_t s, const double* x, int nf, int32_t* flag) {
+    k_check_pos<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, x, nf, flag, D.nl);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cube(const double* __restrict__ z,
+                                                 double* __restrict__ z3, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double v = z[i];
+        z3[i] = v * v * v;
+    }
+}
+void cube(hipStream_t s, const double* z, double* z3, int64_t n) {
+    if (n > 0) k_cube<<<nblocks(n), kBlock, 0, s>>>(z, z3, n);
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_float(const double* __restrict__ x,
+                                                     float* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (float)x[i];
+}
+__global__ __launch_bounds__(kBlock) void k_to_double(const float* __restrict__ x,
+                                                      double* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (double)x[i];
+}
+void to_float(hipStream_t s, const double* x, float* y, int64_t n) {
+    if (n > 0) k_to_float<<<nblocks(n), kBlock, 0, s>>>(x, y, n);
+}
+void to_double(hipStream_t s, const float* x, double* y, int64_t n) {
+    if (n > 0) k_to_double<<<nblocks(n), kBlock, 0, s>>>(x, y, n);
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES per-problem scalars (one thread per problem)
+//   H: [nprob][(m+1) * m], column j at H[p][(m+1) j]
+// ---------------------------------------------------------------------------
+
+__global__ void k_gmres_column(int nprob, int m, int j, const int32_t* __restrict__ active,
+                               const double* __restrict__ h1, const double* __restrict__ h2,
+                               const double* __restrict__ hn2, double* __restrict__ H,
+                               double* __restrict__ cs, double* __restrict__ sn,
+                               double* __restrict__ g, double* __restrict__ rho,
+                               double* __restrict__ vscale) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    if (active && !active[p]) {
+        vscale[p] = 0.0;
+        return;
+    }
+    double* col = H + (int64_t)p * (m + 1) * m + (int64_t)(m + 1) * j;
+    double* c = cs + p * m;
+    double* s = sn + p * m;
+    double* gg = g + p * (m + 1);
+    for (int i = 0; i <= j; ++i) col[i] = h1[p * (j + 1) + i] + h2[p * (j + 1) + i];
+    const double hn = sqrt(hn2[p]);
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double tmp = c[i] * col[i] + s[i] * col[i + 1];
+        col[i + 1] = -s[i] * col[i] + c[i] * col[i + 1];
+        col[i] = tmp;
+    }
+    const double a = col[j], b = col[j + 1];
+    double cc, ss, r;
+    if (b == 0.0) {
+        cc = 1.0;
+        ss = 0.0;
+        r = a;
+    } else {
+        r = sqrt(a * a + b * b);
+        cc = a / r;
+        ss = b / r;
+    }
+    c[j] = cc;
+    s[j] = ss;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    gg[j + 1] = -ss * gg[j];
+    gg[j] = cc * gg[j];
+    rho[p] = fabs(gg[j + 1]);
+    vscale[p] = hn > 0.0 ? 1.0 / hn : 0.0;
+}
+
+void gmres_column(hipStream_t s, int nprob, int m, int j, const int32_t* active,
+                  const double* h1, const double* h2, const double* hn2, double* H, double* cs,
+                  double* sn, double* g, double* rho, double* vscale) {
+    k_gmres_column<<<(nprob + 63) / 64, 64, 0, s>>>(nprob, m, j, active, h1, h2, hn2, H, cs,
+                                                    sn, g, rho, vscale);
+}
+
+__global__ void k_gmres_backsolve(int nprob, int m, const int32_t* __restrict__ kdim,
+                                  const double* __restrict__ H, const double* __restrict__ g,
+                                  double* __restrict__ y) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    const int k = kdim[p];
+    const double* Hp = H + (int64_t)p * (m + 1) * m;
+    const double* gp = g + p * (m + 1);
+    double* yp = y + p * m;
+    for (int i = k; i < m; ++i) yp[i] = 0.0;
+    for (int i = k - 1; i >= 0; --i) {
+        double acc = gp[i];
+        for (int l = i + 1; l < k; ++l) acc -= Hp[(m + 1) * l + i] * yp[l];
+        yp[i] = acc / Hp[(m + 1) * i + i];
+    }
+}
+
+void gmres_backsolve(hipStream_t s, int nprob, int m, const int32_t* kdim, const double* H,
+                     const double* g, double* y) {
+    k_gmres_backsolve<<<(nprob + 63) / 64, 64, 0, s>>>(nprob, m, kdim, H, g, y);
+}
+
+}  // namespace nrd

@@ -1,0 +1,274 @@
+"""ctypes binding of libnrd.so (the C ABI in include/nrd.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory (the workspace and the vectors)
+and the stream.  Importing this module fails loudly if the library has not
+been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnrd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_1302_6303_amd.build`")
+# torch ships its own HIP runtime (soname libamdhip64.so.7); loading it first
+# makes libnrd.so resolve to that same runtime instead of a second copy.
+import torch  # noqa: E402,F401
+_lib = C.CDLL(LIB_PATH)
+
+NRD_OK, NRD_EINVAL, NRD_ENESTING, NRD_ESTATE = 0, -1, -2, -3
+NRD_ENONPOS, NRD_ENOTCONV, NRD_EDEVICE, NRD_EUNSUPPORTED = -4, -5, -6, -7
+NRD_FP64, NRD_MIXED = 0, 1
+NRD_BATCHED, NRD_PER_PATCH = 0, 1
+NRD_TIMER_RESIDUAL, NRD_TIMER_JVP, NRD_TIMER_PRECOND = 0, 1, 2
+
+
+class nrd_box(C.Structure):
+    _fields_ = [("problem", C.c_int32), ("level", C.c_int32),
+                ("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3)]
+
+
+class nrd_problem(C.Structure):
+    _fields_ = [("base_n", C.c_int32 * 3), ("lo", C.c_double * 3),
+                ("hi", C.c_double * 3), ("bc_E", C.c_int32 * 6),
+                ("robin_R", C.c_double * 6), ("kappa", C.c_double)]
+
+
+class nrd_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("launch", C.c_int32),
+                ("use_graph", C.c_int32), ("jvp_mode", C.c_int32),
+                ("limiter", C.c_double), ("p2_mode", C.c_int32),
+                ("newton_rtol", C.c_double), ("newton_atol", C.c_double),
+                ("newton_maxit", C.c_int32), ("gmres_restart", C.c_int32),
+                ("gmres_maxrestarts", C.c_int32), ("mg_nu_pre", C.c_int32),
+                ("mg_nu_post", C.c_int32), ("adjoint_slots", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
+
+
+class nrd_step_stats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("krylov_iters", C.c_int32),
+                ("positivity_cuts", C.c_int32), ("converged", C.c_int32),
+                ("fnorm0", C.c_double), ("fnorm", C.c_double),
+                ("krylov_per_newton", C.c_int32 * 24)]
+
+    def as_dict(self):
+        return {"newton_iters": self.newton_iters,
+                "krylov_iters": self.krylov_iters,
+                "positivity_cuts": self.positivity_cuts,
+                "converged": bool(self.converged), "fnorm0": self.fnorm0,
+                "fnorm": self.fnorm,
+                "krylov_per_newton": list(self.krylov_per_newton[:self.newton_iters])}
+
+
+_H = C.c_void_p
+_P = C.c_void_p
+_sigs = {
+    "nrd_last_error": (C.c_char_p, []),
+    "nrd_default_options": (None, [C.POINTER(nrd_options)]),
+    "nrd_hierarchy_create": (C.c_int32, [C.POINTER(nrd_problem), C.c_int32,
+                                         C.POINTER(nrd_box), C.c_int32,
+                                         C.POINTER(nrd_options), _P, C.POINTER(_H)]),
+    "nrd_hierarchy_destroy": (C.c_int32, [_H]),
+    "nrd_workspace_size": (C.c_int32, [_H, C.POINTER(C.c_size_t)]),
+    "nrd_bind_workspace": (C.c_int32, [_H, _P, C.c_size_t]),
+    "nrd_layout": (C.c_int32, [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "nrd_pack": (C.c_int32, [_H, _P, _P]),
+    "nrd_unpack": (C.c_int32, [_H, _P, _P]),
+    "nrd_set_fields": (C.c_int32, [_H, _P, _P, _P]),
+    "nrd_get_fields": (C.c_int32, [_H, _P, _P]),
+    "nrd_begin_step": (C.c_int32, [_H, C.POINTER(C.c_double)]),
+    "nrd_residual": (C.c_int32, [_H, _P, _P]),
+    "nrd_jvp": (C.c_int32, [_H, _P, _P, _P]),
+    "nrd_precond_setup": (C.c_int32, [_H, _P]),
+    "nrd_precond_apply": (C.c_int32, [_H, _P, _P]),
+    "nrd_vjp": (C.c_int32, [_H, _P, _P, _P, _P]),
+    "nrd_implicit_step": (C.c_int32, [_H, C.POINTER(C.c_double),
+                                      C.POINTER(nrd_step_stats)]),
+    "nrd_adjoint_run": (C.c_int32, [_H, C.POINTER(C.c_double), C.c_int32,
+                                    C.c_int32, _P, _P]),
+    "nrd_dot": (C.c_int32, [_H, _P, _P, C.POINTER(C.c_double)]),
+    "nrd_timer_enable": (C.c_int32, [_H, C.c_int32]),
+    "nrd_timer_read": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_int32)]),
+}
+EXPORTED = tuple(_sigs)
+for _name, (_res, _args) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+
+class NrdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"nrd status {status}: {msg}")
+        self.status = status
+
+
+def check(status):
+    if status != NRD_OK:
+        raise NrdError(status, nrd_last_error().decode())
+    return status
+
+
+def default_options(**kw) -> nrd_options:
+    o = nrd_options()
+    nrd_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def make_problems(problems) -> C.Array:
+    arr = (nrd_problem * len(problems))()
+    for a, p in zip(arr, problems):
+        a.base_n[:] = [int(v) for v in p.base_n]
+        a.lo[:] = [float(v) for v in p.lo]
+        a.hi[:] = [float(v) for v in p.hi]
+        a.bc_E[:] = [int(v) for v in p.bc_E]
+        a.robin_R[:] = [float(v) for v in p.robin_R]
+        a.kappa = float(p.kappa)
+    return arr
+
+
+def make_boxes(boxes) -> C.Array:
+    arr = (nrd_box * len(boxes))()
+    for a, b in zip(arr, boxes):
+        a.problem = int(b.problem)
+        a.level = int(b.level)
+        a.lo[:] = [int(v) for v in b.lo]
+        a.hi[:] = [int(v) for v in b.hi]
+    return arr
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _dt(values):
+    return (C.c_double * len(values))(*[float(v) for v in values])
+
+
+class Hierarchy:
+    """Owns one nrd_hierarchy and its torch-allocated workspace."""
+
+    def __init__(self, problems, boxes, options: Optional[nrd_options] = None,
+                 device="cuda", stream=None, bind=True):
+        import torch
+        self.torch = torch
+        self.problems = problems
+        self.boxes = boxes
+        self._probs = make_problems(problems)
+        self._boxes = make_boxes(boxes)
+        self.opt = options if options is not None else default_options()
+        self.device = device
+        h = _H()
+        s = None
+        if bind:
+            st = stream if stream is not None else torch.cuda.current_stream()
+            s = C.c_void_p(st.cuda_stream)
+            self.stream = st
+        check(nrd_hierarchy_create(self._probs, len(problems), self._boxes, len(boxes),
+                                   C.byref(self.opt), s, C.byref(h)))
+        self.h = h
+        n = C.c_int64()
+        nl = C.c_int64()
+        check(nrd_layout(h, C.byref(n), C.byref(nl)))
+        self.ncells, self.native_len = n.value, nl.value
+        sz = C.c_size_t()
+        check(nrd_workspace_size(h, C.byref(sz)))
+        self.workspace_bytes = sz.value
+        self.nprob = len(problems)
+        self.ws = None
+        if bind:
+            self.ws = torch.empty(sz.value, dtype=torch.uint8, device=device)
+            check(nrd_bind_workspace(h, _ptr(self.ws), sz.value))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            nrd_hierarchy_destroy(h)
+            self.h = None
+
+    # -- vectors ----------------------------------------------------------
+    def native(self):
+        return self.torch.zeros(2 * self.native_len, dtype=self.torch.float64,
+                                device=self.device)
+
+    def compact(self, nf=2):
+        return self.torch.zeros(nf * self.ncells, dtype=self.torch.float64,
+                                device=self.device)
+
+    def pack(self, native, out=None):
+        out = self.compact() if out is None else out
+        check(nrd_pack(self.h, _ptr(native), _ptr(out)))
+        return out
+
+    def unpack(self, compact, out=None):
+        out = self.native() if out is None else out
+        check(nrd_unpack(self.h, _ptr(compact), _ptr(out)))
+        return out
+
+    # -- calls ------------------------------------------------------------
+    def set_fields(self, E, T, z):
+        check(nrd_set_fields(self.h, _ptr(E), _ptr(T), _ptr(z)))
+
+    def get_fields(self):
+        E = self.compact(1)
+        T = self.compact(1)
+        check(nrd_get_fields(self.h, _ptr(E), _ptr(T)))
+        return E, T
+
+    def begin_step(self, dt: Sequence[float]):
+        check(nrd_begin_step(self.h, _dt(dt)))
+
+    def residual(self, u, F):
+        check(nrd_residual(self.h, _ptr(u), _ptr(F)))
+        return F
+
+    def jvp(self, u, v, Jv):
+        check(nrd_jvp(self.h, _ptr(u), _ptr(v), _ptr(Jv)))
+        return Jv
+
+    def precond_setup(self, u):
+        check(nrd_precond_setup(self.h, _ptr(u)))
+
+    def precond_apply(self, w, y):
+        check(nrd_precond_apply(self.h, _ptr(w), _ptr(y)))
+        return y
+
+    def vjp(self, u, lam, JTl, gz=None):
+        check(nrd_vjp(self.h, _ptr(u), _ptr(lam), _ptr(JTl), _ptr(gz)))
+        return JTl, gz
+
+    def implicit_step(self, dt: Sequence[float], raise_on_fail=True):
+        st = (nrd_step_stats * self.nprob)()
+        rc = nrd_implicit_step(self.h, _dt(dt), st)
+        if raise_on_fail:
+            check(rc)
+        return rc, [s.as_dict() for s in st]
+
+    def adjoint_run(self, dt, nsteps, ckpt_every, dJdE=None):
+        gz = self.compact(1)
+        check(nrd_adjoint_run(self.h, _dt(dt), nsteps, ckpt_every, _ptr(dJdE), _ptr(gz)))
+        return gz
+
+    def dot(self, x, y) -> List[float]:
+        out = (C.c_double * self.nprob)()
+        check(nrd_dot(self.h, _ptr(x), _ptr(y), out))
+        return list(out)
+
+    def timer_enable(self, on=True):
+        check(nrd_timer_enable(self.h, 1 if on else 0))
+
+    def timer_read(self, which):
+        ms = C.c_double()
+        n = C.c_int32()
+        check(nrd_timer_read(self.h, which, C.byref(ms), C.byref(n)))
+        return ms.value, n.value

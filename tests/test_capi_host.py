@@ -1,0 +1,68 @@
+"""C ABI on the host: the library loads, exports every declared symbol and
+validates hierarchies (no device calls)."""
+import os
+import re
+
+import pytest
+
+from paper_1302_6303_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_every_declared_symbol_is_exported():
+    from paper_1302_6303_amd import nrd
+    hdr = open(os.path.join(ROOT, "include", "nrd.h")).read()
+    declared = set(re.findall(r"\b(nrd_[a-z_]+)\s*\(", hdr))
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(nrd._lib, name), name
+    assert declared == set(nrd.EXPORTED)
+
+
+def _create(problems, boxes, **opt):
+    from paper_1302_6303_amd import nrd
+    return nrd.Hierarchy(problems, boxes, nrd.default_options(**opt), bind=False)
+
+
+def test_layout_counts():
+    w = I.small_amr(8)
+    H = _create(w.problems, w.boxes)
+    assert H.ncells == sum(b.ncells for b in w.boxes)
+    assert H.native_len == sum((b.shape[0] + 2) * (b.shape[1] + 2) * (b.shape[2] + 2)
+                               for b in w.boxes)
+    assert H.workspace_bytes > 40 * 2 * 8 * H.native_len      # Krylov basis included
+
+
+@pytest.mark.parametrize("boxes,status", [
+    ([(0, (0, 0, 0), (8, 8, 8)), (1, (0, 0, 0), (4, 4, 4)), (1, (2, 2, 2), (6, 6, 6))], -2),
+    ([(0, (0, 0, 0), (8, 8, 8)), (1, (1, 2, 2), (5, 6, 6))], -2),
+    ([(0, (0, 0, 0), (8, 8, 8)), (1, (2, 2, 2), (6, 6, 6)), (2, (4, 4, 4), (10, 10, 10))], -2),
+    ([(0, (0, 0, 0), (4, 8, 8)), (0, (4, 0, 0), (8, 8, 8))], -2),       # two level-0 boxes
+    ([(0, (0, 0, 0), (8, 8, 8)), (2, (4, 4, 4), (8, 8, 8))], -2),       # level gap
+    ([(1, (2, 2, 2), (6, 6, 6)), (0, (0, 0, 0), (8, 8, 8))], -1),       # unordered
+])
+def test_invalid_hierarchies_are_rejected(boxes, status):
+    from paper_1302_6303_amd import nrd
+    bx = [I.Box(0, lv, lo, hi) for lv, lo, hi in boxes]
+    with pytest.raises(nrd.NrdError) as e:
+        _create([I.Problem((8, 8, 8))], bx)
+    assert e.value.status == status
+
+
+def test_bad_options_are_rejected():
+    from paper_1302_6303_amd import nrd
+    w = I.marshak_single(8)
+    for kw in ({"gmres_restart": 0}, {"gmres_restart": 65}, {"newton_maxit": 0},
+               {"jvp_mode": 1}):
+        with pytest.raises(nrd.NrdError):
+            _create(w.problems, w.boxes, **kw)
+
+
+def test_calls_before_binding_report_state_error():
+    from paper_1302_6303_amd import nrd
+    import ctypes as C
+    w = I.marshak_single(8)
+    H = _create(w.problems, w.boxes)
+    rc = nrd.nrd_residual(H.h, C.c_void_p(0), C.c_void_p(0))
+    assert rc == nrd.NRD_ESTATE
