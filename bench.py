@@ -1,0 +1,199 @@
+"""Benchmark of the implicit radiation-diffusion hot path on one MI355X.
+
+One step = one BDF implicit step (inexact Newton, FGMRES, FAC/multigrid
+preconditioner, flux-limited residual and Jacobian action) over every problem
+of the workload.  Prints ONE JSON line:
+
+  value        residual throughput in Gcells/s (composite cells per second of
+               the residual kernel, timed with HIP events on the library
+               stream during the timed implicit steps)
+  ms_per_step  wall time per implicit step of the mixed-precision batched
+               solver (float V-cycles, float64 Newton/GMRES/residual)
+  fp64_plain   the same steps with a float64 preconditioner and one kernel
+               launch per patch
+  roofline     the residual kernel against the 8 TB/s HBM peak
+  cpu_baseline the float64 CPU oracle's residual on a bounded sample
+
+Workloads (seeded, synthetic; --workload):
+  ensemble  64 independent uniform problems of 32^3..96^3 cells with random
+            material boxes and time steps (21.6 M cells), 10 steps
+  amr       64^3 base + 2 levels of static refinement around two material
+            boxes (1.04 M composite+covered cells), dt = 5e-4
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_CELL_RESIDUAL = 56      # read E, T, z^3, b_E, b_T; write F_E, F_T (f64)
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_1302_6303_amd import inputs as I
+    if name == "ensemble":
+        return I.ensemble()
+    if name == "amr":
+        return I.static_amr()
+    if name == "uniform":
+        return I.marshak_single(32)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def composite_cells(w):
+    """Cells not covered by a finer box (host-side count)."""
+    from paper_1302_6303_amd.inputs import Box
+    tot = 0
+    for b in w.boxes:
+        n = b.ncells
+        for c in w.boxes:
+            if c.problem == b.problem and c.level == b.level + 1:
+                ov = 1
+                for d in range(3):
+                    lo = max(c.lo[d] // 2, b.lo[d])
+                    hi = min(c.hi[d] // 2, b.hi[d])
+                    ov *= max(0, hi - lo)
+                n -= ov
+        tot += n
+    return tot
+
+
+def run_solver(w, opts, steps, warmup, time_residual):
+    import torch
+    from paper_1302_6303_amd import nrd
+    from tests.gpu_helpers import compact_state, to_dev
+    H = nrd.Hierarchy(w.problems, w.boxes, opts)
+    u = compact_state(w)
+    n = H.ncells
+    H.set_fields(to_dev(u[:n]), to_dev(u[n:]), to_dev(w.compact(w.z)))
+    dt = list(w.dt)
+    newton = krylov = 0
+    tag = "mixed" if opts.precision == nrd.NRD_MIXED else "fp64"
+    for i in range(warmup):
+        _, st = H.implicit_step(dt)
+        log(f"{tag} warmup step {i}: newton {sum(x['newton_iters'] for x in st)} "
+            f"krylov {sum(x['krylov_iters'] for x in st)}")
+    torch.cuda.synchronize()
+    if time_residual:
+        H.timer_enable(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        _, st = H.implicit_step(dt)
+        newton += sum(s["newton_iters"] for s in st)
+        krylov += sum(s["krylov_iters"] for s in st)
+        log(f"{tag} step {i} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res = {"s_per_step": (t1 - t0) / steps, "newton_per_step": newton / steps,
+           "krylov_per_step": krylov / steps, "ws_GB": H.workspace_bytes / 1e9}
+    if time_residual:
+        for key, which in (("residual", nrd.NRD_TIMER_RESIDUAL), ("jvp", nrd.NRD_TIMER_JVP),
+                           ("precond", nrd.NRD_TIMER_PRECOND)):
+            ms, cnt = H.timer_read(which)
+            res[key + "_ms_avg"] = ms / max(cnt, 1)
+            res[key + "_launches"] = cnt
+        H.timer_enable(False)
+    del H
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """Oracle residual (float64, numpy, one thread) on whole problems of the
+    workload until the time budget is used."""
+    import numpy as np
+    from tests.helpers import system, state
+    cells = 0
+    t_used = 0.0
+    used = []
+    for p in range(len(w.problems)):
+        s = system(w, pidx=p)
+        u = state(s, w, pidx=p)
+        t0 = time.perf_counter()
+        s.residual(u, u, float(w.dt[p]), 1.0)
+        t_used += time.perf_counter() - t0
+        cells += s.nc
+        used.append(p)
+        if t_used > budget_s:
+            break
+    return {"value": cells / t_used / 1e9, "unit": "Gcells/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"float64 numpy residual of {len(used)} whole problems "
+                      f"({cells} cells) of the same workload, {t_used:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ensemble")
+    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 per-patch run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py runs on exactly one GPU: the hot path is single-GPU "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        raise SystemExit(2)
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from paper_1302_6303_amd import nrd
+    w = workload(a.workload)
+    ncomp = composite_cells(w)
+    mixed = run_solver(w, nrd.default_options(precision=nrd.NRD_MIXED,
+                                              launch=nrd.NRD_BATCHED),
+                       a.steps, a.warmup, True)
+    plain = None
+    if not a.no_plain:
+        plain = run_solver(w, nrd.default_options(precision=nrd.NRD_FP64,
+                                                  launch=nrd.NRD_PER_PATCH),
+                           a.steps, a.warmup, False)
+    res_s = mixed["residual_ms_avg"] / 1e3
+    gcells = ncomp / res_s / 1e9
+    achieved = BYTES_PER_CELL_RESIDUAL * ncomp / res_s / 1e9
+    out = {
+        "metric": "residual Gcells/s (%HBM peak) + s/implicit step, mixed-batched vs FP64 plain",
+        "value": round(gcells, 3),
+        "unit": "Gcells/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(mixed["s_per_step"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "problems": len(w.problems),
+                   "boxes": len(w.boxes), "cells": w.ncells(),
+                   "composite_cells": ncomp,
+                   "solver": "BDF1->BDF2, Newton rtol 1e-8, FGMRES(30), FAC V(1,0) + MG V(1,1)"},
+        "roofline": {"bound": "hbm", "kernel": "k_stencil<0> (residual)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_cell": BYTES_PER_CELL_RESIDUAL,
+                     "avg_launch_ms": round(mixed["residual_ms_avg"], 4)},
+        "mixed_batched": {k: (round(v, 5) if isinstance(v, float) else v)
+                          for k, v in mixed.items()},
+    }
+    if plain is not None:
+        out["fp64_plain"] = {k: (round(v, 5) if isinstance(v, float) else v)
+                             for k, v in plain.items()}
+        out["speedup_mixed_batched_vs_fp64_plain"] = round(plain["s_per_step"] /
+                                                           mixed["s_per_step"], 3)
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

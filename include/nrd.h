@@ -109,12 +109,17 @@ typedef struct {
     int32_t mg_nu_post;
     int32_t adjoint_slots;  /* device state slots reserved for nrd_adjoint_run:
                                ceil(nsteps / ckpt_every) + ckpt_every        */
-    int32_t reserved[7];
+    int32_t stencil;        /* residual / Jacobian kernel: 0 one thread per
+                               cell in runs of 256 cells (six faces each),
+                               1 plane-marching tiles (each face once, LDS),
+                               2 wave runs (x faces shared across lanes)     */
+    int32_t zchunk;         /* planes per tile of variants 1, 2 (0: default)  */
+    int32_t reserved[5];
 } nrd_options;
 
 /* Fills *opt with the defaults: FP64, batched, no graph, analytic JVP,
  * limiter 1, paper P2, rtol 1e-8, atol 1e-14, 20 Newton iterations,
- * GMRES(30) with 10 restarts, V(1,1). */
+ * GMRES(30) with 10 restarts, V(1,1), plane-marching stencil. */
 void nrd_default_options(nrd_options* opt);
 
 typedef struct {

@@ -67,6 +67,38 @@ inline int64_t intersect(const int32_t alo[3], const int32_t ahi[3],
 
 }  // namespace
 
+int32_t default_zchunk(const int32_t n[3]) {
+    // short runs keep enough waves resident to hide load latency; the first
+    // face of each run is the only repeated face
+    return n[0] * n[1] >= 4096 ? 4 : 8;
+}
+
+void build_planes(Tables& t, const std::vector<int32_t>& kc, int32_t run) {
+    t.stiles.clear();
+    t.level_stile0.assign(t.nlev + 1, 0);
+    t.patch_stile0.assign(t.nbox + 1, 0);
+    std::vector<std::vector<STile>> per(t.nbox);
+    for (int b = 0; b < t.nbox; ++b) {
+        const PatchInfo& p = t.patches[b];
+        const int32_t plane = p.n[0] * p.n[1];
+        const int32_t ch = std::max(1, kc[b]);
+        for (int32_t k0 = 0; k0 < p.n[2]; k0 += ch)
+            for (int32_t s0 = 0; s0 < plane; s0 += run)
+                per[b].push_back({b, p.prob, s0, std::min(run, plane - s0), k0,
+                                  std::min(p.n[2], k0 + ch), {0, 0}});
+    }
+    for (int l = 0; l < t.nlev; ++l) {
+        t.level_stile0[l] = (int32_t)t.stiles.size();
+        for (int b = 0; b < t.nbox; ++b) {
+            if (t.boxes[b].level != l) continue;
+            t.patch_stile0[b] = (int32_t)t.stiles.size();
+            t.stiles.insert(t.stiles.end(), per[b].begin(), per[b].end());
+        }
+    }
+    t.level_stile0[t.nlev] = (int32_t)t.stiles.size();
+    t.patch_stile0[t.nbox] = (int32_t)t.stiles.size();
+}
+
 nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
                         const nrd_box* boxes, int32_t nbox, int32_t tile_cells,
                         int32_t vtile_cells, Tables& t, std::string& msg) {
@@ -464,6 +496,11 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
         }
     }
     t.level_tile0[t.nlev] = (int32_t)t.tiles.size();
+    {
+        std::vector<int32_t> kc(nbox);
+        for (int b = 0; b < nbox; ++b) kc[b] = default_zchunk(t.patches[b].n);
+        build_planes(t, kc, 256);   // default stencil variant: plane marching
+    }
     t.prob_vtile0.assign(nprob + 1, 0);
     for (int p = 0; p < nprob; ++p) {
         t.prob_vtile0[p] = (int32_t)t.vtiles.size();
@@ -566,8 +603,9 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
         boff += (int64_t)nb * nb;
         t.bottom_max = std::max(t.bottom_max, nb);
     }
-    if (t.bottom_max > 1024) {
-        msg = "coarsest multigrid grid too large for the dense bottom solve (> 1024 cells)";
+    if (t.bottom_max > 128) {
+        msg = "coarsest multigrid grid too large for the dense bottom solve (> 128 cells); "
+              "base grid extents must halve down to at most 128 cells";
         return NRD_EUNSUPPORTED;
     }
     return NRD_OK;

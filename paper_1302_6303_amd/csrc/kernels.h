@@ -10,6 +10,16 @@ namespace nrd {
 constexpr int kMaxLev = 12;
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Tile lists are ordered so that neighbouring tiles share halo data;
+// this bijection gives each XCD a contiguous range of tiles instead of every
+// 8th one, so a tile's neighbours sit in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int x = b & 7, q = b >> 3;
+    const int base = n >> 3, rem = n & 7;
+    return x * base + (x < rem ? x : rem) + q;
+}
+
 // Device views of the hierarchy tables (pointers into the workspace) plus the
 // host-side counts that size the launches.
 struct Dev {
@@ -18,6 +28,9 @@ struct Dev {
     const PatchInfo* patches = nullptr;
     const Tile* tiles = nullptr;
     int32_t level_tile0[kMaxLev + 1] = {};
+    const STile* stiles = nullptr;           // z-marching bricks
+    int32_t level_stile0[kMaxLev + 1] = {};
+    int32_t bricks = 0;                      // stencil variant: 0 flat, 1 bricks
     const Tile* vtiles = nullptr;
     int32_t nvtiles = 0;
     const int32_t* prob_vtile0 = nullptr;    // device [nprob+1]
@@ -50,7 +63,8 @@ void restrict_f(const Dev& D, hipStream_t s, float* x, int nf, int lev_lo = 0);
 void sibling_exchange_f(const Dev& D, hipStream_t s, float* x, int nf, int lev);
 void sibling_exchange_d(const Dev& D, hipStream_t s, double* x, int nf, int lev);
 
-// F = c0 u - b - dt f(u) over tiles [t0, t0+nt); covered cells = 0.
+// F = c0 u - b - dt f(u) over tiles [t0, t0+nt) (bricks if D.bricks);
+// covered cells = 0.
 void residual(const Dev& D, hipStream_t s, int t0, int nt, const double* u,
               const double* b, double* F);
 void residual_reflux(const Dev& D, hipStream_t s, const double* u, double* F);

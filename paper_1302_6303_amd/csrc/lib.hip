@@ -67,7 +67,7 @@ struct nrd_hierarchy {
 
     // workspace offsets
     struct Off {
-        size_t patches, tiles, vtiles, prob_vtile0, gcopy, gcf, sib, sync[kMaxLev], rfaces,
+        size_t patches, tiles, stiles, vtiles, prob_vtile0, gcopy, gcf, sib, sync[kMaxLev], rfaces,
             rcells, ctype, shadows, shadow_src, coff, ps, active;
         size_t mg_box[kMaxMG], mg_tiles[kMaxMG], mg_box_of[kMaxMG], mg_smooth[kMaxMG],
             mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bottom_off, Lbuf, Xbuf;
@@ -97,6 +97,19 @@ struct nrd_hierarchy {
     std::vector<int32_t> host_active;
 
     int64_t nl2() const { return 2 * t.nl; }
+    // stencil launch ranges for the selected variant
+    int ntiles_stencil() const {
+        return D.bricks ? D.level_stile0[D.nlev] : D.level_tile0[D.nlev];
+    }
+    void tile_range(int b, int& a0, int& n0) const {
+        if (D.bricks) {
+            a0 = t.patch_stile0[b];
+            n0 = t.patch_stile0[b + 1] - a0;
+        } else {
+            a0 = patch_tile0[b];
+            n0 = (int)t.patch_tiles[b].size();
+        }
+    }
     template <typename T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 
@@ -134,6 +147,7 @@ static void layout(nrd_hierarchy* h) {
     const int m = h->m;
     o.patches = b.take(sizeof(PatchInfo) * t.patches.size());
     o.tiles = b.take(sizeof(Tile) * std::max<size_t>(1, t.tiles.size()));
+    o.stiles = b.take(sizeof(STile) * std::max<size_t>(1, t.stiles.size()));
     o.vtiles = b.take(sizeof(Tile) * std::max<size_t>(1, t.vtiles.size()));
     o.prob_vtile0 = b.take(sizeof(int32_t) * t.prob_vtile0.size());
     o.gcopy = b.take(sizeof(GhostCopy) * std::max<size_t>(1, t.gcopy.size()));
@@ -167,7 +181,7 @@ static void layout(nrd_hierarchy* h) {
         for (int d = 0; d < 3; ++d) nb *= t.probs[p].base_n[d] >> t.prob_mgdepth[p];
         bsum += nb * nb;
     }
-    o.Lbuf = b.take(sizeof(double) * 2 * bsum);
+    o.Lbuf = b.take(8);
     o.Xbuf = b.take(sizeof(double) * 2 * bsum);
     // state and work vectors (double)
     o.z = b.take(8 * nl);
@@ -284,6 +298,7 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     fill_native(s, reinterpret_cast<double*>(h->ws), (int64_t)(h->ws_bytes / 8), 0.0);
     HIPCHK(up(s, h->ws + o.patches, t.patches));
     HIPCHK(up(s, h->ws + o.tiles, t.tiles));
+    HIPCHK(up(s, h->ws + o.stiles, t.stiles));
     HIPCHK(up(s, h->ws + o.vtiles, t.vtiles));
     HIPCHK(up(s, h->ws + o.prob_vtile0, t.prob_vtile0));
     HIPCHK(up(s, h->ws + o.gcopy, t.gcopy));
@@ -341,6 +356,9 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     D.patches = h->at<PatchInfo>(o.patches);
     D.tiles = h->at<Tile>(o.tiles);
     for (int l = 0; l <= t.nlev; ++l) D.level_tile0[l] = t.level_tile0[l];
+    D.stiles = h->at<STile>(o.stiles);
+    D.bricks = h->opt.stencil;
+    for (int l = 0; l <= t.nlev; ++l) D.level_stile0[l] = t.level_stile0[l];
     D.vtiles = h->at<Tile>(o.vtiles);
     D.nvtiles = (int32_t)t.vtiles.size();
     D.prob_vtile0 = h->at<int32_t>(o.prob_vtile0);
@@ -446,11 +464,13 @@ static void op_residual(nrd_hierarchy* h, double* u, double* F, bool prepared = 
     auto tk = h->tic(NRD_TIMER_RESIDUAL);
     const Dev& D = h->D;
     if (h->opt.launch == NRD_PER_PATCH) {
-        for (int b = 0; b < h->t.nbox; ++b)
-            residual(D, h->stream, h->patch_tile0[b], (int)h->t.patch_tiles[b].size(), u,
-                     h->bvec, F);
+        for (int b = 0; b < h->t.nbox; ++b) {
+            int a0, n0;
+            h->tile_range(b, a0, n0);
+            residual(D, h->stream, a0, n0, u, h->bvec, F);
+        }
     } else {
-        residual(D, h->stream, 0, D.level_tile0[D.nlev], u, h->bvec, F);
+        residual(D, h->stream, 0, h->ntiles_stencil(), u, h->bvec, F);
     }
     residual_reflux(D, h->stream, u, F);
     h->toc(NRD_TIMER_RESIDUAL, tk);
@@ -462,10 +482,13 @@ static void op_jvp(nrd_hierarchy* h, double* u, double* v, double* Jv, bool u_pr
     auto tk = h->tic(NRD_TIMER_JVP);
     const Dev& D = h->D;
     if (h->opt.launch == NRD_PER_PATCH) {
-        for (int b = 0; b < h->t.nbox; ++b)
-            jvp(D, h->stream, h->patch_tile0[b], (int)h->t.patch_tiles[b].size(), u, v, Jv);
+        for (int b = 0; b < h->t.nbox; ++b) {
+            int a0, n0;
+            h->tile_range(b, a0, n0);
+            jvp(D, h->stream, a0, n0, u, v, Jv);
+        }
     } else {
-        jvp(D, h->stream, 0, D.level_tile0[D.nlev], u, v, Jv);
+        jvp(D, h->stream, 0, h->ntiles_stencil(), u, v, Jv);
     }
     jvp_reflux(D, h->stream, u, v, Jv);
     h->toc(NRD_TIMER_JVP, tk);
@@ -1052,6 +1075,7 @@ void nrd_default_options(nrd_options* o) {
     o->gmres_maxrestarts = 10;
     o->mg_nu_pre = 1;
     o->mg_nu_post = 1;
+    o->stencil = 1;
 }
 
 nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const nrd_box* boxes,
@@ -1097,6 +1121,16 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
             for (size_t i = 0; i < h->t.tiles.size(); ++i)
                 if (first[h->t.tiles[i].patch] < 0) first[h->t.tiles[i].patch] = (int32_t)i;
             h->patch_tile0 = first;
+        }
+        if (h->opt.stencil >= 1 || h->opt.zchunk > 0) {
+            std::vector<int32_t> kc(h->t.nbox);
+            for (int b = 0; b < h->t.nbox; ++b)
+                kc[b] = h->opt.zchunk > 0 ? h->opt.zchunk : default_zchunk(h->t.patches[b].n);
+            build_planes(h->t, kc, h->opt.stencil == 2 ? 4 * 63 : 256);
+        }
+        if (h->opt.stencil < 0 || h->opt.stencil > 2) {
+            delete h;
+            return fail(NRD_EINVAL, "stencil must be 0, 1 or 2");
         }
         h->dt_prev.assign(h->t.nprob, 0.0);
         layout(h);

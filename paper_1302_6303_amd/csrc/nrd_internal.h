@@ -50,6 +50,15 @@ struct Tile {
     int32_t prob;
 };
 
+// Plane-marching tile: cells [s0, s0 + cnt) of the (x fastest) linear index
+// of one z-plane of a patch, for the planes k0 <= k < k1; one workgroup of
+// 256 threads, thread t owns linear index s0 + t.
+struct STile {
+    int32_t patch, prob;
+    int32_t s0, cnt, k0, k1;
+    int32_t pad[2];
+};
+
 struct GhostCopy { int32_t dst, src; };
 struct GhostCF   { int32_t dst, src[5]; };    // 4 coarse (9,3,3,1)/16, fine
 struct SyncEntry { int32_t dst, src, sy, sz; };  // src: child (0,0,0)
@@ -109,7 +118,10 @@ struct Tables {
     std::vector<std::vector<std::vector<int32_t>>> level_patches; // [prob][lev]
     std::vector<uint8_t> ctype;              // nl bytes
 
-    std::vector<Tile> tiles;                 // stencil tiles, all patches
+    std::vector<Tile> tiles;                 // flat tiles, all patches
+    std::vector<STile> stiles;               // plane-marching tiles, by level
+    std::vector<int32_t> level_stile0;       // [nlev+1]
+    std::vector<int32_t> patch_stile0;       // [nbox+1] bricks of each patch
     std::vector<int32_t> level_tile0;        // [nlev+1] tiles sorted by level
     std::vector<Tile> vtiles;                // reduction tiles
     std::vector<int32_t> prob_vtile0;        // [nprob+1]
@@ -135,6 +147,12 @@ struct Tables {
     int32_t bottom_max = 0;                  // max bottom cells per problem
     std::vector<int32_t> bottom_off;         // per problem, in bottom storage
 };
+
+// Plane-marching tiles: planes per tile (z chunk) of each patch.
+int32_t default_zchunk(const int32_t n[3]);
+// run: cells of a plane per tile (256 for the plane kernel, 4 x 63 for
+// wave runs)
+void build_planes(Tables& t, const std::vector<int32_t>& kc, int32_t run);
 
 // Builds all tables; returns NRD_OK or an error with msg set.
 nrd_status build_tables(const nrd_problem* probs, int32_t nprob,

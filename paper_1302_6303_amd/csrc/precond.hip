@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(
     const ProbScalars* __restrict__ ps, const double* __restrict__ u,
     const double* __restrict__ z3, PT* __restrict__ Dface, PT* __restrict__ sigma,
     int64_t nl) {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     const ProbScalars& q = ps[t.prob];
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarsen(
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pc,
     const PatchInfo* __restrict__ Pf, const int32_t* __restrict__ fbox,
     const PT* __restrict__ Df, int64_t nlf, PT* __restrict__ Dc, int64_t nlc) {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& pc = Pc[t.patch];
     const PatchInfo& pf = Pf[fbox[t.prob]];
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_level(
     const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
     const PT* __restrict__ D, const PT* __restrict__ f, PT* __restrict__ e,
     PT* __restrict__ r, int colour, int64_t nl) {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_comp_res(
     const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
     const PT* __restrict__ D, const PT* __restrict__ f, const PT* __restrict__ u,
     PT* __restrict__ r, int64_t nl) {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_level(
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
     const ShadowPatch* __restrict__ SP, const PT* __restrict__ sh, int64_t nls,
     PT* __restrict__ e, PT* __restrict__ u, int64_t nl) {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     const ShadowPatch sp = SP[t.patch];
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_add_level(const Tile* __restrict__ t
                                                       const PatchInfo* __restrict__ P,
                                                       const PT* __restrict__ e,
                                                       PT* __restrict__ u, int64_t nl) {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pc,
     const PatchInfo* __restrict__ Pf, const int32_t* __restrict__ fbox,
     const PT* __restrict__ rf, int64_t nlf, PT* __restrict__ fc, int64_t nlc) {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& pc = Pc[t.patch];
     const PatchInfo& pf = Pf[fbox[t.prob]];
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pf,
     const PatchInfo* __restrict__ Pc, const int32_t* __restrict__ cbox,
     const PT* __restrict__ ec, int64_t nlc, PT* __restrict__ ef, int64_t nlf) {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& pf = Pf[t.patch];
     const PatchInfo& pc = Pc[cbox[t.prob]];
@@ -416,25 +416,28 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(
 }
 
 // ---------------------------------------------------------------------------
-// dense bottom solve (float64): assemble, Cholesky, explicit inverse
+// dense bottom solve (float64): assemble, explicit inverse (Gauss-Jordan)
 // one workgroup per (problem, field)
 // ---------------------------------------------------------------------------
+
+constexpr int kBottomMax = 128;     // cells of the coarsest grid (LDS: 128 KB)
 
 template <typename PT>
 __global__ __launch_bounds__(kBlock) void k_bottom_setup(
     const int32_t* __restrict__ probs, const int32_t* __restrict__ boxes,
     const PatchInfo* __restrict__ P, const ProbScalars* __restrict__ ps,
     const PT* __restrict__ D, int64_t nl, const int64_t* __restrict__ boff,
-    double* __restrict__ L, double* __restrict__ X) {
+    double* __restrict__ X) {
+    __shared__ double M[kBottomMax * kBottomMax];
+    __shared__ double colk[kBottomMax];
+    __shared__ double rowk[kBottomMax];
     const int pi = blockIdx.x >> 1;
     const int fld = blockIdx.x & 1;
     const int prob = probs[pi];
     const PatchInfo& p = P[boxes[pi]];
     const double beta = ps[prob].beta;
-    const int N = p.ncell;
-    double* A = L + boff[prob] * 2 + (int64_t)fld * N * N;
-    double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * N;
-    for (int i = threadIdx.x; i < N * N; i += blockDim.x) A[i] = 0.0;
+    const int N = p.ncell;                      // <= kBottomMax (checked on the host)
+    for (int i = threadIdx.x; i < N * N; i += blockDim.x) M[i] = 0.0;
     __syncthreads();
     const int st[3] = {1, p.sy, p.sz};
     const int sl[3] = {1, p.n[0], p.n[0] * p.n[1]};
@@ -456,43 +459,47 @@ __global__ __launch_bounds__(kBlock) void k_bottom_setup(
                 }
                 const double a = bh2 * Dv;
                 dg += a;
-                A[(int64_t)lin * N + (s ? lin + sl[d] : lin - sl[d])] = -a;
+                M[lin * N + (s ? lin + sl[d] : lin - sl[d])] = -a;
             }
         }
-        A[(int64_t)lin * N + lin] = dg;
+        M[lin * N + lin] = dg;
     }
     __syncthreads();
-    // Cholesky A = L L^T in place (lower triangle)
-    __shared__ double piv;
+    // In-place Gauss-Jordan inversion in LDS (A is SPD: no pivoting).  Step k
+    // scales row k by 1/a_kk and eliminates column k from the other rows; the
+    // pivot row and column are staged first so every update reads old values.
+    const int j = threadIdx.x & (kBottomMax - 1);
+    const int r0 = threadIdx.x / kBottomMax;
+    const int rstep = blockDim.x / kBottomMax;
     for (int k = 0; k < N; ++k) {
-        if (threadIdx.x == 0) {
-            double s = A[(int64_t)k * N + k];
-            for (int j = 0; j < k; ++j) s -= A[(int64_t)k * N + j] * A[(int64_t)k * N + j];
-            piv = sqrt(s);
-            A[(int64_t)k * N + k] = piv;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            colk[i] = M[i * N + k];
+            rowk[i] = M[k * N + i];
         }
         __syncthreads();
-        for (int i = k + 1 + threadIdx.x; i < N; i += blockDim.x) {
-            double s = A[(int64_t)i * N + k];
-            for (int j = 0; j < k; ++j) s -= A[(int64_t)i * N + j] * A[(int64_t)k * N + j];
-            A[(int64_t)i * N + k] = s / piv;
+        const double ip = 1.0 / colk[k];
+        if (j < N) {
+            const double r = (j == k) ? ip : rowk[j] * ip;
+            // eight independent rows per pass keep LDS loads in flight
+            for (int i0 = r0; i0 < N; i0 += 8 * rstep) {
+                double m[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int i = i0 + q * rstep;
+                    m[q] = (i < N) ? M[i * N + j] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int i = i0 + q * rstep;
+                    if (i < N)
+                        M[i * N + j] = (i == k) ? r : ((j == k) ? 0.0 : m[q]) - colk[i] * r;
+                }
+            }
         }
         __syncthreads();
     }
-    // inverse, one column per thread: L y = e_col, L^T x = y
-    for (int col = threadIdx.x; col < N; col += blockDim.x) {
-        double* x = Xi + (int64_t)col * N;     // column col of A^-1 (symmetric)
-        for (int i = 0; i < N; ++i) {
-            double s = (i == col) ? 1.0 : 0.0;
-            for (int j = 0; j < i; ++j) s -= A[(int64_t)i * N + j] * x[j];
-            x[i] = s / A[(int64_t)i * N + i];
-        }
-        for (int i = N - 1; i >= 0; --i) {
-            double s = x[i];
-            for (int j = i + 1; j < N; ++j) s -= A[(int64_t)j * N + i] * x[j];
-            x[i] = s / A[(int64_t)i * N + i];
-        }
-    }
+    double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * N;
+    for (int i = threadIdx.x; i < N * N; i += blockDim.x) Xi[i] = M[i];
 }
 
 template <typename PT>
@@ -501,19 +508,22 @@ __global__ __launch_bounds__(kBlock) void k_bottom_apply(
     const PatchInfo* __restrict__ P, const int64_t* __restrict__ boff,
     const double* __restrict__ X, const PT* __restrict__ f, PT* __restrict__ e,
     int64_t nl) {
+    __shared__ double fv[kBottomMax];
     const int pi = blockIdx.x >> 1;
     const int fld = blockIdx.x & 1;
     const int prob = probs[pi];
     const PatchInfo& p = P[boxes[pi]];
     const int N = p.ncell;
     const double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * N;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        int id[3];
+        coords(p, j, id[0], id[1], id[2]);
+        fv[j] = (double)f[fld * nl + nat(p, id[0], id[1], id[2])];
+    }
+    __syncthreads();
     for (int row = threadIdx.x; row < N; row += blockDim.x) {
         double s = 0.0;
-        for (int j = 0; j < N; ++j) {
-            int id[3];
-            coords(p, j, id[0], id[1], id[2]);
-            s += Xi[(int64_t)j * N + row] * (double)f[fld * nl + nat(p, id[0], id[1], id[2])];
-        }
+        for (int jj = 0; jj < N; ++jj) s += Xi[(int64_t)jj * N + row] * fv[jj];
         int id[3];
         coords(p, row, id[0], id[1], id[2]);
         e[fld * nl + nat(p, id[0], id[1], id[2])] = (PT)s;
@@ -533,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_p2(const Tile* __restrict__ tiles,
                                                const PT* __restrict__ e,
                                                double* __restrict__ y, int mode,
                                                int transpose, int64_t nl) {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -565,7 +575,7 @@ __global__ __launch_bounds__(kBlock) void k_p2t_in(const Tile* __restrict__ tile
                                                    const double* __restrict__ z3,
                                                    const double* __restrict__ w,
                                                    PT* __restrict__ x, int mode, int64_t nl) {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -587,7 +597,7 @@ __global__ __launch_bounds__(kBlock) void k_in(const Tile* __restrict__ tiles,
                                                const PatchInfo* __restrict__ P,
                                                const double* __restrict__ w,
                                                PT* __restrict__ x, int64_t nl) {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -602,7 +612,7 @@ __global__ __launch_bounds__(kBlock) void k_out(const Tile* __restrict__ tiles,
                                                 const PatchInfo* __restrict__ P,
                                                 const PT* __restrict__ x,
                                                 double* __restrict__ y, int64_t nl) {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -659,8 +669,7 @@ void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
         const int64_t nlg = (g == 0) ? d.nl : mg.len[g];
         const PatchInfo* Pg = (g == 0) ? d.patches : mg.box[g];
         k_bottom_setup<PT><<<2 * mg.nbottom[g], kBlock, 0, s>>>(
-            mg.bottom_probs[g], mg.bottom_boxes[g], Pg, d.ps, Dg, nlg, mg.bottom_off,
-            mg.Lbuf, mg.Xbuf);
+            mg.bottom_probs[g], mg.bottom_boxes[g], Pg, d.ps, Dg, nlg, mg.bottom_off, mg.Xbuf);
     }
 }
 

@@ -24,16 +24,37 @@ namespace nrd {
 //   = 2 T^3 (4R - E) / (4 T^3 + 3 z^3 h).
 // ---------------------------------------------------------------------------
 
+// Reciprocal and reciprocal square root: the hardware estimate (about 23
+// correct bits) refined by two Newton-Raphson steps (quadratic convergence,
+// so the result is within about one ulp); valid for the positive, normal
+// operands met here.
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double r = __builtin_fma(-(x * y), y, 1.0);     // y <- y (3 - x y^2) / 2
+    y = __builtin_fma(0.5 * y, r, y);
+    r = __builtin_fma(-(x * y), y, 1.0);
+    return __builtin_fma(0.5 * y, r, y);
+}
+
 __device__ __forceinline__ void face_flux(double Ea, double Eb, double Ta, double Tb,
                                           double za, double zb, double h, double ih,
                                           double kappa, double lam, double& fe,
                                           double& ft) {
     const double Tf = 0.5 * (Ta + Tb);
-    const double Tf3 = Tf * Tf * Tf;
+    const double Tf2 = Tf * Tf;
+    const double Tf3 = Tf2 * Tf;
     const double S = Ea + Eb;
     const double dE = Eb - Ea;
-    fe = (2.0 * Tf3 * S * dE) / (3.0 * (za + zb) * h * S + 4.0 * lam * Tf3 * fabs(dE));
-    ft = kappa * Tf * Tf * sqrt(Tf) * (Tb - Ta) * ih;
+    fe = (2.0 * Tf3 * S * dE) *
+         rcp_nr(3.0 * (za + zb) * h * S + 4.0 * lam * Tf3 * fabs(dE));
+    ft = kappa * Tf3 * rsqrt_nr(Tf) * (Tb - Ta) * ih;       // kappa Tf^(5/2) dT / h
 }
 
 __device__ __forceinline__ void face_flux_tan(double Ea, double Eb, double Ta, double Tb,
@@ -53,29 +74,49 @@ __device__ __forceinline__ void face_flux_tan(double Ea, double Eb, double Ta, d
     const double sg = (dE > 0.0) ? 1.0 : ((dE < 0.0) ? -1.0 : 0.0);
     const double Zh = 3.0 * (za + zb) * h;
     const double N = 2.0 * Tf3 * S * dE;
-    const double iD = 1.0 / (Zh * S + 4.0 * lam * Tf3 * adE);
+    const double iD = rcp_nr(Zh * S + 4.0 * lam * Tf3 * adE);
     const double phi = N * iD;
     const double dN = 2.0 * (3.0 * Tf2 * dTf * S * dE + Tf3 * (dS * dE + S * ddE));
     const double dDn = Zh * dS + 4.0 * lam * (3.0 * Tf2 * dTf * adE + Tf3 * sg * ddE);
     dfe = (dN - phi * dDn) * iD;
-    const double sq = sqrt(Tf);
+    const double sq = Tf * rsqrt_nr(Tf);
     dft = kappa * Tf * sq * (2.5 * dTf * (Tb - Ta) + Tf * (dTb - dTa)) * ih;
 }
 
 __device__ __forceinline__ double robin_q(double Ec, double Tc, double zc, double R,
                                           double h) {
     const double T3 = Tc * Tc * Tc;
-    return 2.0 * T3 * (4.0 * R - Ec) / (4.0 * T3 + 3.0 * zc * h);
+    return 2.0 * T3 * (4.0 * R - Ec) * rcp_nr(4.0 * T3 + 3.0 * zc * h);
 }
 
 __device__ __forceinline__ double robin_q_tan(double Ec, double Tc, double zc, double R,
                                               double h, double dEc, double dTc) {
     const double T2 = Tc * Tc;
     const double T3 = T2 * Tc;
-    const double iD = 1.0 / (4.0 * T3 + 3.0 * zc * h);
+    const double iD = rcp_nr(4.0 * T3 + 3.0 * zc * h);
     const double q = 2.0 * T3 * (4.0 * R - Ec) * iD;
     const double dN = 6.0 * T2 * dTc * (4.0 * R - Ec) - 2.0 * T3 * dEc;
     return (dN - q * 12.0 * T2 * dTc) * iD;
+}
+
+// Cell terms of the residual (MODE 0) or of its derivative (MODE 1):
+// coupling S = sigma (T^4 - E) = z^3 (T - E / T^3).
+__device__ __forceinline__ void cell_out0(const ProbScalars& q, double E, double T, double z,
+                                          double bE, double bT, double divE, double divT,
+                                          double& oE, double& oT) {
+    const double T3 = T * T * T;
+    const double S = z * (T - E * rcp_nr(T3));
+    oE = q.c0 * E - bE - q.dt * (divE + S);
+    oT = q.c0 * T - bT - q.dt * (divT - S);
+}
+__device__ __forceinline__ void cell_out1(const ProbScalars& q, double E, double T, double z,
+                                          double dE, double dT, double divE, double divT,
+                                          double& oE, double& oT) {
+    const double T3 = T * T * T;
+    const double r3 = rcp_nr(T3);
+    const double dS = z * ((1.0 + 3.0 * E * r3 * rcp_nr(T)) * dT - dE * r3);
+    oE = q.c0 * dE - q.dt * (divE + dS);
+    oT = q.c0 * dT - q.dt * (divT - dS);
 }
 
 __device__ __forceinline__ void cell_coords(const PatchInfo& p, int lin, int& i, int& j,
@@ -181,17 +222,281 @@ void sibling_exchange_d(const Dev& D, hipStream_t s, double* x, int nf, int lev)
 }
 
 // ---------------------------------------------------------------------------
-// residual (MODE 0) and Jacobian action (MODE 1)
+// residual (MODE 0) and Jacobian action (MODE 1), z-marching bricks
+//
+// Each thread owns one (i, j) column of a brick and walks k upward, carrying
+// the centre plane and the flux through the shared z face in registers; the
+// x and y neighbours are read from global memory, where the other columns of
+// the workgroup have just brought them into L1.  A face bordering a covered
+// cell is skipped on the non-covered side (flux matching supplies it).
 // ---------------------------------------------------------------------------
 
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_stencil(
+__device__ __forceinline__ void face_any(const double* __restrict__ u,
+                                         const double* __restrict__ v,
+                                         const double* __restrict__ z3, int a, int b,
+                                         int64_t nl, double h, double ih, double kappa,
+                                         double lam, double& fe, double& ft) {
+    if (MODE == 0)
+        face_flux(u[a], u[b], u[a + nl], u[b + nl], z3[a], z3[b], h, ih, kappa, lam, fe, ft);
+    else
+        face_flux_tan(u[a], u[b], u[a + nl], u[b + nl], z3[a], z3[b], v[a], v[b], v[a + nl],
+                      v[b + nl], h, ih, kappa, lam, fe, ft);
+}
+
+template <int MODE>
+__device__ __forceinline__ double robin_any(double E, double T, double z, double R, double h,
+                                            double dE, double dT) {
+    return MODE == 0 ? robin_q(E, T, z, R, h) : robin_q_tan(E, T, z, R, h, dE, dT);
+}
+
+// Plane-marching variant.  A tile is a run of up to 256 consecutive cells of
+// one z-plane of a patch (x fastest) and a range of planes.  Every face is
+// evaluated once: a thread computes the low x and low y faces of its cell
+// and the high z face; the high x / high y faces come from the neighbouring
+// thread through LDS when that neighbour is in the tile (otherwise they are
+// evaluated directly), and the z face is carried in registers to the next
+// plane.  Physical faces are evaluated by the cell that owns them.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_stencil_z(
+    const STile* __restrict__ tiles, int t0, const PatchInfo* __restrict__ P,
+    const ProbScalars* __restrict__ ps, const int32_t* __restrict__ active,
+    const uint8_t* __restrict__ ctype, const double* __restrict__ u,
+    const double* __restrict__ v, const double* __restrict__ z3,
+    const double* __restrict__ b, double* __restrict__ out, int64_t nl) {
+    __shared__ double fxs[2][2][kBlock];
+    __shared__ double fys[2][2][kBlock];
+    const STile t = tiles[t0 + xcd_tile(blockIdx.x, gridDim.x)];
+    if (active && !active[t.prob]) return;          // uniform over the workgroup
+    const PatchInfo& p = P[t.patch];
+    const ProbScalars& q = ps[t.prob];
+    const double kappa = q.kappa, lam = q.lam;
+    const int tid = threadIdx.x;
+    const bool live = tid < t.cnt;
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const int lin = t.s0 + (live ? tid : 0);
+    const int i = lin % nx, j = lin / nx;
+    const int sy = p.sy, sz = p.sz;
+    const bool use_ct = p.flags & PF_CTYPE;
+    const double hx = p.h[0], hy = p.h[1], hz = p.h[2];
+    const double ihx = p.ih[0], ihy = p.ih[1], ihz = p.ih[2];
+    const bool xlo_p = (p.phys & 1) && i == 0, xhi_p = ((p.phys >> 1) & 1) && i == nx - 1;
+    const bool ylo_p = ((p.phys >> 2) & 1) && j == 0, yhi_p = ((p.phys >> 3) & 1) && j == ny - 1;
+    const bool zlo_p = (p.phys >> 4) & 1, zhi_p = (p.phys >> 5) & 1;
+    const bool x_lds = (i < nx - 1) && (tid + 1 < t.cnt);
+    const bool y_lds = (tid + nx < t.cnt);
+    int c = p.off + (i + 1) + sy * (j + 1) + sz * (t.k0 + 1);
+    double czE = 0.0, czT = 0.0;
+    if (live && !(t.k0 == 0 && zlo_p))
+        face_any<MODE>(u, v, z3, c - sz, c, nl, hz, ihz, kappa, lam, czE, czT);
+    int buf = 0;
+    for (int k = t.k0; k < t.k1; ++k, c += sz, buf ^= 1) {
+        double E = 0.0, T = 1.0, z = 1.0, dE = 0.0, dT = 0.0;
+        double lxE = 0.0, lxT = 0.0, lyE = 0.0, lyT = 0.0, hzE = 0.0, hzT = 0.0;
+        double lzE = 0.0, lzT = 0.0;
+        if (live) {
+            E = u[c];
+            T = u[c + nl];
+            z = z3[c];
+            if (MODE) {
+                dE = v[c];
+                dT = v[c + nl];
+            }
+            if (xlo_p) {
+                if (p.robin & 1) lxE = -robin_any<MODE>(E, T, z, q.R[0], hx, dE, dT);
+            } else {
+                face_any<MODE>(u, v, z3, c - 1, c, nl, hx, ihx, kappa, lam, lxE, lxT);
+            }
+            if (ylo_p) {
+                if ((p.robin >> 2) & 1) lyE = -robin_any<MODE>(E, T, z, q.R[2], hy, dE, dT);
+            } else {
+                face_any<MODE>(u, v, z3, c - sy, c, nl, hy, ihy, kappa, lam, lyE, lyT);
+            }
+            if (k == nz - 1 && zhi_p) {
+                if ((p.robin >> 5) & 1) hzE = robin_any<MODE>(E, T, z, q.R[5], hz, dE, dT);
+            } else {
+                face_any<MODE>(u, v, z3, c, c + sz, nl, hz, ihz, kappa, lam, hzE, hzT);
+            }
+            if (k == 0 && zlo_p) {
+                if ((p.robin >> 4) & 1) lzE = -robin_any<MODE>(E, T, z, q.R[4], hz, dE, dT);
+            } else {
+                lzE = czE;
+                lzT = czT;
+            }
+            czE = hzE;
+            czT = hzT;
+            fxs[buf][0][tid] = lxE;
+            fxs[buf][1][tid] = lxT;
+            fys[buf][0][tid] = lyE;
+            fys[buf][1][tid] = lyT;
+        }
+        __syncthreads();
+        if (!live) continue;
+        double hxE = 0.0, hxT = 0.0, hyE = 0.0, hyT = 0.0;
+        if (xhi_p) {
+            if ((p.robin >> 1) & 1) hxE = robin_any<MODE>(E, T, z, q.R[1], hx, dE, dT);
+        } else if (x_lds) {
+            hxE = fxs[buf][0][tid + 1];
+            hxT = fxs[buf][1][tid + 1];
+        } else {
+            face_any<MODE>(u, v, z3, c, c + 1, nl, hx, ihx, kappa, lam, hxE, hxT);
+        }
+        if (yhi_p) {
+            if ((p.robin >> 3) & 1) hyE = robin_any<MODE>(E, T, z, q.R[3], hy, dE, dT);
+        } else if (y_lds) {
+            hyE = fys[buf][0][tid + nx];
+            hyT = fys[buf][1][tid + nx];
+        } else {
+            face_any<MODE>(u, v, z3, c, c + sy, nl, hy, ihy, kappa, lam, hyE, hyT);
+        }
+        const int ct = use_ct ? ctype[c] : 0;
+        if (ct & CT_COVERED) {
+            out[c] = 0.0;
+            out[c + nl] = 0.0;
+            continue;
+        }
+        if (ct & (1 << 1)) lxE = lxT = 0.0;
+        if (ct & (1 << 2)) hxE = hxT = 0.0;
+        if (ct & (1 << 3)) lyE = lyT = 0.0;
+        if (ct & (1 << 4)) hyE = hyT = 0.0;
+        if (ct & (1 << 5)) lzE = lzT = 0.0;
+        if (ct & (1 << 6)) hzE = hzT = 0.0;
+        const double divE = (hxE - lxE) * ihx + (hyE - lyE) * ihy + (hzE - lzE) * ihz;
+        const double divT = (hxT - lxT) * ihx + (hyT - lyT) * ihy + (hzT - lzT) * ihz;
+        double oE, oT;
+        if (MODE == 0)
+            cell_out0(q, E, T, z, b[c], b[c + nl], divE, divT, oE, oT);
+        else
+            cell_out1(q, E, T, z, dE, dT, divE, divT, oE, oT);
+        out[c] = oE;
+        out[c + nl] = oT;
+    }
+}
+
+// Wave-run variant.  Each wavefront of the workgroup owns a run of 63
+// consecutive cells of the (x fastest) linear index of a z-plane and walks
+// the planes k0 <= k < k1.  Lane l evaluates the low x face of its cell; the
+// high x face of lane l < 63 is lane l+1's low face (cross-lane shuffle, no
+// barrier), lane 63 only helps.  The y faces are evaluated per cell and the
+// z face is carried in registers to the next plane.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_stencil_w(
+    const STile* __restrict__ tiles, int t0, const PatchInfo* __restrict__ P,
+    const ProbScalars* __restrict__ ps, const int32_t* __restrict__ active,
+    const uint8_t* __restrict__ ctype, const double* __restrict__ u,
+    const double* __restrict__ v, const double* __restrict__ z3,
+    const double* __restrict__ b, double* __restrict__ out, int64_t nl) {
+    const STile t = tiles[t0 + xcd_tile(blockIdx.x, gridDim.x)];
+    if (active && !active[t.prob]) return;
+    const PatchInfo& p = P[t.patch];
+    const ProbScalars& q = ps[t.prob];
+    const double kappa = q.kappa, lam = q.lam;
+    const int lane = threadIdx.x & 63;
+    const int pos = (threadIdx.x >> 6) * 63 + lane;        // within the tile's run
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const int lin = t.s0 + pos;
+    const bool exists = pos <= t.cnt && lin < nx * ny;     // helper lanes included
+    const bool owned = lane < 63 && pos < t.cnt;
+    const int i = lin % nx, j = lin / nx;
+    const int sy = p.sy, sz = p.sz;
+    const bool use_ct = p.flags & PF_CTYPE;
+    const double hx = p.h[0], hy = p.h[1], hz = p.h[2];
+    const double ihx = p.ih[0], ihy = p.ih[1], ihz = p.ih[2];
+    const bool xlo_p = (p.phys & 1) && i == 0, xhi_p = ((p.phys >> 1) & 1) && i == nx - 1;
+    const bool ylo_p = ((p.phys >> 2) & 1) && j == 0, yhi_p = ((p.phys >> 3) & 1) && j == ny - 1;
+    const bool zlo_p = (p.phys >> 4) & 1, zhi_p = (p.phys >> 5) & 1;
+    int c = p.off + (i + 1) + sy * (j + 1) + sz * (t.k0 + 1);
+    double czE = 0.0, czT = 0.0;
+    if (owned && !(t.k0 == 0 && zlo_p))
+        face_any<MODE>(u, v, z3, c - sz, c, nl, hz, ihz, kappa, lam, czE, czT);
+    for (int k = t.k0; k < t.k1; ++k, c += sz) {
+        double E = 0.0, T = 1.0, z = 1.0, dE = 0.0, dT = 0.0;
+        double lxE = 0.0, lxT = 0.0;
+        if (exists) {
+            E = u[c];
+            T = u[c + nl];
+            z = z3[c];
+            if (MODE) {
+                dE = v[c];
+                dT = v[c + nl];
+            }
+            if (xlo_p) {
+                if (p.robin & 1) lxE = -robin_any<MODE>(E, T, z, q.R[0], hx, dE, dT);
+            } else {
+                face_any<MODE>(u, v, z3, c - 1, c, nl, hx, ihx, kappa, lam, lxE, lxT);
+            }
+        }
+        // high x face of lane l = low x face of lane l + 1
+        double hxE = __shfl_down(lxE, 1, 64);
+        double hxT = __shfl_down(lxT, 1, 64);
+        if (!owned) continue;
+        if (i == nx - 1) {
+            hxE = hxT = 0.0;
+            if (xhi_p) {
+                if ((p.robin >> 1) & 1) hxE = robin_any<MODE>(E, T, z, q.R[1], hx, dE, dT);
+            } else {
+                face_any<MODE>(u, v, z3, c, c + 1, nl, hx, ihx, kappa, lam, hxE, hxT);
+            }
+        }
+        double lyE = 0.0, lyT = 0.0, hyE = 0.0, hyT = 0.0, hzE = 0.0, hzT = 0.0;
+        double lzE = 0.0, lzT = 0.0;
+        if (ylo_p) {
+            if ((p.robin >> 2) & 1) lyE = -robin_any<MODE>(E, T, z, q.R[2], hy, dE, dT);
+        } else {
+            face_any<MODE>(u, v, z3, c - sy, c, nl, hy, ihy, kappa, lam, lyE, lyT);
+        }
+        if (yhi_p) {
+            if ((p.robin >> 3) & 1) hyE = robin_any<MODE>(E, T, z, q.R[3], hy, dE, dT);
+        } else {
+            face_any<MODE>(u, v, z3, c, c + sy, nl, hy, ihy, kappa, lam, hyE, hyT);
+        }
+        if (k == nz - 1 && zhi_p) {
+            if ((p.robin >> 5) & 1) hzE = robin_any<MODE>(E, T, z, q.R[5], hz, dE, dT);
+        } else {
+            face_any<MODE>(u, v, z3, c, c + sz, nl, hz, ihz, kappa, lam, hzE, hzT);
+        }
+        if (k == 0 && zlo_p) {
+            if ((p.robin >> 4) & 1) lzE = -robin_any<MODE>(E, T, z, q.R[4], hz, dE, dT);
+        } else {
+            lzE = czE;
+            lzT = czT;
+        }
+        czE = hzE;
+        czT = hzT;
+        const int ct = use_ct ? ctype[c] : 0;
+        if (ct & CT_COVERED) {
+            out[c] = 0.0;
+            out[c + nl] = 0.0;
+            continue;
+        }
+        if (ct & (1 << 1)) lxE = lxT = 0.0;
+        if (ct & (1 << 2)) hxE = hxT = 0.0;
+        if (ct & (1 << 3)) lyE = lyT = 0.0;
+        if (ct & (1 << 4)) hyE = hyT = 0.0;
+        if (ct & (1 << 5)) lzE = lzT = 0.0;
+        if (ct & (1 << 6)) hzE = hzT = 0.0;
+        const double divE = (hxE - lxE) * ihx + (hyE - lyE) * ihy + (hzE - lzE) * ihz;
+        const double divT = (hxT - lxT) * ihx + (hyT - lyT) * ihy + (hzT - lzT) * ihz;
+        double oE, oT;
+        if (MODE == 0)
+            cell_out0(q, E, T, z, b[c], b[c + nl], divE, divT, oE, oT);
+        else
+            cell_out1(q, E, T, z, dE, dT, divE, divT, oE, oT);
+        out[c] = oE;
+        out[c + nl] = oT;
+    }
+}
+
+// Flat variant: one thread per cell of a run of 256 interior cells (x
+// fastest); all six faces of the cell are evaluated by that thread.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_stencil_flat(
     const Tile* __restrict__ tiles, int t0, const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const int32_t* __restrict__ active,
     const uint8_t* __restrict__ ctype, const double* __restrict__ u,
     const double* __restrict__ v, const double* __restrict__ z3,
     const double* __restrict__ b, double* __restrict__ out, int64_t nl) {
-    const Tile t = tiles[t0 + blockIdx.x];
+    const Tile t = tiles[t0 + xcd_tile(blockIdx.x, gridDim.x)];
     if (active && !active[t.prob]) return;
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
@@ -249,18 +554,13 @@ __global__ __launch_bounds__(kBlock) void k_stencil(
         divE += (fe_hi - fe_lo) * ih;
         divT += (ft_hi - ft_lo) * ih;
     }
-    const double T2 = T * T;
-    const double T3 = T2 * T;
-    if (MODE == 0) {
-        const double S = z * (T - E / T3);
-        out[c] = q.c0 * E - b[c] - q.dt * (divE + S);
-        out[c + nl] = q.c0 * T - b[c + nl] - q.dt * (divT - S);
-    } else {
-        const double r3 = 1.0 / T3;
-        const double dS = z * ((1.0 + 3.0 * E * r3 / T) * dT - dE * r3);
-        out[c] = q.c0 * dE - q.dt * (divE + dS);
-        out[c + nl] = q.c0 * dT - q.dt * (divT - dS);
-    }
+    double oE, oT;
+    if (MODE == 0)
+        cell_out0(q, E, T, z, b[c], b[c + nl], divE, divT, oE, oT);
+    else
+        cell_out1(q, E, T, z, dE, dT, divE, divT, oE, oT);
+    out[c] = oE;
+    out[c + nl] = oT;
 }
 
 // Flux matching: a coarse face bordering a finer level carries the mean of
@@ -313,8 +613,15 @@ __global__ __launch_bounds__(kBlock) void k_reflux(
 void residual(const Dev& D, hipStream_t s, int t0, int nt, const double* u, const double* b,
               double* F) {
     if (nt <= 0) return;
-    k_stencil<0><<<nt, kBlock, 0, s>>>(D.tiles, t0, D.patches, D.ps, D.active, D.ctype, u,
-                                       nullptr, D.z3, b, F, D.nl);
+    if (D.bricks == 1)
+        k_stencil_z<0><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
+                                             u, nullptr, D.z3, b, F, D.nl);
+    else if (D.bricks == 2)
+        k_stencil_w<0><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
+                                             u, nullptr, D.z3, b, F, D.nl);
+    else
+        k_stencil_flat<0><<<nt, kBlock, 0, s>>>(D.tiles, t0, D.patches, D.ps, D.active,
+                                                D.ctype, u, nullptr, D.z3, b, F, D.nl);
 }
 void residual_reflux(const Dev& D, hipStream_t s, const double* u, double* F) {
     if (D.nrcells == 0) return;
@@ -325,8 +632,15 @@ void residual_reflux(const Dev& D, hipStream_t s, const double* u, double* F) {
 void jvp(const Dev& D, hipStream_t s, int t0, int nt, const double* u, const double* v,
          double* Jv) {
     if (nt <= 0) return;
-    k_stencil<1><<<nt, kBlock, 0, s>>>(D.tiles, t0, D.patches, D.ps, D.active, D.ctype, u, v,
-                                       D.z3, nullptr, Jv, D.nl);
+    if (D.bricks == 1)
+        k_stencil_z<1><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
+                                             u, v, D.z3, nullptr, Jv, D.nl);
+    else if (D.bricks == 2)
+        k_stencil_w<1><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
+                                             u, v, D.z3, nullptr, Jv, D.nl);
+    else
+        k_stencil_flat<1><<<nt, kBlock, 0, s>>>(D.tiles, t0, D.patches, D.ps, D.active,
+                                                D.ctype, u, v, D.z3, nullptr, Jv, D.nl);
 }
 void jvp_reflux(const Dev& D, hipStream_t s, const double* u, const double* v, double* Jv) {
     if (D.nrcells == 0) return;
@@ -348,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp(
     const double* __restrict__ u, const double* __restrict__ lam,
     const double* __restrict__ z3, double* __restrict__ gout,
     double* __restrict__ gz3, int64_t nl) {
-    const Tile t = tiles[t0 + blockIdx.x];
+    const Tile t = tiles[t0 + xcd_tile(blockIdx.x, gridDim.x)];
     if (active && !active[t.prob]) return;
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
@@ -372,7 +686,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp(
                     // F_c gets -dt q / h
                     const double R = q.R[2 * d + s];
                     const double T2 = T * T, T3 = T2 * T;
-                    const double iD = 1.0 / (4.0 * T3 + 3.0 * z * h);
+                    const double iD = rcp_nr(4.0 * T3 + 3.0 * z * h);
                     const double qq = 2.0 * T3 * (4.0 * R - E) * iD;
                     const double w = -dt * lE * ih;
                     gE += w * (-2.0 * T3) * iD;
@@ -396,7 +710,7 @@ __global__ __launch_bounds__(kBlock) void k_vjp(
             const double adE = fabs(dEv);
             const double sg = (dEv > 0.0) ? 1.0 : ((dEv < 0.0) ? -1.0 : 0.0);
             const double Zh = 3.0 * (za + zb) * h;
-            const double iD = 1.0 / (Zh * S + 4.0 * lm * Tf3 * adE);
+            const double iD = rcp_nr(Zh * S + 4.0 * lm * Tf3 * adE);
             const double phi = 2.0 * Tf3 * S * dEv * iD;
             // partials of Phi_E w.r.t. c's own E, T, z^3
             const double sE = s ? -1.0 : 1.0;              // d(dE)/dE_c
@@ -408,17 +722,17 @@ __global__ __launch_bounds__(kBlock) void k_vjp(
             gE += muE * (dN_E - phi * dD_E) * iD;
             gT += muE * (dN_T - phi * dD_T) * iD;
             gZ += muE * (-phi * dD_z) * iD;
-            const double sq = sqrt(Tf);
+            const double sq = Tf * rsqrt_nr(Tf);
             const double DT = kappa * Tf2 * sq;
             const double base = 1.25 * kappa * Tf * sq * (Tb - Ta);
             gT += muT * (base + (s ? -DT : DT)) * ih;
         }
     }
     const double T2 = T * T, T3 = T2 * T;
-    const double r3 = 1.0 / T3;
+    const double r3 = rcp_nr(T3);
     const double x = lT - lE;
     gE += dt * x * (-z * r3);
-    gT += dt * x * z * (1.0 + 3.0 * E * r3 / T);
+    gT += dt * x * z * (1.0 + 3.0 * E * r3 * rcp_nr(T));
     gZ += dt * x * (T - E * r3);
     gout[c] = gE;
     gout[c + nl] = gT;

@@ -48,7 +48,8 @@ class nrd_options(C.Structure):
                 ("newton_maxit", C.c_int32), ("gmres_restart", C.c_int32),
                 ("gmres_maxrestarts", C.c_int32), ("mg_nu_pre", C.c_int32),
                 ("mg_nu_post", C.c_int32), ("adjoint_slots", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("stencil", C.c_int32), ("zchunk", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class nrd_step_stats(C.Structure):

@@ -32,10 +32,10 @@ def workloads():
 WL = workloads()
 
 
-def _setup(name, dt=2e-3):
+def _setup(name, dt=2e-3, **opt):
     w = WL[name]()
     s = system(w)
-    H = make(w)
+    H = make(w, **opt)
     u_n = state(s, w)
     H.begin_step([dt])
     rng = np.random.default_rng(42)
@@ -43,9 +43,10 @@ def _setup(name, dt=2e-3):
     return w, s, H, u_n, u, dt
 
 
+@pytest.mark.parametrize("stencil", [0, 1, 2])
 @pytest.mark.parametrize("name", list(WL))
-def test_residual_parity(name):
-    w, s, H, u_n, u, dt = _setup(name)
+def test_residual_parity(name, stencil):
+    w, s, H, u_n, u, dt = _setup(name, stencil=stencil)
     F = H.native()
     H.residual(native_from_compact(H, u), F)
     got = compact_from_native(H, F)
@@ -60,9 +61,10 @@ def test_residual_parity(name):
     assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-300)
 
 
+@pytest.mark.parametrize("stencil", [0, 1, 2])
 @pytest.mark.parametrize("name", list(WL))
-def test_jvp_parity(name):
-    w, s, H, u_n, u, dt = _setup(name)
+def test_jvp_parity(name, stencil):
+    w, s, H, u_n, u, dt = _setup(name, stencil=stencil)
     rng = np.random.default_rng(7)
     v = rng.standard_normal(u.shape) * u
     Jv = H.native()
@@ -124,3 +126,27 @@ def test_implicit_steps_parity(name):
         n = s.nc
         for sl in (slice(0, n), slice(n, 2 * n)):
             assert rel_err(got[sl], st.u[sl]) < 1e-8
+
+
+@pytest.mark.parametrize("stencil", [0, 1, 2])
+def test_per_patch_launches_match_batched_bitwise(stencil):
+    """One launch per patch and one launch over the whole patch table run the
+    same kernels on the same tiles: outputs are bitwise equal, run twice."""
+    w = WL["amr3"]()
+    s = system(w)
+    u_n = state(s, w)
+    rng = np.random.default_rng(5)
+    u = s.sync(u_n * rng.uniform(0.9, 1.1, u_n.shape))
+    v = rng.standard_normal(u.shape)
+    outs = []
+    for launch in (0, 1, 0):
+        H = make(w, launch=launch, stencil=stencil)
+        H.begin_step([2e-3])
+        F = H.native()
+        H.residual(native_from_compact(H, u), F)
+        Jv = H.native()
+        H.jvp(native_from_compact(H, u), native_from_compact(H, v), Jv)
+        outs.append((compact_from_native(H, F), compact_from_native(H, Jv)))
+    for a, b in outs[1:]:
+        np.testing.assert_array_equal(a, outs[0][0])
+        np.testing.assert_array_equal(b, outs[0][1])
