@@ -108,7 +108,7 @@ typedef struct {
     int32_t mg_nu_pre;      /* base multigrid V(nu_pre, nu_post)             */
     int32_t mg_nu_post;
     int32_t adjoint_slots;  /* device state slots reserved for nrd_adjoint_run:
-                               ceil(nsteps / ckpt_every) + ckpt_every        */
+                               ceil(nsteps / ckpt_every) + ckpt_every + 3    */
     int32_t stencil;        /* residual / Jacobian kernel: 0 one thread per
                                cell in runs of 256 cells (six faces each),
                                1 plane-marching tiles (each face once, LDS),

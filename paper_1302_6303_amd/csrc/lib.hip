@@ -946,10 +946,16 @@ static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, in
     if (t.nlev != 1) return fail(NRD_EUNSUPPORTED, "adjoint needs a single-level hierarchy");
     if (nsteps <= 0 || every <= 0) return fail(NRD_EINVAL, "nsteps and ckpt_every must be > 0");
     const int nck = (nsteps + every - 1) / every;
-    if (nck + every > h->adjoint_slots)
-        return fail(NRD_EINVAL, "workspace reserved too few adjoint slots");
-    double* ck = h->ckpt;                      // checkpoints 0..nck-1
-    double* seg = h->ckpt + (size_t)nck * NL;  // segment states 1..every
+    if (nck + every + 3 > h->adjoint_slots)
+        return fail(NRD_EINVAL, "workspace reserved too few adjoint slots "
+                                "(need ceil(nsteps / ckpt_every) + ckpt_every + 3)");
+    // slots: checkpoints | segment states | rhs | lambda | gradient; the
+    // forward recomputation (implicit steps) never touches them
+    double* ck = h->ckpt;
+    double* seg = ck + (size_t)nck * NL;
+    double* rhs = seg + (size_t)every * NL;
+    double* lam = rhs + NL;
+    double* gacc = lam + NL;
     std::vector<double> dtv(dt, dt + np);
     // forward with checkpoints of u_0, u_every, ...
     for (int n = 0; n < nsteps; ++n) {
@@ -958,7 +964,6 @@ static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, in
         if (rc) return rc;
     }
     // lambda_N rhs: (dJ/dE, 0)
-    double* rhs = h->rb;
     fill_native(s, rhs, NL, 0.0);
     if (dJdE) {
         unpack(h->D, s, h->at<int64_t>(h->o.coff), dJdE, rhs, 1, t.ncells);
@@ -968,9 +973,8 @@ static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, in
         HIPCHK(hipMemcpyAsync(gz, ones.data(), 8 * t.ncells, hipMemcpyHostToDevice, s));
         unpack(h->D, s, h->at<int64_t>(h->o.coff), gz, rhs, 1, t.ncells);
     }
-    double* lam = h->udot;                     // reuse: the adjoint ends the run
-    double* gacc = h->bvec;                    // dJ/dz^3 accumulator (field 0)
-    fill_native(s, gacc, NL, 0.0);
+    fill_native(s, lam, NL, 0.0);
+    fill_native(s, gacc, NL, 0.0);              // dJ/dz^3 accumulator (field 0)
     for (int p = 0; p < np; ++p) {
         h->ps_host[p].dt = dt[p];
         h->ps_host[p].c0 = 1.0;

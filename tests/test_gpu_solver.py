@@ -1,0 +1,199 @@
+"""Solver-level GPU tests through the C ABI: lock-step ensembles, precision
+modes, determinism, failure handling and the discrete adjoint.
+
+Tolerances: implicit-step solutions 1e-8 relative per field (both sides at
+Newton rtol 1e-10); mixed-precision preconditioning changes only the Krylov
+path, so its converged solution must agree with float64 to the Newton
+tolerance; gradients 1e-7 relative to the oracle's adjoint and 1e-5 to
+central finite differences.
+"""
+import numpy as np
+import pytest
+
+from oracle.hierarchy import Hierarchy
+from oracle.solvers import Stepper, System, adjoint_gradient
+from paper_1302_6303_amd import inputs as I
+from tests.gpu_helpers import (compact_state, make, problem_slices, rel_err, to_dev,
+                               to_host)
+from tests.helpers import state, system
+
+pytestmark = pytest.mark.gpu
+
+
+def small_ensemble(state_kind="front"):
+    """Four independent problems of different sizes, materials and steps."""
+    rng = np.random.default_rng(77)
+    problems, boxes, z = [], [], []
+    sizes = [8, 12, 10, 16]
+    for p, n in enumerate(sizes):
+        pr = I.Problem(base_n=(n, n, n))
+        b = I.Box(p, 0, (0, 0, 0), (n, n, n))
+        zf = I.box_field(I.sample_material_boxes(rng, 1 + p % 3,
+                                                 np.where(rng.uniform(size=3) < 0.5, 1.0, 10.0)))
+        problems.append(pr)
+        boxes.append(b)
+        z.append(zf(*I.cell_centres(pr, b)))
+    if state_kind == "front":
+        E, T = I.front_state(problems, boxes, rng)
+    else:
+        E, T = I.uniform_state(boxes)
+    dts = np.array([1e-3, 5e-4, 2e-3, 8e-4])
+    return I.Workload("ens4", problems, boxes, z, E, T, dts, 3)
+
+
+def _fields(H):
+    E, T = H.get_fields()
+    return np.concatenate([to_host(E), to_host(T)])
+
+
+def test_lockstep_ensemble_matches_each_problem():
+    w = small_ensemble()
+    H = make(w, newton_rtol=1e-10, newton_atol=1e-16)
+    steppers = []
+    for p in range(len(w.problems)):
+        s = system(w, pidx=p)
+        steppers.append((s, Stepper(s, state(s, w, pidx=p), rtol=1e-10, atol=1e-16)))
+    sl = problem_slices(w)
+    for step in range(3):
+        dt = w.dt * (1.0 if step < 2 else 1.5)
+        rc, stats = H.implicit_step(list(dt))
+        got = _fields(H)
+        for p, (s, st) in enumerate(steppers):
+            r = st.step(float(dt[p]))
+            assert r.converged and stats[p]["converged"]
+            n = s.nc
+            ref = st.u
+            g = got[sl[p]]
+            assert rel_err(g[:n], ref[:n]) < 1e-8
+            assert rel_err(g[n:], ref[n:]) < 1e-8
+
+
+@pytest.mark.parametrize("name", ["uniform", "amr"])
+def test_mixed_precision_preconditioner_keeps_the_solution(name):
+    w = I.marshak_single(16, state="front") if name == "uniform" else \
+        I.static_amr(base=16, nlevels=3, side=(8, 16), state="front")
+    Hd = make(w, precision=0, newton_rtol=1e-10, newton_atol=1e-16)
+    Hm = make(w, precision=1, newton_rtol=1e-10, newton_atol=1e-16)
+    kd = km = 0
+    for dt in (1e-3, 1e-3, 1e-3):
+        _, sd = Hd.implicit_step([dt])
+        _, sm = Hm.implicit_step([dt])
+        kd += sd[0]["krylov_iters"]
+        km += sm[0]["krylov_iters"]
+    a, b = _fields(Hd), _fields(Hm)
+    n = len(a) // 2
+    assert rel_err(b[:n], a[:n]) < 1e-8
+    assert rel_err(b[n:], a[n:]) < 1e-8
+    print(f"krylov iterations fp64 {kd} mixed {km}")
+
+
+def test_reruns_are_bitwise_identical():
+    w = I.static_amr(base=16, nlevels=3, side=(8, 16), state="front")
+    outs = []
+    for _ in range(2):
+        H = make(w, precision=1)
+        for dt in (1e-3, 1e-3):
+            H.implicit_step([dt])
+        outs.append(_fields(H))
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
+def test_nonpositive_fields_are_rejected_and_state_kept():
+    from paper_1302_6303_amd import nrd
+    w = I.marshak_single(8, state="front")
+    H = make(w)
+    before = _fields(H)
+    u = compact_state(w)
+    n = H.ncells
+    bad = u.copy()
+    bad[3] = -1.0
+    with pytest.raises(nrd.NrdError) as e:
+        H.set_fields(to_dev(bad[:n]), to_dev(bad[n:]), to_dev(w.compact(w.z)))
+    assert e.value.status == nrd.NRD_ENONPOS
+    nanz = w.compact(w.z).copy()
+    nanz[0] = np.nan
+    with pytest.raises(nrd.NrdError):
+        H.set_fields(to_dev(u[:n]), to_dev(u[n:]), to_dev(nanz))
+    np.testing.assert_array_equal(_fields(H), before)
+
+
+def test_newton_failure_rolls_back():
+    from paper_1302_6303_amd import nrd
+    w = I.marshak_single(8, state="front")
+    H = make(w, newton_maxit=1, newton_rtol=1e-14, newton_atol=0.0)
+    before = _fields(H)
+    rc, stats = H.implicit_step([1e-3], raise_on_fail=False)
+    assert rc == nrd.NRD_ENOTCONV and not stats[0]["converged"]
+    np.testing.assert_array_equal(_fields(H), before)
+
+
+def test_calls_in_wrong_order_report_state_error():
+    from paper_1302_6303_amd import nrd
+    w = I.marshak_single(8, state="front")
+    H = make(w)
+    F = H.native()
+    with pytest.raises(nrd.NrdError) as e:
+        H.residual(H.native(), F)             # no begin_step yet
+    assert e.value.status == nrd.NRD_ESTATE
+
+
+def _smooth_z(n, seed):
+    rng = np.random.default_rng(seed)
+    return 1.0 + 9.0 * np.clip(0.5 + 0.35 * rng.standard_normal((n, n, n)), 0.0, 1.0)
+
+
+def test_adjoint_matches_oracle_adjoint():
+    n, N, every, dt = 8, 4, 2, 2e-3
+    z = _smooth_z(n, 91)
+    w = I.marshak_single(n)
+    w.z = [z]
+    H = make(w, newton_rtol=1e-11, newton_atol=1e-22, newton_maxit=24,
+             adjoint_slots=N // every + every + 3, gmres_maxrestarts=20)
+    gz = to_host(H.adjoint_run([dt], N, every))
+    s = System(Hierarchy((n, n, n), [(0, (0, 0, 0), (n, n, n))]), [z])
+    u0 = np.concatenate([w.compact(w.E), w.compact(w.T)])
+    ref, _ = adjoint_gradient(s, u0, dt, N, tol=1e-13,
+                              newton_kw=dict(rtol=1e-11, atol=1e-22, maxit=40))
+    assert rel_err(gz, ref) < 1e-7
+
+
+def test_adjoint_gradient_matches_central_differences():
+    """dJ/dz of J = sum of E after N BDF1 steps, against central
+    differences of the same GPU forward solve (h = 1e-5 z) on the cells with
+    the largest sensitivity."""
+    from paper_1302_6303_amd import nrd
+    n, N, every, dt = 16, 6, 3, 1e-3
+    z = _smooth_z(n, 92)
+    w = I.marshak_single(n)
+    w.z = [z]
+    opts = dict(newton_rtol=1e-11, newton_atol=1e-22, newton_maxit=24,
+                gmres_maxrestarts=30, adjoint_slots=N // every + every + 3)
+    H = make(w, **opts)
+    g = to_host(H.adjoint_run([dt], N, every))
+    # forward with BDF1 only: use one step per set_fields reset and a
+    # hierarchy that never keeps history
+    zc = w.compact(w.z)
+    order = np.argsort(-np.abs(g))[:6]
+    Hf = make(w, **opts)
+
+    def J(zz):
+        u = compact_state(w)
+        nn = Hf.ncells
+        Hf.set_fields(to_dev(u[:nn]), to_dev(u[nn:]), to_dev(zz))
+        for _ in range(N):
+            rc, st = Hf.implicit_step([dt])
+            # reset history so that every step is BDF1 like the adjoint's
+            E, T = Hf.get_fields()
+            Hf.set_fields(E, T, to_dev(zz))
+        E, _ = Hf.get_fields()
+        e = to_host(E)
+        return np.sum(np.sort(e))
+
+    for c in order:
+        hz = 1e-5 * zc[c]
+        zp = zc.copy()
+        zm = zc.copy()
+        zp[c] += hz
+        zm[c] -= hz
+        fd = (J(zp) - J(zm)) / (2 * hz)
+        assert abs(fd - g[c]) <= 1e-5 * abs(g[c]), (c, fd, g[c])
