@@ -95,7 +95,9 @@ typedef struct {
     int32_t launch;         /* NRD_BATCHED: one launch per operator over the
                                whole patch table; NRD_PER_PATCH: one launch
                                per patch (same kernels, same results)       */
-    int32_t use_graph;      /* capture the preconditioner as a HIP graph     */
+    int32_t use_graph;      /* 1: capture each FGMRES iteration (precond,
+                               Jacobian action, CGS2, Givens) as a HIP graph
+                               on first use and replay it                    */
     int32_t jvp_mode;       /* analytic Jacobian action or finite difference  */
     double limiter;         /* lambda in D_h / (1 + lambda D_h |dE|/(h E_f));
                                1 = Wilson form, 0.5 = the printed pair       */
@@ -112,9 +114,13 @@ typedef struct {
     int32_t stencil;        /* residual / Jacobian kernel: 0 one thread per
                                cell in runs of 256 cells (six faces each),
                                1 plane-marching tiles (each face once, LDS),
-                               2 wave runs (x faces shared across lanes)     */
+                               2 wave runs (x faces shared across lanes),
+                               3 staged planes (each plane slice read once
+                               into LDS, 512-cell tiles)     */
     int32_t zchunk;         /* planes per tile of variants 1, 2 (0: default)  */
-    int32_t reserved[5];
+    int32_t bdf_max_order;  /* 2 (default): BDF2 after the first step; 1: BDF1
+                               throughout (the adjoint assumes BDF1)         */
+    int32_t reserved[4];
 } nrd_options;
 
 /* Fills *opt with the defaults: FP64, batched, no graph, analytic JVP,

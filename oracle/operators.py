@@ -420,6 +420,53 @@ def jvp(H, E, T, z, vE, vT, dt, c0, lam=1.0):
 
 
 # ---------------------------------------------------------------------------
+# Jacobian-free (finite-difference) action, Sec. 4.1 (eq. Jac-free)
+# ---------------------------------------------------------------------------
+
+SQRT_EPS_MACH = float(np.sqrt(np.finfo(np.float64).eps))
+U_MIN = 1e-6
+
+
+def fd_epsilon(H, E, T, vE, vT):
+    """Differencing parameter of Sec. 4.1: sqrt(eps_mach) <u,v> / ||v||^2
+    when |<u,v>| > u_min ||v||_1, otherwise
+    sqrt(eps_mach) u_min sign(<u,v>) ||v||_1 / ||v||^2, u_min = 1e-6.
+
+    Readings: the sums are plain (no volume weights) over the composite
+    cells of both fields; the undefined factor b is 1; the threshold is
+    tested on |<u,v>|; sign(0) = +1.  v = 0 gives 1 (the difference is then
+    exactly 0 whatever epsilon is)."""
+    uv = l1 = v2 = 0.0
+    for p in H.patches:
+        q = p.pid
+        keep = ~H.covered[q]
+        for a, b in ((E[q], vE[q]), (T[q], vT[q])):
+            a = a[keep]
+            b = b[keep]
+            uv += float(np.sum(a * b))
+            l1 += float(np.sum(np.abs(b)))
+            v2 += float(np.sum(b * b))
+    if v2 == 0.0:
+        return 1.0
+    if abs(uv) > U_MIN * l1:
+        return SQRT_EPS_MACH * uv / v2
+    sign = 1.0 if uv >= 0.0 else -1.0
+    return SQRT_EPS_MACH * U_MIN * sign * l1 / v2
+
+
+def jvp_fd(H, E, T, z, vE, vT, bE, bT, dt, c0, lam=1.0):
+    """(F(u + eps v) - F(u)) / eps with eps from fd_epsilon; covered
+    entries -> 0 (F is 0 there on both sides)."""
+    eps = fd_epsilon(H, E, T, vE, vT)
+    F0E, F0T = residual(H, E, T, z, bE, bT, dt, c0, lam)
+    E1 = [a + eps * b for a, b in zip(E, vE)]
+    T1 = [a + eps * b for a, b in zip(T, vT)]
+    F1E, F1T = residual(H, E1, T1, z, bE, bT, dt, c0, lam)
+    return ([(f1 - f0) / eps for f1, f0 in zip(F1E, F0E)],
+            [(f1 - f0) / eps for f1, f0 in zip(F1T, F0T)])
+
+
+# ---------------------------------------------------------------------------
 # transpose (gather over faces); single-level hierarchies
 # ---------------------------------------------------------------------------
 

@@ -34,8 +34,10 @@ class System:
     """One problem: hierarchy, material field, options; compact vectors are
     [E of all patches (x fastest) | T of all patches]."""
 
-    def __init__(self, H, z, lam=1.0, p2_mode="paper"):
+    def __init__(self, H, z, lam=1.0, p2_mode="paper", jvp_mode="analytic"):
         self.H = H
+        self.jvp_mode = jvp_mode
+        self._b = None
         self.z = [np.asarray(a, dtype=np.float64) for a in z]
         self.lam = lam
         self.p2_mode = p2_mode
@@ -82,6 +84,7 @@ class System:
 
     # -- operators --------------------------------------------------------
     def residual(self, u, b, dt, c0):
+        self._b = b
         E, T = self.split(u)
         bE, bT = self.split(b)
         FE, FT = ops.residual(self.H, E, T, self.z, bE, bT, dt, c0, self.lam)
@@ -90,7 +93,13 @@ class System:
     def jvp(self, u, v, dt, c0):
         E, T = self.split(u)
         vE, vT = self.split(v)
-        JE, JT = ops.jvp(self.H, E, T, self.z, vE, vT, dt, c0, self.lam)
+        if self.jvp_mode == "fd":
+            # the difference quotient needs the step's b: the one of the
+            # latest residual evaluation (Newton evaluates F(u^k) first)
+            bE, bT = self.split(self._b)
+            JE, JT = ops.jvp_fd(self.H, E, T, self.z, vE, vT, bE, bT, dt, c0, self.lam)
+        else:
+            JE, JT = ops.jvp(self.H, E, T, self.z, vE, vT, dt, c0, self.lam)
         return self.join(JE, JT)
 
     def vjp(self, u, lmb, dt, c0):

@@ -73,7 +73,14 @@ int32_t default_zchunk(const int32_t n[3]) {
     return n[0] * n[1] >= 4096 ? 4 : 8;
 }
 
-void build_planes(Tables& t, const std::vector<int32_t>& kc, int32_t run) {
+int32_t staged_len(const PatchInfo& p, int32_t s0, int32_t cnt) {
+    const int32_t nx = p.n[0], sy = p.sy;
+    const int32_t la = s0, lb = s0 + cnt - 1;
+    const int32_t g0 = (la % nx + 1) + sy * (la / nx);
+    return (lb % nx + 1) + sy * (lb / nx + 2) - g0 + 1;
+}
+
+bool build_planes(Tables& t, const std::vector<int32_t>& kc, int32_t run, int32_t max_span) {
     t.stiles.clear();
     t.level_stile0.assign(t.nlev + 1, 0);
     t.patch_stile0.assign(t.nbox + 1, 0);
@@ -82,9 +89,20 @@ void build_planes(Tables& t, const std::vector<int32_t>& kc, int32_t run) {
         const PatchInfo& p = t.patches[b];
         const int32_t plane = p.n[0] * p.n[1];
         const int32_t ch = std::max(1, kc[b]);
+        int32_t r = run;
+        if (max_span > 0) {
+            // shorten the runs of this patch until every staged slice fits
+            for (;; r -= 64) {
+                if (r <= 0) return false;
+                bool fits = true;
+                for (int32_t s0 = 0; s0 < plane && fits; s0 += r)
+                    fits = staged_len(p, s0, std::min(r, plane - s0)) <= max_span;
+                if (fits) break;
+            }
+        }
         for (int32_t k0 = 0; k0 < p.n[2]; k0 += ch)
-            for (int32_t s0 = 0; s0 < plane; s0 += run)
-                per[b].push_back({b, p.prob, s0, std::min(run, plane - s0), k0,
+            for (int32_t s0 = 0; s0 < plane; s0 += r)
+                per[b].push_back({b, p.prob, s0, std::min(r, plane - s0), k0,
                                   std::min(p.n[2], k0 + ch), {0, 0}});
     }
     for (int l = 0; l < t.nlev; ++l) {
@@ -97,6 +115,7 @@ void build_planes(Tables& t, const std::vector<int32_t>& kc, int32_t run) {
     }
     t.level_stile0[t.nlev] = (int32_t)t.stiles.size();
     t.patch_stile0[t.nbox] = (int32_t)t.stiles.size();
+    return true;
 }
 
 nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
@@ -597,14 +616,22 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
     int64_t boff = 0;
     t.bottom_max = 0;
     for (int p = 0; p < nprob; ++p) {
-        int32_t nb = 1;
-        for (int d = 0; d < 3; ++d) nb *= probs[p].base_n[d] >> t.prob_mgdepth[p];
+        int32_t nb = 1, nmax = 1;
+        for (int d = 0; d < 3; ++d) {
+            const int32_t e = probs[p].base_n[d] >> t.prob_mgdepth[p];
+            nb *= e;
+            nmax = std::max(nmax, e);
+        }
         t.bottom_off[p] = (int32_t)boff;
-        boff += (int64_t)nb * nb;
+        boff += (int64_t)nb * kBottomBand;
         t.bottom_max = std::max(t.bottom_max, nb);
+        if (nb / nmax + 1 > kBottomBand) {
+            msg = "coarsest multigrid grid too wide for the banded bottom solve";
+            return NRD_EUNSUPPORTED;
+        }
     }
     if (t.bottom_max > 128) {
-        msg = "coarsest multigrid grid too large for the dense bottom solve (> 128 cells); "
+        msg = "coarsest multigrid grid too large for the bottom solve (> 128 cells); "
               "base grid extents must halve down to at most 128 cells";
         return NRD_EUNSUPPORTED;
     }

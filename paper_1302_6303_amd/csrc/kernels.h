@@ -111,6 +111,15 @@ void cube(hipStream_t s, const double* z, double* z3, int64_t n);
 void to_float(hipStream_t s, const double* x, float* y, int64_t n);
 void to_double(hipStream_t s, const float* x, double* y, int64_t n);
 
+// Jacobian-free product pieces (all problems): sums[3 p..] = plain sums over
+// composite cells of u.v, |v|, v.v; w = u + eps_p v; Jv = (Jv - F0) / eps_p.
+void fd_sums(const Dev& D, hipStream_t s, const double* u, const double* v,
+             double* partial, double* sums);
+void fd_shift(const Dev& D, hipStream_t s, const double* sums, const double* u,
+              const double* v, double* w);
+void fd_quotient(const Dev& D, hipStream_t s, const double* sums, const double* F0,
+                 double* Jv);
+
 // Givens / Hessenberg update of FGMRES for every active problem.
 //   hcol [nprob][m+1] holds the new column (CGS sums), hn2 [nprob] = ||w||^2
 void gmres_column(hipStream_t s, int nprob, int m, int j, const int32_t* active,

@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -75,7 +77,7 @@ struct nrd_hierarchy {
         size_t pc_D, pc_sigma, pc_e, pc_u, pc_r, pc_f, pc_tmp, pc_shadow;
         size_t mg_D[kMaxMG], mg_e[kMaxMG], mg_f[kMaxMG], mg_r[kMaxMG];
         size_t partial, dots, h1, h2, hn2, H, cs, sn, g, rho, vscale, y, kdim, coefA, coefB,
-            minout, flag, ckpt;
+            minout, flag, ckpt, fdF, fdw, fdsum;
     } o;
     int32_t adjoint_slots = 0;
     // host-side per-problem state
@@ -86,7 +88,8 @@ struct nrd_hierarchy {
     // device pointers
     double *z, *z3, *cur, *prev, *udot, *bvec, *x, *F, *s, *w, *tmp, *tmp2, *rb, *gz3, *V, *Z;
     double *partial, *dots, *h1, *h2, *hn2, *H, *cs, *sn, *g, *rho, *vscale, *y, *coefA, *coefB,
-        *minout, *ckpt;
+        *minout, *ckpt, *fdF, *fdw, *fdsum;
+    const double* fd_base = nullptr;   // F at the Newton iterate (Jacobian-free mode)
     int32_t *kdim, *flag, *active;
     ProbScalars* ps;
     // timers
@@ -95,6 +98,19 @@ struct nrd_hierarchy {
     size_t ev_used = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pairs;
     std::vector<int32_t> host_active;
+    // one FGMRES iteration per direction (0: J, 1: J^T), linearisation
+    // point (the iterate's buffer rotates with the time-step history) and
+    // Krylov index, captured on first use when use_graph is set
+    std::map<std::tuple<int, const void*, int>, hipGraphExec_t> graphs;
+    hipStream_t cap_stream = nullptr;  // graphs are captured and launched here
+                                       // (the caller's stream may be the legacy
+                                       // null stream), ordered with the
+                                       // caller's stream by two events
+    hipEvent_t gev_in = nullptr, gev_out = nullptr;
+    void drop_graphs() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
 
     int64_t nl2() const { return 2 * t.nl; }
     // stencil launch ranges for the selected variant
@@ -179,7 +195,7 @@ static void layout(nrd_hierarchy* h) {
     for (int p = 0; p < nprob; ++p) {
         int64_t nb = 1;
         for (int d = 0; d < 3; ++d) nb *= t.probs[p].base_n[d] >> t.prob_mgdepth[p];
-        bsum += nb * nb;
+        bsum += nb * kBottomBand;
     }
     o.Lbuf = b.take(8);
     o.Xbuf = b.take(sizeof(double) * 2 * bsum);
@@ -236,6 +252,10 @@ static void layout(nrd_hierarchy* h) {
     o.minout = b.take(8 * nprob);
     o.flag = b.take(4 * 4);
     o.ckpt = b.take(8 * 2 * nl * (size_t)std::max(0, h->adjoint_slots));
+    const bool fd = h->opt.jvp_mode == NRD_JVP_FD;
+    o.fdF = b.take(fd ? 8 * 2 * nl : 8);
+    o.fdw = b.take(fd ? 8 * 2 * nl : 8);
+    o.fdsum = b.take(8 * 3 * nprob);
     h->ws_bytes = b.off;
 }
 
@@ -416,6 +436,9 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     h->minout = h->at<double>(o.minout);
     h->flag = h->at<int32_t>(o.flag);
     h->ckpt = h->at<double>(o.ckpt);
+    h->fdF = h->at<double>(o.fdF);
+    h->fdw = h->at<double>(o.fdw);
+    h->fdsum = h->at<double>(o.fdsum);
     if (h->mixed) {
         wire_pc(h, h->pcf);
         for (int g = 0; g <= G; ++g) {
@@ -476,7 +499,51 @@ static void op_residual(nrd_hierarchy* h, double* u, double* F, bool prepared = 
     h->toc(NRD_TIMER_RESIDUAL, tk);
 }
 
+// Jacobian-free product (Sec. 4.1): Jv = (F(u + eps v) - F(u)) / eps with the
+// per-problem step of the Sec. 4.1 formula.  F0 = F(u) if the caller has it
+// (the Newton residual at the iterate), else it is evaluated here.
+static void op_jvp_fd(nrd_hierarchy* h, double* u, double* v, double* Jv, bool u_prepared,
+                      const double* F0) {
+    if (!u_prepared) prepare_state(h, u);
+    restrict_d(h->D, h->stream, v, 2, 0);
+    auto tk = h->tic(NRD_TIMER_JVP);
+    const Dev& D = h->D;
+    hipStream_t s = h->stream;
+    if (!F0) {
+        if (h->opt.launch == NRD_PER_PATCH) {
+            for (int b = 0; b < h->t.nbox; ++b) {
+                int a0, n0;
+                h->tile_range(b, a0, n0);
+                residual(D, s, a0, n0, u, h->bvec, h->fdF);
+            }
+        } else {
+            residual(D, s, 0, h->ntiles_stencil(), u, h->bvec, h->fdF);
+        }
+        residual_reflux(D, s, u, h->fdF);
+        F0 = h->fdF;
+    }
+    fd_sums(D, s, u, v, h->partial, h->fdsum);
+    fd_shift(D, s, h->fdsum, u, v, h->fdw);
+    prepare_state(h, h->fdw);
+    if (h->opt.launch == NRD_PER_PATCH) {
+        for (int b = 0; b < h->t.nbox; ++b) {
+            int a0, n0;
+            h->tile_range(b, a0, n0);
+            residual(D, s, a0, n0, h->fdw, h->bvec, Jv);
+        }
+    } else {
+        residual(D, s, 0, h->ntiles_stencil(), h->fdw, h->bvec, Jv);
+    }
+    residual_reflux(D, s, h->fdw, Jv);
+    fd_quotient(D, s, h->fdsum, F0, Jv);
+    h->toc(NRD_TIMER_JVP, tk);
+}
+
 static void op_jvp(nrd_hierarchy* h, double* u, double* v, double* Jv, bool u_prepared) {
+    if (h->opt.jvp_mode == NRD_JVP_FD) {
+        op_jvp_fd(h, u, v, Jv, u_prepared, h->fd_base);
+        return;
+    }
     if (!u_prepared) prepare_state(h, u);
     prepare_state(h, v);
     auto tk = h->tic(NRD_TIMER_JVP);
@@ -664,26 +731,67 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
         std::vector<int32_t> live = todo;
         for (int p = 0; p < np; ++p) kd[p] = 0;
         for (int j = 0; j < m; ++j) {
-            double* Vj = h->V + j * NL;
-            double* Zj = h->Z + j * NL;
-            double* wv = h->w;
-            if (!transpose) {
-                pc_apply(h, Vj, Zj);
-                op_jvp(h, u, Zj, wv, true);
+            // one iteration: z_j = P^-1 v_j, w = J z_j, CGS2 against v_0..v_j,
+            // Hessenberg column + Givens, v_{j+1} = w / ||w||.  Everything it
+            // reads that changes between calls (active mask, scalars, the
+            // preconditioner snapshot) is device-resident, so it can be
+            // captured once per j and replayed.
+            auto iteration = [&]() {
+                double* Vj = h->V + j * NL;
+                double* Zj = h->Z + j * NL;
+                double* wv = h->w;
+                if (!transpose) {
+                    pc_apply(h, Vj, Zj);
+                    op_jvp(h, u, Zj, wv, true);
+                } else {
+                    pc_apply_t(h, Vj, Zj);
+                    ghost_fill_d(h->D, s, Zj, 2);
+                    vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], u, Zj, wv, h->gz3);
+                }
+                multidot(h->D, s, h->V, NL, j + 1, wv, h->partial, h->h1);
+                combine(h->D, s, h->V, NL, j + 1, h->h1, j + 1, wv, 1, -1.0);
+                multidot(h->D, s, h->V, NL, j + 1, wv, h->partial, h->h2);
+                combine(h->D, s, h->V, NL, j + 1, h->h2, j + 1, wv, 1, -1.0);
+                multidot(h->D, s, wv, 0, 1, wv, h->partial, h->hn2);
+                gmres_column(s, np, m, j, h->active, h->h1, h->h2, h->hn2, h->H, h->cs, h->sn,
+                             h->g, h->rho, h->vscale);
+                scale_copy(h->D, s, wv, h->vscale, h->V + (j + 1) * NL);
+            };
+            if (h->opt.use_graph) {
+                hipGraphExec_t& ge = h->graphs[std::make_tuple(transpose ? 1 : 0,
+                                                               (const void*)u, j)];
+                if (!h->cap_stream) {
+                    HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+                    HIPCHK(hipEventCreateWithFlags(&h->gev_in, hipEventDisableTiming));
+                    HIPCHK(hipEventCreateWithFlags(&h->gev_out, hipEventDisableTiming));
+                }
+                if (!ge) {
+                    const bool timing = h->timing;
+                    h->timing = false;             // no event records inside a graph
+                    hipStream_t user = s;
+                    hipGraph_t graph = nullptr;
+                    hipError_t ec = hipStreamBeginCapture(h->cap_stream,
+                                                          hipStreamCaptureModeThreadLocal);
+                    if (ec == hipSuccess) {
+                        s = h->stream = h->cap_stream;
+                        iteration();
+                        ec = hipStreamEndCapture(s, &graph);
+                        s = h->stream = user;
+                    }
+                    h->timing = timing;
+                    HIPCHK(ec);
+                    const hipError_t ei = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(graph);
+                    HIPCHK(ei);
+                }
+                HIPCHK(hipEventRecord(h->gev_in, s));
+                HIPCHK(hipStreamWaitEvent(h->cap_stream, h->gev_in, 0));
+                HIPCHK(hipGraphLaunch(ge, h->cap_stream));
+                HIPCHK(hipEventRecord(h->gev_out, h->cap_stream));
+                HIPCHK(hipStreamWaitEvent(s, h->gev_out, 0));
             } else {
-                pc_apply_t(h, Vj, Zj);
-                ghost_fill_d(h->D, s, Zj, 2);
-                vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], u, Zj, wv, h->gz3);
+                iteration();
             }
-            // CGS2
-            multidot(h->D, s, h->V, NL, j + 1, wv, h->partial, h->h1);
-            combine(h->D, s, h->V, NL, j + 1, h->h1, j + 1, wv, 1, -1.0);
-            multidot(h->D, s, h->V, NL, j + 1, wv, h->partial, h->h2);
-            combine(h->D, s, h->V, NL, j + 1, h->h2, j + 1, wv, 1, -1.0);
-            multidot(h->D, s, wv, 0, 1, wv, h->partial, h->hn2);
-            gmres_column(s, np, m, j, h->active, h->h1, h->h2, h->hn2, h->H, h->cs, h->sn, h->g,
-                         h->rho, h->vscale);
-            scale_copy(h->D, s, wv, h->vscale, h->V + (j + 1) * NL);
             std::vector<double> hn(np);
             HIPCHK(hipMemcpyAsync(rho.data(), h->rho, 8 * np, hipMemcpyDeviceToHost, s));
             HIPCHK(hipMemcpyAsync(hn.data(), h->hn2, 8 * np, hipMemcpyDeviceToHost, s));
@@ -787,7 +895,9 @@ static nrd_status newton(nrd_hierarchy* h, std::vector<nrd_step_stats>& st) {
         h->D.active = h->active;
         scale_copy(h->D, s, h->F, h->coefA, h->rb);
         std::vector<int32_t> its;
+        h->fd_base = h->F;                    // F(x) for Jacobian-free products
         rc = fgmres(h, h->x, h->rb, h->s, tol, its, false);
+        h->fd_base = nullptr;
         if (rc) return rc;
         std::vector<int32_t> act = h->host_active;
         for (int p = 0; p < np; ++p)
@@ -1001,7 +1111,12 @@ static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, in
         }
         HIPCHK(up(s, h->ps, h->ps_host));
         for (int n = n1; n > n0; --n) {
-            double* un = seg + (size_t)(n - n0 - 1) * NL;
+            // the linearisation point goes to the Newton iterate's buffer,
+            // which the recomputation no longer needs (and which captured
+            // Krylov iterations read)
+            h->D.active = nullptr;
+            copy_interior(h->D, s, seg + (size_t)(n - n0 - 1) * NL, h->x);
+            double* un = h->x;
             prepare_state(h, un);
             pc_setup(h, un, true);
             // A_n^T lam = rhs
@@ -1080,6 +1195,7 @@ void nrd_default_options(nrd_options* o) {
     o->mg_nu_pre = 1;
     o->mg_nu_post = 1;
     o->stencil = 1;
+    o->bdf_max_order = 2;
 }
 
 nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const nrd_box* boxes,
@@ -1100,9 +1216,13 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
             delete h;
             return fail(NRD_EINVAL, "newton_maxit must be in [1, 24]");
         }
-        if (h->opt.jvp_mode == NRD_JVP_FD) {
+        if (h->opt.bdf_max_order < 1 || h->opt.bdf_max_order > 2) {
             delete h;
-            return fail(NRD_EUNSUPPORTED, "finite-difference Jacobian action is not built");
+            return fail(NRD_EINVAL, "bdf_max_order must be 1 or 2");
+        }
+        if (h->opt.jvp_mode != NRD_JVP_ANALYTIC && h->opt.jvp_mode != NRD_JVP_FD) {
+            delete h;
+            return fail(NRD_EINVAL, "jvp_mode must be ANALYTIC or FD");
         }
         h->m = h->opt.gmres_restart;
         h->mixed = h->opt.precision == NRD_MIXED;
@@ -1130,11 +1250,17 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
             std::vector<int32_t> kc(h->t.nbox);
             for (int b = 0; b < h->t.nbox; ++b)
                 kc[b] = h->opt.zchunk > 0 ? h->opt.zchunk : default_zchunk(h->t.patches[b].n);
-            build_planes(h->t, kc, h->opt.stencil == 2 ? 4 * 63 : 256);
+            const int st = h->opt.stencil;
+            const bool ok = build_planes(h->t, kc, st == 2 ? 4 * 63 : (st == 3 ? kStageCells : 256),
+                                         st == 3 ? kStageLen : 0);
+            if (!ok) {
+                delete h;
+                return fail(NRD_EUNSUPPORTED, "a patch plane is too wide for the staged stencil");
+            }
         }
-        if (h->opt.stencil < 0 || h->opt.stencil > 2) {
+        if (h->opt.stencil < 0 || h->opt.stencil > 3) {
             delete h;
-            return fail(NRD_EINVAL, "stencil must be 0, 1 or 2");
+            return fail(NRD_EINVAL, "stencil must be 0, 1, 2 or 3");
         }
         h->dt_prev.assign(h->t.nprob, 0.0);
         layout(h);
@@ -1147,6 +1273,10 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
 
 nrd_status nrd_hierarchy_destroy(nrd_hierarchy* h) {
     if (!h) return NRD_OK;
+    h->drop_graphs();
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->gev_in) (void)hipEventDestroy(h->gev_in);
+    if (h->gev_out) (void)hipEventDestroy(h->gev_out);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     delete h;
     return NRD_OK;
@@ -1304,7 +1434,7 @@ nrd_status nrd_vjp(nrd_hierarchy* h, double* u, double* lam, double* JTl, double
 nrd_status nrd_implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_stats* stats) {
     NEED_BOUND(h);
     if (!dt) return fail(NRD_EINVAL, "NULL dt");
-    nrd_status rc = implicit_step(h, dt, stats);
+    nrd_status rc = implicit_step(h, dt, stats, h->opt.bdf_max_order == 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(NRD_EDEVICE, hipGetErrorString(e));
     return rc;

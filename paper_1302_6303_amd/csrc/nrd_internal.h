@@ -145,14 +145,29 @@ struct Tables {
     std::vector<MGLevel> mg;                 // grid g = 1..; grid 0 = level 0
     std::vector<int32_t> prob_mgdepth;       // number of grids below level 0
     int32_t bottom_max = 0;                  // max bottom cells per problem
-    std::vector<int32_t> bottom_off;         // per problem, in bottom storage
+    std::vector<int32_t> bottom_off;         // per problem, in units of
+                                             // cells x kBottomBand doubles
 };
+
+// Band storage per row of the coarsest-grid Cholesky factor.
+constexpr int32_t kBottomBand = 32;
+
+// Staged-plane stencil tiles: at most kStageCells cells of a plane per tile,
+// whose ghosted-plane slice (the run plus its x / y neighbours) holds at most
+// kStageLen values.
+constexpr int32_t kStageCells = 512;
+constexpr int32_t kStageLen = 768;
 
 // Plane-marching tiles: planes per tile (z chunk) of each patch.
 int32_t default_zchunk(const int32_t n[3]);
+// Length of the ghosted-plane slice that covers cells [s0, s0 + cnt) of a
+// plane of patch p and their x / y neighbours.
+int32_t staged_len(const PatchInfo& p, int32_t s0, int32_t cnt);
 // run: cells of a plane per tile (256 for the plane kernel, 4 x 63 for
-// wave runs)
-void build_planes(Tables& t, const std::vector<int32_t>& kc, int32_t run);
+// wave runs, kStageCells for staged planes); max_span > 0 shortens a
+// patch's runs until every staged slice fits.  False if none fits.
+bool build_planes(Tables& t, const std::vector<int32_t>& kc, int32_t run,
+                  int32_t max_span = 0);
 
 // Builds all tables; returns NRD_OK or an error with msg set.
 nrd_status build_tables(const nrd_problem* probs, int32_t nprob,

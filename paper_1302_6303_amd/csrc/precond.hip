@@ -416,42 +416,83 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(
 }
 
 // ---------------------------------------------------------------------------
-// dense bottom solve (float64): assemble, explicit inverse (Gauss-Jordan)
-// one workgroup per (problem, field)
+// bottom solve (float64): the coarsest grid's operator is SPD and banded;
+// it is factored as L L^T (band Cholesky) once per setup and solved by two
+// banded triangular sweeps per application.  One wavefront per (problem,
+// field).  Cells are numbered with the longest axis slowest, so the band
+// half-width b = N / n_max <= N^(2/3) <= 25 for N <= 128 cells.
 // ---------------------------------------------------------------------------
 
-constexpr int kBottomMax = 128;     // cells of the coarsest grid (LDS: 128 KB)
+constexpr int kBottomMax = 128;     // cells of the coarsest grid
+constexpr int kBand = kBottomBand; // band storage per row (b + 1 <= 26)
 
+struct BottomOrder {
+    int a[3];      // axes, fastest first
+    int st[3];     // stride of each (original) axis in the band numbering
+    int b;         // half-bandwidth
+};
+
+__device__ __forceinline__ BottomOrder bottom_order(const PatchInfo& p) {
+    BottomOrder o;
+    int slow = 0;
+    if (p.n[1] > p.n[slow]) slow = 1;
+    if (p.n[2] > p.n[slow]) slow = 2;
+    int q = 0;
+    for (int d = 0; d < 3; ++d)
+        if (d != slow) o.a[q++] = d;
+    o.a[2] = slow;
+    o.st[o.a[0]] = 1;
+    o.st[o.a[1]] = p.n[o.a[0]];
+    o.st[o.a[2]] = p.n[o.a[0]] * p.n[o.a[1]];
+    o.b = o.st[o.a[2]];
+    return o;
+}
+
+__device__ __forceinline__ void bottom_coords(const PatchInfo& p, const BottomOrder& o, int lin,
+                                              int id[3]) {
+    id[o.a[0]] = lin % p.n[o.a[0]];
+    const int r = lin / p.n[o.a[0]];
+    id[o.a[1]] = r % p.n[o.a[1]];
+    id[o.a[2]] = r / p.n[o.a[1]];
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// X block of (problem, field): N rows of kBand values, row i holds
+// L_ii at [0] and L(i, i - d) at [d], 1 <= d <= b.
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_bottom_setup(
+__global__ __launch_bounds__(64) void k_bottom_setup(
     const int32_t* __restrict__ probs, const int32_t* __restrict__ boxes,
     const PatchInfo* __restrict__ P, const ProbScalars* __restrict__ ps,
     const PT* __restrict__ D, int64_t nl, const int64_t* __restrict__ boff,
     double* __restrict__ X) {
-    __shared__ double M[kBottomMax * kBottomMax];
-    __shared__ double colk[kBottomMax];
-    __shared__ double rowk[kBottomMax];
+    __shared__ double A[kBottomMax * kBand];     // A(i, i - d) at [i kBand + d]
+    __shared__ double Ld[kBottomMax];
     const int pi = blockIdx.x >> 1;
     const int fld = blockIdx.x & 1;
     const int prob = probs[pi];
     const PatchInfo& p = P[boxes[pi]];
     const double beta = ps[prob].beta;
     const int N = p.ncell;                      // <= kBottomMax (checked on the host)
-    for (int i = threadIdx.x; i < N * N; i += blockDim.x) M[i] = 0.0;
+    const BottomOrder o = bottom_order(p);
+    const int b = o.b;                          // < kBand (checked on the host)
+    for (int i = threadIdx.x; i < N * kBand; i += blockDim.x) A[i] = 0.0;
     __syncthreads();
     const int st[3] = {1, p.sy, p.sz};
-    const int sl[3] = {1, p.n[0], p.n[0] * p.n[1]};
     for (int lin = threadIdx.x; lin < N; lin += blockDim.x) {
         int id[3];
-        coords(p, lin, id[0], id[1], id[2]);
+        bottom_coords(p, o, lin, id);
         const int c = nat(p, id[0], id[1], id[2]);
         double dg = 1.0;
         for (int d = 0; d < 3; ++d) {
             const double bh2 = beta * p.ih[d] * p.ih[d];
             const PT* Dd = D + (fld * 3 + d) * nl;
             for (int s = 0; s < 2; ++s) {
-                const int slot = s ? c + st[d] : c;
-                const double Dv = (double)Dd[slot];
+                const double Dv = (double)Dd[s ? c + st[d] : c];
                 if (id[d] == (s ? p.n[d] - 1 : 0)) {        // grid covers the domain
                     if (fld == 0 && ((p.robin >> (2 * d + s)) & 1))
                         dg += 2.0 * beta * Dv / ((4.0 * Dv + p.h[d]) * p.h[d]);
@@ -459,74 +500,72 @@ __global__ __launch_bounds__(kBlock) void k_bottom_setup(
                 }
                 const double a = bh2 * Dv;
                 dg += a;
-                M[lin * N + (s ? lin + sl[d] : lin - sl[d])] = -a;
+                // the lower neighbour's entry; the upper one is that
+                // neighbour's lower entry (same face, same coefficient)
+                if (s == 0) A[lin * kBand + o.st[d]] = -a;
             }
         }
-        M[lin * N + lin] = dg;
+        A[lin * kBand] = dg;
     }
     __syncthreads();
-    // In-place Gauss-Jordan inversion in LDS (A is SPD: no pivoting).  Step k
-    // scales row k by 1/a_kk and eliminates column k from the other rows; the
-    // pivot row and column are staged first so every update reads old values.
-    const int j = threadIdx.x & (kBottomMax - 1);
-    const int r0 = threadIdx.x / kBottomMax;
-    const int rstep = blockDim.x / kBottomMax;
+    // right-looking band Cholesky: column k, then the trailing b x b block
     for (int k = 0; k < N; ++k) {
-        for (int i = threadIdx.x; i < N; i += blockDim.x) {
-            colk[i] = M[i * N + k];
-            rowk[i] = M[k * N + i];
-        }
+        const double dkk = sqrt(A[k * kBand]);
+        const int m = min(b, N - 1 - k);
+        for (int t = threadIdx.x + 1; t <= m; t += blockDim.x) A[(k + t) * kBand + t] /= dkk;
+        if (threadIdx.x == 0) Ld[k] = dkk;
         __syncthreads();
-        const double ip = 1.0 / colk[k];
-        if (j < N) {
-            const double r = (j == k) ? ip : rowk[j] * ip;
-            // eight independent rows per pass keep LDS loads in flight
-            for (int i0 = r0; i0 < N; i0 += 8 * rstep) {
-                double m[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int i = i0 + q * rstep;
-                    m[q] = (i < N) ? M[i * N + j] : 0.0;
-                }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int i = i0 + q * rstep;
-                    if (i < N)
-                        M[i * N + j] = (i == k) ? r : ((j == k) ? 0.0 : m[q]) - colk[i] * r;
-                }
-            }
+        for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+            const int r = idx / m + 1, q = idx % m + 1;
+            if (q > r) continue;
+            A[(k + r) * kBand + (r - q)] -= A[(k + r) * kBand + r] * A[(k + q) * kBand + q];
         }
         __syncthreads();
     }
-    double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * N;
-    for (int i = threadIdx.x; i < N * N; i += blockDim.x) Xi[i] = M[i];
+    double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * kBand;
+    for (int i = threadIdx.x; i < N * kBand; i += blockDim.x)
+        Xi[i] = (i % kBand == 0) ? Ld[i / kBand] : A[i];
 }
 
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_bottom_apply(
+__global__ __launch_bounds__(64) void k_bottom_apply(
     const int32_t* __restrict__ probs, const int32_t* __restrict__ boxes,
     const PatchInfo* __restrict__ P, const int64_t* __restrict__ boff,
     const double* __restrict__ X, const PT* __restrict__ f, PT* __restrict__ e,
     int64_t nl) {
-    __shared__ double fv[kBottomMax];
+    __shared__ double L[kBottomMax * kBand];
+    __shared__ double y[kBottomMax];
     const int pi = blockIdx.x >> 1;
     const int fld = blockIdx.x & 1;
     const int prob = probs[pi];
     const PatchInfo& p = P[boxes[pi]];
     const int N = p.ncell;
-    const double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * N;
+    const BottomOrder o = bottom_order(p);
+    const int b = o.b;
+    const double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * kBand;
+    for (int i = threadIdx.x; i < N * kBand; i += blockDim.x) L[i] = Xi[i];
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         int id[3];
-        coords(p, j, id[0], id[1], id[2]);
-        fv[j] = (double)f[fld * nl + nat(p, id[0], id[1], id[2])];
+        bottom_coords(p, o, j, id);
+        y[j] = (double)f[fld * nl + nat(p, id[0], id[1], id[2])];
     }
     __syncthreads();
-    for (int row = threadIdx.x; row < N; row += blockDim.x) {
-        double s = 0.0;
-        for (int jj = 0; jj < N; ++jj) s += Xi[(int64_t)jj * N + row] * fv[jj];
+    const int l = threadIdx.x + 1;              // lane l handles band offset l
+    for (int i = 0; i < N; ++i) {               // L y = f
+        const double sum = wave_sum64(l <= min(b, i) ? L[i * kBand + l] * y[i - l] : 0.0);
+        if (threadIdx.x == 0) y[i] = (y[i] - sum) / L[i * kBand];
+        __syncthreads();
+    }
+    for (int i = N - 1; i >= 0; --i) {          // L^T x = y
+        const double sum =
+            wave_sum64(l <= min(b, N - 1 - i) ? L[(i + l) * kBand + l] * y[i + l] : 0.0);
+        if (threadIdx.x == 0) y[i] = (y[i] - sum) / L[i * kBand];
+        __syncthreads();
+    }
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
         int id[3];
-        coords(p, row, id[0], id[1], id[2]);
-        e[fld * nl + nat(p, id[0], id[1], id[2])] = (PT)s;
+        bottom_coords(p, o, j, id);
+        e[fld * nl + nat(p, id[0], id[1], id[2])] = (PT)y[j];
     }
 }
 
@@ -628,6 +667,15 @@ __global__ __launch_bounds__(kBlock) void k_fill_t(PT* __restrict__ x, int64_t n
     if (i < n) x[i] = PT(0);
 }
 
+// plain copy (a kernel rather than a runtime copy, so that captured graphs
+// hold only kernel nodes)
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_copy_t(const PT* __restrict__ x,
+                                                   PT* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+
 // ---------------------------------------------------------------------------
 // drivers
 // ---------------------------------------------------------------------------
@@ -668,7 +716,7 @@ void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
         const PT* Dg = (g == 0) ? Dface : mg.Dg[g];
         const int64_t nlg = (g == 0) ? d.nl : mg.len[g];
         const PatchInfo* Pg = (g == 0) ? d.patches : mg.box[g];
-        k_bottom_setup<PT><<<2 * mg.nbottom[g], kBlock, 0, s>>>(
+        k_bottom_setup<PT><<<2 * mg.nbottom[g], 64, 0, s>>>(
             mg.bottom_probs[g], mg.bottom_boxes[g], Pg, d.ps, Dg, nlg, mg.bottom_off, mg.Xbuf);
     }
 }
@@ -703,7 +751,7 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
                 mg.len[g + 1]);
         }
         if (mg.nbottom[g] > 0)
-            k_bottom_apply<PT><<<2 * mg.nbottom[g], kBlock, 0, s>>>(
+            k_bottom_apply<PT><<<2 * mg.nbottom[g], 64, 0, s>>>(
                 mg.bottom_probs[g], mg.bottom_boxes[g], Pg, mg.bottom_off, mg.Xbuf, fg, eg,
                 nlg);
     }
@@ -776,7 +824,7 @@ void PcArrays<PT>::fac(hipStream_t s) const {
     for (int lev = L; lev >= 0; --lev) {
         if (lev == L) {
             // u = 0: r = f on composite cells, restricted below
-            (void)hipMemcpyAsync(r, f, sizeof(PT) * 2 * d.nl, hipMemcpyDeviceToDevice, s);
+            k_copy_t<PT><<<nblocks(2 * d.nl), kBlock, 0, s>>>(f, r, 2 * d.nl);
             restrict_(s, r, 0);
         } else {
             composite_residual(s);

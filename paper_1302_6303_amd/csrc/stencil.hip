@@ -563,6 +563,249 @@ __global__ __launch_bounds__(kBlock) void k_stencil_flat(
     out[c + nl] = oT;
 }
 
+// Staged-plane variant.  A tile is a run of up to 2 x 256 consecutive cells
+// of one z-plane (x fastest) and a range of planes; thread t owns cells t and
+// t + 256 of the run.  For every plane the workgroup copies the contiguous
+// slice of the ghosted plane that covers the run and its x / y neighbours
+// (E, T, z^3, plus the tangent in MODE 1) into LDS once, so every value is
+// read from memory once per tile rather than once per face.  Each face is
+// evaluated once: low x / low y faces by the cell, high ones from the
+// neighbouring cell through LDS (evaluated directly when the neighbour is
+// outside the run), the z face carried in registers to the next plane.  The
+// next plane's slice is loaded into registers while the current faces are
+// evaluated.
+static_assert(kStageCells == 2 * kBlock, "two cells per thread");
+constexpr int kStagePer = (kStageLen + kBlock - 1) / kBlock;
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_stencil_s(
+    const STile* __restrict__ tiles, int t0, const PatchInfo* __restrict__ P,
+    const ProbScalars* __restrict__ ps, const int32_t* __restrict__ active,
+    const uint8_t* __restrict__ ctype, const double* __restrict__ u,
+    const double* __restrict__ v, const double* __restrict__ z3,
+    const double* __restrict__ b, double* __restrict__ out, int64_t nl) {
+    constexpr int NA = MODE ? 5 : 3;            // E, T, z^3 (, vE, vT)
+    __shared__ double sl[NA][kStageLen];
+    __shared__ double fl[4][kStageCells];       // low x E/T, low y E/T fluxes
+    const STile t = tiles[t0 + xcd_tile(blockIdx.x, gridDim.x)];
+    if (active && !active[t.prob]) return;      // uniform over the workgroup
+    const PatchInfo& p = P[t.patch];
+    const ProbScalars& q = ps[t.prob];
+    const double kappa = q.kappa, lam = q.lam;
+    const int tid = threadIdx.x;
+    const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const int sy = p.sy, sz = p.sz;
+    const bool use_ct = p.flags & PF_CTYPE;
+    const double hx = p.h[0], hy = p.h[1], hz = p.h[2];
+    const double ihx = p.ih[0], ihy = p.ih[1], ihz = p.ih[2];
+    const bool zlo_p = (p.phys >> 4) & 1, zhi_p = (p.phys >> 5) & 1;
+    // the slice [g0, g0 + len) of a ghosted plane covers the run and its
+    // x / y neighbours (host-checked: len <= kStageLen)
+    const int la = t.s0, lb = t.s0 + t.cnt - 1;
+    const int g0 = (la % nx + 1) + sy * (la / nx);
+    const int len = (lb % nx + 1) + sy * (lb / nx + 2) - g0 + 1;
+    const double* src[NA];
+    src[0] = u;
+    src[1] = u + nl;
+    src[2] = z3;
+    if (MODE) {
+        src[NA - 2] = v;
+        src[NA - 1] = v + nl;
+    }
+    // per cell (r = 0, 1): run index, coordinates, slice index, native index
+    int ix[2], jx[2], sidx[2], cn[2];
+    bool live[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int idx = tid + r * kBlock;
+        live[r] = idx < t.cnt;
+        const int lin = t.s0 + (live[r] ? idx : 0);
+        ix[r] = lin % nx;
+        jx[r] = lin / nx;
+        sidx[r] = (ix[r] + 1) + sy * (jx[r] + 1) - g0;
+        cn[r] = p.off + (ix[r] + 1) + sy * (jx[r] + 1);   // plane offset added per k
+    }
+    // prologue: stage plane k0 directly
+    {
+        const int64_t base = p.off + (int64_t)sz * (t.k0 + 1) + g0;
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+            for (int e = tid; e < len; e += kBlock) sl[a][e] = src[a][base + e];
+    }
+    __syncthreads();
+    double oE[2], oT[2], oz[2], odE[2], odT[2];          // own values, plane k
+    double czE[2], czT[2];                               // low z face fluxes
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        oE[r] = sl[0][sidx[r]];
+        oT[r] = sl[1][sidx[r]];
+        oz[r] = sl[2][sidx[r]];
+        odE[r] = MODE ? sl[NA - 2][sidx[r]] : 0.0;
+        odT[r] = MODE ? sl[NA - 1][sidx[r]] : 0.0;
+        czE[r] = czT[r] = 0.0;
+        if (!live[r]) continue;
+        const int c = cn[r] + sz * (t.k0 + 1);
+        if (t.k0 == 0 && zlo_p) {
+            if ((p.robin >> 4) & 1) czE[r] = -robin_any<MODE>(oE[r], oT[r], oz[r], q.R[4], hz,
+                                                              odE[r], odT[r]);
+        } else {
+            const int a = c - sz;
+            if (MODE == 0)
+                face_flux(u[a], oE[r], u[a + nl], oT[r], z3[a], oz[r], hz, ihz, kappa, lam,
+                          czE[r], czT[r]);
+            else
+                face_flux_tan(u[a], oE[r], u[a + nl], oT[r], z3[a], oz[r], v[a], odE[r],
+                              v[a + nl], odT[r], hz, ihz, kappa, lam, czE[r], czT[r]);
+        }
+    }
+    for (int k = t.k0; k < t.k1; ++k) {
+        // next plane's slice into registers (the ghost plane when k = nz - 1)
+        double pre[NA][kStagePer];
+        {
+            const int64_t base = p.off + (int64_t)sz * (k + 2) + g0;
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+#pragma unroll
+                for (int w = 0; w < kStagePer; ++w) {
+                    const int e = tid + w * kBlock;
+                    pre[a][w] = (e < len) ? src[a][base + e] : 0.0;
+                }
+        }
+        double bE[2] = {0.0, 0.0}, bT[2] = {0.0, 0.0};
+        if (MODE == 0) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                if (live[r]) {
+                    const int c = cn[r] + sz * (k + 1);
+                    bE[r] = b[c];
+                    bT[r] = b[c + nl];
+                }
+        }
+        // phase A: faces from the staged plane k
+        double lxE[2], lxT[2], lyE[2], lyT[2], hxE[2], hxT[2], hyE[2], hyT[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            lxE[r] = lxT[r] = lyE[r] = lyT[r] = hxE[r] = hxT[r] = hyE[r] = hyT[r] = 0.0;
+            if (!live[r]) continue;
+            const int idx = tid + r * kBlock;
+            const int si = sidx[r];
+            const int i = ix[r], j = jx[r];
+            const double E = oE[r], T = oT[r], z = oz[r], dE = odE[r], dT = odT[r];
+            auto face = [&](int sa, int sb, double h, double ih, double& fe, double& ft) {
+                if (MODE == 0)
+                    face_flux(sl[0][sa], sl[0][sb], sl[1][sa], sl[1][sb], sl[2][sa], sl[2][sb], h,
+                              ih, kappa, lam, fe, ft);
+                else
+                    face_flux_tan(sl[0][sa], sl[0][sb], sl[1][sa], sl[1][sb], sl[2][sa],
+                                  sl[2][sb], sl[NA - 2][sa], sl[NA - 2][sb], sl[NA - 1][sa],
+                                  sl[NA - 1][sb], h, ih, kappa, lam, fe, ft);
+            };
+            if (i == 0 && (p.phys & 1)) {
+                if (p.robin & 1) lxE[r] = -robin_any<MODE>(E, T, z, q.R[0], hx, dE, dT);
+            } else {
+                face(si - 1, si, hx, ihx, lxE[r], lxT[r]);
+            }
+            if (j == 0 && ((p.phys >> 2) & 1)) {
+                if ((p.robin >> 2) & 1) lyE[r] = -robin_any<MODE>(E, T, z, q.R[2], hy, dE, dT);
+            } else {
+                face(si - sy, si, hy, ihy, lyE[r], lyT[r]);
+            }
+            if (i == nx - 1 && ((p.phys >> 1) & 1)) {
+                if ((p.robin >> 1) & 1) hxE[r] = robin_any<MODE>(E, T, z, q.R[1], hx, dE, dT);
+            } else if (!(i < nx - 1 && idx + 1 < t.cnt)) {
+                face(si, si + 1, hx, ihx, hxE[r], hxT[r]);
+            }
+            if (j == ny - 1 && ((p.phys >> 3) & 1)) {
+                if ((p.robin >> 3) & 1) hyE[r] = robin_any<MODE>(E, T, z, q.R[3], hy, dE, dT);
+            } else if (!(idx + nx < t.cnt)) {
+                face(si, si + sy, hy, ihy, hyE[r], hyT[r]);
+            }
+        }
+        __syncthreads();
+        // phase B: publish low fluxes, stage plane k + 1
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int idx = tid + r * kBlock;
+            fl[0][idx] = lxE[r];
+            fl[1][idx] = lxT[r];
+            fl[2][idx] = lyE[r];
+            fl[3][idx] = lyT[r];
+        }
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+            for (int w = 0; w < kStagePer; ++w) {
+                const int e = tid + w * kBlock;
+                if (e < len) sl[a][e] = pre[a][w];
+            }
+        __syncthreads();
+        // phase C: high faces, z faces, cell terms
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int idx = tid + r * kBlock;
+            const int si = sidx[r];
+            const double nE = sl[0][si], nT = sl[1][si], nz3 = sl[2][si];
+            const double ndE = MODE ? sl[NA - 2][si] : 0.0;
+            const double ndT = MODE ? sl[NA - 1][si] : 0.0;
+            if (live[r]) {
+                const int i = ix[r];
+                const int c = cn[r] + sz * (k + 1);
+                const double E = oE[r], T = oT[r], z = oz[r], dE = odE[r], dT = odT[r];
+                if (i < nx - 1 && idx + 1 < t.cnt && !(i == nx - 1 && ((p.phys >> 1) & 1))) {
+                    hxE[r] = fl[0][idx + 1];
+                    hxT[r] = fl[1][idx + 1];
+                }
+                if (idx + nx < t.cnt && !(jx[r] == ny - 1 && ((p.phys >> 3) & 1))) {
+                    hyE[r] = fl[2][idx + nx];
+                    hyT[r] = fl[3][idx + nx];
+                }
+                double hzE = 0.0, hzT = 0.0;
+                if (k == nz - 1 && zhi_p) {
+                    if ((p.robin >> 5) & 1) hzE = robin_any<MODE>(E, T, z, q.R[5], hz, dE, dT);
+                } else if (MODE == 0) {
+                    face_flux(E, nE, T, nT, z, nz3, hz, ihz, kappa, lam, hzE, hzT);
+                } else {
+                    face_flux_tan(E, nE, T, nT, z, nz3, dE, ndE, dT, ndT, hz, ihz, kappa, lam,
+                                  hzE, hzT);
+                }
+                double l_xE = lxE[r], l_xT = lxT[r], l_yE = lyE[r], l_yT = lyT[r];
+                double h_xE = hxE[r], h_xT = hxT[r], h_yE = hyE[r], h_yT = hyT[r];
+                double l_zE = czE[r], l_zT = czT[r];
+                czE[r] = hzE;
+                czT[r] = hzT;
+                const int ct = use_ct ? ctype[c] : 0;
+                if (ct & CT_COVERED) {
+                    out[c] = 0.0;
+                    out[c + nl] = 0.0;
+                } else {
+                    if (ct & (1 << 1)) l_xE = l_xT = 0.0;
+                    if (ct & (1 << 2)) h_xE = h_xT = 0.0;
+                    if (ct & (1 << 3)) l_yE = l_yT = 0.0;
+                    if (ct & (1 << 4)) h_yE = h_yT = 0.0;
+                    if (ct & (1 << 5)) l_zE = l_zT = 0.0;
+                    if (ct & (1 << 6)) hzE = hzT = 0.0;
+                    const double divE =
+                        (h_xE - l_xE) * ihx + (h_yE - l_yE) * ihy + (hzE - l_zE) * ihz;
+                    const double divT =
+                        (h_xT - l_xT) * ihx + (h_yT - l_yT) * ihy + (hzT - l_zT) * ihz;
+                    double rE, rT;
+                    if (MODE == 0)
+                        cell_out0(q, E, T, z, bE[r], bT[r], divE, divT, rE, rT);
+                    else
+                        cell_out1(q, E, T, z, dE, dT, divE, divT, rE, rT);
+                    out[c] = rE;
+                    out[c + nl] = rT;
+                }
+            }
+            oE[r] = nE;
+            oT[r] = nT;
+            oz[r] = nz3;
+            odE[r] = ndE;
+            odT[r] = ndT;
+        }
+    }
+}
+
 // Flux matching: a coarse face bordering a finer level carries the mean of
 // the four fine fluxes (Sec. 3.2.1).  The stencil skipped that face; add
 // -dt * (+-mean) / h_c here.  One thread per coarse cell (no races).
@@ -613,7 +856,10 @@ __global__ __launch_bounds__(kBlock) void k_reflux(
 void residual(const Dev& D, hipStream_t s, int t0, int nt, const double* u, const double* b,
               double* F) {
     if (nt <= 0) return;
-    if (D.bricks == 1)
+    if (D.bricks == 3)
+        k_stencil_s<0><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
+                                             u, nullptr, D.z3, b, F, D.nl);
+    else if (D.bricks == 1)
         k_stencil_z<0><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
                                              u, nullptr, D.z3, b, F, D.nl);
     else if (D.bricks == 2)
@@ -632,7 +878,10 @@ void residual_reflux(const Dev& D, hipStream_t s, const double* u, double* F) {
 void jvp(const Dev& D, hipStream_t s, int t0, int nt, const double* u, const double* v,
          double* Jv) {
     if (nt <= 0) return;
-    if (D.bricks == 1)
+    if (D.bricks == 3)
+        k_stencil_s<1><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
+                                             u, v, D.z3, nullptr, Jv, D.nl);
+    else if (D.bricks == 1)
         k_stencil_z<1><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
                                              u, v, D.z3, nullptr, Jv, D.nl);
     else if (D.bricks == 2)

@@ -367,6 +367,93 @@ void to_double(hipStream_t s, const float* x, double* y, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// Jacobian-free product (Sec. 4.1, eq. Jac-free): per-problem plain sums over
+// composite cells of both fields of u.v, |v| and v.v; the differencing step
+//   eps = sqrt(eps_mach) <u,v> / ||v||^2                 if |<u,v>| > u_min ||v||_1
+//       = sqrt(eps_mach) u_min sign(<u,v>) ||v||_1 / ||v||^2   otherwise,
+// u_min = 1e-6, sign(0) = +1, eps = 1 for v = 0; then w = u + eps v and,
+// after the residual of w, Jv = (F(w) - F(u)) / eps.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_fd_sums(
+    const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
+    const uint8_t* __restrict__ ctype, const double* __restrict__ u,
+    const double* __restrict__ v, double* __restrict__ partial, int64_t nl) {
+    __shared__ double sh[4];
+    const Tile t = vt[blockIdx.x];
+    const PatchInfo& p = P[t.patch];
+    const bool cov = p.flags & PF_COVERED;
+    double uv = 0.0, l1 = 0.0, v2 = 0.0;
+    for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+        const int c = interior_index(p, lin);
+        if (cov && (ctype[c] & CT_COVERED)) continue;
+        const double v0 = v[c], v1 = v[c + nl];
+        uv += u[c] * v0 + u[c + nl] * v1;
+        l1 += fabs(v0) + fabs(v1);
+        v2 += v0 * v0 + v1 * v1;
+    }
+    uv = block_sum(uv, sh);
+    l1 = block_sum(l1, sh);
+    v2 = block_sum(v2, sh);
+    if (threadIdx.x == 0) {
+        partial[(int64_t)blockIdx.x * 3 + 0] = uv;
+        partial[(int64_t)blockIdx.x * 3 + 1] = l1;
+        partial[(int64_t)blockIdx.x * 3 + 2] = v2;
+    }
+}
+
+__device__ __forceinline__ double fd_step(const double* __restrict__ S) {
+    const double uv = S[0], l1 = S[1], v2 = S[2];
+    const double root = 0x1p-26;                 // sqrt(2^-52), exact
+    if (!(v2 > 0.0)) return 1.0;
+    if (fabs(uv) > 1e-6 * l1) return root * uv / v2;
+    const double sg = uv >= 0.0 ? 1.0 : -1.0;
+    return root * 1e-6 * sg * l1 / v2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fd_shift(
+    const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
+    const double* __restrict__ sums, const double* __restrict__ u,
+    const double* __restrict__ v, double* __restrict__ w, int64_t nl) {
+    const Tile t = vt[blockIdx.x];
+    const PatchInfo& p = P[t.patch];
+    const double eps = fd_step(sums + 3 * t.prob);
+    for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+        const int c = interior_index(p, lin);
+        w[c] = u[c] + eps * v[c];
+        w[c + nl] = u[c + nl] + eps * v[c + nl];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fd_quotient(
+    const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
+    const double* __restrict__ sums, const double* __restrict__ F0,
+    double* __restrict__ Jv, int64_t nl) {
+    const Tile t = vt[blockIdx.x];
+    const PatchInfo& p = P[t.patch];
+    const double eps = fd_step(sums + 3 * t.prob);
+    for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+        const int c = interior_index(p, lin);
+        Jv[c] = (Jv[c] - F0[c]) / eps;
+        Jv[c + nl] = (Jv[c + nl] - F0[c + nl]) / eps;
+    }
+}
+
+void fd_sums(const Dev& D, hipStream_t s, const double* u, const double* v, double* partial,
+             double* sums) {
+    k_fd_sums<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, u, v, partial, D.nl);
+    k_sum_partials<<<D.nprob, kBlock, 0, s>>>(D.prob_vtile0, partial, 3, sums, 3);
+}
+void fd_shift(const Dev& D, hipStream_t s, const double* sums, const double* u,
+              const double* v, double* w) {
+    k_fd_shift<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, sums, u, v, w, D.nl);
+}
+void fd_quotient(const Dev& D, hipStream_t s, const double* sums, const double* F0,
+                 double* Jv) {
+    k_fd_quotient<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, sums, F0, Jv, D.nl);
+}
+
+// ---------------------------------------------------------------------------
 // FGMRES per-problem scalars (one thread per problem)
 //   H: [nprob][(m+1) * m], column j at H[p][(m+1) j]
 // ---------------------------------------------------------------------------

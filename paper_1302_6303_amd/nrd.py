@@ -49,7 +49,7 @@ class nrd_options(C.Structure):
                 ("gmres_maxrestarts", C.c_int32), ("mg_nu_pre", C.c_int32),
                 ("mg_nu_post", C.c_int32), ("adjoint_slots", C.c_int32),
                 ("stencil", C.c_int32), ("zchunk", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("bdf_max_order", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class nrd_step_stats(C.Structure):

@@ -43,7 +43,7 @@ def _setup(name, dt=2e-3, **opt):
     return w, s, H, u_n, u, dt
 
 
-@pytest.mark.parametrize("stencil", [0, 1, 2])
+@pytest.mark.parametrize("stencil", [0, 1, 2, 3])
 @pytest.mark.parametrize("name", list(WL))
 def test_residual_parity(name, stencil):
     w, s, H, u_n, u, dt = _setup(name, stencil=stencil)
@@ -61,7 +61,7 @@ def test_residual_parity(name, stencil):
     assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-300)
 
 
-@pytest.mark.parametrize("stencil", [0, 1, 2])
+@pytest.mark.parametrize("stencil", [0, 1, 2, 3])
 @pytest.mark.parametrize("name", list(WL))
 def test_jvp_parity(name, stencil):
     w, s, H, u_n, u, dt = _setup(name, stencil=stencil)
@@ -128,7 +128,7 @@ def test_implicit_steps_parity(name):
             assert rel_err(got[sl], st.u[sl]) < 1e-8
 
 
-@pytest.mark.parametrize("stencil", [0, 1, 2])
+@pytest.mark.parametrize("stencil", [0, 1, 2, 3])
 def test_per_patch_launches_match_batched_bitwise(stencil):
     """One launch per patch and one launch over the whole patch table run the
     same kernels on the same tiles: outputs are bitwise equal, run twice."""
@@ -150,3 +150,28 @@ def test_per_patch_launches_match_batched_bitwise(stencil):
     for a, b in outs[1:]:
         np.testing.assert_array_equal(a, outs[0][0])
         np.testing.assert_array_equal(b, outs[0][1])
+
+
+@pytest.mark.parametrize("name", ["uniform16", "amr3"])
+def test_fd_jvp_parity(name):
+    """Jacobian-free mode (Sec. 4.1): the GPU difference quotient against the
+    oracle's with the same step rule to 1e-6 (the quotient magnifies the
+    round-off of the two residuals by 1/eps ~ 1e8), and against the analytic
+    action to 1e-5."""
+    w, s, H, u_n, u, dt = _setup(name, jvp_mode=1)
+    rng = np.random.default_rng(7)
+    v = s.sync(rng.standard_normal(u.shape) * u)
+    v /= s.norm(v)
+    Jv = H.native()
+    H.jvp(native_from_compact(H, u), native_from_compact(H, v), Jv)
+    got = compact_from_native(H, Jv)
+    E, T = s.split(u)
+    vE, vT = s.split(v)
+    bE, bT = s.split(u_n)
+    JE, JT = ops.jvp_fd(s.H, E, T, s.z, vE, vT, bE, bT, dt, 1.0, s.lam)
+    ref = s.join(JE, JT)
+    ana = s.jvp(u, v, dt, 1.0)
+    n = s.nc
+    for sl in (slice(0, n), slice(n, 2 * n)):
+        assert rel_err(got[sl], ref[sl]) < 1e-6
+        assert rel_err(got[sl], ana[sl]) < 1e-5

@@ -170,21 +170,17 @@ def test_adjoint_gradient_matches_central_differences():
                 gmres_maxrestarts=30, adjoint_slots=N // every + every + 3)
     H = make(w, **opts)
     g = to_host(H.adjoint_run([dt], N, every))
-    # forward with BDF1 only: use one step per set_fields reset and a
-    # hierarchy that never keeps history
+    # the forward solve with backward Euler throughout, like the adjoint's
     zc = w.compact(w.z)
     order = np.argsort(-np.abs(g))[:6]
-    Hf = make(w, **opts)
+    Hf = make(w, bdf_max_order=1, **opts)
 
     def J(zz):
         u = compact_state(w)
         nn = Hf.ncells
         Hf.set_fields(to_dev(u[:nn]), to_dev(u[nn:]), to_dev(zz))
         for _ in range(N):
-            rc, st = Hf.implicit_step([dt])
-            # reset history so that every step is BDF1 like the adjoint's
-            E, T = Hf.get_fields()
-            Hf.set_fields(E, T, to_dev(zz))
+            Hf.implicit_step([dt])
         E, _ = Hf.get_fields()
         e = to_host(E)
         return np.sum(np.sort(e))
@@ -197,3 +193,82 @@ def test_adjoint_gradient_matches_central_differences():
         zm[c] -= hz
         fd = (J(zp) - J(zm)) / (2 * hz)
         assert abs(fd - g[c]) <= 1e-5 * abs(g[c]), (c, fd, g[c])
+
+
+def test_autograd_function_gives_the_adjoint_gradient():
+    """torch.autograd through RadDiffEvolve equals the oracle's adjoint."""
+    import torch
+    from paper_1302_6303_amd.autograd import RadDiffEvolve
+    n, N, every, dt = 8, 4, 2, 2e-3
+    zc = _smooth_z(n, 93)
+    w = I.marshak_single(n)
+    w.z = [zc]
+    H = make(w, newton_rtol=1e-11, newton_atol=1e-22, newton_maxit=24, bdf_max_order=1,
+             adjoint_slots=N // every + every + 3, gmres_maxrestarts=20)
+    u = compact_state(w)
+    nc = H.ncells
+    E0, T0 = to_dev(u[:nc]), to_dev(u[nc:])
+    z = to_dev(w.compact(w.z)).requires_grad_(True)
+    E = RadDiffEvolve.apply(z, H, E0, T0, dt, N, every)
+    E.sum().backward()
+    s = System(Hierarchy((n, n, n), [(0, (0, 0, 0), (n, n, n))]), [zc])
+    ref, states = adjoint_gradient(s, u, dt, N, tol=1e-13,
+                                   newton_kw=dict(rtol=1e-11, atol=1e-22, maxit=40))
+    assert rel_err(to_host(E), states[-1][:nc]) < 1e-8
+    assert rel_err(to_host(z.grad), ref) < 1e-7
+
+
+def test_jacobian_free_mode_reaches_the_same_solution():
+    """Newton with difference-quotient products converges to the solution of
+    the analytic-Jacobian run (the products only steer the Krylov solves)."""
+    w = I.static_amr(base=16, nlevels=3, side=(8, 16), state="front")
+    Ha = make(w, newton_rtol=1e-10, newton_atol=1e-16)
+    Hf = make(w, jvp_mode=1, newton_rtol=1e-10, newton_atol=1e-16)
+    for dt in (1e-3, 1e-3):
+        _, sa = Ha.implicit_step([dt])
+        _, sf = Hf.implicit_step([dt])
+        assert sa[0]["converged"] and sf[0]["converged"]
+    a, b = _fields(Ha), _fields(Hf)
+    n = len(a) // 2
+    assert rel_err(b[:n], a[:n]) < 1e-8
+    assert rel_err(b[n:], a[n:]) < 1e-8
+
+
+@pytest.mark.parametrize("kind", ["amr", "ensemble"])
+def test_graph_captured_iterations_replay_bitwise(kind):
+    """FGMRES iterations captured as HIP graphs (one per Krylov index) and
+    replayed across Newton iterations, restarts and steps, with eager work
+    and host synchronisations in between, give bitwise the eager results."""
+    w = I.static_amr(base=16, nlevels=3, side=(8, 16), state="front") if kind == "amr" \
+        else small_ensemble()
+    outs = []
+    for g in (0, 1):
+        H = make(w, precision=1, use_graph=g)
+        dts = list(w.dt)
+        stats = []
+        for step in range(3):
+            _, st = H.implicit_step([d * (1.0 if step < 2 else 1.3) for d in dts])
+            stats.append([(s["newton_iters"], s["krylov_iters"]) for s in st])
+            outs.append((g, step, _fields(H)))
+        outs.append((g, "stats", stats))
+    eager = [o for o in outs if o[0] == 0]
+    graph = [o for o in outs if o[0] == 1]
+    for a, b in zip(eager, graph):
+        if a[1] == "stats":
+            assert a[2] == b[2]
+        else:
+            np.testing.assert_array_equal(a[2], b[2])
+
+
+def test_graph_captured_adjoint_matches_eager():
+    n, N, every, dt = 8, 4, 2, 2e-3
+    z = _smooth_z(n, 94)
+    w = I.marshak_single(n)
+    w.z = [z]
+    g = []
+    for use_graph in (0, 1):
+        H = make(w, newton_rtol=1e-11, newton_atol=1e-22, newton_maxit=24,
+                 adjoint_slots=N // every + every + 3, gmres_maxrestarts=20,
+                 use_graph=use_graph)
+        g.append(to_host(H.adjoint_run([dt], N, every)))
+    np.testing.assert_array_equal(g[0], g[1])

@@ -470,3 +470,51 @@ def test_vjp_z_derivative_matches_fd():
         s.z = [z0]
         fd = (vals[0] - vals[1]) / (2 * hz)
         assert abs(fd - gz[c]) <= 1e-6 * max(abs(gz[c]), 1e-3 * np.abs(gz).max())
+
+
+# ---------------------------------------------------------------------------
+# Jacobian-free product (Sec. 4.1)
+# ---------------------------------------------------------------------------
+
+def test_fd_epsilon_special_cases():
+    """v = u gives <u,v>/||v||^2 = 1, so eps = sqrt(eps_mach); v = -u flips
+    the sign; a v orthogonal to u takes the u_min branch; v = 0 gives 1."""
+    w = I.static_amr(base=8, nlevels=2, side=(4, 8), state="front")
+    s = system(w)
+    u = state(s, w)
+    E, T = s.split(u)
+    root = np.sqrt(np.finfo(np.float64).eps)
+    assert ops.fd_epsilon(s.H, E, T, E, T) == pytest.approx(root, rel=1e-15)
+    mE, mT = s.split(-u)
+    assert ops.fd_epsilon(s.H, E, T, mE, mT) == pytest.approx(-root, rel=1e-15)
+    rng = np.random.default_rng(12)
+    keep = s.composite
+    v = rng.standard_normal(u.shape) * keep
+    v -= (np.dot(u[keep], v[keep]) / np.dot(u[keep], u[keep])) * u * keep
+    vE, vT = s.split(v)
+    l1, v2 = np.abs(v[keep]).sum(), (v[keep] ** 2).sum()
+    eps = ops.fd_epsilon(s.H, E, T, vE, vT)
+    assert abs(eps) == pytest.approx(root * 1e-6 * l1 / v2, rel=1e-12)
+    zE, zT = s.split(0.0 * u)
+    assert ops.fd_epsilon(s.H, E, T, zE, zT) == 1.0
+
+
+@pytest.mark.parametrize("amr", [False, True])
+def test_fd_jvp_agrees_with_analytic(amr):
+    """The Jacobian-free product approximates the analytic one (itself
+    pinned by brute force) to ~sqrt(eps_mach) for normalised v."""
+    w = I.static_amr(base=8, nlevels=2, side=(4, 8), state="front") if amr else \
+        I.marshak_single(8, state="front")
+    s = system(w)
+    s_fd = system(w)
+    s_fd.jvp_mode = "fd"
+    u = state(s, w)
+    b = 0.9 * u
+    rng = np.random.default_rng(13)
+    s_fd.residual(u, b, 1e-3, 1.0)
+    for _ in range(3):
+        v = s.sync(rng.standard_normal(u.shape) * u)
+        v /= s.norm(v)
+        Ja = s.jvp(u, v, 1e-3, 1.0)
+        Jf = s_fd.jvp(u, v, 1e-3, 1.0)
+        assert np.linalg.norm(Jf - Ja) <= 1e-6 * np.linalg.norm(Ja)
