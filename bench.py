@@ -32,7 +32,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 BYTES_PER_CELL_RESIDUAL = 56      # read E, T, z^3, b_E, b_T; write F_E, F_T (f64)
+BYTES_PER_CELL_JVP = 56           # read E, T, z^3, v_E, v_T; write 2 (f64)
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per residual launch on the ensemble workload from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch, FETCH scaled by the
+# factor a plain 2 GiB copy reads in the same run, WRITE by its own factor),
+# valid for the stencil source with this SHA-256 prefix; null otherwise.
+MEASURED_TRAFFIC = None
+
+
+def stencil_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1302_6303_amd", "csrc", "stencil.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def log(msg):
@@ -76,6 +90,8 @@ def run_solver(w, opts, steps, warmup, time_residual):
     u = compact_state(w)
     n = H.ncells
     H.set_fields(to_dev(u[:n]), to_dev(u[n:]), to_dev(w.compact(w.z)))
+    tuned = H.autotune(None)                   # tile shapes per patch-size class
+    log(f"tile shapes tuned for {tuned} patch-size classes")
     dt = list(w.dt)
     newton = krylov = 0
     tag = "mixed" if opts.precision == nrd.NRD_MIXED else "fp64"
@@ -106,6 +122,19 @@ def run_solver(w, opts, steps, warmup, time_residual):
     del H
     torch.cuda.empty_cache()
     return res
+
+
+def copy_calibration(nbytes=2 << 30):
+    """A plain device copy of known size (for scaling HBM byte counters)."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {nbytes} bytes read and written per copy, 3 copies")
+    del x, y
+    torch.cuda.empty_cache()
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -140,6 +169,8 @@ def main():
     ap.add_argument("--workload", default="ensemble")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 per-patch run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a 2 GiB device copy (reference for HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on exactly one GPU: the hot path is single-GPU "
@@ -154,12 +185,19 @@ def main():
                        a.steps, a.warmup, True)
     plain = None
     if not a.no_plain:
+        # per-patch launches need many workgroups per patch: the register
+        # plane-marching stencil with short z chunks suits them best
         plain = run_solver(w, nrd.default_options(precision=nrd.NRD_FP64,
-                                                  launch=nrd.NRD_PER_PATCH),
+                                                  launch=nrd.NRD_PER_PATCH, stencil=1),
                            a.steps, a.warmup, False)
     res_s = mixed["residual_ms_avg"] / 1e3
     gcells = ncomp / res_s / 1e9
     achieved = BYTES_PER_CELL_RESIDUAL * ncomp / res_s / 1e9
+    traffic = None
+    if (MEASURED_TRAFFIC and MEASURED_TRAFFIC["workload"] == a.workload
+            and MEASURED_TRAFFIC["stencil_sha256"] == stencil_source_hash()):
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+    jvp_s = mixed["jvp_ms_avg"] / 1e3
     out = {
         "metric": "residual Gcells/s (%HBM peak) + s/implicit step, mixed-batched vs FP64 plain",
         "value": round(gcells, 3),
@@ -177,11 +215,17 @@ def main():
                    "boxes": len(w.boxes), "cells": w.ncells(),
                    "composite_cells": ncomp,
                    "solver": "BDF1->BDF2, Newton rtol 1e-8, FGMRES(30), FAC V(1,0) + MG V(1,1)"},
-        "roofline": {"bound": "hbm", "kernel": "k_stencil<0> (residual)",
+        "roofline": {"bound": "hbm", "kernel": "k_stencil_s<0> (residual)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_cell": BYTES_PER_CELL_RESIDUAL,
+                     "bytes_per_launch": BYTES_PER_CELL_RESIDUAL * ncomp,
                      "avg_launch_ms": round(mixed["residual_ms_avg"], 4)},
+        "jvp_roofline": {"kernel": "k_stencil_s<1> (Jacobian action)",
+                         "achieved": round(BYTES_PER_CELL_JVP * ncomp / jvp_s / 1e9, 1),
+                         "unit": "GB/s",
+                         "frac": round(BYTES_PER_CELL_JVP * ncomp / jvp_s / 1e9 / HBM_PEAK_GBS, 4),
+                         "avg_launch_ms": round(mixed["jvp_ms_avg"], 4)},
         "mixed_batched": {k: (round(v, 5) if isinstance(v, float) else v)
                           for k, v in mixed.items()},
     }
@@ -192,6 +236,8 @@ def main():
                                                            mixed["s_per_step"], 3)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
+    if a.copy_calibration:
+        copy_calibration()
     print(json.dumps(out), flush=True)
 
 

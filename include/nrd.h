@@ -234,6 +234,22 @@ nrd_status nrd_adjoint_run(nrd_hierarchy* h, const double* dt, int32_t nsteps,
 nrd_status nrd_dot(nrd_hierarchy* h, const double* dev_x, const double* dev_y,
                    double* out);
 
+/* Tile-shape tuner of the batching machinery (patch table + tile lists).
+ * For every patch-size class (interior extents nx x ny x nz) the residual
+ * kernel is timed on that class's patches with each candidate plane-tile
+ * shape of the configured stencil variant (planes per tile, cells per plane
+ * run) and the fastest shape is used for that class from then on; results
+ * do not change (every shape evaluates the same face and cell formulas on
+ * the same operands).  cache_path (may be NULL) is a text file of earlier
+ * choices, one line "arch v<variant> <nx>x<ny>x<nz> <planes> <run> <us>" per
+ * class; classes found for this device architecture and variant are not
+ * timed again, newly timed ones are appended.  *timed_classes (may be NULL)
+ * returns how many classes were timed.  Needs a bound workspace and
+ * nrd_set_fields (NRD_ESTATE otherwise); synchronises the stream; drops
+ * captured graphs.  Variant 0 has nothing to tune (returns NRD_OK). */
+nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path,
+                        int32_t* timed_classes);
+
 /* Time of the last kernels of one operator, for measurement: launches of
  * the residual kernel family since the last call are timed with HIP events
  * on the library stream.  *ms_total / *count.  Synchronises. */

@@ -67,9 +67,11 @@ inline int64_t intersect(const int32_t alo[3], const int32_t ahi[3],
 
 }  // namespace
 
-int32_t default_zchunk(const int32_t n[3]) {
-    // short runs keep enough waves resident to hide load latency; the first
-    // face of each run is the only repeated face
+int32_t default_zchunk(const int32_t n[3], int32_t variant) {
+    // staged planes: long runs amortise the first plane's staging and its
+    // repeated z face; register-marching: short runs keep enough waves
+    // resident to hide load latency
+    if (variant == 3) return 16;
     return n[0] * n[1] >= 4096 ? 4 : 8;
 }
 
@@ -80,31 +82,40 @@ int32_t staged_len(const PatchInfo& p, int32_t s0, int32_t cnt) {
     return (lb % nx + 1) + sy * (lb / nx + 2) - g0 + 1;
 }
 
+bool patch_planes(const PatchInfo& p, int32_t b, int32_t kc, int32_t run, int32_t max_span,
+                  std::vector<STile>& out) {
+    const int32_t plane = p.n[0] * p.n[1];
+    const int32_t ch = std::max(1, kc);
+    int32_t r = run;
+    if (max_span > 0) {
+        // shorten the runs of this patch until every staged slice fits
+        for (;; r -= 64) {
+            if (r <= 0) return false;
+            bool fits = true;
+            for (int32_t s0 = 0; s0 < plane && fits; s0 += r)
+                fits = staged_len(p, s0, std::min(r, plane - s0)) <= max_span;
+            if (fits) break;
+        }
+    }
+    for (int32_t k0 = 0; k0 < p.n[2]; k0 += ch)
+        for (int32_t s0 = 0; s0 < plane; s0 += r)
+            out.push_back({b, p.prob, s0, std::min(r, plane - s0), k0, std::min(p.n[2], k0 + ch),
+                           {0, 0}});
+    return true;
+}
+
 bool build_planes(Tables& t, const std::vector<int32_t>& kc, int32_t run, int32_t max_span) {
+    return build_planes(t, kc, std::vector<int32_t>(t.nbox, run), max_span);
+}
+
+bool build_planes(Tables& t, const std::vector<int32_t>& kc, const std::vector<int32_t>& run,
+                  int32_t max_span) {
     t.stiles.clear();
     t.level_stile0.assign(t.nlev + 1, 0);
     t.patch_stile0.assign(t.nbox + 1, 0);
     std::vector<std::vector<STile>> per(t.nbox);
-    for (int b = 0; b < t.nbox; ++b) {
-        const PatchInfo& p = t.patches[b];
-        const int32_t plane = p.n[0] * p.n[1];
-        const int32_t ch = std::max(1, kc[b]);
-        int32_t r = run;
-        if (max_span > 0) {
-            // shorten the runs of this patch until every staged slice fits
-            for (;; r -= 64) {
-                if (r <= 0) return false;
-                bool fits = true;
-                for (int32_t s0 = 0; s0 < plane && fits; s0 += r)
-                    fits = staged_len(p, s0, std::min(r, plane - s0)) <= max_span;
-                if (fits) break;
-            }
-        }
-        for (int32_t k0 = 0; k0 < p.n[2]; k0 += ch)
-            for (int32_t s0 = 0; s0 < plane; s0 += r)
-                per[b].push_back({b, p.prob, s0, std::min(r, plane - s0), k0,
-                                  std::min(p.n[2], k0 + ch), {0, 0}});
-    }
+    for (int b = 0; b < t.nbox; ++b)
+        if (!patch_planes(t.patches[b], b, kc[b], run[b], max_span, per[b])) return false;
     for (int l = 0; l < t.nlev; ++l) {
         t.level_stile0[l] = (int32_t)t.stiles.size();
         for (int b = 0; b < t.nbox; ++b) {
@@ -517,7 +528,7 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
     t.level_tile0[t.nlev] = (int32_t)t.tiles.size();
     {
         std::vector<int32_t> kc(nbox);
-        for (int b = 0; b < nbox; ++b) kc[b] = default_zchunk(t.patches[b].n);
+        for (int b = 0; b < nbox; ++b) kc[b] = default_zchunk(t.patches[b].n, 1);
         build_planes(t, kc, 256);   // default stencil variant: plane marching
     }
     t.prob_vtile0.assign(nprob + 1, 0);
@@ -623,7 +634,7 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
             nmax = std::max(nmax, e);
         }
         t.bottom_off[p] = (int32_t)boff;
-        boff += (int64_t)nb * kBottomBand;
+        boff += (int64_t)nb * nb;
         t.bottom_max = std::max(t.bottom_max, nb);
         if (nb / nmax + 1 > kBottomBand) {
             msg = "coarsest multigrid grid too wide for the banded bottom solve";

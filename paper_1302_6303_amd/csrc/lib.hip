@@ -10,7 +10,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -73,20 +75,22 @@ struct nrd_hierarchy {
             rcells, ctype, shadows, shadow_src, coff, ps, active;
         size_t mg_box[kMaxMG], mg_tiles[kMaxMG], mg_box_of[kMaxMG], mg_smooth[kMaxMG],
             mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bottom_off, Lbuf, Xbuf;
-        size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, rb, gz3, V, Z;
+        size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, gz3, V, Z;
         size_t pc_D, pc_sigma, pc_e, pc_u, pc_r, pc_f, pc_tmp, pc_shadow;
         size_t mg_D[kMaxMG], mg_e[kMaxMG], mg_f[kMaxMG], mg_r[kMaxMG];
         size_t partial, dots, h1, h2, hn2, H, cs, sn, g, rho, vscale, y, kdim, coefA, coefB,
             minout, flag, ckpt, fdF, fdw, fdsum;
     } o;
     int32_t adjoint_slots = 0;
+    size_t stile_cap = 0;           // plane tiles the workspace holds (tuning scratch incl.)
+    bool fields_set = false;
     // host-side per-problem state
     std::vector<double> dt_prev;   // 0: no history (next step BDF1)
     std::vector<double> c0, alpha, beta, dt_cur;
     std::vector<ProbScalars> ps_host;
     bool step_ready = false;
     // device pointers
-    double *z, *z3, *cur, *prev, *udot, *bvec, *x, *F, *s, *w, *tmp, *tmp2, *rb, *gz3, *V, *Z;
+    double *z, *z3, *cur, *prev, *udot, *bvec, *x, *F, *s, *w, *tmp, *tmp2, *gz3, *V, *Z;
     double *partial, *dots, *h1, *h2, *hn2, *H, *cs, *sn, *g, *rho, *vscale, *y, *coefA, *coefB,
         *minout, *ckpt, *fdF, *fdw, *fdsum;
     const double* fd_base = nullptr;   // F at the Newton iterate (Jacobian-free mode)
@@ -163,7 +167,13 @@ static void layout(nrd_hierarchy* h) {
     const int m = h->m;
     o.patches = b.take(sizeof(PatchInfo) * t.patches.size());
     o.tiles = b.take(sizeof(Tile) * std::max<size_t>(1, t.tiles.size()));
-    o.stiles = b.take(sizeof(STile) * std::max<size_t>(1, t.stiles.size()));
+    // room for the current plane tiles plus any candidate shape the tuner
+    // times (at least one plane and 64 cells per tile)
+    size_t cap = t.stiles.size();
+    for (const PatchInfo& p : t.patches)
+        cap += (size_t)p.n[2] * (size_t)((p.n[0] * p.n[1] + 63) / 64);
+    h->stile_cap = std::max<size_t>(1, cap);
+    o.stiles = b.take(sizeof(STile) * h->stile_cap);
     o.vtiles = b.take(sizeof(Tile) * std::max<size_t>(1, t.vtiles.size()));
     o.prob_vtile0 = b.take(sizeof(int32_t) * t.prob_vtile0.size());
     o.gcopy = b.take(sizeof(GhostCopy) * std::max<size_t>(1, t.gcopy.size()));
@@ -195,7 +205,7 @@ static void layout(nrd_hierarchy* h) {
     for (int p = 0; p < nprob; ++p) {
         int64_t nb = 1;
         for (int d = 0; d < 3; ++d) nb *= t.probs[p].base_n[d] >> t.prob_mgdepth[p];
-        bsum += nb * kBottomBand;
+        bsum += nb * nb;
     }
     o.Lbuf = b.take(8);
     o.Xbuf = b.take(sizeof(double) * 2 * bsum);
@@ -212,7 +222,6 @@ static void layout(nrd_hierarchy* h) {
     o.w = b.take(8 * 2 * nl);
     o.tmp = b.take(8 * 2 * nl);
     o.tmp2 = b.take(8 * 2 * nl);
-    o.rb = b.take(8 * 2 * nl);
     o.gz3 = b.take(8 * nl);
     o.V = b.take(8 * 2 * nl * (size_t)(m + 1));
     o.Z = b.take(8 * 2 * nl * (size_t)m);
@@ -414,7 +423,6 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     h->w = h->at<double>(o.w);
     h->tmp = h->at<double>(o.tmp);
     h->tmp2 = h->at<double>(o.tmp2);
-    h->rb = h->at<double>(o.rb);
     h->gz3 = h->at<double>(o.gz3);
     h->V = h->at<double>(o.V);
     h->Z = h->at<double>(o.Z);
@@ -674,21 +682,19 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
     its.assign(np, 0);
     std::vector<double> beta0(np), rho(np), inv(np);
     std::vector<int32_t> kd(np);
-    // sol = 0
+    // sol = 0 (write-only pass over the active problems)
     h->D.active = h->active;
-    std::vector<double> zeros(np, 0.0);
-    HIPCHK(up(s, h->coefA, zeros));
-    scale_copy(h->D, s, rhs, h->coefA, sol);
+    combine(h->D, s, nullptr, 0, 0, h->coefA, 0, sol, 0, 1.0);
     std::vector<int32_t> todo = outer;
     for (int cycle = 0; cycle <= h->opt.gmres_maxrestarts; ++cycle) {
         // r = rhs - A sol  (first cycle: rhs)
-        double* r = h->w;
+        // r = rhs on the first cycle (read in place), else rhs - A sol in w
+        const double* r = rhs;
         h->host_active = todo;
         RCHK(upload_active(h));
         h->D.active = h->active;
-        if (cycle == 0) {
-            copy_interior(h->D, s, rhs, r);
-        } else {
+        if (cycle > 0) {
+            r = h->w;
             copy_interior(h->D, s, sol, h->tmp2);
             if (!transpose) {
                 op_jvp(h, u, h->tmp2, h->tmp, true);
@@ -696,11 +702,11 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
                 ghost_fill_d(h->D, s, h->tmp2, 2);
                 vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], u, h->tmp2, h->tmp, h->gz3);
             }
-            copy_interior(h->D, s, rhs, r);
+            copy_interior(h->D, s, rhs, h->w);
             std::vector<double> mone(np, -1.0), pone(np, 1.0);
             HIPCHK(up(s, h->coefA, mone));
             HIPCHK(up(s, h->coefB, pone));
-            axpby(h->D, s, h->coefA, h->tmp, h->coefB, r);
+            axpby(h->D, s, h->coefA, h->tmp, h->coefB, h->w);
         }
         std::vector<double> b2;
         {
@@ -889,14 +895,11 @@ static nrd_status newton(nrd_hierarchy* h, std::vector<nrd_step_stats>& st) {
         RCHK(upload_active(h));
         h->D.active = nullptr;
         pc_setup(h, h->x, true);              // x was prepared by the residual
-        // s = J^-1 (-F)
-        std::vector<double> mone(np, -1.0);
-        HIPCHK(up(s, h->coefA, mone));
+        // s = J^-1 F; the Newton step is -s
         h->D.active = h->active;
-        scale_copy(h->D, s, h->F, h->coefA, h->rb);
         std::vector<int32_t> its;
         h->fd_base = h->F;                    // F(x) for Jacobian-free products
-        rc = fgmres(h, h->x, h->rb, h->s, tol, its, false);
+        rc = fgmres(h, h->x, h->F, h->s, tol, its, false);
         h->fd_base = nullptr;
         if (rc) return rc;
         std::vector<int32_t> act = h->host_active;
@@ -909,8 +912,10 @@ static nrd_status newton(nrd_hierarchy* h, std::vector<nrd_step_stats>& st) {
         std::vector<double> lam(np, 1.0), mn(np);
         std::vector<int32_t> ok(np, 0);
         for (int p = 0; p < np; ++p) ok[p] = !act[p];
+        std::vector<double> mlam(np);
         for (int cut = 0; cut <= 30; ++cut) {
-            HIPCHK(up(s, h->coefA, lam));
+            for (int p = 0; p < np; ++p) mlam[p] = -lam[p];      // step = -lam s
+            HIPCHK(up(s, h->coefA, mlam));
             h->D.active = h->active;
             min_positive(h->D, s, h->x, h->s, h->coefA, h->partial, h->minout);
             HIPCHK(hipMemcpyAsync(mn.data(), h->minout, 8 * np, hipMemcpyDeviceToHost, s));
@@ -936,7 +941,8 @@ static nrd_status newton(nrd_hierarchy* h, std::vector<nrd_step_stats>& st) {
         for (int p = 0; p < np; ++p) h->host_active[p] = act[p] && !failed[p];
         RCHK(upload_active(h));
         std::vector<double> one(np, 1.0);
-        HIPCHK(up(s, h->coefA, lam));
+        for (int p = 0; p < np; ++p) mlam[p] = -lam[p];
+        HIPCHK(up(s, h->coefA, mlam));
         HIPCHK(up(s, h->coefB, one));
         h->D.active = h->active;
         axpby(h->D, s, h->coefA, h->s, h->coefB, h->x);
@@ -1194,7 +1200,7 @@ void nrd_default_options(nrd_options* o) {
     o->gmres_maxrestarts = 10;
     o->mg_nu_pre = 1;
     o->mg_nu_post = 1;
-    o->stencil = 1;
+    o->stencil = 3;
     o->bdf_max_order = 2;
 }
 
@@ -1249,7 +1255,8 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
         if (h->opt.stencil >= 1 || h->opt.zchunk > 0) {
             std::vector<int32_t> kc(h->t.nbox);
             for (int b = 0; b < h->t.nbox; ++b)
-                kc[b] = h->opt.zchunk > 0 ? h->opt.zchunk : default_zchunk(h->t.patches[b].n);
+                kc[b] = h->opt.zchunk > 0 ? h->opt.zchunk
+                                          : default_zchunk(h->t.patches[b].n, h->opt.stencil);
             const int st = h->opt.stencil;
             const bool ok = build_planes(h->t, kc, st == 2 ? 4 * 63 : (st == 3 ? kStageCells : 256),
                                          st == 3 ? kStageLen : 0);
@@ -1347,6 +1354,7 @@ nrd_status nrd_set_fields(nrd_hierarchy* h, const double* E, const double* T, co
     fill_native(s, h->udot, 2 * h->t.nl, 0.0);
     std::fill(h->dt_prev.begin(), h->dt_prev.end(), 0.0);
     h->step_ready = false;
+    h->fields_set = true;
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
     return NRD_OK;
@@ -1445,6 +1453,153 @@ nrd_status nrd_adjoint_run(nrd_hierarchy* h, const double* dt, int32_t nsteps, i
     NEED_BOUND(h);
     if (!dt || !gz) return fail(NRD_EINVAL, "NULL argument");
     return adjoint_run(h, dt, nsteps, every, dJdE, gz);
+}
+
+// ---------------------------------------------------------------------------
+// tile-shape tuner: per patch-size class, the plane-tile shape (planes per
+// tile, cells per plane run) of the plane stencils, chosen by timing the
+// residual kernel on that class's patches with every candidate shape
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct ClassKey {
+    int32_t n[3];
+    bool operator<(const ClassKey& o) const {
+        return std::lexicographical_compare(n, n + 3, o.n, o.n + 3);
+    }
+};
+
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+}  // namespace
+
+nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed_classes) {
+    NEED_BOUND(h);
+    if (timed_classes) *timed_classes = 0;
+    const int var = h->opt.stencil;
+    if (var == 0) return NRD_OK;                 // one-cell tiles: nothing to choose
+    if (!h->fields_set) return fail(NRD_ESTATE, "nrd_autotune needs nrd_set_fields first");
+    Tables& t = h->t;
+    hipStream_t s = h->stream;
+    const int32_t span = var == 3 ? kStageLen : 0;
+    std::vector<std::pair<int32_t, int32_t>> cand;           // (planes, run)
+    if (var == 3) {
+        for (int kc : {4, 8, 16, 32})
+            for (int run : {256, kStageCells}) cand.push_back({kc, run});
+    } else {
+        for (int kc : {2, 4, 8, 16}) cand.push_back({kc, var == 2 ? 4 * 63 : 256});
+    }
+    std::map<ClassKey, std::vector<int32_t>> cls;
+    for (int b = 0; b < t.nbox; ++b) {
+        ClassKey k;
+        std::copy(t.patches[b].n, t.patches[b].n + 3, k.n);
+        cls[k].push_back(b);
+    }
+    const std::string arch = device_arch();
+    std::map<ClassKey, std::pair<int32_t, int32_t>> pick;
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string a, v, dims;
+            int32_t kc = 0, run = 0;
+            if (!(ls >> a >> v >> dims >> kc >> run)) continue;
+            ClassKey k;
+            if (a != arch || v != "v" + std::to_string(var) ||
+                std::sscanf(dims.c_str(), "%dx%dx%d", &k.n[0], &k.n[1], &k.n[2]) != 3 ||
+                kc <= 0 || run <= 0)
+                continue;
+            pick[k] = {kc, run};
+        }
+    }
+    // timing scratch: the tile region beyond the current tiles
+    STile* scratch = h->at<STile>(h->o.stiles) + t.stiles.size();
+    const size_t room = h->stile_cap - t.stiles.size();
+    h->D.active = nullptr;
+    prepare_state(h, h->cur);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    std::ofstream out;
+    if (cache_path) out.open(cache_path, std::ios::app);
+    nrd_status rc = NRD_OK;
+    for (auto& kv : cls) {
+        if (pick.count(kv.first)) continue;
+        double best = 1e300;
+        std::pair<int32_t, int32_t> choice{0, 0};
+        for (auto [kc, run] : cand) {
+            std::vector<STile> tl;
+            bool ok = true;
+            for (int b : kv.second)
+                ok = ok && patch_planes(t.patches[b], b, kc, run, span, tl);
+            if (!ok || tl.empty() || tl.size() > room) continue;
+            if (hipMemcpyAsync(scratch, tl.data(), sizeof(STile) * tl.size(),
+                               hipMemcpyHostToDevice, s) != hipSuccess) {
+                rc = fail(NRD_EDEVICE, "tile upload failed");
+                break;
+            }
+            Dev Dt = h->D;
+            Dt.stiles = scratch;
+            residual(Dt, s, 0, (int)tl.size(), h->cur, h->bvec, h->tmp);    // warm-up
+            double ms_min = 1e300;
+            for (int rep = 0; rep < 3; ++rep) {
+                (void)hipEventRecord(e0, s);
+                residual(Dt, s, 0, (int)tl.size(), h->cur, h->bvec, h->tmp);
+                (void)hipEventRecord(e1, s);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                ms_min = std::min(ms_min, (double)ms);
+            }
+            if (ms_min < best) {
+                best = ms_min;
+                choice = {kc, run};
+            }
+        }
+        if (rc) break;
+        if (choice.first == 0) continue;                 // keep the default shape
+        pick[kv.first] = choice;
+        if (timed_classes) ++*timed_classes;
+        if (out)
+            out << arch << " v" << var << " " << kv.first.n[0] << "x" << kv.first.n[1] << "x"
+                << kv.first.n[2] << " " << choice.first << " " << choice.second << " "
+                << best * 1e3 << "\n";
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    HIPCHK(hipGetLastError());
+    // apply: rebuild the plane tiles with the chosen shapes
+    std::vector<int32_t> kc(t.nbox), run(t.nbox);
+    for (int b = 0; b < t.nbox; ++b) {
+        ClassKey k;
+        std::copy(t.patches[b].n, t.patches[b].n + 3, k.n);
+        auto it = pick.find(k);
+        kc[b] = it != pick.end() ? it->second.first : default_zchunk(t.patches[b].n, var);
+        run[b] = it != pick.end() ? it->second.second
+                                  : (var == 2 ? 4 * 63 : (var == 3 ? kStageCells : 256));
+    }
+    Tables trial = t;
+    if (!build_planes(trial, kc, run, span) || trial.stiles.size() > h->stile_cap)
+        return fail(NRD_EINVAL, "tuned tile shapes do not fit");
+    t.stiles.swap(trial.stiles);
+    t.level_stile0.swap(trial.level_stile0);
+    t.patch_stile0.swap(trial.patch_stile0);
+    HIPCHK(up(s, h->ws + h->o.stiles, t.stiles));
+    for (int l = 0; l <= t.nlev; ++l) h->D.level_stile0[l] = t.level_stile0[l];
+    h->drop_graphs();                               // captured launches used the old tiles
+    HIPCHK(hipStreamSynchronize(s));
+    return NRD_OK;
 }
 
 nrd_status nrd_dot(nrd_hierarchy* h, const double* x, const double* y, double* out) {

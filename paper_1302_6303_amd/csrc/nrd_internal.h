@@ -146,11 +146,11 @@ struct Tables {
     std::vector<int32_t> prob_mgdepth;       // number of grids below level 0
     int32_t bottom_max = 0;                  // max bottom cells per problem
     std::vector<int32_t> bottom_off;         // per problem, in units of
-                                             // cells x kBottomBand doubles
+                                             // cells^2 doubles
 };
 
-// Band storage per row of the coarsest-grid Cholesky factor.
-constexpr int32_t kBottomBand = 32;
+// Band storage per row of the coarsest-grid Cholesky factor (b + 1).
+constexpr int32_t kBottomBand = 26;
 
 // Staged-plane stencil tiles: at most kStageCells cells of a plane per tile,
 // whose ghosted-plane slice (the run plus its x / y neighbours) holds at most
@@ -159,7 +159,7 @@ constexpr int32_t kStageCells = 512;
 constexpr int32_t kStageLen = 768;
 
 // Plane-marching tiles: planes per tile (z chunk) of each patch.
-int32_t default_zchunk(const int32_t n[3]);
+int32_t default_zchunk(const int32_t n[3], int32_t variant);
 // Length of the ghosted-plane slice that covers cells [s0, s0 + cnt) of a
 // plane of patch p and their x / y neighbours.
 int32_t staged_len(const PatchInfo& p, int32_t s0, int32_t cnt);
@@ -168,6 +168,11 @@ int32_t staged_len(const PatchInfo& p, int32_t s0, int32_t cnt);
 // patch's runs until every staged slice fits.  False if none fits.
 bool build_planes(Tables& t, const std::vector<int32_t>& kc, int32_t run,
                   int32_t max_span = 0);
+// Per-patch runs; patch_planes appends one patch's tiles (false: no run fits).
+bool build_planes(Tables& t, const std::vector<int32_t>& kc, const std::vector<int32_t>& run,
+                  int32_t max_span);
+bool patch_planes(const PatchInfo& p, int32_t b, int32_t kc, int32_t run, int32_t max_span,
+                  std::vector<STile>& out);
 
 // Builds all tables; returns NRD_OK or an error with msg set.
 nrd_status build_tables(const nrd_problem* probs, int32_t nprob,

@@ -20,7 +20,7 @@ struct MGDev {
     const int32_t* bottom_probs[kMaxMG] = {};    // problems whose coarsest
     const int32_t* bottom_boxes[kMaxMG] = {};    // grid is g
     int nbottom[kMaxMG] = {};
-    const int64_t* bottom_off = nullptr;         // [nprob] in cells x kBottomBand units
+    const int64_t* bottom_off = nullptr;         // [nprob] in cells^2 units
     double* Lbuf = nullptr;
     double* Xbuf = nullptr;
 };

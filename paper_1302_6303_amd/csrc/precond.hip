@@ -36,14 +36,16 @@ __device__ __forceinline__ int nat(const PatchInfo& p, int i, int j, int k) {
 // snapshot: D_E, D_T on every face of every patch, sigma per cell
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void face_D(double Ea, double Eb, double Ta, double Tb,
-                                       double za, double zb, double h, double kappa,
-                                       double lam, double& DE, double& DT) {
-    const double Tf = 0.5 * (Ta + Tb);
-    const double Tf3 = Tf * Tf * Tf;
-    const double S = Ea + Eb;
+// Face coefficients in the preconditioner's precision (the inputs are
+// rounded to PT first; in float64 mode this is the float64 formula).
+template <typename PT>
+__device__ __forceinline__ void face_D(PT Ea, PT Eb, PT Ta, PT Tb, PT za, PT zb, PT h, PT kappa,
+                                       PT lam, PT& DE, PT& DT) {
+    const PT Tf = PT(0.5) * (Ta + Tb);
+    const PT Tf3 = Tf * Tf * Tf;
+    const PT S = Ea + Eb;
     // D_h / (1 + lam D_h g) with D_h = 2 Tf^3 / (3 Zf), g = 2|dE| / (h S)
-    DE = 2.0 * Tf3 * h * S / (3.0 * (za + zb) * h * S + 4.0 * lam * Tf3 * fabs(Eb - Ea));
+    DE = PT(2) * Tf3 * h * S / (PT(3) * (za + zb) * h * S + PT(4) * lam * Tf3 * fabs(Eb - Ea));
     DT = kappa * Tf * Tf * sqrt(Tf);
 }
 
@@ -61,27 +63,30 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(
     coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
     const int c = nat(p, id[0], id[1], id[2]);
     const int st[3] = {1, p.sy, p.sz};
-    const double E = u[c], T = u[c + nl], z = z3[c];
-    sigma[c] = (PT)(z / (T * T * T));
+    const PT E = (PT)u[c], T = (PT)u[c + nl], z = (PT)z3[c];
+    const PT kappa = (PT)q.kappa, lam = (PT)q.lam;
+    sigma[c] = z / (T * T * T);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
+        const PT h = (PT)p.h[d];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             if (s == 1 && id[d] != p.n[d] - 1) continue;     // high face owned by c+st
             const int slot = s ? c + st[d] : c;
-            double DE, DT;
+            PT DE, DT;
             if ((id[d] == (s ? p.n[d] - 1 : 0)) && ((p.phys >> (2 * d + s)) & 1)) {
-                DT = 0.0;
-                DE = ((p.robin >> (2 * d + s)) & 1) ? T * T * T / (3.0 * z) : 0.0;
+                DT = PT(0);
+                DE = ((p.robin >> (2 * d + s)) & 1) ? T * T * T / (PT(3) * z) : PT(0);
             } else {
                 const int nb = s ? c + st[d] : c - st[d];
+                const PT En = (PT)u[nb], Tn = (PT)u[nb + nl], zn = (PT)z3[nb];
                 if (s)
-                    face_D(E, u[nb], T, u[nb + nl], z, z3[nb], p.h[d], q.kappa, q.lam, DE, DT);
+                    face_D<PT>(E, En, T, Tn, z, zn, h, kappa, lam, DE, DT);
                 else
-                    face_D(u[nb], E, u[nb + nl], T, z3[nb], z, p.h[d], q.kappa, q.lam, DE, DT);
+                    face_D<PT>(En, E, Tn, T, zn, z, h, kappa, lam, DE, DT);
             }
-            Dface[(0 * 3 + d) * nl + slot] = (PT)DE;
-            Dface[(1 * 3 + d) * nl + slot] = (PT)DT;
+            Dface[(0 * 3 + d) * nl + slot] = DE;
+            Dface[(1 * 3 + d) * nl + slot] = DT;
         }
     }
 }
@@ -129,43 +134,80 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarsen(
 //   Marshak faces (E): diag += 2 beta D_b / ((4 D_b + h) h)
 // ---------------------------------------------------------------------------
 
-template <typename PT, int MODE>   // MODE 0: RBGS colour (ZERO start) 1: colour 2: residual
-__device__ __forceinline__ void level_cell(const PatchInfo& p, const int id[3], int c,
-                                          int fld, const PT* __restrict__ D, int64_t nl,
-                                          double beta, const uint8_t* __restrict__ ctype,
-                                          const PT* __restrict__ e, PT& diag, PT& nsum) {
+// Both fields of one cell.  Faces are classified without branching on the
+// common path: an interior (or sibling) face contributes a = beta D / h^2 to
+// the diagonal and a e_nb to the neighbour sum; a physical face contributes
+// nothing (plus the Marshak term for E on a Robin face); a coarse-fine face
+// contributes 2/3 a to the diagonal only.  Neighbour values are loaded
+// unconditionally (ghost slots always hold finite values).
+template <typename PT, int MODE>   // MODE 0: RBGS colour (zero start) 1: colour 2: residual
+__device__ __forceinline__ void level_update(const PatchInfo& p, const int id[3], double beta,
+                                             const uint8_t* __restrict__ ctype,
+                                             const PT* __restrict__ D,
+                                             const PT* __restrict__ f, PT* __restrict__ e,
+                                             PT* __restrict__ r, int64_t nl) {
+    const int c = nat(p, id[0], id[1], id[2]);
     const int st[3] = {1, p.sy, p.sz};
-    PT dg = PT(1);
-    PT ns = PT(0);
+    PT bh2[3];
+    bool ph[6], cf[6];
+    bool any_robin = false;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const PT bh2 = (PT)(beta * p.ih[d] * p.ih[d]);
-        const PT* Dd = D + (fld * 3 + d) * nl;
+        bh2[d] = (PT)(beta * p.ih[d] * p.ih[d]);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            const int slot = s ? c + st[d] : c;
-            const PT a = bh2 * Dd[slot];
-            const int nb = s ? c + st[d] : c - st[d];
+            const int fc = 2 * d + s;
             const bool edge = id[d] == (s ? p.n[d] - 1 : 0);
-            if (edge && ((p.phys >> (2 * d + s)) & 1)) {
-                if (fld == 0 && ((p.robin >> (2 * d + s)) & 1)) {
-                    const double Db = (double)Dd[slot];
-                    dg += (PT)(2.0 * beta * Db / ((4.0 * Db + p.h[d]) * p.h[d]));
-                }
-                continue;
-            }
-            if (edge && ctype[nb] == GK_CF) {
-                dg += PT(2.0 / 3.0) * a;
-                continue;
-            }
-            dg += a;
-            if (MODE != 0) ns += a * e[nb];
+            ph[fc] = edge && ((p.phys >> fc) & 1);
+            cf[fc] = false;
+            if (edge && !ph[fc]) cf[fc] = ctype[s ? c + st[d] : c - st[d]] == GK_CF;
+            any_robin |= ph[fc] && ((p.robin >> fc) & 1);
         }
     }
-    diag = dg;
-    nsum = ns;
+#pragma unroll
+    for (int fld = 0; fld < 2; ++fld) {
+        const PT* ef = e + fld * nl;
+        PT dg = PT(1), ns = PT(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const PT* Dd = D + (fld * 3 + d) * nl;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int fc = 2 * d + s;
+                const PT a = bh2[d] * Dd[s ? c + st[d] : c];
+                const PT enb = (MODE == 0) ? PT(0) : ef[s ? c + st[d] : c - st[d]];
+                const bool open = !(ph[fc] || cf[fc]);
+                dg += open ? a : (cf[fc] ? PT(2.0 / 3.0) * a : PT(0));
+                ns += open ? a * enb : PT(0);
+            }
+        }
+        if (fld == 0 && any_robin) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const int fc = 2 * d + s;
+                    if (ph[fc] && ((p.robin >> fc) & 1)) {
+                        const PT Db = D[d * nl + (s ? c + st[d] : c)];
+                        const PT h = (PT)p.h[d];
+                        dg += PT(2) * (PT)beta * Db / ((PT(4) * Db + h) * h);
+                    }
+                }
+        }
+        const int64_t cfi = fld * nl + c;
+        if (MODE == 2)
+            r[cfi] = f[cfi] - (dg * ef[c] - ns);
+        else
+            e[cfi] = (f[cfi] + ns) / dg;
+    }
 }
 
+// MODE 2 (residual): kBlock threads, one per cell of the tile.
+// MODE 0 / 1 (one colour): kBlock / 2 threads.  When the patch's x extent is
+// even, rows start at even linear indices, so every pair (2q, 2q + 1) of a
+// tile lies in one row and holds exactly one cell of each colour: thread q
+// updates that cell and every lane does useful work.  Otherwise each thread
+// tests two cells.
 template <typename PT, int MODE>
 __global__ __launch_bounds__(kBlock) void k_level(
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
@@ -173,22 +215,28 @@ __global__ __launch_bounds__(kBlock) void k_level(
     const PT* __restrict__ D, const PT* __restrict__ f, PT* __restrict__ e,
     PT* __restrict__ r, int colour, int64_t nl) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
-    if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
-    int id[3];
-    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
-    if (MODE != 2 && (((id[0] + id[1] + id[2] + p.lo[0] + p.lo[1] + p.lo[2]) & 1) != colour))
-        return;
-    const int c = nat(p, id[0], id[1], id[2]);
     const double beta = ps[t.prob].beta;
-    for (int fld = 0; fld < 2; ++fld) {
-        PT dg, ns;
-        level_cell<PT, MODE>(p, id, c, fld, D, nl, beta, ctype, e + fld * nl, dg, ns);
-        const int64_t cf = fld * nl + c;
-        if (MODE == 2)
-            r[cf] = f[cf] - (dg * e[cf] - ns);
-        else
-            e[cf] = (f[cf] + ns) / dg;
+    int id[3];
+    if (MODE == 2) {
+        if ((int)threadIdx.x >= t.count) return;
+        coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+        level_update<PT, MODE>(p, id, beta, ctype, D, f, e, r, nl);
+        return;
+    }
+    const int lo = p.lo[0] + p.lo[1] + p.lo[2];
+    if ((p.n[0] & 1) == 0) {
+        const int a = 2 * (int)threadIdx.x;          // tile starts are even
+        if (a >= t.count) return;
+        coords(p, t.start + a, id[0], id[1], id[2]);  // id[0] even
+        id[0] += (colour + id[1] + id[2] + lo) & 1;
+        level_update<PT, MODE>(p, id, beta, ctype, D, f, e, r, nl);
+    } else {
+        for (int q = threadIdx.x; q < t.count; q += kBlock / 2) {
+            coords(p, t.start + q, id[0], id[1], id[2]);
+            if (((id[0] + id[1] + id[2] + lo) & 1) != colour) continue;
+            level_update<PT, MODE>(p, id, beta, ctype, D, f, e, r, nl);
+        }
     }
 }
 
@@ -416,15 +464,17 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(
 }
 
 // ---------------------------------------------------------------------------
-// bottom solve (float64): the coarsest grid's operator is SPD and banded;
-// it is factored as L L^T (band Cholesky) once per setup and solved by two
-// banded triangular sweeps per application.  One wavefront per (problem,
-// field).  Cells are numbered with the longest axis slowest, so the band
-// half-width b = N / n_max <= N^(2/3) <= 25 for N <= 128 cells.
+// bottom solve (float64).  The coarsest grid's operator is SPD and banded:
+// setup factors it as L L^T (band Cholesky; cells numbered with the longest
+// axis slowest, so the half-bandwidth b = N / n_max <= N^(2/3) <= 25 for
+// N <= 128 cells) and forms the explicit inverse column by column with two
+// banded triangular solves (one thread per column); apply is then a dense
+// matrix-vector product with one thread per row.  One workgroup per
+// (problem, field).
 // ---------------------------------------------------------------------------
 
 constexpr int kBottomMax = 128;     // cells of the coarsest grid
-constexpr int kBand = kBottomBand; // band storage per row (b + 1 <= 26)
+constexpr int kBandLd = kBottomBand; // band row stride in LDS (b + 1 <= 26)
 
 struct BottomOrder {
     int a[3];      // axes, fastest first
@@ -432,46 +482,50 @@ struct BottomOrder {
     int b;         // half-bandwidth
 };
 
+// (written with selects only, so that nothing is indexed at run time)
 __device__ __forceinline__ BottomOrder bottom_order(const PatchInfo& p) {
     BottomOrder o;
-    int slow = 0;
-    if (p.n[1] > p.n[slow]) slow = 1;
-    if (p.n[2] > p.n[slow]) slow = 2;
-    int q = 0;
-    for (int d = 0; d < 3; ++d)
-        if (d != slow) o.a[q++] = d;
+    const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
+    const int slow = (n2 > n0 && n2 > n1) ? 2 : ((n1 > n0) ? 1 : 0);
+    o.a[0] = slow == 0 ? 1 : 0;
+    o.a[1] = slow == 2 ? 1 : 2;
     o.a[2] = slow;
-    o.st[o.a[0]] = 1;
-    o.st[o.a[1]] = p.n[o.a[0]];
-    o.st[o.a[2]] = p.n[o.a[0]] * p.n[o.a[1]];
-    o.b = o.st[o.a[2]];
+    const int na0 = slow == 0 ? n1 : n0;                  // extent of axis a[0]
+    const int na1 = slow == 2 ? n1 : n2;                  // extent of axis a[1]
+    o.st[0] = slow == 0 ? na0 * na1 : 1;
+    o.st[1] = slow == 1 ? na0 * na1 : (slow == 0 ? 1 : na0);
+    o.st[2] = slow == 2 ? na0 * na1 : na0;
+    o.b = na0 * na1;
     return o;
 }
 
 __device__ __forceinline__ void bottom_coords(const PatchInfo& p, const BottomOrder& o, int lin,
                                               int id[3]) {
-    id[o.a[0]] = lin % p.n[o.a[0]];
-    const int r = lin / p.n[o.a[0]];
-    id[o.a[1]] = r % p.n[o.a[1]];
-    id[o.a[2]] = r / p.n[o.a[1]];
+    const int n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
+    const int slow = o.a[2];
+    const int na0 = slow == 0 ? n1 : n0;
+    const int na1 = slow == 2 ? n1 : n2;
+    const int c0 = lin % na0;
+    const int r = lin / na0;
+    const int c1 = r % na1;
+    const int c2 = r / na1;
+    // axis a[0] gets c0, a[1] gets c1, a[2] (slow) gets c2
+    id[0] = slow == 0 ? c2 : c0;
+    id[1] = slow == 1 ? c2 : (slow == 0 ? c0 : c1);
+    id[2] = slow == 2 ? c2 : c1;
 }
 
-__device__ __forceinline__ double wave_sum64(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// X block of (problem, field): N rows of kBand values, row i holds
-// L_ii at [0] and L(i, i - d) at [d], 1 <= d <= b.
+// X block of (problem, field): the N x N inverse, row-major, in the band
+// numbering.
 template <typename PT>
-__global__ __launch_bounds__(64) void k_bottom_setup(
+__global__ __launch_bounds__(kBottomMax) void k_bottom_setup(
     const int32_t* __restrict__ probs, const int32_t* __restrict__ boxes,
     const PatchInfo* __restrict__ P, const ProbScalars* __restrict__ ps,
     const PT* __restrict__ D, int64_t nl, const int64_t* __restrict__ boff,
     double* __restrict__ X) {
-    __shared__ double A[kBottomMax * kBand];     // A(i, i - d) at [i kBand + d]
-    __shared__ double Ld[kBottomMax];
+    __shared__ double A[kBottomMax * kBandLd];   // A(i, i - d) at [i kBandLd + d]
+    __shared__ double Ld[kBottomMax];            // diagonal of L
+    __shared__ double W[kBottomMax * kBottomMax];   // column j of the inverse at [i N + j]
     const int pi = blockIdx.x >> 1;
     const int fld = blockIdx.x & 1;
     const int prob = probs[pi];
@@ -479,18 +533,21 @@ __global__ __launch_bounds__(64) void k_bottom_setup(
     const double beta = ps[prob].beta;
     const int N = p.ncell;                      // <= kBottomMax (checked on the host)
     const BottomOrder o = bottom_order(p);
-    const int b = o.b;                          // < kBand (checked on the host)
-    for (int i = threadIdx.x; i < N * kBand; i += blockDim.x) A[i] = 0.0;
+    const int b = o.b;                          // < kBandLd (checked on the host)
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N * kBandLd; i += blockDim.x) A[i] = 0.0;
     __syncthreads();
     const int st[3] = {1, p.sy, p.sz};
-    for (int lin = threadIdx.x; lin < N; lin += blockDim.x) {
+    for (int lin = tid; lin < N; lin += blockDim.x) {
         int id[3];
         bottom_coords(p, o, lin, id);
         const int c = nat(p, id[0], id[1], id[2]);
         double dg = 1.0;
+#pragma unroll
         for (int d = 0; d < 3; ++d) {
             const double bh2 = beta * p.ih[d] * p.ih[d];
             const PT* Dd = D + (fld * 3 + d) * nl;
+#pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const double Dv = (double)Dd[s ? c + st[d] : c];
                 if (id[d] == (s ? p.n[d] - 1 : 0)) {        // grid covers the domain
@@ -502,70 +559,88 @@ __global__ __launch_bounds__(64) void k_bottom_setup(
                 dg += a;
                 // the lower neighbour's entry; the upper one is that
                 // neighbour's lower entry (same face, same coefficient)
-                if (s == 0) A[lin * kBand + o.st[d]] = -a;
+                if (s == 0) A[lin * kBandLd + o.st[d]] = -a;
             }
         }
-        A[lin * kBand] = dg;
+        A[lin * kBandLd] = dg;
+    }
+    // this thread's (r, q) pairs of the trailing-update triangle 1 <= q <= r <= b
+    int pr[3], pq[3];
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+        const int idx = tid + w * kBottomMax;
+        int r = 1;
+        while (r * (r + 1) / 2 <= idx) ++r;
+        pr[w] = (idx < b * (b + 1) / 2) ? r : kBottomMax;   // out of range: never used
+        pq[w] = idx - r * (r - 1) / 2 + 1;
     }
     __syncthreads();
-    // right-looking band Cholesky: column k, then the trailing b x b block
+    // right-looking band Cholesky: scale column k, update the trailing triangle
     for (int k = 0; k < N; ++k) {
-        const double dkk = sqrt(A[k * kBand]);
+        const double dkk = sqrt(A[k * kBandLd]);
+        const double inv = 1.0 / dkk;
         const int m = min(b, N - 1 - k);
-        for (int t = threadIdx.x + 1; t <= m; t += blockDim.x) A[(k + t) * kBand + t] /= dkk;
-        if (threadIdx.x == 0) Ld[k] = dkk;
+        if (tid >= 1 && tid <= m) A[(k + tid) * kBandLd + tid] *= inv;
+        if (tid == 0) Ld[k] = dkk;
         __syncthreads();
-        for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-            const int r = idx / m + 1, q = idx % m + 1;
-            if (q > r) continue;
-            A[(k + r) * kBand + (r - q)] -= A[(k + r) * kBand + r] * A[(k + q) * kBand + q];
+#pragma unroll
+        for (int w = 0; w < 3; ++w) {
+            const int r = pr[w], q = pq[w];
+            if (r <= m)
+                A[(k + r) * kBandLd + (r - q)] -= A[(k + r) * kBandLd + r] * A[(k + q) * kBandLd + q];
         }
         __syncthreads();
     }
-    double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * kBand;
-    for (int i = threadIdx.x; i < N * kBand; i += blockDim.x)
-        Xi[i] = (i % kBand == 0) ? Ld[i / kBand] : A[i];
+    // inverse: thread j solves L L^T x = e_j into column j of W
+    const int j = tid;
+    if (j < N) {
+        for (int i = 0; i < j; ++i) W[i * N + j] = 0.0;
+        for (int i = j; i < N; ++i) {               // L y = e_j
+            double acc = (i == j) ? 1.0 : 0.0;
+            const int lmax = min(b, i - j);
+            for (int l = 1; l <= lmax; ++l) acc -= A[i * kBandLd + l] * W[(i - l) * N + j];
+            W[i * N + j] = acc / Ld[i];
+        }
+        for (int i = N - 1; i >= 0; --i) {          // L^T x = y
+            double acc = W[i * N + j];
+            const int lmax = min(b, N - 1 - i);
+            for (int l = 1; l <= lmax; ++l) acc -= A[(i + l) * kBandLd + l] * W[(i + l) * N + j];
+            W[i * N + j] = acc / Ld[i];
+        }
+    }
+    __syncthreads();
+    double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * N;
+    for (int i = tid; i < N * N; i += blockDim.x) Xi[i] = W[i];
 }
 
 template <typename PT>
-__global__ __launch_bounds__(64) void k_bottom_apply(
+__global__ __launch_bounds__(kBlock) void k_bottom_apply(
     const int32_t* __restrict__ probs, const int32_t* __restrict__ boxes,
     const PatchInfo* __restrict__ P, const int64_t* __restrict__ boff,
     const double* __restrict__ X, const PT* __restrict__ f, PT* __restrict__ e,
     int64_t nl) {
-    __shared__ double L[kBottomMax * kBand];
-    __shared__ double y[kBottomMax];
+    __shared__ double fv[kBottomMax];
     const int pi = blockIdx.x >> 1;
     const int fld = blockIdx.x & 1;
     const int prob = probs[pi];
     const PatchInfo& p = P[boxes[pi]];
     const int N = p.ncell;
     const BottomOrder o = bottom_order(p);
-    const int b = o.b;
-    const double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * kBand;
-    for (int i = threadIdx.x; i < N * kBand; i += blockDim.x) L[i] = Xi[i];
+    const double* Xi = X + boff[prob] * 2 + (int64_t)fld * N * N;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         int id[3];
         bottom_coords(p, o, j, id);
-        y[j] = (double)f[fld * nl + nat(p, id[0], id[1], id[2])];
+        fv[j] = (double)f[fld * nl + nat(p, id[0], id[1], id[2])];
     }
     __syncthreads();
-    const int l = threadIdx.x + 1;              // lane l handles band offset l
-    for (int i = 0; i < N; ++i) {               // L y = f
-        const double sum = wave_sum64(l <= min(b, i) ? L[i * kBand + l] * y[i - l] : 0.0);
-        if (threadIdx.x == 0) y[i] = (y[i] - sum) / L[i * kBand];
-        __syncthreads();
-    }
-    for (int i = N - 1; i >= 0; --i) {          // L^T x = y
-        const double sum =
-            wave_sum64(l <= min(b, N - 1 - i) ? L[(i + l) * kBand + l] * y[i + l] : 0.0);
-        if (threadIdx.x == 0) y[i] = (y[i] - sum) / L[i * kBand];
-        __syncthreads();
-    }
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    // X is symmetric: row i = column i, read with consecutive threads on
+    // consecutive addresses
+    for (int row = threadIdx.x; row < N; row += blockDim.x) {
+        double acc = 0.0;
+        for (int jj = 0; jj < N; ++jj) acc += Xi[(int64_t)jj * N + row] * fv[jj];
         int id[3];
-        bottom_coords(p, o, j, id);
-        e[fld * nl + nat(p, id[0], id[1], id[2])] = (PT)y[j];
+        bottom_coords(p, o, row, id);
+        e[fld * nl + nat(p, id[0], id[1], id[2])] = (PT)acc;
     }
 }
 
@@ -716,7 +791,7 @@ void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
         const PT* Dg = (g == 0) ? Dface : mg.Dg[g];
         const int64_t nlg = (g == 0) ? d.nl : mg.len[g];
         const PatchInfo* Pg = (g == 0) ? d.patches : mg.box[g];
-        k_bottom_setup<PT><<<2 * mg.nbottom[g], 64, 0, s>>>(
+        k_bottom_setup<PT><<<2 * mg.nbottom[g], kBottomMax, 0, s>>>(
             mg.bottom_probs[g], mg.bottom_boxes[g], Pg, d.ps, Dg, nlg, mg.bottom_off, mg.Xbuf);
     }
 }
@@ -737,12 +812,12 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
             const int nt = mg.nsmooth[g];
             for (int it = 0; it < nu_pre; ++it) {
                 if (it == 0)
-                    k_level<PT, 0><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg,
+                    k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg,
                                                         nullptr, 0, nlg);
                 else
-                    k_level<PT, 1><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg,
+                    k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg,
                                                         nullptr, 0, nlg);
-                k_level<PT, 1><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg,
+                k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg,
                                                     nullptr, 1, nlg);
             }
             k_level<PT, 2><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg, rg, 0, nlg);
@@ -751,7 +826,7 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
                 mg.len[g + 1]);
         }
         if (mg.nbottom[g] > 0)
-            k_bottom_apply<PT><<<2 * mg.nbottom[g], 64, 0, s>>>(
+            k_bottom_apply<PT><<<2 * mg.nbottom[g], kBlock, 0, s>>>(
                 mg.bottom_probs[g], mg.bottom_boxes[g], Pg, mg.bottom_off, mg.Xbuf, fg, eg,
                 nlg);
     }
@@ -767,9 +842,9 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
         k_mg_prolong<PT><<<nt, kBlock, 0, s>>>(tl, Pg, mg.box[g + 1], mg.box_of[g + 1],
                                               mg.eg[g + 1], mg.len[g + 1], eg, nlg);
         for (int it = 0; it < nu_post; ++it) {
-            k_level<PT, 1><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 0,
+            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 0,
                                                 nlg);
-            k_level<PT, 1><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 1,
+            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 1,
                                                 nlg);
         }
     }
@@ -822,7 +897,10 @@ void PcArrays<PT>::fac(hipStream_t s) const {
     const int L = d.nlev - 1;
     k_fill_t<PT><<<nblocks(2 * d.nl), kBlock, 0, s>>>(u, 2 * d.nl);
     for (int lev = L; lev >= 0; --lev) {
-        if (lev == L) {
+        const PT* rhs = r;
+        if (lev == L && L == 0) {
+            rhs = f;                // one level, u = 0: the residual is f itself
+        } else if (lev == L) {
             // u = 0: r = f on composite cells, restricted below
             k_copy_t<PT><<<nblocks(2 * d.nl), kBlock, 0, s>>>(f, r, 2 * d.nl);
             restrict_(s, r, 0);
@@ -833,15 +911,16 @@ void PcArrays<PT>::fac(hipStream_t s) const {
         if (lev > 0) {
             // one red-black sweep on A^l e = f^l from e = 0, sibling ghosts
             // refreshed between the half-sweeps
-            k_level<PT, 0><<<nt, kBlock, 0, s>>>(d.tiles + t0, d.patches, d.ps, d.ctype, Dface,
-                                                r, e, nullptr, 0, d.nl);
+            k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.tiles + t0, d.patches, d.ps, d.ctype, Dface,
+                                                rhs, e, nullptr, 0, d.nl);
             siblings(s, e, lev);
-            k_level<PT, 1><<<nt, kBlock, 0, s>>>(d.tiles + t0, d.patches, d.ps, d.ctype, Dface,
-                                                r, e, nullptr, 1, d.nl);
+            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.tiles + t0, d.patches, d.ps, d.ctype, Dface,
+                                                rhs, e, nullptr, 1, d.nl);
         } else {
-            // base level: multigrid V-cycle with rhs f^0 = r on level 0
+            // base level: multigrid V-cycle with rhs f^0 = r on level 0 (the
+            // V-cycle only reads its level-0 right-hand side)
             PcArrays<PT> v = *this;
-            v.f = r;
+            v.f = const_cast<PT*>(rhs);
             v.vcycle(s);
         }
         k_add_level<PT><<<nt, kBlock, 0, s>>>(d.tiles + t0, d.patches, e, u, d.nl);

@@ -94,6 +94,7 @@ _sigs = {
     "nrd_adjoint_run": (C.c_int32, [_H, C.POINTER(C.c_double), C.c_int32,
                                     C.c_int32, _P, _P]),
     "nrd_dot": (C.c_int32, [_H, _P, _P, C.POINTER(C.c_double)]),
+    "nrd_autotune": (C.c_int32, [_H, C.c_char_p, C.POINTER(C.c_int32)]),
     "nrd_timer_enable": (C.c_int32, [_H, C.c_int32]),
     "nrd_timer_read": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_double),
                                    C.POINTER(C.c_int32)]),
@@ -259,6 +260,14 @@ class Hierarchy:
         gz = self.compact(1)
         check(nrd_adjoint_run(self.h, _dt(dt), nsteps, ckpt_every, _ptr(dJdE), _ptr(gz)))
         return gz
+
+    def autotune(self, cache_path: Optional[str] = None) -> int:
+        """Pick plane-tile shapes per patch-size class; returns the number of
+        classes timed (the rest came from cache_path)."""
+        n = C.c_int32(0)
+        path = cache_path.encode() if cache_path else None
+        check(nrd_autotune(self.h, path, C.byref(n)))
+        return n.value
 
     def dot(self, x, y) -> List[float]:
         out = (C.c_double * self.nprob)()
