@@ -39,7 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch, FETCH scaled by the
 # factor a plain 2 GiB copy reads in the same run, WRITE by its own factor),
 # valid for the stencil source with this SHA-256 prefix; null otherwise.
-MEASURED_TRAFFIC = None
+MEASURED_TRAFFIC = {"workload": "ensemble", "stencil_sha256": "61bbfb8000a36a01",
+                    "bytes_per_launch": 1347216612,
+                    "fetch_bytes": 989381824, "write_bytes": 357834788,
+                    "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def stencil_source_hash():
@@ -171,10 +174,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 2 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--fp64-batched", action="store_true",
+                    help="also time the FP64 solver with batched launches (per-patch vs "
+                         "batched comparison at equal precision)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py runs on exactly one GPU: the hot path is single-GPU "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the hot path is built and measured on a "
+              "single GPU (sharding over several GPUs is a design note only)", file=sys.stderr)
         raise SystemExit(2)
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     from paper_1302_6303_amd import nrd
@@ -190,6 +196,11 @@ def main():
         plain = run_solver(w, nrd.default_options(precision=nrd.NRD_FP64,
                                                   launch=nrd.NRD_PER_PATCH, stencil=1),
                            a.steps, a.warmup, False)
+    batched64 = None
+    if a.fp64_batched:
+        batched64 = run_solver(w, nrd.default_options(precision=nrd.NRD_FP64,
+                                                      launch=nrd.NRD_BATCHED),
+                               a.steps, a.warmup, False)
     res_s = mixed["residual_ms_avg"] / 1e3
     gcells = ncomp / res_s / 1e9
     achieved = BYTES_PER_CELL_RESIDUAL * ncomp / res_s / 1e9
@@ -234,6 +245,12 @@ def main():
                              for k, v in plain.items()}
         out["speedup_mixed_batched_vs_fp64_plain"] = round(plain["s_per_step"] /
                                                            mixed["s_per_step"], 3)
+    if batched64 is not None:
+        out["fp64_batched"] = {k: (round(v, 5) if isinstance(v, float) else v)
+                               for k, v in batched64.items()}
+        if plain is not None:
+            out["speedup_fp64_batched_vs_fp64_plain"] = round(plain["s_per_step"] /
+                                                              batched64["s_per_step"], 3)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     if a.copy_calibration:

@@ -339,7 +339,7 @@ def residual(H, E, T, z, bE, bT, dt, c0, lam=1.0, parts=False):
 
 
 def residual_scale(H, E, T, z, bE, bT, dt, c0, lam=1.0):
-    """Per-cell sum of magnitudes of the terms entering F (used to judge
+    """Per-cell sum of magnitudes of the terms entering F (the scale for
     entries near the T^4 - E cancellation)."""
     Eg, Tg = ghosted_state(H, E, T)
     z3 = ghosted_z3(H, z)

@@ -91,6 +91,11 @@ void min_positive(const Dev& D, hipStream_t s, const double* u, const double* du
 void combine(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
              int nv, const double* coef, int cstride, double* y, int accumulate,
              double alpha);
+// y -= sum_v coef[p][v] x_v, then out[p] = ||y||^2 (composite, volume
+// weighted) in the same pass over y
+void combine_norm(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
+                  int nv, const double* coef, int cstride, double* y, double* partial,
+                  double* out);
 // y = a_p x + b_p y elementwise (a, b per problem, host-computed device arrays)
 void axpby(const Dev& D, hipStream_t s, const double* a, const double* x,
            const double* b, double* y);

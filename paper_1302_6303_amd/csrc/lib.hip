@@ -757,8 +757,7 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
                 multidot(h->D, s, h->V, NL, j + 1, wv, h->partial, h->h1);
                 combine(h->D, s, h->V, NL, j + 1, h->h1, j + 1, wv, 1, -1.0);
                 multidot(h->D, s, h->V, NL, j + 1, wv, h->partial, h->h2);
-                combine(h->D, s, h->V, NL, j + 1, h->h2, j + 1, wv, 1, -1.0);
-                multidot(h->D, s, wv, 0, 1, wv, h->partial, h->hn2);
+                combine_norm(h->D, s, h->V, NL, j + 1, h->h2, j + 1, wv, h->partial, h->hn2);
                 gmres_column(s, np, m, j, h->active, h->h1, h->h2, h->hn2, h->H, h->cs, h->sn,
                              h->g, h->rho, h->vscale);
                 scale_copy(h->D, s, wv, h->vscale, h->V + (j + 1) * NL);
@@ -1482,6 +1481,18 @@ std::string device_arch() {
 
 }  // namespace
 
+// Tiles of every patch with the given per-patch shapes, in launch order
+// (level by level); false if some patch has no shape that fits.
+static bool plane_list(const Tables& t, const std::vector<int32_t>& kc,
+                       const std::vector<int32_t>& run, int32_t span, std::vector<STile>& out) {
+    out.clear();
+    for (int l = 0; l < t.nlev; ++l)
+        for (int b = 0; b < t.nbox; ++b)
+            if (t.boxes[b].level == l && !patch_planes(t.patches[b], b, kc[b], run[b], span, out))
+                return false;
+    return true;
+}
+
 nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed_classes) {
     NEED_BOUND(h);
     if (timed_classes) *timed_classes = 0;
@@ -1491,12 +1502,13 @@ nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed
     Tables& t = h->t;
     hipStream_t s = h->stream;
     const int32_t span = var == 3 ? kStageLen : 0;
+    const int32_t run0 = var == 2 ? 4 * 63 : (var == 3 ? kStageCells : 256);
     std::vector<std::pair<int32_t, int32_t>> cand;           // (planes, run)
     if (var == 3) {
         for (int kc : {4, 8, 16, 32})
             for (int run : {256, kStageCells}) cand.push_back({kc, run});
     } else {
-        for (int kc : {2, 4, 8, 16}) cand.push_back({kc, var == 2 ? 4 * 63 : 256});
+        for (int kc : {2, 4, 8, 16}) cand.push_back({kc, run0});
     }
     std::map<ClassKey, std::vector<int32_t>> cls;
     for (int b = 0; b < t.nbox; ++b) {
@@ -1522,7 +1534,18 @@ nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed
             pick[k] = {kc, run};
         }
     }
-    // timing scratch: the tile region beyond the current tiles
+    // current shapes: cached choices, else the defaults
+    std::vector<int32_t> kc(t.nbox), run(t.nbox);
+    for (auto& kv : cls) {
+        auto it = pick.find(kv.first);
+        for (int b : kv.second) {
+            kc[b] = it != pick.end() ? it->second.first : default_zchunk(t.patches[b].n, var);
+            run[b] = it != pick.end() ? it->second.second : run0;
+        }
+    }
+    // Coordinate descent on the objective that matters: the time of the whole
+    // batched residual launch, varying one class's shape with the others held.
+    // Trial tile lists go to the tile region beyond the current tiles.
     STile* scratch = h->at<STile>(h->o.stiles) + t.stiles.size();
     const size_t room = h->stile_cap - t.stiles.size();
     h->D.active = nullptr;
@@ -1530,44 +1553,63 @@ nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    nrd_status rc = NRD_OK;
+    std::vector<STile> tl;
+    auto time_list = [&](double& ms_out) -> bool {
+        if (tl.empty() || tl.size() > room) return false;
+        if (hipMemcpyAsync(scratch, tl.data(), sizeof(STile) * tl.size(), hipMemcpyHostToDevice,
+                           s) != hipSuccess) {
+            rc = fail(NRD_EDEVICE, "tile upload failed");
+            return false;
+        }
+        Dev Dt = h->D;
+        Dt.stiles = scratch;
+        residual(Dt, s, 0, (int)tl.size(), h->cur, h->bvec, h->tmp);    // warm-up
+        double best = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {
+            (void)hipEventRecord(e0, s);
+            residual(Dt, s, 0, (int)tl.size(), h->cur, h->bvec, h->tmp);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            best = std::min(best, (double)ms);
+        }
+        ms_out = best;
+        return true;
+    };
     std::ofstream out;
     if (cache_path) out.open(cache_path, std::ios::app);
-    nrd_status rc = NRD_OK;
+    double cur_ms = 1e300;
+    if (plane_list(t, kc, run, span, tl)) (void)time_list(cur_ms);
     for (auto& kv : cls) {
+        if (rc) break;
         if (pick.count(kv.first)) continue;
-        double best = 1e300;
-        std::pair<int32_t, int32_t> choice{0, 0};
-        for (auto [kc, run] : cand) {
-            std::vector<STile> tl;
-            bool ok = true;
-            for (int b : kv.second)
-                ok = ok && patch_planes(t.patches[b], b, kc, run, span, tl);
-            if (!ok || tl.empty() || tl.size() > room) continue;
-            if (hipMemcpyAsync(scratch, tl.data(), sizeof(STile) * tl.size(),
-                               hipMemcpyHostToDevice, s) != hipSuccess) {
-                rc = fail(NRD_EDEVICE, "tile upload failed");
-                break;
+        std::pair<int32_t, int32_t> choice{kc[kv.second[0]], run[kv.second[0]]};
+        double best = cur_ms;
+        for (auto [ckc, crun] : cand) {
+            if (ckc == choice.first && crun == choice.second) continue;
+            std::vector<int32_t> kc2 = kc, run2 = run;
+            for (int b : kv.second) {
+                kc2[b] = ckc;
+                run2[b] = crun;
             }
-            Dev Dt = h->D;
-            Dt.stiles = scratch;
-            residual(Dt, s, 0, (int)tl.size(), h->cur, h->bvec, h->tmp);    // warm-up
-            double ms_min = 1e300;
-            for (int rep = 0; rep < 3; ++rep) {
-                (void)hipEventRecord(e0, s);
-                residual(Dt, s, 0, (int)tl.size(), h->cur, h->bvec, h->tmp);
-                (void)hipEventRecord(e1, s);
-                (void)hipEventSynchronize(e1);
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                ms_min = std::min(ms_min, (double)ms);
+            double ms = 0.0;
+            if (!plane_list(t, kc2, run2, span, tl) || !time_list(ms)) {
+                if (rc) break;
+                continue;
             }
-            if (ms_min < best) {
-                best = ms_min;
-                choice = {kc, run};
+            if (ms < 0.98 * best) {                  // keep a change only if it pays
+                best = ms;
+                choice = {ckc, crun};
             }
         }
         if (rc) break;
-        if (choice.first == 0) continue;                 // keep the default shape
+        for (int b : kv.second) {
+            kc[b] = choice.first;
+            run[b] = choice.second;
+        }
+        cur_ms = best;
         pick[kv.first] = choice;
         if (timed_classes) ++*timed_classes;
         if (out)
@@ -1579,17 +1621,12 @@ nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     HIPCHK(hipGetLastError());
-    // apply: rebuild the plane tiles with the chosen shapes
-    std::vector<int32_t> kc(t.nbox), run(t.nbox);
-    for (int b = 0; b < t.nbox; ++b) {
-        ClassKey k;
-        std::copy(t.patches[b].n, t.patches[b].n + 3, k.n);
-        auto it = pick.find(k);
-        kc[b] = it != pick.end() ? it->second.first : default_zchunk(t.patches[b].n, var);
-        run[b] = it != pick.end() ? it->second.second
-                                  : (var == 2 ? 4 * 63 : (var == 3 ? kStageCells : 256));
-    }
-    Tables trial = t;
+    // apply the chosen shapes
+    Tables trial;
+    trial.nlev = t.nlev;
+    trial.nbox = t.nbox;
+    trial.patches = t.patches;
+    trial.boxes = t.boxes;
     if (!build_planes(trial, kc, run, span) || trial.stiles.size() > h->stile_cap)
         return fail(NRD_EINVAL, "tuned tile shapes do not fit");
     t.stiles.swap(trial.stiles);

@@ -591,21 +591,34 @@ __global__ __launch_bounds__(kBottomMax) void k_bottom_setup(
         }
         __syncthreads();
     }
-    // inverse: thread j solves L L^T x = e_j into column j of W
+    // inverse: thread j solves L L^T x = e_j into column j of W.  The band
+    // sums run over a fixed 25 offsets (masked beyond the band) so that all
+    // their LDS loads are independent and issue back to back.
     const int j = tid;
     if (j < N) {
         for (int i = 0; i < j; ++i) W[i * N + j] = 0.0;
         for (int i = j; i < N; ++i) {               // L y = e_j
-            double acc = (i == j) ? 1.0 : 0.0;
             const int lmax = min(b, i - j);
-            for (int l = 1; l <= lmax; ++l) acc -= A[i * kBandLd + l] * W[(i - l) * N + j];
-            W[i * N + j] = acc / Ld[i];
+            double acc0 = (i == j) ? 1.0 : 0.0, acc1 = 0.0;
+#pragma unroll
+            for (int l = 1; l < kBandLd; ++l) {
+                const bool in = l <= lmax;
+                const double term = in ? A[i * kBandLd + l] * W[(i - (in ? l : 0)) * N + j] : 0.0;
+                if (l & 1) acc0 -= term; else acc1 -= term;
+            }
+            W[i * N + j] = (acc0 + acc1) / Ld[i];
         }
         for (int i = N - 1; i >= 0; --i) {          // L^T x = y
-            double acc = W[i * N + j];
             const int lmax = min(b, N - 1 - i);
-            for (int l = 1; l <= lmax; ++l) acc -= A[(i + l) * kBandLd + l] * W[(i + l) * N + j];
-            W[i * N + j] = acc / Ld[i];
+            double acc0 = W[i * N + j], acc1 = 0.0;
+#pragma unroll
+            for (int l = 1; l < kBandLd; ++l) {
+                const bool in = l <= lmax;
+                const int r = i + (in ? l : 0);
+                const double term = in ? A[r * kBandLd + l] * W[r * N + j] : 0.0;
+                if (l & 1) acc0 -= term; else acc1 -= term;
+            }
+            W[i * N + j] = (acc0 + acc1) / Ld[i];
         }
     }
     __syncthreads();

@@ -224,6 +224,72 @@ void combine(const Dev& D, hipStream_t s, const double* X, int64_t xstride, int 
     }
 }
 
+// y -= sum_v coef[p][v] x_v (accumulating into y) and, in the same pass,
+// out[p] = ||y||^2 (volume weighted over composite cells; fixed-order
+// two-stage sum).  The second Gram-Schmidt pass of FGMRES ends with the
+// norm of the orthogonalised vector, so this saves one pass over it.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_combine_norm(
+    const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
+    const uint8_t* __restrict__ ctype, const int32_t* __restrict__ active,
+    const double* __restrict__ X, int64_t xs, int nv, const double* __restrict__ coef, int cs,
+    double* __restrict__ y, double* __restrict__ partial, int64_t nl) {
+    __shared__ double sh[4];
+    const Tile t = vt[blockIdx.x];
+    double acc = 0.0;
+    const bool on = !active || active[t.prob];
+    const PatchInfo& p = P[t.patch];
+    if (on) {
+        double cf[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) cf[v] = (v < nv) ? -coef[t.prob * cs + v] : 0.0;
+        const bool cov = p.flags & PF_COVERED;
+        for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+            const int c = interior_index(p, lin);
+            double a0 = y[c], a1 = y[c + nl];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < nv && cf[v] != 0.0) {
+                    a0 += cf[v] * X[v * xs + c];
+                    a1 += cf[v] * X[v * xs + c + nl];
+                }
+            y[c] = a0;
+            y[c + nl] = a1;
+            if (!(cov && (ctype[c] & CT_COVERED))) acc += a0 * a0 + a1 * a1;
+        }
+    }
+    const double sblk = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sblk * p.vol;
+}
+
+void combine_norm(const Dev& D, hipStream_t s, const double* X, int64_t xstride, int nv,
+                  const double* coef, int cstride, double* y, double* partial, double* out) {
+    // more than 16 basis vectors: plain combines first, the norm with the last 16
+    int v0 = 0;
+    for (; nv - v0 > 16; v0 += 16)
+        combine(D, s, X + v0 * xstride, xstride, 16, coef + v0, cstride, y, 1, -1.0);
+    const int c = nv - v0;
+    const double* Xc = X + v0 * xstride;
+    const double* cc = coef + v0;
+    if (c <= 1)
+        k_combine_norm<1><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
+                                                       Xc, xstride, c, cc, cstride, y, partial,
+                                                       D.nl);
+    else if (c <= 4)
+        k_combine_norm<4><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
+                                                       Xc, xstride, c, cc, cstride, y, partial,
+                                                       D.nl);
+    else if (c <= 8)
+        k_combine_norm<8><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
+                                                       Xc, xstride, c, cc, cstride, y, partial,
+                                                       D.nl);
+    else
+        k_combine_norm<16><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
+                                                        Xc, xstride, c, cc, cstride, y, partial,
+                                                        D.nl);
+    k_sum_partials<<<D.nprob, kBlock, 0, s>>>(D.prob_vtile0, partial, 1, out, 1);
+}
+
 __global__ __launch_bounds__(kBlock) void k_axpby(const Tile* __restrict__ vt,
                                                   const PatchInfo* __restrict__ P,
                                                   const int32_t* __restrict__ active,
