@@ -56,6 +56,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def compact_state(w):
+    """[E of all boxes | T of all boxes], the library's compact layout."""
+    import numpy as np
+    return np.concatenate([w.compact(w.E), w.compact(w.T)])
+
+
+def to_dev(x):
+    import numpy as np
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to("cuda")
+
+
 def workload(name):
     from paper_1302_6303_amd import inputs as I
     if name == "ensemble":
@@ -88,7 +100,6 @@ def composite_cells(w):
 def run_solver(w, opts, steps, warmup, time_residual):
     import torch
     from paper_1302_6303_amd import nrd
-    from tests.gpu_helpers import compact_state, to_dev
     H = nrd.Hierarchy(w.problems, w.boxes, opts)
     u = compact_state(w)
     n = H.ncells
@@ -164,6 +175,68 @@ def cpu_baseline(w, budget_s=15.0):
                       f"({cells} cells) of the same workload, {t_used:.1f} s"}
 
 
+def adjoint_bench(nsteps, every, reps=20):
+    """Forward BDF1 trajectory, checkpointed discrete adjoint of the sum of E
+    at the final time, and the transpose kernel alone, on the 64^3 smooth
+    random material field (float64 throughout)."""
+    import numpy as np
+    import torch
+    from paper_1302_6303_amd import inputs as I, nrd
+    w = I.differentiation(n=64, nsteps=nsteps)
+    opts = nrd.default_options(precision=nrd.NRD_FP64, bdf_max_order=1,
+                               adjoint_slots=-(-nsteps // every) + every + 3)
+    H = nrd.Hierarchy(w.problems, w.boxes, opts)
+    u = compact_state(w)
+    n = H.ncells
+    z = to_dev(w.compact(w.z))
+    H.set_fields(to_dev(u[:n]), to_dev(u[n:]), z)
+    H.autotune(None)
+    dt = [float(w.dt[0])]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    newton = krylov = 0
+    for i in range(nsteps):
+        _, st = H.implicit_step(dt)
+        newton += st[0]["newton_iters"]
+        krylov += st[0]["krylov_iters"]
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    log(f"forward {nsteps} steps: {fwd:.3f} s")
+    H.set_fields(to_dev(u[:n]), to_dev(u[n:]), z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gz = H.adjoint_run(dt, nsteps, every)
+    torch.cuda.synchronize()
+    adj = time.perf_counter() - t0
+    log(f"forward + reverse: {adj:.3f} s")
+    # transpose kernel alone
+    H.begin_step(dt)
+    U = H.unpack(to_dev(u))
+    L = H.unpack(to_dev(np.random.default_rng(1).standard_normal(u.shape)))
+    G = H.native()
+    g = H.compact(1)
+    for _ in range(3):
+        H.vjp(U, L, G, g)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        H.vjp(U, L, G, g)
+    e1.record()
+    torch.cuda.synchronize()
+    vjp_ms = e0.elapsed_time(e1) / reps
+    out = {"metric": "adjoint s/step, 64^3 BDF1, checkpointed transpose-Jacobian FGMRES",
+           "value": round((adj - fwd) / nsteps, 5), "unit": "s/step", "n_gpus": 1,
+           "steps": nsteps, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "differentiation", "cells": n, "ckpt_every": every},
+           "forward_s_per_step": round(fwd / nsteps, 5),
+           "forward_plus_adjoint_s": round(adj, 4),
+           "forward_newton_per_step": newton / nsteps, "forward_krylov_per_step": krylov / nsteps,
+           "vjp_ms": round(vjp_ms, 4), "vjp_gcells_per_s": round(n / vjp_ms / 1e6, 2),
+           "grad_norm": float(torch.linalg.norm(gz))}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +247,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 2 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--ckpt-every", type=int, default=10,
+                    help="adjoint workload: checkpoint interval")
     ap.add_argument("--fp64-batched", action="store_true",
                     help="also time the FP64 solver with batched launches (per-patch vs "
                          "batched comparison at equal precision)")
@@ -184,6 +259,9 @@ def main():
         raise SystemExit(2)
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     from paper_1302_6303_amd import nrd
+    if a.workload == "adjoint":
+        adjoint_bench(a.steps, a.ckpt_every)
+        return
     w = workload(a.workload)
     ncomp = composite_cells(w)
     mixed = run_solver(w, nrd.default_options(precision=nrd.NRD_MIXED,

@@ -113,6 +113,8 @@ void unpack(const Dev& D, hipStream_t s, const int64_t* coff,
 void check_positive(const Dev& D, hipStream_t s, const double* x, int nf,
                     int32_t* flag);
 void cube(hipStream_t s, const double* z, double* z3, int64_t n);
+// g *= 3 z^2 (compact arrays of n values)
+void chain_z(hipStream_t s, const double* z, double* g, int64_t n);
 void to_float(hipStream_t s, const double* x, float* y, int64_t n);
 void to_double(hipStream_t s, const float* x, double* y, int64_t n);
 

@@ -1152,18 +1152,9 @@ static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, in
         }
     }
     // gz = 3 z^2 gacc (compact)
-    {
-        // tmp field 0 = 3 z^2 * gacc field 0
-        std::vector<double> zz;
-        pack(h->D, s, h->at<int64_t>(h->o.coff), gacc, gz, 1, t.ncells);
-        pack(h->D, s, h->at<int64_t>(h->o.coff), h->z, h->tmp, 1, t.ncells);
-        std::vector<double> g(t.ncells), zc(t.ncells);
-        HIPCHK(hipMemcpyAsync(g.data(), gz, 8 * t.ncells, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(zc.data(), h->tmp, 8 * t.ncells, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int64_t i = 0; i < t.ncells; ++i) g[i] *= 3.0 * zc[i] * zc[i];
-        HIPCHK(hipMemcpyAsync(gz, g.data(), 8 * t.ncells, hipMemcpyHostToDevice, s));
-    }
+    pack(h->D, s, h->at<int64_t>(h->o.coff), gacc, gz, 1, t.ncells);
+    pack(h->D, s, h->at<int64_t>(h->o.coff), h->z, h->tmp, 1, t.ncells);
+    chain_z(s, h->tmp, gz, t.ncells);
     // the state ends at u_N: recompute it from the last checkpoint
     copy_interior(h->D, s, ck + (size_t)(nck - 1) * NL, h->cur);
     prepare_state(h, h->cur);
@@ -1422,17 +1413,11 @@ nrd_status nrd_vjp(nrd_hierarchy* h, double* u, double* lam, double* JTl, double
     ghost_fill_d(h->D, s, lam, 2);
     vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], u, lam, JTl, h->gz3);
     if (gz) {
-        // gz = 3 z^2 * dF/dz^3 (compact): stage z into tmp field 1
+        // gz = 3 z^2 * dF/dz^3 (compact)
         const int64_t* coff = h->at<int64_t>(h->o.coff);
         pack(h->D, s, coff, h->gz3, gz, 1, h->t.ncells);
-        std::vector<double> g(h->t.ncells), zc(h->t.ncells);
         pack(h->D, s, coff, h->z, h->tmp, 1, h->t.ncells);
-        HIPCHK(hipMemcpyAsync(g.data(), gz, 8 * h->t.ncells, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(zc.data(), h->tmp, 8 * h->t.ncells, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int64_t i = 0; i < h->t.ncells; ++i) g[i] *= 3.0 * zc[i] * zc[i];
-        HIPCHK(hipMemcpyAsync(gz, g.data(), 8 * h->t.ncells, hipMemcpyHostToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
+        chain_z(s, h->tmp, gz, h->t.ncells);
     }
     HIPCHK(hipGetLastError());
     return NRD_OK;
