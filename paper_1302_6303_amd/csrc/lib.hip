@@ -892,7 +892,7 @@ static nrd_status newton(nrd_hierarchy* h, std::vector<nrd_step_stats>& st) {
         if (!any) break;
         for (int p = 0; p < np; ++p) h->host_active[p] = !(done[p] || failed[p]);
         RCHK(upload_active(h));
-        h->D.active = nullptr;
+        h->D.active = h->active;              // snapshot only the problems still iterating
         pc_setup(h, h->x, true);              // x was prepared by the residual
         // s = J^-1 F; the Newton step is -s
         h->D.active = h->active;

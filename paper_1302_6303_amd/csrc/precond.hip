@@ -50,12 +50,13 @@ __device__ __forceinline__ void face_D(PT Ea, PT Eb, PT Ta, PT Tb, PT za, PT zb,
 }
 
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_snapshot(
+__global__ __launch_bounds__(kBlock) void k_snapshot(const int32_t* __restrict__ act, 
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const double* __restrict__ u,
     const double* __restrict__ z3, PT* __restrict__ Dface, PT* __restrict__ sigma,
     int64_t nl) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     const ProbScalars& q = ps[t.prob];
@@ -94,11 +95,12 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(
 // Coarse face coefficient = mean of the four fine face coefficients
 // (grid g+1 from grid g); boundary faces included.
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_mg_coarsen(
+__global__ __launch_bounds__(kBlock) void k_mg_coarsen(const int32_t* __restrict__ act, 
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pc,
     const PatchInfo* __restrict__ Pf, const int32_t* __restrict__ fbox,
     const PT* __restrict__ Df, int64_t nlf, PT* __restrict__ Dc, int64_t nlc) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& pc = Pc[t.patch];
     const PatchInfo& pf = Pf[fbox[t.prob]];
@@ -209,12 +211,13 @@ __device__ __forceinline__ void level_update(const PatchInfo& p, const int id[3]
 // updates that cell and every lane does useful work.  Otherwise each thread
 // tests two cells.
 template <typename PT, int MODE>
-__global__ __launch_bounds__(kBlock) void k_level(
+__global__ __launch_bounds__(kBlock) void k_level(const int32_t* __restrict__ act, 
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
     const PT* __restrict__ D, const PT* __restrict__ f, PT* __restrict__ e,
     PT* __restrict__ r, int colour, int64_t nl) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
     const PatchInfo& p = P[t.patch];
     const double beta = ps[t.prob].beta;
     int id[3];
@@ -247,12 +250,13 @@ __global__ __launch_bounds__(kBlock) void k_level(
 // ---------------------------------------------------------------------------
 
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_comp_res(
+__global__ __launch_bounds__(kBlock) void k_comp_res(const int32_t* __restrict__ act, 
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
     const PT* __restrict__ D, const PT* __restrict__ f, const PT* __restrict__ u,
     PT* __restrict__ r, int64_t nl) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -350,11 +354,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ s
 // Trilinear prolongation (weights 3/4, 1/4 per axis) of the shadow block of
 // each level-m patch onto its cells: e = P e_coarse, u += e.
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_prolong_level(
+__global__ __launch_bounds__(kBlock) void k_prolong_level(const int32_t* __restrict__ act, 
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
     const ShadowPatch* __restrict__ SP, const PT* __restrict__ sh, int64_t nls,
     PT* __restrict__ e, PT* __restrict__ u, int64_t nl) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     const ShadowPatch sp = SP[t.patch];
@@ -383,11 +388,12 @@ __global__ __launch_bounds__(kBlock) void k_prolong_level(
 }
 
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_add_level(const Tile* __restrict__ tiles,
+__global__ __launch_bounds__(kBlock) void k_add_level(const int32_t* __restrict__ act, const Tile* __restrict__ tiles,
                                                       const PatchInfo* __restrict__ P,
                                                       const PT* __restrict__ e,
                                                       PT* __restrict__ u, int64_t nl) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -399,11 +405,12 @@ __global__ __launch_bounds__(kBlock) void k_add_level(const Tile* __restrict__ t
 
 // multigrid: restriction (mean of 8) from grid g to g+1
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_mg_restrict(
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(const int32_t* __restrict__ act, 
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pc,
     const PatchInfo* __restrict__ Pf, const int32_t* __restrict__ fbox,
     const PT* __restrict__ rf, int64_t nlf, PT* __restrict__ fc, int64_t nlc) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& pc = Pc[t.patch];
     const PatchInfo& pf = Pf[fbox[t.prob]];
@@ -427,11 +434,12 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(
 
 // multigrid: e_g += trilinear prolongation of e_{g+1} (copy rule at edges)
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_mg_prolong(
+__global__ __launch_bounds__(kBlock) void k_mg_prolong(const int32_t* __restrict__ act, 
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pf,
     const PatchInfo* __restrict__ Pc, const int32_t* __restrict__ cbox,
     const PT* __restrict__ ec, int64_t nlc, PT* __restrict__ ef, int64_t nlf) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& pf = Pf[t.patch];
     const PatchInfo& pc = Pc[cbox[t.prob]];
@@ -518,7 +526,7 @@ __device__ __forceinline__ void bottom_coords(const PatchInfo& p, const BottomOr
 // X block of (problem, field): the N x N inverse, row-major, in the band
 // numbering.
 template <typename PT>
-__global__ __launch_bounds__(kBottomMax) void k_bottom_setup(
+__global__ __launch_bounds__(kBottomMax) void k_bottom_setup(const int32_t* __restrict__ act, 
     const int32_t* __restrict__ probs, const int32_t* __restrict__ boxes,
     const PatchInfo* __restrict__ P, const ProbScalars* __restrict__ ps,
     const PT* __restrict__ D, int64_t nl, const int64_t* __restrict__ boff,
@@ -529,6 +537,7 @@ __global__ __launch_bounds__(kBottomMax) void k_bottom_setup(
     const int pi = blockIdx.x >> 1;
     const int fld = blockIdx.x & 1;
     const int prob = probs[pi];
+    if (act && !act[prob]) return;
     const PatchInfo& p = P[boxes[pi]];
     const double beta = ps[prob].beta;
     const int N = p.ncell;                      // <= kBottomMax (checked on the host)
@@ -591,33 +600,37 @@ __global__ __launch_bounds__(kBottomMax) void k_bottom_setup(
         }
         __syncthreads();
     }
-    // inverse: thread j solves L L^T x = e_j into column j of W.  The band
-    // sums run over a fixed 25 offsets (masked beyond the band) so that all
-    // their LDS loads are independent and issue back to back.
+    // inverse: thread j solves L L^T x = e_j into column j of W (band sums
+    // unrolled by four with two accumulators so that their LDS loads issue
+    // back to back)
     const int j = tid;
     if (j < N) {
         for (int i = 0; i < j; ++i) W[i * N + j] = 0.0;
         for (int i = j; i < N; ++i) {               // L y = e_j
             const int lmax = min(b, i - j);
+            const double* Ai = A + i * kBandLd;
             double acc0 = (i == j) ? 1.0 : 0.0, acc1 = 0.0;
-#pragma unroll
-            for (int l = 1; l < kBandLd; ++l) {
-                const bool in = l <= lmax;
-                const double term = in ? A[i * kBandLd + l] * W[(i - (in ? l : 0)) * N + j] : 0.0;
-                if (l & 1) acc0 -= term; else acc1 -= term;
+            int l = 1;
+            for (; l + 3 <= lmax; l += 4) {
+                acc0 -= Ai[l] * W[(i - l) * N + j];
+                acc1 -= Ai[l + 1] * W[(i - l - 1) * N + j];
+                acc0 -= Ai[l + 2] * W[(i - l - 2) * N + j];
+                acc1 -= Ai[l + 3] * W[(i - l - 3) * N + j];
             }
+            for (; l <= lmax; ++l) acc0 -= Ai[l] * W[(i - l) * N + j];
             W[i * N + j] = (acc0 + acc1) / Ld[i];
         }
         for (int i = N - 1; i >= 0; --i) {          // L^T x = y
             const int lmax = min(b, N - 1 - i);
             double acc0 = W[i * N + j], acc1 = 0.0;
-#pragma unroll
-            for (int l = 1; l < kBandLd; ++l) {
-                const bool in = l <= lmax;
-                const int r = i + (in ? l : 0);
-                const double term = in ? A[r * kBandLd + l] * W[r * N + j] : 0.0;
-                if (l & 1) acc0 -= term; else acc1 -= term;
+            int l = 1;
+            for (; l + 3 <= lmax; l += 4) {
+                acc0 -= A[(i + l) * kBandLd + l] * W[(i + l) * N + j];
+                acc1 -= A[(i + l + 1) * kBandLd + l + 1] * W[(i + l + 1) * N + j];
+                acc0 -= A[(i + l + 2) * kBandLd + l + 2] * W[(i + l + 2) * N + j];
+                acc1 -= A[(i + l + 3) * kBandLd + l + 3] * W[(i + l + 3) * N + j];
             }
+            for (; l <= lmax; ++l) acc0 -= A[(i + l) * kBandLd + l] * W[(i + l) * N + j];
             W[i * N + j] = (acc0 + acc1) / Ld[i];
         }
     }
@@ -627,7 +640,7 @@ __global__ __launch_bounds__(kBottomMax) void k_bottom_setup(
 }
 
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_bottom_apply(
+__global__ __launch_bounds__(kBlock) void k_bottom_apply(const int32_t* __restrict__ act, 
     const int32_t* __restrict__ probs, const int32_t* __restrict__ boxes,
     const PatchInfo* __restrict__ P, const int64_t* __restrict__ boff,
     const double* __restrict__ X, const PT* __restrict__ f, PT* __restrict__ e,
@@ -636,6 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_bottom_apply(
     const int pi = blockIdx.x >> 1;
     const int fld = blockIdx.x & 1;
     const int prob = probs[pi];
+    if (act && !act[prob]) return;
     const PatchInfo& p = P[boxes[pi]];
     const int N = p.ncell;
     const BottomOrder o = bottom_order(p);
@@ -662,7 +676,7 @@ __global__ __launch_bounds__(kBlock) void k_bottom_apply(
 // ---------------------------------------------------------------------------
 
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_p2(const Tile* __restrict__ tiles,
+__global__ __launch_bounds__(kBlock) void k_p2(const int32_t* __restrict__ act, const Tile* __restrict__ tiles,
                                                const PatchInfo* __restrict__ P,
                                                const ProbScalars* __restrict__ ps,
                                                const PT* __restrict__ sigma,
@@ -671,6 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_p2(const Tile* __restrict__ tiles,
                                                double* __restrict__ y, int mode,
                                                int transpose, int64_t nl) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -695,7 +710,7 @@ __global__ __launch_bounds__(kBlock) void k_p2(const Tile* __restrict__ tiles,
 
 // P2^-T applied first (transposed preconditioner): double in, PT out
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_p2t_in(const Tile* __restrict__ tiles,
+__global__ __launch_bounds__(kBlock) void k_p2t_in(const int32_t* __restrict__ act, const Tile* __restrict__ tiles,
                                                    const PatchInfo* __restrict__ P,
                                                    const ProbScalars* __restrict__ ps,
                                                    const PT* __restrict__ sigma,
@@ -703,6 +718,7 @@ __global__ __launch_bounds__(kBlock) void k_p2t_in(const Tile* __restrict__ tile
                                                    const double* __restrict__ w,
                                                    PT* __restrict__ x, int mode, int64_t nl) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -720,11 +736,12 @@ __global__ __launch_bounds__(kBlock) void k_p2t_in(const Tile* __restrict__ tile
 }
 
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_in(const Tile* __restrict__ tiles,
+__global__ __launch_bounds__(kBlock) void k_in(const int32_t* __restrict__ act, const Tile* __restrict__ tiles,
                                                const PatchInfo* __restrict__ P,
                                                const double* __restrict__ w,
                                                PT* __restrict__ x, int64_t nl) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -735,11 +752,12 @@ __global__ __launch_bounds__(kBlock) void k_in(const Tile* __restrict__ tiles,
 }
 
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_out(const Tile* __restrict__ tiles,
+__global__ __launch_bounds__(kBlock) void k_out(const int32_t* __restrict__ act, const Tile* __restrict__ tiles,
                                                 const PatchInfo* __restrict__ P,
                                                 const PT* __restrict__ x,
                                                 double* __restrict__ y, int64_t nl) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
     int id[3];
@@ -789,13 +807,13 @@ template <typename PT>
 void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
     const Dev& d = *D;
     const int ntiles = d.level_tile0[d.nlev];
-    k_snapshot<PT><<<ntiles, kBlock, 0, s>>>(d.tiles, d.patches, d.ps, u_state, d.z3, Dface,
+    k_snapshot<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, u_state, d.z3, Dface,
                                             sigma, d.nl);
     for (int g = 1; g <= mg.G; ++g) {
         const PT* Df = (g == 1) ? Dface : mg.Dg[g - 1];
         const int64_t nlf = (g == 1) ? d.nl : mg.len[g - 1];
         const PatchInfo* Pf = (g == 1) ? d.patches : mg.box[g - 1];
-        k_mg_coarsen<PT><<<mg.ntiles[g], kBlock, 0, s>>>(mg.tiles[g], mg.box[g], Pf,
+        k_mg_coarsen<PT><<<mg.ntiles[g], kBlock, 0, s>>>(d.active, mg.tiles[g], mg.box[g], Pf,
                                                          mg.box_of[g - 1], Df, nlf, mg.Dg[g],
                                                          mg.len[g]);
     }
@@ -804,7 +822,7 @@ void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
         const PT* Dg = (g == 0) ? Dface : mg.Dg[g];
         const int64_t nlg = (g == 0) ? d.nl : mg.len[g];
         const PatchInfo* Pg = (g == 0) ? d.patches : mg.box[g];
-        k_bottom_setup<PT><<<2 * mg.nbottom[g], kBottomMax, 0, s>>>(
+        k_bottom_setup<PT><<<2 * mg.nbottom[g], kBottomMax, 0, s>>>(d.active, 
             mg.bottom_probs[g], mg.bottom_boxes[g], Pg, d.ps, Dg, nlg, mg.bottom_off, mg.Xbuf);
     }
 }
@@ -825,21 +843,21 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
             const int nt = mg.nsmooth[g];
             for (int it = 0; it < nu_pre; ++it) {
                 if (it == 0)
-                    k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg,
+                    k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
                                                         nullptr, 0, nlg);
                 else
-                    k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg,
+                    k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
                                                         nullptr, 0, nlg);
-                k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg,
+                k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
                                                     nullptr, 1, nlg);
             }
-            k_level<PT, 2><<<nt, kBlock, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg, rg, 0, nlg);
-            k_mg_restrict<PT><<<mg.ntiles[g + 1], kBlock, 0, s>>>(
+            k_level<PT, 2><<<nt, kBlock, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, rg, 0, nlg);
+            k_mg_restrict<PT><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active, 
                 mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g], rg, nlg, mg.fg[g + 1],
                 mg.len[g + 1]);
         }
         if (mg.nbottom[g] > 0)
-            k_bottom_apply<PT><<<2 * mg.nbottom[g], kBlock, 0, s>>>(
+            k_bottom_apply<PT><<<2 * mg.nbottom[g], kBlock, 0, s>>>(d.active, 
                 mg.bottom_probs[g], mg.bottom_boxes[g], Pg, mg.bottom_off, mg.Xbuf, fg, eg,
                 nlg);
     }
@@ -852,12 +870,12 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
         const PT* Dg = (g == 0) ? Dface : mg.Dg[g];
         const Tile* tl = mg.smooth_tiles[g];
         const int nt = mg.nsmooth[g];
-        k_mg_prolong<PT><<<nt, kBlock, 0, s>>>(tl, Pg, mg.box[g + 1], mg.box_of[g + 1],
+        k_mg_prolong<PT><<<nt, kBlock, 0, s>>>(d.active, tl, Pg, mg.box[g + 1], mg.box_of[g + 1],
                                               mg.eg[g + 1], mg.len[g + 1], eg, nlg);
         for (int it = 0; it < nu_post; ++it) {
-            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 0,
+            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 0,
                                                 nlg);
-            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 1,
+            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 1,
                                                 nlg);
         }
     }
@@ -895,7 +913,7 @@ void PcArrays<PT>::composite_residual(hipStream_t s) const {
     restrict_(s, u, 0);
     fill_ghosts(s, u);
     const int ntiles = d.level_tile0[d.nlev];
-    k_comp_res<PT><<<ntiles, kBlock, 0, s>>>(d.tiles, d.patches, d.ps, d.ctype, Dface, f, u, r,
+    k_comp_res<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, d.ctype, Dface, f, u, r,
                                             d.nl);
     if (d.nrcells > 0)
         k_comp_reflux<PT><<<nblocks(d.nrcells), kBlock, 0, s>>>(
@@ -924,10 +942,10 @@ void PcArrays<PT>::fac(hipStream_t s) const {
         if (lev > 0) {
             // one red-black sweep on A^l e = f^l from e = 0, sibling ghosts
             // refreshed between the half-sweeps
-            k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.tiles + t0, d.patches, d.ps, d.ctype, Dface,
+            k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, d.tiles + t0, d.patches, d.ps, d.ctype, Dface,
                                                 rhs, e, nullptr, 0, d.nl);
             siblings(s, e, lev);
-            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.tiles + t0, d.patches, d.ps, d.ctype, Dface,
+            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, d.tiles + t0, d.patches, d.ps, d.ctype, Dface,
                                                 rhs, e, nullptr, 1, d.nl);
         } else {
             // base level: multigrid V-cycle with rhs f^0 = r on level 0 (the
@@ -936,13 +954,13 @@ void PcArrays<PT>::fac(hipStream_t s) const {
             v.f = const_cast<PT*>(rhs);
             v.vcycle(s);
         }
-        k_add_level<PT><<<nt, kBlock, 0, s>>>(d.tiles + t0, d.patches, e, u, d.nl);
+        k_add_level<PT><<<nt, kBlock, 0, s>>>(d.active, d.tiles + t0, d.patches, e, u, d.nl);
         for (int m = lev + 1; m <= L; ++m) {
             const int a = d.level_shadow0[m], b = d.level_shadow0[m + 1];
             k_gather<PT><<<nblocks(b - a), kBlock, 0, s>>>(shadow_src + a, b - a, e, d.nl,
                                                            shadow + a, shadow_len);
             const int m0 = d.level_tile0[m], mt = d.level_tile0[m + 1] - m0;
-            k_prolong_level<PT><<<mt, kBlock, 0, s>>>(d.tiles + m0, d.patches, shadows,
+            k_prolong_level<PT><<<mt, kBlock, 0, s>>>(d.active, d.tiles + m0, d.patches, shadows,
                                                       shadow, shadow_len, e, u, d.nl);
         }
         restrict_(s, u, 0);
@@ -953,9 +971,9 @@ template <typename PT>
 void PcArrays<PT>::apply(hipStream_t s, const double* w, double* y) const {
     const Dev& d = *D;
     const int ntiles = d.level_tile0[d.nlev];
-    k_in<PT><<<ntiles, kBlock, 0, s>>>(d.tiles, d.patches, w, f, d.nl);
+    k_in<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, w, f, d.nl);
     fac(s);
-    k_p2<PT><<<ntiles, kBlock, 0, s>>>(d.tiles, d.patches, d.ps, sigma, d.z3, u, y, p2_mode, 0,
+    k_p2<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, sigma, d.z3, u, y, p2_mode, 0,
                                        d.nl);
 }
 
@@ -963,10 +981,10 @@ template <typename PT>
 void PcArrays<PT>::apply_transpose(hipStream_t s, const double* w, double* y) const {
     const Dev& d = *D;
     const int ntiles = d.level_tile0[d.nlev];
-    k_p2t_in<PT><<<ntiles, kBlock, 0, s>>>(d.tiles, d.patches, d.ps, sigma, d.z3, w, f,
+    k_p2t_in<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, sigma, d.z3, w, f,
                                            p2_mode, d.nl);
     fac(s);
-    k_out<PT><<<ntiles, kBlock, 0, s>>>(d.tiles, d.patches, u, y, d.nl);
+    k_out<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, u, y, d.nl);
 }
 
 template struct PcArrays<float>;
