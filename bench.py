@@ -283,6 +283,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 2 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="1: capture FGMRES iterations as HIP graphs in the mixed run "
+                         "(measured slower than direct launches on this software stack)")
     ap.add_argument("--ckpt-every", type=int, default=10,
                     help="adjoint workload: checkpoint interval")
     ap.add_argument("--fp64-batched", action="store_true",
@@ -300,9 +303,11 @@ def main():
         return
     w = workload(a.workload)
     ncomp = composite_cells(w)
+    use_graph = a.graph
     mixed = run_solver(w, nrd.default_options(precision=nrd.NRD_MIXED,
-                                              launch=nrd.NRD_BATCHED),
+                                              launch=nrd.NRD_BATCHED, use_graph=use_graph),
                        a.steps, a.warmup, True)
+    mixed["use_graph"] = use_graph
     plain = None
     if not a.no_plain:
         # per-patch launches need many workgroups per patch: the register
