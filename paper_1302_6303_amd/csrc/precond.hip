@@ -525,8 +525,10 @@ __device__ __forceinline__ void bottom_coords(const PatchInfo& p, const BottomOr
 
 // X block of (problem, field): the N x N inverse, row-major, in the band
 // numbering.
+constexpr int kBottomThreads = 4 * kBottomMax;   // four threads per inverse column
+
 template <typename PT>
-__global__ __launch_bounds__(kBottomMax) void k_bottom_setup(const int32_t* __restrict__ act, 
+__global__ __launch_bounds__(kBottomThreads) void k_bottom_setup(const int32_t* __restrict__ act, 
     const int32_t* __restrict__ probs, const int32_t* __restrict__ boxes,
     const PatchInfo* __restrict__ P, const ProbScalars* __restrict__ ps,
     const PT* __restrict__ D, int64_t nl, const int64_t* __restrict__ boff,
@@ -573,15 +575,14 @@ __global__ __launch_bounds__(kBottomMax) void k_bottom_setup(const int32_t* __re
         }
         A[lin * kBandLd] = dg;
     }
-    // this thread's (r, q) pairs of the trailing-update triangle 1 <= q <= r <= b
-    int pr[3], pq[3];
-#pragma unroll
-    for (int w = 0; w < 3; ++w) {
-        const int idx = tid + w * kBottomMax;
+    // this thread's (r, q) pair of the trailing-update triangle 1 <= q <= r <= b
+    // (b (b + 1) / 2 <= 325 < kBottomThreads)
+    int pr, pq;
+    {
         int r = 1;
-        while (r * (r + 1) / 2 <= idx) ++r;
-        pr[w] = (idx < b * (b + 1) / 2) ? r : kBottomMax;   // out of range: never used
-        pq[w] = idx - r * (r - 1) / 2 + 1;
+        while (r * (r + 1) / 2 <= tid) ++r;
+        pr = (tid < b * (b + 1) / 2) ? r : kBottomMax;      // out of range: never used
+        pq = tid - r * (r - 1) / 2 + 1;
     }
     __syncthreads();
     // right-looking band Cholesky: scale column k, update the trailing triangle
@@ -592,46 +593,34 @@ __global__ __launch_bounds__(kBottomMax) void k_bottom_setup(const int32_t* __re
         if (tid >= 1 && tid <= m) A[(k + tid) * kBandLd + tid] *= inv;
         if (tid == 0) Ld[k] = dkk;
         __syncthreads();
-#pragma unroll
-        for (int w = 0; w < 3; ++w) {
-            const int r = pr[w], q = pq[w];
-            if (r <= m)
-                A[(k + r) * kBandLd + (r - q)] -= A[(k + r) * kBandLd + r] * A[(k + q) * kBandLd + q];
-        }
+        if (pr <= m)
+            A[(k + pr) * kBandLd + (pr - pq)] -= A[(k + pr) * kBandLd + pr] * A[(k + pq) * kBandLd + pq];
         __syncthreads();
     }
-    // inverse: thread j solves L L^T x = e_j into column j of W (band sums
-    // unrolled by four with two accumulators so that their LDS loads issue
-    // back to back)
-    const int j = tid;
+    // inverse: the four threads 4j..4j+3 (one wavefront holds whole groups)
+    // solve L L^T x = e_j into column j of W; each sums every fourth band term
+    // and the group adds its partial sums with two cross-lane exchanges, so
+    // all four hold the row value and write it (same value, same address).
+    // Groups run different row counts: no workgroup barrier inside.
+    const int j = tid >> 2, q = tid & 3;
     if (j < N) {
-        for (int i = 0; i < j; ++i) W[i * N + j] = 0.0;
+        for (int i = q; i < j; i += 4) W[i * N + j] = 0.0;
         for (int i = j; i < N; ++i) {               // L y = e_j
             const int lmax = min(b, i - j);
-            const double* Ai = A + i * kBandLd;
-            double acc0 = (i == j) ? 1.0 : 0.0, acc1 = 0.0;
-            int l = 1;
-            for (; l + 3 <= lmax; l += 4) {
-                acc0 -= Ai[l] * W[(i - l) * N + j];
-                acc1 -= Ai[l + 1] * W[(i - l - 1) * N + j];
-                acc0 -= Ai[l + 2] * W[(i - l - 2) * N + j];
-                acc1 -= Ai[l + 3] * W[(i - l - 3) * N + j];
-            }
-            for (; l <= lmax; ++l) acc0 -= Ai[l] * W[(i - l) * N + j];
-            W[i * N + j] = (acc0 + acc1) / Ld[i];
+            double acc = 0.0;
+            for (int l = 1 + q; l <= lmax; l += 4) acc -= A[i * kBandLd + l] * W[(i - l) * N + j];
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            W[i * N + j] = (((i == j) ? 1.0 : 0.0) + acc) / Ld[i];
         }
         for (int i = N - 1; i >= 0; --i) {          // L^T x = y
             const int lmax = min(b, N - 1 - i);
-            double acc0 = W[i * N + j], acc1 = 0.0;
-            int l = 1;
-            for (; l + 3 <= lmax; l += 4) {
-                acc0 -= A[(i + l) * kBandLd + l] * W[(i + l) * N + j];
-                acc1 -= A[(i + l + 1) * kBandLd + l + 1] * W[(i + l + 1) * N + j];
-                acc0 -= A[(i + l + 2) * kBandLd + l + 2] * W[(i + l + 2) * N + j];
-                acc1 -= A[(i + l + 3) * kBandLd + l + 3] * W[(i + l + 3) * N + j];
-            }
-            for (; l <= lmax; ++l) acc0 -= A[(i + l) * kBandLd + l] * W[(i + l) * N + j];
-            W[i * N + j] = (acc0 + acc1) / Ld[i];
+            double acc = 0.0;
+            for (int l = 1 + q; l <= lmax; l += 4)
+                acc -= A[(i + l) * kBandLd + l] * W[(i + l) * N + j];
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            W[i * N + j] = (W[i * N + j] + acc) / Ld[i];
         }
     }
     __syncthreads();
@@ -822,7 +811,7 @@ void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
         const PT* Dg = (g == 0) ? Dface : mg.Dg[g];
         const int64_t nlg = (g == 0) ? d.nl : mg.len[g];
         const PatchInfo* Pg = (g == 0) ? d.patches : mg.box[g];
-        k_bottom_setup<PT><<<2 * mg.nbottom[g], kBottomMax, 0, s>>>(d.active, 
+        k_bottom_setup<PT><<<2 * mg.nbottom[g], kBottomThreads, 0, s>>>(d.active, 
             mg.bottom_probs[g], mg.bottom_boxes[g], Pg, d.ps, Dg, nlg, mg.bottom_off, mg.Xbuf);
     }
 }

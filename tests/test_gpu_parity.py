@@ -26,6 +26,8 @@ def workloads():
             1e-3, 1, np.random.default_rng(4), state="front"),
         "amr2": lambda: I.small_amr(8, state="front"),
         "amr3": lambda: I.static_amr(base=16, nlevels=3, side=(8, 16), state="front"),
+        "amr4": lambda: I.static_amr(base=8, nlevels=4, side=(8, 16), seed_k=3,
+                                     state="front"),
     }
 
 
