@@ -38,6 +38,11 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_CELL_RESIDUAL = 56      # read E, T, z^3, b_E, b_T; write F_E, F_T (f64)
 BYTES_PER_CELL_JVP = 56           # read E, T, z^3, v_E, v_T; write 2 (f64)
+# red-black sweep in float: read the right-hand side (2), the frozen state
+# E, T, z^3 (3) and the iterate (2), write the iterate (2); the first sweep
+# of a V-cycle starts from zero and does not read the iterate
+BYTES_PER_CELL_SWEEP = 36
+BYTES_PER_CELL_SWEEP_ZERO = 28
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per residual launch on the ensemble workload from rocprofv3
@@ -160,7 +165,9 @@ def run_solver(w, opts, steps, warmup, time_residual):
             H.jvp(U, V, Y)
         for _ in range(20):
             H.precond_apply(V, Y)
-        for key, which in (("jvp", nrd.NRD_TIMER_JVP), ("precond", nrd.NRD_TIMER_PRECOND)):
+        for key, which in (("jvp", nrd.NRD_TIMER_JVP), ("precond", nrd.NRD_TIMER_PRECOND),
+                           ("sweep", nrd.NRD_TIMER_SMOOTH),
+                           ("sweep_zero", nrd.NRD_TIMER_SMOOTH_ZERO)):
             ms, cnt = H.timer_read(which)
             res[key + "_ms_avg"] = ms / max(cnt, 1)
             res[key + "_calls"] = cnt
@@ -328,6 +335,12 @@ def main():
             and MEASURED_TRAFFIC["stencil_sha256"] == stencil_source_hash()):
         traffic = MEASURED_TRAFFIC["bytes_per_launch"]
     jvp_s = mixed["jvp_ms_avg"] / 1e3
+    base_cells = sum(b.ncells for b in w.boxes if b.level == 0)
+    def gbs(nbytes, ms):
+        return round(nbytes / ms / 1e6, 1) if ms > 0 else None
+
+    def frac(nbytes, ms):
+        return round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 4) if ms > 0 else None
     out = {
         "metric": "residual Gcells/s (%HBM peak) + s/implicit step, mixed-batched vs FP64 plain",
         "value": round(gcells, 3),
@@ -356,6 +369,19 @@ def main():
                          "unit": "GB/s",
                          "frac": round(BYTES_PER_CELL_JVP * ncomp / jvp_s / 1e9 / HBM_PEAK_GBS, 4),
                          "avg_launch_ms": round(mixed["jvp_ms_avg"], 4)},
+        "smoother_roofline": {
+            "kernel": "k_level<float> (red-black sweep of the base grid, one launch per colour)",
+            "cells": base_cells, "bytes_per_cell": BYTES_PER_CELL_SWEEP,
+            "achieved": gbs(BYTES_PER_CELL_SWEEP * base_cells, mixed["sweep_ms_avg"]),
+            "unit": "GB/s",
+            "frac": frac(BYTES_PER_CELL_SWEEP * base_cells, mixed["sweep_ms_avg"]),
+            "avg_sweep_ms": round(mixed["sweep_ms_avg"], 4),
+            "zero_start": {
+                "bytes_per_cell": BYTES_PER_CELL_SWEEP_ZERO,
+                "achieved": gbs(BYTES_PER_CELL_SWEEP_ZERO * base_cells,
+                                mixed["sweep_zero_ms_avg"]),
+                "frac": frac(BYTES_PER_CELL_SWEEP_ZERO * base_cells, mixed["sweep_zero_ms_avg"]),
+                "avg_sweep_ms": round(mixed["sweep_zero_ms_avg"], 4)}},
         "mixed_batched": {k: (round(v, 5) if isinstance(v, float) else v)
                           for k, v in mixed.items()},
     }

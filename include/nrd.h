@@ -250,13 +250,19 @@ nrd_status nrd_dot(nrd_hierarchy* h, const double* dev_x, const double* dev_y,
 nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path,
                         int32_t* timed_classes);
 
-/* Time of the last kernels of one operator, for measurement: launches of
- * the residual kernel family since the last call are timed with HIP events
- * on the library stream.  *ms_total / *count.  Synchronises. */
+/* Time of the kernels of one operator, for measurement: while timing is
+ * enabled every call of the operator records HIP events on the library
+ * stream around its launches; *ms_total is their summed elapsed time and
+ * *count the number of calls since nrd_timer_enable.  RESIDUAL: the residual
+ * launch(es) of a residual evaluation; JVP: one Jacobian action; PRECOND:
+ * one preconditioner application; SMOOTH: one red-black sweep (both colour
+ * launches) on the base level's multigrid grid starting from a nonzero
+ * iterate; SMOOTH_ZERO: the first such sweep of a V-cycle, from a zero
+ * iterate.  NRD_EINVAL for an unknown timer.  Synchronises. */
 nrd_status nrd_timer_read(nrd_hierarchy* h, int32_t which, double* ms_total,
                           int32_t* count);
 enum { NRD_TIMER_RESIDUAL = 0, NRD_TIMER_JVP = 1, NRD_TIMER_PRECOND = 2,
-       NRD_TIMER_SMOOTH = 3, NRD_TIMER_COUNT = 4 };
+       NRD_TIMER_SMOOTH = 3, NRD_TIMER_SMOOTH_ZERO = 4, NRD_TIMER_COUNT = 5 };
 nrd_status nrd_timer_enable(nrd_hierarchy* h, int32_t on);
 
 #ifdef __cplusplus

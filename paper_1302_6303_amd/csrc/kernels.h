@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "nrd_internal.h"
 
 namespace nrd {
@@ -19,6 +21,15 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
     const int base = n >> 3, rem = n & 7;
     return x * base + (x < rem ? x : rem) + q;
 }
+
+// Event timing of operator launches on the library stream (implemented by
+// the hierarchy; inactive unless timing is enabled).
+struct Clock {
+    virtual std::pair<hipEvent_t, hipEvent_t> tic(int which) = 0;
+    virtual void toc(int which, std::pair<hipEvent_t, hipEvent_t> p) = 0;
+  protected:
+    ~Clock() = default;
+};
 
 // Device views of the hierarchy tables (pointers into the workspace) plus the
 // host-side counts that size the launches.

@@ -55,7 +55,7 @@ struct Bump {
 
 }  // namespace
 
-struct nrd_hierarchy {
+struct nrd_hierarchy final : public Clock {
     Tables t;
     nrd_options opt;
     hipStream_t stream = nullptr;
@@ -141,13 +141,13 @@ struct nrd_hierarchy {
         }
         return ev_pool[ev_used++];
     }
-    std::pair<hipEvent_t, hipEvent_t> tic(int which) {
+    std::pair<hipEvent_t, hipEvent_t> tic(int which) override {
         if (!timing) return {nullptr, nullptr};
         hipEvent_t a = ev(), b = ev();
         (void)hipEventRecord(a, stream);
         return {a, b};
     }
-    void toc(int which, std::pair<hipEvent_t, hipEvent_t> p) {
+    void toc(int which, std::pair<hipEvent_t, hipEvent_t> p) override {
         if (!timing || !p.first) return;
         (void)hipEventRecord(p.second, stream);
         ev_pairs.push_back({which, p});
@@ -314,6 +314,7 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
     pc.p2_mode = h->opt.p2_mode;
     pc.nu_pre = std::max(1, h->opt.mg_nu_pre);
     pc.nu_post = std::max(0, h->opt.mg_nu_post);
+    pc.clock = h;
 }
 
 static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
@@ -1643,6 +1644,7 @@ nrd_status nrd_timer_enable(nrd_hierarchy* h, int32_t on) {
 
 nrd_status nrd_timer_read(nrd_hierarchy* h, int32_t which, double* ms, int32_t* count) {
     if (!h) return fail(NRD_EINVAL, "NULL hierarchy");
+    if (which < 0 || which >= NRD_TIMER_COUNT) return fail(NRD_EINVAL, "unknown timer");
     HIPCHK(hipStreamSynchronize(h->stream));
     double tot = 0.0;
     int32_t n = 0;

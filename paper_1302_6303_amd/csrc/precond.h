@@ -61,12 +61,13 @@ struct PcArrays {
     } mg;
     int p2_mode = 0;
     int nu_pre = 1, nu_post = 1;
+    Clock* clock = nullptr;     // times the base grid's sweeps
 
     void zero(hipStream_t s) const;
     void setup(hipStream_t s, const double* u_state) const;
     void apply(hipStream_t s, const double* w, double* y) const;
     void apply_transpose(hipStream_t s, const double* w, double* y) const;
-    void fac(hipStream_t s) const;
+    const PT* fac(hipStream_t s) const;     // returns u or e (one level)
     void vcycle(hipStream_t s) const;
     void composite_residual(hipStream_t s) const;
     void fill_ghosts(hipStream_t s, PT* x) const;

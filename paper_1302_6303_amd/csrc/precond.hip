@@ -831,6 +831,9 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
             const Tile* tl = mg.smooth_tiles[g];
             const int nt = mg.nsmooth[g];
             for (int it = 0; it < nu_pre; ++it) {
+                const int which = it == 0 ? NRD_TIMER_SMOOTH_ZERO : NRD_TIMER_SMOOTH;
+                std::pair<hipEvent_t, hipEvent_t> tk{nullptr, nullptr};
+                if (g == 0 && clock) tk = clock->tic(which);
                 if (it == 0)
                     k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
                                                         nullptr, 0, nlg);
@@ -839,6 +842,7 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
                                                         nullptr, 0, nlg);
                 k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
                                                     nullptr, 1, nlg);
+                if (g == 0 && clock) clock->toc(which, tk);
             }
             k_level<PT, 2><<<nt, kBlock, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, rg, 0, nlg);
             k_mg_restrict<PT><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active, 
@@ -862,10 +866,13 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
         k_mg_prolong<PT><<<nt, kBlock, 0, s>>>(d.active, tl, Pg, mg.box[g + 1], mg.box_of[g + 1],
                                               mg.eg[g + 1], mg.len[g + 1], eg, nlg);
         for (int it = 0; it < nu_post; ++it) {
+            std::pair<hipEvent_t, hipEvent_t> tk{nullptr, nullptr};
+            if (g == 0 && clock) tk = clock->tic(NRD_TIMER_SMOOTH);
             k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 0,
                                                 nlg);
             k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 1,
                                                 nlg);
+            if (g == 0 && clock) clock->toc(NRD_TIMER_SMOOTH, tk);
         }
     }
 }
@@ -911,16 +918,20 @@ void PcArrays<PT>::composite_residual(hipStream_t s) const {
 }
 
 template <typename PT>
-void PcArrays<PT>::fac(hipStream_t s) const {
-    // One FAC V(1,0) cycle from u = 0 for A^c u = f (Alg. 1).  Result in u.
+const PT* PcArrays<PT>::fac(hipStream_t s) const {
+    // One FAC V(1,0) cycle from u = 0 for A^c u = f (Alg. 1).  Returns the
+    // buffer holding the result: u, or e when there is one level (u = 0 plus
+    // the base level's correction is that correction).
     const Dev& d = *D;
     const int L = d.nlev - 1;
+    if (L == 0) {
+        vcycle(s);
+        return e;
+    }
     k_fill_t<PT><<<nblocks(2 * d.nl), kBlock, 0, s>>>(u, 2 * d.nl);
     for (int lev = L; lev >= 0; --lev) {
         const PT* rhs = r;
-        if (lev == L && L == 0) {
-            rhs = f;                // one level, u = 0: the residual is f itself
-        } else if (lev == L) {
+        if (lev == L) {
             // u = 0: r = f on composite cells, restricted below
             k_copy_t<PT><<<nblocks(2 * d.nl), kBlock, 0, s>>>(f, r, 2 * d.nl);
             restrict_(s, r, 0);
@@ -954,6 +965,7 @@ void PcArrays<PT>::fac(hipStream_t s) const {
         }
         restrict_(s, u, 0);
     }
+    return u;
 }
 
 template <typename PT>
@@ -961,8 +973,8 @@ void PcArrays<PT>::apply(hipStream_t s, const double* w, double* y) const {
     const Dev& d = *D;
     const int ntiles = d.level_tile0[d.nlev];
     k_in<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, w, f, d.nl);
-    fac(s);
-    k_p2<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, sigma, d.z3, u, y, p2_mode, 0,
+    const PT* x = fac(s);
+    k_p2<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, sigma, d.z3, x, y, p2_mode, 0,
                                        d.nl);
 }
 
@@ -972,8 +984,8 @@ void PcArrays<PT>::apply_transpose(hipStream_t s, const double* w, double* y) co
     const int ntiles = d.level_tile0[d.nlev];
     k_p2t_in<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, sigma, d.z3, w, f,
                                            p2_mode, d.nl);
-    fac(s);
-    k_out<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, u, y, d.nl);
+    const PT* x = fac(s);
+    k_out<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, x, y, d.nl);
 }
 
 template struct PcArrays<float>;

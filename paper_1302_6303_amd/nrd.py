@@ -27,6 +27,7 @@ NRD_ENONPOS, NRD_ENOTCONV, NRD_EDEVICE, NRD_EUNSUPPORTED = -4, -5, -6, -7
 NRD_FP64, NRD_MIXED = 0, 1
 NRD_BATCHED, NRD_PER_PATCH = 0, 1
 NRD_TIMER_RESIDUAL, NRD_TIMER_JVP, NRD_TIMER_PRECOND = 0, 1, 2
+NRD_TIMER_SMOOTH, NRD_TIMER_SMOOTH_ZERO = 3, 4
 
 
 class nrd_box(C.Structure):

@@ -59,6 +59,16 @@ def test_bad_options_are_rejected():
             _create(w.problems, w.boxes, **kw)
 
 
+def test_unknown_timer_is_rejected():
+    from paper_1302_6303_amd import nrd
+    import ctypes as C
+    w = I.marshak_single(8)
+    H = _create(w.problems, w.boxes)
+    ms, n = C.c_double(), C.c_int32()
+    for which in (-1, 5):
+        assert nrd.nrd_timer_read(H.h, which, C.byref(ms), C.byref(n)) == nrd.NRD_EINVAL
+
+
 def test_calls_before_binding_report_state_error():
     from paper_1302_6303_amd import nrd
     import ctypes as C

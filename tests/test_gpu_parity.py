@@ -18,6 +18,26 @@ from tests.helpers import state, system
 pytestmark = pytest.mark.gpu
 
 
+def boxes_workload():
+    """Three uniform problems of non-cubic sizes whose grids coarsen to
+    different depths; Marshak faces on x-low and y-high of the first."""
+    rng = np.random.default_rng(11)
+    sizes = [(80, 48, 48), (40, 24, 56), (16, 16, 16)]
+    problems, boxes = [], []
+    for p, n in enumerate(sizes):
+        kw = {}
+        if p == 0:
+            kw = {"bc_E": (1, 0, 0, 1, 0, 0), "robin_R": (1.0, 0.0, 0.0, 1.0, 0.0, 0.0)}
+        problems.append(I.Problem(base_n=n, **kw))
+        boxes.append(I.Box(p, 0, (0, 0, 0), n))
+    z = []
+    for prob, b in zip(problems, boxes):
+        zf = I.box_field(I.sample_material_boxes(rng, 2))
+        z.append(zf(*I.cell_centres(prob, b)))
+    E, T = I.front_state(problems, boxes, rng)
+    return I.Workload("boxes3", problems, boxes, z, E, T, np.array([2e-3, 1e-3, 5e-4]))
+
+
 def workloads():
     return {
         "uniform16": lambda: I.marshak_single(16, state="front"),
@@ -94,6 +114,29 @@ def test_precond_parity(name):
     for sl in (slice(0, n), slice(n, 2 * n)):
         mm = m[sl]
         assert rel_err(got[sl][mm], ref[sl][mm]) < 1e-10
+
+
+def test_precond_parity_noncubic():
+    """Preconditioner of the 80 x 48 x 48 problem (four multigrid grids
+    below it, Marshak faces on two sides) against the oracle."""
+    full = boxes_workload()
+    w = I.Workload("p0", full.problems[:1], full.boxes[:1], full.z[:1], full.E[:1],
+                   full.T[:1], full.dt[:1])
+    s = system(w)
+    H = make(w)
+    dt = 2e-3
+    H.begin_step([dt])
+    u = s.sync(state(s, w) * np.random.default_rng(12).uniform(0.9, 1.1, 2 * s.nc))
+    wv = np.random.default_rng(13).standard_normal(u.shape)
+    H.precond_setup(native_from_compact(H, u))
+    y = H.native()
+    H.precond_apply(native_from_compact(H, wv), y)
+    got = compact_from_native(H, y)
+    P, _ = s.precond(u, dt)
+    ref = P(wv)
+    n = s.nc
+    for sl in (slice(0, n), slice(n, 2 * n)):
+        assert rel_err(got[sl], ref[sl]) < 1e-10
 
 
 @pytest.mark.parametrize("name", ["uniform16", "uniform10"])
