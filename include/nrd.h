@@ -129,9 +129,11 @@ typedef struct {
 void nrd_default_options(nrd_options* opt);
 
 typedef struct {
-    int32_t newton_iters;
+    int32_t newton_iters;        /* accepted Newton updates                  */
     int32_t krylov_iters;        /* total over the Newton iterations         */
-    int32_t positivity_cuts;
+    int32_t positivity_cuts;     /* rejected trial steps (a trial u - l s with
+                                    a nonpositive E or T on a composite cell
+                                    halves l; 31 rejections end the solve)  */
     int32_t converged;
     double fnorm0;
     double fnorm;

@@ -107,6 +107,12 @@ void combine(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
 void combine_norm(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
                   int nv, const double* coef, int cstride, double* y, double* partial,
                   double* out);
+// Newton update from a Krylov basis (nv <= 16): keep = x, x -= sum_v
+// coef[p][v] z_v on active problems, out[p] = min over composite cells of
+// both fields of the new x (-1 for NaN)
+void update_min(const Dev& D, hipStream_t s, const double* Z, int64_t zstride, int nv,
+                const double* coef, int cstride, double* x, double* keep, double* partial,
+                double* out);
 // y = a_p x + b_p y elementwise (a, b per problem, host-computed device arrays)
 void axpby(const Dev& D, hipStream_t s, const double* a, const double* x,
            const double* b, double* y);

@@ -671,9 +671,15 @@ struct GmresOut {
 
 // Solves J s = rhs (rhs native, s native) for active problems with absolute
 // tolerances tol[p].  transpose: use the transposed operators.
+// b2_first: ||rhs||^2 per problem if the caller has it (saves that pass).
+// pending: if given and the solve ends within its first cycle, sol is not
+// formed: *pending returns each problem's Krylov dimension and the caller
+// applies the correction Z y (h->Z, h->y) itself; otherwise *pending is
+// returned empty and sol holds the solution.
 static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double* sol,
                          const std::vector<double>& tol, std::vector<int32_t>& its,
-                         bool transpose) {
+                         bool transpose, const std::vector<double>* b2_first = nullptr,
+                         std::vector<int32_t>* pending = nullptr) {
     Tables& t = h->t;
     const int np = t.nprob;
     const int m = h->m;
@@ -683,9 +689,8 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
     its.assign(np, 0);
     std::vector<double> beta0(np), rho(np), inv(np);
     std::vector<int32_t> kd(np);
-    // sol = 0 (write-only pass over the active problems)
-    h->D.active = h->active;
-    combine(h->D, s, nullptr, 0, 0, h->coefA, 0, sol, 0, 1.0);
+    if (pending) pending->clear();
+    bool sol_set = false;        // sol holds the corrections of earlier cycles
     std::vector<int32_t> todo = outer;
     for (int cycle = 0; cycle <= h->opt.gmres_maxrestarts; ++cycle) {
         // r = rhs - A sol  (first cycle: rhs)
@@ -710,7 +715,9 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
             axpby(h->D, s, h->coefA, h->tmp, h->coefB, h->w);
         }
         std::vector<double> b2;
-        {
+        if (cycle == 0 && b2_first) {
+            b2 = *b2_first;
+        } else {
             multidot(h->D, s, r, 0, 1, r, h->partial, h->dots);
             b2.resize(np);
             HIPCHK(hipMemcpyAsync(b2.data(), h->dots, 8 * np, hipMemcpyDeviceToHost, s));
@@ -738,15 +745,17 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
         std::vector<int32_t> live = todo;
         for (int p = 0; p < np; ++p) kd[p] = 0;
         for (int j = 0; j < m; ++j) {
-            // one iteration: z_j = P^-1 v_j, w = J z_j, CGS2 against v_0..v_j,
-            // Hessenberg column + Givens, v_{j+1} = w / ||w||.  Everything it
-            // reads that changes between calls (active mask, scalars, the
-            // preconditioner snapshot) is device-resident, so it can be
-            // captured once per j and replayed.
+            // one iteration: v_j = w / ||w|| (the previous iteration's w,
+            // scaled only now that another iteration is needed), z_j =
+            // P^-1 v_j, w = J z_j, CGS2 against v_0..v_j, Hessenberg column +
+            // Givens.  Everything it reads that changes between calls (active
+            // mask, scalars, the preconditioner snapshot) is device-resident,
+            // so it can be captured once per j and replayed.
             auto iteration = [&]() {
                 double* Vj = h->V + j * NL;
                 double* Zj = h->Z + j * NL;
                 double* wv = h->w;
+                if (j > 0) scale_copy(h->D, s, wv, h->vscale, Vj);
                 if (!transpose) {
                     pc_apply(h, Vj, Zj);
                     op_jvp(h, u, Zj, wv, true);
@@ -761,7 +770,6 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
                 combine_norm(h->D, s, h->V, NL, j + 1, h->h2, j + 1, wv, h->partial, h->hn2);
                 gmres_column(s, np, m, j, h->active, h->h1, h->h2, h->hn2, h->H, h->cs, h->sn,
                              h->g, h->rho, h->vscale);
-                scale_copy(h->D, s, wv, h->vscale, h->V + (j + 1) * NL);
             };
             if (h->opt.use_graph) {
                 hipGraphExec_t& ge = h->graphs[std::make_tuple(transpose ? 1 : 0,
@@ -826,10 +834,44 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
         HIPCHK(up(s, h->kdim, kd));
         gmres_backsolve(s, np, m, h->kdim, h->H, h->g, h->y);
         int kmax = *std::max_element(kd.begin(), kd.end());
-        combine(h->D, s, h->Z, NL, kmax, h->y, m, sol, 1, 1.0);
         bool rem = false;
         for (int p = 0; p < np; ++p) rem |= todo[p] != 0;
+        if (kmax > 0) {
+            if (!sol_set && !rem && pending) {
+                *pending = kd;               // the caller applies Z y
+                break;
+            }
+            if (!sol_set) {
+                // first correction: problems that did not iterate get sol = 0,
+                // the others sol = Z y (write-only passes)
+                std::vector<int32_t> idle(np, 0);
+                bool any_idle = false;
+                for (int p = 0; p < np; ++p) {
+                    idle[p] = outer[p] && !did[p];
+                    any_idle |= idle[p] != 0;
+                }
+                if (any_idle) {
+                    h->host_active = idle;
+                    RCHK(upload_active(h));
+                    combine(h->D, s, nullptr, 0, 0, h->coefA, 0, sol, 0, 1.0);
+                    h->host_active = did;
+                    RCHK(upload_active(h));
+                }
+                combine(h->D, s, h->Z, NL, kmax, h->y, m, sol, 0, 1.0);
+                sol_set = true;
+            } else {
+                combine(h->D, s, h->Z, NL, kmax, h->y, m, sol, 1, 1.0);
+            }
+        }
         if (!rem) break;
+    }
+    const bool deferred = pending && !pending->empty();
+    if (!sol_set && !deferred) {
+        // no correction at all: sol = 0 for every problem asked to solve
+        h->host_active = outer;
+        RCHK(upload_active(h));
+        h->D.active = h->active;
+        combine(h->D, s, nullptr, 0, 0, h->coefA, 0, sol, 0, 1.0);
     }
     h->host_active = outer;
     RCHK(upload_active(h));
@@ -897,9 +939,9 @@ static nrd_status newton(nrd_hierarchy* h, std::vector<nrd_step_stats>& st) {
         pc_setup(h, h->x, true);              // x was prepared by the residual
         // s = J^-1 F; the Newton step is -s
         h->D.active = h->active;
-        std::vector<int32_t> its;
+        std::vector<int32_t> its, pend;
         h->fd_base = h->F;                    // F(x) for Jacobian-free products
-        rc = fgmres(h, h->x, h->F, h->s, tol, its, false);
+        rc = fgmres(h, h->x, h->F, h->s, tol, its, false, &f2, &pend);
         h->fd_base = nullptr;
         if (rc) return rc;
         std::vector<int32_t> act = h->host_active;
@@ -910,48 +952,98 @@ static nrd_status newton(nrd_hierarchy* h, std::vector<nrd_step_stats>& st) {
             }
         // positivity: halve lambda until E, T > 0 on composite cells
         std::vector<double> lam(np, 1.0), mn(np);
-        std::vector<int32_t> ok(np, 0);
+        std::vector<int32_t> ok(np, 0), moved(np, 0);
         for (int p = 0; p < np; ++p) ok[p] = !act[p];
         std::vector<double> mlam(np);
-        for (int cut = 0; cut <= 30; ++cut) {
+        int cut0 = 0;
+        if (!pend.empty()) {
+            // the full step -s = -Z y from one FGMRES cycle: applied in place
+            // together with its positivity check (the iterate kept in tmp);
+            // problems whose step fails go back to the iterate and continue
+            // with half the step below
+            const int m = h->m;
+            const int64_t NL = h->nl2();
+            std::vector<int32_t> did(np, 0), bad(np, 0);
+            int kmax = 0;
+            for (int p = 0; p < np; ++p) {
+                did[p] = act[p] && pend[p] > 0;
+                kmax = std::max(kmax, did[p] ? pend[p] : 0);
+            }
+            h->host_active = did;
+            RCHK(upload_active(h));
+            h->D.active = h->active;
+            update_min(h->D, s, h->Z, NL, kmax, h->y, m, h->x, h->tmp, h->partial, h->minout);
+            HIPCHK(hipMemcpyAsync(mn.data(), h->minout, 8 * np, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            bool any_bad = false;
+            for (int p = 0; p < np; ++p) {
+                if (!act[p]) continue;
+                if (!did[p] || mn[p] > 0.0) {     // no step (F = 0) or accepted
+                    ok[p] = 1;
+                    moved[p] = did[p];
+                } else {
+                    bad[p] = 1;
+                    any_bad = true;
+                    lam[p] = 0.5;
+                    st[p].positivity_cuts += 1;
+                }
+            }
+            if (any_bad) {
+                h->host_active = bad;
+                RCHK(upload_active(h));
+                copy_interior(h->D, s, h->tmp, h->x);
+                combine(h->D, s, h->Z, NL, kmax, h->y, m, h->s, 0, 1.0);
+            }
+            cut0 = 1;
+        }
+        for (int cut = cut0; cut <= 30; ++cut) {
+            // only problems still searching need a pass
+            bool searching = false;
+            for (int p = 0; p < np; ++p) {
+                h->host_active[p] = act[p] && !ok[p] && !failed[p];
+                searching |= h->host_active[p] != 0;
+            }
+            if (!searching) break;
+            RCHK(upload_active(h));
             for (int p = 0; p < np; ++p) mlam[p] = -lam[p];      // step = -lam s
             HIPCHK(up(s, h->coefA, mlam));
             h->D.active = h->active;
             min_positive(h->D, s, h->x, h->s, h->coefA, h->partial, h->minout);
             HIPCHK(hipMemcpyAsync(mn.data(), h->minout, 8 * np, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            bool all = true;
             for (int p = 0; p < np; ++p) {
-                if (ok[p]) continue;
+                if (!h->host_active[p]) continue;
                 if (mn[p] > 0.0) {
                     ok[p] = 1;
-                } else if (cut < 30) {
-                    lam[p] *= 0.5;
-                    st[p].positivity_cuts += 1;
-                    all = false;
-                } else {
-                    failed[p] = 1;
+                    continue;
                 }
+                st[p].positivity_cuts += 1;       // every rejected trial step
+                if (cut < 30)
+                    lam[p] *= 0.5;
+                else
+                    failed[p] = 1;
             }
-            if (all) break;
-            // only problems still searching need another pass
-            for (int p = 0; p < np; ++p) h->host_active[p] = act[p] && !ok[p] && !failed[p];
-            RCHK(upload_active(h));
         }
-        for (int p = 0; p < np; ++p) h->host_active[p] = act[p] && !failed[p];
-        RCHK(upload_active(h));
-        std::vector<double> one(np, 1.0);
-        for (int p = 0; p < np; ++p) mlam[p] = -lam[p];
-        HIPCHK(up(s, h->coefA, mlam));
-        HIPCHK(up(s, h->coefB, one));
-        h->D.active = h->active;
-        axpby(h->D, s, h->coefA, h->s, h->coefB, h->x);
+        bool step = false;
+        for (int p = 0; p < np; ++p) {
+            h->host_active[p] = act[p] && !failed[p] && !moved[p];
+            step |= h->host_active[p] != 0;
+        }
+        if (step) {
+            RCHK(upload_active(h));
+            std::vector<double> one(np, 1.0);
+            for (int p = 0; p < np; ++p) mlam[p] = -lam[p];
+            HIPCHK(up(s, h->coefA, mlam));
+            HIPCHK(up(s, h->coefB, one));
+            h->D.active = h->active;
+            axpby(h->D, s, h->coefA, h->s, h->coefB, h->x);
+        }
         h->D.active = nullptr;
         op_residual(h, h->x, h->F);
         rc = dot_host(h, h->F, h->F, f2);
         if (rc) return rc;
         for (int p = 0; p < np; ++p) {
-            if (!act[p]) continue;
+            if (!act[p] || failed[p]) continue;   // iterations count accepted updates
             fn_old[p] = fn[p];
             fn[p] = std::sqrt(f2[p]);
             st[p].newton_iters += 1;

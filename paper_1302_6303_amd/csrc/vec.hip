@@ -290,6 +290,73 @@ void combine_norm(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
     k_sum_partials<<<D.nprob, kBlock, 0, s>>>(D.prob_vtile0, partial, 1, out, 1);
 }
 
+// Newton update from the Krylov basis in one pass: for every active
+// problem, keep = x, then x <- x - sum_v coef[p][v] z_v (the values of
+// combine into s followed by axpby x <- -1 s + x), and partial = the
+// minimum over the tile's composite cells of both fields of the new x (NaN
+// counts as -1), as min_positive would report for the step -s.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_update_min(
+    const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
+    const uint8_t* __restrict__ ctype, const int32_t* __restrict__ active,
+    const double* __restrict__ Z, int64_t zs, int nv, const double* __restrict__ coef, int cs,
+    double* __restrict__ x, double* __restrict__ keep, double* __restrict__ partial,
+    int64_t nl) {
+    __shared__ double sh[4];
+    const Tile t = vt[blockIdx.x];
+    double m = DBL_MAX;
+    if (!active || active[t.prob]) {
+        const PatchInfo& p = P[t.patch];
+        double cf[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) cf[v] = (v < nv) ? coef[t.prob * cs + v] : 0.0;
+        const bool cov = p.flags & PF_COVERED;
+        for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+            const int c = interior_index(p, lin);
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < nv && cf[v] != 0.0) {
+                    s0 += cf[v] * Z[v * zs + c];
+                    s1 += cf[v] * Z[v * zs + c + nl];
+                }
+            const double x0 = x[c], x1 = x[c + nl];
+            keep[c] = x0;
+            keep[c + nl] = x1;
+            const double e = -1.0 * s0 + 1.0 * x0;
+            const double tt = -1.0 * s1 + 1.0 * x1;
+            x[c] = e;
+            x[c + nl] = tt;
+            if (cov && (ctype[c] & CT_COVERED)) continue;
+            m = fmin(m, (e == e && tt == tt) ? fmin(e, tt) : -1.0);
+        }
+    }
+    const double r = block_min(m, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+void update_min(const Dev& D, hipStream_t s, const double* Z, int64_t zstride, int nv,
+                const double* coef, int cstride, double* x, double* keep, double* partial,
+                double* out) {
+    if (nv <= 1)
+        k_update_min<1><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, Z,
+                                                     zstride, nv, coef, cstride, x, keep,
+                                                     partial, D.nl);
+    else if (nv <= 4)
+        k_update_min<4><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, Z,
+                                                     zstride, nv, coef, cstride, x, keep,
+                                                     partial, D.nl);
+    else if (nv <= 8)
+        k_update_min<8><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, Z,
+                                                     zstride, nv, coef, cstride, x, keep,
+                                                     partial, D.nl);
+    else
+        k_update_min<16><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, Z,
+                                                      zstride, nv, coef, cstride, x, keep,
+                                                      partial, D.nl);
+    k_min_partials<<<D.nprob, kBlock, 0, s>>>(D.prob_vtile0, partial, out);
+}
+
 __global__ __launch_bounds__(kBlock) void k_axpby(const Tile* __restrict__ vt,
                                                   const PatchInfo* __restrict__ P,
                                                   const int32_t* __restrict__ active,

@@ -173,6 +173,64 @@ def test_implicit_steps_parity(name):
             assert rel_err(got[sl], st.u[sl]) < 1e-8
 
 
+def _far_from_equilibrium(specs):
+    """6^3 problems with E = E0 exp(U(-2, 2)) and T = exp(U(-1, 1)) per cell
+    (seeded): radiation far below the material temperature."""
+    problems, boxes, z, E, T = [], [], [], [], []
+    for p, (seed, E0) in enumerate(specs):
+        w1 = I.marshak_single(6)
+        rng = np.random.default_rng(seed)
+        sh = w1.boxes[0].shape
+        problems.append(w1.problems[0])
+        boxes.append(I.Box(p, 0, (0, 0, 0), sh))
+        z.append(w1.z[0])
+        E.append(E0 * np.exp(rng.uniform(-2, 2, sh)))
+        T.append(np.exp(rng.uniform(-1, 1, sh)))
+    return I.Workload("far", problems, boxes, z, E, T, np.full(len(specs), 1e-2))
+
+
+def _cut_parity(specs):
+    from oracle.solvers import Stepper
+    from tests.gpu_helpers import problem_slices
+    w = _far_from_equilibrium(specs)
+    H = make(w, newton_rtol=1e-10, newton_atol=1e-16, newton_maxit=24, bdf_max_order=1)
+    rc, stats = H.implicit_step([1e-2] * len(specs), raise_on_fail=False)
+    E, T = H.get_fields()
+    got = np.concatenate([to_host(E), to_host(T)])
+    sl = problem_slices(w)
+    res = []
+    for p in range(len(specs)):
+        s = system(w, pidx=p)
+        st = Stepper(s, state(s, w, pidx=p), rtol=1e-10, atol=1e-16, maxit=24)
+        r = st.step(1e-2)
+        assert bool(stats[p]["converged"]) == bool(r.converged)
+        assert stats[p]["newton_iters"] == r.iters
+        assert stats[p]["positivity_cuts"] == r.cuts
+        g = got[sl[p]]
+        n = s.nc
+        for f in (slice(0, n), slice(n, 2 * n)):
+            assert rel_err(g[f], st.u[f]) < 1e-8
+        res.append(r)
+    return rc, res
+
+
+def test_implicit_step_positivity_cuts_in_lock_step():
+    """One BDF1 step of three problems solved together whose full Newton
+    steps are accepted (seed 21) or halved (seeds 20, 25), each against its
+    own oracle run: Newton iterations and cuts equal, states to 1e-8."""
+    rc, res = _cut_parity([(20, 1e-4), (21, 1e-4), (25, 1e-2)])
+    assert rc == 0
+    assert res[1].cuts == 0 and res[0].cuts > 0 and res[2].cuts > 0
+
+
+def test_implicit_step_positivity_stall():
+    """Seed 23: every Newton step needs halving until one cannot be made
+    positive at all; the oracle gives up at the same iteration with the same
+    number of rejected trial steps, and the state is left unchanged."""
+    rc, res = _cut_parity([(23, 1e-4)])
+    assert rc == -5 and not res[0].converged
+
+
 @pytest.mark.parametrize("stencil", [0, 1, 2, 3])
 def test_per_patch_launches_match_batched_bitwise(stencil):
     """One launch per patch and one launch over the whole patch table run the
