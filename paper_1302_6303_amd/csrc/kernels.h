@@ -102,6 +102,10 @@ void min_positive(const Dev& D, hipStream_t s, const double* u, const double* du
 void combine(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
              int nv, const double* coef, int cstride, double* y, int accumulate,
              double alpha);
+// y -= sum_v coef[p][v] x_v, then out[p * nv + v] = x_v . y (one pass for
+// nv <= 16; the values of combine followed by multidot)
+void combine_dot(const Dev& D, hipStream_t s, const double* X, int64_t xstride, int nv,
+                 const double* coef, int cstride, double* y, double* partial, double* out);
 // y -= sum_v coef[p][v] x_v, then out[p] = ||y||^2 (composite, volume
 // weighted) in the same pass over y
 void combine_norm(const Dev& D, hipStream_t s, const double* X, int64_t xstride,

@@ -74,7 +74,8 @@ struct nrd_hierarchy final : public Clock {
         size_t patches, tiles, stiles, vtiles, prob_vtile0, gcopy, gcf, sib, sync[kMaxLev], rfaces,
             rcells, ctype, shadows, shadow_src, coff, ps, active;
         size_t mg_box[kMaxMG], mg_tiles[kMaxMG], mg_box_of[kMaxMG], mg_smooth[kMaxMG],
-            mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bottom_off, Lbuf, Xbuf;
+            mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bot_probs, bot_boxes, bot_grid, bottom_off,
+            Lbuf, Xbuf;
         size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, gz3, V, Z;
         size_t pc_D, pc_sigma, pc_e, pc_u, pc_r, pc_f, pc_tmp, pc_shadow;
         size_t mg_D[kMaxMG], mg_e[kMaxMG], mg_f[kMaxMG], mg_r[kMaxMG];
@@ -200,6 +201,9 @@ static void layout(nrd_hierarchy* h) {
         o.mg_bprobs[g] = b.take(sizeof(int32_t) * nprob);
         o.mg_bboxes[g] = b.take(sizeof(int32_t) * nprob);
     }
+    o.bot_probs = b.take(sizeof(int32_t) * nprob);
+    o.bot_boxes = b.take(sizeof(int32_t) * nprob);
+    o.bot_grid = b.take(sizeof(int32_t) * nprob);
     o.bottom_off = b.take(sizeof(int64_t) * nprob);
     int64_t bsum = 0;
     for (int p = 0; p < nprob; ++p) {
@@ -309,6 +313,10 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
         pc.mg.bottom_boxes[g] = h->at<int32_t>(o.mg_bboxes[g]);
     }
     pc.mg.bottom_off = h->at<int64_t>(o.bottom_off);
+    pc.mg.bot_probs = h->at<int32_t>(o.bot_probs);
+    pc.mg.bot_boxes = h->at<int32_t>(o.bot_boxes);
+    pc.mg.bot_grid = h->at<int32_t>(o.bot_grid);
+    pc.mg.nbot_all = t.nprob;
     pc.mg.Lbuf = h->at<double>(o.Lbuf);
     pc.mg.Xbuf = h->at<double>(o.Xbuf);
     pc.p2_mode = h->opt.p2_mode;
@@ -377,6 +385,17 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     std::vector<int64_t> boff(t.nprob);
     for (int p = 0; p < t.nprob; ++p) boff[p] = t.bottom_off[p];
     HIPCHK(up(s, h->ws + o.bottom_off, boff));
+    std::vector<int32_t> bpa, bba, bga;
+    for (int g = 0; g <= G; ++g)
+        for (int p = 0; p < t.nprob; ++p)
+            if (t.prob_mgdepth[p] == g) {
+                bpa.push_back(p);
+                bba.push_back(box_of[g][p]);
+                bga.push_back(g);
+            }
+    HIPCHK(up(s, h->ws + o.bot_probs, bpa));
+    HIPCHK(up(s, h->ws + o.bot_boxes, bba));
+    HIPCHK(up(s, h->ws + o.bot_grid, bga));
     // device views
     Dev& D = h->D;
     D.nl = t.nl;
@@ -765,8 +784,7 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
                     vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], u, Zj, wv, h->gz3);
                 }
                 multidot(h->D, s, h->V, NL, j + 1, wv, h->partial, h->h1);
-                combine(h->D, s, h->V, NL, j + 1, h->h1, j + 1, wv, 1, -1.0);
-                multidot(h->D, s, h->V, NL, j + 1, wv, h->partial, h->h2);
+                combine_dot(h->D, s, h->V, NL, j + 1, h->h1, j + 1, wv, h->partial, h->h2);
                 combine_norm(h->D, s, h->V, NL, j + 1, h->h2, j + 1, wv, h->partial, h->hn2);
                 gmres_column(s, np, m, j, h->active, h->h1, h->h2, h->hn2, h->H, h->cs, h->sn,
                              h->g, h->rho, h->vscale);

@@ -25,6 +25,15 @@ struct MGDev {
     double* Xbuf = nullptr;
 };
 
+// Per multigrid grid: box table, face coefficients, field length (kernel
+// argument of the merged bottom-solve setup).
+template <typename PT>
+struct BottomGrids {
+    const PatchInfo* P[kMaxMG] = {};
+    const PT* D[kMaxMG] = {};
+    int64_t nl[kMaxMG] = {};
+};
+
 template <typename PT>
 struct PcArrays {
     const Dev* D = nullptr;
@@ -54,6 +63,11 @@ struct PcArrays {
         const int64_t* bottom_off = nullptr;
         double* Lbuf = nullptr;
         double* Xbuf = nullptr;
+        // all problems with their coarsest grid (one setup launch)
+        const int32_t* bot_probs = nullptr;
+        const int32_t* bot_boxes = nullptr;
+        const int32_t* bot_grid = nullptr;
+        int nbot_all = 0;
         PT* Dg[kMaxMG] = {};
         PT* eg[kMaxMG] = {};
         PT* fg[kMaxMG] = {};

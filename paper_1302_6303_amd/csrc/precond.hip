@@ -530,8 +530,8 @@ constexpr int kBottomThreads = 4 * kBottomMax;   // four threads per inverse col
 template <typename PT>
 __global__ __launch_bounds__(kBottomThreads) void k_bottom_setup(const int32_t* __restrict__ act, 
     const int32_t* __restrict__ probs, const int32_t* __restrict__ boxes,
-    const PatchInfo* __restrict__ P, const ProbScalars* __restrict__ ps,
-    const PT* __restrict__ D, int64_t nl, const int64_t* __restrict__ boff,
+    const int32_t* __restrict__ grids, const BottomGrids<PT> G,
+    const ProbScalars* __restrict__ ps, const int64_t* __restrict__ boff,
     double* __restrict__ X) {
     __shared__ double A[kBottomMax * kBandLd];   // A(i, i - d) at [i kBandLd + d]
     __shared__ double Ld[kBottomMax];            // diagonal of L
@@ -540,7 +540,10 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom_setup(const int32_t* 
     const int fld = blockIdx.x & 1;
     const int prob = probs[pi];
     if (act && !act[prob]) return;
-    const PatchInfo& p = P[boxes[pi]];
+    const int g = grids[pi];                    // the problem's coarsest grid
+    const PatchInfo& p = G.P[g][boxes[pi]];
+    const PT* __restrict__ D = G.D[g];
+    const int64_t nl = G.nl[g];
     const double beta = ps[prob].beta;
     const int N = p.ncell;                      // <= kBottomMax (checked on the host)
     const BottomOrder o = bottom_order(p);
@@ -806,14 +809,17 @@ void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
                                                          mg.box_of[g - 1], Df, nlf, mg.Dg[g],
                                                          mg.len[g]);
     }
+    // every problem's coarsest grid in one launch
+    BottomGrids<PT> bg;
     for (int g = 0; g <= mg.G; ++g) {
-        if (mg.nbottom[g] == 0) continue;
-        const PT* Dg = (g == 0) ? Dface : mg.Dg[g];
-        const int64_t nlg = (g == 0) ? d.nl : mg.len[g];
-        const PatchInfo* Pg = (g == 0) ? d.patches : mg.box[g];
-        k_bottom_setup<PT><<<2 * mg.nbottom[g], kBottomThreads, 0, s>>>(d.active, 
-            mg.bottom_probs[g], mg.bottom_boxes[g], Pg, d.ps, Dg, nlg, mg.bottom_off, mg.Xbuf);
+        bg.P[g] = (g == 0) ? d.patches : mg.box[g];
+        bg.D[g] = (g == 0) ? Dface : mg.Dg[g];
+        bg.nl[g] = (g == 0) ? d.nl : mg.len[g];
     }
+    if (mg.nbot_all > 0)
+        k_bottom_setup<PT><<<2 * mg.nbot_all, kBottomThreads, 0, s>>>(
+            d.active, mg.bot_probs, mg.bot_boxes, mg.bot_grid, bg, d.ps, mg.bottom_off,
+            mg.Xbuf);
 }
 
 template <typename PT>

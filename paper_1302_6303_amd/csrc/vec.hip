@@ -224,6 +224,84 @@ void combine(const Dev& D, hipStream_t s, const double* X, int64_t xstride, int 
     }
 }
 
+// y -= sum_v coef[p][v] x_v (combine with alpha = -1, accumulating) and, in
+// the same pass, out[p][v] = x_v . y of the new y (multidot), nv <= 16: the
+// first Gram-Schmidt correction of FGMRES followed by the inner products of
+// the second, with the expressions of those two kernels.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_combine_dot(
+    const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
+    const uint8_t* __restrict__ ctype, const int32_t* __restrict__ active,
+    const double* __restrict__ X, int64_t xs, int nv, const double* __restrict__ coef, int cs,
+    double* __restrict__ y, double* __restrict__ partial, int64_t nl) {
+    __shared__ double sh[4];
+    const Tile t = vt[blockIdx.x];
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    const bool on = !active || active[t.prob];
+    const PatchInfo& p = P[t.patch];
+    if (on) {
+        double cf[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) cf[v] = (v < nv) ? -1.0 * coef[t.prob * cs + v] : 0.0;
+        const bool cov = p.flags & PF_COVERED;
+        for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+            const int c = interior_index(p, lin);
+            double a0 = y[c], a1 = y[c + nl];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < nv && cf[v] != 0.0) {
+                    a0 += cf[v] * X[v * xs + c];
+                    a1 += cf[v] * X[v * xs + c + nl];
+                }
+            y[c] = a0;
+            y[c + nl] = a1;
+            if (cov && (ctype[c] & CT_COVERED)) continue;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < nv) acc[v] += X[v * xs + c] * a0 + X[v * xs + c + nl] * a1;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (v < nv) {
+            const double sv = block_sum(acc[v], sh);
+            if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * nv + v] = sv * p.vol;
+        }
+    }
+}
+
+void combine_dot(const Dev& D, hipStream_t s, const double* X, int64_t xstride, int nv,
+                 const double* coef, int cstride, double* y, double* partial, double* out) {
+    if (nv > 16) {
+        combine(D, s, X, xstride, nv, coef, cstride, y, 1, -1.0);
+        multidot(D, s, X, xstride, nv, y, partial, out);
+        return;
+    }
+    if (nv <= 1)
+        k_combine_dot<1><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, X,
+                                                      xstride, nv, coef, cstride, y, partial,
+                                                      D.nl);
+    else if (nv <= 2)
+        k_combine_dot<2><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, X,
+                                                      xstride, nv, coef, cstride, y, partial,
+                                                      D.nl);
+    else if (nv <= 4)
+        k_combine_dot<4><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, X,
+                                                      xstride, nv, coef, cstride, y, partial,
+                                                      D.nl);
+    else if (nv <= 8)
+        k_combine_dot<8><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, X,
+                                                      xstride, nv, coef, cstride, y, partial,
+                                                      D.nl);
+    else
+        k_combine_dot<16><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
+                                                       X, xstride, nv, coef, cstride, y, partial,
+                                                       D.nl);
+    k_sum_partials<<<D.nprob, kBlock, 0, s>>>(D.prob_vtile0, partial, nv, out, nv);
+}
+
 // y -= sum_v coef[p][v] x_v (accumulating into y) and, in the same pass,
 // out[p] = ||y||^2 (volume weighted over composite cells; fixed-order
 // two-stage sum).  The second Gram-Schmidt pass of FGMRES ends with the

@@ -117,26 +117,30 @@ def test_precond_parity(name):
 
 
 def test_precond_parity_noncubic():
-    """Preconditioner of the 80 x 48 x 48 problem (four multigrid grids
-    below it, Marshak faces on two sides) against the oracle."""
-    full = boxes_workload()
-    w = I.Workload("p0", full.problems[:1], full.boxes[:1], full.z[:1], full.E[:1],
-                   full.T[:1], full.dt[:1])
-    s = system(w)
+    """Preconditioner of three non-cubic problems in one hierarchy (their
+    coarsest grids are 2, 3 and 4 grids down; Marshak faces on two sides of
+    the first), each problem against its own oracle."""
+    from tests.gpu_helpers import problem_slices
+    w = boxes_workload()
     H = make(w)
-    dt = 2e-3
-    H.begin_step([dt])
-    u = s.sync(state(s, w) * np.random.default_rng(12).uniform(0.9, 1.1, 2 * s.nc))
+    dts = [float(x) for x in w.dt]
+    H.begin_step(dts)
+    rng = np.random.default_rng(12)
+    u = compact_state(w) * rng.uniform(0.9, 1.1, 2 * w.ncells())
     wv = np.random.default_rng(13).standard_normal(u.shape)
     H.precond_setup(native_from_compact(H, u))
     y = H.native()
     H.precond_apply(native_from_compact(H, wv), y)
     got = compact_from_native(H, y)
-    P, _ = s.precond(u, dt)
-    ref = P(wv)
-    n = s.nc
-    for sl in (slice(0, n), slice(n, 2 * n)):
-        assert rel_err(got[sl], ref[sl]) < 1e-10
+    sl = problem_slices(w)
+    for p in range(len(w.problems)):
+        s = system(w, pidx=p)
+        P, _ = s.precond(u[sl[p]], dts[p])
+        ref = P(wv[sl[p]])
+        g = got[sl[p]]
+        n = s.nc
+        for f in (slice(0, n), slice(n, 2 * n)):
+            assert rel_err(g[f], ref[f]) < 1e-10
 
 
 @pytest.mark.parametrize("name", ["uniform16", "uniform10"])
