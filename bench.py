@@ -293,6 +293,10 @@ def main():
     ap.add_argument("--graph", type=int, default=0,
                     help="1: capture FGMRES iterations as HIP graphs in the mixed run "
                          "(measured slower than direct launches on this software stack)")
+    ap.add_argument("--bdf-max-order", type=int, default=2,
+                    help="2: BDF1 first step then BDF2; 1: BDF1 throughout")
+    ap.add_argument("--dt-scale", type=float, default=1.0,
+                    help="multiplies every problem's time step")
     ap.add_argument("--ckpt-every", type=int, default=10,
                     help="adjoint workload: checkpoint interval")
     ap.add_argument("--fp64-batched", action="store_true",
@@ -309,10 +313,13 @@ def main():
         adjoint_bench(a.steps, a.ckpt_every)
         return
     w = workload(a.workload)
+    if a.dt_scale != 1.0:
+        w.dt = w.dt * a.dt_scale
     ncomp = composite_cells(w)
     use_graph = a.graph
     mixed = run_solver(w, nrd.default_options(precision=nrd.NRD_MIXED,
-                                              launch=nrd.NRD_BATCHED, use_graph=use_graph),
+                                              launch=nrd.NRD_BATCHED, use_graph=use_graph,
+                                              bdf_max_order=a.bdf_max_order),
                        a.steps, a.warmup, True)
     mixed["use_graph"] = use_graph
     plain = None
@@ -320,12 +327,14 @@ def main():
         # per-patch launches need many workgroups per patch: the register
         # plane-marching stencil with short z chunks suits them best
         plain = run_solver(w, nrd.default_options(precision=nrd.NRD_FP64,
-                                                  launch=nrd.NRD_PER_PATCH, stencil=1),
+                                                  launch=nrd.NRD_PER_PATCH, stencil=1,
+                                                  bdf_max_order=a.bdf_max_order),
                            a.steps, a.warmup, False)
     batched64 = None
     if a.fp64_batched:
         batched64 = run_solver(w, nrd.default_options(precision=nrd.NRD_FP64,
-                                                      launch=nrd.NRD_BATCHED),
+                                                      launch=nrd.NRD_BATCHED,
+                                                      bdf_max_order=a.bdf_max_order),
                                a.steps, a.warmup, False)
     res_s = mixed["residual_ms_avg"] / 1e3
     gcells = ncomp / res_s / 1e9
@@ -357,7 +366,9 @@ def main():
         "config": {"workload": a.workload, "problems": len(w.problems),
                    "boxes": len(w.boxes), "cells": w.ncells(),
                    "composite_cells": ncomp,
-                   "solver": "BDF1->BDF2, Newton rtol 1e-8, FGMRES(30), FAC V(1,0) + MG V(1,1)"},
+                   "dt_scale": a.dt_scale,
+                   "solver": ("BDF1->BDF2" if a.bdf_max_order == 2 else "BDF1") +
+                             ", Newton rtol 1e-8, FGMRES(30), FAC V(1,0) + MG V(1,1)"},
         "roofline": {"bound": "hbm", "kernel": "k_stencil_s<0> (residual)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
