@@ -1601,8 +1601,7 @@ nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed
     const int32_t run0 = var == 2 ? 4 * 63 : (var == 3 ? kStageCells : 256);
     std::vector<std::pair<int32_t, int32_t>> cand;           // (planes, run)
     if (var == 3) {
-        for (int kc : {4, 8, 16, 32})
-            for (int run : {256, kStageCells}) cand.push_back({kc, run});
+        for (int kc : {4, 8, 16, 32}) cand.push_back({kc, kStageCells});
     } else {
         for (int kc : {2, 4, 8, 16}) cand.push_back({kc, run0});
     }

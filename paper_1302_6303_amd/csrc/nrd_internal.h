@@ -152,11 +152,13 @@ struct Tables {
 // Band storage per row of the coarsest-grid Cholesky factor (b + 1).
 constexpr int32_t kBottomBand = 26;
 
-// Staged-plane stencil tiles: at most kStageCells cells of a plane per tile,
-// whose ghosted-plane slice (the run plus its x / y neighbours) holds at most
+// Staged-plane stencil tiles: at most kStageCells cells of a plane per tile
+// (one per thread: 256-cell runs keep the kernel at 78 registers and 20 KB of
+// LDS, six waves per SIMD, faster than two cells per thread at four), whose
+// ghosted-plane slice (the run plus its x / y neighbours) holds at most
 // kStageLen values.
-constexpr int32_t kStageCells = 512;
-constexpr int32_t kStageLen = 768;
+constexpr int32_t kStageCells = 256;
+constexpr int32_t kStageLen = 512;
 
 // Plane-marching tiles: planes per tile (z chunk) of each patch.
 int32_t default_zchunk(const int32_t n[3], int32_t variant);

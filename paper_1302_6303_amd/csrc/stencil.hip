@@ -574,7 +574,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil_flat(
 // outside the run), the z face carried in registers to the next plane.  The
 // next plane's slice is loaded into registers while the current faces are
 // evaluated.
-static_assert(kStageCells == 2 * kBlock, "two cells per thread");
+constexpr int kStageCPT = kStageCells / kBlock;    // cells per thread
+static_assert(kStageCells == kStageCPT * kBlock, "whole cells per thread");
 constexpr int kStagePer = (kStageLen + kBlock - 1) / kBlock;
 
 template <int MODE>
@@ -613,10 +614,10 @@ __global__ __launch_bounds__(kBlock) void k_stencil_s(
         src[NA - 1] = v + nl;
     }
     // per cell (r = 0, 1): run index, coordinates, slice index, native index
-    int ix[2], jx[2], sidx[2], cn[2];
-    bool live[2];
+    int ix[kStageCPT], jx[kStageCPT], sidx[kStageCPT], cn[kStageCPT];
+    bool live[kStageCPT];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < kStageCPT; ++r) {
         const int idx = tid + r * kBlock;
         live[r] = idx < t.cnt;
         const int lin = t.s0 + (live[r] ? idx : 0);
@@ -633,10 +634,10 @@ __global__ __launch_bounds__(kBlock) void k_stencil_s(
             for (int e = tid; e < len; e += kBlock) sl[a][e] = src[a][base + e];
     }
     __syncthreads();
-    double oE[2], oT[2], oz[2], odE[2], odT[2];          // own values, plane k
-    double czE[2], czT[2];                               // low z face fluxes
+    double oE[kStageCPT], oT[kStageCPT], oz[kStageCPT], odE[kStageCPT], odT[kStageCPT];          // own values, plane k
+    double czE[kStageCPT], czT[kStageCPT];                               // low z face fluxes
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < kStageCPT; ++r) {
         oE[r] = sl[0][sidx[r]];
         oT[r] = sl[1][sidx[r]];
         oz[r] = sl[2][sidx[r]];
@@ -671,10 +672,10 @@ __global__ __launch_bounds__(kBlock) void k_stencil_s(
                     pre[a][w] = (e < len) ? src[a][base + e] : 0.0;
                 }
         }
-        double bE[2] = {0.0, 0.0}, bT[2] = {0.0, 0.0};
+        double bE[kStageCPT] = {}, bT[kStageCPT] = {};
         if (MODE == 0) {
 #pragma unroll
-            for (int r = 0; r < 2; ++r)
+            for (int r = 0; r < kStageCPT; ++r)
                 if (live[r]) {
                     const int c = cn[r] + sz * (k + 1);
                     bE[r] = b[c];
@@ -682,9 +683,10 @@ __global__ __launch_bounds__(kBlock) void k_stencil_s(
                 }
         }
         // phase A: faces from the staged plane k
-        double lxE[2], lxT[2], lyE[2], lyT[2], hxE[2], hxT[2], hyE[2], hyT[2];
+        double lxE[kStageCPT], lxT[kStageCPT], lyE[kStageCPT], lyT[kStageCPT], hxE[kStageCPT],
+            hxT[kStageCPT], hyE[kStageCPT], hyT[kStageCPT];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < kStageCPT; ++r) {
             lxE[r] = lxT[r] = lyE[r] = lyT[r] = hxE[r] = hxT[r] = hyE[r] = hyT[r] = 0.0;
             if (!live[r]) continue;
             const int idx = tid + r * kBlock;
@@ -724,7 +726,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_s(
         __syncthreads();
         // phase B: publish low fluxes, stage plane k + 1
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < kStageCPT; ++r) {
             const int idx = tid + r * kBlock;
             fl[0][idx] = lxE[r];
             fl[1][idx] = lxT[r];
@@ -741,7 +743,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_s(
         __syncthreads();
         // phase C: high faces, z faces, cell terms
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < kStageCPT; ++r) {
             const int idx = tid + r * kBlock;
             const int si = sidx[r];
             const double nE = sl[0][si], nT = sl[1][si], nz3 = sl[2][si];
