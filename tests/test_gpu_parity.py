@@ -38,8 +38,21 @@ def boxes_workload():
     return I.Workload("boxes3", problems, boxes, z, E, T, np.array([2e-3, 1e-3, 5e-4]))
 
 
+def odd_workload():
+    """One 5 x 7 x 3 patch: odd extents, an odd block size and an odd plane
+    stride (7 * 9); its coarsest multigrid grid is the patch itself."""
+    rng = np.random.default_rng(17)
+    prob = I.Problem(base_n=(5, 7, 3))
+    box = I.Box(0, 0, (0, 0, 0), (5, 7, 3))
+    zf = I.box_field(I.sample_material_boxes(rng, 2))
+    z = [zf(*I.cell_centres(prob, box))]
+    E, T = I.front_state([prob], [box], rng)
+    return I.Workload("odd573", [prob], [box], z, E, T, np.array([1e-3]))
+
+
 def workloads():
     return {
+        "odd573": odd_workload,
         "uniform16": lambda: I.marshak_single(16, state="front"),
         "uniform10": lambda: I.uniform_workload(
             "u10", 10, I.box_field(I.sample_material_boxes(np.random.default_rng(3), 2)),
