@@ -49,9 +49,9 @@ HBM_PEAK_GBS = 8000.0
 # FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch, FETCH scaled by the
 # factor a plain 2 GiB copy reads in the same run, WRITE by its own factor),
 # valid for the stencil source with this SHA-256 prefix; null otherwise.
-MEASURED_TRAFFIC = {"workload": "ensemble", "stencil_sha256": "61bbfb8000a36a01",
-                    "bytes_per_launch": 1347216612,
-                    "fetch_bytes": 989381824, "write_bytes": 357834788,
+MEASURED_TRAFFIC = {"workload": "ensemble", "stencil_sha256": "2fa3d00d82a23e09",
+                    "bytes_per_launch": 1374843722,
+                    "fetch_bytes": 1015851861, "write_bytes": 358991861,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 
 
