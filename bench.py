@@ -4,9 +4,10 @@ One step = one BDF implicit step (inexact Newton, FGMRES, FAC/multigrid
 preconditioner, flux-limited residual and Jacobian action) over every problem
 of the workload.  Prints ONE JSON line:
 
-  value        residual throughput in Gcells/s (composite cells per second of
-               the residual kernel, timed with HIP events on the library
-               stream during the timed implicit steps)
+  value        residual throughput in Gcells/s: composite cells covered by the
+               residual launches of the timed implicit steps (after the first
+               Newton update a launch covers only the problems still
+               iterating) over their HIP-event time on the library stream
   ms_per_step  wall time per implicit step of the mixed-precision batched
                solver (float V-cycles, float64 Newton/GMRES/residual)
   fp64_plain   the same steps with a float64 preconditioner and one kernel
@@ -20,7 +21,8 @@ Workloads (seeded, synthetic; --workload):
   amr       64^3 base + 2 levels of static refinement around two material
             boxes (228 patches, 1.04 M composite+covered cells), dt = 5e-4
   amr128    128^3 base + 3 levels around six material boxes (2794 patches,
-            39 M cells), dt = 5e-4
+            39 M cells), dt = 5e-4; run with --bdf-max-order 1 (BDF2 stalls
+            at the second step without time-step control)
   uniform   one 32^3 patch, dt = 1e-3
   adjoint   64^3 smooth random material, 50 BDF1 steps: forward, checkpointed
             reverse sweep, transpose kernel
@@ -45,13 +47,15 @@ BYTES_PER_CELL_SWEEP = 36
 BYTES_PER_CELL_SWEEP_ZERO = 28
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per residual launch on the ensemble workload from rocprofv3
-# FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch, FETCH scaled by the
-# factor a plain 2 GiB copy reads in the same run, WRITE by its own factor),
-# valid for the stencil source with this SHA-256 prefix; null otherwise.
+# HBM bytes per composite cell of the residual on the ensemble workload from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch, FETCH scaled by
+# the factor a plain 2 GiB copy reads in the same run, WRITE by its own
+# factor; launches of one implicit step over the cells they covered), valid
+# for the stencil source with this SHA-256 prefix; null otherwise.
 MEASURED_TRAFFIC = {"workload": "ensemble", "stencil_sha256": "2fa3d00d82a23e09",
-                    "bytes_per_launch": 1374843722,
-                    "fetch_bytes": 1015851861, "write_bytes": 358991861,
+                    "bytes_per_cell": 63.5590,
+                    "fetch_bytes_per_cell": 46.9628,
+                    "write_bytes_per_cell": 16.5962,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -143,13 +147,18 @@ def run_solver(w, opts, steps, warmup, time_residual):
     if time_residual:
         # residual evaluations inside the timed steps always cover every
         # problem (Newton evaluates F for all of them)
+        # launches after the first Newton update cover only the problems
+        # still iterating: rates use the composite cells each launch covered
         ms, cnt = H.timer_read(nrd.NRD_TIMER_RESIDUAL)
+        cells = H.timer_cells(nrd.NRD_TIMER_RESIDUAL)
         res["residual_ms_avg"] = ms / max(cnt, 1)
         res["residual_launches"] = cnt
+        res["residual_cells_avg"] = cells / max(cnt, 1)
         H.timer_enable(False)
-        # Jacobian action and preconditioner inside the steps skip problems
-        # that have converged, so their rates are taken from calls over all
-        # problems on the final state (3 warm-up calls, 20 timed)
+        # the operators again over all problems on the final state (3 warm-up
+        # calls, 20 timed each): the Jacobian action and preconditioner skip
+        # converged problems inside the steps, and full residual launches
+        # complement the timed-region rate above
         H.begin_step(dt)
         E, T = H.get_fields()
         U = H.unpack(torch.cat([E, T]))
@@ -162,10 +171,13 @@ def run_solver(w, opts, steps, warmup, time_residual):
         torch.cuda.synchronize()
         H.timer_enable(True)
         for _ in range(20):
+            H.residual(U, Y)
+        for _ in range(20):
             H.jvp(U, V, Y)
         for _ in range(20):
             H.precond_apply(V, Y)
-        for key, which in (("jvp", nrd.NRD_TIMER_JVP), ("precond", nrd.NRD_TIMER_PRECOND),
+        for key, which in (("residual_full", nrd.NRD_TIMER_RESIDUAL),
+                           ("jvp", nrd.NRD_TIMER_JVP), ("precond", nrd.NRD_TIMER_PRECOND),
                            ("sweep", nrd.NRD_TIMER_SMOOTH),
                            ("sweep_zero", nrd.NRD_TIMER_SMOOTH_ZERO)):
             ms, cnt = H.timer_read(which)
@@ -337,12 +349,13 @@ def main():
                                                       bdf_max_order=a.bdf_max_order),
                                a.steps, a.warmup, False)
     res_s = mixed["residual_ms_avg"] / 1e3
-    gcells = ncomp / res_s / 1e9
-    achieved = BYTES_PER_CELL_RESIDUAL * ncomp / res_s / 1e9
+    res_cells = mixed["residual_cells_avg"]           # per launch, average
+    gcells = res_cells / res_s / 1e9
+    achieved = BYTES_PER_CELL_RESIDUAL * res_cells / res_s / 1e9
     traffic = None
     if (MEASURED_TRAFFIC and MEASURED_TRAFFIC["workload"] == a.workload
             and MEASURED_TRAFFIC["stencil_sha256"] == stencil_source_hash()):
-        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+        traffic = round(MEASURED_TRAFFIC["bytes_per_cell"] * res_cells)
     jvp_s = mixed["jvp_ms_avg"] / 1e3
     base_cells = sum(b.ncells for b in w.boxes if b.level == 0)
     def gbs(nbytes, ms):
@@ -373,8 +386,16 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_cell": BYTES_PER_CELL_RESIDUAL,
-                     "bytes_per_launch": BYTES_PER_CELL_RESIDUAL * ncomp,
-                     "avg_launch_ms": round(mixed["residual_ms_avg"], 4)},
+                     "cells_per_launch": round(res_cells),
+                     "bytes_per_launch": round(BYTES_PER_CELL_RESIDUAL * res_cells),
+                     "avg_launch_ms": round(mixed["residual_ms_avg"], 4),
+                     "full_launch": {
+                         "cells": ncomp,
+                         "avg_launch_ms": round(mixed["residual_full_ms_avg"], 4),
+                         "achieved": round(BYTES_PER_CELL_RESIDUAL * ncomp /
+                                           mixed["residual_full_ms_avg"] / 1e6, 1),
+                         "frac": round(BYTES_PER_CELL_RESIDUAL * ncomp /
+                                       mixed["residual_full_ms_avg"] / 1e6 / HBM_PEAK_GBS, 4)}},
         "jvp_roofline": {"kernel": "k_stencil_s<1> (Jacobian action)",
                          "achieved": round(BYTES_PER_CELL_JVP * ncomp / jvp_s / 1e9, 1),
                          "unit": "GB/s",

@@ -267,6 +267,13 @@ enum { NRD_TIMER_RESIDUAL = 0, NRD_TIMER_JVP = 1, NRD_TIMER_PRECOND = 2,
        NRD_TIMER_SMOOTH = 3, NRD_TIMER_SMOOTH_ZERO = 4, NRD_TIMER_COUNT = 5 };
 nrd_status nrd_timer_enable(nrd_hierarchy* h, int32_t on);
 
+/* Composite cells covered by the timed calls of a RESIDUAL or JVP timer
+ * since nrd_timer_enable (a call over the problems still iterating in a
+ * lock-step Newton solve covers only theirs); 0 for the other timers.  With
+ * nrd_timer_read this gives the operator's cells per second.  NRD_EINVAL for
+ * an unknown timer. */
+nrd_status nrd_timer_cells(nrd_hierarchy* h, int32_t which, int64_t* cells);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,8 +92,11 @@ void vjp(const Dev& D, hipStream_t s, int t0, int nt, const double* u,
 // Deterministic per-problem reductions over vtiles.
 //   out[p * nv + v] = sum over composite cells of problem p of
 //                     vol * (x_v . y) (both fields), x_v = X + v * xstride
+//   (xsc: optional per-problem factor applied to every x_v as it is read,
+//   giving the values a scale_copy of X would hold; also for the next two)
 void multidot(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
-              int nv, const double* y, double* partial, double* out);
+              int nv, const double* y, double* partial, double* out,
+              const double* xsc = nullptr);
 // out[p] = min over composite cells of min(E + lam_p dE, T + lam_p dT)
 void min_positive(const Dev& D, hipStream_t s, const double* u, const double* du,
                   const double* lam, double* partial, double* out);
@@ -105,12 +108,13 @@ void combine(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
 // y -= sum_v coef[p][v] x_v, then out[p * nv + v] = x_v . y (one pass for
 // nv <= 16; the values of combine followed by multidot)
 void combine_dot(const Dev& D, hipStream_t s, const double* X, int64_t xstride, int nv,
-                 const double* coef, int cstride, double* y, double* partial, double* out);
+                 const double* coef, int cstride, double* y, double* partial, double* out,
+                 const double* xsc = nullptr);
 // y -= sum_v coef[p][v] x_v, then out[p] = ||y||^2 (composite, volume
 // weighted) in the same pass over y
 void combine_norm(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
                   int nv, const double* coef, int cstride, double* y, double* partial,
-                  double* out);
+                  double* out, const double* xsc = nullptr);
 // Newton update from a Krylov basis (nv <= 16): keep = x, x -= sum_v
 // coef[p][v] z_v on active problems, out[p] = min over composite cells of
 // both fields of the new x (-1 for NaN)

@@ -101,7 +101,13 @@ struct nrd_hierarchy final : public Clock {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pairs;
+    struct Timed {
+        int which;
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        int64_t cells;               // composite cells the launches covered
+    };
+    std::vector<Timed> ev_pairs;
+    std::vector<int64_t> prob_comp;  // composite cells per problem
     std::vector<int32_t> host_active;
     // one FGMRES iteration per direction (0: J, 1: J^T), linearisation
     // point (the iterate's buffer rotates with the time-step history) and
@@ -149,9 +155,19 @@ struct nrd_hierarchy final : public Clock {
         return {a, b};
     }
     void toc(int which, std::pair<hipEvent_t, hipEvent_t> p) override {
+        toc_cells(which, p, 0);
+    }
+    void toc_cells(int which, std::pair<hipEvent_t, hipEvent_t> p, int64_t cells) {
         if (!timing || !p.first) return;
         (void)hipEventRecord(p.second, stream);
-        ev_pairs.push_back({which, p});
+        ev_pairs.push_back({which, p, cells});
+    }
+    // composite cells of the problems an operator launch covers now
+    int64_t covered_cells() const {
+        int64_t n = 0;
+        for (size_t q = 0; q < prob_comp.size(); ++q)
+            if (!D.active || host_active[q]) n += prob_comp[q];
+        return n;
     }
 };
 
@@ -512,6 +528,7 @@ static void prepare_state(nrd_hierarchy* h, double* u) {
 
 static void op_residual(nrd_hierarchy* h, double* u, double* F, bool prepared = false) {
     if (!prepared) prepare_state(h, u);
+    const int64_t cells = h->timing ? h->covered_cells() : 0;
     auto tk = h->tic(NRD_TIMER_RESIDUAL);
     const Dev& D = h->D;
     if (h->opt.launch == NRD_PER_PATCH) {
@@ -524,7 +541,7 @@ static void op_residual(nrd_hierarchy* h, double* u, double* F, bool prepared = 
         residual(D, h->stream, 0, h->ntiles_stencil(), u, h->bvec, F);
     }
     residual_reflux(D, h->stream, u, F);
-    h->toc(NRD_TIMER_RESIDUAL, tk);
+    h->toc_cells(NRD_TIMER_RESIDUAL, tk, cells);
 }
 
 // Jacobian-free product (Sec. 4.1): Jv = (F(u + eps v) - F(u)) / eps with the
@@ -534,6 +551,7 @@ static void op_jvp_fd(nrd_hierarchy* h, double* u, double* v, double* Jv, bool u
                       const double* F0) {
     if (!u_prepared) prepare_state(h, u);
     restrict_d(h->D, h->stream, v, 2, 0);
+    const int64_t cells = h->timing ? h->covered_cells() : 0;
     auto tk = h->tic(NRD_TIMER_JVP);
     const Dev& D = h->D;
     hipStream_t s = h->stream;
@@ -564,7 +582,7 @@ static void op_jvp_fd(nrd_hierarchy* h, double* u, double* v, double* Jv, bool u
     }
     residual_reflux(D, s, h->fdw, Jv);
     fd_quotient(D, s, h->fdsum, F0, Jv);
-    h->toc(NRD_TIMER_JVP, tk);
+    h->toc_cells(NRD_TIMER_JVP, tk, cells);
 }
 
 static void op_jvp(nrd_hierarchy* h, double* u, double* v, double* Jv, bool u_prepared) {
@@ -574,6 +592,7 @@ static void op_jvp(nrd_hierarchy* h, double* u, double* v, double* Jv, bool u_pr
     }
     if (!u_prepared) prepare_state(h, u);
     prepare_state(h, v);
+    const int64_t cells = h->timing ? h->covered_cells() : 0;
     auto tk = h->tic(NRD_TIMER_JVP);
     const Dev& D = h->D;
     if (h->opt.launch == NRD_PER_PATCH) {
@@ -586,7 +605,7 @@ static void op_jvp(nrd_hierarchy* h, double* u, double* v, double* Jv, bool u_pr
         jvp(D, h->stream, 0, h->ntiles_stencil(), u, v, Jv);
     }
     jvp_reflux(D, h->stream, u, v, Jv);
-    h->toc(NRD_TIMER_JVP, tk);
+    h->toc_cells(NRD_TIMER_JVP, tk, cells);
 }
 
 static void pc_setup(nrd_hierarchy* h, double* u, bool prepared) {
@@ -597,12 +616,13 @@ static void pc_setup(nrd_hierarchy* h, double* u, bool prepared) {
         h->pcd.setup(h->stream, u);
 }
 
-static void pc_apply(nrd_hierarchy* h, const double* w, double* y) {
+static void pc_apply(nrd_hierarchy* h, const double* w, double* y,
+                     const double* wsc = nullptr) {
     auto tk = h->tic(NRD_TIMER_PRECOND);
     if (h->mixed)
-        h->pcf.apply(h->stream, w, y);
+        h->pcf.apply(h->stream, w, y, wsc);
     else
-        h->pcd.apply(h->stream, w, y);
+        h->pcd.apply(h->stream, w, y, wsc);
     h->toc(NRD_TIMER_PRECOND, tk);
 }
 
@@ -619,9 +639,10 @@ static nrd_status upload_active(nrd_hierarchy* h) {
     return NRD_OK;
 }
 
+// masked: only the problems of the current active mask (0 for the others)
 static nrd_status dot_host(nrd_hierarchy* h, const double* x, const double* y,
-                           std::vector<double>& out) {
-    h->D.active = nullptr;
+                           std::vector<double>& out, bool masked = false) {
+    if (!masked) h->D.active = nullptr;
     multidot(h->D, h->stream, x, 0, 1, y, h->partial, h->dots);
     out.resize(h->t.nprob);
     HIPCHK(hipMemcpyAsync(out.data(), h->dots, 8 * h->t.nprob, hipMemcpyDeviceToHost,
@@ -757,7 +778,11 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
         h->host_active = todo;
         RCHK(upload_active(h));
         HIPCHK(up(s, h->coefA, inv));
-        scale_copy(h->D, s, r, h->coefA, h->V);
+        // v_0 = r / beta.  On a forward solve's first cycle r (the right-hand
+        // side) stays untouched, so iteration 0 reads r scaled by 1/beta
+        // (coefA) in place of v_0 and v_0 is formed only if iteration 1 runs.
+        const bool v0_lazy = cycle == 0 && !transpose;
+        if (!v0_lazy) scale_copy(h->D, s, r, h->coefA, h->V);
         std::vector<double> g0((size_t)np * (m + 1), 0.0);
         for (int p = 0; p < np; ++p) g0[(size_t)p * (m + 1)] = beta0[p];
         HIPCHK(up(s, h->g, g0));
@@ -775,23 +800,28 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
                 double* Zj = h->Z + j * NL;
                 double* wv = h->w;
                 if (j > 0) scale_copy(h->D, s, wv, h->vscale, Vj);
+                if (j == 1 && v0_lazy) scale_copy(h->D, s, r, h->coefA, h->V);
+                // the basis read by this iteration: v_0 .. v_j, or r with 1/beta
+                const double* Vb = (j == 0 && v0_lazy) ? r : h->V;
+                const double* vsc = (j == 0 && v0_lazy) ? h->coefA : nullptr;
                 if (!transpose) {
-                    pc_apply(h, Vj, Zj);
+                    pc_apply(h, (j == 0 && v0_lazy) ? r : Vj, Zj, vsc);
                     op_jvp(h, u, Zj, wv, true);
                 } else {
                     pc_apply_t(h, Vj, Zj);
                     ghost_fill_d(h->D, s, Zj, 2);
                     vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], u, Zj, wv, h->gz3);
                 }
-                multidot(h->D, s, h->V, NL, j + 1, wv, h->partial, h->h1);
-                combine_dot(h->D, s, h->V, NL, j + 1, h->h1, j + 1, wv, h->partial, h->h2);
-                combine_norm(h->D, s, h->V, NL, j + 1, h->h2, j + 1, wv, h->partial, h->hn2);
+                multidot(h->D, s, Vb, NL, j + 1, wv, h->partial, h->h1, vsc);
+                combine_dot(h->D, s, Vb, NL, j + 1, h->h1, j + 1, wv, h->partial, h->h2, vsc);
+                combine_norm(h->D, s, Vb, NL, j + 1, h->h2, j + 1, wv, h->partial, h->hn2,
+                             vsc);
                 gmres_column(s, np, m, j, h->active, h->h1, h->h2, h->hn2, h->H, h->cs, h->sn,
                              h->g, h->rho, h->vscale);
             };
             if (h->opt.use_graph) {
-                hipGraphExec_t& ge = h->graphs[std::make_tuple(transpose ? 1 : 0,
-                                                               (const void*)u, j)];
+                hipGraphExec_t& ge = h->graphs[std::make_tuple(
+                    (transpose ? 1 : 0) + (v0_lazy ? 2 : 0), (const void*)u, j)];
                 if (!h->cap_stream) {
                     HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
                     HIPCHK(hipEventCreateWithFlags(&h->gev_in, hipEventDisableTiming));
@@ -1056,9 +1086,13 @@ static nrd_status newton(nrd_hierarchy* h, std::vector<nrd_step_stats>& st) {
             h->D.active = h->active;
             axpby(h->D, s, h->coefA, h->s, h->coefB, h->x);
         }
-        h->D.active = nullptr;
+        // F and its norm only where x changed (problems still iterating)
+        for (int p = 0; p < np; ++p) h->host_active[p] = act[p] && !failed[p];
+        RCHK(upload_active(h));
+        h->D.active = h->active;
         op_residual(h, h->x, h->F);
-        rc = dot_host(h, h->F, h->F, f2);
+        rc = dot_host(h, h->F, h->F, f2, true);
+        h->D.active = nullptr;
         if (rc) return rc;
         for (int p = 0; p < np; ++p) {
             if (!act[p] || failed[p]) continue;   // iterations count accepted updates
@@ -1344,6 +1378,19 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
         if (h->t.nlev > kMaxLev || (int)h->t.mg.size() > kMaxMG) {
             delete h;
             return fail(NRD_EUNSUPPORTED, "too many levels");
+        }
+        h->prob_comp.assign(h->t.nprob, 0);
+        for (const PatchInfo& pi : h->t.patches) {
+            int64_t n = pi.ncell;
+            if (pi.flags & PF_COVERED)
+                for (int k = 0; k < pi.n[2]; ++k)
+                    for (int j = 0; j < pi.n[1]; ++j)
+                        for (int i = 0; i < pi.n[0]; ++i) {
+                            const int64_t c = pi.off + (i + 1) + (int64_t)pi.sy * (j + 1) +
+                                              (int64_t)pi.sz * (k + 1);
+                            if (h->t.ctype[c] & CT_COVERED) --n;
+                        }
+            h->prob_comp[pi.prob] += n;
         }
         h->patch_tile0.assign(h->t.nbox, 0);
         {
@@ -1758,14 +1805,24 @@ nrd_status nrd_timer_read(nrd_hierarchy* h, int32_t which, double* ms, int32_t* 
     double tot = 0.0;
     int32_t n = 0;
     for (auto& pr : h->ev_pairs) {
-        if (pr.first != which) continue;
+        if (pr.which != which) continue;
         float dtm = 0.f;
-        HIPCHK(hipEventElapsedTime(&dtm, pr.second.first, pr.second.second));
+        HIPCHK(hipEventElapsedTime(&dtm, pr.ev.first, pr.ev.second));
         tot += dtm;
         ++n;
     }
     if (ms) *ms = tot;
     if (count) *count = n;
+    return NRD_OK;
+}
+
+nrd_status nrd_timer_cells(nrd_hierarchy* h, int32_t which, int64_t* cells) {
+    if (!h) return fail(NRD_EINVAL, "NULL hierarchy");
+    if (which < 0 || which >= NRD_TIMER_COUNT) return fail(NRD_EINVAL, "unknown timer");
+    int64_t n = 0;
+    for (auto& pr : h->ev_pairs)
+        if (pr.which == which) n += pr.cells;
+    if (cells) *cells = n;
     return NRD_OK;
 }
 

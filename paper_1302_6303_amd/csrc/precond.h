@@ -79,7 +79,9 @@ struct PcArrays {
 
     void zero(hipStream_t s) const;
     void setup(hipStream_t s, const double* u_state) const;
-    void apply(hipStream_t s, const double* w, double* y) const;
+    // y = P^-1 (wsc_p w); wsc (per problem, may be NULL) scales the input as
+    // it is read
+    void apply(hipStream_t s, const double* w, double* y, const double* wsc = nullptr) const;
     void apply_transpose(hipStream_t s, const double* w, double* y) const;
     const PT* fac(hipStream_t s) const;     // returns u or e (one level)
     void vcycle(hipStream_t s) const;

@@ -728,19 +728,22 @@ __global__ __launch_bounds__(kBlock) void k_p2t_in(const int32_t* __restrict__ a
 }
 
 template <typename PT>
+// x = wsc_p w (wsc may be NULL: factor 1) rounded to PT
 __global__ __launch_bounds__(kBlock) void k_in(const int32_t* __restrict__ act, const Tile* __restrict__ tiles,
                                                const PatchInfo* __restrict__ P,
                                                const double* __restrict__ w,
+                                               const double* __restrict__ wsc,
                                                PT* __restrict__ x, int64_t nl) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
+    const double sc = wsc ? wsc[t.prob] : 1.0;
     int id[3];
     coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
     const int c = nat(p, id[0], id[1], id[2]);
-    x[c] = (PT)w[c];
-    x[c + nl] = (PT)w[c + nl];
+    x[c] = (PT)(sc * w[c]);
+    x[c + nl] = (PT)(sc * w[c + nl]);
 }
 
 template <typename PT>
@@ -975,10 +978,10 @@ const PT* PcArrays<PT>::fac(hipStream_t s) const {
 }
 
 template <typename PT>
-void PcArrays<PT>::apply(hipStream_t s, const double* w, double* y) const {
+void PcArrays<PT>::apply(hipStream_t s, const double* w, double* y, const double* wsc) const {
     const Dev& d = *D;
     const int ntiles = d.level_tile0[d.nlev];
-    k_in<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, w, f, d.nl);
+    k_in<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, w, wsc, f, d.nl);
     const PT* x = fac(s);
     k_p2<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, sigma, d.z3, x, y, p2_mode, 0,
                                        d.nl);

@@ -57,8 +57,8 @@ template <int NV>
 __global__ __launch_bounds__(kBlock) void k_multidot(
     const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
     const uint8_t* __restrict__ ctype, const int32_t* __restrict__ active,
-    const double* __restrict__ X, int64_t xs, int nv, const double* __restrict__ y,
-    double* __restrict__ partial, int64_t nl) {
+    const double* __restrict__ X, int64_t xs, int nv, const double* __restrict__ xsc,
+    const double* __restrict__ y, double* __restrict__ partial, int64_t nl) {
     __shared__ double sh[4];
     const Tile t = vt[blockIdx.x];
     double acc[NV];
@@ -68,13 +68,17 @@ __global__ __launch_bounds__(kBlock) void k_multidot(
     const PatchInfo& p = P[t.patch];
     if (on) {
         const bool cov = p.flags & PF_COVERED;
+        const double sc = xsc ? xsc[t.prob] : 1.0;
         for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
             const int c = interior_index(p, lin);
             if (cov && (ctype[c] & CT_COVERED)) continue;
             const double y0 = y[c], y1 = y[c + nl];
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                if (v < nv) acc[v] += X[v * xs + c] * y0 + X[v * xs + c + nl] * y1;
+                if (v < nv) {
+                    const double x0 = sc * X[v * xs + c], x1 = sc * X[v * xs + c + nl];
+                    acc[v] += x0 * y0 + x1 * y1;
+                }
         }
     }
 #pragma unroll
@@ -102,26 +106,26 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(
 }
 
 void multidot(const Dev& D, hipStream_t s, const double* X, int64_t xstride, int nv,
-              const double* y, double* partial, double* out) {
+              const double* y, double* partial, double* out, const double* xsc) {
     for (int v0 = 0; v0 < nv; v0 += 16) {
         const int c = std::min(16, nv - v0);
         const double* Xc = X + v0 * xstride;
         if (c == 1)
             k_multidot<1><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
-                                                       Xc, xstride, c, y, partial, D.nl);
+                                                       Xc, xstride, c, xsc, y, partial, D.nl);
         else if (c <= 2)
             k_multidot<2><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
-                                                       Xc, xstride, c, y, partial, D.nl);
+                                                       Xc, xstride, c, xsc, y, partial, D.nl);
         else if (c <= 4)
             k_multidot<4><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
-                                                       Xc, xstride, c, y, partial, D.nl);
+                                                       Xc, xstride, c, xsc, y, partial, D.nl);
         else if (c <= 8)
             k_multidot<8><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
-                                                       Xc, xstride, c, y, partial, D.nl);
+                                                       Xc, xstride, c, xsc, y, partial, D.nl);
         else
             k_multidot<16><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype,
-                                                        D.active, Xc, xstride, c, y, partial,
-                                                        D.nl);
+                                                        D.active, Xc, xstride, c, xsc, y,
+                                                        partial, D.nl);
         k_sum_partials<<<D.nprob, kBlock, 0, s>>>(D.prob_vtile0, partial, c, out + v0, nv);
     }
 }
@@ -232,8 +236,9 @@ template <int NV>
 __global__ __launch_bounds__(kBlock) void k_combine_dot(
     const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
     const uint8_t* __restrict__ ctype, const int32_t* __restrict__ active,
-    const double* __restrict__ X, int64_t xs, int nv, const double* __restrict__ coef, int cs,
-    double* __restrict__ y, double* __restrict__ partial, int64_t nl) {
+    const double* __restrict__ X, int64_t xs, int nv, const double* __restrict__ xsc,
+    const double* __restrict__ coef, int cs, double* __restrict__ y,
+    double* __restrict__ partial, int64_t nl) {
     __shared__ double sh[4];
     const Tile t = vt[blockIdx.x];
     double acc[NV];
@@ -246,21 +251,28 @@ __global__ __launch_bounds__(kBlock) void k_combine_dot(
 #pragma unroll
         for (int v = 0; v < NV; ++v) cf[v] = (v < nv) ? -1.0 * coef[t.prob * cs + v] : 0.0;
         const bool cov = p.flags & PF_COVERED;
+        const double sc = xsc ? xsc[t.prob] : 1.0;
         for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
             const int c = interior_index(p, lin);
             double a0 = y[c], a1 = y[c + nl];
+            double x0[NV], x1[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                x0[v] = (v < nv) ? sc * X[v * xs + c] : 0.0;
+                x1[v] = (v < nv) ? sc * X[v * xs + c + nl] : 0.0;
+            }
 #pragma unroll
             for (int v = 0; v < NV; ++v)
                 if (v < nv && cf[v] != 0.0) {
-                    a0 += cf[v] * X[v * xs + c];
-                    a1 += cf[v] * X[v * xs + c + nl];
+                    a0 += cf[v] * x0[v];
+                    a1 += cf[v] * x1[v];
                 }
             y[c] = a0;
             y[c + nl] = a1;
             if (cov && (ctype[c] & CT_COVERED)) continue;
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                if (v < nv) acc[v] += X[v * xs + c] * a0 + X[v * xs + c + nl] * a1;
+                if (v < nv) acc[v] += x0[v] * a0 + x1[v] * a1;
         }
     }
 #pragma unroll
@@ -273,31 +285,32 @@ __global__ __launch_bounds__(kBlock) void k_combine_dot(
 }
 
 void combine_dot(const Dev& D, hipStream_t s, const double* X, int64_t xstride, int nv,
-                 const double* coef, int cstride, double* y, double* partial, double* out) {
-    if (nv > 16) {
+                 const double* coef, int cstride, double* y, double* partial, double* out,
+                 const double* xsc) {
+    if (nv > 16) {            // (never with xsc: scaled bases have one vector)
         combine(D, s, X, xstride, nv, coef, cstride, y, 1, -1.0);
         multidot(D, s, X, xstride, nv, y, partial, out);
         return;
     }
     if (nv <= 1)
         k_combine_dot<1><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, X,
-                                                      xstride, nv, coef, cstride, y, partial,
+                                                      xstride, nv, xsc, coef, cstride, y, partial,
                                                       D.nl);
     else if (nv <= 2)
         k_combine_dot<2><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, X,
-                                                      xstride, nv, coef, cstride, y, partial,
+                                                      xstride, nv, xsc, coef, cstride, y, partial,
                                                       D.nl);
     else if (nv <= 4)
         k_combine_dot<4><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, X,
-                                                      xstride, nv, coef, cstride, y, partial,
+                                                      xstride, nv, xsc, coef, cstride, y, partial,
                                                       D.nl);
     else if (nv <= 8)
         k_combine_dot<8><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, X,
-                                                      xstride, nv, coef, cstride, y, partial,
+                                                      xstride, nv, xsc, coef, cstride, y, partial,
                                                       D.nl);
     else
         k_combine_dot<16><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
-                                                       X, xstride, nv, coef, cstride, y, partial,
+                                                       X, xstride, nv, xsc, coef, cstride, y, partial,
                                                        D.nl);
     k_sum_partials<<<D.nprob, kBlock, 0, s>>>(D.prob_vtile0, partial, nv, out, nv);
 }
@@ -310,8 +323,9 @@ template <int NV>
 __global__ __launch_bounds__(kBlock) void k_combine_norm(
     const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
     const uint8_t* __restrict__ ctype, const int32_t* __restrict__ active,
-    const double* __restrict__ X, int64_t xs, int nv, const double* __restrict__ coef, int cs,
-    double* __restrict__ y, double* __restrict__ partial, int64_t nl) {
+    const double* __restrict__ X, int64_t xs, int nv, const double* __restrict__ xsc,
+    const double* __restrict__ coef, int cs, double* __restrict__ y,
+    double* __restrict__ partial, int64_t nl) {
     __shared__ double sh[4];
     const Tile t = vt[blockIdx.x];
     double acc = 0.0;
@@ -322,14 +336,15 @@ __global__ __launch_bounds__(kBlock) void k_combine_norm(
 #pragma unroll
         for (int v = 0; v < NV; ++v) cf[v] = (v < nv) ? -coef[t.prob * cs + v] : 0.0;
         const bool cov = p.flags & PF_COVERED;
+        const double sc = xsc ? xsc[t.prob] : 1.0;
         for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
             const int c = interior_index(p, lin);
             double a0 = y[c], a1 = y[c + nl];
 #pragma unroll
             for (int v = 0; v < NV; ++v)
                 if (v < nv && cf[v] != 0.0) {
-                    a0 += cf[v] * X[v * xs + c];
-                    a1 += cf[v] * X[v * xs + c + nl];
+                    a0 += cf[v] * (sc * X[v * xs + c]);
+                    a1 += cf[v] * (sc * X[v * xs + c + nl]);
                 }
             y[c] = a0;
             y[c + nl] = a1;
@@ -341,7 +356,8 @@ __global__ __launch_bounds__(kBlock) void k_combine_norm(
 }
 
 void combine_norm(const Dev& D, hipStream_t s, const double* X, int64_t xstride, int nv,
-                  const double* coef, int cstride, double* y, double* partial, double* out) {
+                  const double* coef, int cstride, double* y, double* partial, double* out,
+                  const double* xsc) {
     // more than 16 basis vectors: plain combines first, the norm with the last 16
     int v0 = 0;
     for (; nv - v0 > 16; v0 += 16)
@@ -351,19 +367,19 @@ void combine_norm(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
     const double* cc = coef + v0;
     if (c <= 1)
         k_combine_norm<1><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
-                                                       Xc, xstride, c, cc, cstride, y, partial,
+                                                       Xc, xstride, c, xsc, cc, cstride, y, partial,
                                                        D.nl);
     else if (c <= 4)
         k_combine_norm<4><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
-                                                       Xc, xstride, c, cc, cstride, y, partial,
+                                                       Xc, xstride, c, xsc, cc, cstride, y, partial,
                                                        D.nl);
     else if (c <= 8)
         k_combine_norm<8><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
-                                                       Xc, xstride, c, cc, cstride, y, partial,
+                                                       Xc, xstride, c, xsc, cc, cstride, y, partial,
                                                        D.nl);
     else
         k_combine_norm<16><<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active,
-                                                        Xc, xstride, c, cc, cstride, y, partial,
+                                                        Xc, xstride, c, xsc, cc, cstride, y, partial,
                                                         D.nl);
     k_sum_partials<<<D.nprob, kBlock, 0, s>>>(D.prob_vtile0, partial, 1, out, 1);
 }

@@ -97,6 +97,7 @@ _sigs = {
     "nrd_dot": (C.c_int32, [_H, _P, _P, C.POINTER(C.c_double)]),
     "nrd_autotune": (C.c_int32, [_H, C.c_char_p, C.POINTER(C.c_int32)]),
     "nrd_timer_enable": (C.c_int32, [_H, C.c_int32]),
+    "nrd_timer_cells": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_int64)]),
     "nrd_timer_read": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_double),
                                    C.POINTER(C.c_int32)]),
 }
@@ -283,3 +284,8 @@ class Hierarchy:
         n = C.c_int32()
         check(nrd_timer_read(self.h, which, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def timer_cells(self, which):
+        cells = C.c_int64()
+        check(nrd_timer_cells(self.h, which, C.byref(cells)))
+        return cells.value
