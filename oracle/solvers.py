@@ -265,6 +265,18 @@ def bdf_coefficients(dt, dt_prev):
     return (1.0 + 2.0 * a) / (1.0 + a), a
 
 
+def bdf2_history(u, u_prev, a):
+    """b of eq. bdf2 written as c0 u_{n+1} - b = dt f(u_{n+1}):
+    b = (1 + a) u_n - a^2 / (1 + a) u_{n-1}, a = dt_n / dt_{n-1}."""
+    return (1.0 + a) * u - (a * a / (1.0 + a)) * u_prev
+
+
+def leapfrog_predictor(u, u_prev, udot, dt, a):
+    """Generalised leapfrog predictor (eq. leapfrog):
+    u^p_{n+1} = u_n + (1 + a) dt u'_n - a^2 (u_n - u_{n-1})."""
+    return u + (1.0 + a) * dt * udot - a * a * (u - u_prev)
+
+
 class Stepper:
     """Library-owned state u_n, u_{n-1}, dt_{n-1}, udot_n (eqs. be, bdf2,
     leapfrog)."""
@@ -287,9 +299,9 @@ class Stepper:
             guess = self.u.copy()
         else:
             c0, a = bdf_coefficients(dt, self.dt_prev)
-            b = (1.0 + a) * self.u - (a * a / (1.0 + a)) * self.u_prev
-            guess = (self.u + (1.0 + a) * dt * self.udot
-                     - a * a * (self.u - self.u_prev))
+            b = bdf2_history(self.u, self.u_prev, a)
+            guess = leapfrog_predictor(self.u, self.u_prev, self.udot, dt, a)
+            self.predicted = guess.copy()
             if not np.all(guess[self.sys.composite] > 0.0):
                 guess = self.u.copy()
             guess = self.sys.sync(guess)
@@ -297,7 +309,12 @@ class Stepper:
         return c0, a, b, guess, beta
 
     def step(self, dt):
+        """One step of size dt; on failure the state is left unchanged.
+        self.predicted / self.alpha hold the step's leapfrog predictor and
+        step ratio (None / 0 for a BDF1 step)."""
+        self.predicted = None
         c0, a, b, guess, beta = self.rhs_and_guess(dt)
+        self.alpha = a
         res = newton(self.sys, guess, b, dt, c0, beta, **self.kw)
         if not res.converged:
             return res
@@ -306,6 +323,92 @@ class Stepper:
         self.u = res.u
         self.dt_prev = dt
         self.history.append(res)
+        return res
+
+
+# ---------------------------------------------------------------------------
+# time-step control (Sec. 2: eqs. odets, pc47, leapfrog, bdf2le)
+# ---------------------------------------------------------------------------
+
+def bdf2_error_estimate(u_new, u_pred, a):
+    """Local error of a variable-step BDF2 step from the leapfrog
+    predictor (eq. bdf2le): e = (a + 1) / (3 a + 2) (u_{n+1} - u^p)."""
+    return (a + 1.0) / (3.0 * a + 2.0) * (u_new - u_pred)
+
+
+def scaled_max_norm(sys: System, e, u, eta_E, eta_T):
+    """max(max |e_E / (E + eta_E)|, max |e_T / (T + eta_T)|) over composite
+    cells, u the solution the error belongs to (the scaled max norm of
+    Sec. 2)."""
+    n = sys.nc
+    m = sys.composite[:n]
+    eE, eT, E, T = e[:n], e[n:], u[:n], u[n:]
+    return max(float(np.max(np.abs(eE[m] / (E[m] + eta_E)))),
+               float(np.max(np.abs(eT[m] / (T[m] + eta_T)))))
+
+
+def eps_step_factor(eps, err, k=3):
+    """Elementary error-per-step controller (eq. odets): dt_{n+1} / dt_n
+    = (eps / ||e_n||)^(1/k), k = 3 for BDF2."""
+    return (eps / err) ** (1.0 / k)
+
+
+def pc47_ratio(eps, err, err_prev, a, k=3, kI=0.4, kP=0.7):
+    """PI controller PC.4.7 (eq. pc47) with k kI = 0.4, k kP = 0.7:
+    a_{n+1} = (eps / ||e_n||)^kI (||e_{n-1}|| / ||e_n||)^kP a_n, the
+    exponents taken as 0.4 / k and 0.7 / k."""
+    return (eps / err) ** (kI / k) * (err_prev / err) ** (kP / k) * a
+
+
+class AdaptiveStepper(Stepper):
+    """BDF1 first step, then BDF2 with the step size chosen by PC.4.7 from
+    the local error estimate (EPS for the first estimate, which has no
+    predecessor).  Readings: the step ratio is kept in [ratio_min,
+    ratio_max] (variable-step BDF2 is zero-stable only for ratios below
+    1 + sqrt 2); a step whose Newton solve fails is retried with half the
+    step (at most max_halvings times); converged steps are always accepted
+    and the controller answers their error."""
+
+    def __init__(self, sys: System, u0, dt0, eps, eta_E, eta_T, controller="pc47",
+                 ratio_min=0.25, ratio_max=2.0, max_halvings=10, **newton_kw):
+        super().__init__(sys, u0, **newton_kw)
+        self.dt = float(dt0)
+        self.eps = eps
+        self.eta = (eta_E, eta_T)
+        self.controller = controller
+        self.ratio_min, self.ratio_max = ratio_min, ratio_max
+        self.max_halvings = max_halvings
+        self.err_prev = None
+        self.t = 0.0
+        self.log = []           # (dt, converged after halvings, err or None)
+
+    def advance(self):
+        """One accepted step (with retries); returns its Newton result."""
+        dt = self.dt
+        for _ in range(self.max_halvings + 1):
+            res = self.step(dt)
+            if res.converged:
+                break
+            dt *= 0.5
+        else:
+            raise RuntimeError("time step could not be made to converge")
+        self.t += dt
+        err = None
+        ratio = 1.0
+        if self.predicted is not None:
+            err = scaled_max_norm(self.sys, bdf2_error_estimate(self.u, self.predicted, self.alpha),
+                                  self.u, *self.eta)
+            if err > 0.0:
+                if self.controller == "pc47" and self.err_prev is not None:
+                    ratio = pc47_ratio(self.eps, err, self.err_prev, self.alpha)
+                else:
+                    ratio = eps_step_factor(self.eps, err)
+            else:
+                ratio = self.ratio_max
+            self.err_prev = err
+        ratio = min(max(ratio, self.ratio_min), self.ratio_max)
+        self.log.append((dt, err))
+        self.dt = ratio * dt
         return res
 
 
