@@ -120,12 +120,21 @@ typedef struct {
     int32_t zchunk;         /* planes per tile of variants 1, 2 (0: default)  */
     int32_t bdf_max_order;  /* 2 (default): BDF2 after the first step; 1: BDF1
                                throughout (the adjoint assumes BDF1)         */
-    int32_t reserved[4];
+    int32_t error_estimate; /* 1: every BDF2 step keeps its leapfrog predictor
+                               and reports the scaled max norm of its local
+                               error estimate (eq. bdf2le) in
+                               nrd_step_stats.err_norm; needed by
+                               nrd_adaptive_steps (0 default)                */
+    int32_t reserved[3];
+    double err_eta_E;       /* eta_E, eta_T of that norm,                    */
+    double err_eta_T;       /* max |e / (u + eta)| over composite cells      */
 } nrd_options;
 
 /* Fills *opt with the defaults: FP64, batched, no graph, analytic JVP,
  * limiter 1, paper P2, rtol 1e-8, atol 1e-14, 20 Newton iterations,
- * GMRES(30) with 10 restarts, V(1,1), plane-marching stencil. */
+ * GMRES(30) with 10 restarts, V(1,1), staged-plane stencil, BDF2, no error
+ * estimate, eta_E = 1e-5 (the initial energy density of Sec. 5), eta_T =
+ * 1e-5^(1/4). */
 void nrd_default_options(nrd_options* opt);
 
 typedef struct {
@@ -138,7 +147,23 @@ typedef struct {
     double fnorm0;
     double fnorm;
     int32_t krylov_per_newton[24];
+    double dt;                   /* the step size of this step               */
+    double err_norm;             /* scaled max norm of the local error
+                                    estimate (error_estimate set, BDF2 step);
+                                    -1 otherwise                             */
 } nrd_step_stats;
+
+/* Time-step control (Sec. 2, eqs. odets, pc47, bdf2le). */
+enum { NRD_CTL_PC47 = 0, NRD_CTL_EPS = 1 };
+typedef struct {
+    double eps;                  /* target local error eps_t                 */
+    double ratio_min;            /* bounds of dt_{n+1} / dt_n (variable-step */
+    double ratio_max;            /* BDF2 is zero-stable below 1 + sqrt 2)    */
+    int32_t controller;          /* NRD_CTL_PC47 (k_I = 0.4/3, k_P = 0.7/3;
+                                    EPS for a problem's first estimate) or
+                                    NRD_CTL_EPS (dt (eps / err)^(1/3))       */
+    int32_t max_halvings;        /* retries of a step whose solve fails      */
+} nrd_timectl;
 
 typedef struct nrd_hierarchy nrd_hierarchy;
 
@@ -221,6 +246,20 @@ nrd_status nrd_vjp(nrd_hierarchy* h, double* dev_u, double* dev_lam,
  * NRD_ENOTCONV is returned.  Synchronises. */
 nrd_status nrd_implicit_step(nrd_hierarchy* h, const double* dt,
                              nrd_step_stats* stats);
+
+/* nsteps accepted steps of every problem with step sizes chosen by the
+ * controller from each problem's own local error estimates (the hierarchy
+ * must be created with error_estimate = 1).  dt: host [nprob], in: the next
+ * step size of every problem, out: the size chosen for the step after the
+ * last.  t: host [nprob] or NULL, advanced by the accepted steps.  A batch
+ * whose solve fails for some problems is rolled back and retried with those
+ * problems' steps halved (the others repeat the same step); more than
+ * max_halvings retries of one problem's step give NRD_ENOTCONV with the state
+ * of the last accepted step.  The first step after nrd_set_fields is BDF1 and
+ * keeps its size.  stats: host [nsteps * nprob] (step-major) or NULL.
+ * Synchronises. */
+nrd_status nrd_adaptive_steps(nrd_hierarchy* h, const nrd_timectl* ctl, int32_t nsteps,
+                              double* dt, double* t, nrd_step_stats* stats);
 
 /* Discrete adjoint of nsteps BDF1 steps of size dt from the current state
  * for J = sum over cells of dJdE_final[c] * E_N(c) (device, compact E part;

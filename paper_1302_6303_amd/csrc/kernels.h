@@ -121,6 +121,10 @@ void combine_norm(const Dev& D, hipStream_t s, const double* X, int64_t xstride,
 void update_min(const Dev& D, hipStream_t s, const double* Z, int64_t zstride, int nv,
                 const double* coef, int cstride, double* x, double* keep, double* partial,
                 double* out);
+// out[p] = max over composite cells of |c_p (x - xp)| / (x + eta) over both
+// fields (eta_E, eta_T): the scaled max norm of the BDF2 error estimate
+void err_norm(const Dev& D, hipStream_t s, const double* x, const double* xp,
+              const double* coef, double eta_E, double eta_T, double* partial, double* out);
 // y = a_p x + b_p y elementwise (a, b per problem, host-computed device arrays)
 void axpby(const Dev& D, hipStream_t s, const double* a, const double* x,
            const double* b, double* y);

@@ -76,7 +76,7 @@ struct nrd_hierarchy final : public Clock {
         size_t mg_box[kMaxMG], mg_tiles[kMaxMG], mg_box_of[kMaxMG], mg_smooth[kMaxMG],
             mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bot_probs, bot_boxes, bot_grid, bottom_off,
             Lbuf, Xbuf;
-        size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, gz3, V, Z;
+        size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, gz3, V, Z, pred;
         size_t pc_D, pc_sigma, pc_e, pc_u, pc_r, pc_f, pc_tmp, pc_shadow;
         size_t mg_D[kMaxMG], mg_e[kMaxMG], mg_f[kMaxMG], mg_r[kMaxMG];
         size_t partial, dots, h1, h2, hn2, H, cs, sn, g, rho, vscale, y, kdim, coefA, coefB,
@@ -91,7 +91,8 @@ struct nrd_hierarchy final : public Clock {
     std::vector<ProbScalars> ps_host;
     bool step_ready = false;
     // device pointers
-    double *z, *z3, *cur, *prev, *udot, *bvec, *x, *F, *s, *w, *tmp, *tmp2, *gz3, *V, *Z;
+    double *z, *z3, *cur, *prev, *udot, *bvec, *x, *F, *s, *w, *tmp, *tmp2, *gz3, *V, *Z, *pred;
+    std::vector<double> err_prev;   // per problem: last error norm (-1: none)
     double *partial, *dots, *h1, *h2, *hn2, *H, *cs, *sn, *g, *rho, *vscale, *y, *coefA, *coefB,
         *minout, *ckpt, *fdF, *fdw, *fdsum;
     const double* fd_base = nullptr;   // F at the Newton iterate (Jacobian-free mode)
@@ -245,6 +246,7 @@ static void layout(nrd_hierarchy* h) {
     o.gz3 = b.take(8 * nl);
     o.V = b.take(8 * 2 * nl * (size_t)(m + 1));
     o.Z = b.take(8 * 2 * nl * (size_t)m);
+    o.pred = b.take(h->opt.error_estimate ? 8 * 2 * nl : 8);
     // preconditioner (float or double)
     const size_t es = h->mixed ? 4 : 8;
     o.pc_D = b.take(es * 6 * nl);
@@ -462,6 +464,8 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     h->gz3 = h->at<double>(o.gz3);
     h->V = h->at<double>(o.V);
     h->Z = h->at<double>(o.Z);
+    h->pred = h->at<double>(o.pred);
+    h->err_prev.assign(t.nprob, -1.0);
     h->partial = h->at<double>(o.partial);
     h->dots = h->at<double>(o.dots);
     h->h1 = h->at<double>(o.h1);
@@ -1147,6 +1151,7 @@ static nrd_status implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_sta
         axpby(h->D, s, h->coefA, h->udot, h->coefA + 3 * np, h->tmp);        // + A udot
         axpby(h->D, s, h->coefA + np, h->prev, h->coefA + 3 * np, h->tmp);   // + a^2 u_{n-1}
         axpby(h->D, s, h->coefA + 2 * np, h->cur, h->coefA + 3 * np, h->tmp); // - a^2 u_n
+        if (h->opt.error_estimate) copy_interior(h->D, s, h->tmp, h->pred);
         // accept per problem if positive
         std::vector<double> zero(np, 0.0), mn(np);
         HIPCHK(up(s, h->coefB, zero));
@@ -1165,6 +1170,31 @@ static nrd_status implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_sta
     }
     std::vector<nrd_step_stats> st;
     rc = newton(h, st);
+    for (int p = 0; p < np; ++p) {
+        st[p].dt = dt[p];
+        st[p].err_norm = -1.0;
+    }
+    if (rc == NRD_OK && h->opt.error_estimate && any2) {
+        // local error estimate of the BDF2 steps (eq. bdf2le), scaled max norm
+        std::vector<double> cf(np), en(np);
+        for (int p = 0; p < np; ++p) {
+            const double a = h->alpha[p];
+            cf[p] = (a + 1.0) / (3.0 * a + 2.0);
+            h->host_active[p] = a > 0.0;
+        }
+        RCHK(upload_active(h));
+        HIPCHK(up(s, h->coefA, cf));
+        h->D.active = h->active;
+        err_norm(h->D, s, h->x, h->pred, h->coefA, h->opt.err_eta_E, h->opt.err_eta_T,
+                 h->partial, h->minout);
+        h->D.active = nullptr;
+        HIPCHK(hipMemcpyAsync(en.data(), h->minout, 8 * np, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        h->host_active.assign(np, 1);
+        RCHK(upload_active(h));
+        for (int p = 0; p < np; ++p)
+            if (h->alpha[p] > 0.0) st[p].err_norm = en[p];
+    }
     if (stats)
         for (int p = 0; p < np; ++p) stats[p] = st[p];
     if (rc) {
@@ -1337,6 +1367,9 @@ void nrd_default_options(nrd_options* o) {
     o->mg_nu_post = 1;
     o->stencil = 3;
     o->bdf_max_order = 2;
+    o->error_estimate = 0;
+    o->err_eta_E = 1e-5;
+    o->err_eta_T = std::pow(1e-5, 0.25);
 }
 
 nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const nrd_box* boxes,
@@ -1360,6 +1393,11 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
         if (h->opt.bdf_max_order < 1 || h->opt.bdf_max_order > 2) {
             delete h;
             return fail(NRD_EINVAL, "bdf_max_order must be 1 or 2");
+        }
+        if (h->opt.error_estimate < 0 || h->opt.error_estimate > 1 ||
+            !(h->opt.err_eta_E >= 0.0) || !(h->opt.err_eta_T >= 0.0)) {
+            delete h;
+            return fail(NRD_EINVAL, "error_estimate must be 0 or 1, err_eta_E/T >= 0");
         }
         if (h->opt.jvp_mode != NRD_JVP_ANALYTIC && h->opt.jvp_mode != NRD_JVP_FD) {
             delete h;
@@ -1501,6 +1539,7 @@ nrd_status nrd_set_fields(nrd_hierarchy* h, const double* E, const double* T, co
     copy_interior(h->D, s, h->cur, h->prev);
     fill_native(s, h->udot, 2 * h->t.nl, 0.0);
     std::fill(h->dt_prev.begin(), h->dt_prev.end(), 0.0);
+    std::fill(h->err_prev.begin(), h->err_prev.end(), -1.0);
     h->step_ready = false;
     h->fields_set = true;
     HIPCHK(hipStreamSynchronize(s));
@@ -1588,6 +1627,68 @@ nrd_status nrd_implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_stats*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(NRD_EDEVICE, hipGetErrorString(e));
     return rc;
+}
+
+nrd_status nrd_adaptive_steps(nrd_hierarchy* h, const nrd_timectl* ctl, int32_t nsteps,
+                              double* dt, double* t, nrd_step_stats* stats) {
+    NEED_BOUND(h);
+    if (!ctl || !dt || nsteps < 0) return fail(NRD_EINVAL, "NULL argument or nsteps < 0");
+    if (!h->opt.error_estimate)
+        return fail(NRD_EINVAL, "the hierarchy was created without error_estimate");
+    if (!(ctl->eps > 0.0) || !(ctl->ratio_min > 0.0) || !(ctl->ratio_max >= ctl->ratio_min) ||
+        ctl->max_halvings < 0 || (ctl->controller != NRD_CTL_PC47 && ctl->controller != NRD_CTL_EPS))
+        return fail(NRD_EINVAL, "bad time-step controller settings");
+    const int np = h->t.nprob;
+    for (int p = 0; p < np; ++p)
+        if (!(dt[p] > 0.0)) return fail(NRD_EINVAL, "step sizes must be positive");
+    std::vector<nrd_step_stats> st(np);
+    for (int n = 0; n < nsteps; ++n) {
+        std::vector<double> cur(dt, dt + np);
+        std::vector<int32_t> halvings(np, 0);
+        for (;;) {
+            const nrd_status rc = implicit_step(h, cur.data(), st.data(),
+                                                h->opt.bdf_max_order == 1);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return fail(NRD_EDEVICE, hipGetErrorString(e));
+            if (rc == NRD_OK) break;
+            if (rc != NRD_ENOTCONV) return rc;
+            // the batch was rolled back: halve the steps that failed
+            bool retry = false;
+            for (int p = 0; p < np; ++p) {
+                if (st[p].converged) continue;
+                if (halvings[p] >= ctl->max_halvings)
+                    return fail(NRD_ENOTCONV, "a step did not converge after max_halvings "
+                                              "halvings; state of the last accepted step");
+                cur[p] *= 0.5;
+                ++halvings[p];
+                retry = true;
+            }
+            if (!retry) return rc;
+        }
+        // next step sizes: PC.4.7 (EPS for a problem's first estimate) or EPS,
+        // ratio bounded; a BDF1 step keeps its size
+        for (int p = 0; p < np; ++p) {
+            if (t) t[p] += cur[p];
+            double ratio = 1.0;
+            const double err = st[p].err_norm;
+            if (err >= 0.0) {
+                if (err > 0.0) {
+                    if (ctl->controller == NRD_CTL_PC47 && h->err_prev[p] >= 0.0)
+                        ratio = std::pow(ctl->eps / err, 0.4 / 3.0) *
+                                std::pow(h->err_prev[p] / err, 0.7 / 3.0) * h->alpha[p];
+                    else
+                        ratio = std::pow(ctl->eps / err, 1.0 / 3.0);
+                } else {
+                    ratio = ctl->ratio_max;
+                }
+                h->err_prev[p] = err;
+            }
+            ratio = std::min(std::max(ratio, ctl->ratio_min), ctl->ratio_max);
+            dt[p] = ratio * cur[p];
+            if (stats) stats[(size_t)n * np + p] = st[p];
+        }
+    }
+    return NRD_OK;
 }
 
 nrd_status nrd_adjoint_run(nrd_hierarchy* h, const double* dt, int32_t nsteps, int32_t every,

@@ -45,6 +45,21 @@ __device__ __forceinline__ double block_min(double v, double* sh) {
     return r;
 }
 
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double block_max(double v, double* sh) {
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    const double r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    __syncthreads();
+    return r;
+}
+
 __device__ __forceinline__ int interior_index(const PatchInfo& p, int lin) {
     const int i = lin % p.n[0];
     const int r = lin / p.n[0];
@@ -449,6 +464,53 @@ void update_min(const Dev& D, hipStream_t s, const double* Z, int64_t zstride, i
                                                       zstride, nv, coef, cstride, x, keep,
                                                       partial, D.nl);
     k_min_partials<<<D.nprob, kBlock, 0, s>>>(D.prob_vtile0, partial, out);
+}
+
+// Scaled max norm of the BDF2 local error estimate (eq. bdf2le):
+// partial = max over the tile's composite cells of |c_p (x - x^p)| / (x + eta)
+// for both fields (eta_E, eta_T), a NaN counting as infinity.
+__global__ __launch_bounds__(kBlock) void k_err_max(
+    const Tile* __restrict__ vt, const PatchInfo* __restrict__ P,
+    const uint8_t* __restrict__ ctype, const int32_t* __restrict__ active,
+    const double* __restrict__ x, const double* __restrict__ xp,
+    const double* __restrict__ coef, double eta_E, double eta_T,
+    double* __restrict__ partial, int64_t nl) {
+    __shared__ double sh[4];
+    const Tile t = vt[blockIdx.x];
+    double m = 0.0;
+    if (!active || active[t.prob]) {
+        const PatchInfo& p = P[t.patch];
+        const double cf = coef[t.prob];
+        const bool cov = p.flags & PF_COVERED;
+        for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+            const int c = interior_index(p, lin);
+            if (cov && (ctype[c] & CT_COVERED)) continue;
+            const double vE = fabs(cf * (x[c] - xp[c])) / (x[c] + eta_E);
+            const double vT = fabs(cf * (x[c + nl] - xp[c + nl])) / (x[c + nl] + eta_T);
+            const double v = fmax(vE, vT);
+            m = fmax(m, (vE == vE && vT == vT) ? v : HUGE_VAL);
+        }
+    }
+    const double r = block_max(m, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_max_partials(const int32_t* __restrict__ t0,
+                                                         const double* __restrict__ partial,
+                                                         double* __restrict__ out) {
+    __shared__ double sh[4];
+    const int p = blockIdx.x;
+    double m = 0.0;
+    for (int i = t0[p] + threadIdx.x; i < t0[p + 1]; i += kBlock) m = fmax(m, partial[i]);
+    const double r = block_max(m, sh);
+    if (threadIdx.x == 0) out[p] = r;
+}
+
+void err_norm(const Dev& D, hipStream_t s, const double* x, const double* xp,
+              const double* coef, double eta_E, double eta_T, double* partial, double* out) {
+    k_err_max<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.ctype, D.active, x, xp, coef,
+                                           eta_E, eta_T, partial, D.nl);
+    k_max_partials<<<D.nprob, kBlock, 0, s>>>(D.prob_vtile0, partial, out);
 }
 
 __global__ __launch_bounds__(kBlock) void k_axpby(const Tile* __restrict__ vt,

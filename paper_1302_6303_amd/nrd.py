@@ -50,14 +50,17 @@ class nrd_options(C.Structure):
                 ("gmres_maxrestarts", C.c_int32), ("mg_nu_pre", C.c_int32),
                 ("mg_nu_post", C.c_int32), ("adjoint_slots", C.c_int32),
                 ("stencil", C.c_int32), ("zchunk", C.c_int32),
-                ("bdf_max_order", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("bdf_max_order", C.c_int32), ("error_estimate", C.c_int32),
+                ("reserved", C.c_int32 * 3), ("err_eta_E", C.c_double),
+                ("err_eta_T", C.c_double)]
 
 
 class nrd_step_stats(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("krylov_iters", C.c_int32),
                 ("positivity_cuts", C.c_int32), ("converged", C.c_int32),
                 ("fnorm0", C.c_double), ("fnorm", C.c_double),
-                ("krylov_per_newton", C.c_int32 * 24)]
+                ("krylov_per_newton", C.c_int32 * 24),
+                ("dt", C.c_double), ("err_norm", C.c_double)]
 
     def as_dict(self):
         return {"newton_iters": self.newton_iters,
@@ -65,7 +68,17 @@ class nrd_step_stats(C.Structure):
                 "positivity_cuts": self.positivity_cuts,
                 "converged": bool(self.converged), "fnorm0": self.fnorm0,
                 "fnorm": self.fnorm,
-                "krylov_per_newton": list(self.krylov_per_newton[:self.newton_iters])}
+                "krylov_per_newton": list(self.krylov_per_newton[:self.newton_iters]),
+                "dt": self.dt, "err_norm": self.err_norm}
+
+
+NRD_CTL_PC47, NRD_CTL_EPS = 0, 1
+
+
+class nrd_timectl(C.Structure):
+    _fields_ = [("eps", C.c_double), ("ratio_min", C.c_double),
+                ("ratio_max", C.c_double), ("controller", C.c_int32),
+                ("max_halvings", C.c_int32)]
 
 
 _H = C.c_void_p
@@ -92,6 +105,9 @@ _sigs = {
     "nrd_vjp": (C.c_int32, [_H, _P, _P, _P, _P]),
     "nrd_implicit_step": (C.c_int32, [_H, C.POINTER(C.c_double),
                                       C.POINTER(nrd_step_stats)]),
+    "nrd_adaptive_steps": (C.c_int32, [_H, C.POINTER(nrd_timectl), C.c_int32,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(nrd_step_stats)]),
     "nrd_adjoint_run": (C.c_int32, [_H, C.POINTER(C.c_double), C.c_int32,
                                     C.c_int32, _P, _P]),
     "nrd_dot": (C.c_int32, [_H, _P, _P, C.POINTER(C.c_double)]),
@@ -257,6 +273,22 @@ class Hierarchy:
         if raise_on_fail:
             check(rc)
         return rc, [s.as_dict() for s in st]
+
+    def adaptive_steps(self, nsteps, dt, eps, controller=NRD_CTL_PC47, ratio_min=0.25,
+                       ratio_max=2.0, max_halvings=10, t=None, raise_on_fail=True):
+        """nsteps controlled steps of every problem; returns (status, next
+        step sizes, times, per-step lists of per-problem stats)."""
+        ctl = nrd_timectl(float(eps), float(ratio_min), float(ratio_max), int(controller),
+                          int(max_halvings))
+        d = _dt(dt)
+        tt = _dt(t if t is not None else [0.0] * self.nprob)
+        st = (nrd_step_stats * (self.nprob * max(nsteps, 1)))()
+        rc = nrd_adaptive_steps(self.h, C.byref(ctl), int(nsteps), d, tt, st)
+        if raise_on_fail:
+            check(rc)
+        steps = [[st[n * self.nprob + p].as_dict() for p in range(self.nprob)]
+                 for n in range(nsteps)]
+        return rc, list(d), list(tt), steps
 
     def adjoint_run(self, dt, nsteps, ckpt_every, dJdE=None):
         gz = self.compact(1)

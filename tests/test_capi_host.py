@@ -76,3 +76,30 @@ def test_calls_before_binding_report_state_error():
     H = _create(w.problems, w.boxes)
     rc = nrd.nrd_residual(H.h, C.c_void_p(0), C.c_void_p(0))
     assert rc == nrd.NRD_ESTATE
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the ctypes mirrors of the public structs have the C sizes and offsets
+    import ctypes as C
+    import subprocess
+    from paper_1302_6303_amd import nrd
+    src = tmp_path / "sizes.c"
+    src.write_text("""
+#include <stddef.h>
+#include <stdio.h>
+#include "nrd.h"
+int main(void) {
+    printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(nrd_options), offsetof(nrd_options, err_eta_T),
+           sizeof(nrd_step_stats), offsetof(nrd_step_stats, err_norm), sizeof(nrd_timectl),
+           sizeof(nrd_problem), sizeof(nrd_box));
+    return 0;
+}
+""")
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [C.sizeof(nrd.nrd_options), nrd.nrd_options.err_eta_T.offset,
+            C.sizeof(nrd.nrd_step_stats), nrd.nrd_step_stats.err_norm.offset,
+            C.sizeof(nrd.nrd_timectl), C.sizeof(nrd.nrd_problem), C.sizeof(nrd.nrd_box)]
+    assert got == want

@@ -248,6 +248,57 @@ def test_implicit_step_positivity_stall():
     assert rc == -5 and not res[0].converged
 
 
+def test_adaptive_steps_match_the_oracle():
+    """PC.4.7 time-step control on three problems stepped together: two
+    Marshak fronts (8^3, 10^3) and a far-from-equilibrium 6^3 problem whose
+    first step of 1e-2 must be halved.  Against each problem's own oracle
+    adaptive run: accepted step sizes, error norms and the final state."""
+    from oracle.solvers import AdaptiveStepper
+    from tests.gpu_helpers import problem_slices
+    parts = [I.marshak_single(8, state="front"),
+             I.uniform_workload("u10", 10, I.box_field(I.sample_material_boxes(
+                 np.random.default_rng(31), 2)), 5e-4, 1, np.random.default_rng(32),
+                 state="front"),
+             _far_from_equilibrium([(23, 1e-4)])]
+    problems, boxes, z, E, T = [], [], [], [], []
+    for p, wp in enumerate(parts):
+        problems.append(wp.problems[0])
+        b = wp.boxes[0]
+        boxes.append(I.Box(p, 0, b.lo, b.hi))
+        z.append(wp.z[0])
+        E.append(wp.E[0])
+        T.append(wp.T[0])
+    w = I.Workload("adapt3", problems, boxes, z, E, T, np.array([1e-3, 5e-4, 1e-2]))
+    eps, nsteps = 5e-3, 6
+    kw = dict(newton_rtol=1e-10, newton_atol=1e-16, newton_maxit=24)
+    H = make(w, error_estimate=1, **kw)
+    rc, dt_next, t, steps = H.adaptive_steps(nsteps, list(w.dt), eps)
+    E_g, T_g = H.get_fields()
+    got = np.concatenate([to_host(E_g), to_host(T_g)])
+    sl = problem_slices(w)
+    for p in range(3):
+        s = system(w, pidx=p)
+        ad = AdaptiveStepper(s, state(s, w, pidx=p), w.dt[p], eps, 1e-5, 1e-5 ** 0.25,
+                             rtol=1e-10, atol=1e-16, maxit=24)
+        for _ in range(nsteps):
+            ad.advance()
+        dts = [steps[n][p]["dt"] for n in range(nsteps)]
+        errs = [steps[n][p]["err_norm"] for n in range(nsteps)]
+        for n, (d_o, e_o) in enumerate(ad.log):
+            assert abs(dts[n] / d_o - 1) < 1e-6, (p, n, dts[n], d_o)
+            if e_o is None:
+                assert errs[n] == -1.0
+            else:
+                assert abs(errs[n] / e_o - 1) < 1e-5, (p, n, errs[n], e_o)
+        assert abs(dt_next[p] / ad.dt - 1) < 1e-6
+        assert abs(t[p] - ad.t) < 1e-12
+        g = got[sl[p]]
+        n = s.nc
+        for f in (slice(0, n), slice(n, 2 * n)):
+            assert rel_err(g[f], ad.u[f]) < 1e-8
+    assert steps[0][2]["dt"] < 1e-2          # the third problem's first step was halved
+
+
 @pytest.mark.parametrize("stencil", [0, 1, 2, 3])
 def test_per_patch_launches_match_batched_bitwise(stencil):
     """One launch per patch and one launch over the whole patch table run the
