@@ -115,9 +115,14 @@ def composite_cells(w):
     return tot
 
 
-def run_solver(w, opts, steps, warmup, time_residual):
+def run_solver(w, opts, steps, warmup, time_residual, adaptive_eps=None):
+    """adaptive_eps: take the steps with PC.4.7 time-step control at this
+    local error tolerance (each step as long as the controller says, failed
+    solves retried with half the step) instead of the workload's fixed dt."""
     import torch
     from paper_1302_6303_amd import nrd
+    if adaptive_eps is not None:
+        opts.error_estimate = 1
     H = nrd.Hierarchy(w.problems, w.boxes, opts)
     u = compact_state(w)
     n = H.ncells
@@ -126,9 +131,20 @@ def run_solver(w, opts, steps, warmup, time_residual):
     log(f"tile shapes tuned for {tuned} patch-size classes")
     dt = list(w.dt)
     newton = krylov = 0
+    accepted = []
     tag = "mixed" if opts.precision == nrd.NRD_MIXED else "fp64"
+
+    def one_step():
+        nonlocal dt
+        if adaptive_eps is None:
+            _, st = H.implicit_step(dt)
+            return st
+        _, dt, _, steps_ = H.adaptive_steps(1, dt, adaptive_eps)
+        accepted.append([x["dt"] for x in steps_[0]])
+        return steps_[0]
+
     for i in range(warmup):
-        _, st = H.implicit_step(dt)
+        st = one_step()
         log(f"{tag} warmup step {i}: newton {sum(x['newton_iters'] for x in st)} "
             f"krylov {sum(x['krylov_iters'] for x in st)}")
     torch.cuda.synchronize()
@@ -136,7 +152,7 @@ def run_solver(w, opts, steps, warmup, time_residual):
         H.timer_enable(True)
     t0 = time.perf_counter()
     for i in range(steps):
-        _, st = H.implicit_step(dt)
+        st = one_step()
         newton += sum(s["newton_iters"] for s in st)
         krylov += sum(s["krylov_iters"] for s in st)
         log(f"{tag} step {i} done")
@@ -144,6 +160,8 @@ def run_solver(w, opts, steps, warmup, time_residual):
     t1 = time.perf_counter()
     res = {"s_per_step": (t1 - t0) / steps, "newton_per_step": newton / steps,
            "krylov_per_step": krylov / steps, "ws_GB": H.workspace_bytes / 1e9}
+    if adaptive_eps is not None:
+        res["accepted_dt_problem0"] = [round(a[0], 9) for a in accepted]
     if time_residual:
         # residual evaluations inside the timed steps always cover every
         # problem (Newton evaluates F for all of them)
@@ -309,6 +327,10 @@ def main():
                     help="2: BDF1 first step then BDF2; 1: BDF1 throughout")
     ap.add_argument("--dt-scale", type=float, default=1.0,
                     help="multiplies every problem's time step")
+    ap.add_argument("--adaptive-eps", type=float, default=None,
+                    help="PC.4.7 time-step control with this local error tolerance "
+                         "(eps_t; the paper uses 5e-4 at 32^3 resolution, halved per "
+                         "doubling); default: the workload's fixed time steps")
     ap.add_argument("--ckpt-every", type=int, default=10,
                     help="adjoint workload: checkpoint interval")
     ap.add_argument("--fp64-batched", action="store_true",
@@ -332,7 +354,7 @@ def main():
     mixed = run_solver(w, nrd.default_options(precision=nrd.NRD_MIXED,
                                               launch=nrd.NRD_BATCHED, use_graph=use_graph,
                                               bdf_max_order=a.bdf_max_order),
-                       a.steps, a.warmup, True)
+                       a.steps, a.warmup, True, a.adaptive_eps)
     mixed["use_graph"] = use_graph
     plain = None
     if not a.no_plain:
@@ -341,13 +363,13 @@ def main():
         plain = run_solver(w, nrd.default_options(precision=nrd.NRD_FP64,
                                                   launch=nrd.NRD_PER_PATCH, stencil=1,
                                                   bdf_max_order=a.bdf_max_order),
-                           a.steps, a.warmup, False)
+                           a.steps, a.warmup, False, a.adaptive_eps)
     batched64 = None
     if a.fp64_batched:
         batched64 = run_solver(w, nrd.default_options(precision=nrd.NRD_FP64,
                                                       launch=nrd.NRD_BATCHED,
                                                       bdf_max_order=a.bdf_max_order),
-                               a.steps, a.warmup, False)
+                               a.steps, a.warmup, False, a.adaptive_eps)
     res_s = mixed["residual_ms_avg"] / 1e3
     res_cells = mixed["residual_cells_avg"]           # per launch, average
     gcells = res_cells / res_s / 1e9
@@ -380,6 +402,8 @@ def main():
                    "boxes": len(w.boxes), "cells": w.ncells(),
                    "composite_cells": ncomp,
                    "dt_scale": a.dt_scale,
+                   "time_control": (f"PC.4.7, eps_t {a.adaptive_eps}" if a.adaptive_eps
+                                    else "fixed steps"),
                    "solver": ("BDF1->BDF2" if a.bdf_max_order == 2 else "BDF1") +
                              ", Newton rtol 1e-8, FGMRES(30), FAC V(1,0) + MG V(1,1)"},
         "roofline": {"bound": "hbm", "kernel": "k_stencil_s<0> (residual)",
