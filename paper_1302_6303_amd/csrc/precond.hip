@@ -270,6 +270,10 @@ __global__ __launch_bounds__(kBlock) void k_comp_res(const int32_t* __restrict__
     }
     const double beta = ps[t.prob].beta;
     const int st[3] = {1, p.sy, p.sz};
+    // faces classified with selects (operands loaded unconditionally; ghost
+    // slots are finite): a physical face carries the Marshak flux of E or
+    // nothing, a face whose flux comes from flux matching nothing, any other
+    // face the flux D (u_b - u_a) / h
     for (int fld = 0; fld < 2; ++fld) {
         const PT* uf = u + fld * nl;
         const PT uc = uf[c];
@@ -278,23 +282,20 @@ __global__ __launch_bounds__(kBlock) void k_comp_res(const int32_t* __restrict__
         for (int d = 0; d < 3; ++d) {
             const PT* Dd = D + (fld * 3 + d) * nl;
             const PT ih = (PT)p.ih[d];
-            PT lo = PT(0), hi = PT(0);
-            if (id[d] == 0 && ((p.phys >> (2 * d)) & 1)) {
-                if (fld == 0 && ((p.robin >> (2 * d)) & 1)) {
-                    const PT Db = Dd[c];
-                    lo = PT(2) * Db * uc / (PT(4) * Db + (PT)p.h[d]);
-                }
-            } else if (!((ct >> (2 * d + 1)) & 1)) {
-                lo = Dd[c] * (uc - uf[c - st[d]]) * ih;
-            }
             const int up = c + st[d];
-            if (id[d] == p.n[d] - 1 && ((p.phys >> (2 * d + 1)) & 1)) {
-                if (fld == 0 && ((p.robin >> (2 * d + 1)) & 1)) {
-                    const PT Db = Dd[up];
-                    hi = -PT(2) * Db * uc / (PT(4) * Db + (PT)p.h[d]);
-                }
-            } else if (!((ct >> (2 * d + 2)) & 1)) {
-                hi = Dd[up] * (uf[up] - uc) * ih;
+            const PT Dlo = Dd[c], Dhi = Dd[up];
+            const PT ulo = uf[c - st[d]], uhi = uf[up];
+            const bool plo = id[d] == 0 && ((p.phys >> (2 * d)) & 1);
+            const bool phi = id[d] == p.n[d] - 1 && ((p.phys >> (2 * d + 1)) & 1);
+            const bool mlo = (ct >> (2 * d + 1)) & 1;
+            const bool mhi = (ct >> (2 * d + 2)) & 1;
+            PT lo = (plo || mlo) ? PT(0) : Dlo * (uc - ulo) * ih;
+            PT hi = (phi || mhi) ? PT(0) : Dhi * (uhi - uc) * ih;
+            if (fld == 0 && ((p.robin >> (2 * d)) & 3)) {      // uniform per patch
+                if (plo && ((p.robin >> (2 * d)) & 1))
+                    lo = PT(2) * Dlo * uc / (PT(4) * Dlo + (PT)p.h[d]);
+                if (phi && ((p.robin >> (2 * d + 1)) & 1))
+                    hi = -PT(2) * Dhi * uc / (PT(4) * Dhi + (PT)p.h[d]);
             }
             div += (hi - lo) * ih;
         }
