@@ -22,6 +22,14 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
     return x * base + (x < rem ? x : rem) + q;
 }
 
+// Tile of this workgroup in a launch over tiles [t0, t0 + gridDim.x), or,
+// given an index map (the tiles of the problems being solved, in list
+// order), over map[0 .. gridDim.x).
+__device__ __forceinline__ int tile_index(const int32_t* map, int t0) {
+    const int i = xcd_tile(blockIdx.x, gridDim.x);
+    return map ? map[i] : t0 + i;
+}
+
 // Event timing of operator launches on the library stream (implemented by
 // the hierarchy; inactive unless timing is enabled).
 struct Clock {
@@ -59,6 +67,11 @@ struct Dev {
     const uint8_t* ctype = nullptr;
     const ProbScalars* ps = nullptr;         // device [nprob]
     const int32_t* active = nullptr;         // device [nprob], 1 = work on it
+    // stencil tiles (plane tiles, or flat tiles for the flat variant) of the
+    // problems flagged in active, valid while active is set; NULL when the
+    // launches must read the flags instead (captured graphs)
+    const int32_t* amap = nullptr;
+    int32_t namap = 0;
     const double* z3 = nullptr;              // native, z^3 with ghosts
     int32_t level_shadow0[kMaxLev + 1] = {}; // prolongation shadow cells per level
 };
@@ -75,13 +88,16 @@ void sibling_exchange_f(const Dev& D, hipStream_t s, float* x, int nf, int lev);
 void sibling_exchange_d(const Dev& D, hipStream_t s, double* x, int nf, int lev);
 
 // F = c0 u - b - dt f(u) over tiles [t0, t0+nt) (bricks if D.bricks);
-// covered cells = 0.
+// covered cells = 0.  residual_all / jvp_all cover every tile, or only the
+// tiles of the active problems when D.amap is set.
 void residual(const Dev& D, hipStream_t s, int t0, int nt, const double* u,
               const double* b, double* F);
+void residual_all(const Dev& D, hipStream_t s, const double* u, const double* b, double* F);
 void residual_reflux(const Dev& D, hipStream_t s, const double* u, double* F);
 // Jv
 void jvp(const Dev& D, hipStream_t s, int t0, int nt, const double* u,
          const double* v, double* Jv);
+void jvp_all(const Dev& D, hipStream_t s, const double* u, const double* v, double* Jv);
 void jvp_reflux(const Dev& D, hipStream_t s, const double* u, const double* v,
                 double* Jv);
 // transpose: gE, gT (native, interior) and gz3 (native) = lambda^T dF/dz^3

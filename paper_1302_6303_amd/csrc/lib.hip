@@ -72,7 +72,7 @@ struct nrd_hierarchy final : public Clock {
     // workspace offsets
     struct Off {
         size_t patches, tiles, stiles, vtiles, prob_vtile0, gcopy, gcf, sib, sync[kMaxLev], rfaces,
-            rcells, ctype, shadows, shadow_src, coff, ps, active;
+            rcells, ctype, shadows, shadow_src, coff, ps, active, amap;
         size_t mg_box[kMaxMG], mg_tiles[kMaxMG], mg_box_of[kMaxMG], mg_smooth[kMaxMG],
             mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bot_probs, bot_boxes, bot_grid, bottom_off,
             Lbuf, Xbuf;
@@ -97,6 +97,8 @@ struct nrd_hierarchy final : public Clock {
         *minout, *ckpt, *fdF, *fdw, *fdsum;
     const double* fd_base = nullptr;   // F at the Newton iterate (Jacobian-free mode)
     int32_t *kdim, *flag, *active;
+    int32_t* amap;                  // stencil tiles of the active problems
+    std::vector<int32_t> host_amap;
     ProbScalars* ps;
     // timers
     bool timing = false;
@@ -207,6 +209,7 @@ static void layout(nrd_hierarchy* h) {
     o.coff = b.take(sizeof(int64_t) * t.compact_off.size());
     o.ps = b.take(sizeof(ProbScalars) * nprob);
     o.active = b.take(sizeof(int32_t) * nprob);
+    o.amap = b.take(sizeof(int32_t) * std::max(h->stile_cap, std::max<size_t>(1, t.tiles.size())));
     const int G = (int)t.mg.size() - 1;
     for (int g = 0; g <= G; ++g) {
         if (g >= 1) {
@@ -449,6 +452,7 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     D.z3 = h->at<double>(o.z3);
     h->ps = h->at<ProbScalars>(o.ps);
     h->active = h->at<int32_t>(o.active);
+    h->amap = h->at<int32_t>(o.amap);
     h->z = h->at<double>(o.z);
     h->z3 = h->at<double>(o.z3);
     h->cur = h->at<double>(o.cur);
@@ -542,7 +546,7 @@ static void op_residual(nrd_hierarchy* h, double* u, double* F, bool prepared = 
             residual(D, h->stream, a0, n0, u, h->bvec, F);
         }
     } else {
-        residual(D, h->stream, 0, h->ntiles_stencil(), u, h->bvec, F);
+        residual_all(D, h->stream, u, h->bvec, F);
     }
     residual_reflux(D, h->stream, u, F);
     h->toc_cells(NRD_TIMER_RESIDUAL, tk, cells);
@@ -567,7 +571,7 @@ static void op_jvp_fd(nrd_hierarchy* h, double* u, double* v, double* Jv, bool u
                 residual(D, s, a0, n0, u, h->bvec, h->fdF);
             }
         } else {
-            residual(D, s, 0, h->ntiles_stencil(), u, h->bvec, h->fdF);
+            residual_all(D, s, u, h->bvec, h->fdF);
         }
         residual_reflux(D, s, u, h->fdF);
         F0 = h->fdF;
@@ -582,7 +586,7 @@ static void op_jvp_fd(nrd_hierarchy* h, double* u, double* v, double* Jv, bool u
             residual(D, s, a0, n0, h->fdw, h->bvec, Jv);
         }
     } else {
-        residual(D, s, 0, h->ntiles_stencil(), h->fdw, h->bvec, Jv);
+        residual_all(D, s, h->fdw, h->bvec, Jv);
     }
     residual_reflux(D, s, h->fdw, Jv);
     fd_quotient(D, s, h->fdsum, F0, Jv);
@@ -606,7 +610,7 @@ static void op_jvp(nrd_hierarchy* h, double* u, double* v, double* Jv, bool u_pr
             jvp(D, h->stream, a0, n0, u, v, Jv);
         }
     } else {
-        jvp(D, h->stream, 0, h->ntiles_stencil(), u, v, Jv);
+        jvp_all(D, h->stream, u, v, Jv);
     }
     jvp_reflux(D, h->stream, u, v, Jv);
     h->toc_cells(NRD_TIMER_JVP, tk, cells);
@@ -637,9 +641,31 @@ static void pc_apply_t(nrd_hierarchy* h, const double* w, double* y) {
         h->pcd.apply_transpose(h->stream, w, y);
 }
 
+// Sends the active flags to the device together with the list of stencil
+// tiles of the flagged problems, so masked residual and Jacobian launches
+// have no workgroups for finished problems (captured graphs keep reading the
+// flags: their launch sizes are fixed).
 static nrd_status upload_active(nrd_hierarchy* h) {
     HIPCHK(hipMemcpyAsync(h->active, h->host_active.data(), 4 * h->t.nprob,
                           hipMemcpyHostToDevice, h->stream));
+    h->D.amap = nullptr;
+    h->D.namap = 0;
+    if (h->opt.use_graph) return NRD_OK;
+    const Tables& t = h->t;
+    auto& m = h->host_amap;
+    m.clear();
+    if (h->D.bricks) {
+        for (int32_t i = 0; i < (int32_t)t.stiles.size(); ++i)
+            if (h->host_active[t.stiles[i].prob]) m.push_back(i);
+    } else {
+        for (int32_t i = 0; i < (int32_t)t.tiles.size(); ++i)
+            if (h->host_active[t.tiles[i].prob]) m.push_back(i);
+    }
+    if (!m.empty())
+        HIPCHK(hipMemcpyAsync(h->amap, m.data(), 4 * m.size(), hipMemcpyHostToDevice,
+                              h->stream));
+    h->D.amap = h->amap;
+    h->D.namap = (int32_t)m.size();
     return NRD_OK;
 }
 
@@ -1878,6 +1904,7 @@ nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed
     HIPCHK(up(s, h->ws + h->o.stiles, t.stiles));
     for (int l = 0; l <= t.nlev; ++l) h->D.level_stile0[l] = t.level_stile0[l];
     h->drop_graphs();                               // captured launches used the old tiles
+    RCHK(upload_active(h));                         // tile map of the new list
     HIPCHK(hipStreamSynchronize(s));
     return NRD_OK;
 }

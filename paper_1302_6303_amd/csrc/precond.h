@@ -85,7 +85,7 @@ struct PcArrays {
     void apply_transpose(hipStream_t s, const double* w, double* y) const;
     const PT* fac(hipStream_t s) const;     // returns u or e (one level)
     void vcycle(hipStream_t s) const;
-    void composite_residual(hipStream_t s) const;
+    void composite_residual(hipStream_t s, int lev) const;
     void fill_ghosts(hipStream_t s, PT* x) const;
     void restrict_(hipStream_t s, PT* x, int lev_lo) const;
     void siblings(hipStream_t s, PT* x, int lev) const;

@@ -913,18 +913,19 @@ void PcArrays<double>::siblings(hipStream_t s, double* x, int lev) const {
 }
 
 template <typename PT>
-void PcArrays<PT>::composite_residual(hipStream_t s) const {
-    // r = f - A^c u on composite cells; covered r <- restriction of finer r
+void PcArrays<PT>::composite_residual(hipStream_t s, int lev) const {
+    // r = f - A^c u on the composite cells of levels lev and finer; covered r
+    // <- restriction of finer r on those levels (what the level-lev solve
+    // reads).  The covered cells of u already hold the restriction of u.
     const Dev& d = *D;
-    restrict_(s, u, 0);
     fill_ghosts(s, u);
-    const int ntiles = d.level_tile0[d.nlev];
-    k_comp_res<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, d.ctype, Dface, f, u, r,
-                                            d.nl);
+    const int t0 = d.level_tile0[lev], nt = d.level_tile0[d.nlev] - t0;
+    k_comp_res<PT><<<nt, kBlock, 0, s>>>(d.active, d.tiles + t0, d.patches, d.ps, d.ctype,
+                                         Dface, f, u, r, d.nl);
     if (d.nrcells > 0)
         k_comp_reflux<PT><<<nblocks(d.nrcells), kBlock, 0, s>>>(
             d.rcells, d.nrcells, d.rfaces, d.patches, d.ps, Dface, u, r, d.nl);
-    restrict_(s, r, 0);
+    restrict_(s, r, lev);
 }
 
 template <typename PT>
@@ -942,11 +943,10 @@ const PT* PcArrays<PT>::fac(hipStream_t s) const {
     for (int lev = L; lev >= 0; --lev) {
         const PT* rhs = r;
         if (lev == L) {
-            // u = 0: r = f on composite cells, restricted below
+            // u = 0: r = f (the finest level has no covered cells)
             k_copy_t<PT><<<nblocks(2 * d.nl), kBlock, 0, s>>>(f, r, 2 * d.nl);
-            restrict_(s, r, 0);
         } else {
-            composite_residual(s);
+            composite_residual(s, lev);     // u was restricted at the end of lev + 1
         }
         const int t0 = d.level_tile0[lev], nt = d.level_tile0[lev + 1] - t0;
         if (lev > 0) {

@@ -259,14 +259,15 @@ __device__ __forceinline__ double robin_any(double E, double T, double z, double
 // plane.  Physical faces are evaluated by the cell that owns them.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_stencil_z(
-    const STile* __restrict__ tiles, int t0, const PatchInfo* __restrict__ P,
+    const STile* __restrict__ tiles, int t0, const int32_t* __restrict__ map,
+    const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const int32_t* __restrict__ active,
     const uint8_t* __restrict__ ctype, const double* __restrict__ u,
     const double* __restrict__ v, const double* __restrict__ z3,
     const double* __restrict__ b, double* __restrict__ out, int64_t nl) {
     __shared__ double fxs[2][2][kBlock];
     __shared__ double fys[2][2][kBlock];
-    const STile t = tiles[t0 + xcd_tile(blockIdx.x, gridDim.x)];
+    const STile t = tiles[tile_index(map, t0)];
     if (active && !active[t.prob]) return;          // uniform over the workgroup
     const PatchInfo& p = P[t.patch];
     const ProbScalars& q = ps[t.prob];
@@ -381,12 +382,13 @@ __global__ __launch_bounds__(kBlock) void k_stencil_z(
 // z face is carried in registers to the next plane.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_stencil_w(
-    const STile* __restrict__ tiles, int t0, const PatchInfo* __restrict__ P,
+    const STile* __restrict__ tiles, int t0, const int32_t* __restrict__ map,
+    const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const int32_t* __restrict__ active,
     const uint8_t* __restrict__ ctype, const double* __restrict__ u,
     const double* __restrict__ v, const double* __restrict__ z3,
     const double* __restrict__ b, double* __restrict__ out, int64_t nl) {
-    const STile t = tiles[t0 + xcd_tile(blockIdx.x, gridDim.x)];
+    const STile t = tiles[tile_index(map, t0)];
     if (active && !active[t.prob]) return;
     const PatchInfo& p = P[t.patch];
     const ProbScalars& q = ps[t.prob];
@@ -491,12 +493,13 @@ __global__ __launch_bounds__(kBlock) void k_stencil_w(
 // fastest); all six faces of the cell are evaluated by that thread.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_stencil_flat(
-    const Tile* __restrict__ tiles, int t0, const PatchInfo* __restrict__ P,
+    const Tile* __restrict__ tiles, int t0, const int32_t* __restrict__ map,
+    const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const int32_t* __restrict__ active,
     const uint8_t* __restrict__ ctype, const double* __restrict__ u,
     const double* __restrict__ v, const double* __restrict__ z3,
     const double* __restrict__ b, double* __restrict__ out, int64_t nl) {
-    const Tile t = tiles[t0 + xcd_tile(blockIdx.x, gridDim.x)];
+    const Tile t = tiles[tile_index(map, t0)];
     if (active && !active[t.prob]) return;
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& p = P[t.patch];
@@ -580,7 +583,8 @@ constexpr int kStagePer = (kStageLen + kBlock - 1) / kBlock;
 
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_stencil_s(
-    const STile* __restrict__ tiles, int t0, const PatchInfo* __restrict__ P,
+    const STile* __restrict__ tiles, int t0, const int32_t* __restrict__ map,
+    const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const int32_t* __restrict__ active,
     const uint8_t* __restrict__ ctype, const double* __restrict__ u,
     const double* __restrict__ v, const double* __restrict__ z3,
@@ -588,7 +592,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_s(
     constexpr int NA = MODE ? 5 : 3;            // E, T, z^3 (, vE, vT)
     __shared__ double sl[NA][kStageLen];
     __shared__ double fl[4][kStageCells];       // low x E/T, low y E/T fluxes
-    const STile t = tiles[t0 + xcd_tile(blockIdx.x, gridDim.x)];
+    const STile t = tiles[tile_index(map, t0)];
     if (active && !active[t.prob]) return;      // uniform over the workgroup
     const PatchInfo& p = P[t.patch];
     const ProbScalars& q = ps[t.prob];
@@ -855,21 +859,51 @@ __global__ __launch_bounds__(kBlock) void k_reflux(
     out[cell.c + nl] -= q.dt * accT;
 }
 
-void residual(const Dev& D, hipStream_t s, int t0, int nt, const double* u, const double* b,
-              double* F) {
+static void residual_launch(const Dev& D, hipStream_t s, int t0, int nt, const int32_t* map,
+                            const double* u, const double* b, double* F) {
     if (nt <= 0) return;
     if (D.bricks == 3)
-        k_stencil_s<0><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
-                                             u, nullptr, D.z3, b, F, D.nl);
+        k_stencil_s<0><<<nt, kBlock, 0, s>>>(D.stiles, t0, map, D.patches, D.ps, D.active,
+                                             D.ctype, u, nullptr, D.z3, b, F, D.nl);
     else if (D.bricks == 1)
-        k_stencil_z<0><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
-                                             u, nullptr, D.z3, b, F, D.nl);
+        k_stencil_z<0><<<nt, kBlock, 0, s>>>(D.stiles, t0, map, D.patches, D.ps, D.active,
+                                             D.ctype, u, nullptr, D.z3, b, F, D.nl);
     else if (D.bricks == 2)
-        k_stencil_w<0><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
-                                             u, nullptr, D.z3, b, F, D.nl);
+        k_stencil_w<0><<<nt, kBlock, 0, s>>>(D.stiles, t0, map, D.patches, D.ps, D.active,
+                                             D.ctype, u, nullptr, D.z3, b, F, D.nl);
     else
-        k_stencil_flat<0><<<nt, kBlock, 0, s>>>(D.tiles, t0, D.patches, D.ps, D.active,
+        k_stencil_flat<0><<<nt, kBlock, 0, s>>>(D.tiles, t0, map, D.patches, D.ps, D.active,
                                                 D.ctype, u, nullptr, D.z3, b, F, D.nl);
+}
+static void jvp_launch(const Dev& D, hipStream_t s, int t0, int nt, const int32_t* map,
+                       const double* u, const double* v, double* Jv) {
+    if (nt <= 0) return;
+    if (D.bricks == 3)
+        k_stencil_s<1><<<nt, kBlock, 0, s>>>(D.stiles, t0, map, D.patches, D.ps, D.active,
+                                             D.ctype, u, v, D.z3, nullptr, Jv, D.nl);
+    else if (D.bricks == 1)
+        k_stencil_z<1><<<nt, kBlock, 0, s>>>(D.stiles, t0, map, D.patches, D.ps, D.active,
+                                             D.ctype, u, v, D.z3, nullptr, Jv, D.nl);
+    else if (D.bricks == 2)
+        k_stencil_w<1><<<nt, kBlock, 0, s>>>(D.stiles, t0, map, D.patches, D.ps, D.active,
+                                             D.ctype, u, v, D.z3, nullptr, Jv, D.nl);
+    else
+        k_stencil_flat<1><<<nt, kBlock, 0, s>>>(D.tiles, t0, map, D.patches, D.ps, D.active,
+                                                D.ctype, u, v, D.z3, nullptr, Jv, D.nl);
+}
+static int stencil_tiles(const Dev& D) {
+    return D.bricks ? D.level_stile0[D.nlev] : D.level_tile0[D.nlev];
+}
+
+void residual(const Dev& D, hipStream_t s, int t0, int nt, const double* u, const double* b,
+              double* F) {
+    residual_launch(D, s, t0, nt, nullptr, u, b, F);
+}
+void residual_all(const Dev& D, hipStream_t s, const double* u, const double* b, double* F) {
+    if (D.active && D.amap)
+        residual_launch(D, s, 0, D.namap, D.amap, u, b, F);
+    else
+        residual_launch(D, s, 0, stencil_tiles(D), nullptr, u, b, F);
 }
 void residual_reflux(const Dev& D, hipStream_t s, const double* u, double* F) {
     if (D.nrcells == 0) return;
@@ -879,19 +913,13 @@ void residual_reflux(const Dev& D, hipStream_t s, const double* u, double* F) {
 }
 void jvp(const Dev& D, hipStream_t s, int t0, int nt, const double* u, const double* v,
          double* Jv) {
-    if (nt <= 0) return;
-    if (D.bricks == 3)
-        k_stencil_s<1><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
-                                             u, v, D.z3, nullptr, Jv, D.nl);
-    else if (D.bricks == 1)
-        k_stencil_z<1><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
-                                             u, v, D.z3, nullptr, Jv, D.nl);
-    else if (D.bricks == 2)
-        k_stencil_w<1><<<nt, kBlock, 0, s>>>(D.stiles, t0, D.patches, D.ps, D.active, D.ctype,
-                                             u, v, D.z3, nullptr, Jv, D.nl);
+    jvp_launch(D, s, t0, nt, nullptr, u, v, Jv);
+}
+void jvp_all(const Dev& D, hipStream_t s, const double* u, const double* v, double* Jv) {
+    if (D.active && D.amap)
+        jvp_launch(D, s, 0, D.namap, D.amap, u, v, Jv);
     else
-        k_stencil_flat<1><<<nt, kBlock, 0, s>>>(D.tiles, t0, D.patches, D.ps, D.active,
-                                                D.ctype, u, v, D.z3, nullptr, Jv, D.nl);
+        jvp_launch(D, s, 0, stencil_tiles(D), nullptr, u, v, Jv);
 }
 void jvp_reflux(const Dev& D, hipStream_t s, const double* u, const double* v, double* Jv) {
     if (D.nrcells == 0) return;
