@@ -379,7 +379,8 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
                         int32_t gidx = nidx(pi, L[0], L[1], L[2]);
                         int32_t inner = nidx(pi, I[0], I[1], I[2]);
                         if (phys) {
-                            t.gcopy.push_back({gidx, inner});
+                            // physical faces are evaluated from the cell itself
+                            // (zero flux or Marshak); no kernel reads these ghosts
                             t.ctype[gidx] = GK_PHYS;
                             continue;
                         }

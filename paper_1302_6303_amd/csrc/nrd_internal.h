@@ -127,7 +127,8 @@ struct Tables {
     std::vector<int32_t> prob_vtile0;        // [nprob+1]
     std::vector<std::vector<Tile>> patch_tiles;   // per patch (per-patch launches)
 
-    std::vector<GhostCopy> gcopy;            // physical + sibling
+    std::vector<GhostCopy> gcopy;            // sibling copies (physical ghosts are
+                                             // never read: no entries)
     std::vector<GhostCF> gcf;
     std::vector<int32_t> level_sib0;         // sibling copies per level: CSR
     std::vector<GhostCopy> sib;              // sibling copies sorted by level
