@@ -1,4 +1,4 @@
-// Launchers of the HIP kernels (defined in stencil.hip, vec.hip, precond.hip).
+// Launchers of the HIP kernels (defined in sync.hip, stencil.hip, vec.hip, precond.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -76,8 +76,9 @@ struct Dev {
     int32_t level_shadow0[kMaxLev + 1] = {}; // prolongation shadow cells per level
 };
 
-// ---- stencil.hip --------------------------------------------------------
-// x: NF fields of native length nl.  Fills every face ghost of every patch.
+// ---- sync.hip -----------------------------------------------------------
+// x: NF fields of native length nl.  Fills the sibling and coarse-fine
+// ghosts of every patch (physical ghosts are never read).
 void ghost_fill_d(const Dev& D, hipStream_t s, double* x, int nf);
 void ghost_fill_f(const Dev& D, hipStream_t s, float* x, int nf);
 // covered cells <- mean of children, finest level first
@@ -86,6 +87,8 @@ void restrict_f(const Dev& D, hipStream_t s, float* x, int nf, int lev_lo = 0);
 // sibling ghosts of one level only
 void sibling_exchange_f(const Dev& D, hipStream_t s, float* x, int nf, int lev);
 void sibling_exchange_d(const Dev& D, hipStream_t s, double* x, int nf, int lev);
+
+// ---- stencil.hip --------------------------------------------------------
 
 // F = c0 u - b - dt f(u) over tiles [t0, t0+nt) (bricks if D.bricks);
 // covered cells = 0.  residual_all / jvp_all cover every tile, or only the
