@@ -50,12 +50,12 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per composite cell of the residual on the ensemble workload from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch, FETCH scaled by
 # the factor a plain 2 GiB copy reads in the same run, WRITE by its own
-# factor; launches of one implicit step over the cells they covered), valid
-# for the stencil source with this SHA-256 prefix; null otherwise.
-MEASURED_TRAFFIC = {"workload": "ensemble", "stencil_sha256": "2fa3d00d82a23e09",
-                    "bytes_per_cell": 63.5590,
-                    "fetch_bytes_per_cell": 46.9628,
-                    "write_bytes_per_cell": 16.5962,
+# factor; the 20 full launches timed after the steps), valid for the stencil
+# source with this SHA-256 prefix; null otherwise.
+MEASURED_TRAFFIC = {"workload": "ensemble", "stencil_sha256": "9cd1c74d5a05aa10",
+                    "bytes_per_cell": 63.6171,
+                    "fetch_bytes_per_cell": 47.0014,
+                    "write_bytes_per_cell": 16.6157,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 
 
