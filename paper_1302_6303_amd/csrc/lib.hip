@@ -77,8 +77,8 @@ struct nrd_hierarchy final : public Clock {
             mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bot_probs, bot_boxes, bot_grid, bottom_off,
             Lbuf, Xbuf;
         size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, gz3, V, Z, pred;
-        size_t pc_D, pc_sigma, pc_e, pc_u, pc_r, pc_f, pc_tmp, pc_shadow;
-        size_t mg_D[kMaxMG], mg_e[kMaxMG], mg_f[kMaxMG], mg_r[kMaxMG];
+        size_t pc_D, pc_sigma, pc_e, pc_u, pc_r, pc_f, pc_shadow;
+        size_t mg_D[kMaxMG], mg_e[kMaxMG], mg_f[kMaxMG];
         size_t partial, dots, h1, h2, hn2, H, cs, sn, g, rho, vscale, y, kdim, coefA, coefB,
             minout, flag, ckpt, fdF, fdw, fdsum;
     } o;
@@ -258,14 +258,12 @@ static void layout(nrd_hierarchy* h) {
     o.pc_u = b.take(es * 2 * nl);
     o.pc_r = b.take(es * 2 * nl);
     o.pc_f = b.take(es * 2 * nl);
-    o.pc_tmp = b.take(es * 2 * nl);
     o.pc_shadow = b.take(es * 2 * std::max<int64_t>(1, t.shadow_len));
     for (int g = 1; g <= G; ++g) {
         const int64_t n = t.mg[g].len;
         o.mg_D[g] = b.take(es * 6 * n);
         o.mg_e[g] = b.take(es * 2 * n);
         o.mg_f[g] = b.take(es * 2 * n);
-        o.mg_r[g] = b.take(es * 2 * n);
     }
     // reductions and per-problem scalars
     o.partial = b.take(8 * 16 * std::max<size_t>(1, t.vtiles.size()));
@@ -310,7 +308,6 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
     pc.u = h->at<PT>(o.pc_u);
     pc.r = h->at<PT>(o.pc_r);
     pc.f = h->at<PT>(o.pc_f);
-    pc.tmp = h->at<PT>(o.pc_tmp);
     pc.shadow = h->at<PT>(o.pc_shadow);
     pc.shadow_src = h->at<int32_t>(o.shadow_src);
     pc.shadows = h->at<ShadowPatch>(o.shadows);
@@ -326,7 +323,6 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
             pc.mg.Dg[g] = h->at<PT>(o.mg_D[g]);
             pc.mg.eg[g] = h->at<PT>(o.mg_e[g]);
             pc.mg.fg[g] = h->at<PT>(o.mg_f[g]);
-            pc.mg.rg[g] = h->at<PT>(o.mg_r[g]);
         }
         pc.mg.box_of[g] = h->at<int32_t>(o.mg_box_of[g]);
         pc.mg.smooth_tiles[g] = h->at<Tile>(o.mg_smooth[g]);

@@ -43,7 +43,6 @@ struct PcArrays {
     PT* u = nullptr;
     PT* r = nullptr;
     PT* f = nullptr;
-    PT* tmp = nullptr;
     PT* shadow = nullptr;       // 2 * shadow_len
     const int32_t* shadow_src = nullptr;
     const ShadowPatch* shadows = nullptr;
@@ -71,7 +70,6 @@ struct PcArrays {
         PT* Dg[kMaxMG] = {};
         PT* eg[kMaxMG] = {};
         PT* fg[kMaxMG] = {};
-        PT* rg[kMaxMG] = {};
     } mg;
     int p2_mode = 0;
     int nu_pre = 1, nu_post = 1;

@@ -142,13 +142,13 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarsen(const int32_t* __restrict
 // nothing (plus the Marshak term for E on a Robin face); a coarse-fine face
 // contributes 2/3 a to the diagonal only.  Neighbour values are loaded
 // unconditionally (ghost slots always hold finite values).
-template <typename PT, int MODE>   // MODE 0: RBGS colour (zero start) 1: colour 2: residual
-__device__ __forceinline__ void level_update(const PatchInfo& p, const int id[3], double beta,
-                                             const uint8_t* __restrict__ ctype,
-                                             const PT* __restrict__ D,
-                                             const PT* __restrict__ f, PT* __restrict__ e,
-                                             PT* __restrict__ r, int64_t nl) {
-    const int c = nat(p, id[0], id[1], id[2]);
+// Diagonal dg and neighbour sum ns of both fields at cell c = id (ZERO: the
+// iterate is taken as zero, ns = 0).
+template <typename PT, bool ZERO>
+__device__ __forceinline__ void level_terms(const PatchInfo& p, const int id[3], int c,
+                                            double beta, const uint8_t* __restrict__ ctype,
+                                            const PT* __restrict__ D, const PT* __restrict__ e,
+                                            int64_t nl, PT dgo[2], PT nso[2]) {
     const int st[3] = {1, p.sy, p.sz};
     PT bh2[3];
     bool ph[6], cf[6];
@@ -177,7 +177,7 @@ __device__ __forceinline__ void level_update(const PatchInfo& p, const int id[3]
             for (int s = 0; s < 2; ++s) {
                 const int fc = 2 * d + s;
                 const PT a = bh2[d] * Dd[s ? c + st[d] : c];
-                const PT enb = (MODE == 0) ? PT(0) : ef[s ? c + st[d] : c - st[d]];
+                const PT enb = ZERO ? PT(0) : ef[s ? c + st[d] : c - st[d]];
                 const bool open = !(ph[fc] || cf[fc]);
                 dg += open ? a : (cf[fc] ? PT(2.0 / 3.0) * a : PT(0));
                 ns += open ? a * enb : PT(0);
@@ -196,11 +196,27 @@ __device__ __forceinline__ void level_update(const PatchInfo& p, const int id[3]
                     }
                 }
         }
+        dgo[fld] = dg;
+        nso[fld] = ns;
+    }
+}
+
+template <typename PT, int MODE>   // MODE 0: RBGS colour (zero start) 1: colour 2: residual
+__device__ __forceinline__ void level_update(const PatchInfo& p, const int id[3], double beta,
+                                             const uint8_t* __restrict__ ctype,
+                                             const PT* __restrict__ D,
+                                             const PT* __restrict__ f, PT* __restrict__ e,
+                                             PT* __restrict__ r, int64_t nl) {
+    const int c = nat(p, id[0], id[1], id[2]);
+    PT dg[2], ns[2];
+    level_terms<PT, MODE == 0>(p, id, c, beta, ctype, D, e, nl, dg, ns);
+#pragma unroll
+    for (int fld = 0; fld < 2; ++fld) {
         const int64_t cfi = fld * nl + c;
         if (MODE == 2)
-            r[cfi] = f[cfi] - (dg * ef[c] - ns);
+            r[cfi] = f[cfi] - (dg[fld] * e[cfi] - ns[fld]);
         else
-            e[cfi] = (f[cfi] + ns) / dg;
+            e[cfi] = (f[cfi] + ns[fld]) / dg[fld];
     }
 }
 
@@ -404,32 +420,53 @@ __global__ __launch_bounds__(kBlock) void k_add_level(const int32_t* __restrict_
     u[c + nl] += e[c + nl];
 }
 
-// multigrid: restriction (mean of 8) from grid g to g+1
+// multigrid: f_{g+1} = restriction (mean of 8) of the residual f - A e on
+// grid g, right after a pre-smoothing sweep whose last half-sweep relaxed
+// colour 1.  Relaxing a cell solves its own equation with its neighbours
+// (all of the other colour) held, so the residual of every colour-1 cell is
+// zero and only the four colour-0 children of each coarse cell are
+// evaluated; the residual is never stored.  Four lanes per coarse cell, one
+// child each, summed across the lanes in a fixed order.
 template <typename PT>
-__global__ __launch_bounds__(kBlock) void k_mg_restrict(const int32_t* __restrict__ act, 
+__global__ __launch_bounds__(kBlock) void k_mg_res_restrict(const int32_t* __restrict__ act,
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pc,
     const PatchInfo* __restrict__ Pf, const int32_t* __restrict__ fbox,
-    const PT* __restrict__ rf, int64_t nlf, PT* __restrict__ fc, int64_t nlc) {
+    const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
+    const PT* __restrict__ D, const PT* __restrict__ f, const PT* __restrict__ e, int64_t nlf,
+    PT* __restrict__ fc, int64_t nlc) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
-    if (act && !act[t.prob]) return;           // problem not being solved
-    if ((int)threadIdx.x >= t.count) return;
+    if (act && !act[t.prob]) return;           // uniform over the workgroup
     const PatchInfo& pc = Pc[t.patch];
     const PatchInfo& pf = Pf[fbox[t.prob]];
-    int id[3];
-    coords(pc, t.start + threadIdx.x, id[0], id[1], id[2]);
-    const int c = nat(pc, id[0], id[1], id[2]);
-    const int f0 = nat(pf, 2 * id[0], 2 * id[1], 2 * id[2]);
-    for (int fld = 0; fld < 2; ++fld) {
-        const PT* y = rf + fld * nlf + f0;
-        PT acc = y[0];
-        acc += y[1];
-        acc += y[pf.sy];
-        acc += y[pf.sy + 1];
-        acc += y[pf.sz];
-        acc += y[pf.sz + 1];
-        acc += y[pf.sz + pf.sy];
-        acc += y[pf.sz + pf.sy + 1];
-        fc[fld * nlc + c] = acc * PT(0.125);
+    const double beta = ps[t.prob].beta;
+    const int lo = pf.lo[0] + pf.lo[1] + pf.lo[2];
+    // colour-0 children (bit 0: x, 1: y, 2: z offset): an even offset sum when
+    // lo is even, odd otherwise
+    const int lane = threadIdx.x & 3;
+    const int child = (lane == 0 ? 0 : (lane == 1 ? 3 : (lane == 2 ? 5 : 6))) ^ ((lo & 1) ? 7 : 0);
+    for (int q0 = 0; q0 < t.count; q0 += kBlock / 4) {
+        const int q = q0 + ((int)threadIdx.x >> 2);
+        const bool live = q < t.count;
+        int id[3] = {0, 0, 0};
+        if (live) coords(pc, t.start + q, id[0], id[1], id[2]);
+        PT v0 = PT(0), v1 = PT(0);
+        if (live) {
+            const int fid[3] = {2 * id[0] + (child & 1), 2 * id[1] + ((child >> 1) & 1),
+                                2 * id[2] + (child >> 2)};
+            const int c = nat(pf, fid[0], fid[1], fid[2]);
+            PT dg[2], ns[2];
+            level_terms<PT, false>(pf, fid, c, beta, ctype, D, e, nlf, dg, ns);
+            v0 = f[c] - (dg[0] * e[c] - ns[0]);
+            v1 = f[nlf + c] - (dg[1] * e[nlf + c] - ns[1]);
+        }
+        v0 += __shfl_xor(v0, 1);
+        v1 += __shfl_xor(v1, 1);
+        v0 += __shfl_xor(v0, 2);
+        v1 += __shfl_xor(v1, 2);
+        if (live && lane < 2) {
+            const int cc = nat(pc, id[0], id[1], id[2]);
+            fc[lane * nlc + cc] = (lane ? v1 : v0) * PT(0.125);
+        }
     }
 }
 
@@ -788,14 +825,12 @@ void PcArrays<PT>::zero(hipStream_t s) const {
     k_fill_t<PT><<<nblocks(2 * D->nl), kBlock, 0, s>>>(u, 2 * D->nl);
     k_fill_t<PT><<<nblocks(2 * D->nl), kBlock, 0, s>>>(r, 2 * D->nl);
     k_fill_t<PT><<<nblocks(2 * D->nl), kBlock, 0, s>>>(f, 2 * D->nl);
-    k_fill_t<PT><<<nblocks(2 * D->nl), kBlock, 0, s>>>(tmp, 2 * D->nl);
     k_fill_t<PT><<<nblocks(6 * D->nl), kBlock, 0, s>>>(Dface, 6 * D->nl);
     for (int g = 1; g <= mg.G; ++g) {
         const int64_t n = mg.len[g];
         k_fill_t<PT><<<nblocks(6 * n), kBlock, 0, s>>>(mg.Dg[g], 6 * n);
         k_fill_t<PT><<<nblocks(2 * n), kBlock, 0, s>>>(mg.eg[g], 2 * n);
         k_fill_t<PT><<<nblocks(2 * n), kBlock, 0, s>>>(mg.fg[g], 2 * n);
-        k_fill_t<PT><<<nblocks(2 * n), kBlock, 0, s>>>(mg.rg[g], 2 * n);
     }
 }
 
@@ -835,7 +870,6 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
         const int64_t nlg = (g == 0) ? d.nl : mg.len[g];
         PT* eg = (g == 0) ? e : mg.eg[g];
         PT* fg = (g == 0) ? f : mg.fg[g];
-        PT* rg = (g == 0) ? tmp : mg.rg[g];
         const PT* Dg = (g == 0) ? Dface : mg.Dg[g];
         if (mg.nsmooth[g] > 0) {
             const Tile* tl = mg.smooth_tiles[g];
@@ -854,10 +888,9 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
                                                     nullptr, 1, nlg);
                 if (g == 0 && clock) clock->toc(which, tk);
             }
-            k_level<PT, 2><<<nt, kBlock, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, rg, 0, nlg);
-            k_mg_restrict<PT><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active, 
-                mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g], rg, nlg, mg.fg[g + 1],
-                mg.len[g + 1]);
+            k_mg_res_restrict<PT><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active,
+                mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g], d.ps, d.ctype, Dg, fg, eg, nlg,
+                mg.fg[g + 1], mg.len[g + 1]);
         }
         if (mg.nbottom[g] > 0)
             k_bottom_apply<PT><<<2 * mg.nbottom[g], kBlock, 0, s>>>(d.active, 
