@@ -333,6 +333,9 @@ def main():
                          "doubling); default: the workload's fixed time steps")
     ap.add_argument("--ckpt-every", type=int, default=10,
                     help="adjoint workload: checkpoint interval")
+    ap.add_argument("--fac-nu", type=int, nargs=2, default=(1, 0), metavar=("M", "N"),
+                    help="FAC V(M, N): M down-sweep and N up-sweep red-black sweeps per "
+                         "level above the base (default 1 0, the paper's V(1,0))")
     ap.add_argument("--fp64-batched", action="store_true",
                     help="also time the FP64 solver with batched launches (per-patch vs "
                          "batched comparison at equal precision)")
@@ -353,7 +356,8 @@ def main():
     use_graph = a.graph
     mixed = run_solver(w, nrd.default_options(precision=nrd.NRD_MIXED,
                                               launch=nrd.NRD_BATCHED, use_graph=use_graph,
-                                              bdf_max_order=a.bdf_max_order),
+                                              bdf_max_order=a.bdf_max_order,
+                                              fac_nu_pre=a.fac_nu[0], fac_nu_post=a.fac_nu[1]),
                        a.steps, a.warmup, True, a.adaptive_eps)
     mixed["use_graph"] = use_graph
     plain = None
@@ -362,13 +366,15 @@ def main():
         # plane-marching stencil with short z chunks suits them best
         plain = run_solver(w, nrd.default_options(precision=nrd.NRD_FP64,
                                                   launch=nrd.NRD_PER_PATCH, stencil=1,
-                                                  bdf_max_order=a.bdf_max_order),
+                                                  bdf_max_order=a.bdf_max_order,
+                                                  fac_nu_pre=a.fac_nu[0], fac_nu_post=a.fac_nu[1]),
                            a.steps, a.warmup, False, a.adaptive_eps)
     batched64 = None
     if a.fp64_batched:
         batched64 = run_solver(w, nrd.default_options(precision=nrd.NRD_FP64,
                                                       launch=nrd.NRD_BATCHED,
-                                                      bdf_max_order=a.bdf_max_order),
+                                                      bdf_max_order=a.bdf_max_order,
+                                                      fac_nu_pre=a.fac_nu[0], fac_nu_post=a.fac_nu[1]),
                                a.steps, a.warmup, False, a.adaptive_eps)
     res_s = mixed["residual_ms_avg"] / 1e3
     res_cells = mixed["residual_cells_avg"]           # per launch, average
@@ -405,7 +411,8 @@ def main():
                    "time_control": (f"PC.4.7, eps_t {a.adaptive_eps}" if a.adaptive_eps
                                     else "fixed steps"),
                    "solver": ("BDF1->BDF2" if a.bdf_max_order == 2 else "BDF1") +
-                             ", Newton rtol 1e-8, FGMRES(30), FAC V(1,0) + MG V(1,1)"},
+                             ", Newton rtol 1e-8, FGMRES(30), FAC V(%d,%d) + MG V(1,1)"
+                             % tuple(a.fac_nu)},
         "roofline": {"bound": "hbm", "kernel": "k_stencil_s<0> (residual)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

@@ -116,7 +116,7 @@ typedef struct {
                                1 plane-marching tiles (each face once, LDS),
                                2 wave runs (x faces shared across lanes),
                                3 staged planes (each plane slice read once
-                               into LDS, 512-cell tiles)     */
+                               into LDS, 256-cell runs)                      */
     int32_t zchunk;         /* planes per tile of variants 1, 2 (0: default)  */
     int32_t bdf_max_order;  /* 2 (default): BDF2 after the first step; 1: BDF1
                                throughout (the adjoint assumes BDF1)         */
@@ -125,14 +125,22 @@ typedef struct {
                                error estimate (eq. bdf2le) in
                                nrd_step_stats.err_norm; needed by
                                nrd_adaptive_steps (0 default)                */
-    int32_t reserved[3];
+    int32_t fac_nu_pre;     /* FAC V(m, n) of Alg. 1 on hierarchies with more
+                               than one level: m >= 1 red-black sweeps per
+                               level on the down-sweep (default 1)           */
+    int32_t fac_nu_post;    /* n >= 0 sweeps per level on the up-sweep, each
+                               level's right-hand side the composite
+                               residual refreshed with every correction so
+                               far (default 0: the paper's V(1,0))           */
+    int32_t reserved;
     double err_eta_E;       /* eta_E, eta_T of that norm,                    */
     double err_eta_T;       /* max |e / (u + eta)| over composite cells      */
 } nrd_options;
 
 /* Fills *opt with the defaults: FP64, batched, no graph, analytic JVP,
  * limiter 1, paper P2, rtol 1e-8, atol 1e-14, 20 Newton iterations,
- * GMRES(30) with 10 restarts, V(1,1), staged-plane stencil, BDF2, no error
+ * GMRES(30) with 10 restarts, FAC V(1,0), base multigrid V(1,1),
+ * staged-plane stencil, BDF2, no error
  * estimate, eta_E = 1e-5 (the initial energy density of Sec. 5), eta_T =
  * 1e-5^(1/4). */
 void nrd_default_options(nrd_options* opt);

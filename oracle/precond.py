@@ -87,10 +87,11 @@ class Snapshot:
     robin[f][pid][d] = (low, high) flags of Marshak faces.
     """
 
-    def __init__(self, H, E, T, z, beta, lam=1.0, p2_mode="paper"):
+    def __init__(self, H, E, T, z, beta, lam=1.0, p2_mode="paper", fac_nu=(1, 0)):
         self.H = H
         self.beta = float(beta)
         self.p2_mode = p2_mode
+        self.fac_nu = tuple(fac_nu)
         Eg, Tg = ghosted_state(H, E, T)
         z3 = ghosted_z3(H, z)
         self.T = [a[1:-1, 1:-1, 1:-1].copy() for a in Tg]
@@ -467,14 +468,25 @@ def _level_values(H, lev, vals, Q):
     return out
 
 
-def fac_vcycle(H, snap, f, rhs, mg_grids=None):
-    """One FAC V(1,0) cycle for A^c u = rhs from u = 0 (Alg. 1).
+def fac_vcycle(H, snap, f, rhs, mg_grids=None, nu=None):
+    """One FAC V(m,n) cycle for A^c u = rhs from u = 0 (Alg. 1), nu = (m, n)
+    (default snap.fac_nu, else (1, 0)).
 
-    rhs, result: per-patch interior arrays (result covered cells synced).
+    Down-sweep, finest level to level 1: composite residual, m red-black
+    sweeps from zero on the level, correction of u on the level and (by
+    trilinear prolongation) on every finer level.  Level 0: one multigrid
+    V-cycle.  Up-sweep, level 1 to the finest (when n > 0): the composite
+    residual refreshed with every correction so far, n sweeps from zero,
+    the same correction.  rhs, result: per-patch interior arrays (result
+    covered cells synced).
     """
+    if nu is None:
+        nu = getattr(snap, "fac_nu", (1, 0))
+    m_pre, n_post = int(nu[0]), int(nu[1])
     u = [np.zeros(tuple(int(v) for v in p.n)) for p in H.patches]
     L = H.nlev - 1
-    for lev in range(L, -1, -1):
+
+    def level_rhs():
         r = composite_apply(H, snap, f, u)
         r = [rhs[p.pid] - r[p.pid] for p in H.patches]
         rg = H.from_interior(r)
@@ -482,20 +494,19 @@ def fac_vcycle(H, snap, f, rhs, mg_grids=None):
             inner = rg[p.pid][1:-1, 1:-1, 1:-1]
             inner[H.covered[p.pid]] = 0.0
         H.sync([rg])
-        if lev > 0:
-            e = H.empty()
-            for p in H.by_level[lev]:
-                e[p.pid][...] = 0.0
-            rhs_l = {p.pid: rg[p.pid][1:-1, 1:-1, 1:-1] for p in H.by_level[lev]}
+        return rg
+
+    def smooth(lev, rg, sweeps):
+        e = H.empty()
+        for p in H.by_level[lev]:
+            e[p.pid][...] = 0.0
+        rhs_l = {p.pid: rg[p.pid][1:-1, 1:-1, 1:-1] for p in H.by_level[lev]}
+        for _ in range(sweeps):
             rbgs_level(H, snap, f, lev, rhs_l, e)
-            corr = {p.pid: e[p.pid][1:-1, 1:-1, 1:-1].copy()
-                    for p in H.by_level[lev]}
-        else:
-            p0 = H.by_level[0][0]
-            if mg_grids is None:
-                mg_grids = build_mg(H, snap, f)
-            corr = {p0.pid: mg_vcycle(mg_grids, snap.beta,
-                                      rg[p0.pid][1:-1, 1:-1, 1:-1])}
+        return {p.pid: e[p.pid][1:-1, 1:-1, 1:-1].copy() for p in H.by_level[lev]}
+
+    def correct(lev, corr):
+        nonlocal u
         for q, c in corr.items():
             u[q] = u[q] + c
         for m in range(lev + 1, L + 1):
@@ -505,6 +516,21 @@ def fac_vcycle(H, snap, f, rhs, mg_grids=None):
         ug = H.from_interior(u)
         H.sync([ug])
         u = H.interior(ug)
+
+    for lev in range(L, -1, -1):
+        rg = level_rhs()
+        if lev > 0:
+            corr = smooth(lev, rg, m_pre)
+        else:
+            p0 = H.by_level[0][0]
+            if mg_grids is None:
+                mg_grids = build_mg(H, snap, f)
+            corr = {p0.pid: mg_vcycle(mg_grids, snap.beta,
+                                      rg[p0.pid][1:-1, 1:-1, 1:-1])}
+        correct(lev, corr)
+    if n_post > 0:
+        for lev in range(1, L + 1):
+            correct(lev, smooth(lev, level_rhs(), n_post))
     return u
 
 

@@ -339,6 +339,8 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
     pc.p2_mode = h->opt.p2_mode;
     pc.nu_pre = std::max(1, h->opt.mg_nu_pre);
     pc.nu_post = std::max(0, h->opt.mg_nu_post);
+    pc.fac_pre = h->opt.fac_nu_pre;
+    pc.fac_post = h->opt.fac_nu_post;
     pc.clock = h;
 }
 
@@ -1387,6 +1389,8 @@ void nrd_default_options(nrd_options* o) {
     o->gmres_maxrestarts = 10;
     o->mg_nu_pre = 1;
     o->mg_nu_post = 1;
+    o->fac_nu_pre = 1;
+    o->fac_nu_post = 0;
     o->stencil = 3;
     o->bdf_max_order = 2;
     o->error_estimate = 0;
@@ -1411,6 +1415,11 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
         if (h->opt.newton_maxit < 1 || h->opt.newton_maxit > 24) {
             delete h;
             return fail(NRD_EINVAL, "newton_maxit must be in [1, 24]");
+        }
+        if (h->opt.fac_nu_pre < 1 || h->opt.fac_nu_pre > 8 || h->opt.fac_nu_post < 0 ||
+            h->opt.fac_nu_post > 8) {
+            delete h;
+            return fail(NRD_EINVAL, "fac_nu_pre must be in [1, 8], fac_nu_post in [0, 8]");
         }
         if (h->opt.bdf_max_order < 1 || h->opt.bdf_max_order > 2) {
             delete h;

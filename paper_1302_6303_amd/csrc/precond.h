@@ -73,6 +73,7 @@ struct PcArrays {
     } mg;
     int p2_mode = 0;
     int nu_pre = 1, nu_post = 1;
+    int fac_pre = 1, fac_post = 0;   // FAC V(m, n)
     Clock* clock = nullptr;     // times the base grid's sweeps
 
     void zero(hipStream_t s) const;
@@ -84,6 +85,8 @@ struct PcArrays {
     const PT* fac(hipStream_t s) const;     // returns u or e (one level)
     void vcycle(hipStream_t s) const;
     void composite_residual(hipStream_t s, int lev) const;
+    void smooth_level(hipStream_t s, const PT* rhs, int lev, int sweeps) const;
+    void correct_level(hipStream_t s, int lev) const;
     void fill_ghosts(hipStream_t s, PT* x) const;
     void restrict_(hipStream_t s, PT* x, int lev_lo) const;
     void siblings(hipStream_t s, PT* x, int lev) const;

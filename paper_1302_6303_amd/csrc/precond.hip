@@ -962,10 +962,52 @@ void PcArrays<PT>::composite_residual(hipStream_t s, int lev) const {
 }
 
 template <typename PT>
+void PcArrays<PT>::smooth_level(hipStream_t s, const PT* rhs, int lev, int sweeps) const {
+    // red-black sweeps on A^l e = rhs from e = 0 over the patches of level
+    // lev, sibling ghosts refreshed before every half-sweep that reads them
+    const Dev& d = *D;
+    const int t0 = d.level_tile0[lev], nt = d.level_tile0[lev + 1] - t0;
+    const Tile* tl = d.tiles + t0;
+    k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, tl, d.patches, d.ps, d.ctype, Dface, rhs,
+                                             e, nullptr, 0, d.nl);
+    siblings(s, e, lev);
+    k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, d.patches, d.ps, d.ctype, Dface, rhs,
+                                             e, nullptr, 1, d.nl);
+    for (int it = 1; it < sweeps; ++it)
+        for (int colour = 0; colour < 2; ++colour) {
+            siblings(s, e, lev);
+            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, d.patches, d.ps, d.ctype,
+                                                     Dface, rhs, e, nullptr, colour, d.nl);
+        }
+}
+
+template <typename PT>
+void PcArrays<PT>::correct_level(hipStream_t s, int lev) const {
+    // u += e on level lev and, by trilinear prolongation level by level, on
+    // every finer level; then covered cells of u <- mean of their children
+    const Dev& d = *D;
+    const int L = d.nlev - 1;
+    const int t0 = d.level_tile0[lev], nt = d.level_tile0[lev + 1] - t0;
+    k_add_level<PT><<<nt, kBlock, 0, s>>>(d.active, d.tiles + t0, d.patches, e, u, d.nl);
+    for (int m = lev + 1; m <= L; ++m) {
+        const int a = d.level_shadow0[m], b = d.level_shadow0[m + 1];
+        k_gather<PT><<<nblocks(b - a), kBlock, 0, s>>>(shadow_src + a, b - a, e, d.nl,
+                                                       shadow + a, shadow_len);
+        const int m0 = d.level_tile0[m], mt = d.level_tile0[m + 1] - m0;
+        k_prolong_level<PT><<<mt, kBlock, 0, s>>>(d.active, d.tiles + m0, d.patches, shadows,
+                                                  shadow, shadow_len, e, u, d.nl);
+    }
+    restrict_(s, u, 0);
+}
+
+template <typename PT>
 const PT* PcArrays<PT>::fac(hipStream_t s) const {
-    // One FAC V(1,0) cycle from u = 0 for A^c u = f (Alg. 1).  Returns the
-    // buffer holding the result: u, or e when there is one level (u = 0 plus
-    // the base level's correction is that correction).
+    // One FAC V(m,n) cycle from u = 0 for A^c u = f (Alg. 1): m = fac_pre
+    // sweeps per level on the down-sweep, the base multigrid V-cycle, n =
+    // fac_post sweeps per level on the up-sweep with the composite residual
+    // refreshed.  Returns the buffer holding the result: u, or e when there
+    // is one level (u = 0 plus the base level's correction is that
+    // correction).
     const Dev& d = *D;
     const int L = d.nlev - 1;
     if (L == 0) {
@@ -974,39 +1016,27 @@ const PT* PcArrays<PT>::fac(hipStream_t s) const {
     }
     k_fill_t<PT><<<nblocks(2 * d.nl), kBlock, 0, s>>>(u, 2 * d.nl);
     for (int lev = L; lev >= 0; --lev) {
-        const PT* rhs = r;
         if (lev == L) {
             // u = 0: r = f (the finest level has no covered cells)
             k_copy_t<PT><<<nblocks(2 * d.nl), kBlock, 0, s>>>(f, r, 2 * d.nl);
         } else {
-            composite_residual(s, lev);     // u was restricted at the end of lev + 1
+            composite_residual(s, lev);     // u was restricted by the last correction
         }
-        const int t0 = d.level_tile0[lev], nt = d.level_tile0[lev + 1] - t0;
         if (lev > 0) {
-            // one red-black sweep on A^l e = f^l from e = 0, sibling ghosts
-            // refreshed between the half-sweeps
-            k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, d.tiles + t0, d.patches, d.ps, d.ctype, Dface,
-                                                rhs, e, nullptr, 0, d.nl);
-            siblings(s, e, lev);
-            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, d.tiles + t0, d.patches, d.ps, d.ctype, Dface,
-                                                rhs, e, nullptr, 1, d.nl);
+            smooth_level(s, r, lev, fac_pre);
         } else {
             // base level: multigrid V-cycle with rhs f^0 = r on level 0 (the
             // V-cycle only reads its level-0 right-hand side)
             PcArrays<PT> v = *this;
-            v.f = const_cast<PT*>(rhs);
+            v.f = r;
             v.vcycle(s);
         }
-        k_add_level<PT><<<nt, kBlock, 0, s>>>(d.active, d.tiles + t0, d.patches, e, u, d.nl);
-        for (int m = lev + 1; m <= L; ++m) {
-            const int a = d.level_shadow0[m], b = d.level_shadow0[m + 1];
-            k_gather<PT><<<nblocks(b - a), kBlock, 0, s>>>(shadow_src + a, b - a, e, d.nl,
-                                                           shadow + a, shadow_len);
-            const int m0 = d.level_tile0[m], mt = d.level_tile0[m + 1] - m0;
-            k_prolong_level<PT><<<mt, kBlock, 0, s>>>(d.active, d.tiles + m0, d.patches, shadows,
-                                                      shadow, shadow_len, e, u, d.nl);
-        }
-        restrict_(s, u, 0);
+        correct_level(s, lev);
+    }
+    for (int lev = 1; fac_post > 0 && lev <= L; ++lev) {
+        composite_residual(s, lev);
+        smooth_level(s, r, lev, fac_post);
+        correct_level(s, lev);
     }
     return u;
 }

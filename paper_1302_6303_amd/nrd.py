@@ -51,7 +51,8 @@ class nrd_options(C.Structure):
                 ("mg_nu_post", C.c_int32), ("adjoint_slots", C.c_int32),
                 ("stencil", C.c_int32), ("zchunk", C.c_int32),
                 ("bdf_max_order", C.c_int32), ("error_estimate", C.c_int32),
-                ("reserved", C.c_int32 * 3), ("err_eta_E", C.c_double),
+                ("fac_nu_pre", C.c_int32), ("fac_nu_post", C.c_int32),
+                ("reserved", C.c_int32), ("err_eta_E", C.c_double),
                 ("err_eta_T", C.c_double)]
 
 

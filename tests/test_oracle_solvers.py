@@ -151,6 +151,65 @@ def test_fac_stationary_iteration_converges_on_two_levels():
         assert rate < 0.5, (f, norms)
 
 
+def _fac_contraction(w, nus, iters=6):
+    """Per field, the contraction rate of FAC V(m, n) used as a stationary
+    iteration on A^c x = rhs (smooth single-material coefficients)."""
+    rng0 = np.random.default_rng(250)
+    w.E, w.T = I.front_state(w.problems, w.boxes, rng0, noise=0.0)
+    s = system(w)
+    H = s.H
+    s.z = [np.ones(tuple(int(v) for v in p.n)) for p in H.patches]
+    E, T = s.split(state(s, w))
+    snap = pc.Snapshot(H, E, T, s.z, 5e-2)
+    out = {}
+    for nu in nus:
+        rng = np.random.default_rng(25)
+        rates = []
+        for f in (0, 1):
+            rhs = [rng.standard_normal(tuple(int(v) for v in p.n)) for p in H.patches]
+            x = [np.zeros_like(r) for r in rhs]
+            norms = []
+            for _ in range(iters):
+                Ax = pc.composite_apply(H, snap, f, x)
+                r = [rhs[q] - Ax[q] for q in range(len(rhs))]
+                norms.append(np.sqrt(sum(np.sum(rr[~H.covered[q]] ** 2)
+                                         for q, rr in enumerate(r))))
+                c = pc.fac_vcycle(H, snap, f, r, nu=nu)
+                x = [x[q] + c[q] for q in range(len(x))]
+            rates.append((norms[-1] / norms[1]) ** (1 / (iters - 2)))
+        out[nu] = rates
+    return out
+
+
+def test_fac_more_smoothing_contracts_faster():
+    """Alg. 1 with m > 1 down-sweep sweeps or n > 0 up-sweep sweeps (on the
+    refreshed composite residual) is a better stationary iteration than
+    V(1,0) for both diffusion blocks.  An up-sweep that re-solves the first
+    residual instead of the refreshed one diverges here (rate > 1)."""
+    r = _fac_contraction(I.small_amr(8, state="uniform"), [(1, 0), (2, 0), (1, 1), (2, 1)])
+    for f in (0, 1):
+        for nu in ((2, 0), (1, 1), (2, 1)):
+            assert r[nu][f] < 0.7 * r[(1, 0)][f], (nu, f, r)
+    assert r[(2, 1)][0] < 0.25 and r[(2, 1)][1] < 0.05, r
+
+
+def test_fac_vmn_on_one_level_is_the_base_vcycle():
+    """With a single level there are no levels above the base: V(m, n) of
+    FAC is one base multigrid V-cycle whatever m and n."""
+    w = I.marshak_single(8, state="front")
+    s = system(w)
+    H = s.H
+    E, T = s.split(state(s, w))
+    snap = pc.Snapshot(H, E, T, s.z, 3e-3)
+    rng = np.random.default_rng(31)
+    rhs = [rng.standard_normal(tuple(int(v) for v in p.n)) for p in H.patches]
+    for f in (0, 1):
+        a = pc.fac_vcycle(H, snap, f, rhs, nu=(1, 0))
+        b = pc.fac_vcycle(H, snap, f, rhs, nu=(3, 2))
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
 def test_fgmres_newton_step_matches_sparse_direct():
     w = I.marshak_single(4, state="front")
     s = system(w)
