@@ -89,6 +89,7 @@ enum { NRD_FP64 = 0, NRD_MIXED = 1 };            /* preconditioner precision */
 enum { NRD_BATCHED = 0, NRD_PER_PATCH = 1 };     /* kernel launch grouping   */
 enum { NRD_JVP_ANALYTIC = 0, NRD_JVP_FD = 1 };
 enum { NRD_P2_PAPER = 0, NRD_P2_FROZEN4 = 1 };
+enum { NRD_SMOOTH_RBGS = 0, NRD_SMOOTH_JACOBI = 1 };  /* FAC level smoother */
 
 typedef struct {
     int32_t precision;      /* NRD_FP64 or NRD_MIXED (V-cycles in float)     */
@@ -132,7 +133,9 @@ typedef struct {
                                level's right-hand side the composite
                                residual refreshed with every correction so
                                far (default 0: the paper's V(1,0))           */
-    int32_t reserved;
+    int32_t fac_smoother;   /* FAC level smoother (Sec. 4.3): NRD_SMOOTH_RBGS
+                               (default) or NRD_SMOOTH_JACOBI, damped point
+                               Jacobi with weight 6/7                        */
     double err_eta_E;       /* eta_E, eta_T of that norm,                    */
     double err_eta_T;       /* max |e / (u + eta)| over composite cells      */
 } nrd_options;

@@ -87,11 +87,13 @@ class Snapshot:
     robin[f][pid][d] = (low, high) flags of Marshak faces.
     """
 
-    def __init__(self, H, E, T, z, beta, lam=1.0, p2_mode="paper", fac_nu=(1, 0)):
+    def __init__(self, H, E, T, z, beta, lam=1.0, p2_mode="paper", fac_nu=(1, 0),
+                 fac_smoother="rbgs"):
         self.H = H
         self.beta = float(beta)
         self.p2_mode = p2_mode
         self.fac_nu = tuple(fac_nu)
+        self.fac_smoother = fac_smoother      # "rbgs" or "jacobi" on levels >= 1
         Eg, Tg = ghosted_state(H, E, T)
         z3 = ghosted_z3(H, z)
         self.T = [a[1:-1, 1:-1, 1:-1].copy() for a in Tg]
@@ -230,6 +232,32 @@ def rbgs_level(H, snap, f, level, rhs, e, weights=None):
             val, m = new[p.pid]
             inner = e[p.pid][1:-1, 1:-1, 1:-1]
             inner[m] = val[m]
+
+
+# Damping of the point Jacobi smoother: 2d / (2d + 1) in d = 3 dimensions,
+# the weight that damps the upper half of the 7-point Laplacian's spectrum
+# best (the paper names the smoother, not its weight).
+JACOBI_OMEGA = 6.0 / 7.0
+
+
+def jacobi_level(H, snap, f, level, rhs, e, omega=JACOBI_OMEGA, weights=None):
+    """One damped point Jacobi sweep on all cells of a level (covered cells
+    included) for A^l e = rhs: every cell from the same old values,
+    e <- (1 - omega) e + omega (rhs + sum w e_nb) / diag; e ghosted per
+    patch (sibling ghosts exchanged first), updated in place."""
+    plist = H.by_level[level]
+    if weights is None:
+        weights = {p.pid: level_weights(H, snap, f, p) for p in plist}
+    exchange_siblings(H, level, e)
+    new = {}
+    for p in plist:
+        n = tuple(int(v) for v in p.n)
+        w, diag = weights[p.pid]
+        inner = e[p.pid][1:-1, 1:-1, 1:-1]
+        new[p.pid] = (1.0 - omega) * inner + \
+            omega * ((rhs[p.pid] + _neighbour_sum(w, e[p.pid], n)) / diag)
+    for p in plist:
+        e[p.pid][1:-1, 1:-1, 1:-1] = new[p.pid]
 
 
 # ---------------------------------------------------------------------------
@@ -470,9 +498,11 @@ def _level_values(H, lev, vals, Q):
 
 def fac_vcycle(H, snap, f, rhs, mg_grids=None, nu=None):
     """One FAC V(m,n) cycle for A^c u = rhs from u = 0 (Alg. 1), nu = (m, n)
-    (default snap.fac_nu, else (1, 0)).
+    (default snap.fac_nu, else (1, 0)); the level smoother is red-black
+    Gauss-Seidel or, with snap.fac_smoother == "jacobi", damped point Jacobi
+    (Sec. 4.3 names both).
 
-    Down-sweep, finest level to level 1: composite residual, m red-black
+    Down-sweep, finest level to level 1: composite residual, m smoothing
     sweeps from zero on the level, correction of u on the level and (by
     trilinear prolongation) on every finer level.  Level 0: one multigrid
     V-cycle.  Up-sweep, level 1 to the finest (when n > 0): the composite
@@ -482,6 +512,7 @@ def fac_vcycle(H, snap, f, rhs, mg_grids=None, nu=None):
     """
     if nu is None:
         nu = getattr(snap, "fac_nu", (1, 0))
+    smoother = getattr(snap, "fac_smoother", "rbgs")
     m_pre, n_post = int(nu[0]), int(nu[1])
     u = [np.zeros(tuple(int(v) for v in p.n)) for p in H.patches]
     L = H.nlev - 1
@@ -501,8 +532,9 @@ def fac_vcycle(H, snap, f, rhs, mg_grids=None, nu=None):
         for p in H.by_level[lev]:
             e[p.pid][...] = 0.0
         rhs_l = {p.pid: rg[p.pid][1:-1, 1:-1, 1:-1] for p in H.by_level[lev]}
+        sweep = jacobi_level if smoother == "jacobi" else rbgs_level
         for _ in range(sweeps):
-            rbgs_level(H, snap, f, lev, rhs_l, e)
+            sweep(H, snap, f, lev, rhs_l, e)
         return {p.pid: e[p.pid][1:-1, 1:-1, 1:-1].copy() for p in H.by_level[lev]}
 
     def correct(lev, corr):

@@ -34,7 +34,8 @@ class System:
     """One problem: hierarchy, material field, options; compact vectors are
     [E of all patches (x fastest) | T of all patches]."""
 
-    def __init__(self, H, z, lam=1.0, p2_mode="paper", jvp_mode="analytic", fac_nu=(1, 0)):
+    def __init__(self, H, z, lam=1.0, p2_mode="paper", jvp_mode="analytic", fac_nu=(1, 0),
+                 fac_smoother="rbgs"):
         self.H = H
         self.jvp_mode = jvp_mode
         self._b = None
@@ -42,6 +43,7 @@ class System:
         self.lam = lam
         self.p2_mode = p2_mode
         self.fac_nu = tuple(fac_nu)     # FAC V(m, n) (Alg. 1)
+        self.fac_smoother = fac_smoother
         self.nc = H.ncells()
         w = []
         for p in H.patches:
@@ -111,7 +113,8 @@ class System:
 
     def precond(self, u, beta):
         E, T = self.split(u)
-        snap = pc.Snapshot(self.H, E, T, self.z, beta, self.lam, self.p2_mode, self.fac_nu)
+        snap = pc.Snapshot(self.H, E, T, self.z, beta, self.lam, self.p2_mode, self.fac_nu,
+                           self.fac_smoother)
         mg = (pc.build_mg(self.H, snap, 0), pc.build_mg(self.H, snap, 1))
 
         def apply(w):

@@ -77,7 +77,7 @@ struct nrd_hierarchy final : public Clock {
             mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bot_probs, bot_boxes, bot_grid, bottom_off,
             Lbuf, Xbuf;
         size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, gz3, V, Z, pred;
-        size_t pc_D, pc_sigma, pc_e, pc_u, pc_r, pc_f, pc_shadow;
+        size_t pc_D, pc_sigma, pc_e, pc_e2, pc_u, pc_r, pc_f, pc_shadow;
         size_t mg_D[kMaxMG], mg_e[kMaxMG], mg_f[kMaxMG];
         size_t partial, dots, h1, h2, hn2, H, cs, sn, g, rho, vscale, y, kdim, coefA, coefB,
             minout, flag, ckpt, fdF, fdw, fdsum;
@@ -255,6 +255,7 @@ static void layout(nrd_hierarchy* h) {
     o.pc_D = b.take(es * 6 * nl);
     o.pc_sigma = b.take(es * nl);
     o.pc_e = b.take(es * 2 * nl);
+    o.pc_e2 = b.take(h->opt.fac_smoother == NRD_SMOOTH_JACOBI ? es * 2 * nl : es);
     o.pc_u = b.take(es * 2 * nl);
     o.pc_r = b.take(es * 2 * nl);
     o.pc_f = b.take(es * 2 * nl);
@@ -305,6 +306,7 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
     pc.Dface = h->at<PT>(o.pc_D);
     pc.sigma = h->at<PT>(o.pc_sigma);
     pc.e = h->at<PT>(o.pc_e);
+    pc.e2 = h->at<PT>(o.pc_e2);
     pc.u = h->at<PT>(o.pc_u);
     pc.r = h->at<PT>(o.pc_r);
     pc.f = h->at<PT>(o.pc_f);
@@ -341,6 +343,7 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
     pc.nu_post = std::max(0, h->opt.mg_nu_post);
     pc.fac_pre = h->opt.fac_nu_pre;
     pc.fac_post = h->opt.fac_nu_post;
+    pc.fac_smoother = h->opt.fac_smoother;
     pc.clock = h;
 }
 
@@ -1391,6 +1394,7 @@ void nrd_default_options(nrd_options* o) {
     o->mg_nu_post = 1;
     o->fac_nu_pre = 1;
     o->fac_nu_post = 0;
+    o->fac_smoother = NRD_SMOOTH_RBGS;
     o->stencil = 3;
     o->bdf_max_order = 2;
     o->error_estimate = 0;
@@ -1420,6 +1424,10 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
             h->opt.fac_nu_post > 8) {
             delete h;
             return fail(NRD_EINVAL, "fac_nu_pre must be in [1, 8], fac_nu_post in [0, 8]");
+        }
+        if (h->opt.fac_smoother != NRD_SMOOTH_RBGS && h->opt.fac_smoother != NRD_SMOOTH_JACOBI) {
+            delete h;
+            return fail(NRD_EINVAL, "fac_smoother must be RBGS or JACOBI");
         }
         if (h->opt.bdf_max_order < 1 || h->opt.bdf_max_order > 2) {
             delete h;

@@ -7,6 +7,10 @@ namespace nrd {
 
 constexpr int kMaxMG = 12;
 
+// Damping of the point Jacobi level smoother: 2d / (2d + 1) for d = 3, the
+// weight that damps the upper half of the 7-point Laplacian's spectrum best.
+constexpr double kJacobiOmega = 6.0 / 7.0;
+
 struct MGDev {
     int G = 0;                                   // deepest grid index
     const PatchInfo* box[kMaxMG] = {};           // grid g >= 1 box tables
@@ -74,6 +78,8 @@ struct PcArrays {
     int p2_mode = 0;
     int nu_pre = 1, nu_post = 1;
     int fac_pre = 1, fac_post = 0;   // FAC V(m, n)
+    int fac_smoother = 0;            // NRD_SMOOTH_RBGS or NRD_SMOOTH_JACOBI
+    PT* e2 = nullptr;                // 2 * nl, damped Jacobi with several sweeps
     Clock* clock = nullptr;     // times the base grid's sweeps
 
     void zero(hipStream_t s) const;

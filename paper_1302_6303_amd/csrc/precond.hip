@@ -220,6 +220,33 @@ __device__ __forceinline__ void level_update(const PatchInfo& p, const int id[3]
     }
 }
 
+// Damped point Jacobi on the level operator (the alternative level smoother
+// of Sec. 4.3): every cell from the same old iterate e_in,
+// e_out = (1 - omega) e_in + omega (f + ns) / dg; ZERO: e_in = 0.
+template <typename PT, bool ZERO>
+__global__ __launch_bounds__(kBlock) void k_jacobi(const int32_t* __restrict__ act,
+    const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
+    const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
+    const PT* __restrict__ D, const PT* __restrict__ f, const PT* __restrict__ e_in,
+    PT* __restrict__ e_out, double omega, int64_t nl) {
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    int id[3];
+    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(p, id[0], id[1], id[2]);
+    PT dg[2], ns[2];
+    level_terms<PT, ZERO>(p, id, c, ps[t.prob].beta, ctype, D, e_in, nl, dg, ns);
+    const PT w = (PT)omega;
+#pragma unroll
+    for (int fld = 0; fld < 2; ++fld) {
+        const int64_t cfi = fld * nl + c;
+        const PT x = (f[cfi] + ns[fld]) / dg[fld];
+        e_out[cfi] = ZERO ? w * x : (PT(1) - w) * e_in[cfi] + w * x;
+    }
+}
+
 // MODE 2 (residual): kBlock threads, one per cell of the tile.
 // MODE 0 / 1 (one colour): kBlock / 2 threads.  When the patch's x extent is
 // even, rows start at even linear indices, so every pair (2q, 2q + 1) of a
@@ -402,6 +429,23 @@ __global__ __launch_bounds__(kBlock) void k_prolong_level(const int32_t* __restr
         e[fld * nl + c] = v;
         u[fld * nl + c] += v;
     }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_copy_level(const int32_t* __restrict__ act,
+                                                       const Tile* __restrict__ tiles,
+                                                       const PatchInfo* __restrict__ P,
+                                                       const PT* __restrict__ x,
+                                                       PT* __restrict__ y, int64_t nl) {
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    int id[3];
+    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(p, id[0], id[1], id[2]);
+    y[c] = x[c];
+    y[c + nl] = x[c + nl];
 }
 
 template <typename PT>
@@ -963,11 +1007,27 @@ void PcArrays<PT>::composite_residual(hipStream_t s, int lev) const {
 
 template <typename PT>
 void PcArrays<PT>::smooth_level(hipStream_t s, const PT* rhs, int lev, int sweeps) const {
-    // red-black sweeps on A^l e = rhs from e = 0 over the patches of level
-    // lev, sibling ghosts refreshed before every half-sweep that reads them
+    // smoothing sweeps on A^l e = rhs from e = 0 over the patches of level
+    // lev (red-black Gauss-Seidel, or damped point Jacobi alternating between
+    // e and e2), sibling ghosts refreshed before every sweep that reads them
     const Dev& d = *D;
     const int t0 = d.level_tile0[lev], nt = d.level_tile0[lev + 1] - t0;
     const Tile* tl = d.tiles + t0;
+    if (fac_smoother == NRD_SMOOTH_JACOBI) {
+        k_jacobi<PT, true><<<nt, kBlock, 0, s>>>(d.active, tl, d.patches, d.ps, d.ctype, Dface,
+                                                 rhs, e, e, kJacobiOmega, d.nl);
+        PT* cur = e;
+        PT* nxt = e2;
+        for (int it = 1; it < sweeps; ++it) {
+            siblings(s, cur, lev);
+            k_jacobi<PT, false><<<nt, kBlock, 0, s>>>(d.active, tl, d.patches, d.ps, d.ctype,
+                                                      Dface, rhs, cur, nxt, kJacobiOmega, d.nl);
+            std::swap(cur, nxt);
+        }
+        if (cur != e)
+            k_copy_level<PT><<<nt, kBlock, 0, s>>>(d.active, tl, d.patches, cur, e, d.nl);
+        return;
+    }
     k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, tl, d.patches, d.ps, d.ctype, Dface, rhs,
                                              e, nullptr, 0, d.nl);
     siblings(s, e, lev);

@@ -89,6 +89,28 @@ def test_level_operator_matches_composite_operator_on_one_level():
     np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-14)
 
 
+def test_jacobi_sweep_is_the_textbook_damped_update():
+    """One damped point Jacobi sweep on a single-level grid is
+    e + omega D^-1 (f - A e) with A assembled column by column from the
+    composite operator and D its diagonal (Marshak face included)."""
+    n = 5
+    H, snap = _mg_grid_from_state(n)
+    p = H.by_level[0][0]
+    rng = np.random.default_rng(41)
+    for f in (0, 1):
+        A = _dense_from_apply(lambda x: pc.composite_apply(H, snap, f, [x])[0], (n,) * 3)
+        e0 = rng.standard_normal((n, n, n))
+        rhs = rng.standard_normal((n, n, n))
+        e = H.empty()
+        e[p.pid][...] = 0.0                   # physical ghosts: weight 0
+        e[p.pid][1:-1, 1:-1, 1:-1] = e0
+        pc.jacobi_level(H, snap, f, 0, {p.pid: rhs}, e)
+        x = e0.ravel(order="F")
+        ref = x + pc.JACOBI_OMEGA * (rhs.ravel(order="F") - A @ x) / np.diag(A)
+        np.testing.assert_allclose(e[p.pid][1:-1, 1:-1, 1:-1].ravel(order="F"), ref,
+                                   rtol=1e-12, atol=1e-13)
+
+
 def test_bottom_grid_is_an_exact_solve():
     n = 5                                     # cannot coarsen: bottom = grid
     H, snap = _mg_grid_from_state(n)
@@ -191,6 +213,24 @@ def test_fac_more_smoothing_contracts_faster():
         for nu in ((2, 0), (1, 1), (2, 1)):
             assert r[nu][f] < 0.7 * r[(1, 0)][f], (nu, f, r)
     assert r[(2, 1)][0] < 0.25 and r[(2, 1)][1] < 0.05, r
+
+
+def test_fac_with_jacobi_smoothing_converges():
+    """FAC with the damped point Jacobi level smoother (Sec. 4.3) is a
+    convergent stationary iteration, and more sweeps make it faster."""
+    w = I.small_amr(8, state="uniform")
+    orig = pc.Snapshot.__init__
+
+    def jacobi_init(self, *a, **k):
+        orig(self, *a, **k)
+        self.fac_smoother = "jacobi"
+    pc.Snapshot.__init__ = jacobi_init
+    try:
+        r = _fac_contraction(w, [(1, 0), (2, 1)])
+    finally:
+        pc.Snapshot.__init__ = orig
+    for f in (0, 1):
+        assert r[(1, 0)][f] < 0.7 and r[(2, 1)][f] < 0.7 * r[(1, 0)][f], r
 
 
 def test_fac_vmn_on_one_level_is_the_base_vcycle():
