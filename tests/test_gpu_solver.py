@@ -68,12 +68,13 @@ def test_lockstep_ensemble_matches_each_problem():
             assert rel_err(g[n:], ref[n:]) < 1e-8
 
 
-@pytest.mark.parametrize("name", ["uniform", "amr"])
+@pytest.mark.parametrize("name", ["uniform", "amr", "amr-jacobi"])
 def test_mixed_precision_preconditioner_keeps_the_solution(name):
     w = I.marshak_single(16, state="front") if name == "uniform" else \
         I.static_amr(base=16, nlevels=3, side=(8, 16), state="front")
-    Hd = make(w, precision=0, newton_rtol=1e-10, newton_atol=1e-16)
-    Hm = make(w, precision=1, newton_rtol=1e-10, newton_atol=1e-16)
+    extra = {"fac_smoother": 1, "fac_nu_pre": 2} if name == "amr-jacobi" else {}
+    Hd = make(w, precision=0, newton_rtol=1e-10, newton_atol=1e-16, **extra)
+    Hm = make(w, precision=1, newton_rtol=1e-10, newton_atol=1e-16, **extra)
     kd = km = 0
     for dt in (1e-3, 1e-3, 1e-3):
         _, sd = Hd.implicit_step([dt])
