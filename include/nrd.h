@@ -127,10 +127,10 @@ typedef struct {
                                nrd_step_stats.err_norm; needed by
                                nrd_adaptive_steps (0 default)                */
     int32_t fac_nu_pre;     /* FAC V(m, n) of Alg. 1 on hierarchies with more
-                               than one level: m >= 1 red-black sweeps per
-                               level on the down-sweep (default 1)           */
-    int32_t fac_nu_post;    /* n >= 0 sweeps per level on the up-sweep, each
-                               level's right-hand side the composite
+                               than one level: m in [1, 8] smoothing sweeps
+                               per level on the down-sweep (default 1)       */
+    int32_t fac_nu_post;    /* n in [0, 8] sweeps per level on the up-sweep,
+                               each level's right-hand side the composite
                                residual refreshed with every correction so
                                far (default 0: the paper's V(1,0))           */
     int32_t fac_smoother;   /* FAC level smoother (Sec. 4.3): NRD_SMOOTH_RBGS

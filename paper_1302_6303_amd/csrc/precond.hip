@@ -402,6 +402,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong_level(const int32_t* __restr
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
     const ShadowPatch* __restrict__ SP, const PT* __restrict__ sh, int64_t nls,
     PT* __restrict__ e, PT* __restrict__ u, int64_t nl) {
+    // e: the prolonged correction, kept as the source for the next finer
+    // level (NULL on the finest level, where only u is updated)
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
@@ -426,7 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_level(const int32_t* __restr
                      PT(9.0 / 64) * (s[ox] + s[oy] + s[oz]) +
                      PT(3.0 / 64) * (s[ox + oy] + s[ox + oz] + s[oy + oz]) +
                      PT(1.0 / 64) * s[ox + oy + oz];
-        e[fld * nl + c] = v;
+        if (e) e[fld * nl + c] = v;
         u[fld * nl + c] += v;
     }
 }
@@ -1055,7 +1057,8 @@ void PcArrays<PT>::correct_level(hipStream_t s, int lev) const {
                                                        shadow + a, shadow_len);
         const int m0 = d.level_tile0[m], mt = d.level_tile0[m + 1] - m0;
         k_prolong_level<PT><<<mt, kBlock, 0, s>>>(d.active, d.tiles + m0, d.patches, shadows,
-                                                  shadow, shadow_len, e, u, d.nl);
+                                                  shadow, shadow_len, m < L ? e : nullptr, u,
+                                                  d.nl);
     }
     restrict_(s, u, 0);
 }
