@@ -201,22 +201,19 @@ __device__ __forceinline__ void level_terms(const PatchInfo& p, const int id[3],
     }
 }
 
-template <typename PT, int MODE>   // MODE 0: RBGS colour (zero start) 1: colour 2: residual
+template <typename PT, int MODE>   // MODE 0: RBGS colour (zero start) 1: colour
 __device__ __forceinline__ void level_update(const PatchInfo& p, const int id[3], double beta,
                                              const uint8_t* __restrict__ ctype,
                                              const PT* __restrict__ D,
                                              const PT* __restrict__ f, PT* __restrict__ e,
-                                             PT* __restrict__ r, int64_t nl) {
+                                             int64_t nl) {
     const int c = nat(p, id[0], id[1], id[2]);
     PT dg[2], ns[2];
     level_terms<PT, MODE == 0>(p, id, c, beta, ctype, D, e, nl, dg, ns);
 #pragma unroll
     for (int fld = 0; fld < 2; ++fld) {
         const int64_t cfi = fld * nl + c;
-        if (MODE == 2)
-            r[cfi] = f[cfi] - (dg[fld] * e[cfi] - ns[fld]);
-        else
-            e[cfi] = (f[cfi] + ns[fld]) / dg[fld];
+        e[cfi] = (f[cfi] + ns[fld]) / dg[fld];
     }
 }
 
@@ -247,8 +244,8 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(const int32_t* __restrict__ a
     }
 }
 
-// MODE 2 (residual): kBlock threads, one per cell of the tile.
-// MODE 0 / 1 (one colour): kBlock / 2 threads.  When the patch's x extent is
+// One colour of a red-black sweep (MODE 0: from e = 0), kBlock / 2 threads
+// per tile of kBlock cells.  When the patch's x extent is
 // even, rows start at even linear indices, so every pair (2q, 2q + 1) of a
 // tile lies in one row and holds exactly one cell of each colour: thread q
 // updates that cell and every lane does useful work.  Otherwise each thread
@@ -258,30 +255,24 @@ __global__ __launch_bounds__(kBlock) void k_level(const int32_t* __restrict__ ac
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
     const PT* __restrict__ D, const PT* __restrict__ f, PT* __restrict__ e,
-    PT* __restrict__ r, int colour, int64_t nl) {
+    int colour, int64_t nl) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     const PatchInfo& p = P[t.patch];
     const double beta = ps[t.prob].beta;
     int id[3];
-    if (MODE == 2) {
-        if ((int)threadIdx.x >= t.count) return;
-        coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
-        level_update<PT, MODE>(p, id, beta, ctype, D, f, e, r, nl);
-        return;
-    }
     const int lo = p.lo[0] + p.lo[1] + p.lo[2];
     if ((p.n[0] & 1) == 0) {
         const int a = 2 * (int)threadIdx.x;          // tile starts are even
         if (a >= t.count) return;
         coords(p, t.start + a, id[0], id[1], id[2]);  // id[0] even
         id[0] += (colour + id[1] + id[2] + lo) & 1;
-        level_update<PT, MODE>(p, id, beta, ctype, D, f, e, r, nl);
+        level_update<PT, MODE>(p, id, beta, ctype, D, f, e, nl);
     } else {
         for (int q = threadIdx.x; q < t.count; q += kBlock / 2) {
             coords(p, t.start + q, id[0], id[1], id[2]);
             if (((id[0] + id[1] + id[2] + lo) & 1) != colour) continue;
-            level_update<PT, MODE>(p, id, beta, ctype, D, f, e, r, nl);
+            level_update<PT, MODE>(p, id, beta, ctype, D, f, e, nl);
         }
     }
 }
@@ -926,12 +917,12 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
                 if (g == 0 && clock) tk = clock->tic(which);
                 if (it == 0)
                     k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
-                                                        nullptr, 0, nlg);
+                                                        0, nlg);
                 else
                     k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
-                                                        nullptr, 0, nlg);
+                                                        0, nlg);
                 k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
-                                                    nullptr, 1, nlg);
+                                                    1, nlg);
                 if (g == 0 && clock) clock->toc(which, tk);
             }
             k_mg_res_restrict<PT><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active,
@@ -957,9 +948,9 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
         for (int it = 0; it < nu_post; ++it) {
             std::pair<hipEvent_t, hipEvent_t> tk{nullptr, nullptr};
             if (g == 0 && clock) tk = clock->tic(NRD_TIMER_SMOOTH);
-            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 0,
+            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, 0,
                                                 nlg);
-            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, nullptr, 1,
+            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, 1,
                                                 nlg);
             if (g == 0 && clock) clock->toc(NRD_TIMER_SMOOTH, tk);
         }
@@ -1031,15 +1022,15 @@ void PcArrays<PT>::smooth_level(hipStream_t s, const PT* rhs, int lev, int sweep
         return;
     }
     k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, tl, d.patches, d.ps, d.ctype, Dface, rhs,
-                                             e, nullptr, 0, d.nl);
+                                             e, 0, d.nl);
     siblings(s, e, lev);
     k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, d.patches, d.ps, d.ctype, Dface, rhs,
-                                             e, nullptr, 1, d.nl);
+                                             e, 1, d.nl);
     for (int it = 1; it < sweeps; ++it)
         for (int colour = 0; colour < 2; ++colour) {
             siblings(s, e, lev);
             k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, d.patches, d.ps, d.ctype,
-                                                     Dface, rhs, e, nullptr, colour, d.nl);
+                                                     Dface, rhs, e, colour, d.nl);
         }
 }
 
