@@ -26,6 +26,9 @@ Workloads (seeded, synthetic; --workload):
   uniform   one 32^3 patch, dt = 1e-3
   adjoint   64^3 smooth random material, 50 BDF1 steps: forward, checkpointed
             reverse sweep, transpose kernel
+  paperN    the paper's model problem on a uniform N^3 grid integrated to
+            --t-final (default 1) with PC.4.7; reports seconds, steps and
+            iterations per step beside the paper's uniform-grid tables
 """
 from __future__ import annotations
 
@@ -248,6 +251,60 @@ def cpu_baseline(w, budget_s=12.0):
                       f"workload's problems ({cells} cells), {t_used:.1f} s on one core"}
 
 
+# Levels = 1 column of the paper's Tables case1-li, case1-nli and ndt
+# (uniform grids): average linear and nonlinear iterations per step, the
+# number of steps and the final time of those runs.
+PAPER_UNIFORM = {32: (7.68, 2.99, 1334, 1.0), 64: (7.15, 2.96, 3253, 1.0),
+                 128: (6.43, 2.61, 8207, 1.0), 256: (6.72, 3.04, 8698, 0.5)}
+
+
+def paper_bench(n, t_final):
+    """The paper's model problem on a uniform n^3 grid integrated to t_final
+    with BDF2 and PC.4.7 at its tolerance (eps_t = 5e-4 at 32^3, halved per
+    doubling), Newton tolerances 1e-12 / 1e-10, FAC V(1,0), mixed precision;
+    the last step is shortened to land on t_final."""
+    from paper_1302_6303_amd import inputs as I, nrd
+    w = I.paper_marshak(n)
+    eps = 5e-4 * 32.0 / n
+    opts = nrd.default_options(precision=nrd.NRD_MIXED, error_estimate=1,
+                               newton_rtol=1e-12, newton_atol=1e-10)
+    H = nrd.Hierarchy(w.problems, w.boxes, opts)
+    u = compact_state(w)
+    m = H.ncells
+    H.set_fields(to_dev(u[:m]), to_dev(u[m:]), to_dev(w.compact(w.z)))
+    H.autotune(None)
+    t, dt = 0.0, float(w.dt[0])
+    steps = newton = krylov = cuts = 0
+    t0 = time.perf_counter()
+    while t < t_final * (1.0 - 1e-12):
+        dt = min(dt, t_final - t)
+        _, dtn, tt, st = H.adaptive_steps(1, [dt], eps, t=[t])
+        s = st[0][0]
+        steps += 1
+        newton += s["newton_iters"]
+        krylov += s["krylov_iters"]
+        cuts += s["positivity_cuts"]
+        t, dt = tt[0], dtn[0]
+        if steps % 500 == 0:
+            log(f"paper{n}: step {steps}, t = {t:.4g}, dt = {dt:.3g}")
+    wall = time.perf_counter() - t0
+    ref = PAPER_UNIFORM.get(n)
+    out = {"metric": f"seconds to t = {t_final:g}, paper model problem, uniform {n}^3",
+           "value": round(wall, 3), "unit": "s", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"paper{n}", "cells": n ** 3, "eps_t": eps,
+                      "solver": "BDF2, PC.4.7, Newton rtol 1e-12 atol 1e-10, FGMRES(30), "
+                                "FAC V(1,0) + MG V(1,1), mixed precision"},
+           "steps": steps, "t_final": t,
+           "linear_per_step": round(krylov / steps, 3),
+           "nonlinear_per_step": round(newton / steps, 3),
+           "positivity_cuts": cuts, "ms_per_step": round(1e3 * wall / steps, 3),
+           "paper_levels1": ({"linear_per_step": ref[0], "nonlinear_per_step": ref[1],
+                              "steps": ref[2]} if ref and abs(t_final - ref[3]) < 1e-12
+                             else None)}
+    print(json.dumps(out), flush=True)
+
+
 def adjoint_bench(nsteps, every, reps=20):
     """Forward BDF1 trajectory, checkpointed discrete adjoint of the sum of E
     at the final time, and the transpose kernel alone, on the 64^3 smooth
@@ -339,6 +396,8 @@ def main():
     ap.add_argument("--fac-smoother", choices=("rbgs", "jacobi"), default="rbgs",
                     help="FAC level smoother: red-black Gauss-Seidel (default) or damped "
                          "point Jacobi")
+    ap.add_argument("--t-final", type=float, default=1.0,
+                    help="paperN workloads: integrate the model problem to this time")
     ap.add_argument("--fp64-batched", action="store_true",
                     help="also time the FP64 solver with batched launches (per-patch vs "
                          "batched comparison at equal precision)")
@@ -351,6 +410,9 @@ def main():
     from paper_1302_6303_amd import nrd
     if a.workload == "adjoint":
         adjoint_bench(a.steps, a.ckpt_every)
+        return
+    if a.workload.startswith("paper"):
+        paper_bench(int(a.workload[5:]), a.t_final)
         return
     w = workload(a.workload)
     if a.dt_scale != 1.0:

@@ -117,7 +117,9 @@ typedef struct {
                                1 plane-marching tiles (each face once, LDS),
                                2 wave runs (x faces shared across lanes),
                                3 staged planes (each plane slice read once
-                               into LDS, 256-cell runs)                      */
+                               into LDS, 256-cell runs; a hierarchy with a
+                               patch wider than about 250 cells in x runs
+                               variant 1 instead)                            */
     int32_t zchunk;         /* planes per tile of variants 1, 2 (0: default)  */
     int32_t bdf_max_order;  /* 2 (default): BDF2 after the first step; 1: BDF1
                                throughout (the adjoint assumes BDF1)         */

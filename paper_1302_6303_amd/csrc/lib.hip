@@ -1482,9 +1482,18 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
             for (int b = 0; b < h->t.nbox; ++b)
                 kc[b] = h->opt.zchunk > 0 ? h->opt.zchunk
                                           : default_zchunk(h->t.patches[b].n, h->opt.stencil);
-            const int st = h->opt.stencil;
-            const bool ok = build_planes(h->t, kc, st == 2 ? 4 * 63 : (st == 3 ? kStageCells : 256),
-                                         st == 3 ? kStageLen : 0);
+            int st = h->opt.stencil;
+            bool ok = build_planes(h->t, kc, st == 2 ? 4 * 63 : (st == 3 ? kStageCells : 256),
+                                   st == 3 ? kStageLen : 0);
+            if (!ok && st == 3) {
+                // rows too wide for the staged slices (x extent above about
+                // 250): the plane-marching variant, same values, any width
+                st = h->opt.stencil = 1;
+                for (int b = 0; b < h->t.nbox; ++b)
+                    kc[b] = h->opt.zchunk > 0 ? h->opt.zchunk
+                                              : default_zchunk(h->t.patches[b].n, st);
+                ok = build_planes(h->t, kc, 256, 0);
+            }
             if (!ok) {
                 delete h;
                 return fail(NRD_EUNSUPPORTED, "a patch plane is too wide for the staged stencil");

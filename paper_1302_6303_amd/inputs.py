@@ -332,6 +332,22 @@ def uniform_workload(name, n, zfun, dt, nsteps, rng=None, state="uniform",
                     bdf1_only)
 
 
+# The three z = 10 boxes of the paper's model problem (Sec. 5), unit cube.
+PAPER_BOXES = [((0.0625, 0.375, 0.375), (0.2, 0.625, 0.625), 10.0),
+               ((0.125, 0.0, 0.0), (0.375, 1.0, 0.125), 10.0),
+               ((0.125, 0.0, 0.875), (0.375, 1.0, 1.0), 10.0)]
+
+
+def paper_marshak(n=32, dt=1e-5):
+    """The paper's model problem (Sec. 5) on one uniform n^3 grid: z = 10 in
+    its three boxes and 1 elsewhere, E = E0 and T = T0 everywhere, Robin
+    faces for E at x = 0 (R = 1) and x = 1 (R = 0), zero flux elsewhere;
+    dt is the first step size handed to the time-step controller."""
+    return uniform_workload(f"paper{n}", n, box_field(PAPER_BOXES), dt, 0,
+                            problem_kw={"bc_E": (1, 1, 0, 0, 0, 0),
+                                        "robin_R": (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)})
+
+
 def marshak_single(n=32, seed_k=1, state="uniform", nbox=2):
     """Single uniform patch with 2 seeded z = 10 boxes (the 32^3 workload)."""
     rng = np.random.default_rng(SEED_BASE + seed_k)

@@ -105,3 +105,13 @@ int main(void) {
             C.sizeof(nrd.nrd_step_stats), nrd.nrd_step_stats.err_norm.offset,
             C.sizeof(nrd.nrd_timectl), C.sizeof(nrd.nrd_problem), C.sizeof(nrd.nrd_box)]
     assert got == want
+
+
+def test_wide_patch_is_accepted_with_the_default_stencil():
+    """A patch whose rows do not fit the staged plane slices (the paper's
+    uniform 256^3 grid) is accepted: the hierarchy falls back to the
+    plane-marching variant."""
+    prob = I.Problem(base_n=(256, 256, 256))
+    box = I.Box(0, 0, (0, 0, 0), (256, 256, 256))
+    H = _create([prob], [box])
+    assert H.ncells == 256 ** 3

@@ -36,3 +36,23 @@ def test_workloads_are_seeded_and_nested():
     e = I.ensemble(nprob=8)
     assert len(e.boxes) == 8 and all(32 <= x.shape[0] <= 96 for x in e.boxes)
     assert np.all((e.dt >= 1e-4) & (e.dt <= 1e-3))
+
+
+def test_paper_model_problem_layout():
+    """The paper's model problem (Sec. 5): z = 10 exactly on the cells whose
+    centres lie in its three boxes, Robin faces at x = 0 and x = 1 only."""
+    n = 32
+    w = I.paper_marshak(n)
+    c = (np.arange(n) + 0.5) / n
+    expect = 0
+    for lo, hi, _ in I.PAPER_BOXES:
+        k = 1
+        for d in range(3):
+            k *= int(np.sum((c >= lo[d]) & (c < hi[d])))
+        expect += k
+    assert int(np.sum(w.z[0] == 10.0)) == expect
+    assert int(np.sum(w.z[0] == 1.0)) == n ** 3 - expect
+    p = w.problems[0]
+    assert tuple(p.bc_E) == (1, 1, 0, 0, 0, 0)
+    assert p.robin_R[0] == 1.0 and p.robin_R[1] == 0.0
+    assert np.all(w.E[0] == I.E0) and np.all(w.T[0] == I.T0)
