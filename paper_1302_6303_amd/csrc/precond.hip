@@ -1,10 +1,11 @@
 // Physics-based preconditioner kernels (paper Sec. 4.2-4.3, Alg. 1).
 //
 // P1 = diag(I - beta div D_E grad, I - beta div D_T grad) with D frozen at
-// u^k, approximately inverted by one FAC V(1,0) cycle: one red-black
-// Gauss-Seidel sweep per refinement level and a multigrid V(1,1) cycle on
-// the base level whose coarsest grid is solved with a dense float64
-// inverse.  P2 is the per-cell 2x2 coupling block.  PT is the storage and
+// u^k, approximately inverted by one FAC V(m,n) cycle (default V(1,0)):
+// red-black Gauss-Seidel (or damped point Jacobi) sweeps per refinement
+// level and a multigrid V(1,1) cycle on the base level whose coarsest grid
+// is solved with a dense float64 inverse.  P2 is the per-cell 2x2 coupling
+// block.  PT is the storage and
 // arithmetic type of the V-cycle (float in mixed precision, double
 // otherwise); the bottom solve always uses double.
 //
@@ -609,7 +610,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom_setup(const int32_t* 
     const ProbScalars* __restrict__ ps, const int64_t* __restrict__ boff,
     double* __restrict__ X) {
     __shared__ double A[kBottomMax * kBandLd];   // A(i, i - d) at [i kBandLd + d]
-    __shared__ double Ld[kBottomMax];            // diagonal of L
+    __shared__ double Li[kBottomMax];            // 1 / diagonal of L
     __shared__ double W[kBottomMax * kBottomMax];   // column j of the inverse at [i N + j]
     const int pi = blockIdx.x >> 1;
     const int fld = blockIdx.x & 1;
@@ -669,7 +670,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom_setup(const int32_t* 
         const double inv = 1.0 / dkk;
         const int m = min(b, N - 1 - k);
         if (tid >= 1 && tid <= m) A[(k + tid) * kBandLd + tid] *= inv;
-        if (tid == 0) Ld[k] = dkk;
+        if (tid == 0) Li[k] = inv;
         __syncthreads();
         if (pr <= m)
             A[(k + pr) * kBandLd + (pr - pq)] -= A[(k + pr) * kBandLd + pr] * A[(k + pq) * kBandLd + pq];
@@ -689,7 +690,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom_setup(const int32_t* 
             for (int l = 1 + q; l <= lmax; l += 4) acc -= A[i * kBandLd + l] * W[(i - l) * N + j];
             acc += __shfl_xor(acc, 1, 64);
             acc += __shfl_xor(acc, 2, 64);
-            W[i * N + j] = (((i == j) ? 1.0 : 0.0) + acc) / Ld[i];
+            W[i * N + j] = (((i == j) ? 1.0 : 0.0) + acc) * Li[i];
         }
         for (int i = N - 1; i >= 0; --i) {          // L^T x = y
             const int lmax = min(b, N - 1 - i);
@@ -698,7 +699,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom_setup(const int32_t* 
                 acc -= A[(i + l) * kBandLd + l] * W[(i + l) * N + j];
             acc += __shfl_xor(acc, 1, 64);
             acc += __shfl_xor(acc, 2, 64);
-            W[i * N + j] = (W[i * N + j] + acc) / Ld[i];
+            W[i * N + j] = (W[i * N + j] + acc) * Li[i];
         }
     }
     __syncthreads();
