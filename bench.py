@@ -29,6 +29,8 @@ Workloads (seeded, synthetic; --workload):
   paperN    the paper's model problem on a uniform N^3 grid integrated to
             --t-final (default 1) with PC.4.7; reports seconds, steps and
             iterations per step beside the paper's uniform-grid tables
+  paper-spatial  uniform 128^3 against a 256^3 reference with the same
+            steps: L2 errors beside the paper's spatial-accuracy table
 """
 from __future__ import annotations
 
@@ -305,6 +307,79 @@ def paper_bench(n, t_final):
     print(json.dumps(out), flush=True)
 
 
+# Row 128b1l of the paper's spatial-accuracy table (uniform 128^3 against
+# a uniform 256^3 reference run with the same time steps): L2 errors of E
+# and T at these times.
+PAPER_SPATIAL_T = (0.04, 0.10, 0.19, 0.25, 0.35, 0.46)
+PAPER_SPATIAL_128 = {"E": (2.38e-2, 1.39e-2, 1.17e-2, 1.11e-2, 1.44e-2, 2.29e-2),
+                     "T": (5.53e-3, 4.43e-3, 5.45e-3, 7.63e-3, 1.11e-2, 1.64e-2)}
+
+
+def paper_spatial_bench():
+    """Spatial error of the uniform 128^3 grid on the paper's model problem:
+    a 256^3 run with PC.4.7 (steps shortened to land on the table's times)
+    records its step sizes and its fields at those times, averaged onto the
+    128^3 cells; the 128^3 run repeats the same steps; the error is the
+    volume-weighted L2 norm of the difference (unit cube)."""
+    import torch
+    from paper_1302_6303_amd import inputs as I, nrd
+
+    def make_h(n, estimate):
+        w = I.paper_marshak(n)
+        o = nrd.default_options(precision=nrd.NRD_MIXED, error_estimate=estimate,
+                                newton_rtol=1e-12, newton_atol=1e-10)
+        H = nrd.Hierarchy(w.problems, w.boxes, o)
+        u = compact_state(w)
+        m = H.ncells
+        H.set_fields(to_dev(u[:m]), to_dev(u[m:]), to_dev(w.compact(w.z)))
+        H.autotune(None)
+        return H, w
+
+    def coarse(x):                    # 256^3 compact (x fastest) -> 128^3 means
+        return x.view(128, 2, 128, 2, 128, 2).mean(dim=(1, 3, 5))
+
+    t0 = time.perf_counter()
+    H, w = make_h(256, 1)
+    t, dt = 0.0, float(w.dt[0])
+    eps = 5e-4 * 32.0 / 256
+    dts, ref = [], []
+    for tg in PAPER_SPATIAL_T:
+        while t < tg * (1.0 - 1e-12):
+            dt = min(dt, tg - t)
+            _, dtn, tt, st = H.adaptive_steps(1, [dt], eps, t=[t])
+            dts.append(st[0][0]["dt"])
+            t, dt = tt[0], dtn[0]
+            if len(dts) % 500 == 0:
+                log(f"256^3 reference: step {len(dts)}, t = {t:.4g}")
+        E, T = H.get_fields()
+        ref.append((coarse(E).clone(), coarse(T).clone(), len(dts)))
+        log(f"256^3 reference at t = {t:.4g} after {len(dts)} steps")
+    del H
+    torch.cuda.empty_cache()
+    H, _ = make_h(128, 0)
+    errs = {"E": [], "T": []}
+    k = 0
+    for i, tg in enumerate(PAPER_SPATIAL_T):
+        while k < ref[i][2]:                 # the reference run's steps up to tg
+            H.implicit_step([dts[k]])
+            k += 1
+        t = tg
+        E, T = H.get_fields()
+        for name, a, b in (("E", E, ref[i][0]), ("T", T, ref[i][1])):
+            errs[name].append(float(torch.sqrt(torch.mean((a.view(128, 128, 128) - b) ** 2))))
+        log(f"128^3 at t = {t:.4g}: E error {errs['E'][-1]:.3e}, T error {errs['T'][-1]:.3e}")
+    out = {"metric": "L2 error of uniform 128^3 against 256^3 with the same steps, paper "
+                     "model problem",
+           "value": errs["E"][-1], "unit": "L2 (E, last time)", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "paper-spatial", "times": list(PAPER_SPATIAL_T),
+                      "steps": len(dts), "eps_t_256": eps},
+           "errors": {kk: [round(v, 6) for v in vv] for kk, vv in errs.items()},
+           "paper_128b1l": PAPER_SPATIAL_128,
+           "wall_s": round(time.perf_counter() - t0, 1)}
+    print(json.dumps(out), flush=True)
+
+
 def adjoint_bench(nsteps, every, reps=20):
     """Forward BDF1 trajectory, checkpointed discrete adjoint of the sum of E
     at the final time, and the transpose kernel alone, on the 64^3 smooth
@@ -410,6 +485,9 @@ def main():
     from paper_1302_6303_amd import nrd
     if a.workload == "adjoint":
         adjoint_bench(a.steps, a.ckpt_every)
+        return
+    if a.workload == "paper-spatial":
+        paper_spatial_bench()
         return
     if a.workload.startswith("paper"):
         paper_bench(int(a.workload[5:]), a.t_final)
