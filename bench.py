@@ -31,6 +31,8 @@ Workloads (seeded, synthetic; --workload):
             iterations per step beside the paper's uniform-grid tables
   paper-spatial  uniform 128^3 against a 256^3 reference with the same
             steps: L2 errors beside the paper's spatial-accuracy table
+  paper-temporal  fixed BDF2 steps 2e-4, 1e-4, 5e-5 against 2.5e-5 on
+            128^3: L2 errors beside the paper's temporal-accuracy table
 """
 from __future__ import annotations
 
@@ -380,6 +382,67 @@ def paper_spatial_bench():
     print(json.dumps(out), flush=True)
 
 
+# The paper's temporal-accuracy table (fixed BDF2 steps against a 2.5e-5
+# reference, equivalent 128^3 resolution): L2 errors of E and T.
+PAPER_TEMPORAL_T = (0.05, 0.15, 0.25, 0.35, 0.45)
+PAPER_TEMPORAL = {2e-4: {"E": (4.53e-5, 3.93e-5, 2.87e-5, 2.47e-5, 2.36e-5),
+                         "T": (2.43e-5, 2.06e-5, 1.89e-5, 1.87e-5, 1.82e-5)},
+                  1e-4: {"E": (1.13e-5, 9.80e-6, 7.10e-6, 6.10e-6, 5.80e-6),
+                         "T": (6.00e-6, 5.10e-6, 4.70e-6, 4.60e-6, 4.50e-6)},
+                  5e-5: {"E": (2.30e-6, 2.00e-6, 1.50e-6, 1.30e-6, 1.20e-6),
+                         "T": (1.20e-6, 1.00e-6, 1.00e-6, 9.00e-7, 9.00e-7)}}
+
+
+def paper_temporal_bench(n=128, dt_ref=2.5e-5):
+    """Temporal error of fixed-step BDF2 (first step BDF1) on the paper's
+    model problem, uniform n^3: runs with the table's steps against a run
+    with dt_ref, volume-weighted L2 norms at the table's times."""
+    import torch
+    from paper_1302_6303_amd import inputs as I, nrd
+    w = I.paper_marshak(n)
+    o = nrd.default_options(precision=nrd.NRD_MIXED, newton_rtol=1e-12, newton_atol=1e-10)
+    H = nrd.Hierarchy(w.problems, w.boxes, o)
+    u = compact_state(w)
+    m = H.ncells
+    E0, T0, z = to_dev(u[:m]), to_dev(u[m:]), to_dev(w.compact(w.z))
+    H.set_fields(E0, T0, z)
+    H.autotune(None)
+    t0 = time.perf_counter()
+
+    def run(dt):
+        H.set_fields(E0, T0, z)                # resets the history: BDF1 first
+        out, k = [], 0
+        for tg in PAPER_TEMPORAL_T:
+            kk = int(round(tg / dt))
+            while k < kk:
+                H.implicit_step([dt])
+                k += 1
+            E, T = H.get_fields()
+            out.append((E.clone(), T.clone()))
+        log(f"fixed step {dt:g}: {k} steps")
+        return out
+
+    ref = run(dt_ref)
+    errs = {}
+    for dt in sorted(PAPER_TEMPORAL, reverse=True):
+        got = run(dt)
+        errs[f"{dt:g}"] = {
+            "E": [round(float(torch.sqrt(torch.mean((a[0] - b[0]) ** 2))), 9)
+                  for a, b in zip(got, ref)],
+            "T": [round(float(torch.sqrt(torch.mean((a[1] - b[1]) ** 2))), 9)
+                  for a, b in zip(got, ref)]}
+    out = {"metric": f"L2 temporal error of fixed-step BDF2 against dt = {dt_ref:g}, paper "
+                     f"model problem, uniform {n}^3",
+           "value": errs[f"{min(PAPER_TEMPORAL):g}"]["E"][-1], "unit": "L2 (E, smallest step)",
+           "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "paper-temporal", "cells": n ** 3,
+                      "times": list(PAPER_TEMPORAL_T), "dt_ref": dt_ref},
+           "errors": errs,
+           "paper": {f"{k:g}": v for k, v in PAPER_TEMPORAL.items()},
+           "wall_s": round(time.perf_counter() - t0, 1)}
+    print(json.dumps(out), flush=True)
+
+
 def adjoint_bench(nsteps, every, reps=20):
     """Forward BDF1 trajectory, checkpointed discrete adjoint of the sum of E
     at the final time, and the transpose kernel alone, on the 64^3 smooth
@@ -488,6 +551,9 @@ def main():
         return
     if a.workload == "paper-spatial":
         paper_spatial_bench()
+        return
+    if a.workload == "paper-temporal":
+        paper_temporal_bench()
         return
     if a.workload.startswith("paper"):
         paper_bench(int(a.workload[5:]), a.t_final)
