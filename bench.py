@@ -262,7 +262,7 @@ PAPER_UNIFORM = {32: (7.68, 2.99, 1334, 1.0), 64: (7.15, 2.96, 3253, 1.0),
                  128: (6.43, 2.61, 8207, 1.0), 256: (6.72, 3.04, 8698, 0.5)}
 
 
-def paper_bench(n, t_final):
+def paper_bench(n, t_final, limiter=0.5):
     """The paper's model problem on a uniform n^3 grid integrated to t_final
     with BDF2 and PC.4.7 at its tolerance (eps_t = 5e-4 at 32^3, halved per
     doubling), Newton tolerances 1e-12 / 1e-10, FAC V(1,0), mixed precision;
@@ -271,7 +271,7 @@ def paper_bench(n, t_final):
     w = I.paper_marshak(n)
     eps = 5e-4 * 32.0 / n
     opts = nrd.default_options(precision=nrd.NRD_MIXED, error_estimate=1,
-                               newton_rtol=1e-12, newton_atol=1e-10)
+                               newton_rtol=1e-12, newton_atol=1e-10, limiter=limiter)
     H = nrd.Hierarchy(w.problems, w.boxes, opts)
     u = compact_state(w)
     m = H.ncells
@@ -297,6 +297,7 @@ def paper_bench(n, t_final):
            "value": round(wall, 3), "unit": "s", "n_gpus": 1, "higher_is_better": False,
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"paper{n}", "cells": n ** 3, "eps_t": eps,
+                      "limiter": limiter,
                       "solver": "BDF2, PC.4.7, Newton rtol 1e-12 atol 1e-10, FGMRES(30), "
                                 "FAC V(1,0) + MG V(1,1), mixed precision"},
            "steps": steps, "t_final": t,
@@ -317,7 +318,7 @@ PAPER_SPATIAL_128 = {"E": (2.38e-2, 1.39e-2, 1.17e-2, 1.11e-2, 1.44e-2, 2.29e-2)
                      "T": (5.53e-3, 4.43e-3, 5.45e-3, 7.63e-3, 1.11e-2, 1.64e-2)}
 
 
-def paper_spatial_bench():
+def paper_spatial_bench(limiter=0.5):
     """Spatial error of the uniform 128^3 grid on the paper's model problem:
     a 256^3 run with PC.4.7 (steps shortened to land on the table's times)
     records its step sizes and its fields at those times, averaged onto the
@@ -329,7 +330,7 @@ def paper_spatial_bench():
     def make_h(n, estimate):
         w = I.paper_marshak(n)
         o = nrd.default_options(precision=nrd.NRD_MIXED, error_estimate=estimate,
-                                newton_rtol=1e-12, newton_atol=1e-10)
+                                newton_rtol=1e-12, newton_atol=1e-10, limiter=limiter)
         H = nrd.Hierarchy(w.problems, w.boxes, o)
         u = compact_state(w)
         m = H.ncells
@@ -375,6 +376,7 @@ def paper_spatial_bench():
            "value": errs["E"][-1], "unit": "L2 (E, last time)", "n_gpus": 1,
            "higher_is_better": False, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "paper-spatial", "times": list(PAPER_SPATIAL_T),
+                      "limiter": limiter,
                       "steps": len(dts), "eps_t_256": eps},
            "errors": {kk: [round(v, 6) for v in vv] for kk, vv in errs.items()},
            "paper_128b1l": PAPER_SPATIAL_128,
@@ -393,14 +395,15 @@ PAPER_TEMPORAL = {2e-4: {"E": (4.53e-5, 3.93e-5, 2.87e-5, 2.47e-5, 2.36e-5),
                          "T": (1.20e-6, 1.00e-6, 1.00e-6, 9.00e-7, 9.00e-7)}}
 
 
-def paper_temporal_bench(n=128, dt_ref=2.5e-5):
+def paper_temporal_bench(n=128, dt_ref=2.5e-5, limiter=0.5):
     """Temporal error of fixed-step BDF2 (first step BDF1) on the paper's
     model problem, uniform n^3: runs with the table's steps against a run
     with dt_ref, volume-weighted L2 norms at the table's times."""
     import torch
     from paper_1302_6303_amd import inputs as I, nrd
     w = I.paper_marshak(n)
-    o = nrd.default_options(precision=nrd.NRD_MIXED, newton_rtol=1e-12, newton_atol=1e-10)
+    o = nrd.default_options(precision=nrd.NRD_MIXED, newton_rtol=1e-12, newton_atol=1e-10,
+                            limiter=limiter)
     H = nrd.Hierarchy(w.problems, w.boxes, o)
     u = compact_state(w)
     m = H.ncells
@@ -435,7 +438,7 @@ def paper_temporal_bench(n=128, dt_ref=2.5e-5):
                      f"model problem, uniform {n}^3",
            "value": errs[f"{min(PAPER_TEMPORAL):g}"]["E"][-1], "unit": "L2 (E, smallest step)",
            "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "paper-temporal", "cells": n ** 3,
+           "config": {"workload": "paper-temporal", "cells": n ** 3, "limiter": limiter,
                       "times": list(PAPER_TEMPORAL_T), "dt_ref": dt_ref},
            "errors": errs,
            "paper": {f"{k:g}": v for k, v in PAPER_TEMPORAL.items()},
@@ -534,6 +537,9 @@ def main():
     ap.add_argument("--fac-smoother", choices=("rbgs", "jacobi"), default="rbgs",
                     help="FAC level smoother: red-black Gauss-Seidel (default) or damped "
                          "point Jacobi")
+    ap.add_argument("--limiter", type=float, default=0.5,
+                    help="paper workloads: lambda of the flux limiter (0.5: the printed "
+                         "pair, the library default; 1: Wilson form)")
     ap.add_argument("--t-final", type=float, default=1.0,
                     help="paperN workloads: integrate the model problem to this time")
     ap.add_argument("--fp64-batched", action="store_true",
@@ -550,13 +556,13 @@ def main():
         adjoint_bench(a.steps, a.ckpt_every)
         return
     if a.workload == "paper-spatial":
-        paper_spatial_bench()
+        paper_spatial_bench(a.limiter)
         return
     if a.workload == "paper-temporal":
-        paper_temporal_bench()
+        paper_temporal_bench(limiter=a.limiter)
         return
     if a.workload.startswith("paper"):
-        paper_bench(int(a.workload[5:]), a.t_final)
+        paper_bench(int(a.workload[5:]), a.t_final, a.limiter)
         return
     w = workload(a.workload)
     if a.dt_scale != 1.0:

@@ -101,7 +101,7 @@ typedef struct {
                                on first use and replay it                    */
     int32_t jvp_mode;       /* analytic Jacobian action or finite difference  */
     double limiter;         /* lambda in D_h / (1 + lambda D_h |dE|/(h E_f));
-                               1 = Wilson form, 0.5 = the printed pair       */
+                               0.5 = the printed pair (default), 1 = Wilson  */
     int32_t p2_mode;        /* coupling block entries                        */
     double newton_rtol;     /* ||F_k|| <= max(rtol ||F_0||, atol)            */
     double newton_atol;
@@ -143,7 +143,7 @@ typedef struct {
 } nrd_options;
 
 /* Fills *opt with the defaults: FP64, batched, no graph, analytic JVP,
- * limiter 1, paper P2, rtol 1e-8, atol 1e-14, 20 Newton iterations,
+ * limiter 1/2 (the printed pair), paper P2, rtol 1e-8, atol 1e-14, 20 Newton iterations,
  * GMRES(30) with 10 restarts, FAC V(1,0), base multigrid V(1,1),
  * staged-plane stencil, BDF2, no error
  * estimate, eta_E = 1e-5 (the initial energy density of Sec. 5), eta_T =

@@ -34,7 +34,7 @@ class System:
     """One problem: hierarchy, material field, options; compact vectors are
     [E of all patches (x fastest) | T of all patches]."""
 
-    def __init__(self, H, z, lam=1.0, p2_mode="paper", jvp_mode="analytic", fac_nu=(1, 0),
+    def __init__(self, H, z, lam=0.5, p2_mode="paper", jvp_mode="analytic", fac_nu=(1, 0),
                  fac_smoother="rbgs"):
         self.H = H
         self.jvp_mode = jvp_mode

@@ -1383,7 +1383,7 @@ void nrd_default_options(nrd_options* o) {
     o->launch = NRD_BATCHED;
     o->use_graph = 0;
     o->jvp_mode = NRD_JVP_ANALYTIC;
-    o->limiter = 1.0;
+    o->limiter = 0.5;
     o->p2_mode = NRD_P2_PAPER;
     o->newton_rtol = 1e-8;
     o->newton_atol = 1e-14;

@@ -91,7 +91,7 @@ def test_residual_parity(name, stencil):
         assert rel_err(got[sl], ref[sl]) < 1e-12
     E, T = s.split(u)
     bE, bT = s.split(u_n)
-    sE, sT = ops.residual_scale(s.H, E, T, s.z, bE, bT, dt, 1.0)
+    sE, sT = ops.residual_scale(s.H, E, T, s.z, bE, bT, dt, 1.0, s.lam)
     scale = s.join(sE, sT)
     assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-300)
 

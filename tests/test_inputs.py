@@ -56,3 +56,7 @@ def test_paper_model_problem_layout():
     assert tuple(p.bc_E) == (1, 1, 0, 0, 0, 0)
     assert p.robin_R[0] == 1.0 and p.robin_R[1] == 0.0
     assert np.all(w.E[0] == I.E0) and np.all(w.T[0] == I.T0)
+    with open(GOLD) as f:
+        gold = json.load(f)
+    assert [[list(lo), list(hi)] for lo, hi, _ in I.PAPER_BOXES] == gold["z_boxes"]
+    assert all(zv == gold["z_inside"] for _, _, zv in I.PAPER_BOXES)

@@ -280,7 +280,7 @@ def test_mms_second_order():
     errs = []
     for n in (8, 16, 32):
         H = Hierarchy((n, n, n), [(0, (0, 0, 0), (n, n, n))], bc_E=(0,) * 6)
-        s = System(H, [np.full((n, n, n), 1.3)])
+        s = System(H, [np.full((n, n, n), 1.3)], lam=1.0)     # the continuum flux above
         errs.append(_mms_error(s, H))
     rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(rates) > 1.8, (errs, rates)
