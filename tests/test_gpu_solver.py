@@ -273,3 +273,23 @@ def test_graph_captured_adjoint_matches_eager():
                  use_graph=use_graph)
         g.append(to_host(H.adjoint_run([dt], N, every)))
     np.testing.assert_array_equal(g[0], g[1])
+
+
+def test_paper_model_problem_step_count_matches_the_paper():
+    """The paper's model problem (Sec. 5) on the uniform 32^3 grid with its
+    solver settings (BDF2, PC.4.7 at eps_t = 5e-4, Newton 1e-12 / 1e-10)
+    integrated to t = 1 takes the paper's number of time steps (1334 in
+    its Table ndt, Levels = 1) within 5 %."""
+    from paper_1302_6303_amd import nrd
+    w = I.paper_marshak(32)
+    H = make(w, precision=nrd.NRD_MIXED, error_estimate=1, newton_rtol=1e-12,
+             newton_atol=1e-10)
+    t, dt, steps = 0.0, 1e-5, 0
+    while t < 1.0 - 1e-12:
+        dt = min(dt, 1.0 - t)
+        _, dtn, tt, _ = H.adaptive_steps(1, [dt], 5e-4, t=[t])
+        t, dt = tt[0], dtn[0]
+        steps += 1
+        assert steps < 3000
+    print(f"steps to t = 1: {steps} (paper 1334)")
+    assert abs(steps - 1334) < 0.05 * 1334
