@@ -31,6 +31,7 @@ Workloads (seeded, synthetic; --workload):
             iterations per step beside the paper's uniform-grid tables
   paper-spatial  uniform 128^3 against a 256^3 reference with the same
             steps: L2 errors beside the paper's spatial-accuracy table
+            (paper-spatial-z1: its single-material variant, z = 1)
   paper-temporal  fixed BDF2 steps 2e-4, 1e-4, 5e-5 against 2.5e-5 on
             128^3: L2 errors beside the paper's temporal-accuracy table
 """
@@ -316,9 +317,13 @@ def paper_bench(n, t_final, limiter=0.5):
 PAPER_SPATIAL_T = (0.04, 0.10, 0.19, 0.25, 0.35, 0.46)
 PAPER_SPATIAL_128 = {"E": (2.38e-2, 1.39e-2, 1.17e-2, 1.11e-2, 1.44e-2, 2.29e-2),
                      "T": (5.53e-3, 4.43e-3, 5.45e-3, 7.63e-3, 1.11e-2, 1.64e-2)}
+# The same for the paper's single-material runs (z = 1 everywhere).
+PAPER_SPATIAL_T_Z1 = (0.05, 0.11, 0.19, 0.27, 0.36, 0.45)
+PAPER_SPATIAL_128_Z1 = {"E": (1.94e-2, 1.30e-2, 1.08e-2, 1.07e-2, 1.06e-2, 9.12e-3),
+                        "T": (5.15e-3, 4.37e-3, 3.91e-3, 3.81e-3, 4.14e-3, 4.19e-3)}
 
 
-def paper_spatial_bench(limiter=0.5):
+def paper_spatial_bench(limiter=0.5, single_material=False):
     """Spatial error of the uniform 128^3 grid on the paper's model problem:
     a 256^3 run with PC.4.7 (steps shortened to land on the table's times)
     records its step sizes and its fields at those times, averaged onto the
@@ -327,8 +332,11 @@ def paper_spatial_bench(limiter=0.5):
     import torch
     from paper_1302_6303_amd import inputs as I, nrd
 
+    times = PAPER_SPATIAL_T_Z1 if single_material else PAPER_SPATIAL_T
+    paper = PAPER_SPATIAL_128_Z1 if single_material else PAPER_SPATIAL_128
+
     def make_h(n, estimate):
-        w = I.paper_marshak(n)
+        w = I.paper_marshak(n, single_material=single_material)
         o = nrd.default_options(precision=nrd.NRD_MIXED, error_estimate=estimate,
                                 newton_rtol=1e-12, newton_atol=1e-10, limiter=limiter)
         H = nrd.Hierarchy(w.problems, w.boxes, o)
@@ -346,7 +354,7 @@ def paper_spatial_bench(limiter=0.5):
     t, dt = 0.0, float(w.dt[0])
     eps = 5e-4 * 32.0 / 256
     dts, ref = [], []
-    for tg in PAPER_SPATIAL_T:
+    for tg in times:
         while t < tg * (1.0 - 1e-12):
             dt = min(dt, tg - t)
             _, dtn, tt, st = H.adaptive_steps(1, [dt], eps, t=[t])
@@ -362,7 +370,7 @@ def paper_spatial_bench(limiter=0.5):
     H, _ = make_h(128, 0)
     errs = {"E": [], "T": []}
     k = 0
-    for i, tg in enumerate(PAPER_SPATIAL_T):
+    for i, tg in enumerate(times):
         while k < ref[i][2]:                 # the reference run's steps up to tg
             H.implicit_step([dts[k]])
             k += 1
@@ -375,11 +383,11 @@ def paper_spatial_bench(limiter=0.5):
                      "model problem",
            "value": errs["E"][-1], "unit": "L2 (E, last time)", "n_gpus": 1,
            "higher_is_better": False, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "paper-spatial", "times": list(PAPER_SPATIAL_T),
-                      "limiter": limiter,
+           "config": {"workload": "paper-spatial" + ("-z1" if single_material else ""),
+                      "times": list(times), "limiter": limiter,
                       "steps": len(dts), "eps_t_256": eps},
            "errors": {kk: [round(v, 6) for v in vv] for kk, vv in errs.items()},
-           "paper_128b1l": PAPER_SPATIAL_128,
+           "paper_128b1l": paper,
            "wall_s": round(time.perf_counter() - t0, 1)}
     print(json.dumps(out), flush=True)
 
@@ -555,8 +563,8 @@ def main():
     if a.workload == "adjoint":
         adjoint_bench(a.steps, a.ckpt_every)
         return
-    if a.workload == "paper-spatial":
-        paper_spatial_bench(a.limiter)
+    if a.workload in ("paper-spatial", "paper-spatial-z1"):
+        paper_spatial_bench(a.limiter, a.workload.endswith("z1"))
         return
     if a.workload == "paper-temporal":
         paper_temporal_bench(limiter=a.limiter)

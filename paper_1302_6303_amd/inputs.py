@@ -338,12 +338,14 @@ PAPER_BOXES = [((0.0625, 0.375, 0.375), (0.2, 0.625, 0.625), 10.0),
                ((0.125, 0.0, 0.875), (0.375, 1.0, 1.0), 10.0)]
 
 
-def paper_marshak(n=32, dt=1e-5):
+def paper_marshak(n=32, dt=1e-5, single_material=False):
     """The paper's model problem (Sec. 5) on one uniform n^3 grid: z = 10 in
-    its three boxes and 1 elsewhere, E = E0 and T = T0 everywhere, Robin
+    its three boxes and 1 elsewhere (z = 1 everywhere for the paper's
+    single-material accuracy runs), E = E0 and T = T0 everywhere, Robin
     faces for E at x = 0 (R = 1) and x = 1 (R = 0), zero flux elsewhere;
     dt is the first step size handed to the time-step controller."""
-    return uniform_workload(f"paper{n}", n, box_field(PAPER_BOXES), dt, 0,
+    zf = box_field([] if single_material else PAPER_BOXES)
+    return uniform_workload(f"paper{n}", n, zf, dt, 0,
                             problem_kw={"bc_E": (1, 1, 0, 0, 0, 0),
                                         "robin_R": (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)})
 
