@@ -90,6 +90,7 @@ enum { NRD_BATCHED = 0, NRD_PER_PATCH = 1 };     /* kernel launch grouping   */
 enum { NRD_JVP_ANALYTIC = 0, NRD_JVP_FD = 1 };
 enum { NRD_P2_PAPER = 0, NRD_P2_FROZEN4 = 1 };
 enum { NRD_SMOOTH_RBGS = 0, NRD_SMOOTH_JACOBI = 1 };  /* FAC level smoother */
+enum { NRD_BASE_MG = 0, NRD_BASE_SMOOTH = 1 };       /* FAC base level     */
 
 typedef struct {
     int32_t precision;      /* NRD_FP64 or NRD_MIXED (V-cycles in float)     */
@@ -140,6 +141,11 @@ typedef struct {
                                Jacobi with weight 6/7                        */
     double err_eta_E;       /* eta_E, eta_T of that norm,                    */
     double err_eta_T;       /* max |e / (u + eta)| over composite cells      */
+    int32_t fac_base;       /* base level of FAC: NRD_BASE_MG (default), one
+                               multigrid V-cycle, or NRD_BASE_SMOOTH, only
+                               fac_nu_pre level sweeps there (the paper's
+                               runs smooth on the coarsest level, Sec. 4.3)  */
+    int32_t pad_;
 } nrd_options;
 
 /* Fills *opt with the defaults: FP64, batched, no graph, analytic JVP,

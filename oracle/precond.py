@@ -88,12 +88,13 @@ class Snapshot:
     """
 
     def __init__(self, H, E, T, z, beta, lam=1.0, p2_mode="paper", fac_nu=(1, 0),
-                 fac_smoother="rbgs"):
+                 fac_smoother="rbgs", fac_base="mg"):
         self.H = H
         self.beta = float(beta)
         self.p2_mode = p2_mode
         self.fac_nu = tuple(fac_nu)
         self.fac_smoother = fac_smoother      # "rbgs" or "jacobi" on levels >= 1
+        self.fac_base = fac_base              # "mg": V-cycle on level 0; "smooth": sweeps
         Eg, Tg = ghosted_state(H, E, T)
         z3 = ghosted_z3(H, z)
         self.T = [a[1:-1, 1:-1, 1:-1].copy() for a in Tg]
@@ -500,7 +501,8 @@ def fac_vcycle(H, snap, f, rhs, mg_grids=None, nu=None):
     """One FAC V(m,n) cycle for A^c u = rhs from u = 0 (Alg. 1), nu = (m, n)
     (default snap.fac_nu, else (1, 0)); the level smoother is red-black
     Gauss-Seidel or, with snap.fac_smoother == "jacobi", damped point Jacobi
-    (Sec. 4.3 names both).
+    (Sec. 4.3 names both); snap.fac_base == "smooth" replaces the base
+    level's V-cycle by m smoothing sweeps (what the paper's runs did).
 
     Down-sweep, finest level to level 1: composite residual, m smoothing
     sweeps from zero on the level, correction of u on the level and (by
@@ -549,9 +551,10 @@ def fac_vcycle(H, snap, f, rhs, mg_grids=None, nu=None):
         H.sync([ug])
         u = H.interior(ug)
 
+    base_smooth = getattr(snap, "fac_base", "mg") == "smooth"
     for lev in range(L, -1, -1):
         rg = level_rhs()
-        if lev > 0:
+        if lev > 0 or base_smooth:
             corr = smooth(lev, rg, m_pre)
         else:
             p0 = H.by_level[0][0]

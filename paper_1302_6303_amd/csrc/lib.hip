@@ -344,6 +344,7 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
     pc.fac_pre = h->opt.fac_nu_pre;
     pc.fac_post = h->opt.fac_nu_post;
     pc.fac_smoother = h->opt.fac_smoother;
+    pc.base_smooth = h->opt.fac_base == NRD_BASE_SMOOTH;
     pc.clock = h;
 }
 
@@ -1395,6 +1396,7 @@ void nrd_default_options(nrd_options* o) {
     o->fac_nu_pre = 1;
     o->fac_nu_post = 0;
     o->fac_smoother = NRD_SMOOTH_RBGS;
+    o->fac_base = NRD_BASE_MG;
     o->stencil = 3;
     o->bdf_max_order = 2;
     o->error_estimate = 0;
@@ -1428,6 +1430,10 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
         if (h->opt.fac_smoother != NRD_SMOOTH_RBGS && h->opt.fac_smoother != NRD_SMOOTH_JACOBI) {
             delete h;
             return fail(NRD_EINVAL, "fac_smoother must be RBGS or JACOBI");
+        }
+        if (h->opt.fac_base != NRD_BASE_MG && h->opt.fac_base != NRD_BASE_SMOOTH) {
+            delete h;
+            return fail(NRD_EINVAL, "fac_base must be MG or SMOOTH");
         }
         if (h->opt.bdf_max_order < 1 || h->opt.bdf_max_order > 2) {
             delete h;

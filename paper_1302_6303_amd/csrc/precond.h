@@ -79,6 +79,7 @@ struct PcArrays {
     int nu_pre = 1, nu_post = 1;
     int fac_pre = 1, fac_post = 0;   // FAC V(m, n)
     int fac_smoother = 0;            // NRD_SMOOTH_RBGS or NRD_SMOOTH_JACOBI
+    bool base_smooth = false;        // base level: level sweeps instead of multigrid
     PT* e2 = nullptr;                // 2 * nl, damped Jacobi with several sweeps
     Clock* clock = nullptr;     // times the base grid's sweeps
 

@@ -878,6 +878,7 @@ void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
     const int ntiles = d.level_tile0[d.nlev];
     k_snapshot<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, u_state, d.z3, Dface,
                                             sigma, d.nl);
+    if (base_smooth) return;                   // no multigrid grids to set up
     for (int g = 1; g <= mg.G; ++g) {
         const PT* Df = (g == 1) ? Dface : mg.Dg[g - 1];
         const int64_t nlf = (g == 1) ? d.nl : mg.len[g - 1];
@@ -1066,7 +1067,10 @@ const PT* PcArrays<PT>::fac(hipStream_t s) const {
     const Dev& d = *D;
     const int L = d.nlev - 1;
     if (L == 0) {
-        vcycle(s);
+        if (base_smooth)
+            smooth_level(s, f, 0, fac_pre);
+        else
+            vcycle(s);
         return e;
     }
     k_fill_t<PT><<<nblocks(2 * d.nl), kBlock, 0, s>>>(u, 2 * d.nl);
@@ -1077,7 +1081,7 @@ const PT* PcArrays<PT>::fac(hipStream_t s) const {
         } else {
             composite_residual(s, lev);     // u was restricted by the last correction
         }
-        if (lev > 0) {
+        if (lev > 0 || base_smooth) {
             smooth_level(s, r, lev, fac_pre);
         } else {
             // base level: multigrid V-cycle with rhs f^0 = r on level 0 (the

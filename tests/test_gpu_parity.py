@@ -183,6 +183,33 @@ def test_precond_parity_fac_jacobi(name, nu):
         assert rel_err(got[sl][mm], ref[sl][mm]) < 1e-10
 
 
+@pytest.mark.parametrize("name,nu", [("uniform16", (1, 0)), ("uniform16", (2, 0)),
+                                     ("amr2", (1, 0)), ("amr3", (2, 1))])
+def test_precond_parity_fac_base_smoothing(name, nu):
+    """FAC whose base level is only smoothed (fac_base = SMOOTH, as in the
+    paper's runs) against the oracle's cycle of the same shape, FP64."""
+    from paper_1302_6303_amd import nrd
+    w = WL[name]()
+    s = system(w, fac_nu=nu, fac_base="smooth")
+    H = make(w, fac_nu_pre=nu[0], fac_nu_post=nu[1], fac_base=nrd.NRD_BASE_SMOOTH)
+    dt = 2e-3
+    H.begin_step([dt])
+    rng = np.random.default_rng(42)
+    u = s.sync(state(s, w) * rng.uniform(0.9, 1.1, 2 * s.nc))
+    wv = np.random.default_rng(8).standard_normal(u.shape)
+    H.precond_setup(native_from_compact(H, u))
+    y = H.native()
+    H.precond_apply(native_from_compact(H, wv), y)
+    got = compact_from_native(H, y)
+    P, _ = s.precond(u, dt)
+    ref = P(wv)
+    m = s.composite
+    n = s.nc
+    for sl in (slice(0, n), slice(n, 2 * n)):
+        mm = m[sl]
+        assert rel_err(got[sl][mm], ref[sl][mm]) < 1e-10
+
+
 def test_precond_parity_noncubic():
     """Preconditioner of three non-cubic problems in one hierarchy (their
     coarsest grids are 2, 3 and 4 grids down; Marshak faces on two sides of

@@ -233,6 +233,26 @@ def test_fac_with_jacobi_smoothing_converges():
         assert r[(1, 0)][f] < 0.7 and r[(2, 1)][f] < 0.7 * r[(1, 0)][f], r
 
 
+def test_fac_base_smoothing_is_weaker_than_the_base_vcycle():
+    """Sec. 4.3: the paper's runs only smooth on the coarsest level.  As a
+    stationary iteration that still converges on two levels, but more
+    slowly than with the multigrid V-cycle on the base level."""
+    w = I.small_amr(8, state="uniform")
+    rv = _fac_contraction(w, [(1, 0)])
+    orig = pc.Snapshot.__init__
+
+    def smooth_init(self, *a, **k):
+        orig(self, *a, **k)
+        self.fac_base = "smooth"
+    pc.Snapshot.__init__ = smooth_init
+    try:
+        rs = _fac_contraction(I.small_amr(8, state="uniform"), [(1, 0)])
+    finally:
+        pc.Snapshot.__init__ = orig
+    for f in (0, 1):
+        assert rv[(1, 0)][f] < rs[(1, 0)][f] < 1.0, (rv, rs)
+
+
 def test_fac_vmn_on_one_level_is_the_base_vcycle():
     """With a single level there are no levels above the base: V(m, n) of
     FAC is one base multigrid V-cycle whatever m and n."""
