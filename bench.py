@@ -263,7 +263,7 @@ PAPER_UNIFORM = {32: (7.68, 2.99, 1334, 1.0), 64: (7.15, 2.96, 3253, 1.0),
                  128: (6.43, 2.61, 8207, 1.0), 256: (6.72, 3.04, 8698, 0.5)}
 
 
-def paper_bench(n, t_final, limiter=0.5, base="mg"):
+def paper_bench(n, t_final, limiter=0.5, base="mg", jvp="analytic"):
     """The paper's model problem on a uniform n^3 grid integrated to t_final
     with BDF2 and PC.4.7 at its tolerance (eps_t = 5e-4 at 32^3, halved per
     doubling), Newton tolerances 1e-12 / 1e-10, FAC V(1,0), mixed precision;
@@ -274,7 +274,8 @@ def paper_bench(n, t_final, limiter=0.5, base="mg"):
     opts = nrd.default_options(precision=nrd.NRD_MIXED, error_estimate=1,
                                newton_rtol=1e-12, newton_atol=1e-10, limiter=limiter,
                                fac_base=(nrd.NRD_BASE_SMOOTH if base == "smooth"
-                                         else nrd.NRD_BASE_MG))
+                                         else nrd.NRD_BASE_MG),
+                               jvp_mode=nrd.NRD_JVP_FD if jvp == "fd" else nrd.NRD_JVP_ANALYTIC)
     H = nrd.Hierarchy(w.problems, w.boxes, opts)
     u = compact_state(w)
     m = H.ncells
@@ -300,7 +301,7 @@ def paper_bench(n, t_final, limiter=0.5, base="mg"):
            "value": round(wall, 3), "unit": "s", "n_gpus": 1, "higher_is_better": False,
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"paper{n}", "cells": n ** 3, "eps_t": eps,
-                      "limiter": limiter,
+                      "limiter": limiter, "jvp": jvp,
                       "solver": "BDF2, PC.4.7, Newton rtol 1e-12 atol 1e-10, FGMRES(30), "
                                 "FAC V(1,0) + " + ("base-level smoothing" if base == "smooth"
                                                     else "MG V(1,1)") + ", mixed precision"},
@@ -554,6 +555,9 @@ def main():
     ap.add_argument("--fac-base", choices=("mg", "smooth"), default="mg",
                     help="paperN workloads: base level of FAC, a multigrid V-cycle (default) "
                          "or only level sweeps (the paper's runs)")
+    ap.add_argument("--jvp", choices=("analytic", "fd"), default="analytic",
+                    help="paperN workloads: Jacobian action, analytic (default) or the "
+                         "paper's Jacobian-free difference quotient")
     ap.add_argument("--t-final", type=float, default=1.0,
                     help="paperN workloads: integrate the model problem to this time")
     ap.add_argument("--fp64-batched", action="store_true",
@@ -576,7 +580,7 @@ def main():
         paper_temporal_bench(limiter=a.limiter)
         return
     if a.workload.startswith("paper"):
-        paper_bench(int(a.workload[5:]), a.t_final, a.limiter, a.fac_base)
+        paper_bench(int(a.workload[5:]), a.t_final, a.limiter, a.fac_base, a.jvp)
         return
     w = workload(a.workload)
     if a.dt_scale != 1.0:

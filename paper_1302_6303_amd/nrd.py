@@ -28,6 +28,7 @@ NRD_FP64, NRD_MIXED = 0, 1
 NRD_BATCHED, NRD_PER_PATCH = 0, 1
 NRD_SMOOTH_RBGS, NRD_SMOOTH_JACOBI = 0, 1
 NRD_BASE_MG, NRD_BASE_SMOOTH = 0, 1
+NRD_JVP_ANALYTIC, NRD_JVP_FD = 0, 1
 NRD_TIMER_RESIDUAL, NRD_TIMER_JVP, NRD_TIMER_PRECOND = 0, 1, 2
 NRD_TIMER_SMOOTH, NRD_TIMER_SMOOTH_ZERO = 3, 4
 
