@@ -321,6 +321,9 @@ def paper_bench(n, t_final, limiter=0.5, base="mg", jvp="analytic"):
 PAPER_SPATIAL_T = (0.04, 0.10, 0.19, 0.25, 0.35, 0.46)
 PAPER_SPATIAL_128 = {"E": (2.38e-2, 1.39e-2, 1.17e-2, 1.11e-2, 1.44e-2, 2.29e-2),
                      "T": (5.53e-3, 4.43e-3, 5.45e-3, 7.63e-3, 1.11e-2, 1.64e-2)}
+# its row 16b1l (uniform 16^3)
+PAPER_SPATIAL_16 = {"E": (6.01e-2, 3.32e-1, 4.55e-1, 4.99e-1, 4.49e-1, 3.77e-1),
+                    "T": (3.15e-2, 1.52e-1, 2.21e-1, 2.32e-1, 2.23e-1, 2.06e-1)}
 # The same for the paper's single-material runs (z = 1 everywhere).
 PAPER_SPATIAL_T_Z1 = (0.05, 0.11, 0.19, 0.27, 0.36, 0.45)
 PAPER_SPATIAL_128_Z1 = {"E": (1.94e-2, 1.30e-2, 1.08e-2, 1.07e-2, 1.06e-2, 9.12e-3),
@@ -350,8 +353,9 @@ def paper_spatial_bench(limiter=0.5, single_material=False):
         H.autotune(None)
         return H, w
 
-    def coarse(x):                    # 256^3 compact (x fastest) -> 128^3 means
-        return x.view(128, 2, 128, 2, 128, 2).mean(dim=(1, 3, 5))
+    def coarse(x, m=128):             # 256^3 compact (x fastest) -> m^3 means
+        r = 256 // m
+        return x.view(m, r, m, r, m, r).mean(dim=(1, 3, 5))
 
     t0 = time.perf_counter()
     H, w = make_h(256, 1)
@@ -367,22 +371,28 @@ def paper_spatial_bench(limiter=0.5, single_material=False):
             if len(dts) % 500 == 0:
                 log(f"256^3 reference: step {len(dts)}, t = {t:.4g}")
         E, T = H.get_fields()
-        ref.append((coarse(E).clone(), coarse(T).clone(), len(dts)))
+        ref.append((coarse(E).clone(), coarse(T).clone(), len(dts),
+                    coarse(E, 16).clone(), coarse(T, 16).clone()))
         log(f"256^3 reference at t = {t:.4g} after {len(dts)} steps")
     del H
     torch.cuda.empty_cache()
-    H, _ = make_h(128, 0)
-    errs = {"E": [], "T": []}
-    k = 0
-    for i, tg in enumerate(times):
-        while k < ref[i][2]:                 # the reference run's steps up to tg
-            H.implicit_step([dts[k]])
-            k += 1
-        t = tg
-        E, T = H.get_fields()
-        for name, a, b in (("E", E, ref[i][0]), ("T", T, ref[i][1])):
-            errs[name].append(float(torch.sqrt(torch.mean((a.view(128, 128, 128) - b) ** 2))))
-        log(f"128^3 at t = {t:.4g}: E error {errs['E'][-1]:.3e}, T error {errs['T'][-1]:.3e}")
+    allerr = {}
+    for m, (iE, iT) in ((128, (0, 1)), (16, (3, 4))):
+        H, _ = make_h(m, 0)
+        errs = {"E": [], "T": []}
+        k = 0
+        for i, tg in enumerate(times):
+            while k < ref[i][2]:             # the reference run's steps up to tg
+                H.implicit_step([dts[k]])
+                k += 1
+            E, T = H.get_fields()
+            for name, a, b in (("E", E, ref[i][iE]), ("T", T, ref[i][iT])):
+                errs[name].append(float(torch.sqrt(torch.mean((a.view(m, m, m) - b) ** 2))))
+            log(f"{m}^3 at t = {tg:.4g}: E error {errs['E'][-1]:.3e}, "
+                f"T error {errs['T'][-1]:.3e}")
+        allerr[m] = errs
+        del H
+    errs = allerr[128]
     out = {"metric": "L2 error of uniform 128^3 against 256^3 with the same steps, paper "
                      "model problem",
            "value": errs["E"][-1], "unit": "L2 (E, last time)", "n_gpus": 1,
@@ -392,6 +402,8 @@ def paper_spatial_bench(limiter=0.5, single_material=False):
                       "steps": len(dts), "eps_t_256": eps},
            "errors": {kk: [round(v, 6) for v in vv] for kk, vv in errs.items()},
            "paper_128b1l": paper,
+           "errors_16": {kk: [round(v, 6) for v in vv] for kk, vv in allerr[16].items()},
+           "paper_16b1l": None if single_material else PAPER_SPATIAL_16,
            "wall_s": round(time.perf_counter() - t0, 1)}
     print(json.dumps(out), flush=True)
 
