@@ -419,7 +419,7 @@ PAPER_TEMPORAL = {2e-4: {"E": (4.53e-5, 3.93e-5, 2.87e-5, 2.47e-5, 2.36e-5),
                          "T": (1.20e-6, 1.00e-6, 1.00e-6, 9.00e-7, 9.00e-7)}}
 
 
-def paper_temporal_bench(n=128, dt_ref=2.5e-5, limiter=0.5):
+def paper_temporal_bench(n=128, dt_ref=2.5e-5, limiter=0.5, ramp=False):
     """Temporal error of fixed-step BDF2 (first step BDF1) on the paper's
     model problem, uniform n^3: runs with the table's steps against a run
     with dt_ref, volume-weighted L2 norms at the table's times."""
@@ -439,6 +439,11 @@ def paper_temporal_bench(n=128, dt_ref=2.5e-5, limiter=0.5):
     def run(dt):
         H.set_fields(E0, T0, z)                # resets the history: BDF1 first
         out, k = [], 0
+        if ramp and dt > dt_ref:
+            # first interval as dt/4 (BDF1), dt/4, dt/2: step ratios 1 and 2
+            for d in (0.25 * dt, 0.25 * dt, 0.5 * dt):
+                H.implicit_step([d])
+            k = 1
         for tg in PAPER_TEMPORAL_T:
             kk = int(round(tg / dt))
             while k < kk:
@@ -463,6 +468,7 @@ def paper_temporal_bench(n=128, dt_ref=2.5e-5, limiter=0.5):
            "value": errs[f"{min(PAPER_TEMPORAL):g}"]["E"][-1], "unit": "L2 (E, smallest step)",
            "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "paper-temporal", "cells": n ** 3, "limiter": limiter,
+                      "ramp": ramp,
                       "times": list(PAPER_TEMPORAL_T), "dt_ref": dt_ref},
            "errors": errs,
            "paper": {f"{k:g}": v for k, v in PAPER_TEMPORAL.items()},
@@ -570,6 +576,8 @@ def main():
     ap.add_argument("--jvp", choices=("analytic", "fd"), default="analytic",
                     help="paperN workloads: Jacobian action, analytic (default) or the "
                          "paper's Jacobian-free difference quotient")
+    ap.add_argument("--ramp", action="store_true",
+                    help="paper-temporal: take each run's first interval as dt/4, dt/4, dt/2")
     ap.add_argument("--t-final", type=float, default=1.0,
                     help="paperN workloads: integrate the model problem to this time")
     ap.add_argument("--fp64-batched", action="store_true",
@@ -589,7 +597,7 @@ def main():
         paper_spatial_bench(a.limiter, a.workload.endswith("z1"))
         return
     if a.workload == "paper-temporal":
-        paper_temporal_bench(limiter=a.limiter)
+        paper_temporal_bench(limiter=a.limiter, ramp=a.ramp)
         return
     if a.workload.startswith("paper"):
         paper_bench(int(a.workload[5:]), a.t_final, a.limiter, a.fac_base, a.jvp)
