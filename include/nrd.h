@@ -152,7 +152,7 @@ typedef struct {
  * limiter 1/2 (the printed pair), paper P2, rtol 1e-8, atol 1e-14, 20 Newton iterations,
  * GMRES(30) with 10 restarts, FAC V(1,0), base multigrid V(1,1),
  * staged-plane stencil, BDF2, no error
- * estimate, eta_E = 1e-5 (the initial energy density of Sec. 5), eta_T =
+ * estimate, eta_E = 1e-5 (the initial energy density of Sec. 6), eta_T =
  * 1e-5^(1/4). */
 void nrd_default_options(nrd_options* opt);
 
@@ -172,7 +172,7 @@ typedef struct {
                                     -1 otherwise                             */
 } nrd_step_stats;
 
-/* Time-step control (Sec. 2, eqs. odets, pc47, bdf2le). */
+/* Time-step control (Sec. 3.4-3.5, eqs. odets, pc47, bdf2le). */
 enum { NRD_CTL_PC47 = 0, NRD_CTL_EPS = 1 };
 typedef struct {
     double eps;                  /* target local error eps_t                 */
@@ -301,9 +301,11 @@ nrd_status nrd_dot(nrd_hierarchy* h, const double* dev_x, const double* dev_y,
  * run) and the fastest shape is used for that class from then on; results
  * do not change (every shape evaluates the same face and cell formulas on
  * the same operands).  cache_path (may be NULL) is a text file of earlier
- * choices, one line "arch v<variant> <nx>x<ny>x<nz> <planes> <run> <us>" per
- * class; classes found for this device architecture and variant are not
- * timed again, newly timed ones are appended.  *timed_classes (may be NULL)
+ * choices, one line "arch v<variant> <fmt> <nx>x<ny>x<nz> <planes> <run> <us>"
+ * per class (<fmt> names the tile constants of the build that wrote it);
+ * classes found for this device architecture, variant and format whose shape
+ * is one this build would try are not timed again (other lines are ignored),
+ * newly timed ones are appended.  *timed_classes (may be NULL)
  * returns how many classes were timed.  Needs a bound workspace and
  * nrd_set_fields (NRD_ESTATE otherwise); synchronises the stream; drops
  * captured graphs.  Variant 0 has nothing to tune (returns NRD_OK). */

@@ -17,8 +17,9 @@ Definitions (paper Sec. 3.1-3.3 and 4.1):
 Readings (the paper is ambiguous):
 * the printed face pair (D_r, then 2 D_r / (1 + D_r g)) is read as the true
   harmonic mean D_h = 2 T_f^3 / (3 (z_a^3 + z_b^3)) limited as
-  D_h / (1 + lam D_h g) with lam = 1 (the Wilson form of Sec. 3.1); lam = 1/2
-  reproduces the printed pair literally;
+  D_h / (1 + lam D_h g); the default reading (System, lam = 1/2) is the
+  printed pair literally, lam = 1 gives the Wilson form of Sec. 3.1 (the
+  functions below take lam explicitly);
 * face D_T = kappa T_f^(5/2) with the arithmetic face temperature;
 * Robin ghost from the discrete boundary relation, giving the inflow flux
   q = 2 D_b (4 R - E_c) / (4 D_b + h) into the boundary cell;

@@ -332,7 +332,7 @@ class Stepper:
 
 
 # ---------------------------------------------------------------------------
-# time-step control (Sec. 2: eqs. odets, pc47, leapfrog, bdf2le)
+# time-step control (Sec. 3.4-3.5: eqs. odets, pc47, leapfrog, bdf2le)
 # ---------------------------------------------------------------------------
 
 def bdf2_error_estimate(u_new, u_pred, a):
@@ -344,7 +344,7 @@ def bdf2_error_estimate(u_new, u_pred, a):
 def scaled_max_norm(sys: System, e, u, eta_E, eta_T):
     """max(max |e_E / (E + eta_E)|, max |e_T / (T + eta_T)|) over composite
     cells, u the solution the error belongs to (the scaled max norm of
-    Sec. 2)."""
+    Sec. 3.5)."""
     n = sys.nc
     m = sys.composite[:n]
     eE, eT, E, T = e[:n], e[n:], u[:n], u[n:]

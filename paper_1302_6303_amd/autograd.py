@@ -18,6 +18,11 @@ import torch
 class RadDiffEvolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, z, hier, E0, T0, dt, nsteps, ckpt_every):
+        if hier.opt.bdf_max_order != 1:
+            # the adjoint differentiates backward-Euler steps: a BDF2 forward
+            # trajectory would get the gradient of another trajectory
+            raise ValueError("RadDiffEvolve needs a hierarchy created with "
+                             "bdf_max_order = 1")
         z = z.detach().contiguous()
         hier.set_fields(E0, T0, z)
         for _ in range(nsteps):
@@ -36,4 +41,4 @@ class RadDiffEvolve(torch.autograd.Function):
         hier.set_fields(E0, T0, z)
         gz = hier.adjoint_run([dt] * hier.nprob, nsteps, every,
                               grad_E.detach().to(torch.float64).contiguous())
-        return gz, None, None, None, None, None, None
+        return gz.view_as(z), None, None, None, None, None, None

@@ -86,6 +86,8 @@ bool patch_planes(const PatchInfo& p, int32_t b, int32_t kc, int32_t run, int32_
                   std::vector<STile>& out) {
     const int32_t plane = p.n[0] * p.n[1];
     const int32_t ch = std::max(1, kc);
+    // a tile's cells are owned one per thread of a 256-thread workgroup
+    if (run <= 0 || run > kStageCells) return false;
     int32_t r = run;
     if (max_span > 0) {
         // shorten the runs of this patch until every staged slice fits

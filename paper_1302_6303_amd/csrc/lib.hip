@@ -1286,9 +1286,8 @@ static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, in
     if (dJdE) {
         unpack(h->D, s, h->at<int64_t>(h->o.coff), dJdE, rhs, 1, t.ncells);
     } else {
-        std::vector<double> ones(t.ncells, 1.0);
-        // build a compact vector of ones in gz scratch region via host upload
-        HIPCHK(hipMemcpyAsync(gz, ones.data(), 8 * t.ncells, hipMemcpyHostToDevice, s));
+        // a compact vector of ones, built on the device in gz (overwritten below)
+        fill_native(s, gz, t.ncells, 1.0);
         unpack(h->D, s, h->at<int64_t>(h->o.coff), gz, rhs, 1, t.ncells);
     }
     fill_native(s, lam, NL, 0.0);
@@ -1814,20 +1813,28 @@ nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed
         cls[k].push_back(b);
     }
     const std::string arch = device_arch();
+    // cache format tag: the tile constants the cached shapes were chosen with
+    const std::string cache_fmt =
+        "f" + std::to_string(kStageCells) + "x" + std::to_string(kStageLen) + "b" +
+        std::to_string(kBlock);
     std::map<ClassKey, std::pair<int32_t, int32_t>> pick;
     if (cache_path) {
         std::ifstream in(cache_path);
         std::string line;
         while (std::getline(in, line)) {
             std::istringstream ls(line);
-            std::string a, v, dims;
+            std::string a, v, fmt, dims;
             int32_t kc = 0, run = 0;
-            if (!(ls >> a >> v >> dims >> kc >> run)) continue;
+            if (!(ls >> a >> v >> fmt >> dims >> kc >> run)) continue;
             ClassKey k;
-            if (a != arch || v != "v" + std::to_string(var) ||
-                std::sscanf(dims.c_str(), "%dx%dx%d", &k.n[0], &k.n[1], &k.n[2]) != 3 ||
-                kc <= 0 || run <= 0)
+            if (a != arch || v != "v" + std::to_string(var) || fmt != cache_fmt ||
+                std::sscanf(dims.c_str(), "%dx%dx%d", &k.n[0], &k.n[1], &k.n[2]) != 3)
                 continue;
+            // only shapes this build would itself try: a stale or edited line
+            // can never give a tile more cells than a workgroup holds
+            bool known = false;
+            for (auto [ckc, crun] : cand) known |= (ckc == kc && crun == run);
+            if (!known) continue;
             pick[k] = {kc, run};
         }
     }
@@ -1910,7 +1917,8 @@ nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed
         pick[kv.first] = choice;
         if (timed_classes) ++*timed_classes;
         if (out)
-            out << arch << " v" << var << " " << kv.first.n[0] << "x" << kv.first.n[1] << "x"
+            out << arch << " v" << var << " " << cache_fmt << " " << kv.first.n[0] << "x"
+                << kv.first.n[1] << "x"
                 << kv.first.n[2] << " " << choice.first << " " << choice.second << " "
                 << best * 1e3 << "\n";
     }

@@ -18,7 +18,7 @@ Conventions
   side, ``s = 1`` the high side.  ``bc_E[f]`` is 0 for a zero-flux (Neumann)
   face and 1 for a Marshak/Robin face with incoming value ``robin_R[f]``.
 
-The workloads follow the paper's Marshak test problem (Sec. 5): E0 = 1e-5,
+The workloads follow the paper's Marshak test problem (Sec. 6): E0 = 1e-5,
 T0 = E0**0.25, kappa = 0.01, z = 10 inside axis-aligned material boxes and 1
 elsewhere, Robin inflow R = 1 on the x = 0 face.
 """
@@ -332,14 +332,14 @@ def uniform_workload(name, n, zfun, dt, nsteps, rng=None, state="uniform",
                     bdf1_only)
 
 
-# The three z = 10 boxes of the paper's model problem (Sec. 5), unit cube.
+# The three z = 10 boxes of the paper's model problem (Sec. 6), unit cube.
 PAPER_BOXES = [((0.0625, 0.375, 0.375), (0.2, 0.625, 0.625), 10.0),
                ((0.125, 0.0, 0.0), (0.375, 1.0, 0.125), 10.0),
                ((0.125, 0.0, 0.875), (0.375, 1.0, 1.0), 10.0)]
 
 
 def paper_marshak(n=32, dt=1e-5, single_material=False):
-    """The paper's model problem (Sec. 5) on one uniform n^3 grid: z = 10 in
+    """The paper's model problem (Sec. 6) on one uniform n^3 grid: z = 10 in
     its three boxes and 1 elsewhere (z = 1 everywhere for the paper's
     single-material accuracy runs), E = E0 and T = T0 everywhere, Robin
     faces for E at x = 0 (R = 1) and x = 1 (R = 0), zero flux elsewhere;

@@ -175,6 +175,26 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
 
 
+def _vec(t, n, name, optional=False):
+    """Device pointer of a float64 CUDA tensor of exactly n contiguous
+    values.  The library reads and writes n values through the pointer, so
+    a tensor of another type, device, length or stride is refused here."""
+    if t is None:
+        if optional:
+            return C.c_void_p(0)
+        raise ValueError(f"{name}: a tensor is required")
+    import torch
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected torch.float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor is not contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name}: {t.numel()} values, expected {n}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: tensor on {t.device}, expected a CUDA device")
+    return C.c_void_p(t.data_ptr())
+
+
 def _dt(values):
     return (C.c_double * len(values))(*[float(v) for v in values])
 
@@ -216,11 +236,21 @@ class Hierarchy:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        if h is None or not h.value:
+            return
+        self.h = None
+        try:
             nrd_hierarchy_destroy(h)
-            self.h = None
+        except Exception:       # interpreter shutdown: module globals may be gone
+            pass
 
     # -- vectors ----------------------------------------------------------
+    def _nat(self, t, name):
+        return _vec(t, 2 * self.native_len, name)
+
+    def _cmp(self, t, name):
+        return _vec(t, 2 * self.ncells, name)
+
     def native(self):
         return self.torch.zeros(2 * self.native_len, dtype=self.torch.float64,
                                 device=self.device)
@@ -231,44 +261,46 @@ class Hierarchy:
 
     def pack(self, native, out=None):
         out = self.compact() if out is None else out
-        check(nrd_pack(self.h, _ptr(native), _ptr(out)))
+        check(nrd_pack(self.h, self._nat(native, "native"), self._cmp(out, "out")))
         return out
 
     def unpack(self, compact, out=None):
         out = self.native() if out is None else out
-        check(nrd_unpack(self.h, _ptr(compact), _ptr(out)))
+        check(nrd_unpack(self.h, self._cmp(compact, "compact"), self._nat(out, "out")))
         return out
 
     # -- calls ------------------------------------------------------------
     def set_fields(self, E, T, z):
-        check(nrd_set_fields(self.h, _ptr(E), _ptr(T), _ptr(z)))
+        n = self.ncells
+        check(nrd_set_fields(self.h, _vec(E, n, "E"), _vec(T, n, "T"), _vec(z, n, "z")))
 
     def get_fields(self):
         E = self.compact(1)
         T = self.compact(1)
-        check(nrd_get_fields(self.h, _ptr(E), _ptr(T)))
+        check(nrd_get_fields(self.h, _vec(E, self.ncells, "E"), _vec(T, self.ncells, "T")))
         return E, T
 
     def begin_step(self, dt: Sequence[float]):
         check(nrd_begin_step(self.h, _dt(dt)))
 
     def residual(self, u, F):
-        check(nrd_residual(self.h, _ptr(u), _ptr(F)))
+        check(nrd_residual(self.h, self._nat(u, "u"), self._nat(F, "F")))
         return F
 
     def jvp(self, u, v, Jv):
-        check(nrd_jvp(self.h, _ptr(u), _ptr(v), _ptr(Jv)))
+        check(nrd_jvp(self.h, self._nat(u, "u"), self._nat(v, "v"), self._nat(Jv, "Jv")))
         return Jv
 
     def precond_setup(self, u):
-        check(nrd_precond_setup(self.h, _ptr(u)))
+        check(nrd_precond_setup(self.h, self._nat(u, "u")))
 
     def precond_apply(self, w, y):
-        check(nrd_precond_apply(self.h, _ptr(w), _ptr(y)))
+        check(nrd_precond_apply(self.h, self._nat(w, "w"), self._nat(y, "y")))
         return y
 
     def vjp(self, u, lam, JTl, gz=None):
-        check(nrd_vjp(self.h, _ptr(u), _ptr(lam), _ptr(JTl), _ptr(gz)))
+        check(nrd_vjp(self.h, self._nat(u, "u"), self._nat(lam, "lam"), self._nat(JTl, "JTl"),
+                      _vec(gz, self.ncells, "gz", optional=True)))
         return JTl, gz
 
     def implicit_step(self, dt: Sequence[float], raise_on_fail=True):
@@ -296,7 +328,9 @@ class Hierarchy:
 
     def adjoint_run(self, dt, nsteps, ckpt_every, dJdE=None):
         gz = self.compact(1)
-        check(nrd_adjoint_run(self.h, _dt(dt), nsteps, ckpt_every, _ptr(dJdE), _ptr(gz)))
+        check(nrd_adjoint_run(self.h, _dt(dt), nsteps, ckpt_every,
+                              _vec(dJdE, self.ncells, "dJdE", optional=True),
+                              _vec(gz, self.ncells, "gz")))
         return gz
 
     def autotune(self, cache_path: Optional[str] = None) -> int:
@@ -309,7 +343,7 @@ class Hierarchy:
 
     def dot(self, x, y) -> List[float]:
         out = (C.c_double * self.nprob)()
-        check(nrd_dot(self.h, _ptr(x), _ptr(y), out))
+        check(nrd_dot(self.h, self._nat(x, "x"), self._nat(y, "y"), out))
         return list(out)
 
     def timer_enable(self, on=True):

@@ -115,3 +115,39 @@ def test_wide_patch_is_accepted_with_the_default_stencil():
     box = I.Box(0, 0, (0, 0, 0), (256, 256, 256))
     H = _create([prob], [box])
     assert H.ncells == 256 ** 3
+
+
+def test_binding_refuses_tensors_the_library_cannot_read():
+    """Every device pointer the binding hands over must address exactly the
+    float64 values the call reads: other dtypes, lengths, strides or a host
+    tensor are refused before the library is called."""
+    import torch
+    from paper_1302_6303_amd import nrd
+    w = I.marshak_single(8)
+    H = _create(w.problems, w.boxes)
+    n = H.ncells
+    good = torch.zeros(n, dtype=torch.float64)
+    with pytest.raises(ValueError, match="dtype"):
+        H.set_fields(good.float(), good, good)
+    with pytest.raises(ValueError, match="CUDA"):
+        H.set_fields(good, good, good)
+    with pytest.raises(ValueError, match="dtype"):
+        H.residual(torch.zeros(2 * H.native_len, dtype=torch.float32),
+                   torch.zeros(2 * H.native_len, dtype=torch.float32))
+    with pytest.raises(ValueError, match="contiguous"):
+        nrd._vec(torch.zeros(2 * n, dtype=torch.float64)[::2], n, "z")
+    with pytest.raises(ValueError, match="values"):
+        nrd._vec(torch.zeros(n - 1, dtype=torch.float64), n, "z")
+
+
+def test_autograd_refuses_a_bdf2_hierarchy():
+    """The adjoint differentiates backward-Euler steps; a hierarchy left at
+    the default BDF2 order is refused instead of returning the gradient of
+    another trajectory."""
+    import torch
+    from paper_1302_6303_amd.autograd import RadDiffEvolve
+    w = I.marshak_single(8)
+    H = _create(w.problems, w.boxes)
+    z = torch.ones(H.ncells, dtype=torch.float64, requires_grad=True)
+    with pytest.raises(ValueError, match="bdf_max_order"):
+        RadDiffEvolve.apply(z, H, z.detach(), z.detach(), 1e-3, 2, 1)

@@ -62,3 +62,31 @@ def test_tuned_solver_steps_match_untuned():
         outs.append((E.cpu().numpy(), T.cpu().numpy()))
     np.testing.assert_array_equal(outs[0][0], outs[1][0])
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_cache_lines_with_unknown_shapes_are_ignored(tmp_path):
+    """A stale or edited cache line (a plane run longer than a workgroup
+    holds, an unknown plane count, another format tag) is never applied: the
+    class is timed afresh and the results stay bitwise the defaults'."""
+    w = _workload()
+    classes = sorted({tuple(int(x) for x in b.shape) for b in w.boxes})
+    H = make(w, stencil=3)
+    before = _outputs(H, w)
+    # learn this build's format tag and architecture from a real cache line
+    good = str(tmp_path / "good.txt")
+    H.autotune(good)
+    arch, var, fmt = open(good).read().split("\n")[0].split()[:3]
+    bad = str(tmp_path / "bad.txt")
+    with open(bad, "w") as f:
+        for i, c in enumerate(classes):
+            dims = "x".join(str(v) for v in c)
+            if i % 3 == 0:
+                f.write(f"{arch} {var} {fmt} {dims} 16 1024 1.0\n")   # run > 256
+            elif i % 3 == 1:
+                f.write(f"{arch} {var} {fmt} {dims} 5 256 1.0\n")     # unknown planes
+            else:
+                f.write(f"{arch} {var} f0x0b0 {dims} 16 256 1.0\n")   # other format
+    H2 = make(w, stencil=3)
+    assert H2.autotune(bad) == len(classes)
+    for a, b in zip(before, _outputs(H2, w)):
+        np.testing.assert_array_equal(a, b)

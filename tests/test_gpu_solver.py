@@ -276,7 +276,7 @@ def test_graph_captured_adjoint_matches_eager():
 
 
 def test_paper_model_problem_step_count_matches_the_paper():
-    """The paper's model problem (Sec. 5) on the uniform 32^3 grid with its
+    """The paper's model problem (Sec. 6) on the uniform 32^3 grid with its
     solver settings (BDF2, PC.4.7 at eps_t = 5e-4, Newton 1e-12 / 1e-10)
     integrated to t = 1 takes the paper's number of time steps (1334 in
     its Table ndt, Levels = 1) within 5 %."""

@@ -39,7 +39,7 @@ def test_workloads_are_seeded_and_nested():
 
 
 def test_paper_model_problem_layout():
-    """The paper's model problem (Sec. 5): z = 10 exactly on the cells whose
+    """The paper's model problem (Sec. 6): z = 10 exactly on the cells whose
     centres lie in its three boxes, Robin faces at x = 0 and x = 1 only."""
     n = 32
     w = I.paper_marshak(n)

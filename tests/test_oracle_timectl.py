@@ -1,4 +1,4 @@
-"""Time-step control of the oracle (Sec. 2: leapfrog predictor, BDF2 local
+"""Time-step control of the oracle (Sec. 3.4-3.5: leapfrog predictor, BDF2 local
 error estimate, scaled max norm, EPS and PC.4.7 controllers) against
 properties the paper and the mathematics fix."""
 import numpy as np
