@@ -36,7 +36,12 @@ Readings (the paper is silent or terse):
 Parity status: P2 pinned by numpy.linalg.solve; the level/MG operators by
 assembled sparse matrices (symmetry, the 7-point Laplacian special case,
 exact solve when the bottom grid is the whole grid) and by multigrid
-contraction; FAC by stationary convergence on two-level problems.
+contraction; the composite operator (Marshak linearisation, coarse-fine
+treatment) by the analytic Jacobian's diffusion part where freezing D is
+exact; red-black sweeps and FAC cycles by bitwise invariance under
+splitting a level's patches into siblings; FAC by stationary convergence on
+two-level problems and by a contraction that stays level independent on
+2-4 nested levels (the prolongation chain to every finer level).
 """
 from __future__ import annotations
 
