@@ -373,6 +373,67 @@ def residual_scale(H, E, T, z, bE, bT, dt, c0, lam=1.0):
     return sE, sT
 
 
+def jvp_scale(H, E, T, z, vE, vT, dt, c0, lam=1.0):
+    """Per-cell sum of magnitudes of the terms entering J(u) v (the scale
+    for entries whose terms cancel): every face's tangent flux split into
+    its products, the Marshak tangent into its two terms, the coupling
+    tangent into its E and T parts."""
+    Eg, Tg = ghosted_state(H, E, T)
+    dEg, dTg = ghosted_state(H, vE, vT)
+    z3 = ghosted_z3(H, z)
+    sE, sT = [], []
+    for p in H.patches:
+        q = p.pid
+        h = H.h(p.level)
+        fl = np.zeros(tuple(int(v) for v in p.n))
+        flT = np.zeros_like(fl)
+        for d in range(3):
+            lo, up = face_slices(d, p.n)
+            Ea, Eb, Ta, Tb = Eg[q][lo], Eg[q][up], Tg[q][lo], Tg[q][up]
+            Tf = 0.5 * (Ta + Tb)
+            dTf = 0.5 * (np.abs(dTg[q][lo]) + np.abs(dTg[q][up]))
+            Dh = 2.0 * Tf**3 / (3.0 * (z3[q][lo] + z3[q][up]))
+            S = Ea + Eb
+            g = np.abs(Eb - Ea) / (0.5 * h[d] * S)
+            dS = np.abs(dEg[q][lo]) + np.abs(dEg[q][up])
+            dg = dS / (0.5 * h[d] * S) + g * dS / S
+            den = 1.0 + lam * Dh * g
+            dDE = (3.0 * Dh * dTf / Tf + lam * Dh**2 * dg) / den**2
+            pe = (dDE * np.abs(Eb - Ea) + Dh / den * dS) / h[d]
+            DT = H.kappa * Tf**2.5
+            pt = (2.5 * DT * dTf / Tf * np.abs(Tb - Ta)
+                  + DT * (np.abs(dTg[q][lo]) + np.abs(dTg[q][up]))) / h[d]
+            n = int(p.n[d])
+            a = [slice(None)] * 3
+            b = [slice(None)] * 3
+            a[d] = slice(0, n)
+            b[d] = slice(1, n + 1)
+            fl += (pe[tuple(a)] + pe[tuple(b)]) / h[d]
+            flT += (pt[tuple(a)] + pt[tuple(b)]) / h[d]
+            for s_ in (0, 1):                       # Marshak tangent terms
+                if not (is_physical(H, p, d, s_) and H.bc_E[2 * d + s_] == 1):
+                    continue
+                c = cell_layer(d, 0 if s_ == 0 else n - 1)
+                Ec, Tc, zc = Eg[q][c], Tg[q][c], z3[q][c]
+                Db = robin_D(Tc, zc)
+                dn = 4.0 * Db + h[d]
+                m = (2.0 * Db / dn * np.abs(dEg[q][c])
+                     + 2.0 * (4.0 * H.robin_R[2 * d + s_] + Ec) * h[d] / dn**2
+                     * 3.0 * Db * np.abs(dTg[q][c]) / Tc) / h[d]
+                fs = [slice(None)] * 3
+                fs[d] = 0 if s_ == 0 else n - 1
+                fl[tuple(fs)] += m
+        e = Eg[q][1:-1, 1:-1, 1:-1]
+        t = Tg[q][1:-1, 1:-1, 1:-1]
+        de = np.abs(dEg[q][1:-1, 1:-1, 1:-1])
+        dtt = np.abs(dTg[q][1:-1, 1:-1, 1:-1])
+        zz = z3[q][1:-1, 1:-1, 1:-1]
+        cpl = zz * ((1.0 + 3.0 * e / t**4) * dtt + de / t**3)
+        sE.append(np.abs(c0) * de + dt * (fl + cpl))
+        sT.append(np.abs(c0) * dtt + dt * (flT + cpl))
+    return sE, sT
+
+
 # ---------------------------------------------------------------------------
 # analytic Jacobian action
 # ---------------------------------------------------------------------------
@@ -500,12 +561,20 @@ def _face_partials(Ea, Eb, Ta, Tb, z3a, z3b, h, kappa, lam):
     return P
 
 
-def vjp(H, E, T, z, lE, lT, dt, c0, lam=1.0):
+def vjp(H, E, T, z, lE, lT, dt, c0, lam=1.0, magnitude=False):
     """lambda^T dF/du (E and T parts) and lambda^T dF/dz (per cell) for a
     single-level hierarchy.  Ghost values are copies (physical or sibling),
-    so their sensitivities are scattered back to the copied cells."""
+    so their sensitivities are scattered back to the copied cells.
+
+    magnitude=True returns instead, per entry, the sum of the magnitudes of
+    the terms that entry adds up (every product and difference taken in
+    absolute values): the scale of its rounding error."""
     if H.nlev != 1:
         raise NotImplementedError("transpose on refined hierarchies")
+    A = np.abs if magnitude else (lambda x: x)
+    if magnitude:
+        lE = [np.abs(a) for a in lE]
+        lT = [np.abs(a) for a in lT]
     Eg, Tg = ghosted_state(H, E, T)
     zg = H.from_interior(z)
     H.fill_ghosts([zg])
@@ -524,8 +593,10 @@ def vjp(H, E, T, z, lE, lT, dt, c0, lam=1.0):
             lo, up = face_slices(d, p.n)
             P = _face_partials(Eg[q][lo], Eg[q][up], Tg[q][lo], Tg[q][up],
                                z3[q][lo], z3[q][up], h[d], H.kappa, lam)
-            muE = dt * (lEg[up] - lEg[lo]) / h[d]
-            muT = dt * (lTg[up] - lTg[lo]) / h[d]
+            sgn = 1.0 if magnitude else -1.0
+            muE = dt * (lEg[up] + sgn * lEg[lo]) / h[d]
+            muT = dt * (lTg[up] + sgn * lTg[lo]) / h[d]
+            P = {k: A(v) for k, v in P.items()}
             for s in (0, 1):                       # physical faces: no flux
                 if is_physical(H, p, d, s):
                     fs = face_index(d, 0 if s == 0 else int(p.n[d]))
@@ -545,21 +616,22 @@ def vjp(H, E, T, z, lE, lT, dt, c0, lam=1.0):
                 Db = robin_D(Tc, zc)
                 den = 4.0 * Db + h[d]
                 R = H.robin_R[2 * d + s]
-                dq_dE = -2.0 * Db / den
-                dq_dDb = 2.0 * (4.0 * R - Ec) * h[d] / den**2
+                dq_dE = A(-2.0 * Db / den)
+                dq_dDb = A(2.0 * (4.0 * R - Ec) * h[d] / den**2)
                 # F_c gets -dt * q / h whichever side the face is on
-                w = -dt * lEg[c] / h[d]
+                w = A(-dt * lEg[c] / h[d])
                 aE[q][c] += w * dq_dE
                 aT[q][c] += w * dq_dDb * 3.0 * Db / Tc
-                aZ[q][c] += w * dq_dDb * (-Db / zc)
+                aZ[q][c] += w * dq_dDb * A(-Db / zc)
         # cell terms
         e = Eg[q][1:-1, 1:-1, 1:-1]
         t = Tg[q][1:-1, 1:-1, 1:-1]
         zz = z3[q][1:-1, 1:-1, 1:-1]
-        dS_dE = -zz / t**3
+        dS_dE = A(-zz / t**3)
         dS_dT = zz * (1.0 + 3.0 * e / t**4)
-        dS_dz = t - e / t**3
-        x = lT[q] - lE[q]                          # F_E has -dt S, F_T has +dt S
+        dS_dz = (t + e / t**3) if magnitude else (t - e / t**3)
+        # F_E has -dt S, F_T has +dt S
+        x = (lT[q] + lE[q]) if magnitude else (lT[q] - lE[q])
         aE[q][1:-1, 1:-1, 1:-1] += c0 * lE[q] + dt * x * dS_dE
         aT[q][1:-1, 1:-1, 1:-1] += c0 * lT[q] + dt * x * dS_dT
         aZ[q][1:-1, 1:-1, 1:-1] += dt * x * dS_dz

@@ -1,8 +1,9 @@
 """HIP path versus the CPU oracle through the C ABI.
 
 Tolerances (float64 operators): residual / Jacobian action / transpose
-1e-12 relative normwise per field and 1e-12 of the per-cell term magnitude
-per entry; preconditioner 1e-10 normwise (dense bottom solve and operation
+1e-12 relative normwise per field and, per entry, 1e-12 of the sum of the
+magnitudes of the terms that entry adds up (oracle residual_scale,
+jvp_scale, vjp(magnitude=True)); preconditioner 1e-10 normwise (dense bottom solve and operation
 order differ); implicit steps 1e-8 relative per field with both sides
 converged to Newton rtol 1e-10.
 """
@@ -109,6 +110,11 @@ def test_jvp_parity(name, stencil):
     n = s.nc
     for sl in (slice(0, n), slice(n, 2 * n)):
         assert rel_err(got[sl], ref[sl]) < 1e-12
+    E, T = s.split(u)
+    vE, vT = s.split(v)
+    sE, sT = ops.jvp_scale(s.H, E, T, s.z, vE, vT, dt, 1.0, s.lam)
+    scale = s.join(sE, sT)
+    assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-300)
 
 
 @pytest.mark.parametrize("name", list(WL))
@@ -251,6 +257,13 @@ def test_vjp_parity(name):
     for sl in (slice(0, n), slice(n, 2 * n)):
         assert rel_err(got[sl], ref[sl]) < 1e-12
     assert rel_err(to_host(gz), refz) < 1e-12
+    E, T = s.split(u)
+    lE, lT = s.split(lam)
+    mE, mT, mz = ops.vjp(s.H, E, T, s.z, lE, lT, dt, 1.0, s.lam, magnitude=True)
+    scale = s.join(mE, mT)
+    assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-300)
+    zscale = np.concatenate([a.ravel(order="F") for a in mz])
+    assert np.all(np.abs(to_host(gz) - refz) <= 1e-12 * zscale + 1e-300)
 
 
 @pytest.mark.parametrize("name", ["uniform16", "amr2"])
