@@ -294,6 +294,22 @@ nrd_status nrd_adjoint_run(nrd_hierarchy* h, const double* dt, int32_t nsteps,
 nrd_status nrd_dot(nrd_hierarchy* h, const double* dev_x, const double* dev_y,
                    double* out);
 
+/* For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops): nrd_dot's inner products <x, y>
+ * per problem written to dev_out (device, nprob doubles) on the library
+ * stream, without synchronising.  Its per-tile partial sums live in a fixed
+ * device array of 32768 doubles (256 KiB) that the library holds on every
+ * GPU it runs on until the process ends, not in the workspace; the
+ * hierarchy still needs its bound workspace (tables).  Same kernels and
+ * summation order as nrd_dot, so the results are equal bit for bit.
+ * NRD_EINVAL if the hierarchy has more reduction tiles (runs of at most
+ * 2048 cells of one patch) than the array holds, or for a NULL argument.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams or host threads) race and must be serialised by the
+ * caller. */
+nrd_status nrd_dot_noalloc(nrd_hierarchy* h, const double* dev_x,
+                           const double* dev_y, double* dev_out);
+
 /* Tile-shape tuner of the batching machinery (patch table + tile lists).
  * For every patch-size class (interior extents nx x ny x nz) the residual
  * kernel is timed on that class's patches with each candidate plane-tile

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <tuple>
 #include <string>
@@ -43,6 +44,34 @@ nrd_status fail(nrd_status st, const std::string& m) {
         nrd_status r_ = (x);           \
         if (r_ != NRD_OK) return r_;   \
     } while (0)
+
+// Partial sums of nrd_dot_noalloc: a fixed device array instead of workspace
+// memory, one per GPU for the life of the process.  Host code never uses
+// the symbol itself (in host code it is not the device address); it uses the
+// address resolved per device by scratch_ptr().
+constexpr int32_t kScratchTiles = 32768;
+static __device__ __align__(256) double scratch[kScratchTiles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, resolved once per device.
+hipError_t scratch_ptr(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
 
 struct Bump {
     size_t off = 0;
@@ -100,6 +129,7 @@ struct nrd_hierarchy final : public Clock {
     int32_t* amap;                  // stencil tiles of the active problems
     std::vector<int32_t> host_amap;
     ProbScalars* ps;
+    double* scratch = nullptr;      // device address of the fixed partial-sum array
     // timers
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -351,6 +381,9 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
 static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     if (bytes < h->ws_bytes) return fail(NRD_EINVAL, "workspace too small");
     if (reinterpret_cast<uintptr_t>(ptr) % 256) return fail(NRD_EINVAL, "workspace not 256-byte aligned");
+    // the fixed partial-sum array of nrd_dot_noalloc, on the device of this
+    // workspace (the current device)
+    HIPCHK(scratch_ptr(&h->scratch));
     h->ws = static_cast<char*>(ptr);
     Tables& t = h->t;
     auto& o = h->o;
@@ -1951,6 +1984,23 @@ nrd_status nrd_dot(nrd_hierarchy* h, const double* x, const double* y, double* o
     nrd_status rc = dot_host(h, x, y, v);
     if (rc) return rc;
     std::copy(v.begin(), v.end(), out);
+    return NRD_OK;
+}
+
+nrd_status nrd_dot_noalloc(nrd_hierarchy* h, const double* x, const double* y, double* out) {
+    if (!h) return fail(NRD_EINVAL, "NULL hierarchy");
+    if (h->t.vtiles.size() > (size_t)kScratchTiles)
+        return fail(NRD_EINVAL, "nrd_dot_noalloc: the hierarchy has " +
+                                    std::to_string(h->t.vtiles.size()) +
+                                    " reduction tiles, more than the " +
+                                    std::to_string(kScratchTiles) + " its fixed array holds");
+    NEED_BOUND(h);
+    if (!x || !y || !out) return fail(NRD_EINVAL, "NULL argument");
+    h->D.active = nullptr;
+    // same kernels and summation order as nrd_dot; partials in the fixed
+    // array, the per-problem sums straight into the caller's device buffer
+    multidot(h->D, h->stream, x, 0, 1, y, h->scratch, out);
+    HIPCHK(hipGetLastError());
     return NRD_OK;
 }
 

@@ -115,6 +115,7 @@ _sigs = {
     "nrd_adjoint_run": (C.c_int32, [_H, C.POINTER(C.c_double), C.c_int32,
                                     C.c_int32, _P, _P]),
     "nrd_dot": (C.c_int32, [_H, _P, _P, C.POINTER(C.c_double)]),
+    "nrd_dot_noalloc": (C.c_int32, [_H, _P, _P, _P]),
     "nrd_autotune": (C.c_int32, [_H, C.c_char_p, C.POINTER(C.c_int32)]),
     "nrd_timer_enable": (C.c_int32, [_H, C.c_int32]),
     "nrd_timer_cells": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_int64)]),
@@ -345,6 +346,13 @@ class Hierarchy:
         out = (C.c_double * self.nprob)()
         check(nrd_dot(self.h, self._nat(x, "x"), self._nat(y, "y"), out))
         return list(out)
+
+    def dot_noalloc(self, x, y, out):
+        """nrd_dot into a device tensor of nprob doubles (no allocation, no
+        synchronisation)."""
+        check(nrd_dot_noalloc(self.h, self._nat(x, "x"), self._nat(y, "y"),
+                              _vec(out, self.nprob, "out")))
+        return out
 
     def timer_enable(self, on=True):
         check(nrd_timer_enable(self.h, 1 if on else 0))

@@ -151,3 +151,21 @@ def test_autograd_refuses_a_bdf2_hierarchy():
     z = torch.ones(H.ncells, dtype=torch.float64, requires_grad=True)
     with pytest.raises(ValueError, match="bdf_max_order"):
         RadDiffEvolve.apply(z, H, z.detach(), z.detach(), 1e-3, 2, 1)
+
+
+def test_dot_noalloc_refuses_hierarchies_beyond_its_fixed_array():
+    """The no-allocation inner product keeps one partial sum per reduction
+    tile in a fixed array of 32768 doubles; a hierarchy with more tiles is
+    refused with NRD_EINVAL before any device work (checked on the host)."""
+    import ctypes as C
+    from paper_1302_6303_amd import nrd
+    n = 32
+    boxes = [I.Box(0, 0, (0, 0, 0), (n, n, n))]
+    for k in range(0, 2 * n, 2):
+        for j in range(0, 2 * n, 2):
+            for i in range(0, 2 * n, 2):
+                boxes.append(I.Box(0, 1, (i, j, k), (i + 2, j + 2, k + 2)))
+    H = _create([I.Problem((n, n, n))], boxes)
+    rc = nrd.nrd_dot_noalloc(H.h, C.c_void_p(0), C.c_void_p(0), C.c_void_p(0))
+    assert rc == nrd.NRD_EINVAL
+    assert "32768" in nrd.nrd_last_error().decode()
