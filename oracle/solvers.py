@@ -327,7 +327,38 @@ class Stepper:
         self.u_prev = self.u
         self.u = res.u
         self.dt_prev = dt
+        self.last = (b, c0, dt)            # the step's system, for a re-solve
         self.history.append(res)
+        return res
+
+    def regrid(self, new_sys):
+        """Move the time history to a new hierarchy and re-solve the last
+        step there (Sec. 5, warm restart with a re-solve): u_n, u_{n-1} and
+        the last step's history vector b are transferred by conservative
+        linear refinement; the last step's system F(u) = c0 u - b - dt f(u)
+        is solved again on the new grid from the transferred u_n; u'_n is
+        recomputed from the re-solved state.  The next step's local error
+        estimate depends on interpolated data and is not to be used
+        (self.after_regrid).  Returns the Newton result of the re-solve."""
+        from . import regrid as rg
+        old = self.sys
+
+        def move(x):
+            E, T = old.split(x)
+            return new_sys.join(rg.transfer(old.H, E, new_sys.H),
+                                rg.transfer(old.H, T, new_sys.H))
+        b, c0, dt = self.last
+        u = move(self.u)
+        self.u_prev = move(self.u_prev) if self.u_prev is not None else None
+        b = move(b)
+        self.sys = new_sys
+        res = newton(new_sys, u, b, dt, c0, dt / c0, **self.kw)
+        if not res.converged:
+            raise RuntimeError("re-solve after regridding did not converge")
+        self.u = res.u
+        self.udot = (c0 * res.u - b) / dt
+        self.last = (b, c0, dt)
+        self.after_regrid = True
         return res
 
 
@@ -400,7 +431,13 @@ class AdaptiveStepper(Stepper):
         self.t += dt
         err = None
         ratio = 1.0
-        if self.predicted is not None:
+        if getattr(self, "after_regrid", False):
+            # the first estimate after a regrid uses interpolated history: it
+            # is not used (Sec. 5); the step size is kept and the next
+            # estimate has no predecessor
+            self.after_regrid = False
+            self.err_prev = None
+        elif self.predicted is not None:
             err = scaled_max_norm(self.sys, bdf2_error_estimate(self.u, self.predicted, self.alpha),
                                   self.u, *self.eta)
             if err > 0.0:
