@@ -289,6 +289,89 @@ nrd_status nrd_adjoint_run(nrd_hierarchy* h, const double* dt, int32_t nsteps,
                            int32_t ckpt_every, const double* dev_dJdE_final,
                            double* dev_gz);
 
+/* ---- dynamic regridding (Sec. 5) ------------------------------------- */
+
+/* Refinement criteria; a threshold <= 0 (or z_interface = 0) switches one
+ * off, a cell is tagged when any enabled criterion holds.  With E_d the
+ * centred difference of E along axis d (a neighbour beyond a physical face
+ * is the cell itself):
+ *   grad_E:  |grad E| / E > grad_E, grad E in physical units;
+ *   tau_g:   sum_d |E_{+d} - E_{-d}| / 2 / (0.1 max|E|) > tau_g   (tau^g),
+ *   tau_c:   sum_d |E_{+d} - 2 E + E_{-d}| / (0.1 max|E|) > tau_c  (tau^c),
+ *            the paper's indicators, max|E| over the problem's composite
+ *            cells;
+ *   z_interface: a face neighbour lies in another material (a coarse-fine
+ *            neighbour's material is its coarse parent's z). */
+typedef struct {
+    double grad_E;
+    double tau_g;
+    double tau_c;
+    int32_t z_interface;
+    int32_t pad_;
+} nrd_tagging;
+
+/* Tags of the current state (after nrd_set_fields or a step): dev_tags
+ * (device, ncells bytes, compact layout) receives 1 for a tagged cell and 0
+ * otherwise, for every cell of every box, covered cells included.  NRD_ESTATE
+ * before nrd_set_fields.  Asynchronous. */
+nrd_status nrd_tag(nrd_hierarchy* h, const nrd_tagging* crit, uint8_t* dev_tags);
+
+/* Clustering options (cell counts on the level whose tags are clustered). */
+typedef struct {
+    int32_t max_levels;   /* levels of the new hierarchy, base included      */
+    int32_t buffer;       /* tags grown by this many cells per axis          */
+    double efficiency;    /* a box is kept when tagged / cells >= efficiency  */
+    int32_t min_side;     /* cuts made for efficiency leave sides >= this    */
+    int32_t max_side;     /* longer boxes are halved                         */
+} nrd_cluster_opt;
+
+/* Host only (no device, no hierarchy object): the boxes of a new hierarchy
+ * for the problems probs from the boxes of the current one and their tags
+ * (host_tags: ncells bytes in the compact layout of `boxes`, nonzero =
+ * tagged).  Level 0 is kept.  Level l + 1 is built from tags on the new
+ * level l, each cell taking the tag of the finest old level at or below l
+ * that holds it; tags are grown by `buffer`, restricted to cells whose 26
+ * neighbours lie on level l (proper nesting), and grouped into boxes by the
+ * Berger-Rigoutsos algorithm (Sec. 5): bounding boxes accepted at the
+ * efficiency target, else cut at a plane without tags, at the strongest
+ * inflection of the tag signature, or in the middle.  Boxes longer than
+ * max_side are halved.  The result (ordered by problem and level, level-l
+ * boxes refined by 2) is written to out[0 .. *nout); NRD_EINVAL if it holds
+ * more than cap boxes (*nout is then the count needed) or for bad options.
+ * Deterministic. */
+nrd_status nrd_cluster(const nrd_problem* probs, int32_t nprob, const nrd_box* boxes,
+                       int32_t nbox, const uint8_t* host_tags,
+                       const nrd_cluster_opt* opt, nrd_box* out, int32_t cap,
+                       int32_t* nout);
+
+/* Moves the time history of src to dst (both bound, created for the same
+ * problems, possibly with other boxes; same device): the state u_n, the
+ * previous state u_{n-1} and the last step's history vector b, by
+ * conservative minmod-limited linear refinement (Sec. 5): dst level 0 copies
+ * src level 0; every finer dst level is refined from the dst level below
+ * (each child u_P +- s_d / 4 per axis, s_d the minmod of the two one-sided
+ * differences of its parent, zero across a physical face) and then takes
+ * src's values wherever src has that level (src covered cells hold the mean
+ * of their children); the result is synced.  dev_z (device, compact layout
+ * of dst) is dst's material field, sampled by the caller on every level.
+ * The step-size history moves too; the next nrd_implicit_step continues
+ * with BDF2 on the interpolated history (warm restart), its local error
+ * estimate is not computed (err_norm = -1: it would rest on interpolated
+ * data) and nrd_adaptive_steps keeps that step's size.  Call nrd_resolve
+ * first to solve the last step again on the new grid.  src is unchanged.
+ * Errors: NRD_EINVAL (other problems), NRD_ESTATE (unbound, no fields),
+ * NRD_ENONPOS (z).  Synchronises both streams. */
+nrd_status nrd_transfer(nrd_hierarchy* src, nrd_hierarchy* dst, const double* dev_z);
+
+/* Solves the last step's system F(u) = c0 u - b - dt f(u) = 0 again on the
+ * hierarchy a transfer moved it to (Sec. 5: a re-solve at the current time
+ * with the interpolated history, starting from the interpolated state);
+ * the solution replaces u_n and the time derivative for the next predictor
+ * is recomputed from it.  stats: host [nprob] or NULL.  NRD_OK with no work
+ * when no step had been taken before the transfer.  On failure the
+ * transferred state is kept and NRD_ENOTCONV returned.  Synchronises. */
+nrd_status nrd_resolve(nrd_hierarchy* h, nrd_step_stats* stats);
+
 /* Inner product and norm of native 2-field vectors, per problem, volume
  * weighted over composite cells (host outputs of length nprob). */
 nrd_status nrd_dot(nrd_hierarchy* h, const double* dev_x, const double* dev_y,

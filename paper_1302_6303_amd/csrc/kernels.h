@@ -175,6 +175,27 @@ void fd_shift(const Dev& D, hipStream_t s, const double* sums, const double* u,
 void fd_quotient(const Dev& D, hipStream_t s, const double* sums, const double* F0,
                  double* Jv);
 
+// ---- regrid.hip ---------------------------------------------------------
+// out[p] = max over composite cells of problem p of |x| (field 0)
+void abs_max(const Dev& D, hipStream_t s, const double* x, double* partial, double* out);
+// tags[coff[b] + lin] = 1 where a criterion holds at interior cell lin of
+// patch b (covered cells included); E, z native with ghosts filled (z's
+// coarse-fine ghosts by ghost_fill_parent); emax per problem
+void tag_cells(const Dev& D, hipStream_t s, const int64_t* coff, const double* E,
+               const double* z, const double* emax, const TagCrit& tc, uint8_t* tags);
+// sibling ghosts copied, coarse-fine ghosts set to their coarse parent
+void ghost_fill_parent(const Dev& D, hipStream_t s, double* x);
+// fragment copies from another hierarchy's native vector (src, snl cells
+// per field, patch table sP) into this one's (dst, dnl, dP)
+void xfer_copy(hipStream_t s, int nchunks, const XferChunk* chunks, const XferFrag* frags,
+               const PatchInfo* dP, const PatchInfo* sP, const double* src, double* dst,
+               int64_t snl, int64_t dnl, int nf);
+// every cell of level lev (>= 1) of x <- conservative minmod-limited linear
+// refinement of level lev - 1 of x (sh: shadow scratch of nf * slen values)
+void refine_level(const Dev& D, hipStream_t s, const ShadowPatch* shadows,
+                  const int32_t* shadow_src, int lev, double* x, double* sh, int64_t slen,
+                  int nf);
+
 // Givens / Hessenberg update of FGMRES for every active problem.
 //   hcol [nprob][m+1] holds the new column (CGS sums), hn2 [nprob] = ||w||^2
 void gmres_column(hipStream_t s, int nprob, int m, int j, const int32_t* active,

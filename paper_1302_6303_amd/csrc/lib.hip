@@ -119,6 +119,10 @@ struct nrd_hierarchy final : public Clock {
     std::vector<double> c0, alpha, beta, dt_cur;
     std::vector<ProbScalars> ps_host;
     bool step_ready = false;
+    bool last_valid = false;        // bvec / c0 / alpha / dt_cur hold the last
+                                    // accepted step's system
+    bool resolve_ready = false;     // a transfer brought that system here
+    bool skip_estimate = false;     // next step: no error estimate (regrid)
     // device pointers
     double *z, *z3, *cur, *prev, *udot, *bvec, *x, *F, *s, *w, *tmp, *tmp2, *gz3, *V, *Z, *pred;
     std::vector<double> err_prev;   // per problem: last error norm (-1: none)
@@ -1183,6 +1187,7 @@ static nrd_status implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_sta
     Tables& t = h->t;
     const int np = t.nprob;
     hipStream_t s = h->stream;
+    h->last_valid = false;
     nrd_status rc = begin_step(h, dt, bdf1_only);
     if (rc) return rc;
     // initial guess: leapfrog predictor (BDF2 steps) if positive, else u_n
@@ -1235,7 +1240,7 @@ static nrd_status implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_sta
         st[p].dt = dt[p];
         st[p].err_norm = -1.0;
     }
-    if (rc == NRD_OK && h->opt.error_estimate && any2) {
+    if (rc == NRD_OK && h->opt.error_estimate && any2 && !h->skip_estimate) {
         // local error estimate of the BDF2 steps (eq. bdf2le), scaled max norm
         std::vector<double> cf(np), en(np);
         for (int p = 0; p < np; ++p) {
@@ -1281,6 +1286,9 @@ static nrd_status implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_sta
     for (int p = 0; p < np; ++p) h->dt_prev[p] = bdf1_only ? 0.0 : dt[p];
     HIPCHK(hipStreamSynchronize(s));
     h->step_ready = false;
+    h->last_valid = true;
+    h->resolve_ready = false;
+    h->skip_estimate = false;
     return NRD_OK;
 }
 
@@ -1628,6 +1636,7 @@ nrd_status nrd_set_fields(nrd_hierarchy* h, const double* E, const double* T, co
     std::fill(h->err_prev.begin(), h->err_prev.end(), -1.0);
     h->step_ready = false;
     h->fields_set = true;
+    h->last_valid = h->resolve_ready = h->skip_estimate = false;
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
     return NRD_OK;
@@ -1975,6 +1984,206 @@ nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed
     h->drop_graphs();                               // captured launches used the old tiles
     RCHK(upload_active(h));                         // tile map of the new list
     HIPCHK(hipStreamSynchronize(s));
+    return NRD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// dynamic regridding (Sec. 5)
+// ---------------------------------------------------------------------------
+
+nrd_status nrd_tag(nrd_hierarchy* h, const nrd_tagging* crit, uint8_t* tags) {
+    NEED_BOUND(h);
+    if (!crit || !tags) return fail(NRD_EINVAL, "NULL argument");
+    if (!h->fields_set) return fail(NRD_ESTATE, "nrd_tag needs nrd_set_fields first");
+    hipStream_t s = h->stream;
+    h->D.active = nullptr;
+    prepare_state(h, h->cur);
+    abs_max(h->D, s, h->cur, h->partial, h->minout);
+    // z with every coarse-fine ghost set to its coarse parent's material
+    HIPCHK(hipMemcpyAsync(h->tmp2, h->z, 8 * h->t.nl, hipMemcpyDeviceToDevice, s));
+    ghost_fill_parent(h->D, s, h->tmp2);
+    TagCrit tc;
+    std::memset(&tc, 0, sizeof(tc));
+    tc.grad = crit->grad_E;
+    tc.tau_g = crit->tau_g;
+    tc.tau_c = crit->tau_c;
+    tc.z_interface = crit->z_interface != 0;
+    tag_cells(h->D, s, h->at<int64_t>(h->o.coff), h->cur, h->tmp2, h->minout, tc, tags);
+    HIPCHK(hipGetLastError());
+    return NRD_OK;
+}
+
+nrd_status nrd_cluster(const nrd_problem* probs, int32_t nprob, const nrd_box* boxes,
+                       int32_t nbox, const uint8_t* tags, const nrd_cluster_opt* opt,
+                       nrd_box* out, int32_t cap, int32_t* nout) {
+    if (!probs || !boxes || !tags || !opt || !nout || nprob <= 0 || nbox <= 0)
+        return fail(NRD_EINVAL, "NULL argument or empty input");
+    try {
+        std::vector<nrd_box> res;
+        std::string msg;
+        const nrd_status rc = cluster_boxes(probs, nprob, boxes, nbox, tags, *opt, res, msg);
+        if (rc) return fail(rc, msg);
+        *nout = (int32_t)res.size();
+        if ((int32_t)res.size() > cap || !out)
+            return fail(NRD_EINVAL, "output holds " + std::to_string(cap) + " boxes, " +
+                                        std::to_string(res.size()) + " needed");
+        std::copy(res.begin(), res.end(), out);
+        return NRD_OK;
+    } catch (const std::exception& e) {
+        return fail(NRD_EINVAL, e.what());
+    }
+}
+
+nrd_status nrd_transfer(nrd_hierarchy* src, nrd_hierarchy* dst, const double* z) {
+    NEED_BOUND(src);
+    NEED_BOUND(dst);
+    if (!z) return fail(NRD_EINVAL, "NULL z");
+    if (src == dst) return fail(NRD_EINVAL, "source and destination are the same hierarchy");
+    if (!src->fields_set) return fail(NRD_ESTATE, "the source has no fields");
+    const Tables& ts = src->t;
+    Tables& td = dst->t;
+    const int np = td.nprob;
+    if (ts.nprob != np) return fail(NRD_EINVAL, "the hierarchies hold different problems");
+    for (int p = 0; p < np; ++p) {
+        const nrd_problem &a = ts.probs[p], &b = td.probs[p];
+        for (int d = 0; d < 3; ++d)
+            if (a.base_n[d] != b.base_n[d] || a.lo[d] != b.lo[d] || a.hi[d] != b.hi[d])
+                return fail(NRD_EINVAL, "problem " + std::to_string(p) +
+                                            ": base grid or domain differs");
+    }
+    HIPCHK(hipStreamSynchronize(src->stream));
+    hipStream_t s = dst->stream;
+    dst->D.active = nullptr;
+    // material field of the new hierarchy (staged: a rejected z changes nothing)
+    const int64_t* coff = dst->at<int64_t>(dst->o.coff);
+    unpack(dst->D, s, coff, z, dst->tmp2, 1, td.ncells);
+    fill_native(s, reinterpret_cast<double*>(dst->flag), 1, 0.0);
+    check_positive(dst->D, s, dst->tmp2, 1, dst->flag);
+    int32_t bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, dst->flag, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) return fail(NRD_ENONPOS, "z must be positive and finite");
+    HIPCHK(hipMemcpyAsync(dst->z, dst->tmp2, 8 * td.nl, hipMemcpyDeviceToDevice, s));
+    ghost_fill_d(dst->D, s, dst->z, 1);
+    cube(s, dst->z, dst->z3, td.nl);
+    // copy fragments: dst patch x src patch of the same problem and level
+    std::vector<XferFrag> frags;
+    std::vector<XferChunk> chunks;
+    std::vector<int32_t> lev_chunk0(td.nlev + 1, 0);
+    constexpr int32_t kChunk = 4 * kBlock;
+    for (int l = 0; l < td.nlev; ++l) {
+        lev_chunk0[l] = (int32_t)chunks.size();
+        if (l >= ts.nlev) continue;
+        for (int p = 0; p < np; ++p)
+            for (int32_t db : td.level_patches[p][l])
+                for (int32_t sb : ts.level_patches[p][l]) {
+                    const HostBox &a = td.boxes[db], &b = ts.boxes[sb];
+                    XferFrag f;
+                    f.dpatch = db;
+                    f.spatch = sb;
+                    int64_t n = 1;
+                    for (int d = 0; d < 3; ++d) {
+                        f.lo[d] = std::max(a.lo[d], b.lo[d]);
+                        f.n[d] = std::min(a.hi[d], b.hi[d]) - f.lo[d];
+                        n *= std::max(0, f.n[d]);
+                    }
+                    if (n <= 0) continue;
+                    const int32_t fi = (int32_t)frags.size();
+                    frags.push_back(f);
+                    for (int64_t c0 = 0; c0 < n; c0 += kChunk)
+                        chunks.push_back({fi, (int32_t)c0, (int32_t)std::min<int64_t>(kChunk, n - c0)});
+                }
+    }
+    lev_chunk0[td.nlev] = (int32_t)chunks.size();
+    // the tables go to the Krylov basis region of dst, unused until its next solve
+    const size_t fbytes = (sizeof(XferFrag) * frags.size() + 255) & ~size_t(255);
+    if (fbytes + sizeof(XferChunk) * chunks.size() > 8 * (size_t)dst->nl2() * (dst->m + 1))
+        return fail(NRD_EUNSUPPORTED, "transfer tables exceed the scratch region");
+    char* base = reinterpret_cast<char*>(dst->V);
+    XferFrag* dfr = reinterpret_cast<XferFrag*>(base);
+    XferChunk* dch = reinterpret_cast<XferChunk*>(base + fbytes);
+    HIPCHK(up(s, dfr, frags));
+    HIPCHK(up(s, dch, chunks));
+    const PatchInfo* dP = dst->D.patches;
+    const PatchInfo* sP = src->D.patches;
+    const ShadowPatch* shp = dst->at<ShadowPatch>(dst->o.shadows);
+    const int32_t* ssrc = dst->at<int32_t>(dst->o.shadow_src);
+    const int64_t slen = std::max<int64_t>(1, td.shadow_len);
+    const double* from[3] = {src->cur, src->prev, src->bvec};
+    double* to[3] = {dst->cur, dst->prev, dst->bvec};
+    for (int v = 0; v < 3; ++v) {
+        for (int l = 0; l < td.nlev; ++l) {
+            if (l > 0) refine_level(dst->D, s, shp, ssrc, l, to[v], dst->tmp, slen, 2);
+            const int a = lev_chunk0[l], n = lev_chunk0[l + 1] - a;
+            xfer_copy(s, n, dch + a, dfr, dP, sP, from[v], to[v], ts.nl, td.nl, 2);
+        }
+        prepare_state(dst, to[v]);
+    }
+    // time history and the last step's system
+    dst->dt_prev = src->dt_prev;
+    dst->err_prev.assign(np, -1.0);
+    dst->last_valid = src->last_valid;
+    dst->resolve_ready = src->last_valid;
+    dst->skip_estimate = true;
+    if (src->last_valid) {
+        dst->c0 = src->c0;
+        dst->alpha = src->alpha;
+        dst->beta = src->beta;
+        dst->dt_cur = src->dt_cur;
+        for (int p = 0; p < np; ++p) {
+            dst->ps_host[p].dt = src->ps_host[p].dt;
+            dst->ps_host[p].c0 = src->ps_host[p].c0;
+            dst->ps_host[p].beta = src->ps_host[p].beta;
+            dst->ps_host[p].alpha = src->ps_host[p].alpha;
+        }
+        HIPCHK(up(s, dst->ps, dst->ps_host));
+    }
+    fill_native(s, dst->udot, dst->nl2(), 0.0);
+    dst->drop_graphs();
+    dst->fields_set = true;
+    dst->step_ready = src->last_valid;
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    return NRD_OK;
+}
+
+nrd_status nrd_resolve(nrd_hierarchy* h, nrd_step_stats* stats) {
+    NEED_BOUND(h);
+    const int np = h->t.nprob;
+    if (stats)
+        for (int p = 0; p < np; ++p) std::memset(&stats[p], 0, sizeof(stats[p]));
+    if (!h->resolve_ready) return NRD_OK;
+    hipStream_t s = h->stream;
+    h->D.active = nullptr;
+    HIPCHK(up(s, h->ps, h->ps_host));
+    copy_interior(h->D, s, h->cur, h->x);
+    std::vector<nrd_step_stats> st;
+    const nrd_status rc = newton(h, st);
+    for (int p = 0; p < np; ++p) {
+        st[p].dt = h->dt_cur[p];
+        st[p].err_norm = -1.0;
+    }
+    if (stats)
+        for (int p = 0; p < np; ++p) stats[p] = st[p];
+    if (rc) {
+        if (rc == NRD_ENOTCONV) g_err = "the re-solve did not converge; transferred state kept";
+        return rc;
+    }
+    // u'_n = (c0 u_n - b) / dt from the re-solved state
+    std::vector<double> buf(2 * np), one(np, 1.0);
+    for (int p = 0; p < np; ++p) {
+        buf[p] = h->c0[p] / h->dt_cur[p];
+        buf[np + p] = -1.0 / h->dt_cur[p];
+    }
+    HIPCHK(up(s, h->coefA, buf));
+    scale_copy(h->D, s, h->x, h->coefA, h->udot);
+    HIPCHK(up(s, h->coefB, one));
+    axpby(h->D, s, h->coefA + np, h->bvec, h->coefB, h->udot);
+    std::swap(h->cur, h->x);
+    prepare_state(h, h->cur);
+    HIPCHK(hipStreamSynchronize(s));
+    h->resolve_ready = false;
+    HIPCHK(hipGetLastError());
     return NRD_OK;
 }
 

@@ -79,6 +79,20 @@ struct RefluxCell { int32_t c, first, count, prob; };
 // the coarser level over its coarsened box grown by one cell.
 struct ShadowPatch { int32_t off, m0, m1, m2; };   // shadow extents (with halo)
 
+// Refinement criteria of the tag kernel (a threshold <= 0 switches one off).
+struct TagCrit {
+    double grad;             // |grad E| / E
+    double tau_g, tau_c;     // the paper's gradient and curvature indicators
+    int32_t z_interface;     // a face neighbour of another material
+    int32_t pad;
+};
+
+// Transfer between hierarchies: a box (level index space) whose cells a
+// destination patch takes from a source patch of the same level, cut into
+// launch chunks of consecutive cells (x fastest within the box).
+struct XferFrag { int32_t dpatch, spatch, lo[3], n[3]; };
+struct XferChunk { int32_t frag, start, count; };
+
 struct ProbScalars {         // device per-problem constants of a step
     double dt, c0, beta, alpha;
     double kappa, lam;
@@ -176,6 +190,11 @@ bool build_planes(Tables& t, const std::vector<int32_t>& kc, const std::vector<i
                   int32_t max_span);
 bool patch_planes(const PatchInfo& p, int32_t b, int32_t kc, int32_t run, int32_t max_span,
                   std::vector<STile>& out);
+
+// Berger-Rigoutsos clustering of tags into new boxes (cluster.cpp).
+nrd_status cluster_boxes(const nrd_problem* probs, int32_t nprob, const nrd_box* boxes,
+                         int32_t nbox, const uint8_t* tags, const nrd_cluster_opt& co,
+                         std::vector<nrd_box>& out, std::string& msg);
 
 // Builds all tables; returns NRD_OK or an error with msg set.
 nrd_status build_tables(const nrd_problem* probs, int32_t nprob,

@@ -79,6 +79,17 @@ class nrd_step_stats(C.Structure):
 NRD_CTL_PC47, NRD_CTL_EPS = 0, 1
 
 
+class nrd_tagging(C.Structure):
+    _fields_ = [("grad_E", C.c_double), ("tau_g", C.c_double), ("tau_c", C.c_double),
+                ("z_interface", C.c_int32), ("pad_", C.c_int32)]
+
+
+class nrd_cluster_opt(C.Structure):
+    _fields_ = [("max_levels", C.c_int32), ("buffer", C.c_int32),
+                ("efficiency", C.c_double), ("min_side", C.c_int32),
+                ("max_side", C.c_int32)]
+
+
 class nrd_timectl(C.Structure):
     _fields_ = [("eps", C.c_double), ("ratio_min", C.c_double),
                 ("ratio_max", C.c_double), ("controller", C.c_int32),
@@ -114,6 +125,12 @@ _sigs = {
                                        C.POINTER(nrd_step_stats)]),
     "nrd_adjoint_run": (C.c_int32, [_H, C.POINTER(C.c_double), C.c_int32,
                                     C.c_int32, _P, _P]),
+    "nrd_tag": (C.c_int32, [_H, C.POINTER(nrd_tagging), _P]),
+    "nrd_cluster": (C.c_int32, [C.POINTER(nrd_problem), C.c_int32, C.POINTER(nrd_box),
+                                C.c_int32, C.POINTER(C.c_uint8), C.POINTER(nrd_cluster_opt),
+                                C.POINTER(nrd_box), C.c_int32, C.POINTER(C.c_int32)]),
+    "nrd_transfer": (C.c_int32, [_H, _H, _P]),
+    "nrd_resolve": (C.c_int32, [_H, C.POINTER(nrd_step_stats)]),
     "nrd_dot": (C.c_int32, [_H, _P, _P, C.POINTER(C.c_double)]),
     "nrd_dot_noalloc": (C.c_int32, [_H, _P, _P, _P]),
     "nrd_autotune": (C.c_int32, [_H, C.c_char_p, C.POINTER(C.c_int32)]),
@@ -198,6 +215,29 @@ def _vec(t, n, name, optional=False):
 
 def _dt(values):
     return (C.c_double * len(values))(*[float(v) for v in values])
+
+
+def cluster(problems, boxes, tags, max_levels, buffer=2, efficiency=0.7, min_side=4,
+            max_side=24):
+    """New boxes (list of (problem, level, lo, hi)) from the boxes of a
+    hierarchy and its host tags (a uint8 array of ncells, compact layout)."""
+    import numpy as np
+    t = np.ascontiguousarray(np.asarray(tags, dtype=np.uint8))
+    ncells = sum(int(np.prod([b.hi[d] - b.lo[d] for d in range(3)])) for b in boxes)
+    if t.size != ncells:
+        raise ValueError(f"tags: {t.size} values, expected {ncells}")
+    pr = make_problems(problems)
+    bx = make_boxes(boxes)
+    opt = nrd_cluster_opt(int(max_levels), int(buffer), float(efficiency), int(min_side),
+                          int(max_side))
+    n = C.c_int32(0)
+    tp = t.ctypes.data_as(C.POINTER(C.c_uint8))
+    rc = nrd_cluster(pr, len(problems), bx, len(boxes), tp, C.byref(opt), None, 0, C.byref(n))
+    out = (nrd_box * max(1, n.value))()
+    check(nrd_cluster(pr, len(problems), bx, len(boxes), tp, C.byref(opt), out, n.value,
+                      C.byref(n)))
+    del rc
+    return [(b.problem, b.level, tuple(b.lo), tuple(b.hi)) for b in out[:n.value]]
 
 
 class Hierarchy:
@@ -346,6 +386,29 @@ class Hierarchy:
         out = (C.c_double * self.nprob)()
         check(nrd_dot(self.h, self._nat(x, "x"), self._nat(y, "y"), out))
         return list(out)
+
+    # -- regridding (Sec. 5) ------------------------------------------------
+    def tag(self, grad_E=0.0, tau_g=0.0, tau_c=0.0, z_interface=False, out=None):
+        """Tags of the current state: uint8 device tensor of ncells."""
+        import torch
+        if out is None:
+            out = torch.zeros(self.ncells, dtype=torch.uint8, device=self.device)
+        if out.dtype != torch.uint8 or out.numel() != self.ncells or not out.is_contiguous() \
+                or not out.is_cuda:
+            raise ValueError("out: a contiguous CUDA uint8 tensor of ncells values")
+        crit = nrd_tagging(float(grad_E), float(tau_g), float(tau_c), int(bool(z_interface)), 0)
+        check(nrd_tag(self.h, C.byref(crit), C.c_void_p(out.data_ptr())))
+        return out
+
+    def transfer_to(self, dst, z):
+        """Moves the time history to the hierarchy dst (z: its compact
+        material field, a float64 CUDA tensor)."""
+        check(nrd_transfer(self.h, dst.h, _vec(z, dst.ncells, "z")))
+
+    def resolve(self):
+        st = (nrd_step_stats * self.nprob)()
+        check(nrd_resolve(self.h, st))
+        return [x.as_dict() for x in st]
 
     def dot_noalloc(self, x, y, out):
         """nrd_dot into a device tensor of nprob doubles (no allocation, no
