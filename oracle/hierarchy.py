@@ -192,7 +192,9 @@ class Hierarchy:
         """Fill the face ghosts of every patch of every field, in place.
 
         coarse_fine="linear" is the inhomogeneous interpolation; "zero" uses
-        coarse values 0 (the relation g = f/3 used for level corrections).
+        coarse values 0 (the relation g = f/3 used for level corrections);
+        "parent" gives a coarse-fine ghost the value of the coarse cell it
+        lies in (the material of that cell, for interface tags).
         Assumes covered coarse cells already hold restricted values.
         """
         for p in self.patches:
@@ -212,6 +214,10 @@ class Hierarchy:
                             fine_in = arr[il[m, 0], il[m, 1], il[m, 2]]
                             if coarse_fine == "zero":
                                 val[m] = fine_in / 3.0
+                            elif coarse_fine == "parent":
+                                N = self.N(p.level - 1)
+                                val[m] = self.value_at(f, p.level - 1,
+                                                       np.clip(G[m] // 2, 0, N - 1))
                             else:
                                 ci = self.coarse_interp(f, p.level, G[m], d)
                                 val[m] = (2.0 / 3.0) * ci + (1.0 / 3.0) * fine_in

@@ -13,7 +13,8 @@ synced and ghost-filled state of one problem):
   indicator exceeds its user threshold;
 * the relative gradient |grad E| / E > g_thr with the centred gradient in
   physical units, and material interfaces: a face neighbour whose z
-  differs.
+  differs (a coarse-fine neighbour's z is that of the coarse cell it lies
+  in, not an interpolation: materials are not interpolated).
 Ghost values follow the state's ghost fill (copies at physical faces, so a
 centred difference there is one-sided over half the distance).
 
@@ -73,7 +74,7 @@ def tags(H: Hierarchy, E, z, grad=0.0, z_interface=False, tau_g=0.0, tau_c=0.0):
     H.sync([Eg])
     H.fill_ghosts([Eg])
     zg = H.from_interior(z)
-    H.fill_ghosts([zg])
+    H.fill_ghosts([zg], coarse_fine="parent")
     emax = 0.0
     for p in H.patches:
         e = Eg[p.pid][1:-1, 1:-1, 1:-1]

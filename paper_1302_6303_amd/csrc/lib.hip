@@ -1991,6 +1991,24 @@ nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed
 // dynamic regridding (Sec. 5)
 // ---------------------------------------------------------------------------
 
+// udot = (c0 x - b) / dt per problem with the last step's c0, b and dt
+static nrd_status set_udot(nrd_hierarchy* h, const double* x) {
+    const int np = h->t.nprob;
+    hipStream_t s = h->stream;
+    std::vector<double> buf(2 * np), one(np, 1.0);
+    for (int p = 0; p < np; ++p) {
+        buf[p] = h->c0[p] / h->dt_cur[p];
+        buf[np + p] = -1.0 / h->dt_cur[p];
+    }
+    HIPCHK(up(s, h->coefA, buf));
+    h->D.active = nullptr;
+    scale_copy(h->D, s, x, h->coefA, h->udot);
+    HIPCHK(up(s, h->coefB, one));
+    axpby(h->D, s, h->coefA + np, h->bvec, h->coefB, h->udot);
+    HIPCHK(hipStreamSynchronize(s));      // the host coefficient buffers end here
+    return NRD_OK;
+}
+
 nrd_status nrd_tag(nrd_hierarchy* h, const nrd_tagging* crit, uint8_t* tags) {
     NEED_BOUND(h);
     if (!crit || !tags) return fail(NRD_EINVAL, "NULL argument");
@@ -2138,7 +2156,10 @@ nrd_status nrd_transfer(nrd_hierarchy* src, nrd_hierarchy* dst, const double* z)
         }
         HIPCHK(up(s, dst->ps, dst->ps_host));
     }
-    fill_native(s, dst->udot, dst->nl2(), 0.0);
+    if (src->last_valid)
+        RCHK(set_udot(dst, dst->cur));      // from the interpolated state
+    else
+        fill_native(s, dst->udot, dst->nl2(), 0.0);
     dst->drop_graphs();
     dst->fields_set = true;
     dst->step_ready = src->last_valid;
@@ -2170,15 +2191,7 @@ nrd_status nrd_resolve(nrd_hierarchy* h, nrd_step_stats* stats) {
         return rc;
     }
     // u'_n = (c0 u_n - b) / dt from the re-solved state
-    std::vector<double> buf(2 * np), one(np, 1.0);
-    for (int p = 0; p < np; ++p) {
-        buf[p] = h->c0[p] / h->dt_cur[p];
-        buf[np + p] = -1.0 / h->dt_cur[p];
-    }
-    HIPCHK(up(s, h->coefA, buf));
-    scale_copy(h->D, s, h->x, h->coefA, h->udot);
-    HIPCHK(up(s, h->coefB, one));
-    axpby(h->D, s, h->coefA + np, h->bvec, h->coefB, h->udot);
+    RCHK(set_udot(h, h->x));
     std::swap(h->cur, h->x);
     prepare_state(h, h->cur);
     HIPCHK(hipStreamSynchronize(s));
