@@ -23,6 +23,11 @@ Workloads (seeded, synthetic; --workload):
   amr128    128^3 base + 3 levels around six material boxes (2794 patches,
             39 M cells), dt = 5e-4; run with --bdf-max-order 1 (BDF2 stalls
             at the second step without time-step control)
+  dynamic   128^3 base, 4 levels regridded every 5 steps on |grad E|/E > 10
+            or a material interface (Berger-Rigoutsos), 50 BDF steps of
+            5e-4, warm restart after each regrid; mixed batched, replayed in
+            float64 batched (solution difference, Krylov counts) and for the
+            first 10 steps in float64 per patch
   uniform   one 32^3 patch, dt = 1e-3
   adjoint   64^3 smooth random material, 50 BDF1 steps: forward, checkpointed
             reverse sweep, transpose kernel
@@ -538,6 +543,282 @@ def adjoint_bench(nsteps, every, reps=20):
     print(json.dumps(out), flush=True)
 
 
+def material_sampler(mboxes):
+    """zfun(problems, boxes): the compact material field of a box list on the
+    device (z of the last material box holding a cell centre, 1 elsewhere;
+    the same rule and arithmetic as inputs.box_field)."""
+    def zfun(problems, boxes):
+        import torch
+        outs = []
+        for b in boxes:
+            pr = problems[b.problem]
+            h = pr.h(b.level)
+            ax = [(torch.arange(b.lo[d], b.hi[d], dtype=torch.float64, device="cuda") + 0.5)
+                  * float(h[d]) + float(pr.lo[d]) for d in range(3)]
+            Zc, Yc, Xc = torch.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+            z = torch.ones_like(Xc)
+            for lo, hi, zv in mboxes:
+                m = ((Xc >= lo[0]) & (Xc < hi[0]) & (Yc >= lo[1]) & (Yc < hi[1])
+                     & (Zc >= lo[2]) & (Zc < hi[2]))
+                z[m] = zv
+            outs.append(z.reshape(-1))
+        return torch.cat(outs)
+    return zfun
+
+
+def dynamic_bench(steps, every, plain_steps, base=128, nlev=4, dt0=1e-5, adaptive_eps=None,
+                  tune=True):
+    """Dynamic 4-level AMR (128^3 base, six z = 10 boxes), the paper's cold
+    start (E = E0, T = T0, Marshak inflow at x = 0): steps BDF steps (BDF1
+    first) of dt0 (a step whose Newton solve fails is retried with half the
+    step; steps of 5e-4 stall this hierarchy's Newton solves on the cold
+    front), or with adaptive_eps the paper's PC.4.7 control from a first
+    step dt0; a regrid every `every` steps on |grad E| / E > 10 or a
+    material interface (tags grown by 2 cells, Berger-Rigoutsos boxes of
+    4..24 tagged-level cells, i.e. 8..48 cells per side), each followed by
+    the warm-restart re-solve (whose step's error estimate is skipped).
+    Runs the mixed-precision batched solver, replays the same boxes and the
+    same step sizes with the float64 batched solver (the solution
+    difference and the Krylov counts) and the first plain_steps with the
+    float64 per-patch solver (its seconds per step)."""
+    import numpy as np
+    import tempfile
+    import torch
+    from paper_1302_6303_amd import inputs as I, nrd
+    from paper_1302_6303_amd.regrid import Regridder
+    rng = np.random.default_rng(I.SEED_BASE + 3)
+    mboxes = I.sample_material_boxes(rng, 6)
+    prob = I.Problem((base, base, base))
+    zfun = material_sampler(mboxes)
+    crit = dict(grad_E=10.0, z_interface=True)
+    clus = dict(max_levels=nlev, buffer=2, efficiency=0.7, min_side=4, max_side=24)
+    cache = os.path.join(tempfile.mkdtemp(prefix="nrd_tiles_"), "tiles.txt") if tune else None
+
+    def initial_boxes():
+        """Level by level on the initial (uniform) state: only the material
+        interfaces are tagged."""
+        opts = nrd.default_options(precision=nrd.NRD_MIXED)
+        R = Regridder(opts, crit, clus, zfun)
+        boxes = [I.Box(0, 0, (0, 0, 0), (base, base, base))]
+        for _ in range(nlev - 1):
+            H = nrd.Hierarchy([prob], boxes, opts)
+            n = H.ncells
+            H.set_fields(torch.full((n,), I.E0, dtype=torch.float64, device="cuda"),
+                         torch.full((n,), I.T0, dtype=torch.float64, device="cuda"),
+                         zfun([prob], boxes))
+            boxes = R.boxes_for(H)
+            del H
+        return boxes
+
+    def run(opts, nsteps, plan=None, label="", timers=False):
+        """plan: (box lists per regrid, step sizes) to replay, else recorded."""
+        dt = dt0
+        R = Regridder(opts, crit, clus, zfun, tune_cache=cache if tune else None)
+        boxes = plan[0][0] if plan else initial_boxes()
+        H = nrd.Hierarchy([prob], boxes, opts)
+        n = H.ncells
+        H.set_fields(torch.full((n,), I.E0, dtype=torch.float64, device="cuda"),
+                     torch.full((n,), I.T0, dtype=torch.float64, device="cuda"),
+                     zfun([prob], boxes))
+        if tune:
+            H.autotune(cache)
+        rec_boxes, rec_dt, regrids = [boxes], [], []
+        step_s = []
+        newton = krylov = 0
+        res_ms = res_cnt = res_cells = 0.0
+        for k in range(nsteps):
+            if k > 0 and k % every == 0:
+                if timers:
+                    ms, cnt = H.timer_read(nrd.NRD_TIMER_RESIDUAL)
+                    res_ms += ms
+                    res_cnt += cnt
+                    res_cells += H.timer_cells(nrd.NRD_TIMER_RESIDUAL)
+                nb = plan[0][len(rec_boxes)] if plan else None
+                Hn, nb, info = R.regrid(H, nb)
+                del H
+                H = Hn
+                rec_boxes.append(nb)
+                regrids.append(info)
+                newton += info["resolve_newton"]
+                krylov += info["resolve_krylov"]
+                log(f"{label} regrid at step {k}: {info['boxes']} boxes, "
+                    f"{info['cells']} cells, {info['tag_cluster_s']:.2f} s tag+cluster, "
+                    f"{info['create_transfer_s']:.2f} s create+transfer, "
+                    f"{info['timed_classes']} classes tuned in {info['tune_s']:.2f} s, "
+                    f"re-solve {info['resolve_newton']} Newton in {info['resolve_s']:.2f} s")
+            if timers and (k == 0 or k % every == 0):
+                H.timer_enable(True)
+                torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if plan:
+                d = plan[1][k]
+                _, st = H.implicit_step([d])
+            elif adaptive_eps:
+                _, dtn, _, stp = H.adaptive_steps(1, [dt], adaptive_eps)
+                st = stp[0]
+                d, dt = st[0]["dt"], dtn[0]
+            else:
+                d = dt0
+                for _ in range(8):
+                    rc, st = H.implicit_step([d], raise_on_fail=False)
+                    if rc == 0:
+                        break
+                    d *= 0.5
+                else:
+                    raise RuntimeError(f"{label}: step {k + 1} failed after 8 halvings")
+            step_s.append(time.perf_counter() - t0)
+            rec_dt.append(d)
+            newton += st[0]["newton_iters"]
+            krylov += st[0]["krylov_iters"]
+            log(f"{label} step {k + 1}: dt {d:.3g}, newton {st[0]['newton_iters']}, krylov "
+                f"{st[0]['krylov_iters']}, {step_s[-1] * 1e3:.1f} ms")
+        out = {"s_per_step": float(np.mean(step_s)), "median_s_per_step": float(np.median(step_s)),
+               "newton": newton, "krylov": krylov,
+               "krylov_per_newton": krylov / max(newton, 1),
+               "regrids": regrids, "final_boxes": len(rec_boxes[-1]), "final_cells": H.ncells}
+        if timers:
+            ms, cnt = H.timer_read(nrd.NRD_TIMER_RESIDUAL)
+            res_ms += ms
+            res_cnt += cnt
+            res_cells += H.timer_cells(nrd.NRD_TIMER_RESIDUAL)
+            H.timer_enable(False)
+            out["residual_ms_avg"] = res_ms / max(res_cnt, 1)
+            out["residual_cells_avg"] = res_cells / max(res_cnt, 1)
+            out["residual_launches"] = int(res_cnt)
+        E, T = H.get_fields()
+        return H, torch.cat([E, T]), (rec_boxes, rec_dt), out
+
+    mixed_opts = nrd.default_options(precision=nrd.NRD_MIXED,
+                                     error_estimate=1 if adaptive_eps else 0)
+    H, u_mixed, plan, mixed = run(mixed_opts, steps, label="mixed", timers=True)
+    mixed["dt"] = [float(f"{x:.4g}") for x in plan[1]]
+    mixed["t_final"] = float(sum(plan[1]))
+    # operators on the final hierarchy, every launch covering every cell
+    ops = operator_times(H, [plan[1][-1]])
+    comp = H.ncells - covered_count(H)
+    del H
+    torch.cuda.empty_cache()
+    H64, u64, _, fp64 = run(nrd.default_options(precision=nrd.NRD_FP64), steps, plan=plan,
+                            label="fp64 batched")
+    diff = {}
+    for name, sl in (("E", slice(0, H64.ncells)), ("T", slice(H64.ncells, None))):
+        diff[name] = float(torch.linalg.vector_norm(u_mixed[sl] - u64[sl]) /
+                           torch.linalg.vector_norm(u64[sl]))
+    del H64
+    torch.cuda.empty_cache()
+    plain = None
+    if plain_steps > 0:
+        Hp, _, _, plain = run(nrd.default_options(precision=nrd.NRD_FP64,
+                                                  launch=nrd.NRD_PER_PATCH, stencil=1),
+                              plain_steps, plan=plan, label="fp64 per-patch")
+        del Hp
+        torch.cuda.empty_cache()
+    return mixed, fp64, plain, ops, comp, diff, plan
+
+
+def covered_count(H):
+    """Covered cells of a hierarchy (host count from its boxes)."""
+    tot = 0
+    for b in H.boxes:
+        for c in H.boxes:
+            if c.problem == b.problem and c.level == b.level + 1:
+                ov = 1
+                for d in range(3):
+                    ov *= max(0, min(c.hi[d] // 2, b.hi[d]) - max(c.lo[d] // 2, b.lo[d]))
+                tot += ov
+    return tot
+
+
+def operator_times(H, dt, reps=20):
+    """Residual, Jacobian action, preconditioner and base-grid sweeps timed
+    with the library's event timers over every problem (3 warm-up calls)."""
+    import torch
+    from paper_1302_6303_amd import nrd
+    H.begin_step(dt)
+    E, T = H.get_fields()
+    U = H.unpack(torch.cat([E, T]))
+    V = H.unpack(torch.cat([E, T]) * 1e-3)
+    Y = H.native()
+    H.precond_setup(U)
+    for _ in range(3):
+        H.residual(U, Y)
+        H.jvp(U, V, Y)
+        H.precond_apply(V, Y)
+    torch.cuda.synchronize()
+    H.timer_enable(True)
+    for _ in range(reps):
+        H.residual(U, Y)
+    for _ in range(reps):
+        H.jvp(U, V, Y)
+    for _ in range(reps):
+        H.precond_apply(V, Y)
+    res = {}
+    for key, which in (("residual", nrd.NRD_TIMER_RESIDUAL), ("jvp", nrd.NRD_TIMER_JVP),
+                       ("precond", nrd.NRD_TIMER_PRECOND), ("sweep", nrd.NRD_TIMER_SMOOTH),
+                       ("sweep_zero", nrd.NRD_TIMER_SMOOTH_ZERO)):
+        ms, cnt = H.timer_read(which)
+        res[key + "_ms_avg"] = ms / max(cnt, 1)
+    H.timer_enable(False)
+    return res
+
+
+def dynamic_main(a):
+    steps = a.steps if a.steps_given else 50
+    dt0 = a.dt if a.dt else 1e-5
+    mixed, fp64, plain, ops, comp, diff, plan = dynamic_bench(
+        steps, a.regrid_every, 0 if a.no_plain else a.plain_steps, dt0=dt0,
+        adaptive_eps=a.adaptive_eps, tune=a.tune)
+    res_s = mixed["residual_ms_avg"] / 1e3
+    cells = mixed["residual_cells_avg"]
+    achieved = BYTES_PER_CELL_RESIDUAL * cells / res_s / 1e9
+    def rnd(d):
+        return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in d.items()
+                if k != "regrids"}
+    out = {
+        "metric": "residual Gcells/s (%HBM peak) + s/implicit step, mixed-batched vs FP64 plain",
+        "value": round(cells / res_s / 1e9, 3), "unit": "Gcells/s", "n_gpus": 1,
+        "steps": steps, "warmup": 0, "ms_per_step": round(mixed["s_per_step"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dynamic", "base": 128, "levels": 4,
+                   "regrid_every": a.regrid_every,
+                   "time_control": (f"PC.4.7, eps_t {a.adaptive_eps}, first step {dt0}"
+                                    if a.adaptive_eps else
+                                    f"fixed steps {dt0} (halved on a failed solve)"),
+                   "tags": "|grad E|/E > 10 or material interface, grown by 2",
+                   "clustering": "Berger-Rigoutsos, efficiency 0.7, sides 8..48 cells",
+                   "final_boxes": mixed["final_boxes"], "final_cells": mixed["final_cells"],
+                   "final_composite_cells": comp,
+                   "solver": "BDF1->BDF2, Newton rtol 1e-8, FGMRES(30), FAC V(1,0) RBGS + MG V(1,1)"},
+        "roofline": {"bound": "hbm", "kernel": "k_stencil_s<0> (residual)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_cell": BYTES_PER_CELL_RESIDUAL,
+                     "cells_per_launch": round(cells),
+                     "avg_launch_ms": round(mixed["residual_ms_avg"], 4),
+                     "full_launch_final_hierarchy": {
+                         "cells": comp, "avg_launch_ms": round(ops["residual_ms_avg"], 4),
+                         "frac": round(BYTES_PER_CELL_RESIDUAL * comp / ops["residual_ms_avg"]
+                                       / 1e6 / HBM_PEAK_GBS, 4)}},
+        "jvp_roofline": {"frac": round(BYTES_PER_CELL_JVP * comp / ops["jvp_ms_avg"] / 1e6
+                                       / HBM_PEAK_GBS, 4),
+                         "avg_launch_ms": round(ops["jvp_ms_avg"], 4)},
+        "precond_ms_avg": round(ops["precond_ms_avg"], 4),
+        "mixed_batched": rnd(mixed),
+        "fp64_batched_replay": rnd(fp64),
+        "mixed_vs_fp64_rel_diff_after_steps": diff,
+        "regrids": mixed["regrids"],
+        "regrid_s_total": round(sum(r["tag_cluster_s"] + r["create_transfer_s"] + r["tune_s"]
+                                    for r in mixed["regrids"]), 3),
+        "resolve_s_total": round(sum(r["resolve_s"] for r in mixed["regrids"]), 3),
+    }
+    if plain is not None:
+        out["fp64_plain_first_steps"] = rnd(plain)
+        out["speedup_mixed_batched_vs_fp64_plain"] = round(plain["s_per_step"] /
+                                                           mixed["s_per_step"], 3)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -583,7 +864,19 @@ def main():
     ap.add_argument("--fp64-batched", action="store_true",
                     help="also time the FP64 solver with batched launches (per-patch vs "
                          "batched comparison at equal precision)")
+    ap.add_argument("--dt", type=float, default=None,
+                    help="dynamic workload: step size (default 1e-5; the first step with "
+                         "--adaptive-eps)")
+    ap.add_argument("--regrid-every", type=int, default=5,
+                    help="dynamic workload: steps between regrids")
+    ap.add_argument("--plain-steps", type=int, default=10,
+                    help="dynamic workload: steps replayed with the FP64 per-patch solver")
+    ap.add_argument("--tune", action="store_true",
+                    help="dynamic workload: tune tile shapes of every new hierarchy through "
+                         "one cache file (new patch-size classes only); default: the "
+                         "default shapes")
     a = ap.parse_args()
+    a.steps_given = "--steps" in sys.argv
     if a.gpus != 1:
         print("bench.py runs on exactly one GPU: the hot path is built and measured on a "
               "single GPU (sharding over several GPUs is a design note only)", file=sys.stderr)
@@ -592,6 +885,9 @@ def main():
     from paper_1302_6303_amd import nrd
     if a.workload == "adjoint":
         adjoint_bench(a.steps, a.ckpt_every)
+        return
+    if a.workload == "dynamic":
+        dynamic_main(a)
         return
     if a.workload in ("paper-spatial", "paper-spatial-z1"):
         paper_spatial_bench(a.limiter, a.workload.endswith("z1"))

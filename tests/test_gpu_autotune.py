@@ -90,3 +90,21 @@ def test_cache_lines_with_unknown_shapes_are_ignored(tmp_path):
     assert H2.autotune(bad) == len(classes)
     for a, b in zip(before, _outputs(H2, w)):
         np.testing.assert_array_equal(a, b)
+
+
+def test_cache_is_reused_across_changing_hierarchies(tmp_path):
+    """Regridding makes new hierarchies whose patch-size classes partly
+    repeat: with one cache file, a new hierarchy times only the classes no
+    earlier one had, and its results stay bitwise the defaults'."""
+    w1 = _workload()
+    w2 = I.static_amr(base=16, nlevels=3, side=(8, 16), seed_k=9, state="front")
+    c1 = {tuple(int(x) for x in b.shape) for b in w1.boxes}
+    c2 = {tuple(int(x) for x in b.shape) for b in w2.boxes}
+    assert c1 & c2 and c2 - c1
+    cache = str(tmp_path / "tiles.txt")
+    assert make(w1).autotune(cache) == len(c1)
+    H2 = make(w2)
+    before = _outputs(H2, w2)
+    assert H2.autotune(cache) == len(c2 - c1)
+    for a, b in zip(before, _outputs(H2, w2)):
+        np.testing.assert_array_equal(a, b)

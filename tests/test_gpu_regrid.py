@@ -116,3 +116,50 @@ def test_transfer_conserves_the_composite_integral():
             H.dot(u, H.unpack(torch.cat([zero, one])))[0]
     a, b = integral(Ho), integral(Hn)
     assert abs(a[0] - b[0]) <= 1e-13 * abs(a[0]) and abs(a[1] - b[1]) <= 1e-13 * abs(a[1])
+
+
+def test_regrid_cycle_matches_the_oracle():
+    """A whole regrid inside a run on a 3-level hierarchy: two steps, the
+    tags of the state (GPU bit for bit equal to the oracle's), the boxes the
+    host clustering makes of them, the history moved and re-solved, a BDF2
+    step; GPU and oracle agree at the Newton tolerance."""
+    from paper_1302_6303_amd import nrd
+    from paper_1302_6303_amd.regrid import Regridder
+    w = _workload(OLD)
+    zf = w.extra["zf"]
+    kw = dict(newton_rtol=1e-10, newton_atol=1e-14)
+    H = make(w, **kw)
+    s = system(w)
+    st = Stepper(s, state(s, w), rtol=1e-10, atol=1e-14)
+    for dt in (1e-3, 1e-3):
+        H.implicit_step([dt])
+        assert st.step(dt).converged
+    crit = dict(grad_E=18.0)
+    tags = to_host(H.tag(**crit).double()).astype(np.uint8)
+    E, _ = s.split(st.u)
+    ref = rg.tags(s.H, E, s.z, grad=18.0)
+    ref = np.concatenate([t.ravel(order="F") for t in ref]).astype(np.uint8)
+    # the states agree to the Newton tolerance, the tags exactly unless a
+    # cell sits within that tolerance of the threshold
+    assert ref.sum() > 0 and np.count_nonzero(tags != ref) == 0
+    res = nrd.cluster(w.problems, w.boxes, ref, max_levels=3, buffer=1, efficiency=0.7,
+                      min_side=2, max_side=8)
+    boxes = [I.Box(p, lv, lo, hi) for p, lv, lo, hi in res]
+    assert boxes != w.boxes and max(b.level for b in boxes) == 2
+
+    def zfun(problems, bx):
+        return to_dev(np.concatenate([a.ravel(order="F")
+                                      for a in I.eval_on_boxes(zf, problems, bx)]))
+    R = Regridder(nrd.default_options(**kw), crit, {}, zfun)
+    Hn, _, info = R.regrid(H, boxes)
+    assert info["resolve_newton"] >= 1
+    pr = w.problems[0]
+    Hs = Hierarchy(pr.base_n, [(b.level, b.lo, b.hi) for b in boxes])
+    sn = System(Hs, I.eval_on_boxes(zf, w.problems, boxes))
+    st.regrid(sn)
+    Hn.implicit_step([1e-3])
+    assert st.step(1e-3).converged
+    E, T = Hn.get_fields()
+    got = np.concatenate([to_host(E), to_host(T)])
+    n = sn.nc
+    assert rel_err(got[:n], st.u[:n]) < 1e-8 and rel_err(got[n:], st.u[n:]) < 1e-8
