@@ -546,23 +546,34 @@ def adjoint_bench(nsteps, every, reps=20):
 def material_sampler(mboxes):
     """zfun(problems, boxes): the compact material field of a box list on the
     device (z of the last material box holding a cell centre, 1 elsewhere;
-    the same rule and arithmetic as inputs.box_field)."""
+    the same rule and arithmetic as inputs.box_field), evaluated for all
+    cells at once from their flat compact index."""
     def zfun(problems, boxes):
         import torch
-        outs = []
-        for b in boxes:
-            pr = problems[b.problem]
-            h = pr.h(b.level)
-            ax = [(torch.arange(b.lo[d], b.hi[d], dtype=torch.float64, device="cuda") + 0.5)
-                  * float(h[d]) + float(pr.lo[d]) for d in range(3)]
-            Zc, Yc, Xc = torch.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
-            z = torch.ones_like(Xc)
-            for lo, hi, zv in mboxes:
-                m = ((Xc >= lo[0]) & (Xc < hi[0]) & (Yc >= lo[1]) & (Yc < hi[1])
-                     & (Zc >= lo[2]) & (Zc < hi[2]))
-                z[m] = zv
-            outs.append(z.reshape(-1))
-        return torch.cat(outs)
+        dev = "cuda"
+        ext = torch.tensor([[b.hi[d] - b.lo[d] for d in range(3)] for b in boxes],
+                           dtype=torch.int64, device=dev)
+        lo = torch.tensor([list(b.lo) for b in boxes], dtype=torch.int64, device=dev)
+        h = torch.tensor([list(problems[b.problem].h(b.level)) for b in boxes],
+                         dtype=torch.float64, device=dev)
+        plo = torch.tensor([list(problems[b.problem].lo) for b in boxes],
+                           dtype=torch.float64, device=dev)
+        n = ext.prod(dim=1)
+        start = torch.cumsum(n, 0) - n
+        idx = torch.arange(int(n.sum()), dtype=torch.int64, device=dev)
+        bid = torch.searchsorted(start, idx, right=True) - 1
+        loc = idx - start[bid]
+        e = ext[bid]
+        ijk = torch.stack([loc % e[:, 0], (loc // e[:, 0]) % e[:, 1],
+                           loc // (e[:, 0] * e[:, 1])], dim=1)
+        X = [(ijk[:, d] + lo[bid, d]).to(torch.float64) for d in range(3)]
+        X = [(X[d] + 0.5) * h[bid, d] + plo[bid, d] for d in range(3)]
+        z = torch.ones_like(X[0])
+        for blo, bhi, zv in mboxes:
+            m = ((X[0] >= blo[0]) & (X[0] < bhi[0]) & (X[1] >= blo[1]) & (X[1] < bhi[1])
+                 & (X[2] >= blo[2]) & (X[2] < bhi[2]))
+            z[m] = zv
+        return z
     return zfun
 
 
