@@ -26,7 +26,8 @@ Readings (the paper is silent or terse):
   correction and covered cells are re-synchronised;
 * red cells (even i+j+k in level index space) are relaxed first; sibling
   ghosts are refreshed between the two half-sweeps;
-* base multigrid: coarsen by 2 while every extent is even and > 5; coarse
+* base multigrid on the base grid gathered from the level-0 patches (which
+  tile it): coarsen by 2 while every extent is even and > 5; coarse
   face coefficient = mean of the four fine ones it covers; boundary cells
   re-discretised with the coarse h; restriction = mean of 8; bottom grid
   solved exactly (dense);
@@ -324,12 +325,40 @@ def can_coarsen(n):
     return all(v % 2 == 0 and v > 5 for v in n)
 
 
+def gather_base(H, arrs):
+    """The level-0 patches' interior arrays as one array over the base grid
+    (level 0 tiles it)."""
+    out = np.zeros(tuple(int(v) for v in H.base_n))
+    for p in H.by_level[0]:
+        out[tuple(slice(int(p.lo[d]), int(p.hi[d])) for d in range(3))] = arrs[p.pid]
+    return out
+
+
+def scatter_base(H, full):
+    """{pid: interior array} of the level-0 patches cut from a base-grid array."""
+    return {p.pid: full[tuple(slice(int(p.lo[d]), int(p.hi[d])) for d in range(3))].copy()
+            for p in H.by_level[0]}
+
+
 def build_mg(H, snap, f):
-    if len(H.by_level[0]) != 1:
-        raise NotImplementedError("base multigrid needs one level-0 box")
-    p = H.by_level[0][0]
-    g = MGGrid(p.n, H.h(0), [a.copy() for a in snap.D[f][p.pid]],
-               list(snap.robin[f][p.pid]))
+    """Multigrid grids below level 0: grid 0 is the base grid gathered from
+    the level-0 patches (a face shared by two patches carries the same
+    frozen coefficient in both), coarsened by 2 while every extent is even
+    and > 5."""
+    n = tuple(int(v) for v in H.base_n)
+    D = []
+    for d in range(3):
+        shape = list(n)
+        shape[d] += 1
+        Dd = np.zeros(shape)
+        for p in H.by_level[0]:
+            sl = [slice(int(p.lo[a]), int(p.hi[a])) for a in range(3)]
+            sl[d] = slice(int(p.lo[d]), int(p.hi[d]) + 1)
+            Dd[tuple(sl)] = snap.D[f][p.pid][d]
+        D.append(Dd)
+    robin = [((H.bc_E[2 * d] == 1 and f == 0), (H.bc_E[2 * d + 1] == 1 and f == 0))
+             for d in range(3)]
+    g = MGGrid(n, H.h(0), D, robin)
     grids = [g]
     while can_coarsen(grids[-1].n):
         grids.append(grids[-1].coarsen())
@@ -562,11 +591,11 @@ def fac_vcycle(H, snap, f, rhs, mg_grids=None, nu=None):
         if lev > 0 or base_smooth:
             corr = smooth(lev, rg, m_pre)
         else:
-            p0 = H.by_level[0][0]
             if mg_grids is None:
                 mg_grids = build_mg(H, snap, f)
-            corr = {p0.pid: mg_vcycle(mg_grids, snap.beta,
-                                      rg[p0.pid][1:-1, 1:-1, 1:-1])}
+            rhs0 = gather_base(H, {p.pid: rg[p.pid][1:-1, 1:-1, 1:-1]
+                                   for p in H.by_level[0]})
+            corr = scatter_base(H, mg_vcycle(mg_grids, snap.beta, rhs0))
         correct(lev, corr)
     if n_post > 0:
         for lev in range(1, L + 1):

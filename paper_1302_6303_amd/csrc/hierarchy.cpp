@@ -208,18 +208,33 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
     // level structure, alignment, bounds, overlap
     for (int p = 0; p < nprob; ++p) {
         const auto& L = t.level_patches[p];
-        if (L[0].size() != 1) {
-            err << "problem " << p << ": needs exactly one level-0 box";
+        // level 0: non-overlapping boxes inside the base grid that tile it
+        int64_t vol0 = 0, base = 1;
+        for (int d = 0; d < 3; ++d) base *= probs[p].base_n[d];
+        for (size_t a = 0; a < L[0].size(); ++a) {
+            const HostBox& x = t.boxes[L[0][a]];
+            int64_t v = 1;
+            for (int d = 0; d < 3; ++d) {
+                if (x.lo[d] < 0 || x.hi[d] > probs[p].base_n[d]) {
+                    err << "box " << L[0][a] << " outside the base grid";
+                    msg = err.str();
+                    return NRD_ENESTING;
+                }
+                v *= x.hi[d] - x.lo[d];
+            }
+            vol0 += v;
+            for (size_t c = a + 1; c < L[0].size(); ++c)
+                if (intersect(x.lo, x.hi, t.boxes[L[0][c]].lo, t.boxes[L[0][c]].hi) > 0) {
+                    err << "boxes " << L[0][a] << " and " << L[0][c] << " overlap";
+                    msg = err.str();
+                    return NRD_ENESTING;
+                }
+        }
+        if (L[0].empty() || vol0 != base) {
+            err << "problem " << p << ": the level-0 boxes must tile the base grid";
             msg = err.str();
             return NRD_ENESTING;
         }
-        const HostBox& b0 = t.boxes[L[0][0]];
-        for (int d = 0; d < 3; ++d)
-            if (b0.lo[d] != 0 || b0.hi[d] != probs[p].base_n[d]) {
-                err << "problem " << p << ": level-0 box must cover the base grid";
-                msg = err.str();
-                return NRD_ENESTING;
-            }
         for (int l = 1; l < t.nlev; ++l) {
             if (!L[l].empty() && L[l - 1].empty()) {
                 err << "problem " << p << ": level " << l << " without level " << l - 1;
@@ -593,6 +608,23 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
         }
         t.prob_mgdepth[p] = depth;
         maxdepth = std::max(maxdepth, depth);
+        // a base grid cut into several boxes: the multigrid below it works on
+        // the whole base grid coarsened once, whose cells must each have
+        // their eight children in one level-0 box
+        if (t.level_patches[p][0].size() > 1) {
+            if (depth == 0) {
+                msg = "a base grid cut into several level-0 boxes must coarsen at least once "
+                      "(even extents above 5)";
+                return NRD_EUNSUPPORTED;
+            }
+            for (int32_t b : t.level_patches[p][0])
+                for (int d = 0; d < 3; ++d)
+                    if ((t.boxes[b].lo[d] & 1) || (t.boxes[b].hi[d] & 1)) {
+                        msg = "level-0 boxes of a base grid cut into several boxes must start "
+                              "and end on even planes";
+                        return NRD_EUNSUPPORTED;
+                    }
+        }
     }
     t.mg.assign(maxdepth + 1, MGLevel());
     for (int g = 1; g <= maxdepth; ++g) {

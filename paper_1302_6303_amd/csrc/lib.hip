@@ -104,7 +104,7 @@ struct nrd_hierarchy final : public Clock {
             rcells, ctype, shadows, shadow_src, coff, ps, active, amap;
         size_t mg_box[kMaxMG], mg_tiles[kMaxMG], mg_box_of[kMaxMG], mg_smooth[kMaxMG],
             mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bot_probs, bot_boxes, bot_grid, bottom_off,
-            Lbuf, Xbuf;
+            Lbuf, Xbuf, mg_l0map;
         size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, gz3, V, Z, pred;
         size_t pc_D, pc_sigma, pc_e, pc_e2, pc_u, pc_r, pc_f, pc_shadow;
         size_t mg_D[kMaxMG], mg_e[kMaxMG], mg_f[kMaxMG];
@@ -255,6 +255,9 @@ static void layout(nrd_hierarchy* h) {
         o.mg_bprobs[g] = b.take(sizeof(int32_t) * nprob);
         o.mg_bboxes[g] = b.take(sizeof(int32_t) * nprob);
     }
+    // per native cell of the first multigrid grid: the level-0 patch that
+    // holds its eight children
+    o.mg_l0map = b.take(sizeof(int32_t) * std::max<int64_t>(1, G >= 1 ? t.mg[1].len : 1));
     o.bot_probs = b.take(sizeof(int32_t) * nprob);
     o.bot_boxes = b.take(sizeof(int32_t) * nprob);
     o.bot_grid = b.take(sizeof(int32_t) * nprob);
@@ -365,6 +368,8 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
         pc.mg.bottom_probs[g] = h->at<int32_t>(o.mg_bprobs[g]);
         pc.mg.bottom_boxes[g] = h->at<int32_t>(o.mg_bboxes[g]);
     }
+    pc.mg.l0map = G >= 1 ? h->at<int32_t>(o.mg_l0map) : nullptr;
+    pc.mg.multi0 = t.level_sib0[1] > t.level_sib0[0];
     pc.mg.bottom_off = h->at<int64_t>(o.bottom_off);
     pc.mg.bot_probs = h->at<int32_t>(o.bot_probs);
     pc.mg.bot_boxes = h->at<int32_t>(o.bot_boxes);
@@ -441,6 +446,30 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
         nbottom[g] = (int)bp.size();
         HIPCHK(up(s, h->ws + o.mg_bprobs[g], bp));
         HIPCHK(up(s, h->ws + o.mg_bboxes[g], bb));
+    }
+    if (G >= 1) {
+        // children of every first-grid cell: one level-0 patch (level-0 boxes
+        // of a tiled base start and end on even planes)
+        const MGLevel& M = t.mg[1];
+        std::vector<int32_t> l0(M.len, -1);
+        for (size_t i = 0; i < M.boxes.size(); ++i) {
+            const PatchInfo& g1 = M.boxes[i];
+            const int p = M.probs[i];
+            for (int32_t b : t.level_patches[p][0]) {
+                const HostBox& x = t.boxes[b];
+                int32_t lo[3], hi[3];
+                for (int d = 0; d < 3; ++d) {
+                    lo[d] = x.lo[d] / 2;
+                    hi[d] = (x.hi[d] + 1) / 2;
+                }
+                for (int k = lo[2]; k < hi[2]; ++k)
+                    for (int j = lo[1]; j < hi[1]; ++j)
+                        for (int ii = lo[0]; ii < hi[0]; ++ii)
+                            l0[g1.off + (ii + 1) + (int64_t)g1.sy * (j + 1) +
+                               (int64_t)g1.sz * (k + 1)] = b;
+            }
+        }
+        HIPCHK(up(s, h->ws + o.mg_l0map, l0));
     }
     std::vector<int64_t> boff(t.nprob);
     for (int p = 0; p < t.nprob; ++p) boff[p] = t.bottom_off[p];

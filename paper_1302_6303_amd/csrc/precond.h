@@ -66,6 +66,10 @@ struct PcArrays {
         const int64_t* bottom_off = nullptr;
         double* Lbuf = nullptr;
         double* Xbuf = nullptr;
+        // first grid: per native cell, the level-0 patch of its children
+        // (a base grid cut into several boxes); multi0: level 0 has siblings
+        const int32_t* l0map = nullptr;
+        bool multi0 = false;
         // all problems with their coarsest grid (one setup launch)
         const int32_t* bot_probs = nullptr;
         const int32_t* bot_boxes = nullptr;

@@ -95,22 +95,27 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const int32_t* __restrict__
 
 // Coarse face coefficient = mean of the four fine face coefficients
 // (grid g+1 from grid g); boundary faces included.
+// fmap (may be NULL): per coarse native cell, the fine patch holding its
+// children (a base grid cut into several level-0 boxes); else the problem's
+// one fine box fbox[prob].  Coarse boxes start at 0, so a coarse cell's
+// first child is at 2 id - lo of its fine patch.
 template <typename PT>
 __global__ __launch_bounds__(kBlock) void k_mg_coarsen(const int32_t* __restrict__ act, 
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pc,
     const PatchInfo* __restrict__ Pf, const int32_t* __restrict__ fbox,
+    const int32_t* __restrict__ fmap,
     const PT* __restrict__ Df, int64_t nlf, PT* __restrict__ Dc, int64_t nlc) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& pc = Pc[t.patch];
-    const PatchInfo& pf = Pf[fbox[t.prob]];
     int id[3];
     coords(pc, t.start + threadIdx.x, id[0], id[1], id[2]);
     const int c = nat(pc, id[0], id[1], id[2]);
+    const PatchInfo& pf = Pf[fmap ? fmap[c] : fbox[t.prob]];
     const int stc[3] = {1, pc.sy, pc.sz};
     const int stf[3] = {1, pf.sy, pf.sz};
-    const int f0 = nat(pf, 2 * id[0], 2 * id[1], 2 * id[2]);
+    const int f0 = nat(pf, 2 * id[0] - pf.lo[0], 2 * id[1] - pf.lo[1], 2 * id[2] - pf.lo[2]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int t1 = d == 0 ? 1 : 0;
@@ -465,23 +470,23 @@ __global__ __launch_bounds__(kBlock) void k_add_level(const int32_t* __restrict_
 // zero and only the four colour-0 children of each coarse cell are
 // evaluated; the residual is never stored.  Four lanes per coarse cell, one
 // child each, summed across the lanes in a fixed order.
+// fmap: as in k_mg_coarsen.  The children of a coarse cell start at an even
+// level index, so its colour-0 children are those with an even offset sum.
 template <typename PT>
 __global__ __launch_bounds__(kBlock) void k_mg_res_restrict(const int32_t* __restrict__ act,
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pc,
     const PatchInfo* __restrict__ Pf, const int32_t* __restrict__ fbox,
+    const int32_t* __restrict__ fmap,
     const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
     const PT* __restrict__ D, const PT* __restrict__ f, const PT* __restrict__ e, int64_t nlf,
     PT* __restrict__ fc, int64_t nlc) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // uniform over the workgroup
     const PatchInfo& pc = Pc[t.patch];
-    const PatchInfo& pf = Pf[fbox[t.prob]];
     const double beta = ps[t.prob].beta;
-    const int lo = pf.lo[0] + pf.lo[1] + pf.lo[2];
-    // colour-0 children (bit 0: x, 1: y, 2: z offset): an even offset sum when
-    // lo is even, odd otherwise
+    // colour-0 children (bit 0: x, 1: y, 2: z offset)
     const int lane = threadIdx.x & 3;
-    const int child = (lane == 0 ? 0 : (lane == 1 ? 3 : (lane == 2 ? 5 : 6))) ^ ((lo & 1) ? 7 : 0);
+    const int child = lane == 0 ? 0 : (lane == 1 ? 3 : (lane == 2 ? 5 : 6));
     for (int q0 = 0; q0 < t.count; q0 += kBlock / 4) {
         const int q = q0 + ((int)threadIdx.x >> 2);
         const bool live = q < t.count;
@@ -489,8 +494,10 @@ __global__ __launch_bounds__(kBlock) void k_mg_res_restrict(const int32_t* __res
         if (live) coords(pc, t.start + q, id[0], id[1], id[2]);
         PT v0 = PT(0), v1 = PT(0);
         if (live) {
-            const int fid[3] = {2 * id[0] + (child & 1), 2 * id[1] + ((child >> 1) & 1),
-                                2 * id[2] + (child >> 2)};
+            const PatchInfo& pf = Pf[fmap ? fmap[nat(pc, id[0], id[1], id[2])] : fbox[t.prob]];
+            const int fid[3] = {2 * id[0] + (child & 1) - pf.lo[0],
+                                2 * id[1] + ((child >> 1) & 1) - pf.lo[1],
+                                2 * id[2] + (child >> 2) - pf.lo[2]};
             const int c = nat(pf, fid[0], fid[1], fid[2]);
             PT dg[2], ns[2];
             level_terms<PT, false>(pf, fid, c, beta, ctype, D, e, nlf, dg, ns);
@@ -525,8 +532,9 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(const int32_t* __restrict
     int q[3], nbq[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        q[d] = id[d] >> 1;
-        const int o = (id[d] & 1) ? 1 : -1;
+        const int I = pf.lo[d] + id[d];            // fine level index (coarse box at 0)
+        q[d] = I >> 1;
+        const int o = (I & 1) ? 1 : -1;
         nbq[d] = min(max(q[d] + o, 0), pc.n[d] - 1);
     }
     for (int fld = 0; fld < 2; ++fld) {
@@ -884,8 +892,9 @@ void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
         const int64_t nlf = (g == 1) ? d.nl : mg.len[g - 1];
         const PatchInfo* Pf = (g == 1) ? d.patches : mg.box[g - 1];
         k_mg_coarsen<PT><<<mg.ntiles[g], kBlock, 0, s>>>(d.active, mg.tiles[g], mg.box[g], Pf,
-                                                         mg.box_of[g - 1], Df, nlf, mg.Dg[g],
-                                                         mg.len[g]);
+                                                         mg.box_of[g - 1],
+                                                         g == 1 ? mg.l0map : nullptr, Df, nlf,
+                                                         mg.Dg[g], mg.len[g]);
     }
     // every problem's coarsest grid in one launch
     BottomGrids<PT> bg;
@@ -913,23 +922,29 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
         if (mg.nsmooth[g] > 0) {
             const Tile* tl = mg.smooth_tiles[g];
             const int nt = mg.nsmooth[g];
+            // a base grid cut into several boxes: sibling ghosts refreshed
+            // after every half-sweep that the next one reads
+            const bool sib = g == 0 && mg.multi0;
             for (int it = 0; it < nu_pre; ++it) {
                 const int which = it == 0 ? NRD_TIMER_SMOOTH_ZERO : NRD_TIMER_SMOOTH;
                 std::pair<hipEvent_t, hipEvent_t> tk{nullptr, nullptr};
                 if (g == 0 && clock) tk = clock->tic(which);
+                if (sib && it > 0) siblings(s, eg, 0);
                 if (it == 0)
                     k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
                                                         0, nlg);
                 else
                     k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
                                                         0, nlg);
+                if (sib) siblings(s, eg, 0);
                 k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
                                                     1, nlg);
                 if (g == 0 && clock) clock->toc(which, tk);
             }
+            if (sib) siblings(s, eg, 0);
             k_mg_res_restrict<PT><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active,
-                mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g], d.ps, d.ctype, Dg, fg, eg, nlg,
-                mg.fg[g + 1], mg.len[g + 1]);
+                mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g], g == 0 ? mg.l0map : nullptr,
+                d.ps, d.ctype, Dg, fg, eg, nlg, mg.fg[g + 1], mg.len[g + 1]);
         }
         if (mg.nbottom[g] > 0)
             k_bottom_apply<PT><<<2 * mg.nbottom[g], kBlock, 0, s>>>(d.active, 
@@ -947,11 +962,14 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
         const int nt = mg.nsmooth[g];
         k_mg_prolong<PT><<<nt, kBlock, 0, s>>>(d.active, tl, Pg, mg.box[g + 1], mg.box_of[g + 1],
                                               mg.eg[g + 1], mg.len[g + 1], eg, nlg);
+        const bool sib = g == 0 && mg.multi0;
         for (int it = 0; it < nu_post; ++it) {
             std::pair<hipEvent_t, hipEvent_t> tk{nullptr, nullptr};
             if (g == 0 && clock) tk = clock->tic(NRD_TIMER_SMOOTH);
+            if (sib) siblings(s, eg, 0);
             k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, 0,
                                                 nlg);
+            if (sib) siblings(s, eg, 0);
             k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, 1,
                                                 nlg);
             if (g == 0 && clock) clock->toc(NRD_TIMER_SMOOTH, tk);

@@ -434,6 +434,24 @@ def multi_patch_uniform(n=16, cuts=(6, 11), seed_k=7, state="front"):
     return Workload(f"siblings{n}", [prob], boxes, z, E, T, np.array([1e-3]), 1)
 
 
+def tiled_base(n=16, seed_k=10, state="front", refine=True):
+    """One problem whose base grid is cut into four level-0 boxes at even
+    planes (x = 6 and 10, and y = 8 between them), optionally with a level-1
+    box that straddles the cuts."""
+    rng = np.random.default_rng(SEED_BASE + seed_k)
+    prob = Problem(base_n=(n, n, n))
+    a, b, c = 6 * n // 16, 10 * n // 16, n // 2
+    boxes = [Box(0, 0, (0, 0, 0), (a, n, n)), Box(0, 0, (a, 0, 0), (b, c, n)),
+             Box(0, 0, (a, c, 0), (b, n, n)), Box(0, 0, (b, 0, 0), (n, n, n))]
+    if refine:
+        boxes.append(Box(0, 1, (n // 2, 3 * n // 8, 5 * n // 8),
+                         (3 * n // 2, 11 * n // 8, 11 * n // 8)))
+    zf = box_field(sample_material_boxes(rng, 2))
+    z = eval_on_boxes(zf, [prob], boxes)
+    E, T = front_state([prob], boxes, rng) if state == "front" else uniform_state(boxes)
+    return Workload(f"tiled{n}", [prob], boxes, z, E, T, np.array([1e-3]), 1)
+
+
 def small_amr(base=8, seed_k=8, state="front", boxes_spec=None):
     """Tiny hand-built 2- or 3-level hierarchy for oracle/GPU parity."""
     rng = np.random.default_rng(SEED_BASE + seed_k)

@@ -38,7 +38,9 @@ def test_layout_counts():
     ([(0, (0, 0, 0), (8, 8, 8)), (1, (0, 0, 0), (4, 4, 4)), (1, (2, 2, 2), (6, 6, 6))], -2),
     ([(0, (0, 0, 0), (8, 8, 8)), (1, (1, 2, 2), (5, 6, 6))], -2),
     ([(0, (0, 0, 0), (8, 8, 8)), (1, (2, 2, 2), (6, 6, 6)), (2, (4, 4, 4), (10, 10, 10))], -2),
-    ([(0, (0, 0, 0), (4, 8, 8)), (0, (4, 0, 0), (8, 8, 8))], -2),       # two level-0 boxes
+    ([(0, (0, 0, 0), (4, 8, 8)), (0, (4, 0, 0), (8, 8, 6))], -2),       # level 0 not tiled
+    ([(0, (0, 0, 0), (4, 8, 8)), (0, (2, 0, 0), (8, 8, 8))], -2),       # level 0 overlaps
+    ([(0, (0, 0, 0), (3, 8, 8)), (0, (3, 0, 0), (8, 8, 8))], -7),       # tiled at an odd plane
     ([(0, (0, 0, 0), (8, 8, 8)), (2, (4, 4, 4), (8, 8, 8))], -2),       # level gap
     ([(1, (2, 2, 2), (6, 6, 6)), (0, (0, 0, 0), (8, 8, 8))], -1),       # unordered
 ])
@@ -48,6 +50,20 @@ def test_invalid_hierarchies_are_rejected(boxes, status):
     with pytest.raises(nrd.NrdError) as e:
         _create([I.Problem((8, 8, 8))], bx)
     assert e.value.status == status
+
+
+def test_tiled_base_levels_are_accepted():
+    """The coarsest level is a union of patches (Sec. 3.2): level-0 boxes
+    that tile the base grid at even planes, with finer boxes across the
+    cuts; a base grid that cannot coarsen must stay one box."""
+    from paper_1302_6303_amd import nrd
+    w = I.tiled_base(16)
+    H = _create(w.problems, w.boxes)
+    assert H.ncells == sum(b.ncells for b in w.boxes)
+    with pytest.raises(nrd.NrdError) as e:
+        _create([I.Problem((5, 5, 5))], [I.Box(0, 0, (0, 0, 0), (2, 5, 5)),
+                                          I.Box(0, 0, (2, 0, 0), (5, 5, 5))])
+    assert e.value.status == nrd.NRD_EUNSUPPORTED
 
 
 def test_bad_options_are_rejected():

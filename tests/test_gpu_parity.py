@@ -62,6 +62,10 @@ def workloads():
         "amr3": lambda: I.static_amr(base=16, nlevels=3, side=(8, 16), state="front"),
         "amr4": lambda: I.static_amr(base=8, nlevels=4, side=(8, 16), seed_k=3,
                                      state="front"),
+        # base grid cut into four level-0 boxes, without and with a level-1
+        # box across the cuts
+        "tiled0": lambda: I.tiled_base(16, refine=False),
+        "tiled": lambda: I.tiled_base(16),
     }
 
 
@@ -243,7 +247,7 @@ def test_precond_parity_noncubic():
             assert rel_err(g[f], ref[f]) < 1e-10
 
 
-@pytest.mark.parametrize("name", ["uniform16", "uniform10"])
+@pytest.mark.parametrize("name", ["uniform16", "uniform10", "tiled0"])
 def test_vjp_parity(name):
     w, s, H, u_n, u, dt = _setup(name)
     rng = np.random.default_rng(9)
@@ -266,7 +270,7 @@ def test_vjp_parity(name):
     assert np.all(np.abs(to_host(gz) - refz) <= 1e-12 * zscale + 1e-300)
 
 
-@pytest.mark.parametrize("name", ["uniform16", "amr2"])
+@pytest.mark.parametrize("name", ["uniform16", "amr2", "tiled"])
 def test_implicit_steps_parity(name):
     from oracle.solvers import Stepper
     w = WL[name]()

@@ -188,3 +188,68 @@ def test_fac_contraction_is_level_independent():
     rates = [_fac_rate_E(L) for L in (2, 3, 4)]
     assert max(rates) < 0.6, rates
     assert rates[2] - rates[1] < 0.05 and rates[1] - rates[0] < 0.12, rates
+
+
+def _untiled(w):
+    """The workload with its level-0 boxes merged into one (same values)."""
+    from oracle import precond as pc_
+    base = [b for b in w.boxes if b.level == 0]
+    n = w.problems[0].base_n
+    H = Hierarchy(n, [(0, b.lo, b.hi) for b in base])
+    idx = [i for i, b in enumerate(w.boxes) if b.level == 0]
+    rest = [i for i, b in enumerate(w.boxes) if b.level > 0]
+    merge = lambda arrs: [pc_.gather_base(H, {q: arrs[i] for q, i in enumerate(idx)})] + \
+        [arrs[i] for i in rest]
+    boxes = [I.Box(0, 0, (0, 0, 0), tuple(n))] + [w.boxes[i] for i in rest]
+    return I.Workload(w.name + "-merged", w.problems, boxes, merge(w.z), merge(w.E),
+                      merge(w.T), w.dt, w.nsteps)
+
+
+def test_tiled_base_level_is_the_single_base_box():
+    """Level 0 cut into four boxes (siblings at even planes, a level-1 box
+    across the cuts): residual, preconditioner and a BDF step equal those of
+    the same hierarchy with one level-0 box (Sec. 3.2: the coarsest level is
+    a union of patches)."""
+    w = I.tiled_base(16)
+    m = _untiled(w)
+    sw, sm = system(w), system(m)
+    uw, um = state(sw, w), state(sm, m)
+    Ew, Tw = sw.split(uw)
+    Em, Tm = sm.split(um)
+
+    def by_cell(H, arrs):
+        d = {}
+        for p in H.patches:
+            for lev_key, v in _by_index(H, arrs, p.level).items():
+                d[(p.level,) + lev_key] = v
+        return d
+    for E1, H1, E2, H2 in ((Ew, sw.H, Em, sm.H),):
+        a, b = by_cell(H1, E1), by_cell(H2, E2)
+        assert a == b                          # same input cell by cell
+    dt = 2e-3
+    Fw = sw.split(sw.residual(uw, uw, dt, 1.0))
+    Fm = sm.split(sm.residual(um, um, dt, 1.0))
+    for f in (0, 1):
+        a, b = by_cell(sw.H, Fw[f]), by_cell(sm.H, Fm[f])
+        for k in a:
+            assert a[k] == b[k], ("residual", f, k)
+    rng = np.random.default_rng(3)
+    vw = rng.standard_normal(uw.shape)
+    vE, vT = sw.split(vw)
+    vm = sm.join(*[_untiled_arrays(w, x) for x in (vE, vT)])
+    Pw, _ = sw.precond(uw, dt)
+    Pm, _ = sm.precond(um, dt)
+    yw, ym = sw.split(Pw(vw)), sm.split(Pm(vm))
+    for f in (0, 1):
+        a, b = by_cell(sw.H, yw[f]), by_cell(sm.H, ym[f])
+        for k in a:
+            assert abs(a[k] - b[k]) <= 1e-13 * max(1.0, abs(b[k])), ("precond", f, k)
+
+
+def _untiled_arrays(w, arrs):
+    from oracle import precond as pc_
+    base_i = [i for i, b in enumerate(w.boxes) if b.level == 0]
+    n = w.problems[0].base_n
+    H = Hierarchy(n, [(0, w.boxes[i].lo, w.boxes[i].hi) for i in base_i])
+    full = pc_.gather_base(H, {q: arrs[i] for q, i in enumerate(base_i)})
+    return [full] + [arrs[i] for i, b in enumerate(w.boxes) if b.level > 0]
