@@ -89,7 +89,8 @@ enum { NRD_FP64 = 0, NRD_MIXED = 1 };            /* preconditioner precision */
 enum { NRD_BATCHED = 0, NRD_PER_PATCH = 1 };     /* kernel launch grouping   */
 enum { NRD_JVP_ANALYTIC = 0, NRD_JVP_FD = 1 };
 enum { NRD_P2_PAPER = 0, NRD_P2_FROZEN4 = 1 };
-enum { NRD_SMOOTH_RBGS = 0, NRD_SMOOTH_JACOBI = 1 };  /* FAC level smoother */
+enum { NRD_SMOOTH_RBGS = 0, NRD_SMOOTH_JACOBI = 1,   /* FAC level smoother */
+       NRD_SMOOTH_LINE = 2 };
 enum { NRD_BASE_MG = 0, NRD_BASE_SMOOTH = 1 };       /* FAC base level     */
 
 typedef struct {
@@ -137,8 +138,11 @@ typedef struct {
                                residual refreshed with every correction so
                                far (default 0: the paper's V(1,0))           */
     int32_t fac_smoother;   /* FAC level smoother (Sec. 4.3): NRD_SMOOTH_RBGS
-                               (default) or NRD_SMOOTH_JACOBI, damped point
-                               Jacobi with weight 6/7                        */
+                               (default), NRD_SMOOTH_JACOBI, damped point
+                               Jacobi with weight 6/7, or NRD_SMOOTH_LINE,
+                               block Gauss-Seidel whose blocks are the
+                               x-lines of each patch (red-black by j + k,
+                               each line solved exactly with the rest held) */
     double err_eta_E;       /* eta_E, eta_T of that norm,                    */
     double err_eta_T;       /* max |e / (u + eta)| over composite cells      */
     int32_t fac_base;       /* base level of FAC: NRD_BASE_MG (default), one

@@ -267,6 +267,73 @@ def jacobi_level(H, snap, f, level, rhs, e, omega=JACOBI_OMEGA, weights=None):
         e[p.pid][1:-1, 1:-1, 1:-1] = new[p.pid]
 
 
+def line_gs_level(H, snap, f, level, rhs, e, weights=None):
+    """One block Gauss-Seidel sweep on all cells of a level for A^l e = rhs
+    (the third level smoother Sec. 4.3 names).  Reading: the blocks are the
+    x-lines of each patch (all its cells with the same j, k); lines are
+    coloured by the parity of j + k in level index space and the red lines
+    go first; each line is solved exactly for its own cells (a tridiagonal
+    system of the level operator along x) with every other value held: the
+    y and z neighbours (lines of the other colour, or sibling and
+    coarse-fine ghosts) and, at the patch's x ends, the sibling ghosts.
+    Sibling ghosts are exchanged before each colour.  e ghosted per patch,
+    updated in place."""
+    plist = H.by_level[level]
+    if weights is None:
+        weights = {p.pid: level_weights(H, snap, f, p) for p in plist}
+    for colour in (0, 1):
+        exchange_siblings(H, level, e)
+        new = {}
+        for p in plist:
+            n = tuple(int(v) for v in p.n)
+            w, diag = weights[p.pid]
+            g = e[p.pid]
+            # right-hand side with the y, z neighbours and the x-end ghosts
+            b = rhs[p.pid].copy()
+            for d in (1, 2):
+                lo = [slice(None)] * 3
+                hi = [slice(None)] * 3
+                lo[d] = slice(0, n[d])
+                hi[d] = slice(1, n[d] + 1)
+                em = [slice(1, -1)] * 3
+                ep = [slice(1, -1)] * 3
+                em[d] = slice(0, n[d])
+                ep[d] = slice(2, n[d] + 2)
+                b = b + w[d][tuple(lo)] * g[tuple(em)] + w[d][tuple(hi)] * g[tuple(ep)]
+            b[0] = b[0] + w[0][0] * g[0, 1:-1, 1:-1]
+            b[-1] = b[-1] + w[0][n[0]] * g[n[0] + 1, 1:-1, 1:-1]
+            # tridiagonal along x: -w_lo x_{i-1} + diag x_i - w_hi x_{i+1} = b_i
+            sub = -w[0][1:n[0]]                 # coupling of i and i - 1, i >= 1
+            x = _thomas(sub, diag, sub, b)
+            J = np.arange(p.lo[1], p.hi[1])[:, None]
+            K = np.arange(p.lo[2], p.hi[2])[None, :]
+            new[p.pid] = (x, ((J + K) % 2 == colour))
+        for p in plist:
+            x, m = new[p.pid]
+            inner = e[p.pid][1:-1, 1:-1, 1:-1]
+            inner[:, m] = x[:, m]
+
+
+def _thomas(a, b, c, d):
+    """Solves the tridiagonal systems a_i x_{i-1} + b_i x_i + c_i x_{i+1} =
+    d_i along axis 0 (a, c: n - 1 entries, b, d: n) for every (j, k)."""
+    n = b.shape[0]
+    cp = np.zeros_like(b)
+    dp = np.zeros_like(b)
+    cp[0] = c[0] / b[0] if n > 1 else 0.0
+    dp[0] = d[0] / b[0]
+    for i in range(1, n):
+        den = b[i] - a[i - 1] * cp[i - 1]
+        if i < n - 1:
+            cp[i] = c[i] / den
+        dp[i] = (d[i] - a[i - 1] * dp[i - 1]) / den
+    x = np.zeros_like(b)
+    x[n - 1] = dp[n - 1]
+    for i in range(n - 2, -1, -1):
+        x[i] = dp[i] - cp[i] * x[i + 1]
+    return x
+
+
 # ---------------------------------------------------------------------------
 # base-level multigrid (level 0 must be a single box)
 # ---------------------------------------------------------------------------
@@ -535,6 +602,7 @@ def fac_vcycle(H, snap, f, rhs, mg_grids=None, nu=None):
     """One FAC V(m,n) cycle for A^c u = rhs from u = 0 (Alg. 1), nu = (m, n)
     (default snap.fac_nu, else (1, 0)); the level smoother is red-black
     Gauss-Seidel or, with snap.fac_smoother == "jacobi", damped point Jacobi
+    (or "line", block Gauss-Seidel on x-lines)
     (Sec. 4.3 names both); snap.fac_base == "smooth" replaces the base
     level's V-cycle by m smoothing sweeps (what the paper's runs did).
 
@@ -568,7 +636,7 @@ def fac_vcycle(H, snap, f, rhs, mg_grids=None, nu=None):
         for p in H.by_level[lev]:
             e[p.pid][...] = 0.0
         rhs_l = {p.pid: rg[p.pid][1:-1, 1:-1, 1:-1] for p in H.by_level[lev]}
-        sweep = jacobi_level if smoother == "jacobi" else rbgs_level
+        sweep = {"jacobi": jacobi_level, "line": line_gs_level}.get(smoother, rbgs_level)
         for _ in range(sweeps):
             sweep(H, snap, f, lev, rhs_l, e)
         return {p.pid: e[p.pid][1:-1, 1:-1, 1:-1].copy() for p in H.by_level[lev]}

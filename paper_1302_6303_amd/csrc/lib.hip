@@ -104,7 +104,7 @@ struct nrd_hierarchy final : public Clock {
             rcells, ctype, shadows, shadow_src, coff, ps, active, amap;
         size_t mg_box[kMaxMG], mg_tiles[kMaxMG], mg_box_of[kMaxMG], mg_smooth[kMaxMG],
             mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bot_probs, bot_boxes, bot_grid, bottom_off,
-            Lbuf, Xbuf, mg_l0map;
+            Lbuf, Xbuf, mg_l0map, ltiles;
         size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, gz3, V, Z, pred;
         size_t pc_D, pc_sigma, pc_e, pc_e2, pc_u, pc_r, pc_f, pc_shadow;
         size_t mg_D[kMaxMG], mg_e[kMaxMG], mg_f[kMaxMG];
@@ -292,7 +292,14 @@ static void layout(nrd_hierarchy* h) {
     o.pc_D = b.take(es * 6 * nl);
     o.pc_sigma = b.take(es * nl);
     o.pc_e = b.take(es * 2 * nl);
-    o.pc_e2 = b.take(h->opt.fac_smoother == NRD_SMOOTH_JACOBI ? es * 2 * nl : es);
+    o.pc_e2 = b.take(h->opt.fac_smoother != NRD_SMOOTH_RBGS ? es * 2 * nl : es);
+    // x-line tiles of the block Gauss-Seidel smoother (lines of each patch in
+    // runs of kBlock lines), by level
+    {
+        size_t nlt = 0;
+        for (const PatchInfo& pi : t.patches) nlt += (pi.n[1] * pi.n[2] + kBlock - 1) / kBlock;
+        o.ltiles = b.take(sizeof(Tile) * std::max<size_t>(1, nlt));
+    }
     o.pc_u = b.take(es * 2 * nl);
     o.pc_r = b.take(es * 2 * nl);
     o.pc_f = b.take(es * 2 * nl);
@@ -369,6 +376,7 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
         pc.mg.bottom_boxes[g] = h->at<int32_t>(o.mg_bboxes[g]);
     }
     pc.mg.l0map = G >= 1 ? h->at<int32_t>(o.mg_l0map) : nullptr;
+    pc.ltiles = h->at<Tile>(o.ltiles);
     pc.mg.multi0 = t.level_sib0[1] > t.level_sib0[0];
     pc.mg.bottom_off = h->at<int64_t>(o.bottom_off);
     pc.mg.bot_probs = h->at<int32_t>(o.bot_probs);
@@ -446,6 +454,26 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
         nbottom[g] = (int)bp.size();
         HIPCHK(up(s, h->ws + o.mg_bprobs[g], bp));
         HIPCHK(up(s, h->ws + o.mg_bboxes[g], bb));
+    }
+    {
+        std::vector<Tile> lt;
+        std::vector<int32_t> l0(t.nlev + 1, 0);
+        for (int l = 0; l < t.nlev; ++l) {
+            l0[l] = (int32_t)lt.size();
+            for (int b = 0; b < t.nbox; ++b) {
+                const PatchInfo& pi = t.patches[b];
+                if (pi.level != l) continue;
+                const int32_t nlines = pi.n[1] * pi.n[2];
+                for (int32_t a = 0; a < nlines; a += kBlock)
+                    lt.push_back({b, a, std::min(kBlock, nlines - a), pi.prob});
+            }
+        }
+        l0[t.nlev] = (int32_t)lt.size();
+        HIPCHK(up(s, h->ws + o.ltiles, lt));
+        for (int l = 0; l <= t.nlev; ++l) {
+            h->pcf.level_line0[l] = l0[l];
+            h->pcd.level_line0[l] = l0[l];
+        }
     }
     if (G >= 1) {
         // children of every first-grid cell: one level-0 patch (level-0 boxes
@@ -1496,9 +1524,10 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
             delete h;
             return fail(NRD_EINVAL, "fac_nu_pre must be in [1, 8], fac_nu_post in [0, 8]");
         }
-        if (h->opt.fac_smoother != NRD_SMOOTH_RBGS && h->opt.fac_smoother != NRD_SMOOTH_JACOBI) {
+        if (h->opt.fac_smoother != NRD_SMOOTH_RBGS && h->opt.fac_smoother != NRD_SMOOTH_JACOBI &&
+            h->opt.fac_smoother != NRD_SMOOTH_LINE) {
             delete h;
-            return fail(NRD_EINVAL, "fac_smoother must be RBGS or JACOBI");
+            return fail(NRD_EINVAL, "fac_smoother must be RBGS, JACOBI or LINE");
         }
         if (h->opt.fac_base != NRD_BASE_MG && h->opt.fac_base != NRD_BASE_SMOOTH) {
             delete h;

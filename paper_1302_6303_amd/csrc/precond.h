@@ -82,7 +82,9 @@ struct PcArrays {
     int p2_mode = 0;
     int nu_pre = 1, nu_post = 1;
     int fac_pre = 1, fac_post = 0;   // FAC V(m, n)
-    int fac_smoother = 0;            // NRD_SMOOTH_RBGS or NRD_SMOOTH_JACOBI
+    int fac_smoother = 0;            // NRD_SMOOTH_RBGS, _JACOBI or _LINE
+    const Tile* ltiles = nullptr;    // x-line tiles (block Gauss-Seidel), by level
+    int32_t level_line0[kMaxLev + 1] = {};
     bool base_smooth = false;        // base level: level sweeps instead of multigrid
     PT* e2 = nullptr;                // 2 * nl, damped Jacobi with several sweeps
     Clock* clock = nullptr;     // times the base grid's sweeps

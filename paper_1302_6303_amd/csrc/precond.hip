@@ -250,6 +250,98 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(const int32_t* __restrict__ a
     }
 }
 
+// Block Gauss-Seidel on x-lines (the third level smoother of Sec. 4.3): one
+// thread per line (j, k) of a patch whose colour (j + k in level index space)
+// is being swept solves the tridiagonal system of the level operator along
+// the line exactly (Thomas algorithm, the elimination factors kept in cp),
+// with the y and z neighbours and the sibling ghosts at the line's ends held
+// (ZERO: the iterate is zero, the first colour of a sweep from zero; the
+// lines of the other colour are then set to zero).
+// Faces are classified as in level_terms.
+template <typename PT, bool ZERO>
+__global__ __launch_bounds__(kBlock) void k_line(const int32_t* __restrict__ act,
+    const Tile* __restrict__ ltiles, const PatchInfo* __restrict__ P,
+    const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
+    const PT* __restrict__ D, const PT* __restrict__ f, PT* __restrict__ e,
+    PT* __restrict__ cp, int colour, int64_t nl) {
+    const Tile t = ltiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    const int q = t.start + threadIdx.x;
+    const int j = q % p.n[1], k = q / p.n[1];
+    const int n0 = p.n[0];
+    if (((j + k + p.lo[1] + p.lo[2]) & 1) != colour) {
+        // a sweep from zero: the other colour's lines are zero (their values,
+        // and a sibling's through its ghosts, are read by the next colour)
+        if (ZERO)
+            for (int i = 0; i < n0; ++i) {
+                const int c = nat(p, i, j, k);
+                e[c] = PT(0);
+                e[nl + c] = PT(0);
+            }
+        return;
+    }
+    const double beta = ps[t.prob].beta;
+    const int st[3] = {1, p.sy, p.sz};
+    PT bh2[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) bh2[d] = (PT)(beta * p.ih[d] * p.ih[d]);
+    for (int fld = 0; fld < 2; ++fld) {
+        const PT* Df = D + fld * 3 * nl;
+        PT* ef = e + fld * nl;
+        PT* cf = cp + fld * nl;
+        PT cprev = PT(0), dprev = PT(0);
+        for (int i = 0; i < n0; ++i) {
+            const int id[3] = {i, j, k};
+            const int c = nat(p, i, j, k);
+            PT dg = PT(1), b = f[fld * nl + c], alo = PT(0), ahi = PT(0);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const PT* Dd = Df + d * nl;
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const int fc = 2 * d + s;
+                    const bool edge = id[d] == (s ? p.n[d] - 1 : 0);
+                    const bool ph = edge && ((p.phys >> fc) & 1);
+                    const bool cfc = edge && !ph && ctype[s ? c + st[d] : c - st[d]] == GK_CF;
+                    const PT a = bh2[d] * Dd[s ? c + st[d] : c];
+                    const bool open = !(ph || cfc);
+                    dg += open ? a : (cfc ? PT(2.0 / 3.0) * a : PT(0));
+                    if (ph && fld == 0 && ((p.robin >> fc) & 1)) {
+                        const PT Db = Dd[s ? c + st[d] : c];
+                        const PT h = (PT)p.h[d];
+                        dg += PT(2) * (PT)beta * Db / ((PT(4) * Db + h) * h);
+                    }
+                    if (!open) continue;
+                    if (d == 0 && !edge) {
+                        // coupling within the line
+                        if (s) ahi = a;
+                        else alo = a;
+                    } else if (!ZERO) {
+                        b += a * ef[s ? c + st[d] : c - st[d]];
+                    }
+                }
+            }
+            // Thomas: den = dg - alo cp_{i-1}; cp_i = ahi / den (coupling -ahi);
+            // dp_i = (b + alo dp_{i-1}) / den
+            const PT den = dg - alo * cprev;
+            const PT cpi = ahi / den;
+            const PT dpi = (b + alo * dprev) / den;
+            cf[c] = cpi;
+            ef[c] = dpi;
+            cprev = cpi;
+            dprev = dpi;
+        }
+        PT x = PT(0);
+        for (int i = n0 - 1; i >= 0; --i) {
+            const int c = nat(p, i, j, k);
+            x = ef[c] + cf[c] * x;
+            ef[c] = x;
+        }
+    }
+}
+
 // One colour of a red-black sweep (MODE 0: from e = 0), kBlock / 2 threads
 // per tile of kBlock cells.  When the patch's x extent is
 // even, rows start at even linear indices, so every pair (2q, 2q + 1) of a
@@ -1039,6 +1131,22 @@ void PcArrays<PT>::smooth_level(hipStream_t s, const PT* rhs, int lev, int sweep
         }
         if (cur != e)
             k_copy_level<PT><<<nt, kBlock, 0, s>>>(d.active, tl, d.patches, cur, e, d.nl);
+        return;
+    }
+    if (fac_smoother == NRD_SMOOTH_LINE) {
+        const int l0 = level_line0[lev], nl0 = level_line0[lev + 1] - l0;
+        const Tile* lt = ltiles + l0;
+        k_line<PT, true><<<nl0, kBlock, 0, s>>>(d.active, lt, d.patches, d.ps, d.ctype, Dface,
+                                                rhs, e, e2, 0, d.nl);
+        siblings(s, e, lev);
+        k_line<PT, false><<<nl0, kBlock, 0, s>>>(d.active, lt, d.patches, d.ps, d.ctype, Dface,
+                                                 rhs, e, e2, 1, d.nl);
+        for (int it = 1; it < sweeps; ++it)
+            for (int colour = 0; colour < 2; ++colour) {
+                siblings(s, e, lev);
+                k_line<PT, false><<<nl0, kBlock, 0, s>>>(d.active, lt, d.patches, d.ps, d.ctype,
+                                                         Dface, rhs, e, e2, colour, d.nl);
+            }
         return;
     }
     k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, tl, d.patches, d.ps, d.ctype, Dface, rhs,

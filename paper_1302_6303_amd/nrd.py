@@ -26,7 +26,7 @@ NRD_OK, NRD_EINVAL, NRD_ENESTING, NRD_ESTATE = 0, -1, -2, -3
 NRD_ENONPOS, NRD_ENOTCONV, NRD_EDEVICE, NRD_EUNSUPPORTED = -4, -5, -6, -7
 NRD_FP64, NRD_MIXED = 0, 1
 NRD_BATCHED, NRD_PER_PATCH = 0, 1
-NRD_SMOOTH_RBGS, NRD_SMOOTH_JACOBI = 0, 1
+NRD_SMOOTH_RBGS, NRD_SMOOTH_JACOBI, NRD_SMOOTH_LINE = 0, 1, 2
 NRD_BASE_MG, NRD_BASE_SMOOTH = 0, 1
 NRD_JVP_ANALYTIC, NRD_JVP_FD = 0, 1
 NRD_TIMER_RESIDUAL, NRD_TIMER_JVP, NRD_TIMER_PRECOND = 0, 1, 2

@@ -14,7 +14,8 @@ import pytest
 from paper_1302_6303_amd import inputs as I
 from oracle.solvers import Stepper
 from tests.gpu_helpers import (compact_from_native, compact_state, make,
-                               native_from_compact, problem_slices, rel_err, to_host)
+                               native_from_compact, problem_slices, rel_err, to_dev,
+                               to_host)
 from tests.helpers import state, system
 
 pytestmark = pytest.mark.gpu
@@ -146,3 +147,51 @@ def test_static_amr_residual_full_hierarchy():
     n = s.nc
     assert rel_err(got[:n], ref[:n]) < 1e-12
     assert rel_err(got[n:], ref[n:]) < 1e-12
+
+
+def test_differentiation_workload_gradient_at_full_size():
+    """The differentiation configuration as configured: uniform 64^3, z = 1 +
+    9 s (smoothed random field), 50 backward-Euler steps of 1e-3 with state
+    checkpoints every 10 steps, J = sum of E at the final time.  The adjoint
+    gradient against the oracle's (a stored fixture written by
+    tests/golden/make_adjoint64.py from the oracle alone) at 1e-7, and
+    against central differences of the GPU's own forward solve (Newton rtol
+    1e-13, h = 1e-6) on 20 seeded cells whose sensitivity is at least 1e-3
+    of the largest, at 1e-5."""
+    import json
+    import os
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "adjoint64.json")))
+    N, every, dt = fx["nsteps"], 10, fx["dt"]
+    w = I.differentiation(fx["n"])
+    opts = dict(newton_rtol=1e-13, newton_atol=1e-22, newton_maxit=24, gmres_maxrestarts=30,
+                adjoint_slots=-(-N // every) + every + 3)
+    H = make(w, **opts)
+    g = to_host(H.adjoint_run([dt], N, every))
+    cells = np.array(fx["fd_cells"] + fx["sample_cells"])
+    ref = np.array(fx["fd_values"] + fx["sample_values"])
+    scale = fx["grad_max_abs"]
+    assert np.max(np.abs(g[cells] - ref)) <= 1e-7 * scale, \
+        (np.max(np.abs(g[cells] - ref)), scale)
+    fd_cells = np.array(fx["fd_cells"])
+    assert np.all(np.abs(g[fd_cells] - ref[:20]) <= 1e-7 * np.abs(ref[:20]))
+    # central differences of the forward solve, backward Euler throughout
+    Hf = make(w, bdf_max_order=1, **opts)
+    zc = w.compact(w.z)
+    u = compact_state(w)
+    nn = Hf.ncells
+
+    def J(zz):
+        Hf.set_fields(to_dev(u[:nn]), to_dev(u[nn:]), to_dev(zz))
+        for _ in range(N):
+            Hf.implicit_step([dt])
+        E, _ = Hf.get_fields()
+        return np.sum(np.sort(to_host(E)))
+    h = 1e-6
+    worst = 0.0
+    for c in fd_cells:
+        zp, zm = zc.copy(), zc.copy()
+        zp[c] += h
+        zm[c] -= h
+        fd = (J(zp) - J(zm)) / (2 * h)
+        worst = max(worst, abs(fd - g[c]) / abs(g[c]))
+    assert worst <= 1e-5, worst
