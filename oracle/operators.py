@@ -28,8 +28,9 @@ Readings (the paper is ambiguous):
 Parity status: the face/residual formulas are pinned by special cases
 (gradient-free limit, equilibrium, textbook Laplacian), the discrete energy
 identity, mirror symmetry and second-order MMS convergence; the JVP by
-brute-force finite differences; the VJP by the dot-product identity and
-finite differences in z.
+brute-force finite differences; the VJP by the dot-product identity (one
+level, siblings, two and three levels) and finite differences in z (one
+and two levels).
 """
 from __future__ import annotations
 
@@ -529,7 +530,8 @@ def jvp_fd(H, E, T, z, vE, vT, bE, bT, dt, c0, lam=1.0):
 
 
 # ---------------------------------------------------------------------------
-# transpose (gather over faces); single-level hierarchies
+# transpose (scatter over faces, then the ghost fill and the restriction
+# run backwards); hierarchies of any depth
 # ---------------------------------------------------------------------------
 
 def _face_partials(Ea, Eb, Ta, Tb, z3a, z3b, h, kappa, lam):
@@ -561,16 +563,69 @@ def _face_partials(Ea, Eb, Ta, Tb, z3a, z3b, h, kappa, lam):
     return P
 
 
+def _adjoint_lambda(H, lam):
+    """Ghosted copies of the per-patch multipliers for the transposed face
+    fluxes: covered cells 0 (their residual is 0); a coarse-fine ghost holds
+    1/8 of the multiplier of the coarse cell it lies in (that cell's
+    residual takes the mean of the four fine face fluxes on the shared face,
+    over the coarse mesh width: 1/4 x 1/2 of a fine cell's weight per fine
+    flux); physical and sibling ghosts 0 (a face shared by two siblings is
+    seen by both: each side's view carries its own cell's multiplier, and
+    the two scatters add up to the face's)."""
+    out = []
+    for p, a in zip(H.patches, lam):
+        g = np.zeros(p.gshape)
+        x = np.array(a, dtype=np.float64)
+        x[H.covered[p.pid]] = 0.0
+        g[1:-1, 1:-1, 1:-1] = x
+        out.append(g)
+    inner = [a[1:-1, 1:-1, 1:-1] for a in out]
+    for p in H.patches:
+        for d in range(3):
+            for s_ in range(2):
+                G, gl, il, kind = H.ghost_kinds(p, d, s_)
+                val = np.zeros(len(G))
+                m = kind == 2
+                if m.any():
+                    pid, loc = H.locate(p.level - 1, G[m] // 2)
+                    val[m] = [inner[q][tuple(l)] / 8.0 for q, l in zip(pid, loc)]
+                out[p.pid][gl[:, 0], gl[:, 1], gl[:, 2]] = val
+    return out
+
+
+def _cf_sources(H, level, G, d):
+    """The five sources of coarse-fine ghosts G on level `level` (face
+    normal d) and their weights in g = 2/3 i + 1/3 f, i the 9, 3, 3, 1 / 16
+    bilinear value of the coarse level (copy rule at the domain edges)."""
+    t1, t2 = [a for a in range(3) if a != d]
+    P = G // 2
+    o1 = np.where(G[:, t1] % 2 == 1, 1, -1)
+    o2 = np.where(G[:, t2] % 2 == 1, 1, -1)
+    N = H.N(level - 1)
+    e1 = np.zeros_like(P)
+    e1[:, t1] = o1
+    e2 = np.zeros_like(P)
+    e2[:, t2] = o2
+    return [(np.clip(Q, 0, N - 1), w) for Q, w in
+            ((P, 9.0), (P + e1, 3.0), (P + e2, 3.0), (P + e1 + e2, 1.0))]
+
+
 def vjp(H, E, T, z, lE, lT, dt, c0, lam=1.0, magnitude=False):
-    """lambda^T dF/du (E and T parts) and lambda^T dF/dz (per cell) for a
-    single-level hierarchy.  Ghost values are copies (physical or sibling),
-    so their sensitivities are scattered back to the copied cells.
+    """lambda^T dF/du (E and T parts) and lambda^T dF/dz (per cell, every
+    level) on a hierarchy of any depth.  The residual's linear steps are
+    transposed in reverse order: the face fluxes' partials are scattered to
+    both cells of each face (ghost slots included); coarse faces taken over
+    by flux matching carry no coarse flux, their fine fluxes feed the coarse
+    cell's multiplier through the ghosts (see _adjoint_lambda); ghost
+    sensitivities go back to their sources (sibling copies; coarse-fine
+    interpolation: 2/3 x 9, 3, 3, 1 / 16 to the coarse cells, 1/3 to the
+    fine cell); covered cells pass theirs to their eight children (the
+    transposed restriction, coarse to fine); z has no restriction.  Covered
+    entries of the E and T parts are 0.
 
     magnitude=True returns instead, per entry, the sum of the magnitudes of
     the terms that entry adds up (every product and difference taken in
     absolute values): the scale of its rounding error."""
-    if H.nlev != 1:
-        raise NotImplementedError("transpose on refined hierarchies")
     A = np.abs if magnitude else (lambda x: x)
     if magnitude:
         lE = [np.abs(a) for a in lE]
@@ -581,14 +636,13 @@ def vjp(H, E, T, z, lE, lT, dt, c0, lam=1.0, magnitude=False):
     z3 = [a**3 for a in zg]
     aE = [np.zeros(p.gshape) for p in H.patches]
     aT = [np.zeros(p.gshape) for p in H.patches]
-    aZ = [np.zeros(p.gshape) for p in H.patches]   # w.r.t. z^3
+    aZ = [np.zeros(p.gshape) for p in H.patches]   # w.r.t. z^3, then z
+    lEa = _adjoint_lambda(H, lE)
+    lTa = _adjoint_lambda(H, lT)
     for p in H.patches:
         q = p.pid
         h = H.h(p.level)
-        lEg = np.zeros(p.gshape)
-        lTg = np.zeros(p.gshape)
-        lEg[1:-1, 1:-1, 1:-1] = lE[q]
-        lTg[1:-1, 1:-1, 1:-1] = lT[q]
+        lEg, lTg = lEa[q], lTa[q]
         for d in range(3):
             lo, up = face_slices(d, p.n)
             P = _face_partials(Eg[q][lo], Eg[q][up], Tg[q][lo], Tg[q][up],
@@ -602,6 +656,14 @@ def vjp(H, E, T, z, lE, lT, dt, c0, lam=1.0, magnitude=False):
                     fs = face_index(d, 0 if s == 0 else int(p.n[d]))
                     muE[fs] = 0.0
                     muT[fs] = 0.0
+            t1, t2 = [a for a in range(3) if a != d]
+            for fidx, tloc, _ in cf_faces(H, p, d):   # taken over by matching
+                idx = [None] * 3
+                idx[d] = fidx
+                idx[t1] = tloc[:, 0]
+                idx[t2] = tloc[:, 1]
+                muE[idx[0], idx[1], idx[2]] = 0.0
+                muT[idx[0], idx[1], idx[2]] = 0.0
             aE[q][lo] += muE * P["E_Ea"]
             aE[q][up] += muE * P["E_Eb"]
             aT[q][lo] += muE * P["E_T"] + muT * P["T_Ta"]
@@ -630,11 +692,16 @@ def vjp(H, E, T, z, lE, lT, dt, c0, lam=1.0, magnitude=False):
         dS_dE = A(-zz / t**3)
         dS_dT = zz * (1.0 + 3.0 * e / t**4)
         dS_dz = (t + e / t**3) if magnitude else (t - e / t**3)
-        # F_E has -dt S, F_T has +dt S
-        x = (lT[q] + lE[q]) if magnitude else (lT[q] - lE[q])
-        aE[q][1:-1, 1:-1, 1:-1] += c0 * lE[q] + dt * x * dS_dE
-        aT[q][1:-1, 1:-1, 1:-1] += c0 * lT[q] + dt * x * dS_dT
+        # F_E has -dt S, F_T has +dt S (covered cells: multipliers 0)
+        mE, mT = lEg[1:-1, 1:-1, 1:-1], lTg[1:-1, 1:-1, 1:-1]
+        x = (mT + mE) if magnitude else (mT - mE)
+        aE[q][1:-1, 1:-1, 1:-1] += c0 * mE + dt * x * dS_dE
+        aT[q][1:-1, 1:-1, 1:-1] += c0 * mT + dt * x * dS_dT
         aZ[q][1:-1, 1:-1, 1:-1] += dt * x * dS_dz
+    # w.r.t. z itself, ghosts included: a coarse-fine ghost interpolates z,
+    # not z^3 (edge and corner ghosts hold NaN and receive nothing)
+    aZ = [np.where(a != 0.0, 3.0 * np.nan_to_num(zg[p.pid])**2 * a, 0.0)
+          for p, a in zip(H.patches, aZ)]
     # transpose of the ghost fill: scatter ghost sensitivities to sources
     for p in H.patches:
         for d in range(3):
@@ -652,9 +719,36 @@ def vjp(H, E, T, z, lE, lT, dt, c0, lam=1.0, magnitude=False):
                             ll = loc[mm] + 1
                             np.add.at(acc[qq], (ll[:, 0], ll[:, 1], ll[:, 2]),
                                       g[m][mm])
+                    m = kind == 2
+                    if m.any():
+                        gm = g[m]
+                        np.add.at(acc[p.pid], (il[m, 0], il[m, 1], il[m, 2]), gm / 3.0)
+                        for Q, wq in _cf_sources(H, p.level, G[m], d):
+                            pid, loc = H.locate(p.level - 1, Q)
+                            for qq in np.unique(pid):
+                                mm = pid == qq
+                                ll = loc[mm] + 1
+                                np.add.at(acc[qq], (ll[:, 0], ll[:, 1], ll[:, 2]),
+                                          (2.0 / 3.0) * (wq / 16.0) * gm[mm])
                     acc[p.pid][gl[:, 0], gl[:, 1], gl[:, 2]] = 0.0
+    # transposed restriction, coarse to fine (z is not restricted)
+    for lev in range(H.nlev - 1):
+        for p in H.by_level[lev]:
+            cov = np.argwhere(H.covered[p.pid])
+            if len(cov) == 0:
+                continue
+            I = cov + p.lo
+            for acc in (aE, aT):
+                v = acc[p.pid][cov[:, 0] + 1, cov[:, 1] + 1, cov[:, 2] + 1] / 8.0
+                from .hierarchy import _OCT
+                for o in _OCT:
+                    pid, loc = H.locate(lev + 1, 2 * I + o)
+                    for qq in np.unique(pid):
+                        mm = pid == qq
+                        ll = loc[mm] + 1
+                        np.add.at(acc[qq], (ll[:, 0], ll[:, 1], ll[:, 2]), v[mm])
+                acc[p.pid][cov[:, 0] + 1, cov[:, 1] + 1, cov[:, 2] + 1] = 0.0
     gE = [a[1:-1, 1:-1, 1:-1].copy() for a in aE]
     gT = [a[1:-1, 1:-1, 1:-1].copy() for a in aT]
-    gz = [3.0 * zg[p.pid][1:-1, 1:-1, 1:-1]**2 * aZ[p.pid][1:-1, 1:-1, 1:-1]
-          for p in H.patches]
+    gz = [a[1:-1, 1:-1, 1:-1].copy() for a in aZ]
     return gE, gT, gz

@@ -17,7 +17,8 @@
   the generalised leapfrog predictor (eq. leapfrog) with the time derivative
   taken from the previous step's BDF left-hand side (Remark 2) is the Newton
   initial guess when it is positive.
-* The discrete adjoint of a BDF1 trajectory for J = sum of E over cells.
+* The discrete adjoint of a BDF1 trajectory for J = sum of E over the
+  composite cells.
 
 Norms and inner products are volume weighted over composite (non-covered)
 cells: <x, y> = sum_c V_c (x_E y_E + x_T y_T).
@@ -460,11 +461,16 @@ class AdaptiveStepper(Stepper):
 
 def adjoint_gradient(sys: System, u0, dt, nsteps, tol=1e-11, newton_kw=None,
                      m=30, max_restarts=20):
-    """dJ/dz for J = sum_c E_N(c) after nsteps BDF1 steps of size dt.
+    """dJ/dz for J = sum of E_N over the composite cells (covered cells,
+    which hold restricted values, are not counted) after nsteps BDF1 steps
+    of size dt; z of every level, covered cells included.
 
-    Forward: u_n solves F_n = u_n - u_{n-1} - dt f(u_n; z) = 0.  Reverse:
-    A_N^T l_N = dJ/du_N, A_n^T l_n = l_{n+1}; dJ/dz = -sum_n l_n^T dF_n/dz.
-    Every forward state is kept (the oracle does not checkpoint)."""
+    Forward: u_n solves F_n = u_n - u_{n-1} - dt f(u_n; z) = 0 on the
+    composite cells, covered cells restricted from their children.  Reverse:
+    A_N^T l_N = dJ/du_N, A_n^T l_n = l_{n+1}; dJ/dz = -sum_n l_n^T dF_n/dz,
+    A_n^T the transpose of F_n's derivative in the composite unknowns (the
+    covered entries of l carry nothing).  Every forward state is kept (the
+    oracle does not checkpoint)."""
     kw = dict(newton_kw or {})
     st = Stepper(sys, u0, bdf1_only=True, **kw)
     states = [st.u.copy()]
@@ -474,7 +480,7 @@ def adjoint_gradient(sys: System, u0, dt, nsteps, tol=1e-11, newton_kw=None,
             raise RuntimeError("forward solve failed")
         states.append(st.u.copy())
     nc = sys.nc
-    rhs = np.concatenate([np.ones(nc), np.zeros(nc)])
+    rhs = np.concatenate([sys.composite[:nc].astype(np.float64), np.zeros(nc)])
     grad = np.zeros(nc)
     euclid = lambda x, y: float(np.dot(x, y))
     for n in range(nsteps, 0, -1):

@@ -435,9 +435,14 @@ def test_jvp_taylor_remainder_is_second_order():
     assert 3.5 < r[0] / r[1] < 4.5 and 3.5 < r[1] / r[2] < 4.5
 
 
-@pytest.mark.parametrize("wname", ["single", "siblings"])
+@pytest.mark.parametrize("wname", ["single", "siblings", "amr2", "amr3"])
 def test_vjp_dot_product_identity(wname):
-    w = I.marshak_single(8, state="front") if wname == "single" else I.multi_patch_uniform(10, cuts=(3, 7))
+    """<l, J v> = <J^T l, v>: on refined hierarchies the transpose runs the
+    coarse-fine interpolation, flux matching and restriction backwards."""
+    w = {"single": lambda: I.marshak_single(8, state="front"),
+         "siblings": lambda: I.multi_patch_uniform(10, cuts=(3, 7)),
+         "amr2": lambda: I.small_amr(8, state="front"),
+         "amr3": lambda: I.static_amr(base=8, nlevels=3, side=(8, 16), state="front")}[wname]()
     s = system(w)
     u = state(s, w)
     rng = np.random.default_rng(10)
@@ -450,26 +455,35 @@ def test_vjp_dot_product_identity(wname):
         assert abs(a - b) <= 1e-13 * (np.abs(l) @ np.abs(Jv))
 
 
-def test_vjp_z_derivative_matches_fd():
-    w = I.marshak_single(6, state="front")
+@pytest.mark.parametrize("wname", ["single", "amr2"])
+def test_vjp_z_derivative_matches_fd(wname):
+    """l^T dF/dz against central differences of l^T F in z, every level's
+    z (covered cells included: their z feeds coarse-fine ghosts)."""
+    w = (I.marshak_single(6, state="front") if wname == "single"
+         else I.small_amr(6, state="front", boxes_spec=[(1, (2, 2, 2), (10, 8, 10))]))
     s = system(w)
     u = state(s, w)
     b = 0.9 * u
     rng = np.random.default_rng(11)
     l = rng.standard_normal(u.shape)
     _, gz = s.vjp(u, l, 1e-3, 1.0)
-    z0 = w.z[0].copy()
-    for c in rng.choice(z0.size, 12, replace=False):
-        hz = 1e-6 * z0.ravel(order="F")[c]
+    z0 = [a.copy() for a in s.z]
+    flat = np.concatenate([a.ravel(order="F") for a in z0])
+    for c in rng.choice(flat.size, 16, replace=False):
+        hz = 1e-6 * flat[c]
         vals = []
         for sg in (1, -1):
-            z = z0.copy().ravel(order="F")
-            z[c] += sg * hz
-            s.z = [z.reshape(z0.shape, order="F")]
+            zz = flat.copy()
+            zz[c] += sg * hz
+            out, o = [], 0
+            for a in z0:
+                out.append(zz[o:o + a.size].reshape(a.shape, order="F"))
+                o += a.size
+            s.z = out
             vals.append(np.dot(l, s.residual(u, b, 1e-3, 1.0)))
-        s.z = [z0]
+        s.z = z0
         fd = (vals[0] - vals[1]) / (2 * hz)
-        assert abs(fd - gz[c]) <= 1e-6 * max(abs(gz[c]), 1e-3 * np.abs(gz).max())
+        assert abs(fd - gz[c]) <= 1e-6 * abs(gz[c]) + 1e-8 * np.abs(gz).max(), (c, fd, gz[c])
 
 
 # ---------------------------------------------------------------------------

@@ -392,3 +392,43 @@ def test_adjoint_gradient_matches_central_fd():
         fd = (J(zp.reshape(z.shape, order="F")) - J(zm.reshape(z.shape, order="F"))) / (2 * hz)
         assert abs(fd - g[c]) <= 1e-5 * abs(g[c]), (c, fd, g[c])
     s.z = [z]
+
+
+def test_adjoint_gradient_on_two_levels_matches_central_fd():
+    """The same on a refined hierarchy: J sums E over the composite cells;
+    z of both levels is perturbed, the covered coarse cells' z included
+    (it reaches the fine cells through the coarse-fine ghosts)."""
+    w = I.small_amr(6, boxes_spec=[(1, (2, 2, 2), (10, 8, 10))])
+    H = Hierarchy((6, 6, 6), [(b.level, b.lo, b.hi) for b in w.boxes])
+    s = System(H, w.z)
+    u0 = s.join(w.E, w.T)
+    kw = dict(rtol=1e-11, atol=1e-30, maxit=40)
+    dt, N = 2e-3, 2
+    g, _ = adjoint_gradient(s, u0, dt, N, tol=1e-13, newton_kw=kw)
+    z0 = [a.copy() for a in s.z]
+    flat = np.concatenate([a.ravel(order="F") for a in z0])
+
+    def J(zz):
+        out, o = [], 0
+        for a in z0:
+            out.append(zz[o:o + a.size].reshape(a.shape, order="F"))
+            o += a.size
+        s.z = out
+        st = Stepper(s, u0, bdf1_only=True, **kw)
+        for _ in range(N):
+            assert st.step(dt).converged
+        return np.sum(st.u[:s.nc][s.composite[:s.nc]])
+
+    cov0 = H.covered[0].ravel(order="F")
+    order = list(np.argsort(-np.abs(g))[:3])
+    order.append(int(np.argmax(np.where(cov0, np.abs(g[:cov0.size]), -1.0))))  # a covered cell
+    order.append(cov0.size + int(np.argmax(np.abs(g[cov0.size:]))))           # a fine cell
+    for c in order:
+        hz = 1e-3 * flat[c]
+        zp = flat.copy()
+        zm = flat.copy()
+        zp[c] += hz
+        zm[c] -= hz
+        fd = (J(zp) - J(zm)) / (2 * hz)
+        assert abs(fd - g[c]) <= 1e-5 * abs(g[c]), (c, fd, g[c])
+    s.z = z0
