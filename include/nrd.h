@@ -254,9 +254,14 @@ nrd_status nrd_precond_setup(nrd_hierarchy* h, double* dev_u);
 nrd_status nrd_precond_apply(nrd_hierarchy* h, const double* dev_w,
                              double* dev_y);
 
-/* Transposed action: JTlam = F'(u)^T lam (native, interior written) and
- * gz = (dF/dz)^T lam per cell (compact, ncells).  Single-level hierarchies
- * (the adjoint of coarse-fine interpolation is not provided). */
+/* Transposed action (Sec. 3.2.1's synchronisation run backwards on refined
+ * hierarchies): JTlam = F'(u)^T lam in the composite unknowns (native,
+ * interior written; covered entries 0: the covered cells' restricted values
+ * pass their sensitivities to their children) and gz = (dF/dz)^T lam per
+ * cell (compact, ncells, every level: covered cells' z reaches the fine
+ * level through coarse-fine ghosts).  Covered entries of lam are ignored.
+ * u's ghost/covered entries and lam's ghosts are overwritten; the ghost
+ * slots of JTlam are used as scratch. */
 nrd_status nrd_vjp(nrd_hierarchy* h, double* dev_u, double* dev_lam,
                    double* dev_JTlam, double* dev_gz);
 
@@ -285,10 +290,11 @@ nrd_status nrd_adaptive_steps(nrd_hierarchy* h, const nrd_timectl* ctl, int32_t 
                               double* dt, double* t, nrd_step_stats* stats);
 
 /* Discrete adjoint of nsteps BDF1 steps of size dt from the current state
- * for J = sum over cells of dJdE_final[c] * E_N(c) (device, compact E part;
- * NULL = all ones).  Forward states are checkpointed every ckpt_every steps
- * and recomputed segment by segment.  gz (device, ncells) receives dJ/dz.
- * The state afterwards is u_N. */
+ * for J = sum over the composite cells of dJdE_final[c] * E_N(c) (device,
+ * compact E part, covered entries ignored; NULL = all ones).  Forward
+ * states are checkpointed every ckpt_every steps and recomputed segment by
+ * segment.  gz (device, ncells) receives dJ/dz for the z of every cell of
+ * every level.  The state afterwards is u_N. */
 nrd_status nrd_adjoint_run(nrd_hierarchy* h, const double* dt, int32_t nsteps,
                            int32_t ckpt_every, const double* dev_dJdE_final,
                            double* dev_gz);

@@ -373,6 +373,7 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
     }
     // ghosts
     std::vector<std::vector<GhostCopy>> sib_by_level(t.nlev);
+    std::vector<int32_t> cf_prob;            // problem of each gcf entry
     for (int b = 0; b < nbox; ++b) {
         const HostBox& x = t.boxes[b];
         const PatchInfo& pi = t.patches[b];
@@ -441,9 +442,31 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
                         }
                         e.src[4] = inner;
                         t.gcf.push_back(e);
+                        cf_prob.push_back(x.prob);
                         t.ctype[gidx] = GK_CF;
                     }
             }
+        }
+    }
+    {
+        // the transposed interpolation gathers, per coarse source cell, the
+        // ghosts it feeds (a source clipped at the domain edge may appear
+        // twice for one ghost)
+        struct Ent { int32_t c, ghost, w, prob; };
+        std::vector<Ent> ents;
+        ents.reserve(4 * t.gcf.size());
+        static const int32_t wq[4] = {9, 3, 3, 1};
+        for (size_t i = 0; i < t.gcf.size(); ++i)
+            for (int q = 0; q < 4; ++q)
+                ents.push_back({t.gcf[i].src[q], t.gcf[i].dst, wq[q], cf_prob[i]});
+        std::stable_sort(ents.begin(), ents.end(),
+                         [](const Ent& a, const Ent& b) { return a.c < b.c; });
+        for (size_t i = 0; i < ents.size();) {
+            size_t j = i;
+            while (j < ents.size() && ents[j].c == ents[i].c) ++j;
+            t.cfrows.push_back({ents[i].c, (int32_t)i, (int32_t)(j - i), ents[i].prob});
+            for (size_t k = i; k < j; ++k) t.cfsrc.push_back({ents[k].ghost, ents[k].w});
+            i = j;
         }
     }
     t.level_sib0.assign(t.nlev + 1, 0);

@@ -64,6 +64,9 @@ struct Dev {
     const RefluxFace* rfaces = nullptr;
     const RefluxCell* rcells = nullptr;
     int32_t nrcells = 0;
+    const CFRow* cfrows = nullptr;           // transposed coarse-fine interpolation
+    const CFSrc* cfsrc = nullptr;
+    int32_t ncfrows = 0;
     const uint8_t* ctype = nullptr;
     const ProbScalars* ps = nullptr;         // device [nprob]
     const int32_t* active = nullptr;         // device [nprob], 1 = work on it
@@ -73,6 +76,7 @@ struct Dev {
     const int32_t* amap = nullptr;
     int32_t namap = 0;
     const double* z3 = nullptr;              // native, z^3 with ghosts
+    const double* z = nullptr;               // native, z with ghosts
     int32_t level_shadow0[kMaxLev + 1] = {}; // prolongation shadow cells per level
 };
 
@@ -84,6 +88,14 @@ void ghost_fill_f(const Dev& D, hipStream_t s, float* x, int nf);
 // covered cells <- mean of children, finest level first
 void restrict_d(const Dev& D, hipStream_t s, double* x, int nf, int lev_lo = 0);
 void restrict_f(const Dev& D, hipStream_t s, float* x, int nf, int lev_lo = 0);
+// adjoint fill of a multiplier vector's two fields: sibling copies, 1/8 of
+// the coarse cell at a coarse-fine ghost
+void adjoint_ghost_fill(const Dev& D, hipStream_t s, double* x);
+// transposed restriction (coarsest level first): each covered cell adds 1/8
+// of its value to its children and is set to 0
+void restrict_transpose(const Dev& D, hipStream_t s, double* x, int nf);
+// covered cells <- 0
+void zero_covered(const Dev& D, hipStream_t s, double* x, int nf);
 // sibling ghosts of one level only
 void sibling_exchange_f(const Dev& D, hipStream_t s, float* x, int nf, int lev);
 void sibling_exchange_d(const Dev& D, hipStream_t s, double* x, int nf, int lev);
@@ -103,9 +115,11 @@ void jvp(const Dev& D, hipStream_t s, int t0, int nt, const double* u,
 void jvp_all(const Dev& D, hipStream_t s, const double* u, const double* v, double* Jv);
 void jvp_reflux(const Dev& D, hipStream_t s, const double* u, const double* v,
                 double* Jv);
-// transpose: gE, gT (native, interior) and gz3 (native) = lambda^T dF/dz^3
-void vjp(const Dev& D, hipStream_t s, int t0, int nt, const double* u,
-         const double* lam, double* JTl, double* gz3);
+// transpose on any hierarchy: JTl = (dF/du)^T lam (native; covered cells
+// 0) and gz = (dF/dz)^T lam (native, every cell).  lam's ghosts are
+// overwritten (adjoint fill); the ghost slots of JTl and gz are scratch.
+void vjp_full(const Dev& D, hipStream_t s, const double* u, double* lam, double* JTl,
+              double* gz);
 
 // ---- vec.hip ------------------------------------------------------------
 // Deterministic per-problem reductions over vtiles.
@@ -161,8 +175,6 @@ void unpack(const Dev& D, hipStream_t s, const int64_t* coff,
 void check_positive(const Dev& D, hipStream_t s, const double* x, int nf,
                     int32_t* flag);
 void cube(hipStream_t s, const double* z, double* z3, int64_t n);
-// g *= 3 z^2 (compact arrays of n values)
-void chain_z(hipStream_t s, const double* z, double* g, int64_t n);
 void to_float(hipStream_t s, const double* x, float* y, int64_t n);
 void to_double(hipStream_t s, const float* x, double* y, int64_t n);
 

@@ -101,11 +101,11 @@ struct nrd_hierarchy final : public Clock {
     // workspace offsets
     struct Off {
         size_t patches, tiles, stiles, vtiles, prob_vtile0, gcopy, gcf, sib, sync[kMaxLev], rfaces,
-            rcells, ctype, shadows, shadow_src, coff, ps, active, amap;
+            rcells, cfrows, cfsrc, ctype, shadows, shadow_src, coff, ps, active, amap;
         size_t mg_box[kMaxMG], mg_tiles[kMaxMG], mg_box_of[kMaxMG], mg_smooth[kMaxMG],
             mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bot_probs, bot_boxes, bot_grid, bottom_off,
             Lbuf, Xbuf, mg_l0map, ltiles;
-        size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, gz3, V, Z, pred;
+        size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, gzn, V, Z, pred;
         size_t pc_D, pc_sigma, pc_e, pc_e2, pc_u, pc_r, pc_f, pc_shadow;
         size_t mg_D[kMaxMG], mg_e[kMaxMG], mg_f[kMaxMG];
         size_t partial, dots, h1, h2, hn2, H, cs, sn, g, rho, vscale, y, kdim, coefA, coefB,
@@ -124,7 +124,7 @@ struct nrd_hierarchy final : public Clock {
     bool resolve_ready = false;     // a transfer brought that system here
     bool skip_estimate = false;     // next step: no error estimate (regrid)
     // device pointers
-    double *z, *z3, *cur, *prev, *udot, *bvec, *x, *F, *s, *w, *tmp, *tmp2, *gz3, *V, *Z, *pred;
+    double *z, *z3, *cur, *prev, *udot, *bvec, *x, *F, *s, *w, *tmp, *tmp2, *gzn, *V, *Z, *pred;
     std::vector<double> err_prev;   // per problem: last error norm (-1: none)
     double *partial, *dots, *h1, *h2, *hn2, *H, *cs, *sn, *g, *rho, *vscale, *y, *coefA, *coefB,
         *minout, *ckpt, *fdF, *fdw, *fdsum;
@@ -237,6 +237,8 @@ static void layout(nrd_hierarchy* h) {
         o.sync[l] = b.take(sizeof(SyncEntry) * std::max<size_t>(1, t.sync[l].size()));
     o.rfaces = b.take(sizeof(RefluxFace) * std::max<size_t>(1, t.rfaces.size()));
     o.rcells = b.take(sizeof(RefluxCell) * std::max<size_t>(1, t.rcells.size()));
+    o.cfrows = b.take(sizeof(CFRow) * std::max<size_t>(1, t.cfrows.size()));
+    o.cfsrc = b.take(sizeof(CFSrc) * std::max<size_t>(1, t.cfsrc.size()));
     o.ctype = b.take(t.ctype.size());
     o.shadows = b.take(sizeof(ShadowPatch) * t.shadow.size());
     o.shadow_src = b.take(sizeof(int32_t) * std::max<int64_t>(1, t.shadow_len));
@@ -283,7 +285,7 @@ static void layout(nrd_hierarchy* h) {
     o.w = b.take(8 * 2 * nl);
     o.tmp = b.take(8 * 2 * nl);
     o.tmp2 = b.take(8 * 2 * nl);
-    o.gz3 = b.take(8 * nl);
+    o.gzn = b.take(8 * nl);
     o.V = b.take(8 * 2 * nl * (size_t)(m + 1));
     o.Z = b.take(8 * 2 * nl * (size_t)m);
     o.pred = b.take(h->opt.error_estimate ? 8 * 2 * nl : 8);
@@ -418,6 +420,8 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     for (int l = 0; l < t.nlev; ++l) HIPCHK(up(s, h->ws + o.sync[l], t.sync[l]));
     HIPCHK(up(s, h->ws + o.rfaces, t.rfaces));
     HIPCHK(up(s, h->ws + o.rcells, t.rcells));
+    HIPCHK(up(s, h->ws + o.cfrows, t.cfrows));
+    HIPCHK(up(s, h->ws + o.cfsrc, t.cfsrc));
     HIPCHK(up(s, h->ws + o.ctype, t.ctype));
     HIPCHK(up(s, h->ws + o.shadows, t.shadow));
     HIPCHK(up(s, h->ws + o.shadow_src, t.shadow_src));
@@ -542,10 +546,14 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     D.rfaces = h->at<RefluxFace>(o.rfaces);
     D.rcells = h->at<RefluxCell>(o.rcells);
     D.nrcells = (int32_t)t.rcells.size();
+    D.cfrows = h->at<CFRow>(o.cfrows);
+    D.cfsrc = h->at<CFSrc>(o.cfsrc);
+    D.ncfrows = (int32_t)t.cfrows.size();
     D.ctype = h->at<uint8_t>(o.ctype);
     D.ps = h->at<ProbScalars>(o.ps);
     D.active = nullptr;
     D.z3 = h->at<double>(o.z3);
+    D.z = h->at<double>(o.z);
     h->ps = h->at<ProbScalars>(o.ps);
     h->active = h->at<int32_t>(o.active);
     h->amap = h->at<int32_t>(o.amap);
@@ -561,7 +569,7 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     h->w = h->at<double>(o.w);
     h->tmp = h->at<double>(o.tmp);
     h->tmp2 = h->at<double>(o.tmp2);
-    h->gz3 = h->at<double>(o.gz3);
+    h->gzn = h->at<double>(o.gzn);
     h->V = h->at<double>(o.V);
     h->Z = h->at<double>(o.Z);
     h->pred = h->at<double>(o.pred);
@@ -871,8 +879,7 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
             if (!transpose) {
                 op_jvp(h, u, h->tmp2, h->tmp, true);
             } else {
-                ghost_fill_d(h->D, s, h->tmp2, 2);
-                vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], u, h->tmp2, h->tmp, h->gz3);
+                vjp_full(h->D, s, u, h->tmp2, h->tmp, h->gzn);
             }
             copy_interior(h->D, s, rhs, h->w);
             std::vector<double> mone(np, -1.0), pone(np, 1.0);
@@ -935,8 +942,7 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
                     op_jvp(h, u, Zj, wv, true);
                 } else {
                     pc_apply_t(h, Vj, Zj);
-                    ghost_fill_d(h->D, s, Zj, 2);
-                    vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], u, Zj, wv, h->gz3);
+                    vjp_full(h->D, s, u, Zj, wv, h->gzn);
                 }
                 multidot(h->D, s, Vb, NL, j + 1, wv, h->partial, h->h1, vsc);
                 combine_dot(h->D, s, Vb, NL, j + 1, h->h1, j + 1, wv, h->partial, h->h2, vsc);
@@ -1359,7 +1365,6 @@ static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, in
     const int np = t.nprob;
     hipStream_t s = h->stream;
     const int64_t NL = h->nl2();
-    if (t.nlev != 1) return fail(NRD_EUNSUPPORTED, "adjoint needs a single-level hierarchy");
     if (nsteps <= 0 || every <= 0) return fail(NRD_EINVAL, "nsteps and ckpt_every must be > 0");
     const int nck = (nsteps + every - 1) / every;
     if (nck + every + 3 > h->adjoint_slots)
@@ -1379,7 +1384,8 @@ static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, in
         nrd_status rc = implicit_step(h, dtv.data(), nullptr, true);
         if (rc) return rc;
     }
-    // lambda_N rhs: (dJ/dE, 0)
+    // lambda_N rhs: (dJ/dE, 0) on the composite cells (covered cells hold
+    // restricted values, not unknowns)
     fill_native(s, rhs, NL, 0.0);
     if (dJdE) {
         unpack(h->D, s, h->at<int64_t>(h->o.coff), dJdE, rhs, 1, t.ncells);
@@ -1388,8 +1394,9 @@ static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, in
         fill_native(s, gz, t.ncells, 1.0);
         unpack(h->D, s, h->at<int64_t>(h->o.coff), gz, rhs, 1, t.ncells);
     }
+    zero_covered(h->D, s, rhs, 1);
     fill_native(s, lam, NL, 0.0);
-    fill_native(s, gacc, NL, 0.0);              // dJ/dz^3 accumulator (field 0)
+    fill_native(s, gacc, NL, 0.0);              // dJ/dz accumulator (field 0)
     for (int p = 0; p < np; ++p) {
         h->ps_host[p].dt = dt[p];
         h->ps_host[p].c0 = 1.0;
@@ -1435,26 +1442,22 @@ static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, in
             RCHK(upload_active(h));
             rc = fgmres(h, un, rhs, lam, tol, its, true);
             if (rc) return rc;
-            // grad -= lam^T dF/dz^3 ; next rhs = lam
-            ghost_fill_d(h->D, s, lam, 2);
-            vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], un, lam, h->w, h->gz3);
+            // grad -= lam^T dF/dz ; next rhs = lam
+            vjp_full(h->D, s, un, lam, h->w, h->gzn);
             std::vector<double> mone(np, -1.0), one(np, 1.0);
             HIPCHK(up(s, h->coefA, mone));
             HIPCHK(up(s, h->coefB, one));
-            // gacc (field 0 only used) += -gz3 : use a 2-field axpby on (gz3 | scratch)
+            // gacc (field 0 only used) += -gz : use a 2-field axpby on (gz | scratch)
             {
-                // gz3 is a single field; place it in tmp field 0, zero field 1
+                // gz is a single field; place it in tmp field 0, zero field 1
                 fill_native(s, h->tmp, NL, 0.0);
-                HIPCHK(hipMemcpyAsync(h->tmp, h->gz3, 8 * t.nl, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(h->tmp, h->gzn, 8 * t.nl, hipMemcpyDeviceToDevice, s));
                 axpby(h->D, s, h->coefA, h->tmp, h->coefB, gacc);
             }
             copy_interior(h->D, s, lam, rhs);
         }
     }
-    // gz = 3 z^2 gacc (compact)
     pack(h->D, s, h->at<int64_t>(h->o.coff), gacc, gz, 1, t.ncells);
-    pack(h->D, s, h->at<int64_t>(h->o.coff), h->z, h->tmp, 1, t.ncells);
-    chain_z(s, h->tmp, gz, t.ncells);
     // the state ends at u_N: recompute it from the last checkpoint
     copy_interior(h->D, s, ck + (size_t)(nck - 1) * NL, h->cur);
     prepare_state(h, h->cur);
@@ -1756,19 +1759,11 @@ nrd_status nrd_precond_apply(nrd_hierarchy* h, const double* w, double* y) {
 nrd_status nrd_vjp(nrd_hierarchy* h, double* u, double* lam, double* JTl, double* gz) {
     NEED_BOUND(h);
     if (!h->step_ready) return fail(NRD_ESTATE, "call nrd_begin_step first");
-    if (h->t.nlev != 1) return fail(NRD_EUNSUPPORTED, "transpose needs a single-level hierarchy");
     hipStream_t s = h->stream;
     h->D.active = nullptr;
     prepare_state(h, u);
-    ghost_fill_d(h->D, s, lam, 2);
-    vjp(h->D, s, 0, h->D.level_tile0[h->D.nlev], u, lam, JTl, h->gz3);
-    if (gz) {
-        // gz = 3 z^2 * dF/dz^3 (compact)
-        const int64_t* coff = h->at<int64_t>(h->o.coff);
-        pack(h->D, s, coff, h->gz3, gz, 1, h->t.ncells);
-        pack(h->D, s, coff, h->z, h->tmp, 1, h->t.ncells);
-        chain_z(s, h->tmp, gz, h->t.ncells);
-    }
+    vjp_full(h->D, s, u, lam, JTl, h->gzn);
+    if (gz) pack(h->D, s, h->at<int64_t>(h->o.coff), h->gzn, gz, 1, h->t.ncells);
     HIPCHK(hipGetLastError());
     return NRD_OK;
 }

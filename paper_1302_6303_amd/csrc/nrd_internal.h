@@ -74,6 +74,11 @@ struct RefluxFace {
 };
 // Coarse cells with refluxed faces, CSR into RefluxFace.
 struct RefluxCell { int32_t c, first, count, prob; };
+// Transposed coarse-fine interpolation: the coarse cells that feed
+// coarse-fine ghosts, CSR into the ghosts they feed with the tangential
+// weight (9, 3, 3 or 1) of the bilinear stencil.
+struct CFRow { int32_t c, first, count, prob; };
+struct CFSrc { int32_t ghost, w; };
 
 // Prolongation source buffers: level m patch p owns a "shadow" block of
 // the coarser level over its coarsened box grown by one cell.
@@ -149,6 +154,8 @@ struct Tables {
     std::vector<std::vector<SyncEntry>> sync;        // per level (covered cells)
     std::vector<RefluxFace> rfaces;
     std::vector<RefluxCell> rcells;
+    std::vector<CFRow> cfrows;               // coarse sources of gcf, by cell
+    std::vector<CFSrc> cfsrc;
 
     // prolongation: per fine patch a shadow block of the coarser level
     std::vector<ShadowPatch> shadow;         // per patch (level >= 1)

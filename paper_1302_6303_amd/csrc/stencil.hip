@@ -841,18 +841,26 @@ void jvp_reflux(const Dev& D, hipStream_t s, const double* u, const double* v, d
 }
 
 // ---------------------------------------------------------------------------
-// transpose (gather form, single-level hierarchies): each cell collects the
-// transposed contributions of its six faces and of its own cell terms, so no
-// atomics are needed.  lam's sibling ghosts must hold copies (ghost fill);
-// its physical ghosts are never read.
+// transpose (gather form): each cell collects the transposed contributions of
+// its faces and of its own cell terms, so no atomics are needed.  lam's
+// ghosts must hold the adjoint fill: sibling copies, and at a coarse-fine
+// ghost 1/8 of the multiplier of the coarse cell it lies in (that cell's
+// residual takes the mean of the four fine fluxes through the face, over the
+// coarse width).  Covered cells have no residual and gather nothing here;
+// faces whose flux flux matching supplies are skipped (the fine side carries
+// them).  At a coarse-fine face the cell also takes the sensitivity of its
+// ghost's values: 1/3 of it here (the ghost blends in the cell itself), all
+// of it written to the ghost slot for the coarse sources to gather.  gz is
+// per native cell and w.r.t. z (ghost z interpolates z, not z^3).
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_vjp(
     const Tile* __restrict__ tiles, int t0, const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const int32_t* __restrict__ active,
-    const double* __restrict__ u, const double* __restrict__ lam,
-    const double* __restrict__ z3, double* __restrict__ gout,
-    double* __restrict__ gz3, int64_t nl) {
+    const uint8_t* __restrict__ ctype, const double* __restrict__ u,
+    const double* __restrict__ lam, const double* __restrict__ z3,
+    const double* __restrict__ zv, double* __restrict__ gout,
+    double* __restrict__ gz, int64_t nl) {
     const Tile t = tiles[t0 + xcd_tile(blockIdx.x, gridDim.x)];
     if (active && !active[t.prob]) return;
     if ((int)threadIdx.x >= t.count) return;
@@ -861,17 +869,26 @@ __global__ __launch_bounds__(kBlock) void k_vjp(
     int id[3];
     cell_coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
     const int c = native_index(p, id[0], id[1], id[2]);
+    const bool amr = (p.flags & PF_CTYPE) != 0;
+    const uint32_t ct = amr ? ctype[c] : 0u;
+    if (ct & CT_COVERED) {
+        gout[c] = 0.0;
+        gout[c + nl] = 0.0;
+        gz[c] = 0.0;
+        return;
+    }
     const int st[3] = {1, p.sy, p.sz};
     const double E = u[c], T = u[c + nl], z = z3[c];
     const double lE = lam[c], lT = lam[c + nl];
     const double dt = q.dt, kappa = q.kappa, lm = q.lam;
-    double gE = q.c0 * lE, gT = q.c0 * lT, gZ = 0.0;
+    double gE = q.c0 * lE, gT = q.c0 * lT, gZ = 0.0, gZlin = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double h = p.h[d], ih = p.ih[d];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            const bool phys = (id[d] == (s ? p.n[d] - 1 : 0)) && ((p.phys >> (2 * d + s)) & 1);
+            const bool edge = id[d] == (s ? p.n[d] - 1 : 0);
+            const bool phys = edge && ((p.phys >> (2 * d + s)) & 1);
             if (phys) {
                 if ((p.robin >> (2 * d + s)) & 1) {
                     // F_c gets -dt q / h
@@ -886,7 +903,9 @@ __global__ __launch_bounds__(kBlock) void k_vjp(
                 }
                 continue;
             }
+            if ((ct >> (2 * d + s + 1)) & 1u) continue;    // flux matching
             const int nb = s ? c + st[d] : c - st[d];
+            const bool cf = amr && edge && ctype[nb] == GK_CF;
             // face between lower a and upper b; c is a when s = 1
             const int a = s ? c : nb;
             const int bb = s ? nb : c;
@@ -910,13 +929,29 @@ __global__ __launch_bounds__(kBlock) void k_vjp(
             const double dN_T = 3.0 * Tf2 * S * dEv;
             const double dD_T = 6.0 * lm * Tf2 * adE;
             const double dD_z = 3.0 * h * S;
+            const double pT = muE * (dN_T - phi * dD_T) * iD;
+            const double pZ = muE * (-phi * dD_z) * iD;
             gE += muE * (dN_E - phi * dD_E) * iD;
-            gT += muE * (dN_T - phi * dD_T) * iD;
-            gZ += muE * (-phi * dD_z) * iD;
+            gT += pT;
+            gZ += pZ;
             const double sq = Tf * rsqrt_nr(Tf);
             const double DT = kappa * Tf2 * sq;
             const double base = 1.25 * kappa * Tf * sq * (Tb - Ta);
             gT += muT * (base + (s ? -DT : DT)) * ih;
+            if (cf) {
+                // the same partials w.r.t. the ghost's E, T, z
+                const double gEn = muE * (2.0 * Tf3 * (dEv - S * sE) -
+                                          phi * (Zh - 4.0 * lm * Tf3 * sg * sE)) * iD;
+                const double gTn = pT + muT * (base + (s ? DT : -DT)) * ih;
+                const double zg = zv[nb];
+                const double gZn = 3.0 * zg * zg * pZ;
+                gE += (1.0 / 3.0) * gEn;
+                gT += (1.0 / 3.0) * gTn;
+                gZlin += (1.0 / 3.0) * gZn;
+                gout[nb] = gEn;
+                gout[nb + nl] = gTn;
+                gz[nb] = gZn;
+            }
         }
     }
     const double T2 = T * T, T3 = T2 * T;
@@ -925,16 +960,46 @@ __global__ __launch_bounds__(kBlock) void k_vjp(
     gE += dt * x * (-z * r3);
     gT += dt * x * z * (1.0 + 3.0 * E * r3 * rcp_nr(T));
     gZ += dt * x * (T - E * r3);
+    const double zc = zv[c];
     gout[c] = gE;
     gout[c + nl] = gT;
-    gz3[c] = gZ;
+    gz[c] = 3.0 * zc * zc * gZ + gZlin;
 }
 
-void vjp(const Dev& D, hipStream_t s, int t0, int nt, const double* u, const double* lam,
-         double* JTl, double* gz3) {
-    if (nt <= 0) return;
-    k_vjp<<<nt, kBlock, 0, s>>>(D.tiles, t0, D.patches, D.ps, D.active, u, lam, D.z3, JTl,
-                                gz3, D.nl);
+// Coarse cells gather 2/3 x w/16 of the sensitivities left in the ghost
+// slots they feed (E, T and z).
+__global__ __launch_bounds__(kBlock) void k_cf_gather(
+    const CFRow* __restrict__ rows, int n, const CFSrc* __restrict__ src,
+    const int32_t* __restrict__ active, double* __restrict__ g, double* __restrict__ gz,
+    int64_t nl) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const CFRow row = rows[r];
+    if (active && !active[row.prob]) return;
+    double aE = 0.0, aT = 0.0, aZ = 0.0;
+    for (int k = row.first; k < row.first + row.count; ++k) {
+        const CFSrc e = src[k];
+        const double w = (2.0 / 3.0) * (e.w * 0.0625);
+        aE += w * g[e.ghost];
+        aT += w * g[e.ghost + nl];
+        aZ += w * gz[e.ghost];
+    }
+    g[row.c] += aE;
+    g[row.c + nl] += aT;
+    gz[row.c] += aZ;
+}
+
+void vjp_full(const Dev& D, hipStream_t s, const double* u, double* lam, double* JTl,
+              double* gz) {
+    adjoint_ghost_fill(D, s, lam);
+    const int nt = D.level_tile0[D.nlev];
+    if (nt > 0)
+        k_vjp<<<nt, kBlock, 0, s>>>(D.tiles, 0, D.patches, D.ps, D.active, D.ctype, u, lam,
+                                    D.z3, D.z, JTl, gz, D.nl);
+    if (D.ncfrows > 0)
+        k_cf_gather<<<nblocks(D.ncfrows), kBlock, 0, s>>>(D.cfrows, D.ncfrows, D.cfsrc,
+                                                          D.active, JTl, gz, D.nl);
+    restrict_transpose(D, s, JTl, 2);
 }
 
 }  // namespace nrd

@@ -638,19 +638,6 @@ void cube(hipStream_t s, const double* z, double* z3, int64_t n) {
     if (n > 0) k_cube<<<nblocks(n), kBlock, 0, s>>>(z, z3, n);
 }
 
-// g = 3 z^2 g elementwise (chain rule from d/dz^3 to d/dz; compact arrays)
-__global__ __launch_bounds__(kBlock) void k_chain_z(const double* __restrict__ z,
-                                                    double* __restrict__ g, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        const double zi = z[i];
-        g[i] *= 3.0 * zi * zi;
-    }
-}
-void chain_z(hipStream_t s, const double* z, double* g, int64_t n) {
-    if (n > 0) k_chain_z<<<nblocks(n), kBlock, 0, s>>>(z, g, n);
-}
-
 __global__ __launch_bounds__(kBlock) void k_to_float(const double* __restrict__ x,
                                                      float* __restrict__ y, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -280,7 +280,8 @@ def test_precond_parity_noncubic():
             assert rel_err(g[f], ref[f]) < 1e-10
 
 
-@pytest.mark.parametrize("name", ["uniform16", "uniform10", "tiled0"])
+@pytest.mark.parametrize("name", ["uniform16", "uniform10", "tiled0", "amr2", "amr3", "amr4",
+                                  "tiled"])
 def test_vjp_parity(name):
     w, s, H, u_n, u, dt = _setup(name)
     rng = np.random.default_rng(9)
