@@ -94,8 +94,9 @@ class Snapshot:
     """
 
     def __init__(self, H, E, T, z, beta, lam=1.0, p2_mode="paper", fac_nu=(1, 0),
-                 fac_smoother="rbgs", fac_base="mg"):
+                 fac_smoother="rbgs", fac_base="mg", fac_cycle="mult"):
         self.H = H
+        self.fac_cycle = fac_cycle            # "mult": Alg. 1; "afacx": AFACx
         self.beta = float(beta)
         self.p2_mode = p2_mode
         self.fac_nu = tuple(fac_nu)
@@ -221,9 +222,11 @@ def colour_mask(lo, n, colour):
     return (X + Y + Z) % 2 == colour
 
 
-def rbgs_level(H, snap, f, level, rhs, e, weights=None):
+def rbgs_level(H, snap, f, level, rhs, e, weights=None, region=None):
     """One red-black Gauss-Seidel sweep on all cells of a level (covered
-    cells included) for A^l e = rhs; e ghosted per patch, updated in place."""
+    cells included) for A^l e = rhs; e ghosted per patch, updated in place.
+    region (pid -> boolean interior array): only those cells are relaxed,
+    every other cell keeps its value."""
     plist = H.by_level[level]
     if weights is None:
         weights = {p.pid: level_weights(H, snap, f, p) for p in plist}
@@ -234,7 +237,10 @@ def rbgs_level(H, snap, f, level, rhs, e, weights=None):
             n = tuple(int(v) for v in p.n)
             w, diag = weights[p.pid]
             val = (rhs[p.pid] + _neighbour_sum(w, e[p.pid], n)) / diag
-            new[p.pid] = (val, colour_mask(p.lo, n, colour))
+            m = colour_mask(p.lo, n, colour)
+            if region is not None:
+                m = m & region[p.pid]
+            new[p.pid] = (val, m)
         for p in plist:
             val, m = new[p.pid]
             inner = e[p.pid][1:-1, 1:-1, 1:-1]
@@ -671,12 +677,99 @@ def fac_vcycle(H, snap, f, rhs, mg_grids=None, nu=None):
     return u
 
 
+def afacx_coarse(H, snap, f, lev, r, sweeps):
+    """Coarse approximation of the pair (lev - 1, lev): red-black sweeps of
+    the level-(lev - 1) operator from zero on the cells that level lev
+    covers, every other cell of level lev - 1 held at 0; r: pid -> interior
+    right-hand side on level lev - 1."""
+    c = H.empty()
+    for p in H.by_level[lev - 1]:
+        c[p.pid][...] = 0.0
+    region = {p.pid: H.covered[p.pid] for p in H.by_level[lev - 1]}
+    for _ in range(sweeps):
+        rbgs_level(H, snap, f, lev - 1, r, c, region=region)
+    return {p.pid: c[p.pid][1:-1, 1:-1, 1:-1].copy() for p in H.by_level[lev - 1]}
+
+
+def afacx_fine(H, snap, f, lev, r, s, sweeps):
+    """Fine correction of the pair (lev - 1, lev): red-black sweeps of the
+    level-lev operator (coarse-fine ghosts with coarse values 0) from the
+    interpolated coarse approximation s, minus s."""
+    e = H.empty()
+    for p in H.by_level[lev]:
+        e[p.pid][...] = 0.0
+        e[p.pid][1:-1, 1:-1, 1:-1] = s[p.pid]
+    for _ in range(sweeps):
+        rbgs_level(H, snap, f, lev, r, e)
+    return {p.pid: e[p.pid][1:-1, 1:-1, 1:-1] - s[p.pid] for p in H.by_level[lev]}
+
+
+def afacx_cycle(H, snap, f, rhs, mg_grids=None, nu=None):
+    """AFACx, the asynchronous fast adaptive composite-grid method the
+    paper names for more asynchrony in its solver (Sec. 7, after Lee,
+    McCormick, Philip and Quinlan), for A^c u = rhs from u = 0.
+
+    r = rhs on the composite cells, covered cells the mean of their children
+    (the restricted composite residual).  Level 0: one multigrid V-cycle on
+    r (or m sweeps with snap.fac_base == "smooth").  Every refined level l,
+    independently of the others: m red-black sweeps of the level-(l-1)
+    operator from zero on the cells level l covers (the rest held at 0),
+    its trilinear interpolation s onto level l, m red-black sweeps of the
+    level-l operator from s, the correction e_l = result - s: the coarse
+    approximation only removes from the fine correction what level l-1
+    already represents.  u = the level-0 correction plus every e_l, each
+    carried to every finer level by trilinear prolongation; covered cells
+    synced.  m = nu[0] (default snap.fac_nu[0]).
+    """
+    if nu is None:
+        nu = getattr(snap, "fac_nu", (1, 0))
+    m = int(nu[0])
+    L = H.nlev - 1
+    rg = H.from_interior([np.where(H.covered[p.pid], 0.0, rhs[p.pid]) for p in H.patches])
+    H.sync([rg])
+    r = {p.pid: rg[p.pid][1:-1, 1:-1, 1:-1] for p in H.patches}
+
+    def on(lev):
+        return {p.pid: r[p.pid] for p in H.by_level[lev]}
+
+    if getattr(snap, "fac_base", "mg") == "smooth":
+        e = H.empty()
+        for p in H.by_level[0]:
+            e[p.pid][...] = 0.0
+        for _ in range(m):
+            rbgs_level(H, snap, f, 0, on(0), e)
+        acc = {p.pid: e[p.pid][1:-1, 1:-1, 1:-1].copy() for p in H.by_level[0]}
+    else:
+        if mg_grids is None:
+            mg_grids = build_mg(H, snap, f)
+        acc = dict(scatter_base(H, mg_vcycle(mg_grids, snap.beta, gather_base(H, on(0)))))
+    u = [np.zeros(tuple(int(v) for v in p.n)) for p in H.patches]
+    for q, a in acc.items():
+        u[q] = a
+    for lev in range(1, L + 1):
+        c = afacx_coarse(H, snap, f, lev, on(lev - 1), m)
+        s = dict(prolong_level(H, lev, c))
+        el = afacx_fine(H, snap, f, lev, on(lev), s, m)
+        carried = dict(prolong_level(H, lev, acc))
+        acc = {q: carried[q] + el[q] for q in el}
+        for q, a in acc.items():
+            u[q] = a
+    ug = H.from_interior(u)
+    H.sync([ug])
+    return H.interior(ug)
+
+
+def _p1_cycle(snap):
+    return afacx_cycle if getattr(snap, "fac_cycle", "mult") == "afacx" else fac_vcycle
+
+
 def precond_apply(H, snap, wE, wT, mg=None):
     """y = P2^-1 P1^-1 w (per-patch interior arrays)."""
     mgE = mg[0] if mg else None
     mgT = mg[1] if mg else None
-    eE = fac_vcycle(H, snap, 0, wE, mgE)
-    eT = fac_vcycle(H, snap, 1, wT, mgT)
+    cycle = _p1_cycle(snap)
+    eE = cycle(H, snap, 0, wE, mgE)
+    eT = cycle(H, snap, 1, wT, mgT)
     yE, yT = [], []
     for p in H.patches:
         q = p.pid
@@ -698,4 +791,5 @@ def precond_apply_transpose(H, snap, wE, wT, mg=None):
         xT.append(b)
     mgE = mg[0] if mg else None
     mgT = mg[1] if mg else None
-    return fac_vcycle(H, snap, 0, xE, mgE), fac_vcycle(H, snap, 1, xT, mgT)
+    cycle = _p1_cycle(snap)
+    return cycle(H, snap, 0, xE, mgE), cycle(H, snap, 1, xT, mgT)

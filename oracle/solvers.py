@@ -36,7 +36,7 @@ class System:
     [E of all patches (x fastest) | T of all patches]."""
 
     def __init__(self, H, z, lam=0.5, p2_mode="paper", jvp_mode="analytic", fac_nu=(1, 0),
-                 fac_smoother="rbgs", fac_base="mg"):
+                 fac_smoother="rbgs", fac_base="mg", fac_cycle="mult"):
         self.H = H
         self.jvp_mode = jvp_mode
         self._b = None
@@ -46,6 +46,7 @@ class System:
         self.fac_nu = tuple(fac_nu)     # FAC V(m, n) (Alg. 1)
         self.fac_smoother = fac_smoother
         self.fac_base = fac_base
+        self.fac_cycle = fac_cycle      # "mult": FAC (Alg. 1); "afacx": AFACx
         self.nc = H.ncells()
         w = []
         for p in H.patches:
@@ -116,7 +117,7 @@ class System:
     def precond(self, u, beta):
         E, T = self.split(u)
         snap = pc.Snapshot(self.H, E, T, self.z, beta, self.lam, self.p2_mode, self.fac_nu,
-                           self.fac_smoother, self.fac_base)
+                           self.fac_smoother, self.fac_base, self.fac_cycle)
         mg = (pc.build_mg(self.H, snap, 0), pc.build_mg(self.H, snap, 1))
 
         def apply(w):
