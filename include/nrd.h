@@ -92,6 +92,7 @@ enum { NRD_P2_PAPER = 0, NRD_P2_FROZEN4 = 1 };
 enum { NRD_SMOOTH_RBGS = 0, NRD_SMOOTH_JACOBI = 1,   /* FAC level smoother */
        NRD_SMOOTH_LINE = 2 };
 enum { NRD_BASE_MG = 0, NRD_BASE_SMOOTH = 1 };       /* FAC base level     */
+enum { NRD_FAC_MULT = 0, NRD_FAC_AFACX = 1 };        /* P1 cycle           */
 
 typedef struct {
     int32_t precision;      /* NRD_FP64 or NRD_MIXED (V-cycles in float)     */
@@ -149,12 +150,24 @@ typedef struct {
                                multigrid V-cycle, or NRD_BASE_SMOOTH, only
                                fac_nu_pre level sweeps there (the paper's
                                runs smooth on the coarsest level, Sec. 4.3)  */
-    int32_t pad_;
+    int32_t fac_cycle;      /* P1's cycle on refined hierarchies: NRD_FAC_MULT
+                               (default), the multiplicative FAC of Alg. 1,
+                               or NRD_FAC_AFACX, the asynchronous variant
+                               named in Sec. 7 (after Lee, McCormick, Philip
+                               and Quinlan): the base correction and, for
+                               every refined level l at once, fac_nu_pre
+                               red-black sweeps of the level-(l-1) operator
+                               from zero on the cells level l covers (the
+                               rest held at 0), their interpolation s onto
+                               level l and fac_nu_pre sweeps of the level-l
+                               operator from s, minus s; the corrections are
+                               summed.  Needs the red-black smoother and
+                               fac_nu_post = 0                              */
 } nrd_options;
 
 /* Fills *opt with the defaults: FP64, batched, no graph, analytic JVP,
  * limiter 1/2 (the printed pair), paper P2, rtol 1e-8, atol 1e-14, 20 Newton iterations,
- * GMRES(30) with 10 restarts, FAC V(1,0), base multigrid V(1,1),
+ * GMRES(30) with 10 restarts, multiplicative FAC V(1,0), base multigrid V(1,1),
  * staged-plane stencil, BDF2, no error
  * estimate, eta_E = 1e-5 (the initial energy density of Sec. 6), eta_T =
  * 1e-5^(1/4). */

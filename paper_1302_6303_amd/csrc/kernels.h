@@ -96,9 +96,11 @@ void adjoint_ghost_fill(const Dev& D, hipStream_t s, double* x);
 void restrict_transpose(const Dev& D, hipStream_t s, double* x, int nf);
 // covered cells <- 0
 void zero_covered(const Dev& D, hipStream_t s, double* x, int nf);
-// sibling ghosts of one level only
-void sibling_exchange_f(const Dev& D, hipStream_t s, float* x, int nf, int lev);
-void sibling_exchange_d(const Dev& D, hipStream_t s, double* x, int nf, int lev);
+// sibling ghosts of levels lev .. lev_hi (lev_hi < 0: lev only)
+void sibling_exchange_f(const Dev& D, hipStream_t s, float* x, int nf, int lev,
+                        int lev_hi = -1);
+void sibling_exchange_d(const Dev& D, hipStream_t s, double* x, int nf, int lev,
+                        int lev_hi = -1);
 
 // ---- stencil.hip --------------------------------------------------------
 

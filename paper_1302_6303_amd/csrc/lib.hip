@@ -294,7 +294,9 @@ static void layout(nrd_hierarchy* h) {
     o.pc_D = b.take(es * 6 * nl);
     o.pc_sigma = b.take(es * nl);
     o.pc_e = b.take(es * 2 * nl);
-    o.pc_e2 = b.take(h->opt.fac_smoother != NRD_SMOOTH_RBGS ? es * 2 * nl : es);
+    o.pc_e2 = b.take(h->opt.fac_smoother != NRD_SMOOTH_RBGS || h->opt.fac_cycle == NRD_FAC_AFACX
+                         ? es * 2 * nl
+                         : es);
     // x-line tiles of the block Gauss-Seidel smoother (lines of each patch in
     // runs of kBlock lines), by level
     {
@@ -394,6 +396,7 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
     pc.fac_post = h->opt.fac_nu_post;
     pc.fac_smoother = h->opt.fac_smoother;
     pc.base_smooth = h->opt.fac_base == NRD_BASE_SMOOTH;
+    pc.fac_cycle = h->opt.fac_cycle;
     pc.clock = h;
 }
 
@@ -1497,6 +1500,7 @@ void nrd_default_options(nrd_options* o) {
     o->fac_nu_post = 0;
     o->fac_smoother = NRD_SMOOTH_RBGS;
     o->fac_base = NRD_BASE_MG;
+    o->fac_cycle = NRD_FAC_MULT;
     o->stencil = 3;
     o->bdf_max_order = 2;
     o->error_estimate = 0;
@@ -1535,6 +1539,15 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
         if (h->opt.fac_base != NRD_BASE_MG && h->opt.fac_base != NRD_BASE_SMOOTH) {
             delete h;
             return fail(NRD_EINVAL, "fac_base must be MG or SMOOTH");
+        }
+        if (h->opt.fac_cycle != NRD_FAC_MULT && h->opt.fac_cycle != NRD_FAC_AFACX) {
+            delete h;
+            return fail(NRD_EINVAL, "fac_cycle must be MULT or AFACX");
+        }
+        if (h->opt.fac_cycle == NRD_FAC_AFACX &&
+            (h->opt.fac_smoother != NRD_SMOOTH_RBGS || h->opt.fac_nu_post != 0)) {
+            delete h;
+            return fail(NRD_EINVAL, "AFACx needs the red-black smoother and fac_nu_post = 0");
         }
         if (h->opt.bdf_max_order < 1 || h->opt.bdf_max_order > 2) {
             delete h;

@@ -86,7 +86,9 @@ struct PcArrays {
     const Tile* ltiles = nullptr;    // x-line tiles (block Gauss-Seidel), by level
     int32_t level_line0[kMaxLev + 1] = {};
     bool base_smooth = false;        // base level: level sweeps instead of multigrid
-    PT* e2 = nullptr;                // 2 * nl, damped Jacobi with several sweeps
+    int fac_cycle = 0;               // NRD_FAC_MULT (Alg. 1) or NRD_FAC_AFACX
+    PT* e2 = nullptr;                // 2 * nl: damped Jacobi with several sweeps,
+                                     // line smoother, AFACx coarse approximations
     Clock* clock = nullptr;     // times the base grid's sweeps
 
     void zero(hipStream_t s) const;
@@ -96,13 +98,21 @@ struct PcArrays {
     void apply(hipStream_t s, const double* w, double* y, const double* wsc = nullptr) const;
     void apply_transpose(hipStream_t s, const double* w, double* y) const;
     const PT* fac(hipStream_t s) const;     // returns u or e (one level)
+    const PT* afacx(hipStream_t s) const;   // returns e
+    const PT* p1(hipStream_t s) const;      // the configured cycle
     void vcycle(hipStream_t s) const;
     void composite_residual(hipStream_t s, int lev) const;
     void smooth_level(hipStream_t s, const PT* rhs, int lev, int sweeps) const;
     void correct_level(hipStream_t s, int lev) const;
     void fill_ghosts(hipStream_t s, PT* x) const;
     void restrict_(hipStream_t s, PT* x, int lev_lo) const;
-    void siblings(hipStream_t s, PT* x, int lev) const;
+    // sibling ghosts of levels lev .. lev_hi (lev_hi < 0: lev only)
+    void siblings(hipStream_t s, PT* x, int lev, int lev_hi = -1) const;
+    // red-black sweeps from x = 0 on A^l x = rhs over levels lo .. hi at once
+    // (their patches are independent); region: only covered cells relax,
+    // every other cell is set to 0
+    void smooth_range(hipStream_t s, const PT* rhs, PT* x, int lo, int hi, int sweeps,
+                      bool region) const;
 };
 
 }  // namespace nrd

@@ -342,13 +342,32 @@ __global__ __launch_bounds__(kBlock) void k_line(const int32_t* __restrict__ act
     }
 }
 
+// One cell of a red-black half-sweep; REGION: only covered cells relax,
+// any other cell is set to 0 (the coarse approximation of AFACx lives on
+// the region a finer level covers and vanishes outside it).
+template <typename PT, int MODE, bool REGION>
+__device__ __forceinline__ void level_cell(const PatchInfo& p, const int id[3], double beta,
+                                           const uint8_t* __restrict__ ctype,
+                                           const PT* __restrict__ D, const PT* __restrict__ f,
+                                           PT* __restrict__ e, int64_t nl) {
+    if (REGION) {
+        const int c = nat(p, id[0], id[1], id[2]);
+        if (!(ctype[c] & CT_COVERED)) {
+            e[c] = PT(0);
+            e[c + nl] = PT(0);
+            return;
+        }
+    }
+    level_update<PT, MODE>(p, id, beta, ctype, D, f, e, nl);
+}
+
 // One colour of a red-black sweep (MODE 0: from e = 0), kBlock / 2 threads
 // per tile of kBlock cells.  When the patch's x extent is
 // even, rows start at even linear indices, so every pair (2q, 2q + 1) of a
 // tile lies in one row and holds exactly one cell of each colour: thread q
 // updates that cell and every lane does useful work.  Otherwise each thread
 // tests two cells.
-template <typename PT, int MODE>
+template <typename PT, int MODE, bool REGION = false>
 __global__ __launch_bounds__(kBlock) void k_level(const int32_t* __restrict__ act, 
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
@@ -365,13 +384,40 @@ __global__ __launch_bounds__(kBlock) void k_level(const int32_t* __restrict__ ac
         if (a >= t.count) return;
         coords(p, t.start + a, id[0], id[1], id[2]);  // id[0] even
         id[0] += (colour + id[1] + id[2] + lo) & 1;
-        level_update<PT, MODE>(p, id, beta, ctype, D, f, e, nl);
+        level_cell<PT, MODE, REGION>(p, id, beta, ctype, D, f, e, nl);
     } else {
         for (int q = threadIdx.x; q < t.count; q += kBlock / 2) {
             coords(p, t.start + q, id[0], id[1], id[2]);
             if (((id[0] + id[1] + id[2] + lo) & 1) != colour) continue;
-            level_update<PT, MODE>(p, id, beta, ctype, D, f, e, nl);
+            level_cell<PT, MODE, REGION>(p, id, beta, ctype, D, f, e, nl);
         }
+    }
+}
+
+// r -= A^l e on the cells of the tiles (the level operator: coarse-fine
+// ghosts with coarse values 0); e's sibling ghosts must be current.
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_level_res(const int32_t* __restrict__ act,
+                                                      const Tile* __restrict__ tiles,
+                                                      const PatchInfo* __restrict__ P,
+                                                      const ProbScalars* __restrict__ ps,
+                                                      const uint8_t* __restrict__ ctype,
+                                                      const PT* __restrict__ D,
+                                                      const PT* __restrict__ e,
+                                                      PT* __restrict__ r, int64_t nl) {
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& p = P[t.patch];
+    int id[3];
+    coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int c = nat(p, id[0], id[1], id[2]);
+    PT dg[2], ns[2];
+    level_terms<PT, false>(p, id, c, ps[t.prob].beta, ctype, D, e, nl, dg, ns);
+#pragma unroll
+    for (int fld = 0; fld < 2; ++fld) {
+        const int64_t i = fld * nl + c;
+        r[i] -= dg[fld] * e[i] - ns[fld];
     }
 }
 
@@ -492,7 +538,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong_level(const int32_t* __restr
     const ShadowPatch* __restrict__ SP, const PT* __restrict__ sh, int64_t nls,
     PT* __restrict__ e, PT* __restrict__ u, int64_t nl) {
     // e: the prolonged correction, kept as the source for the next finer
-    // level (NULL on the finest level, where only u is updated)
+    // level (NULL on the finest level, where only u is updated); u NULL:
+    // only e is written
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
@@ -518,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_level(const int32_t* __restr
                      PT(3.0 / 64) * (s[ox + oy] + s[ox + oz] + s[oy + oz]) +
                      PT(1.0 / 64) * s[ox + oy + oz];
         if (e) e[fld * nl + c] = v;
-        u[fld * nl + c] += v;
+        if (u) u[fld * nl + c] += v;
     }
 }
 
@@ -1086,12 +1133,12 @@ void PcArrays<double>::restrict_(hipStream_t s, double* x, int lev_lo) const {
     restrict_d(*D, s, x, 2, lev_lo);
 }
 template <>
-void PcArrays<float>::siblings(hipStream_t s, float* x, int lev) const {
-    sibling_exchange_f(*D, s, x, 2, lev);
+void PcArrays<float>::siblings(hipStream_t s, float* x, int lev, int lev_hi) const {
+    sibling_exchange_f(*D, s, x, 2, lev, lev_hi);
 }
 template <>
-void PcArrays<double>::siblings(hipStream_t s, double* x, int lev) const {
-    sibling_exchange_d(*D, s, x, 2, lev);
+void PcArrays<double>::siblings(hipStream_t s, double* x, int lev, int lev_hi) const {
+    sibling_exchange_d(*D, s, x, 2, lev, lev_hi);
 }
 
 template <typename PT>
@@ -1227,11 +1274,88 @@ const PT* PcArrays<PT>::fac(hipStream_t s) const {
 }
 
 template <typename PT>
+void PcArrays<PT>::smooth_range(hipStream_t s, const PT* rhs, PT* x, int lo, int hi,
+                                int sweeps, bool region) const {
+    const Dev& d = *D;
+    const int t0 = d.level_tile0[lo], nt = d.level_tile0[hi + 1] - t0;
+    if (nt <= 0) return;
+    const Tile* tl = d.tiles + t0;
+    for (int it = 0; it < sweeps; ++it)
+        for (int colour = 0; colour < 2; ++colour) {
+            if (it > 0 || colour > 0) siblings(s, x, lo, hi);
+            const bool zero = it == 0 && colour == 0;
+            if (region && zero)
+                k_level<PT, 0, true><<<nt, kBlock / 2, 0, s>>>(d.active, tl, d.patches, d.ps,
+                                                               d.ctype, Dface, rhs, x, 0, d.nl);
+            else if (region)
+                k_level<PT, 1, true><<<nt, kBlock / 2, 0, s>>>(d.active, tl, d.patches, d.ps,
+                                                               d.ctype, Dface, rhs, x, colour,
+                                                               d.nl);
+            else if (zero)
+                k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, tl, d.patches, d.ps, d.ctype,
+                                                         Dface, rhs, x, 0, d.nl);
+            else
+                k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, d.patches, d.ps, d.ctype,
+                                                         Dface, rhs, x, colour, d.nl);
+        }
+}
+
+template <typename PT>
+const PT* PcArrays<PT>::afacx(hipStream_t s) const {
+    // AFACx from u = 0 for A^c u = f: r = f with covered cells the mean of
+    // their children; the coarse approximations of every pair (l-1, l) at
+    // once in e2 (sweeps on the cells level l covers, the rest 0); their
+    // trilinear interpolation s onto every refined level in e; the fine
+    // right-hand sides r - A^l s; the fine corrections from zero, every
+    // refined level at once (sweeps from s minus s, by linearity); the base
+    // correction; each level's correction carried to the finer levels.
+    const Dev& d = *D;
+    const int L = d.nlev - 1;
+    k_copy_t<PT><<<nblocks(2 * d.nl), kBlock, 0, s>>>(f, r, 2 * d.nl);
+    restrict_(s, r, 0);
+    if (L > 0) {
+        smooth_range(s, r, e2, 0, L - 1, fac_pre, true);
+        const int a = d.level_shadow0[1], b = d.level_shadow0[L + 1];
+        k_gather<PT><<<nblocks(b - a), kBlock, 0, s>>>(shadow_src + a, b - a, e2, d.nl,
+                                                       shadow + a, shadow_len);
+        const int t1 = d.level_tile0[1], nt1 = d.level_tile0[L + 1] - t1;
+        k_prolong_level<PT><<<nt1, kBlock, 0, s>>>(d.active, d.tiles + t1, d.patches, shadows,
+                                                   shadow, shadow_len, e, nullptr, d.nl);
+        siblings(s, e, 1, L);
+        k_level_res<PT><<<nt1, kBlock, 0, s>>>(d.active, d.tiles + t1, d.patches, d.ps, d.ctype,
+                                               Dface, e, r, d.nl);
+        smooth_range(s, r, e, 1, L, fac_pre, false);
+    }
+    if (base_smooth) {
+        smooth_level(s, r, 0, fac_pre);
+    } else {
+        PcArrays<PT> v = *this;
+        v.f = r;
+        v.vcycle(s);
+    }
+    for (int m = 1; m <= L; ++m) {
+        const int a = d.level_shadow0[m], b = d.level_shadow0[m + 1];
+        k_gather<PT><<<nblocks(b - a), kBlock, 0, s>>>(shadow_src + a, b - a, e, d.nl,
+                                                       shadow + a, shadow_len);
+        const int m0 = d.level_tile0[m], mt = d.level_tile0[m + 1] - m0;
+        k_prolong_level<PT><<<mt, kBlock, 0, s>>>(d.active, d.tiles + m0, d.patches, shadows,
+                                                  shadow, shadow_len, nullptr, e, d.nl);
+    }
+    restrict_(s, e, 0);
+    return e;
+}
+
+template <typename PT>
+const PT* PcArrays<PT>::p1(hipStream_t s) const {
+    return fac_cycle == NRD_FAC_AFACX ? afacx(s) : fac(s);
+}
+
+template <typename PT>
 void PcArrays<PT>::apply(hipStream_t s, const double* w, double* y, const double* wsc) const {
     const Dev& d = *D;
     const int ntiles = d.level_tile0[d.nlev];
     k_in<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, w, wsc, f, d.nl);
-    const PT* x = fac(s);
+    const PT* x = p1(s);
     k_p2<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, sigma, d.z3, x, y, p2_mode, 0,
                                        d.nl);
 }
@@ -1242,7 +1366,7 @@ void PcArrays<PT>::apply_transpose(hipStream_t s, const double* w, double* y) co
     const int ntiles = d.level_tile0[d.nlev];
     k_p2t_in<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, sigma, d.z3, w, f,
                                            p2_mode, d.nl);
-    const PT* x = fac(s);
+    const PT* x = p1(s);
     k_out<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, x, y, d.nl);
 }
 

@@ -153,17 +153,17 @@ void zero_covered(const Dev& D, hipStream_t s, double* x, int nf) {
 }
 
 template <typename T>
-static void sib_t(const Dev& D, hipStream_t s, T* x, int nf, int lev) {
-    const int a = D.level_sib0[lev], b = D.level_sib0[lev + 1];
+static void sib_t(const Dev& D, hipStream_t s, T* x, int nf, int lev, int lev_hi) {
+    const int a = D.level_sib0[lev], b = D.level_sib0[(lev_hi < 0 ? lev : lev_hi) + 1];
     if (b <= a) return;
     k_ghost_fill<T><<<nblocks(b - a), kBlock, 0, s>>>(D.sib + a, b - a, nullptr, 0, x, nf,
                                                      D.nl);
 }
-void sibling_exchange_f(const Dev& D, hipStream_t s, float* x, int nf, int lev) {
-    sib_t<float>(D, s, x, nf, lev);
+void sibling_exchange_f(const Dev& D, hipStream_t s, float* x, int nf, int lev, int lev_hi) {
+    sib_t<float>(D, s, x, nf, lev, lev_hi);
 }
-void sibling_exchange_d(const Dev& D, hipStream_t s, double* x, int nf, int lev) {
-    sib_t<double>(D, s, x, nf, lev);
+void sibling_exchange_d(const Dev& D, hipStream_t s, double* x, int nf, int lev, int lev_hi) {
+    sib_t<double>(D, s, x, nf, lev, lev_hi);
 }
 
 }  // namespace nrd

@@ -14,11 +14,12 @@ def hierarchy(w, pidx=0, **over):
     return Hierarchy(pr.base_n, bx, **kw)
 
 
-def system(w, pidx=0, lam=0.5, fac_nu=(1, 0), fac_smoother="rbgs", fac_base="mg", **over):
+def system(w, pidx=0, lam=0.5, fac_nu=(1, 0), fac_smoother="rbgs", fac_base="mg",
+           fac_cycle="mult", **over):
     H = hierarchy(w, pidx, **over)
     z = [zz for zz, b in zip(w.z, w.boxes) if b.problem == pidx]
     return System(H, z, lam=lam, fac_nu=fac_nu, fac_smoother=fac_smoother,
-                  fac_base=fac_base)
+                  fac_base=fac_base, fac_cycle=fac_cycle)
 
 
 def state(sys_, w, pidx=0):

@@ -226,6 +226,82 @@ def test_precond_parity_fac_line_gauss_seidel(name, nu, base):
         assert rel_err(got[sl][mm], ref[sl][mm]) < 1e-10
 
 
+@pytest.mark.parametrize("name,m,base", [("uniform16", 1, "mg"), ("amr2", 1, "mg"),
+                                          ("amr3", 2, "mg"), ("amr4", 1, "smooth"),
+                                          ("tiled", 2, "mg"), ("tiled", 1, "smooth")])
+def test_precond_parity_afacx(name, m, base):
+    """P1 by the AFACx cycle (every refined level's pair at once) against
+    the oracle's AFACx, FP64, on 1-4 levels and a tiled base; two applies
+    in a row (the second finds the first's scratch)."""
+    from paper_1302_6303_amd import nrd
+    w = WL[name]()
+    s = system(w, fac_nu=(m, 0), fac_base=base, fac_cycle="afacx")
+    H = make(w, fac_nu_pre=m, fac_cycle=nrd.NRD_FAC_AFACX,
+             fac_base=nrd.NRD_BASE_SMOOTH if base == "smooth" else nrd.NRD_BASE_MG)
+    dt = 2e-3
+    H.begin_step([dt])
+    rng = np.random.default_rng(42)
+    u = s.sync(state(s, w) * rng.uniform(0.9, 1.1, 2 * s.nc))
+    wv = np.random.default_rng(8).standard_normal(u.shape)
+    H.precond_setup(native_from_compact(H, u))
+    y = H.native()
+    for _ in range(2):
+        H.precond_apply(native_from_compact(H, wv), y)
+    got = compact_from_native(H, y)
+    P, _ = s.precond(u, dt)
+    ref = P(wv)
+    m_ = s.composite
+    n = s.nc
+    for sl in (slice(0, n), slice(n, 2 * n)):
+        mm = m_[sl]
+        assert rel_err(got[sl][mm], ref[sl][mm]) < 1e-10
+
+
+def test_precond_parity_afacx_float32():
+    """The AFACx cycle in FP32 (mixed precision) on three levels against
+    the FP64 oracle."""
+    from paper_1302_6303_amd import nrd
+    w = WL["amr3"]()
+    s = system(w, fac_cycle="afacx")
+    H = make(w, precision=nrd.NRD_MIXED, fac_cycle=nrd.NRD_FAC_AFACX)
+    dt = 2e-3
+    H.begin_step([dt])
+    rng = np.random.default_rng(42)
+    u = s.sync(state(s, w) * rng.uniform(0.9, 1.1, 2 * s.nc))
+    wv = np.random.default_rng(8).standard_normal(u.shape)
+    H.precond_setup(native_from_compact(H, u))
+    y = H.native()
+    H.precond_apply(native_from_compact(H, wv), y)
+    got = compact_from_native(H, y)
+    P, _ = s.precond(u, dt)
+    ref = P(wv)
+    n = s.nc
+    for sl in (slice(0, n), slice(n, 2 * n)):
+        mm = s.composite[sl]
+        assert rel_err(got[sl][mm], ref[sl][mm]) < 1e-4
+
+
+@pytest.mark.parametrize("name", ["amr2", "tiled"])
+def test_implicit_steps_parity_afacx(name):
+    """Implicit steps preconditioned by AFACx: same states as the oracle's
+    stepper with the oracle's AFACx (both at Newton rtol 1e-10)."""
+    from oracle.solvers import Stepper
+    from paper_1302_6303_amd import nrd
+    w = WL[name]()
+    s = system(w, fac_cycle="afacx")
+    H = make(w, newton_rtol=1e-10, newton_atol=1e-16, fac_cycle=nrd.NRD_FAC_AFACX)
+    st = Stepper(s, state(s, w), rtol=1e-10, atol=1e-16)
+    for dt in (1e-3, 1e-3, 1.5e-3):
+        rc, stats = H.implicit_step([dt])
+        r = st.step(dt)
+        assert r.converged and stats[0]["converged"]
+        E, T = H.get_fields()
+        got = np.concatenate([to_host(E), to_host(T)])
+        n = s.nc
+        for sl in (slice(0, n), slice(n, 2 * n)):
+            assert rel_err(got[sl], st.u[sl]) < 1e-8
+
+
 @pytest.mark.parametrize("name,nu", [("uniform16", (1, 0)), ("uniform16", (2, 0)),
                                      ("amr2", (1, 0)), ("amr3", (2, 1))])
 def test_precond_parity_fac_base_smoothing(name, nu):
