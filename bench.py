@@ -856,9 +856,12 @@ def main():
     ap.add_argument("--fac-nu", type=int, nargs=2, default=(1, 0), metavar=("M", "N"),
                     help="FAC V(M, N): M down-sweep and N up-sweep red-black sweeps per "
                          "level above the base (default 1 0, the paper's V(1,0))")
-    ap.add_argument("--fac-smoother", choices=("rbgs", "jacobi"), default="rbgs",
-                    help="FAC level smoother: red-black Gauss-Seidel (default) or damped "
-                         "point Jacobi")
+    ap.add_argument("--fac-smoother", choices=("rbgs", "jacobi", "line"), default="rbgs",
+                    help="FAC level smoother: red-black Gauss-Seidel (default), damped "
+                         "point Jacobi or x-line block Gauss-Seidel")
+    ap.add_argument("--fac-cycle", choices=("mult", "afacx"), default="mult",
+                    help="P1 cycle on refined hierarchies: multiplicative FAC (default) or "
+                         "AFACx (every level pair at once)")
     ap.add_argument("--limiter", type=float, default=0.5,
                     help="paper workloads: lambda of the flux limiter (0.5: the printed "
                          "pair, the library default; 1: Wilson form)")
@@ -914,12 +917,14 @@ def main():
         w.dt = w.dt * a.dt_scale
     ncomp = composite_cells(w)
     use_graph = a.graph
-    smoother = nrd.NRD_SMOOTH_JACOBI if a.fac_smoother == "jacobi" else nrd.NRD_SMOOTH_RBGS
+    smoother = {"rbgs": nrd.NRD_SMOOTH_RBGS, "jacobi": nrd.NRD_SMOOTH_JACOBI,
+                "line": nrd.NRD_SMOOTH_LINE}[a.fac_smoother]
+    cycle = nrd.NRD_FAC_AFACX if a.fac_cycle == "afacx" else nrd.NRD_FAC_MULT
     mixed = run_solver(w, nrd.default_options(precision=nrd.NRD_MIXED,
                                               launch=nrd.NRD_BATCHED, use_graph=use_graph,
                                               bdf_max_order=a.bdf_max_order,
                                               fac_nu_pre=a.fac_nu[0], fac_nu_post=a.fac_nu[1],
-                                              fac_smoother=smoother),
+                                              fac_smoother=smoother, fac_cycle=cycle),
                        a.steps, a.warmup, True, a.adaptive_eps)
     mixed["use_graph"] = use_graph
     plain = None
@@ -930,7 +935,7 @@ def main():
                                                   launch=nrd.NRD_PER_PATCH, stencil=1,
                                                   bdf_max_order=a.bdf_max_order,
                                                   fac_nu_pre=a.fac_nu[0], fac_nu_post=a.fac_nu[1],
-                                                  fac_smoother=smoother),
+                                                  fac_smoother=smoother, fac_cycle=cycle),
                            a.steps, a.warmup, False, a.adaptive_eps)
     batched64 = None
     if a.fp64_batched:
@@ -938,7 +943,7 @@ def main():
                                                       launch=nrd.NRD_BATCHED,
                                                       bdf_max_order=a.bdf_max_order,
                                                       fac_nu_pre=a.fac_nu[0], fac_nu_post=a.fac_nu[1],
-                                                      fac_smoother=smoother),
+                                                      fac_smoother=smoother, fac_cycle=cycle),
                                a.steps, a.warmup, False, a.adaptive_eps)
     res_s = mixed["residual_ms_avg"] / 1e3
     res_cells = mixed["residual_cells_avg"]           # per launch, average
@@ -975,9 +980,11 @@ def main():
                    "time_control": (f"PC.4.7, eps_t {a.adaptive_eps}" if a.adaptive_eps
                                     else "fixed steps"),
                    "solver": ("BDF1->BDF2" if a.bdf_max_order == 2 else "BDF1") +
-                             ", Newton rtol 1e-8, FGMRES(30), FAC V(%d,%d) %s + MG V(1,1)"
-                             % (a.fac_nu[0], a.fac_nu[1],
-                                "RBGS" if a.fac_smoother == "rbgs" else "damped Jacobi")},
+                             ", Newton rtol 1e-8, FGMRES(30), %s V(%d,%d) %s + MG V(1,1)"
+                             % ("AFACx" if a.fac_cycle == "afacx" else "FAC",
+                                a.fac_nu[0], a.fac_nu[1],
+                                {"rbgs": "RBGS", "jacobi": "damped Jacobi",
+                                 "line": "x-line block GS"}[a.fac_smoother])},
         "roofline": {"bound": "hbm", "kernel": "k_stencil_s<0> (residual)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
