@@ -61,8 +61,12 @@ enum {
 };
 
 /* One refinement patch: half-open [lo, hi) in the index space of its level
- * (level l refines level 0 by 2^l per axis).  Level-0 boxes: exactly one per
- * problem, covering the base grid.  Finer boxes: even lo/hi, inside the
+ * (level l refines level 0 by 2^l per axis).  Level-0 boxes tile the base
+ * grid (the coarsest level is a union of patches, Sec. 3.2): no overlap,
+ * together exactly the base grid (NRD_ENESTING otherwise).  A base grid cut
+ * into several boxes must coarsen at least once (even extents above 5) and
+ * be cut at even planes, since the base multigrid coarsens across the cuts
+ * (NRD_EUNSUPPORTED otherwise).  Finer boxes: even lo/hi, inside the
  * coarser level shrunk by one coarse cell away from the physical boundary
  * (proper nesting).  Boxes must be ordered by (problem, level). */
 typedef struct {
