@@ -95,14 +95,14 @@ def test_ensemble_preconditioner_every_problem(precision, tol):
     _per_problem(w, got, ref, tol)
 
 
-def test_ensemble_implicit_step_small_problems():
+def test_ensemble_implicit_step_every_problem():
     """One lock-step BDF1 step of all 64 problems from the benchmark's
     initial state (E0, T0 = E0^(1/4) everywhere, Marshak inflow), mixed
     precision, batched; the 24 problems of 32^3 and 48^3 cells are checked
-    against the oracle's own Newton-Krylov step.  (From the noisy front state
-    some of the 64-96^3 problems need more than 24 Newton iterations at
-    rtol 1e-10 with the safeguarded forcing terms; the oracle's Newton
-    history on them is the same.)"""
+    against the oracle's own Newton-Krylov step, the 40 problems of 64^3 to
+    96^3 cells by the oracle's residual of the step at the GPU's solution,
+    which must be down by the Newton tolerance from its value at the initial
+    guess (the oracle's own solve of those takes minutes per problem)."""
     w = I.ensemble()
     H = make(w, precision=1, newton_rtol=1e-10, newton_atol=1e-16, newton_maxit=24)
     H.autotune(None)
@@ -114,8 +114,16 @@ def test_ensemble_implicit_step_small_problems():
     got = np.concatenate([to_host(E), to_host(T)])
     sl = problem_slices(w)
     checked = 0
+    large = 0
     for p, b in enumerate(w.boxes):
         if b.shape[0] > 48:
+            s = system(w, pidx=p)
+            u0 = state(s, w, pidx=p)
+            dt = float(w.dt[p])
+            f0 = s.norm(s.residual(u0, u0, dt, 1.0))
+            f1 = s.norm(s.residual(got[sl[p]], u0, dt, 1.0))
+            assert f1 <= 2e-10 * f0, (p, f0, f1)
+            large += 1
             continue
         s = system(w, pidx=p)
         st = Stepper(s, state(s, w, pidx=p), rtol=1e-10, atol=1e-16)
@@ -126,7 +134,7 @@ def test_ensemble_implicit_step_small_problems():
         assert rel_err(g[:n], st.u[:n]) < 1e-8
         assert rel_err(g[n:], st.u[n:]) < 1e-8
         checked += 1
-    assert checked == 24
+    assert checked == 24 and large == 40
 
 
 def test_static_amr_residual_full_hierarchy():

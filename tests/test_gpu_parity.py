@@ -257,6 +257,32 @@ def test_precond_parity_afacx(name, m, base):
         assert rel_err(got[sl][mm], ref[sl][mm]) < 1e-10
 
 
+@pytest.mark.parametrize("name", ["amr3", "tiled"])
+def test_precond_parity_fac_float32_amr(name):
+    """The multiplicative FAC cycle in FP32 (mixed precision) on refined
+    hierarchies (three levels; a tiled base under a level-1 box) against the
+    FP64 oracle."""
+    from paper_1302_6303_amd import nrd
+    w = WL[name]()
+    s = system(w)
+    H = make(w, precision=nrd.NRD_MIXED)
+    dt = 2e-3
+    H.begin_step([dt])
+    rng = np.random.default_rng(42)
+    u = s.sync(state(s, w) * rng.uniform(0.9, 1.1, 2 * s.nc))
+    wv = np.random.default_rng(8).standard_normal(u.shape)
+    H.precond_setup(native_from_compact(H, u))
+    y = H.native()
+    H.precond_apply(native_from_compact(H, wv), y)
+    got = compact_from_native(H, y)
+    P, _ = s.precond(u, dt)
+    ref = P(wv)
+    n = s.nc
+    for sl in (slice(0, n), slice(n, 2 * n)):
+        mm = s.composite[sl]
+        assert rel_err(got[sl][mm], ref[sl][mm]) < 1e-4
+
+
 def test_precond_parity_afacx_float32():
     """The AFACx cycle in FP32 (mixed precision) on three levels against
     the FP64 oracle."""
