@@ -578,7 +578,7 @@ def material_sampler(mboxes):
 
 
 def dynamic_bench(steps, every, plain_steps, base=128, nlev=4, dt0=1e-5, adaptive_eps=None,
-                  tune=True):
+                  tune=True, fac_cycle=0):
     """Dynamic 4-level AMR (128^3 base, six z = 10 boxes), the paper's cold
     start (E = E0, T = T0, Marshak inflow at x = 0): steps BDF steps (BDF1
     first) of dt0 (a step whose Newton solve fails is retried with half the
@@ -591,7 +591,8 @@ def dynamic_bench(steps, every, plain_steps, base=128, nlev=4, dt0=1e-5, adaptiv
     Runs the mixed-precision batched solver, replays the same boxes and the
     same step sizes with the float64 batched solver (the solution
     difference and the Krylov counts) and the first plain_steps with the
-    float64 per-patch solver (its seconds per step)."""
+    float64 per-patch solver (its seconds per step).  fac_cycle: P1's cycle
+    (NRD_FAC_MULT or NRD_FAC_AFACX) in every run."""
     import numpy as np
     import tempfile
     import torch
@@ -623,6 +624,7 @@ def dynamic_bench(steps, every, plain_steps, base=128, nlev=4, dt0=1e-5, adaptiv
 
     def run(opts, nsteps, plan=None, label="", timers=False):
         """plan: (box lists per regrid, step sizes) to replay, else recorded."""
+        opts.fac_cycle = fac_cycle
         dt = dt0
         R = Regridder(opts, crit, clus, zfun, tune_cache=cache if tune else None)
         boxes = plan[0][0] if plan else initial_boxes()
@@ -776,9 +778,11 @@ def operator_times(H, dt, reps=20):
 def dynamic_main(a):
     steps = a.steps if a.steps_given else 50
     dt0 = a.dt if a.dt else 1e-5
+    from paper_1302_6303_amd import nrd
+    cycle = nrd.NRD_FAC_AFACX if a.fac_cycle == "afacx" else nrd.NRD_FAC_MULT
     mixed, fp64, plain, ops, comp, diff, plan = dynamic_bench(
         steps, a.regrid_every, 0 if a.no_plain else a.plain_steps, dt0=dt0,
-        adaptive_eps=a.adaptive_eps, tune=a.tune)
+        adaptive_eps=a.adaptive_eps, tune=a.tune, fac_cycle=cycle)
     res_s = mixed["residual_ms_avg"] / 1e3
     cells = mixed["residual_cells_avg"]
     achieved = BYTES_PER_CELL_RESIDUAL * cells / res_s / 1e9
@@ -800,7 +804,8 @@ def dynamic_main(a):
                    "clustering": "Berger-Rigoutsos, efficiency 0.7, sides 8..48 cells",
                    "final_boxes": mixed["final_boxes"], "final_cells": mixed["final_cells"],
                    "final_composite_cells": comp,
-                   "solver": "BDF1->BDF2, Newton rtol 1e-8, FGMRES(30), FAC V(1,0) RBGS + MG V(1,1)"},
+                   "solver": "BDF1->BDF2, Newton rtol 1e-8, FGMRES(30), %s RBGS + MG V(1,1)"
+                             % ("AFACx m = 1" if a.fac_cycle == "afacx" else "FAC V(1,0)")},
         "roofline": {"bound": "hbm", "kernel": "k_stencil_s<0> (residual)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
