@@ -65,10 +65,10 @@ HBM_PEAK_GBS = 8000.0
 # the factor a plain 2 GiB copy reads in the same run, WRITE by its own
 # factor; the 20 full launches timed after the steps), valid for the stencil
 # source with this SHA-256 prefix; null otherwise.
-MEASURED_TRAFFIC = {"workload": "ensemble", "stencil_sha256": "9cd1c74d5a05aa10",
-                    "bytes_per_cell": 63.6171,
-                    "fetch_bytes_per_cell": 47.0014,
-                    "write_bytes_per_cell": 16.6157,
+MEASURED_TRAFFIC = {"workload": "ensemble", "stencil_sha256": "14268eb99b528677",
+                    "bytes_per_cell": 62.4151,
+                    "fetch_bytes_per_cell": 45.8215,
+                    "write_bytes_per_cell": 16.5936,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 
 
