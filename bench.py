@@ -268,7 +268,7 @@ PAPER_UNIFORM = {32: (7.68, 2.99, 1334, 1.0), 64: (7.15, 2.96, 3253, 1.0),
                  128: (6.43, 2.61, 8207, 1.0), 256: (6.72, 3.04, 8698, 0.5)}
 
 
-def paper_bench(n, t_final, limiter=0.5, base="mg", jvp="analytic"):
+def paper_bench(n, t_final, limiter=0.5, base="mg", jvp="analytic", forcing=0):
     """The paper's model problem on a uniform n^3 grid integrated to t_final
     with BDF2 and PC.4.7 at its tolerance (eps_t = 5e-4 at 32^3, halved per
     doubling), Newton tolerances 1e-12 / 1e-10, FAC V(1,0), mixed precision;
@@ -280,7 +280,8 @@ def paper_bench(n, t_final, limiter=0.5, base="mg", jvp="analytic"):
                                newton_rtol=1e-12, newton_atol=1e-10, limiter=limiter,
                                fac_base=(nrd.NRD_BASE_SMOOTH if base == "smooth"
                                          else nrd.NRD_BASE_MG),
-                               jvp_mode=nrd.NRD_JVP_FD if jvp == "fd" else nrd.NRD_JVP_ANALYTIC)
+                               jvp_mode=nrd.NRD_JVP_FD if jvp == "fd" else nrd.NRD_JVP_ANALYTIC,
+                               newton_forcing=forcing)
     H = nrd.Hierarchy(w.problems, w.boxes, opts)
     u = compact_state(w)
     m = H.ncells
@@ -864,6 +865,9 @@ def main():
     ap.add_argument("--fac-smoother", choices=("rbgs", "jacobi", "line"), default="rbgs",
                     help="FAC level smoother: red-black Gauss-Seidel (default), damped "
                          "point Jacobi or x-line block Gauss-Seidel")
+    ap.add_argument("--forcing", choices=("kelley", "petsc"), default="kelley",
+                    help="Eisenstat-Walker forcing terms of the Newton solves: Kelley's "
+                         "choice (default) or PETSc's choice 2")
     ap.add_argument("--fac-cycle", choices=("mult", "afacx"), default="mult",
                     help="P1 cycle on refined hierarchies: multiplicative FAC (default) or "
                          "AFACx (every level pair at once)")
@@ -915,7 +919,8 @@ def main():
         paper_temporal_bench(limiter=a.limiter, ramp=a.ramp)
         return
     if a.workload.startswith("paper"):
-        paper_bench(int(a.workload[5:]), a.t_final, a.limiter, a.fac_base, a.jvp)
+        paper_bench(int(a.workload[5:]), a.t_final, a.limiter, a.fac_base, a.jvp,
+                    nrd.NRD_EW_PETSC if a.forcing == "petsc" else nrd.NRD_EW_KELLEY)
         return
     w = workload(a.workload)
     if a.dt_scale != 1.0:
@@ -925,11 +930,13 @@ def main():
     smoother = {"rbgs": nrd.NRD_SMOOTH_RBGS, "jacobi": nrd.NRD_SMOOTH_JACOBI,
                 "line": nrd.NRD_SMOOTH_LINE}[a.fac_smoother]
     cycle = nrd.NRD_FAC_AFACX if a.fac_cycle == "afacx" else nrd.NRD_FAC_MULT
+    forcing = nrd.NRD_EW_PETSC if a.forcing == "petsc" else nrd.NRD_EW_KELLEY
     mixed = run_solver(w, nrd.default_options(precision=nrd.NRD_MIXED,
                                               launch=nrd.NRD_BATCHED, use_graph=use_graph,
                                               bdf_max_order=a.bdf_max_order,
                                               fac_nu_pre=a.fac_nu[0], fac_nu_post=a.fac_nu[1],
-                                              fac_smoother=smoother, fac_cycle=cycle),
+                                              fac_smoother=smoother, fac_cycle=cycle,
+                                              newton_forcing=forcing),
                        a.steps, a.warmup, True, a.adaptive_eps)
     mixed["use_graph"] = use_graph
     plain = None
@@ -940,7 +947,8 @@ def main():
                                                   launch=nrd.NRD_PER_PATCH, stencil=1,
                                                   bdf_max_order=a.bdf_max_order,
                                                   fac_nu_pre=a.fac_nu[0], fac_nu_post=a.fac_nu[1],
-                                                  fac_smoother=smoother, fac_cycle=cycle),
+                                                  fac_smoother=smoother, fac_cycle=cycle,
+                                              newton_forcing=forcing),
                            a.steps, a.warmup, False, a.adaptive_eps)
     batched64 = None
     if a.fp64_batched:
@@ -948,7 +956,8 @@ def main():
                                                       launch=nrd.NRD_BATCHED,
                                                       bdf_max_order=a.bdf_max_order,
                                                       fac_nu_pre=a.fac_nu[0], fac_nu_post=a.fac_nu[1],
-                                                      fac_smoother=smoother, fac_cycle=cycle),
+                                                      fac_smoother=smoother, fac_cycle=cycle,
+                                              newton_forcing=forcing),
                                a.steps, a.warmup, False, a.adaptive_eps)
     res_s = mixed["residual_ms_avg"] / 1e3
     res_cells = mixed["residual_cells_avg"]           # per launch, average
@@ -985,8 +994,10 @@ def main():
                    "time_control": (f"PC.4.7, eps_t {a.adaptive_eps}" if a.adaptive_eps
                                     else "fixed steps"),
                    "solver": ("BDF1->BDF2" if a.bdf_max_order == 2 else "BDF1") +
-                             ", Newton rtol 1e-8, FGMRES(30), %s V(%d,%d) %s + MG V(1,1)"
-                             % ("AFACx" if a.fac_cycle == "afacx" else "FAC",
+                             ", Newton rtol 1e-8 (%s forcing), FGMRES(30), %s V(%d,%d) %s"
+                             " + MG V(1,1)"
+                             % ("PETSc" if a.forcing == "petsc" else "Kelley",
+                                "AFACx" if a.fac_cycle == "afacx" else "FAC",
                                 a.fac_nu[0], a.fac_nu[1],
                                 {"rbgs": "RBGS", "jacobi": "damped Jacobi",
                                  "line": "x-line block GS"}[a.fac_smoother])},

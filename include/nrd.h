@@ -97,6 +97,7 @@ enum { NRD_SMOOTH_RBGS = 0, NRD_SMOOTH_JACOBI = 1,   /* FAC level smoother */
        NRD_SMOOTH_LINE = 2 };
 enum { NRD_BASE_MG = 0, NRD_BASE_SMOOTH = 1 };       /* FAC base level     */
 enum { NRD_FAC_MULT = 0, NRD_FAC_AFACX = 1 };        /* P1 cycle           */
+enum { NRD_EW_KELLEY = 0, NRD_EW_PETSC = 1 };         /* Newton forcing     */
 
 typedef struct {
     int32_t precision;      /* NRD_FP64 or NRD_MIXED (V-cycles in float)     */
@@ -167,11 +168,24 @@ typedef struct {
                                operator from s, minus s; the corrections are
                                summed.  Needs the red-black smoother and
                                fac_nu_post = 0                              */
+    int32_t newton_forcing; /* Eisenstat-Walker forcing term of the inexact
+                               Newton solve (Sec. 4.1 points to Kelley's
+                               algorithm and Sec. 6 to PETSc's
+                               implementation): NRD_EW_PETSC (default):
+                               eta_0 = 0.3, eta_k = (|F_k| / |F_k-1|)^a,
+                               a = (1 + 5^1/2) / 2, at least eta_k-1^a when
+                               that exceeds 0.1; or NRD_EW_KELLEY: eta_0 =
+                               0.9, eta_k = 0.9 (|F_k| / |F_k-1|)^2, at least
+                               0.9 eta_k-1^2 when that exceeds 0.1.  Both
+                               capped at 0.9 and floored at 0.5 tau / |F_k|,
+                               tau the Newton stopping tolerance          */
+    int32_t pad_;
 } nrd_options;
 
 /* Fills *opt with the defaults: FP64, batched, no graph, analytic JVP,
  * limiter 1/2 (the printed pair), paper P2, rtol 1e-8, atol 1e-14, 20 Newton iterations,
- * GMRES(30) with 10 restarts, multiplicative FAC V(1,0), base multigrid V(1,1),
+ * PETSc's Eisenstat-Walker forcing terms, GMRES(30) with 10 restarts,
+ * multiplicative FAC V(1,0), base multigrid V(1,1),
  * staged-plane stencil, BDF2, no error
  * estimate, eta_E = 1e-5 (the initial energy density of Sec. 6), eta_T =
  * 1e-5^(1/4). */

@@ -217,7 +217,20 @@ class NewtonResult:
 
 
 def newton(sys: System, u0, b, dt, c0, beta, rtol=1e-8, atol=1e-14, maxit=20,
-           m=30, max_restarts=10, eta_max=0.9, gamma=0.9):
+           m=30, max_restarts=10, eta_max=0.9, forcing="petsc"):
+    """Inexact Newton with positivity-preserving step halving.  Forcing
+    terms (Eisenstat-Walker; Sec. 4.1 cites Kelley's algorithm, Sec. 6 says
+    the solver is PETSc's implementation, slightly modified): "petsc"
+    (PETSc's choice 2: gamma = 1, exponent (1 + 5^1/2) / 2, eta_0 = 0.3;
+    the default) or "kelley" (Kelley's safeguarded choice: gamma = 0.9,
+    exponent 2, eta_0 = eta_max); the same safeguard threshold 0.1, cap
+    eta_max and floor 0.5 tau / ||F_k||."""
+    if forcing == "petsc":
+        gamma, expo, eta0 = 1.0, 0.5 * (1.0 + np.sqrt(5.0)), 0.3
+    elif forcing == "kelley":
+        gamma, expo, eta0 = 0.9, 2.0, eta_max
+    else:
+        raise ValueError(f"unknown forcing {forcing}")
     u = u0.copy()
     F = sys.residual(u, b, dt, c0)
     fn = sys.norm(F)
@@ -225,15 +238,15 @@ def newton(sys: System, u0, b, dt, c0, beta, rtol=1e-8, atol=1e-14, maxit=20,
     fnorms = [fn]
     krylov = []
     cuts = 0
-    eta = eta_max
+    eta = eta0
     fn_old = fn
     k = 0
     while fn > stop and k < maxit:
         if k > 0:
             rat = fn / fn_old
-            enew = gamma * rat * rat
-            if gamma * eta * eta > 0.1:
-                enew = max(enew, gamma * eta * eta)
+            enew = gamma * rat**expo
+            if gamma * eta**expo > 0.1:
+                enew = max(enew, gamma * eta**expo)
             eta = min(enew, eta_max)
             eta = max(eta, 0.5 * stop / fn)
         P, _ = sys.precond(u, beta)

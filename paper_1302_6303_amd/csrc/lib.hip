@@ -1080,7 +1080,11 @@ static nrd_status newton(nrd_hierarchy* h, std::vector<nrd_step_stats>& st) {
     std::vector<double> f2;
     nrd_status rc = dot_host(h, h->F, h->F, f2);
     if (rc) return rc;
-    std::vector<double> fn(np), fn_old(np), stop(np), eta(np, 0.9), tol(np);
+    // forcing terms (Eisenstat-Walker): Kelley's choice, or PETSc's choice 2
+    const bool petsc = O.newton_forcing == NRD_EW_PETSC;
+    const double gamma = petsc ? 1.0 : 0.9, eta_max = 0.9;
+    const double ew_a = petsc ? 0.5 * (1.0 + std::sqrt(5.0)) : 2.0;
+    std::vector<double> fn(np), fn_old(np), stop(np), eta(np, petsc ? 0.3 : 0.9), tol(np);
     std::vector<int32_t> done(np, 0), failed(np, 0);
     for (int p = 0; p < np; ++p) {
         fn[p] = std::sqrt(f2[p]);
@@ -1088,7 +1092,6 @@ static nrd_status newton(nrd_hierarchy* h, std::vector<nrd_step_stats>& st) {
         stop[p] = std::max(O.newton_rtol * fn[p], O.newton_atol);
         fn_old[p] = fn[p];
     }
-    const double gamma = 0.9, eta_max = 0.9;
     for (int k = 0;; ++k) {
         bool any = false;
         for (int p = 0; p < np; ++p) {
@@ -1108,8 +1111,15 @@ static nrd_status newton(nrd_hierarchy* h, std::vector<nrd_step_stats>& st) {
             any = true;
             if (k > 0) {
                 const double rat = fn[p] / fn_old[p];
-                double en = gamma * rat * rat;
-                if (gamma * eta[p] * eta[p] > 0.1) en = std::max(en, gamma * eta[p] * eta[p]);
+                double en, sg;
+                if (petsc) {
+                    en = gamma * std::pow(rat, ew_a);
+                    sg = gamma * std::pow(eta[p], ew_a);
+                } else {
+                    en = gamma * rat * rat;
+                    sg = gamma * eta[p] * eta[p];
+                }
+                if (sg > 0.1) en = std::max(en, sg);
                 eta[p] = std::min(en, eta_max);
                 eta[p] = std::max(eta[p], 0.5 * stop[p] / fn[p]);
             }
@@ -1501,6 +1511,8 @@ void nrd_default_options(nrd_options* o) {
     o->fac_smoother = NRD_SMOOTH_RBGS;
     o->fac_base = NRD_BASE_MG;
     o->fac_cycle = NRD_FAC_MULT;
+    o->newton_forcing = NRD_EW_PETSC;
+    o->pad_ = 0;
     o->stencil = 3;
     o->bdf_max_order = 2;
     o->error_estimate = 0;
@@ -1539,6 +1551,10 @@ nrd_status nrd_hierarchy_create(const nrd_problem* probs, int32_t nprob, const n
         if (h->opt.fac_base != NRD_BASE_MG && h->opt.fac_base != NRD_BASE_SMOOTH) {
             delete h;
             return fail(NRD_EINVAL, "fac_base must be MG or SMOOTH");
+        }
+        if (h->opt.newton_forcing != NRD_EW_KELLEY && h->opt.newton_forcing != NRD_EW_PETSC) {
+            delete h;
+            return fail(NRD_EINVAL, "newton_forcing must be KELLEY or PETSC");
         }
         if (h->opt.fac_cycle != NRD_FAC_MULT && h->opt.fac_cycle != NRD_FAC_AFACX) {
             delete h;

@@ -29,6 +29,7 @@ NRD_BATCHED, NRD_PER_PATCH = 0, 1
 NRD_SMOOTH_RBGS, NRD_SMOOTH_JACOBI, NRD_SMOOTH_LINE = 0, 1, 2
 NRD_BASE_MG, NRD_BASE_SMOOTH = 0, 1
 NRD_FAC_MULT, NRD_FAC_AFACX = 0, 1
+NRD_EW_KELLEY, NRD_EW_PETSC = 0, 1
 NRD_JVP_ANALYTIC, NRD_JVP_FD = 0, 1
 NRD_TIMER_RESIDUAL, NRD_TIMER_JVP, NRD_TIMER_PRECOND = 0, 1, 2
 NRD_TIMER_SMOOTH, NRD_TIMER_SMOOTH_ZERO = 3, 4
@@ -57,7 +58,8 @@ class nrd_options(C.Structure):
                 ("bdf_max_order", C.c_int32), ("error_estimate", C.c_int32),
                 ("fac_nu_pre", C.c_int32), ("fac_nu_post", C.c_int32),
                 ("fac_smoother", C.c_int32), ("err_eta_E", C.c_double),
-                ("err_eta_T", C.c_double), ("fac_base", C.c_int32), ("fac_cycle", C.c_int32)]
+                ("err_eta_T", C.c_double), ("fac_base", C.c_int32), ("fac_cycle", C.c_int32),
+                ("newton_forcing", C.c_int32), ("pad_", C.c_int32)]
 
 
 class nrd_step_stats(C.Structure):

@@ -73,7 +73,8 @@ def test_bad_options_are_rejected():
                {"jvp_mode": 2}, {"stencil": 4}, {"bdf_max_order": 3},
                {"fac_nu_pre": 0}, {"fac_nu_post": -1}, {"fac_nu_post": 9},
                {"fac_smoother": 3}, {"fac_base": 2}, {"fac_cycle": 2},
-               {"fac_cycle": 1, "fac_smoother": 1}, {"fac_cycle": 1, "fac_nu_post": 1}):
+               {"fac_cycle": 1, "fac_smoother": 1}, {"fac_cycle": 1, "fac_nu_post": 1},
+               {"newton_forcing": 2}):
         with pytest.raises(nrd.NrdError):
             _create(w.problems, w.boxes, **kw)
 

@@ -307,6 +307,31 @@ def test_precond_parity_afacx_float32():
         assert rel_err(got[sl][mm], ref[sl][mm]) < 1e-4
 
 
+@pytest.mark.parametrize("name,forcing", [("uniform16", "petsc"), ("amr2", "petsc"),
+                                          ("uniform16", "kelley"), ("amr2", "kelley")])
+def test_implicit_steps_parity_forcing(name, forcing):
+    """Implicit steps with either choice of Eisenstat-Walker forcing terms:
+    the same states and Newton iteration counts as the oracle's stepper with
+    the same forcing."""
+    from oracle.solvers import Stepper
+    from paper_1302_6303_amd import nrd
+    w = WL[name]()
+    s = system(w)
+    H = make(w, newton_rtol=1e-10, newton_atol=1e-16,
+             newton_forcing=nrd.NRD_EW_PETSC if forcing == "petsc" else nrd.NRD_EW_KELLEY)
+    st = Stepper(s, state(s, w), rtol=1e-10, atol=1e-16, forcing=forcing)
+    for dt in (1e-3, 1e-3, 1.5e-3):
+        rc, stats = H.implicit_step([dt])
+        r = st.step(dt)
+        assert r.converged and stats[0]["converged"]
+        assert stats[0]["newton_iters"] == r.iters
+        E, T = H.get_fields()
+        got = np.concatenate([to_host(E), to_host(T)])
+        n = s.nc
+        for sl in (slice(0, n), slice(n, 2 * n)):
+            assert rel_err(got[sl], st.u[sl]) < 1e-8
+
+
 @pytest.mark.parametrize("name", ["amr2", "tiled"])
 def test_implicit_steps_parity_afacx(name):
     """Implicit steps preconditioned by AFACx: same states as the oracle's
@@ -444,7 +469,8 @@ def _cut_parity(specs):
     from oracle.solvers import Stepper
     from tests.gpu_helpers import problem_slices
     w = _far_from_equilibrium(specs)
-    H = make(w, newton_rtol=1e-10, newton_atol=1e-16, newton_maxit=24, bdf_max_order=1)
+    H = make(w, newton_rtol=1e-10, newton_atol=1e-16, newton_maxit=24, bdf_max_order=1,
+             newton_forcing=0)
     rc, stats = H.implicit_step([1e-2] * len(specs), raise_on_fail=False)
     E, T = H.get_fields()
     got = np.concatenate([to_host(E), to_host(T)])
@@ -452,7 +478,7 @@ def _cut_parity(specs):
     res = []
     for p in range(len(specs)):
         s = system(w, pidx=p)
-        st = Stepper(s, state(s, w, pidx=p), rtol=1e-10, atol=1e-16, maxit=24)
+        st = Stepper(s, state(s, w, pidx=p), rtol=1e-10, atol=1e-16, maxit=24, forcing="kelley")
         r = st.step(1e-2)
         assert bool(stats[p]["converged"]) == bool(r.converged)
         assert stats[p]["newton_iters"] == r.iters
@@ -467,8 +493,9 @@ def _cut_parity(specs):
 
 def test_implicit_step_positivity_cuts_in_lock_step():
     """One BDF1 step of three problems solved together whose full Newton
-    steps are accepted (seed 21) or halved (seeds 20, 25), each against its
-    own oracle run: Newton iterations and cuts equal, states to 1e-8."""
+    steps are accepted (seed 21) or halved (seeds 20, 25) with Kelley's
+    forcing terms, each against its own oracle run: Newton iterations and
+    cuts equal, states to 1e-8."""
     rc, res = _cut_parity([(20, 1e-4), (21, 1e-4), (25, 1e-2)])
     assert rc == 0
     assert res[1].cuts == 0 and res[0].cuts > 0 and res[2].cuts > 0
@@ -504,7 +531,7 @@ def test_adaptive_steps_match_the_oracle():
         T.append(wp.T[0])
     w = I.Workload("adapt3", problems, boxes, z, E, T, np.array([1e-3, 5e-4, 1e-2]))
     eps, nsteps = 5e-3, 6
-    kw = dict(newton_rtol=1e-10, newton_atol=1e-16, newton_maxit=24)
+    kw = dict(newton_rtol=1e-10, newton_atol=1e-16, newton_maxit=24, newton_forcing=0)
     H = make(w, error_estimate=1, **kw)
     rc, dt_next, t, steps = H.adaptive_steps(nsteps, list(w.dt), eps)
     E_g, T_g = H.get_fields()
@@ -513,7 +540,7 @@ def test_adaptive_steps_match_the_oracle():
     for p in range(3):
         s = system(w, pidx=p)
         ad = AdaptiveStepper(s, state(s, w, pidx=p), w.dt[p], eps, 1e-5, 1e-5 ** 0.25,
-                             rtol=1e-10, atol=1e-16, maxit=24)
+                             rtol=1e-10, atol=1e-16, maxit=24, forcing="kelley")
         for _ in range(nsteps):
             ad.advance()
         dts = [steps[n][p]["dt"] for n in range(nsteps)]
