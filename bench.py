@@ -865,9 +865,9 @@ def main():
     ap.add_argument("--fac-smoother", choices=("rbgs", "jacobi", "line"), default="rbgs",
                     help="FAC level smoother: red-black Gauss-Seidel (default), damped "
                          "point Jacobi or x-line block Gauss-Seidel")
-    ap.add_argument("--forcing", choices=("kelley", "petsc"), default="kelley",
-                    help="Eisenstat-Walker forcing terms of the Newton solves: Kelley's "
-                         "choice (default) or PETSc's choice 2")
+    ap.add_argument("--forcing", choices=("petsc", "kelley"), default="petsc",
+                    help="Eisenstat-Walker forcing terms of the Newton solves: PETSc's "
+                         "choice 2 (default, the library's) or Kelley's choice")
     ap.add_argument("--fac-cycle", choices=("mult", "afacx"), default="mult",
                     help="P1 cycle on refined hierarchies: multiplicative FAC (default) or "
                          "AFACx (every level pair at once)")
