@@ -34,6 +34,10 @@ Workloads (seeded, synthetic; --workload):
   paperN    the paper's model problem on a uniform N^3 grid integrated to
             --t-final (default 1) with PC.4.7; reports seconds, steps and
             iterations per step beside the paper's uniform-grid tables
+  paperNbLl the same problem on a dynamically refined hierarchy: base N^3,
+            L levels, tags tau^g or tau^c > --tau checked every 10 steps,
+            regrid (transfer, warm restart with re-solve) when the boxes
+            change; beside the paper's AMR columns of those tables
   paper-spatial  uniform 128^3 against a 256^3 reference with the same
             steps: L2 errors beside the paper's spatial-accuracy table
             (paper-spatial-z1: its single-material variant, z = 1)
@@ -45,6 +49,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -318,6 +323,93 @@ def paper_bench(n, t_final, limiter=0.5, base="mg", jvp="analytic", forcing=0):
            "paper_levels1": ({"linear_per_step": ref[0], "nonlinear_per_step": ref[1],
                               "steps": ref[2]} if ref and abs(t_final - ref[3]) < 1e-12
                              else None)}
+    print(json.dumps(out), flush=True)
+
+
+# The paper's efficiency tables (average linear and nonlinear iterations per
+# step, steps to t = 1) for AMR runs: base n^3 and L levels -> (linear,
+# nonlinear, steps).
+PAPER_AMR = {(16, 2): (7.71, 2.99, 1333), (16, 3): (7.21, 2.96, 3251), (16, 4): (6.63, 2.64, 8204),
+             (16, 5): (6.92, 2.71, 8697), (32, 2): (7.22, 2.96, 3251), (32, 3): (6.61, 2.63, 8204),
+             (32, 4): (6.91, 2.71, 8704), (64, 2): (6.63, 2.64, 8204), (64, 3): (6.92, 2.71, 8704),
+             (128, 2): (6.86, 2.72, 8734)}
+
+
+def paper_amr_bench(n, nlev, t_final, every=10, tau=0.5, forcing=1, cycle=0):
+    """The paper's model problem on a dynamically refined hierarchy: base
+    n^3 and nlev levels, integrated to t_final with BDF2 and PC.4.7 at the
+    tolerance of the finest resolution (eps_t = 5e-4 at 32^3, halved per
+    doubling), Newton tolerances 1e-12 / 1e-10, mixed precision.  Every
+    `every` steps the cells with tau^g or tau^c above tau are tagged (Sec. 5),
+    grown by 2 cells and clustered (Berger-Rigoutsos, efficiency 0.7, sides
+    4..24 tagged-level cells); a regrid (transfer, warm restart with
+    re-solve) happens only when the boxes change."""
+    import torch
+    from paper_1302_6303_amd import inputs as I, nrd
+    from paper_1302_6303_amd.regrid import Regridder
+    w = I.paper_marshak(n)
+    prob = w.problems[0]
+    eps = 5e-4 * 32.0 / (n * 2 ** (nlev - 1))
+    opts = nrd.default_options(precision=nrd.NRD_MIXED, error_estimate=1,
+                               newton_rtol=1e-12, newton_atol=1e-10,
+                               newton_forcing=forcing, fac_cycle=cycle)
+    zfun = material_sampler(I.PAPER_BOXES)
+    R = Regridder(opts, dict(tau_g=tau, tau_c=tau),
+                  dict(max_levels=nlev, buffer=2, efficiency=0.7, min_side=4, max_side=24),
+                  zfun)
+    boxes = list(w.boxes)
+    H = nrd.Hierarchy([prob], boxes, opts)
+    m = H.ncells
+    H.set_fields(torch.full((m,), I.E0, dtype=torch.float64, device="cuda"),
+                 torch.full((m,), I.T0, dtype=torch.float64, device="cuda"),
+                 zfun([prob], boxes))
+    t, dt = 0.0, float(w.dt[0])
+    steps = newton = krylov = cuts = 0
+    regrids = rs_newton = rs_krylov = 0
+    cells_sum = 0
+    t0 = time.perf_counter()
+    while t < t_final * (1.0 - 1e-12):
+        if steps > 0 and steps % every == 0:
+            nb = R.boxes_for(H)
+            key = sorted((b.level, tuple(b.lo), tuple(b.hi)) for b in nb)
+            if key != sorted((b.level, tuple(b.lo), tuple(b.hi)) for b in boxes):
+                Hn, boxes, info = R.regrid(H, nb)
+                del H
+                H = Hn
+                regrids += 1
+                rs_newton += info["resolve_newton"]
+                rs_krylov += info["resolve_krylov"]
+        dt = min(dt, t_final - t)
+        _, dtn, tt, st = H.adaptive_steps(1, [dt], eps, t=[t])
+        s = st[0][0]
+        steps += 1
+        newton += s["newton_iters"]
+        krylov += s["krylov_iters"]
+        cuts += s["positivity_cuts"]
+        cells_sum += H.ncells
+        t, dt = tt[0], dtn[0]
+        if steps % 500 == 0:
+            log(f"paper{n}b{nlev}l: step {steps}, t = {t:.4g}, dt = {dt:.3g}, "
+                f"{len(boxes)} boxes, {H.ncells} cells, {regrids} regrids")
+    wall = time.perf_counter() - t0
+    ref = PAPER_AMR.get((n, nlev))
+    out = {"metric": f"seconds to t = {t_final:g}, paper model problem, {n}^3 base, "
+                     f"{nlev} levels",
+           "value": round(wall, 3), "unit": "s", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"paper{n}b{nlev}l", "eps_t": eps, "regrid_every": every,
+                      "tags": f"tau_g or tau_c > {tau}, grown by 2",
+                      "solver": "BDF2, PC.4.7, Newton rtol 1e-12 atol 1e-10, FGMRES(30), "
+                                + ("AFACx" if cycle else "FAC V(1,0)")
+                                + " + MG V(1,1), mixed precision"},
+           "steps": steps, "t_final": t,
+           "linear_per_step": round(krylov / steps, 3),
+           "nonlinear_per_step": round(newton / steps, 3),
+           "regrids": regrids, "resolve_newton": rs_newton, "resolve_krylov": rs_krylov,
+           "positivity_cuts": cuts, "ms_per_step": round(1e3 * wall / steps, 3),
+           "mean_cells": round(cells_sum / steps), "final_boxes": len(boxes),
+           "paper": ({"linear_per_step": ref[0], "nonlinear_per_step": ref[1], "steps": ref[2]}
+                     if ref and abs(t_final - 1.0) < 1e-12 else None)}
     print(json.dumps(out), flush=True)
 
 
@@ -880,6 +972,8 @@ def main():
     ap.add_argument("--jvp", choices=("analytic", "fd"), default="analytic",
                     help="paperN workloads: Jacobian action, analytic (default) or the "
                          "paper's Jacobian-free difference quotient")
+    ap.add_argument("--tau", type=float, default=0.5,
+                    help="paperNbLl workloads: tagging threshold of tau^g and tau^c")
     ap.add_argument("--ramp", action="store_true",
                     help="paper-temporal: take each run's first interval as dt/4, dt/4, dt/2")
     ap.add_argument("--t-final", type=float, default=1.0,
@@ -917,6 +1011,12 @@ def main():
         return
     if a.workload == "paper-temporal":
         paper_temporal_bench(limiter=a.limiter, ramp=a.ramp)
+        return
+    mm = re.fullmatch(r"paper(\d+)b(\d+)l", a.workload)
+    if mm:
+        paper_amr_bench(int(mm.group(1)), int(mm.group(2)), a.t_final, tau=a.tau,
+                        forcing=nrd.NRD_EW_PETSC if a.forcing == "petsc" else nrd.NRD_EW_KELLEY,
+                        cycle=nrd.NRD_FAC_AFACX if a.fac_cycle == "afacx" else nrd.NRD_FAC_MULT)
         return
     if a.workload.startswith("paper"):
         paper_bench(int(a.workload[5:]), a.t_final, a.limiter, a.fac_base, a.jvp,
