@@ -367,10 +367,13 @@ def paper_amr_bench(n, nlev, t_final, every=10, tau=0.5, forcing=1, cycle=0):
     steps = newton = krylov = cuts = 0
     regrids = rs_newton = rs_krylov = 0
     cells_sum = 0
+    regrid_s = {"tag_cluster": 0.0, "create_transfer": 0.0, "resolve": 0.0}
     t0 = time.perf_counter()
     while t < t_final * (1.0 - 1e-12):
         if steps > 0 and steps % every == 0:
+            ta = time.perf_counter()
             nb = R.boxes_for(H)
+            regrid_s["tag_cluster"] += time.perf_counter() - ta
             key = sorted((b.level, tuple(b.lo), tuple(b.hi)) for b in nb)
             if key != sorted((b.level, tuple(b.lo), tuple(b.hi)) for b in boxes):
                 Hn, boxes, info = R.regrid(H, nb)
@@ -379,6 +382,8 @@ def paper_amr_bench(n, nlev, t_final, every=10, tau=0.5, forcing=1, cycle=0):
                 regrids += 1
                 rs_newton += info["resolve_newton"]
                 rs_krylov += info["resolve_krylov"]
+                regrid_s["create_transfer"] += info["create_transfer_s"]
+                regrid_s["resolve"] += info["resolve_s"]
         dt = min(dt, t_final - t)
         _, dtn, tt, st = H.adaptive_steps(1, [dt], eps, t=[t])
         s = st[0][0]
@@ -406,6 +411,7 @@ def paper_amr_bench(n, nlev, t_final, every=10, tau=0.5, forcing=1, cycle=0):
            "linear_per_step": round(krylov / steps, 3),
            "nonlinear_per_step": round(newton / steps, 3),
            "regrids": regrids, "resolve_newton": rs_newton, "resolve_krylov": rs_krylov,
+           "regrid_s": {k: round(v, 2) for k, v in regrid_s.items()},
            "positivity_cuts": cuts, "ms_per_step": round(1e3 * wall / steps, 3),
            "mean_cells": round(cells_sum / steps), "final_boxes": len(boxes),
            "paper": ({"linear_per_step": ref[0], "nonlinear_per_step": ref[1], "steps": ref[2]}
