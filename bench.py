@@ -960,6 +960,8 @@ def main():
     ap.add_argument("--fac-nu", type=int, nargs=2, default=(1, 0), metavar=("M", "N"),
                     help="FAC V(M, N): M down-sweep and N up-sweep red-black sweeps per "
                          "level above the base (default 1 0, the paper's V(1,0))")
+    ap.add_argument("--mg-nu", type=int, nargs=2, default=(1, 1), metavar=("PRE", "POST"),
+                    help="base multigrid V(PRE, POST) red-black sweeps per grid (default 1 1)")
     ap.add_argument("--fac-smoother", choices=("rbgs", "jacobi", "line"), default="rbgs",
                     help="FAC level smoother: red-black Gauss-Seidel (default), damped "
                          "point Jacobi or x-line block Gauss-Seidel")
@@ -1042,7 +1044,8 @@ def main():
                                               bdf_max_order=a.bdf_max_order,
                                               fac_nu_pre=a.fac_nu[0], fac_nu_post=a.fac_nu[1],
                                               fac_smoother=smoother, fac_cycle=cycle,
-                                              newton_forcing=forcing),
+                                              newton_forcing=forcing, mg_nu_pre=a.mg_nu[0],
+                                              mg_nu_post=a.mg_nu[1]),
                        a.steps, a.warmup, True, a.adaptive_eps)
     mixed["use_graph"] = use_graph
     plain = None
@@ -1054,7 +1057,8 @@ def main():
                                                   bdf_max_order=a.bdf_max_order,
                                                   fac_nu_pre=a.fac_nu[0], fac_nu_post=a.fac_nu[1],
                                                   fac_smoother=smoother, fac_cycle=cycle,
-                                              newton_forcing=forcing),
+                                              newton_forcing=forcing, mg_nu_pre=a.mg_nu[0],
+                                              mg_nu_post=a.mg_nu[1]),
                            a.steps, a.warmup, False, a.adaptive_eps)
     batched64 = None
     if a.fp64_batched:
@@ -1063,7 +1067,8 @@ def main():
                                                       bdf_max_order=a.bdf_max_order,
                                                       fac_nu_pre=a.fac_nu[0], fac_nu_post=a.fac_nu[1],
                                                       fac_smoother=smoother, fac_cycle=cycle,
-                                              newton_forcing=forcing),
+                                              newton_forcing=forcing, mg_nu_pre=a.mg_nu[0],
+                                              mg_nu_post=a.mg_nu[1]),
                                a.steps, a.warmup, False, a.adaptive_eps)
     res_s = mixed["residual_ms_avg"] / 1e3
     res_cells = mixed["residual_cells_avg"]           # per launch, average
@@ -1101,12 +1106,13 @@ def main():
                                     else "fixed steps"),
                    "solver": ("BDF1->BDF2" if a.bdf_max_order == 2 else "BDF1") +
                              ", Newton rtol 1e-8 (%s forcing), FGMRES(30), %s V(%d,%d) %s"
-                             " + MG V(1,1)"
+                             " + MG V(%d,%d)"
                              % ("PETSc" if a.forcing == "petsc" else "Kelley",
                                 "AFACx" if a.fac_cycle == "afacx" else "FAC",
                                 a.fac_nu[0], a.fac_nu[1],
                                 {"rbgs": "RBGS", "jacobi": "damped Jacobi",
-                                 "line": "x-line block GS"}[a.fac_smoother])},
+                                 "line": "x-line block GS"}[a.fac_smoother],
+                                a.mg_nu[0], a.mg_nu[1])},
         "roofline": {"bound": "hbm", "kernel": "k_stencil_s<0> (residual)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

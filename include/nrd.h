@@ -321,8 +321,9 @@ nrd_status nrd_adaptive_steps(nrd_hierarchy* h, const nrd_timectl* ctl, int32_t 
                               double* dt, double* t, nrd_step_stats* stats);
 
 /* Discrete adjoint of nsteps BDF1 steps of size dt from the current state
- * for J = sum over the composite cells of dJdE_final[c] * E_N(c) (device,
- * compact E part, covered entries ignored; NULL = all ones).  Forward
+ * for J = sum over cells of dJdE_final[c] * E_N(c) (device, compact E part;
+ * a covered cell's E is the mean of its children's, so its weight reaches
+ * them; NULL = 1 on every composite cell and 0 on covered cells).  Forward
  * states are checkpointed every ckpt_every steps and recomputed segment by
  * segment.  gz (device, ncells) receives dJ/dz for the z of every cell of
  * every level.  The state afterwards is u_N. */

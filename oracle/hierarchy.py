@@ -168,6 +168,26 @@ class Hierarchy:
                         acc += self.value_at(f, l + 1, 2 * I + o)
                     f[p.pid][loc[:, 0] + 1, loc[:, 1] + 1, loc[:, 2] + 1] = acc / 8.0
 
+    def sync_transpose(self, fields):
+        """Transpose of sync, in place on ghosted arrays: coarsest level
+        first, every covered cell hands 1/8 of its value to each of its
+        eight children and keeps none."""
+        for l in range(self.nlev - 1):
+            for p in self.by_level[l]:
+                cov = np.argwhere(self.covered[p.pid])
+                if len(cov) == 0:
+                    continue
+                I = cov + p.lo
+                for f in fields:
+                    v = f[p.pid][cov[:, 0] + 1, cov[:, 1] + 1, cov[:, 2] + 1] / 8.0
+                    for o in _OCT:
+                        pid, loc = self.locate(l + 1, 2 * I + o)
+                        for q in np.unique(pid):
+                            m = pid == q
+                            ll = loc[m] + 1
+                            np.add.at(f[q], (ll[:, 0], ll[:, 1], ll[:, 2]), v[m])
+                    f[p.pid][cov[:, 0] + 1, cov[:, 1] + 1, cov[:, 2] + 1] = 0.0
+
     # -- ghost fill -------------------------------------------------------
     def ghost_kinds(self, p, d, s):
         """Ghost layer of face (d, s) of patch p: level indices and kind.

@@ -732,22 +732,7 @@ def vjp(H, E, T, z, lE, lT, dt, c0, lam=1.0, magnitude=False):
                                           (2.0 / 3.0) * (wq / 16.0) * gm[mm])
                     acc[p.pid][gl[:, 0], gl[:, 1], gl[:, 2]] = 0.0
     # transposed restriction, coarse to fine (z is not restricted)
-    for lev in range(H.nlev - 1):
-        for p in H.by_level[lev]:
-            cov = np.argwhere(H.covered[p.pid])
-            if len(cov) == 0:
-                continue
-            I = cov + p.lo
-            for acc in (aE, aT):
-                v = acc[p.pid][cov[:, 0] + 1, cov[:, 1] + 1, cov[:, 2] + 1] / 8.0
-                from .hierarchy import _OCT
-                for o in _OCT:
-                    pid, loc = H.locate(lev + 1, 2 * I + o)
-                    for qq in np.unique(pid):
-                        mm = pid == qq
-                        ll = loc[mm] + 1
-                        np.add.at(acc[qq], (ll[:, 0], ll[:, 1], ll[:, 2]), v[mm])
-                acc[p.pid][cov[:, 0] + 1, cov[:, 1] + 1, cov[:, 2] + 1] = 0.0
+    H.sync_transpose([aE, aT])
     gE = [a[1:-1, 1:-1, 1:-1].copy() for a in aE]
     gT = [a[1:-1, 1:-1, 1:-1].copy() for a in aT]
     gz = [a[1:-1, 1:-1, 1:-1].copy() for a in aZ]

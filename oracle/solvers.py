@@ -474,10 +474,12 @@ class AdaptiveStepper(Stepper):
 # ---------------------------------------------------------------------------
 
 def adjoint_gradient(sys: System, u0, dt, nsteps, tol=1e-11, newton_kw=None,
-                     m=30, max_restarts=20):
-    """dJ/dz for J = sum of E_N over the composite cells (covered cells,
-    which hold restricted values, are not counted) after nsteps BDF1 steps
-    of size dt; z of every level, covered cells included.
+                     m=30, max_restarts=20, dJdE=None):
+    """dJ/dz for J = sum over cells of dJdE[c] E_N(c) (compact E part;
+    default: 1 on every composite cell, 0 on covered cells) after nsteps
+    BDF1 steps of size dt; z of every level, covered cells included.  A
+    covered cell's E is the mean of its children's, so its weight passes to
+    them (transposed restriction) before the reverse sweep.
 
     Forward: u_n solves F_n = u_n - u_{n-1} - dt f(u_n; z) = 0 on the
     composite cells, covered cells restricted from their children.  Reverse:
@@ -494,7 +496,14 @@ def adjoint_gradient(sys: System, u0, dt, nsteps, tol=1e-11, newton_kw=None,
             raise RuntimeError("forward solve failed")
         states.append(st.u.copy())
     nc = sys.nc
-    rhs = np.concatenate([sys.composite[:nc].astype(np.float64), np.zeros(nc)])
+    if dJdE is None:
+        gE = sys.composite[:nc].astype(np.float64)
+    else:
+        E, _ = sys.split(np.concatenate([np.asarray(dJdE, dtype=np.float64), np.zeros(nc)]))
+        Eg = sys.H.from_interior(E)
+        sys.H.sync_transpose([Eg])
+        gE = np.concatenate([a[1:-1, 1:-1, 1:-1].ravel(order="F") for a in Eg])
+    rhs = np.concatenate([gE, np.zeros(nc)])
     grad = np.zeros(nc)
     euclid = lambda x, y: float(np.dot(x, y))
     for n in range(nsteps, 0, -1):

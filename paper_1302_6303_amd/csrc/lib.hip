@@ -1397,17 +1397,19 @@ static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, in
         nrd_status rc = implicit_step(h, dtv.data(), nullptr, true);
         if (rc) return rc;
     }
-    // lambda_N rhs: (dJ/dE, 0) on the composite cells (covered cells hold
-    // restricted values, not unknowns)
+    // lambda_N rhs: (dJ/dE, 0) in the composite unknowns.  A covered cell
+    // holds the mean of its children, so a weight given to it passes to them
+    // (transposed restriction); the default objective counts composite cells.
     fill_native(s, rhs, NL, 0.0);
     if (dJdE) {
         unpack(h->D, s, h->at<int64_t>(h->o.coff), dJdE, rhs, 1, t.ncells);
+        restrict_transpose(h->D, s, rhs, 1);
     } else {
         // a compact vector of ones, built on the device in gz (overwritten below)
         fill_native(s, gz, t.ncells, 1.0);
         unpack(h->D, s, h->at<int64_t>(h->o.coff), gz, rhs, 1, t.ncells);
+        zero_covered(h->D, s, rhs, 1);
     }
-    zero_covered(h->D, s, rhs, 1);
     fill_native(s, lam, NL, 0.0);
     fill_native(s, gacc, NL, 0.0);              // dJ/dz accumulator (field 0)
     for (int p = 0; p < np; ++p) {

@@ -215,6 +215,56 @@ def test_adjoint_on_two_levels_matches_central_differences():
         assert abs(fd - g[c]) <= 1e-5 * abs(g[c]), (c, fd, g[c])
 
 
+def test_adjoint_of_a_batch_with_a_refined_problem():
+    """Two problems adjoined together, one refined (two levels) and one
+    uniform with smooth random material: each problem's part of dJ/dz
+    against its own oracle adjoint (J sums E over every problem's composite
+    cells, so the problems' gradients are independent)."""
+    a = _two_level()
+    b = I.marshak_single(6)
+    b.z = [_smooth_z(6, 94)]
+    boxes = list(a.boxes) + [I.Box(1, bb.level, bb.lo, bb.hi) for bb in b.boxes]
+    w = I.Workload("pair", a.problems + b.problems, boxes, a.z + b.z, a.E + b.E, a.T + b.T,
+                   np.array([2e-3, 2e-3]))
+    N, every, dt = 3, 2, 2e-3
+    H = make(w, newton_rtol=1e-11, newton_atol=1e-22, newton_maxit=24,
+             adjoint_slots=(N + every - 1) // every + every + 3, gmres_maxrestarts=20)
+    gz = to_host(H.adjoint_run([dt, dt], N, every))
+    off = 0
+    for p in range(2):
+        s = system(w, pidx=p)
+        ref, _ = adjoint_gradient(s, state(s, w, pidx=p), dt, N, tol=1e-13,
+                                  newton_kw=dict(rtol=1e-11, atol=1e-22, maxit=40))
+        assert rel_err(gz[off:off + s.nc], ref) < 1e-7, p
+        off += s.nc
+
+
+def test_autograd_on_a_refined_hierarchy():
+    """torch.autograd through RadDiffEvolve on two levels: E at the end and
+    dJ/dz of J = a weighted sum of E over every cell, covered cells included
+    (their E is the mean of their children's, so their weights reach the
+    children), against the oracle's adjoint of the same objective."""
+    import torch
+    from paper_1302_6303_amd.autograd import RadDiffEvolve
+    w = _two_level()
+    N, every, dt = 2, 1, 2e-3
+    H = make(w, newton_rtol=1e-11, newton_atol=1e-22, newton_maxit=24, bdf_max_order=1,
+             adjoint_slots=N // every + every + 3, gmres_maxrestarts=20)
+    u = compact_state(w)
+    nc = H.ncells
+    E0, T0 = to_dev(u[:nc]), to_dev(u[nc:])
+    z = to_dev(w.compact(w.z)).requires_grad_(True)
+    E = RadDiffEvolve.apply(z, H, E0, T0, dt, N, every)
+    s = system(w)
+    wts = np.random.default_rng(95).uniform(0.5, 1.5, nc)
+    (E * to_dev(wts)).sum().backward()
+    ref, states = adjoint_gradient(s, state(s, w), dt, N, tol=1e-13,
+                                   newton_kw=dict(rtol=1e-11, atol=1e-22, maxit=40),
+                                   dJdE=wts)
+    assert rel_err(to_host(E), states[-1][:nc]) < 1e-8
+    assert rel_err(to_host(z.grad), ref) < 1e-7
+
+
 def test_adjoint_gradient_matches_central_differences():
     """dJ/dz of J = sum of E after N BDF1 steps, against central
     differences of the same GPU forward solve (h = 1e-5 z) on the cells with

@@ -316,3 +316,22 @@ def test_line_smoother_beats_point_smoothing_on_stretched_cells():
             x = [x[q] + c[q] for q in range(len(x))]
         rates[sm] = (norms[-1] / norms[2]) ** 0.25
     assert rates["line"] < 0.5 * rates["rbgs"] and rates["line"] < 0.5, rates
+
+
+@pytest.mark.parametrize("nlev", [2, 3])
+def test_sync_transpose_is_the_transpose_of_sync(nlev):
+    """<S x, y> = <x, S^T y> for the restriction S that sync applies (covered
+    cells take the mean of their children, finest level first) and the
+    coarse-to-fine hand-down of sync_transpose, on random per-patch data."""
+    H = Hierarchy((8, 8, 8), _nested(nlev))
+    rng = np.random.default_rng(40 + nlev)
+    x = H.from_interior([rng.standard_normal(tuple(int(v) for v in p.n)) for p in H.patches])
+    y = H.from_interior([rng.standard_normal(tuple(int(v) for v in p.n)) for p in H.patches])
+    Sx = [a.copy() for a in x]
+    H.sync([Sx])
+    Sty = [a.copy() for a in y]
+    H.sync_transpose([Sty])
+    inner = lambda a, b: sum(float(np.sum(u[1:-1, 1:-1, 1:-1] * v[1:-1, 1:-1, 1:-1]))
+                             for u, v in zip(a, b))
+    lhs, rhs = inner(Sx, y), inner(x, Sty)
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + abs(rhs))
