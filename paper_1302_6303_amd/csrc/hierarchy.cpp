@@ -373,7 +373,6 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
     }
     // ghosts
     std::vector<std::vector<GhostCopy>> sib_by_level(t.nlev);
-    std::vector<int32_t> cf_prob;            // problem of each gcf entry
     for (int b = 0; b < nbox; ++b) {
         const HostBox& x = t.boxes[b];
         const PatchInfo& pi = t.patches[b];
@@ -442,31 +441,10 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
                         }
                         e.src[4] = inner;
                         t.gcf.push_back(e);
-                        cf_prob.push_back(x.prob);
+                        t.gcf_prob.push_back(x.prob);
                         t.ctype[gidx] = GK_CF;
                     }
             }
-        }
-    }
-    {
-        // the transposed interpolation gathers, per coarse source cell, the
-        // ghosts it feeds (a source clipped at the domain edge may appear
-        // twice for one ghost)
-        struct Ent { int32_t c, ghost, w, prob; };
-        std::vector<Ent> ents;
-        ents.reserve(4 * t.gcf.size());
-        static const int32_t wq[4] = {9, 3, 3, 1};
-        for (size_t i = 0; i < t.gcf.size(); ++i)
-            for (int q = 0; q < 4; ++q)
-                ents.push_back({t.gcf[i].src[q], t.gcf[i].dst, wq[q], cf_prob[i]});
-        std::stable_sort(ents.begin(), ents.end(),
-                         [](const Ent& a, const Ent& b) { return a.c < b.c; });
-        for (size_t i = 0; i < ents.size();) {
-            size_t j = i;
-            while (j < ents.size() && ents[j].c == ents[i].c) ++j;
-            t.cfrows.push_back({ents[i].c, (int32_t)i, (int32_t)(j - i), ents[i].prob});
-            for (size_t k = i; k < j; ++k) t.cfsrc.push_back({ents[k].ghost, ents[k].w});
-            i = j;
         }
     }
     t.level_sib0.assign(t.nlev + 1, 0);
@@ -705,6 +683,48 @@ nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
         return NRD_EUNSUPPORTED;
     }
     return NRD_OK;
+}
+
+// The transposed coarse-fine interpolation gathers, per coarse source cell,
+// the ghosts it feeds (a source clipped at the domain edge may appear twice
+// for one ghost): CSR rows sorted by the source's native index.  Built on
+// the first transposed product only (forward work never reads it).
+void build_cf_transpose(const Tables& t, std::vector<CFRow>& rows, std::vector<CFSrc>& src) {
+    struct Ent { int32_t c, ghost, w, prob; };
+    std::vector<Ent> ents;
+    ents.reserve(4 * t.gcf.size());
+    static const int32_t wq[4] = {9, 3, 3, 1};
+    for (size_t i = 0; i < t.gcf.size(); ++i)
+        for (int q = 0; q < 4; ++q)
+            ents.push_back({t.gcf[i].src[q], t.gcf[i].dst, wq[q], t.gcf_prob[i]});
+    // stable LSD radix sort by source cell (millions of entries on deep
+    // hierarchies)
+    uint32_t cmax = 0;
+    for (const Ent& e : ents) cmax = std::max(cmax, (uint32_t)e.c);
+    int bits = 1;
+    while (bits < 32 && (cmax >> bits)) ++bits;
+    const int npass = (bits + 12) / 13;
+    const int dig = (bits + npass - 1) / npass;
+    const uint32_t mask = (1u << dig) - 1u;
+    std::vector<Ent> tmp(ents.size());
+    std::vector<size_t> cnt((size_t)mask + 2);
+    for (int shift = 0; shift < npass * dig; shift += dig) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (const Ent& e : ents) ++cnt[((uint32_t)e.c >> shift & mask) + 1];
+        for (uint32_t i = 0; i <= mask; ++i) cnt[i + 1] += cnt[i];
+        for (const Ent& e : ents) tmp[cnt[(uint32_t)e.c >> shift & mask]++] = e;
+        ents.swap(tmp);
+    }
+    rows.clear();
+    src.clear();
+    src.reserve(ents.size());
+    for (size_t i = 0; i < ents.size();) {
+        size_t j = i;
+        while (j < ents.size() && ents[j].c == ents[i].c) ++j;
+        rows.push_back({ents[i].c, (int32_t)i, (int32_t)(j - i), ents[i].prob});
+        for (size_t k = i; k < j; ++k) src.push_back({ents[k].ghost, ents[k].w});
+        i = j;
+    }
 }
 
 }  // namespace nrd

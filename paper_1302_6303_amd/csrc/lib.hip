@@ -96,6 +96,7 @@ struct nrd_hierarchy final : public Clock {
     PcArrays<float> pcf;
     PcArrays<double> pcd;
     bool mixed = false;
+    bool cf_built = false;          // transposed coarse-fine table uploaded
     std::vector<int32_t> patch_tile0;
 
     // workspace offsets
@@ -237,8 +238,10 @@ static void layout(nrd_hierarchy* h) {
         o.sync[l] = b.take(sizeof(SyncEntry) * std::max<size_t>(1, t.sync[l].size()));
     o.rfaces = b.take(sizeof(RefluxFace) * std::max<size_t>(1, t.rfaces.size()));
     o.rcells = b.take(sizeof(RefluxCell) * std::max<size_t>(1, t.rcells.size()));
-    o.cfrows = b.take(sizeof(CFRow) * std::max<size_t>(1, t.cfrows.size()));
-    o.cfsrc = b.take(sizeof(CFSrc) * std::max<size_t>(1, t.cfsrc.size()));
+    // transposed coarse-fine interpolation, built on the first transposed
+    // product: at most 4 sources and 4 rows per coarse-fine ghost
+    o.cfrows = b.take(sizeof(CFRow) * std::max<size_t>(1, 4 * t.gcf.size()));
+    o.cfsrc = b.take(sizeof(CFSrc) * std::max<size_t>(1, 4 * t.gcf.size()));
     o.ctype = b.take(t.ctype.size());
     o.shadows = b.take(sizeof(ShadowPatch) * t.shadow.size());
     o.shadow_src = b.take(sizeof(int32_t) * std::max<int64_t>(1, t.shadow_len));
@@ -423,8 +426,6 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     for (int l = 0; l < t.nlev; ++l) HIPCHK(up(s, h->ws + o.sync[l], t.sync[l]));
     HIPCHK(up(s, h->ws + o.rfaces, t.rfaces));
     HIPCHK(up(s, h->ws + o.rcells, t.rcells));
-    HIPCHK(up(s, h->ws + o.cfrows, t.cfrows));
-    HIPCHK(up(s, h->ws + o.cfsrc, t.cfsrc));
     HIPCHK(up(s, h->ws + o.ctype, t.ctype));
     HIPCHK(up(s, h->ws + o.shadows, t.shadow));
     HIPCHK(up(s, h->ws + o.shadow_src, t.shadow_src));
@@ -551,7 +552,8 @@ static nrd_status bind(nrd_hierarchy* h, void* ptr, size_t bytes) {
     D.nrcells = (int32_t)t.rcells.size();
     D.cfrows = h->at<CFRow>(o.cfrows);
     D.cfsrc = h->at<CFSrc>(o.cfsrc);
-    D.ncfrows = (int32_t)t.cfrows.size();
+    D.ncfrows = 0;                 // set by ensure_cf_transpose
+    h->cf_built = false;
     D.ctype = h->at<uint8_t>(o.ctype);
     D.ps = h->at<ProbScalars>(o.ps);
     D.active = nullptr;
@@ -1368,6 +1370,21 @@ static nrd_status implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_sta
     return NRD_OK;
 }
 
+// The transposed coarse-fine interpolation table, built and uploaded on the
+// first transposed product (forward work never reads it).
+static nrd_status ensure_cf_transpose(nrd_hierarchy* h) {
+    if (h->cf_built) return NRD_OK;
+    std::vector<CFRow> rows;
+    std::vector<CFSrc> src;
+    build_cf_transpose(h->t, rows, src);
+    HIPCHK(up(h->stream, h->ws + h->o.cfrows, rows));
+    HIPCHK(up(h->stream, h->ws + h->o.cfsrc, src));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->D.ncfrows = (int32_t)rows.size();
+    h->cf_built = true;
+    return NRD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // discrete adjoint of BDF1 steps with checkpoints
 // ---------------------------------------------------------------------------
@@ -1379,6 +1396,7 @@ static nrd_status adjoint_run(nrd_hierarchy* h, const double* dt, int nsteps, in
     hipStream_t s = h->stream;
     const int64_t NL = h->nl2();
     if (nsteps <= 0 || every <= 0) return fail(NRD_EINVAL, "nsteps and ckpt_every must be > 0");
+    RCHK(ensure_cf_transpose(h));
     const int nck = (nsteps + every - 1) / every;
     if (nck + every + 3 > h->adjoint_slots)
         return fail(NRD_EINVAL, "workspace reserved too few adjoint slots "
@@ -1790,6 +1808,7 @@ nrd_status nrd_precond_apply(nrd_hierarchy* h, const double* w, double* y) {
 nrd_status nrd_vjp(nrd_hierarchy* h, double* u, double* lam, double* JTl, double* gz) {
     NEED_BOUND(h);
     if (!h->step_ready) return fail(NRD_ESTATE, "call nrd_begin_step first");
+    RCHK(ensure_cf_transpose(h));
     hipStream_t s = h->stream;
     h->D.active = nullptr;
     prepare_state(h, u);

@@ -154,8 +154,7 @@ struct Tables {
     std::vector<std::vector<SyncEntry>> sync;        // per level (covered cells)
     std::vector<RefluxFace> rfaces;
     std::vector<RefluxCell> rcells;
-    std::vector<CFRow> cfrows;               // coarse sources of gcf, by cell
-    std::vector<CFSrc> cfsrc;
+    std::vector<int32_t> gcf_prob;           // problem of each gcf entry
 
     // prolongation: per fine patch a shadow block of the coarser level
     std::vector<ShadowPatch> shadow;         // per patch (level >= 1)
@@ -202,6 +201,11 @@ bool patch_planes(const PatchInfo& p, int32_t b, int32_t kc, int32_t run, int32_
 nrd_status cluster_boxes(const nrd_problem* probs, int32_t nprob, const nrd_box* boxes,
                          int32_t nbox, const uint8_t* tags, const nrd_cluster_opt& co,
                          std::vector<nrd_box>& out, std::string& msg);
+
+// CSR of the transposed coarse-fine interpolation (coarse source cell ->
+// the ghosts it feeds, with the tangential weight), at most 4 entries and 4
+// rows per gcf entry.
+void build_cf_transpose(const Tables& t, std::vector<CFRow>& rows, std::vector<CFSrc>& src);
 
 // Builds all tables; returns NRD_OK or an error with msg set.
 nrd_status build_tables(const nrd_problem* probs, int32_t nprob,
