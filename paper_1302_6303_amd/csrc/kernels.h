@@ -22,6 +22,20 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
     return x * base + (x < rem ? x : rem) + q;
 }
 
+// Flux matching runs four lanes per coarse cell, lane q of a quad taking
+// fine face q of each refluxed face.  quad_sum returns, in lane 0 of the
+// quad, (((0 + x_0) + x_1) + x_2) + x_3 of the quad's values: the order of a
+// sequential loop over the four fine faces.  Every lane of the quad must
+// be active.
+template <typename V>
+__device__ __forceinline__ V quad_sum(V x) {
+    const int b = (int)(threadIdx.x & 63) & ~3;
+    const V x1 = __shfl(x, b + 1, 64);
+    const V x2 = __shfl(x, b + 2, 64);
+    const V x3 = __shfl(x, b + 3, 64);
+    return (((V(0) + x) + x1) + x2) + x3;
+}
+
 // Tile of this workgroup in a launch over tiles [t0, t0 + gridDim.x), or,
 // given an index map (the tiles of the problems being solved, in list
 // order), over map[0 .. gridDim.x).

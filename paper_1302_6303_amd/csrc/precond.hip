@@ -486,7 +486,9 @@ __global__ __launch_bounds__(kBlock) void k_comp_reflux(
     const RefluxCell* __restrict__ rc, int n, const RefluxFace* __restrict__ rf,
     const PatchInfo* __restrict__ P, const ProbScalars* __restrict__ ps,
     const PT* __restrict__ D, const PT* __restrict__ u, PT* __restrict__ r, int64_t nl) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    // four lanes per coarse cell (the quad shares the cell's loop bounds)
+    const int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    const int k = threadIdx.x & 3;
     if (t >= n) return;
     const RefluxCell cell = rc[t];
     const double beta = ps[cell.prob].beta;
@@ -494,24 +496,21 @@ __global__ __launch_bounds__(kBlock) void k_comp_reflux(
         const PT* uf = u + fld * nl;
         PT acc = PT(0);
         for (int e = cell.first; e < cell.first + cell.count; ++e) {
-            const RefluxFace fc = rf[e];
-            const int d = fc.face >> 1;
-            const bool hi = fc.face & 1;
-            const PatchInfo& fp = P[fc.fpatch];
+            const int face = rf[e].face;
+            const int d = face >> 1;
+            const bool hi = face & 1;
+            const PatchInfo& fp = P[rf[e].fpatch];
             const PT* Dd = D + (fld * 3 + d) * nl;
             const PT ih = (PT)fp.ih[d];
-            PT sum = PT(0);
-            for (int k = 0; k < 4; ++k) {
-                const int fi = fc.fine[k];
-                const int g = fi + fc.gofs;
-                // fine face: lower cell a, upper cell b; its D sits at b's slot
-                const int a = hi ? g : fi;
-                const int b = hi ? fi : g;
-                sum += Dd[b] * (uf[b] - uf[a]) * ih;
-            }
+            const int fi = rf[e].fine[k];
+            const int g = fi + rf[e].gofs;
+            // fine face: lower cell a, upper cell b; its D sits at b's slot
+            const int a = hi ? g : fi;
+            const int b = hi ? fi : g;
+            const PT sum = quad_sum(Dd[b] * (uf[b] - uf[a]) * ih);
             acc += (hi ? PT(1) : PT(-1)) * PT(0.25) * sum * (PT(0.5) * ih);
         }
-        r[fld * nl + cell.c] += (PT)beta * acc;
+        if (k == 0) r[fld * nl + cell.c] += (PT)beta * acc;
     }
 }
 
@@ -1152,7 +1151,7 @@ void PcArrays<PT>::composite_residual(hipStream_t s, int lev) const {
     k_comp_res<PT><<<nt, kBlock, 0, s>>>(d.active, d.tiles + t0, d.patches, d.ps, d.ctype,
                                          Dface, f, u, r, d.nl);
     if (d.nrcells > 0)
-        k_comp_reflux<PT><<<nblocks(d.nrcells), kBlock, 0, s>>>(
+        k_comp_reflux<PT><<<nblocks(4 * (int64_t)d.nrcells), kBlock, 0, s>>>(
             d.rcells, d.nrcells, d.rfaces, d.patches, d.ps, Dface, u, r, d.nl);
     restrict_(s, r, lev);
 }

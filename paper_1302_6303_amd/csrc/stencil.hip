@@ -707,41 +707,41 @@ __global__ __launch_bounds__(kBlock) void k_reflux(
     const int32_t* __restrict__ active, const double* __restrict__ u,
     const double* __restrict__ v, const double* __restrict__ z3,
     double* __restrict__ out, int64_t nl) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    // four lanes per coarse cell (the quad shares the cell's loop bounds)
+    const int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    const int k = threadIdx.x & 3;
     if (t >= n) return;
     const RefluxCell cell = rc[t];
     if (active && !active[cell.prob]) return;
     const ProbScalars& q = ps[cell.prob];
     double accE = 0.0, accT = 0.0;
     for (int e = cell.first; e < cell.first + cell.count; ++e) {
-        const RefluxFace f = rf[e];
-        const int d = f.face >> 1;
-        const bool hi = f.face & 1;
-        const PatchInfo& fp = P[f.fpatch];
+        const int face = rf[e].face;
+        const int d = face >> 1;
+        const bool hi = face & 1;
+        const PatchInfo& fp = P[rf[e].fpatch];
         const double h = fp.h[d], ih = fp.ih[d];
-        double se = 0.0, st = 0.0;
-        for (int k = 0; k < 4; ++k) {
-            const int fi = f.fine[k];
-            const int g = fi + f.gofs;
-            const int a = hi ? g : fi;        // lower cell of the fine face
-            const int b = hi ? fi : g;
-            double fe, ft;
-            if (MODE == 0)
-                face_flux(u[a], u[b], u[a + nl], u[b + nl], z3[a], z3[b], h, ih, q.kappa,
-                          q.lam, fe, ft);
-            else
-                face_flux_tan(u[a], u[b], u[a + nl], u[b + nl], z3[a], z3[b], v[a], v[b],
-                              v[a + nl], v[b + nl], h, ih, q.kappa, q.lam, fe, ft);
-            se += fe;
-            st += ft;
-        }
+        const int fi = rf[e].fine[k];
+        const int g = fi + rf[e].gofs;
+        const int a = hi ? g : fi;            // lower cell of the fine face
+        const int b = hi ? fi : g;
+        double fe, ft;
+        if (MODE == 0)
+            face_flux(u[a], u[b], u[a + nl], u[b + nl], z3[a], z3[b], h, ih, q.kappa, q.lam,
+                      fe, ft);
+        else
+            face_flux_tan(u[a], u[b], u[a + nl], u[b + nl], z3[a], z3[b], v[a], v[b],
+                          v[a + nl], v[b + nl], h, ih, q.kappa, q.lam, fe, ft);
+        const double se = quad_sum(fe), st = quad_sum(ft);
         const double sgn = hi ? 1.0 : -1.0;
         const double ihc = 0.5 * ih;          // coarse h = 2 fine h
         accE += sgn * 0.25 * se * ihc;
         accT += sgn * 0.25 * st * ihc;
     }
-    out[cell.c] -= q.dt * accE;
-    out[cell.c + nl] -= q.dt * accT;
+    if (k == 0) {
+        out[cell.c] -= q.dt * accE;
+        out[cell.c + nl] -= q.dt * accT;
+    }
 }
 
 static void residual_launch(const Dev& D, hipStream_t s, int t0, int nt, const int32_t* map,
@@ -792,7 +792,7 @@ void residual_all(const Dev& D, hipStream_t s, const double* u, const double* b,
 }
 void residual_reflux(const Dev& D, hipStream_t s, const double* u, double* F) {
     if (D.nrcells == 0) return;
-    k_reflux<0><<<nblocks(D.nrcells), kBlock, 0, s>>>(D.rcells, D.nrcells, D.rfaces,
+    k_reflux<0><<<nblocks(4 * (int64_t)D.nrcells), kBlock, 0, s>>>(D.rcells, D.nrcells, D.rfaces,
                                                       D.patches, D.ps, D.active, u,
                                                       nullptr, D.z3, F, D.nl);
 }
@@ -808,7 +808,7 @@ void jvp_all(const Dev& D, hipStream_t s, const double* u, const double* v, doub
 }
 void jvp_reflux(const Dev& D, hipStream_t s, const double* u, const double* v, double* Jv) {
     if (D.nrcells == 0) return;
-    k_reflux<1><<<nblocks(D.nrcells), kBlock, 0, s>>>(D.rcells, D.nrcells, D.rfaces,
+    k_reflux<1><<<nblocks(4 * (int64_t)D.nrcells), kBlock, 0, s>>>(D.rcells, D.nrcells, D.rfaces,
                                                       D.patches, D.ps, D.active, u, v,
                                                       D.z3, Jv, D.nl);
 }
