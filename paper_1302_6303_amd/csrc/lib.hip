@@ -349,6 +349,51 @@ static hipError_t up(hipStream_t s, void* dst, const std::vector<T>& v) {
     return hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s);
 }
 
+// Colour-split storage of the level-0 V-cycle vectors (split0): problems
+// of one level and one level-0 box, even x extents, a multigrid base.  The
+// index map is checked here for every box shape: a bijection of the ghosted
+// block onto itself, and each interior cell's stencil indices those of its
+// neighbours' positions.
+static bool split0_ok(const Tables& t, bool base_smooth) {
+    if (base_smooth || t.nlev != 1 || t.level_sib0[1] != t.level_sib0[0]) return false;
+    std::map<std::tuple<int, int, int, int, int, int>, bool> shapes;
+    for (const PatchInfo& p : t.patches) {
+        if ((p.n[0] & 1) || (p.sy & 1) || p.sy != p.n[0] + 2) return false;
+        shapes[std::make_tuple(p.n[0], p.n[1], p.n[2], p.sy, p.sz,
+                               (p.lo[0] + p.lo[1] + p.lo[2]) & 1)] = true;
+    }
+    for (const auto& kv : shapes) {
+        PatchInfo q;
+        std::memset(&q, 0, sizeof(q));
+        std::tie(q.n[0], q.n[1], q.n[2], q.sy, q.sz, q.lo[0]) = kv.first;
+        const int64_t vol = (int64_t)q.sz * (q.n[2] + 2);
+        std::vector<char> seen(vol, 0);
+        for (int z = 0; z < q.n[2] + 2; ++z)
+            for (int y = 0; y < q.n[1] + 2; ++y)
+                for (int x = 0; x < q.sy; ++x) {
+                    const int i = split_index(q, x, y, z);
+                    if (i < 0 || i >= vol || seen[i]) return false;
+                    seen[i] = 1;
+                }
+        for (int k = 0; k < q.n[2]; ++k)
+            for (int j = 0; j < q.n[1]; ++j)
+                for (int i = 0; i < q.n[0]; ++i) {
+                    const int id[3] = {i, j, k};
+                    int own, nb[6];
+                    split_stencil(q, id, own, nb);
+                    const int x = i + 1, y = j + 1, z = k + 1;
+                    if (own != split_index(q, x, y, z) || nb[0] != split_index(q, x - 1, y, z) ||
+                        nb[1] != split_index(q, x + 1, y, z) ||
+                        nb[2] != split_index(q, x, y - 1, z) ||
+                        nb[3] != split_index(q, x, y + 1, z) ||
+                        nb[4] != split_index(q, x, y, z - 1) ||
+                        nb[5] != split_index(q, x, y, z + 1))
+                        return false;
+                }
+    }
+    return true;
+}
+
 template <typename PT>
 static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
     auto& o = h->o;
@@ -399,6 +444,7 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
     pc.fac_post = h->opt.fac_nu_post;
     pc.fac_smoother = h->opt.fac_smoother;
     pc.base_smooth = h->opt.fac_base == NRD_BASE_SMOOTH;
+    pc.split0 = split0_ok(t, pc.base_smooth);
     pc.fac_cycle = h->opt.fac_cycle;
     pc.clock = h;
 }

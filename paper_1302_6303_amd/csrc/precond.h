@@ -7,6 +7,43 @@ namespace nrd {
 
 constexpr int kMaxMG = 12;
 
+// Colour-split storage of the level-0 iterate e and right-hand side f of
+// the multigrid V-cycle (hierarchies whose problems have one level and one
+// level-0 box, each of even x extent; `split0`).  Within the ghosted block of
+// (n0 + 2)(n1 + 2)(n2 + 2) values of a box, the positions of colour 0 come
+// first and those of colour 1 after them, each half in native order with
+// rows of (n0 + 2) / 2 values.  The colour of ghosted position (x, y, z) is
+// the parity of x + y + z + lo_0 + lo_1 + lo_2 + 1: for interior cell
+// (x - 1, y - 1, z - 1) its red-black colour.  A half-sweep then reads only
+// its own colour's f and the other colour's e, and writes whole lines of e.
+__host__ __device__ inline int split_colour(const PatchInfo& p, int x, int y, int z) {
+    return (x + y + z + p.lo[0] + p.lo[1] + p.lo[2] + 1) & 1;
+}
+__host__ __device__ inline int split_index(const PatchInfo& p, int x, int y, int z) {
+    const int half = (p.sz >> 1) * (p.n[2] + 2);
+    return p.off + split_colour(p, x, y, z) * half + (x >> 1) + (p.sy >> 1) * y +
+           (p.sz >> 1) * z;
+}
+// Interior cell id of a box: its own split index and those of its six face
+// neighbours (x-, x+, y-, y+, z-, z+; all of the other colour, so they share
+// the other half's base and the neighbour's x >> 1, y and z).
+__host__ __device__ inline void split_stencil(const PatchInfo& p, const int id[3], int& own,
+                                              int nb[6]) {
+    const int x = id[0] + 1, y = id[1] + 1, z = id[2] + 1;
+    const int col = split_colour(p, x, y, z);
+    const int half = (p.sz >> 1) * (p.n[2] + 2);
+    const int R = p.sy >> 1, RZ = p.sz >> 1;
+    const int row = R * y + RZ * z;
+    own = p.off + col * half + (x >> 1) + row;
+    const int ob = p.off + (1 - col) * half + row;
+    nb[0] = ob + ((x - 1) >> 1);
+    nb[1] = ob + ((x + 1) >> 1);
+    nb[2] = ob + (x >> 1) - R;
+    nb[3] = ob + (x >> 1) + R;
+    nb[4] = ob + (x >> 1) - RZ;
+    nb[5] = ob + (x >> 1) + RZ;
+}
+
 // Damping of the point Jacobi level smoother: 2d / (2d + 1) for d = 3, the
 // weight that damps the upper half of the 7-point Laplacian's spectrum best.
 constexpr double kJacobiOmega = 6.0 / 7.0;
@@ -86,6 +123,7 @@ struct PcArrays {
     const Tile* ltiles = nullptr;    // x-line tiles (block Gauss-Seidel), by level
     int32_t level_line0[kMaxLev + 1] = {};
     bool base_smooth = false;        // base level: level sweeps instead of multigrid
+    bool split0 = false;             // level-0 e and f in colour-split storage
     int fac_cycle = 0;               // NRD_FAC_MULT (Alg. 1) or NRD_FAC_AFACX
     PT* e2 = nullptr;                // 2 * nl: damped Jacobi with several sweeps,
                                      // line smoother, AFACx coarse approximations

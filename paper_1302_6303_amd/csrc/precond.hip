@@ -150,11 +150,14 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarsen(const int32_t* __restrict
 // unconditionally (ghost slots always hold finite values).
 // Diagonal dg and neighbour sum ns of both fields at cell c = id (ZERO: the
 // iterate is taken as zero, ns = 0).
-template <typename PT, bool ZERO>
+// SPLIT: e in colour-split storage, its neighbours at enb (c indexes the
+// face coefficients and cell types, which stay native).
+template <typename PT, bool ZERO, bool SPLIT = false>
 __device__ __forceinline__ void level_terms(const PatchInfo& p, const int id[3], int c,
                                             double beta, const uint8_t* __restrict__ ctype,
                                             const PT* __restrict__ D, const PT* __restrict__ e,
-                                            int64_t nl, PT dgo[2], PT nso[2]) {
+                                            int64_t nl, PT dgo[2], PT nso[2],
+                                            const int* enb = nullptr) {
     const int st[3] = {1, p.sy, p.sz};
     PT bh2[3];
     bool ph[6], cf[6];
@@ -183,10 +186,11 @@ __device__ __forceinline__ void level_terms(const PatchInfo& p, const int id[3],
             for (int s = 0; s < 2; ++s) {
                 const int fc = 2 * d + s;
                 const PT a = bh2[d] * Dd[s ? c + st[d] : c];
-                const PT enb = ZERO ? PT(0) : ef[s ? c + st[d] : c - st[d]];
+                const PT en = ZERO ? PT(0)
+                                   : ef[SPLIT ? enb[fc] : (s ? c + st[d] : c - st[d])];
                 const bool open = !(ph[fc] || cf[fc]);
                 dg += open ? a : (cf[fc] ? PT(2.0 / 3.0) * a : PT(0));
-                ns += open ? a * enb : PT(0);
+                ns += open ? a * en : PT(0);
             }
         }
         if (fld == 0 && any_robin) {
@@ -207,18 +211,21 @@ __device__ __forceinline__ void level_terms(const PatchInfo& p, const int id[3],
     }
 }
 
-template <typename PT, int MODE>   // MODE 0: RBGS colour (zero start) 1: colour
+// SPLIT: e and f in colour-split storage
+template <typename PT, int MODE, bool SPLIT>   // MODE 0: RBGS colour (zero start) 1: colour
 __device__ __forceinline__ void level_update(const PatchInfo& p, const int id[3], double beta,
                                              const uint8_t* __restrict__ ctype,
                                              const PT* __restrict__ D,
                                              const PT* __restrict__ f, PT* __restrict__ e,
                                              int64_t nl) {
     const int c = nat(p, id[0], id[1], id[2]);
+    int own = c, enb[6];
+    if (SPLIT) split_stencil(p, id, own, enb);
     PT dg[2], ns[2];
-    level_terms<PT, MODE == 0>(p, id, c, beta, ctype, D, e, nl, dg, ns);
+    level_terms<PT, MODE == 0, SPLIT>(p, id, c, beta, ctype, D, e, nl, dg, ns, enb);
 #pragma unroll
     for (int fld = 0; fld < 2; ++fld) {
-        const int64_t cfi = fld * nl + c;
+        const int64_t cfi = fld * nl + own;
         e[cfi] = (f[cfi] + ns[fld]) / dg[fld];
     }
 }
@@ -345,11 +352,12 @@ __global__ __launch_bounds__(kBlock) void k_line(const int32_t* __restrict__ act
 // One cell of a red-black half-sweep; REGION: only covered cells relax,
 // any other cell is set to 0 (the coarse approximation of AFACx lives on
 // the region a finer level covers and vanishes outside it).
-template <typename PT, int MODE, bool REGION>
+template <typename PT, int MODE, bool REGION, bool SPLIT>
 __device__ __forceinline__ void level_cell(const PatchInfo& p, const int id[3], double beta,
                                            const uint8_t* __restrict__ ctype,
                                            const PT* __restrict__ D, const PT* __restrict__ f,
                                            PT* __restrict__ e, int64_t nl) {
+    static_assert(!(REGION && SPLIT), "region sweeps run on native storage");
     if (REGION) {
         const int c = nat(p, id[0], id[1], id[2]);
         if (!(ctype[c] & CT_COVERED)) {
@@ -358,7 +366,7 @@ __device__ __forceinline__ void level_cell(const PatchInfo& p, const int id[3], 
             return;
         }
     }
-    level_update<PT, MODE>(p, id, beta, ctype, D, f, e, nl);
+    level_update<PT, MODE, SPLIT>(p, id, beta, ctype, D, f, e, nl);
 }
 
 // One colour of a red-black sweep (MODE 0: from e = 0), kBlock / 2 threads
@@ -366,8 +374,8 @@ __device__ __forceinline__ void level_cell(const PatchInfo& p, const int id[3], 
 // even, rows start at even linear indices, so every pair (2q, 2q + 1) of a
 // tile lies in one row and holds exactly one cell of each colour: thread q
 // updates that cell and every lane does useful work.  Otherwise each thread
-// tests two cells.
-template <typename PT, int MODE, bool REGION = false>
+// tests two cells.  SPLIT: e and f in colour-split storage (even x extents).
+template <typename PT, int MODE, bool REGION = false, bool SPLIT = false>
 __global__ __launch_bounds__(kBlock) void k_level(const int32_t* __restrict__ act, 
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
@@ -384,12 +392,12 @@ __global__ __launch_bounds__(kBlock) void k_level(const int32_t* __restrict__ ac
         if (a >= t.count) return;
         coords(p, t.start + a, id[0], id[1], id[2]);  // id[0] even
         id[0] += (colour + id[1] + id[2] + lo) & 1;
-        level_cell<PT, MODE, REGION>(p, id, beta, ctype, D, f, e, nl);
-    } else {
+        level_cell<PT, MODE, REGION, SPLIT>(p, id, beta, ctype, D, f, e, nl);
+    } else if (!SPLIT) {
         for (int q = threadIdx.x; q < t.count; q += kBlock / 2) {
             coords(p, t.start + q, id[0], id[1], id[2]);
             if (((id[0] + id[1] + id[2] + lo) & 1) != colour) continue;
-            level_cell<PT, MODE, REGION>(p, id, beta, ctype, D, f, e, nl);
+            level_cell<PT, MODE, REGION, false>(p, id, beta, ctype, D, f, e, nl);
         }
     }
 }
@@ -610,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_add_level(const int32_t* __restrict_
 // child each, summed across the lanes in a fixed order.
 // fmap: as in k_mg_coarsen.  The children of a coarse cell start at an even
 // level index, so its colour-0 children are those with an even offset sum.
-template <typename PT>
+template <typename PT, bool SPLIT = false>   // SPLIT: fine grid's e, f colour-split
 __global__ __launch_bounds__(kBlock) void k_mg_res_restrict(const int32_t* __restrict__ act,
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pc,
     const PatchInfo* __restrict__ Pf, const int32_t* __restrict__ fbox,
@@ -637,10 +645,12 @@ __global__ __launch_bounds__(kBlock) void k_mg_res_restrict(const int32_t* __res
                                 2 * id[1] + ((child >> 1) & 1) - pf.lo[1],
                                 2 * id[2] + (child >> 2) - pf.lo[2]};
             const int c = nat(pf, fid[0], fid[1], fid[2]);
+            int own = c, enb[6];
+            if (SPLIT) split_stencil(pf, fid, own, enb);
             PT dg[2], ns[2];
-            level_terms<PT, false>(pf, fid, c, beta, ctype, D, e, nlf, dg, ns);
-            v0 = f[c] - (dg[0] * e[c] - ns[0]);
-            v1 = f[nlf + c] - (dg[1] * e[nlf + c] - ns[1]);
+            level_terms<PT, false, SPLIT>(pf, fid, c, beta, ctype, D, e, nlf, dg, ns, enb);
+            v0 = f[own] - (dg[0] * e[own] - ns[0]);
+            v1 = f[nlf + own] - (dg[1] * e[nlf + own] - ns[1]);
         }
         v0 += __shfl_xor(v0, 1);
         v1 += __shfl_xor(v1, 1);
@@ -658,7 +668,8 @@ template <typename PT>
 __global__ __launch_bounds__(kBlock) void k_mg_prolong(const int32_t* __restrict__ act, 
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pf,
     const PatchInfo* __restrict__ Pc, const int32_t* __restrict__ cbox,
-    const PT* __restrict__ ec, int64_t nlc, PT* __restrict__ ef, int64_t nlf) {
+    const PT* __restrict__ ec, int64_t nlc, PT* __restrict__ ef, int64_t nlf, int split) {
+    // split: ef in colour-split storage
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
@@ -666,7 +677,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(const int32_t* __restrict
     const PatchInfo& pc = Pc[cbox[t.prob]];
     int id[3];
     coords(pf, t.start + threadIdx.x, id[0], id[1], id[2]);
-    const int c = nat(pf, id[0], id[1], id[2]);
+    const int c = split ? split_index(pf, id[0] + 1, id[1] + 1, id[2] + 1)
+                        : nat(pf, id[0], id[1], id[2]);
     int q[3], nbq[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -858,7 +870,8 @@ __global__ __launch_bounds__(kBlock) void k_bottom_apply(const int32_t* __restri
     const int32_t* __restrict__ probs, const int32_t* __restrict__ boxes,
     const PatchInfo* __restrict__ P, const int64_t* __restrict__ boff,
     const double* __restrict__ X, const PT* __restrict__ f, PT* __restrict__ e,
-    int64_t nl) {
+    int64_t nl, int split) {
+    // split: e and f in colour-split storage
     __shared__ double fv[kBottomMax];
     const int pi = blockIdx.x >> 1;
     const int fld = blockIdx.x & 1;
@@ -871,7 +884,9 @@ __global__ __launch_bounds__(kBlock) void k_bottom_apply(const int32_t* __restri
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         int id[3];
         bottom_coords(p, o, j, id);
-        fv[j] = (double)f[fld * nl + nat(p, id[0], id[1], id[2])];
+        const int c = split ? split_index(p, id[0] + 1, id[1] + 1, id[2] + 1)
+                            : nat(p, id[0], id[1], id[2]);
+        fv[j] = (double)f[fld * nl + c];
     }
     __syncthreads();
     // X is symmetric: row i = column i, read with consecutive threads on
@@ -881,7 +896,9 @@ __global__ __launch_bounds__(kBlock) void k_bottom_apply(const int32_t* __restri
         for (int jj = 0; jj < N; ++jj) acc += Xi[(int64_t)jj * N + row] * fv[jj];
         int id[3];
         bottom_coords(p, o, row, id);
-        e[fld * nl + nat(p, id[0], id[1], id[2])] = (PT)acc;
+        const int c = split ? split_index(p, id[0] + 1, id[1] + 1, id[2] + 1)
+                            : nat(p, id[0], id[1], id[2]);
+        e[fld * nl + c] = (PT)acc;
     }
 }
 
@@ -897,7 +914,8 @@ __global__ __launch_bounds__(kBlock) void k_p2(const int32_t* __restrict__ act, 
                                                const double* __restrict__ z3,
                                                const PT* __restrict__ e,
                                                double* __restrict__ y, int mode,
-                                               int transpose, int64_t nl) {
+                                               int transpose, int64_t nl, int split) {
+    // split: e in colour-split storage
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
@@ -912,7 +930,8 @@ __global__ __launch_bounds__(kBlock) void k_p2(const int32_t* __restrict__ act, 
     // [[1 + sigma beta, -k beta z^3], [-sigma beta, 1 + k beta z^3]]  (sigma T^3 = z^3)
     const double a = 1.0 + sg * beta, b = -k * beta * z, cc = -sg * beta, d = 1.0 + k * beta * z;
     const double det = a * d - b * cc;
-    const double eE = (double)e[c], eT = (double)e[c + nl];
+    const int ce = split ? split_index(p, id[0] + 1, id[1] + 1, id[2] + 1) : c;
+    const double eE = (double)e[ce], eT = (double)e[ce + nl];
     if (!transpose) {
         y[c] = (d * eE - b * eT) / det;
         y[c + nl] = (a * eT - cc * eE) / det;
@@ -930,7 +949,9 @@ __global__ __launch_bounds__(kBlock) void k_p2t_in(const int32_t* __restrict__ a
                                                    const PT* __restrict__ sigma,
                                                    const double* __restrict__ z3,
                                                    const double* __restrict__ w,
-                                                   PT* __restrict__ x, int mode, int64_t nl) {
+                                                   PT* __restrict__ x, int mode, int64_t nl,
+                                                   int split) {
+    // split: x in colour-split storage
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
@@ -945,8 +966,9 @@ __global__ __launch_bounds__(kBlock) void k_p2t_in(const int32_t* __restrict__ a
     const double a = 1.0 + sg * beta, b = -k * beta * z, cc = -sg * beta, d = 1.0 + k * beta * z;
     const double det = a * d - b * cc;
     const double eE = w[c], eT = w[c + nl];
-    x[c] = (PT)((d * eE - cc * eT) / det);
-    x[c + nl] = (PT)((a * eT - b * eE) / det);
+    const int cx = split ? split_index(p, id[0] + 1, id[1] + 1, id[2] + 1) : c;
+    x[cx] = (PT)((d * eE - cc * eT) / det);
+    x[cx + nl] = (PT)((a * eT - b * eE) / det);
 }
 
 template <typename PT>
@@ -955,7 +977,8 @@ __global__ __launch_bounds__(kBlock) void k_in(const int32_t* __restrict__ act, 
                                                const PatchInfo* __restrict__ P,
                                                const double* __restrict__ w,
                                                const double* __restrict__ wsc,
-                                               PT* __restrict__ x, int64_t nl) {
+                                               PT* __restrict__ x, int64_t nl, int split) {
+    // split: x in colour-split storage
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
@@ -964,15 +987,18 @@ __global__ __launch_bounds__(kBlock) void k_in(const int32_t* __restrict__ act, 
     int id[3];
     coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
     const int c = nat(p, id[0], id[1], id[2]);
-    x[c] = (PT)(sc * w[c]);
-    x[c + nl] = (PT)(sc * w[c + nl]);
+    const int cx = split ? split_index(p, id[0] + 1, id[1] + 1, id[2] + 1) : c;
+    x[cx] = (PT)(sc * w[c]);
+    x[cx + nl] = (PT)(sc * w[c + nl]);
 }
 
 template <typename PT>
 __global__ __launch_bounds__(kBlock) void k_out(const int32_t* __restrict__ act, const Tile* __restrict__ tiles,
                                                 const PatchInfo* __restrict__ P,
                                                 const PT* __restrict__ x,
-                                                double* __restrict__ y, int64_t nl) {
+                                                double* __restrict__ y, int64_t nl,
+                                                int split) {
+    // split: x in colour-split storage
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
@@ -980,8 +1006,9 @@ __global__ __launch_bounds__(kBlock) void k_out(const int32_t* __restrict__ act,
     int id[3];
     coords(p, t.start + threadIdx.x, id[0], id[1], id[2]);
     const int c = nat(p, id[0], id[1], id[2]);
-    y[c] = (double)x[c];
-    y[c + nl] = (double)x[c + nl];
+    const int cx = split ? split_index(p, id[0] + 1, id[1] + 1, id[2] + 1) : c;
+    y[c] = (double)x[cx];
+    y[c + nl] = (double)x[cx + nl];
 }
 
 template <typename PT>
@@ -1049,17 +1076,37 @@ void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
 
 template <typename PT>
 void PcArrays<PT>::vcycle(hipStream_t s) const {
-    // grid 0 = the level-0 patches: rhs in f (native), result in e
+    // grid 0 = the level-0 patches: rhs in f, result in e (colour-split
+    // storage when split0, native otherwise)
     const Dev& d = *D;
+    // one colour of a red-black sweep of grid g (zero: from e = 0)
+    auto half_sweep = [&](int g, const PatchInfo* Pg, const PT* Dg, const PT* fg, PT* eg,
+                          int64_t nlg, bool zero, int colour) {
+        const Tile* tl = mg.smooth_tiles[g];
+        const int nt = mg.nsmooth[g];
+        if (g == 0 && split0) {
+            if (zero)
+                k_level<PT, 0, false, true><<<nt, kBlock / 2, 0, s>>>(
+                    d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, colour, nlg);
+            else
+                k_level<PT, 1, false, true><<<nt, kBlock / 2, 0, s>>>(
+                    d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, colour, nlg);
+        } else if (zero) {
+            k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
+                                                     colour, nlg);
+        } else {
+            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
+                                                     colour, nlg);
+        }
+    };
     for (int g = 0; g <= mg.G; ++g) {
         const PatchInfo* Pg = (g == 0) ? d.patches : mg.box[g];
         const int64_t nlg = (g == 0) ? d.nl : mg.len[g];
         PT* eg = (g == 0) ? e : mg.eg[g];
         PT* fg = (g == 0) ? f : mg.fg[g];
         const PT* Dg = (g == 0) ? Dface : mg.Dg[g];
+        const bool sp = g == 0 && split0;
         if (mg.nsmooth[g] > 0) {
-            const Tile* tl = mg.smooth_tiles[g];
-            const int nt = mg.nsmooth[g];
             // a base grid cut into several boxes: sibling ghosts refreshed
             // after every half-sweep that the next one reads
             const bool sib = g == 0 && mg.multi0;
@@ -1068,26 +1115,26 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
                 std::pair<hipEvent_t, hipEvent_t> tk{nullptr, nullptr};
                 if (g == 0 && clock) tk = clock->tic(which);
                 if (sib && it > 0) siblings(s, eg, 0);
-                if (it == 0)
-                    k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
-                                                        0, nlg);
-                else
-                    k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
-                                                        0, nlg);
+                half_sweep(g, Pg, Dg, fg, eg, nlg, it == 0, 0);
                 if (sib) siblings(s, eg, 0);
-                k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
-                                                    1, nlg);
+                half_sweep(g, Pg, Dg, fg, eg, nlg, false, 1);
                 if (g == 0 && clock) clock->toc(which, tk);
             }
             if (sib) siblings(s, eg, 0);
-            k_mg_res_restrict<PT><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active,
-                mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g], g == 0 ? mg.l0map : nullptr,
-                d.ps, d.ctype, Dg, fg, eg, nlg, mg.fg[g + 1], mg.len[g + 1]);
+            if (sp)
+                k_mg_res_restrict<PT, true><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active,
+                    mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g], mg.l0map, d.ps, d.ctype,
+                    Dg, fg, eg, nlg, mg.fg[g + 1], mg.len[g + 1]);
+            else
+                k_mg_res_restrict<PT><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active,
+                    mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g],
+                    g == 0 ? mg.l0map : nullptr, d.ps, d.ctype, Dg, fg, eg, nlg, mg.fg[g + 1],
+                    mg.len[g + 1]);
         }
         if (mg.nbottom[g] > 0)
             k_bottom_apply<PT><<<2 * mg.nbottom[g], kBlock, 0, s>>>(d.active, 
                 mg.bottom_probs[g], mg.bottom_boxes[g], Pg, mg.bottom_off, mg.Xbuf, fg, eg,
-                nlg);
+                nlg, sp ? 1 : 0);
     }
     for (int g = mg.G - 1; g >= 0; --g) {
         if (mg.nsmooth[g] == 0) continue;
@@ -1099,17 +1146,16 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
         const Tile* tl = mg.smooth_tiles[g];
         const int nt = mg.nsmooth[g];
         k_mg_prolong<PT><<<nt, kBlock, 0, s>>>(d.active, tl, Pg, mg.box[g + 1], mg.box_of[g + 1],
-                                              mg.eg[g + 1], mg.len[g + 1], eg, nlg);
+                                              mg.eg[g + 1], mg.len[g + 1], eg, nlg,
+                                              (g == 0 && split0) ? 1 : 0);
         const bool sib = g == 0 && mg.multi0;
         for (int it = 0; it < nu_post; ++it) {
             std::pair<hipEvent_t, hipEvent_t> tk{nullptr, nullptr};
             if (g == 0 && clock) tk = clock->tic(NRD_TIMER_SMOOTH);
             if (sib) siblings(s, eg, 0);
-            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, 0,
-                                                nlg);
+            half_sweep(g, Pg, Dg, fg, eg, nlg, false, 0);
             if (sib) siblings(s, eg, 0);
-            k_level<PT, 1><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, 1,
-                                                nlg);
+            half_sweep(g, Pg, Dg, fg, eg, nlg, false, 1);
             if (g == 0 && clock) clock->toc(NRD_TIMER_SMOOTH, tk);
         }
     }
@@ -1353,20 +1399,23 @@ template <typename PT>
 void PcArrays<PT>::apply(hipStream_t s, const double* w, double* y, const double* wsc) const {
     const Dev& d = *D;
     const int ntiles = d.level_tile0[d.nlev];
-    k_in<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, w, wsc, f, d.nl);
+    // with split0 the cycle reads f and returns e in colour-split storage
+    const int sp = split0 ? 1 : 0;
+    k_in<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, w, wsc, f, d.nl, sp);
     const PT* x = p1(s);
-    k_p2<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, sigma, d.z3, x, y, p2_mode, 0,
-                                       d.nl);
+    k_p2<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, sigma, d.z3, x, y,
+                                       p2_mode, 0, d.nl, sp);
 }
 
 template <typename PT>
 void PcArrays<PT>::apply_transpose(hipStream_t s, const double* w, double* y) const {
     const Dev& d = *D;
     const int ntiles = d.level_tile0[d.nlev];
+    const int sp = split0 ? 1 : 0;
     k_p2t_in<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, sigma, d.z3, w, f,
-                                           p2_mode, d.nl);
+                                           p2_mode, d.nl, sp);
     const PT* x = p1(s);
-    k_out<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, x, y, d.nl);
+    k_out<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, x, y, d.nl, sp);
 }
 
 template struct PcArrays<float>;

@@ -51,6 +51,24 @@ def odd_workload():
     return I.Workload("odd573", [prob], [box], z, E, T, np.array([1e-3]))
 
 
+def tiny_workload():
+    """Three small uniform problems: 4^3 and 6 x 4 x 2 are their own coarsest
+    multigrid grids (bottom solve on the level-0 box), 12 x 8 x 6 coarsens
+    once; all x extents even."""
+    rng = np.random.default_rng(19)
+    sizes = [(4, 4, 4), (6, 4, 2), (12, 8, 6)]
+    problems, boxes = [], []
+    for p, n in enumerate(sizes):
+        problems.append(I.Problem(base_n=n))
+        boxes.append(I.Box(p, 0, (0, 0, 0), n))
+    z = []
+    for prob, b in zip(problems, boxes):
+        zf = I.box_field(I.sample_material_boxes(rng, 2))
+        z.append(zf(*I.cell_centres(prob, b)))
+    E, T = I.front_state(problems, boxes, rng)
+    return I.Workload("tiny3", problems, boxes, z, E, T, np.array([1e-3, 2e-3, 1e-3]))
+
+
 def workloads():
     return {
         "odd573": odd_workload,
@@ -380,12 +398,14 @@ def test_precond_parity_fac_base_smoothing(name, nu):
         assert rel_err(got[sl][mm], ref[sl][mm]) < 1e-10
 
 
-def test_precond_parity_noncubic():
-    """Preconditioner of three non-cubic problems in one hierarchy (their
-    coarsest grids are 2, 3 and 4 grids down; Marshak faces on two sides of
-    the first), each problem against its own oracle."""
+@pytest.mark.parametrize("wl", [boxes_workload, tiny_workload])
+def test_precond_parity_noncubic(wl):
+    """Preconditioner of three non-cubic problems in one hierarchy, each
+    problem against its own oracle: coarsest grids 2, 3 and 4 grids down
+    (Marshak faces on two sides of the first), or two problems that are
+    their own coarsest grid beside one that coarsens once."""
     from tests.gpu_helpers import problem_slices
-    w = boxes_workload()
+    w = wl()
     H = make(w)
     dts = [float(x) for x in w.dt]
     H.begin_step(dts)
