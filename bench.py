@@ -70,10 +70,10 @@ HBM_PEAK_GBS = 8000.0
 # the factor a plain 2 GiB copy reads in the same run, WRITE by its own
 # factor; the 20 full launches timed after the steps), valid for the stencil
 # source with this SHA-256 prefix; null otherwise.
-MEASURED_TRAFFIC = {"workload": "ensemble", "stencil_sha256": "14268eb99b528677",
-                    "bytes_per_cell": 62.4151,
-                    "fetch_bytes_per_cell": 45.8215,
-                    "write_bytes_per_cell": 16.5936,
+MEASURED_TRAFFIC = {"workload": "ensemble", "stencil_sha256": "c9ec114e166c8b40",
+                    "bytes_per_cell": 62.4317,
+                    "fetch_bytes_per_cell": 45.8374,
+                    "write_bytes_per_cell": 16.5944,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -1133,7 +1133,8 @@ def main():
                          "frac": round(BYTES_PER_CELL_JVP * ncomp / jvp_s / 1e9 / HBM_PEAK_GBS, 4),
                          "avg_launch_ms": round(mixed["jvp_ms_avg"], 4)},
         "smoother_roofline": {
-            "kernel": "k_level<float> (red-black sweep of the base grid, one launch per colour)",
+            "kernel": "k_level<float> (red-black sweep of the base grid, one launch per colour, "
+                      "colour-split iterate and right-hand side)",
             "cells": base_cells, "bytes_per_cell": BYTES_PER_CELL_SWEEP,
             "achieved": gbs(BYTES_PER_CELL_SWEEP * base_cells, mixed["sweep_ms_avg"]),
             "unit": "GB/s",
