@@ -48,24 +48,6 @@ __host__ __device__ inline void split_stencil(const PatchInfo& p, const int id[3
 // weight that damps the upper half of the 7-point Laplacian's spectrum best.
 constexpr double kJacobiOmega = 6.0 / 7.0;
 
-struct MGDev {
-    int G = 0;                                   // deepest grid index
-    const PatchInfo* box[kMaxMG] = {};           // grid g >= 1 box tables
-    int64_t len[kMaxMG] = {};                    // ghosted cells per field
-    const Tile* tiles[kMaxMG] = {};              // all boxes of grid g >= 1
-    int ntiles[kMaxMG] = {};
-    const int32_t* box_of[kMaxMG] = {};          // [nprob]: box of problem in
-                                                 // grid g (g = 0: patch id)
-    const Tile* smooth_tiles[kMaxMG] = {};       // grid g boxes of problems
-    int nsmooth[kMaxMG] = {};                    // deeper than g
-    const int32_t* bottom_probs[kMaxMG] = {};    // problems whose coarsest
-    const int32_t* bottom_boxes[kMaxMG] = {};    // grid is g
-    int nbottom[kMaxMG] = {};
-    const int64_t* bottom_off = nullptr;         // [nprob] in cells^2 units
-    double* Lbuf = nullptr;
-    double* Xbuf = nullptr;
-};
-
 // Per multigrid grid: box table, face coefficients, field length (kernel
 // argument of the merged bottom-solve setup).
 template <typename PT>
