@@ -177,6 +177,14 @@ void err_norm(const Dev& D, hipStream_t s, const double* x, const double* xp,
 // y = a_p x + b_p y elementwise (a, b per problem, host-computed device arrays)
 void axpby(const Dev& D, hipStream_t s, const double* a, const double* x,
            const double* b, double* y);
+// y = a_p x + b_p w elementwise in one pass (a, b per problem)
+void lincomb2(const Dev& D, hipStream_t s, const double* a, const double* x, const double* b,
+              const double* w, double* y);
+// The leapfrog predictor of a BDF2 step in one pass, coefficients c = (A, B,
+// C) per problem: y = u + A udot + B u_prev + C u; pred (may be NULL) gets
+// a copy of y
+void bdf2_predict(const Dev& D, hipStream_t s, const double* c, const double* u,
+                  const double* udot, const double* uprev, double* y, double* pred);
 // y = x * scale_p (scale device [nprob])
 void scale_copy(const Dev& D, hipStream_t s, const double* x, const double* sc,
                 double* y);

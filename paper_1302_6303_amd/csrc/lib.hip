@@ -876,11 +876,7 @@ static nrd_status begin_step(nrd_hierarchy* h, const double* dt, bool bdf1_only 
     }
     HIPCHK(up(s, h->coefA, coef));
     h->D.active = nullptr;
-    scale_copy(h->D, s, h->cur, h->coefA, h->bvec);
-    // bvec += b_p * prev  (axpby with y = bvec, a = b_p, b = 1)
-    std::vector<double> ones(np, 1.0);
-    HIPCHK(up(s, h->coefB, ones));
-    axpby(h->D, s, h->coefA + np, h->prev, h->coefB, h->bvec);
+    lincomb2(h->D, s, h->coefA, h->cur, h->coefA + np, h->prev, h->bvec);
     HIPCHK(hipStreamSynchronize(s));
     h->step_ready = true;
     return NRD_OK;
@@ -1321,7 +1317,7 @@ static nrd_status implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_sta
     for (int p = 0; p < np; ++p) any2 |= h->alpha[p] > 0.0;
     if (any2) {
         // x = (1 - a^2) u_n + (1 + a) dt u'_n + a^2 u_{n-1}
-        std::vector<double> A(np), B(np), C(np), one(np, 1.0);
+        std::vector<double> A(np), B(np), C(np);
         for (int p = 0; p < np; ++p) {
             const double a = h->alpha[p];
             const bool bdf2 = a > 0.0;
@@ -1329,19 +1325,17 @@ static nrd_status implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_sta
             B[p] = bdf2 ? a * a : 0.0;
             C[p] = bdf2 ? -a * a : 0.0;
         }
-        std::vector<double> buf(4 * np);
+        std::vector<double> buf(3 * np);
         for (int p = 0; p < np; ++p) {
             buf[p] = A[p];
             buf[np + p] = B[p];
             buf[2 * np + p] = C[p];
-            buf[3 * np + p] = 1.0;
         }
         HIPCHK(up(s, h->coefA, buf));
-        copy_interior(h->D, s, h->cur, h->tmp);
-        axpby(h->D, s, h->coefA, h->udot, h->coefA + 3 * np, h->tmp);        // + A udot
-        axpby(h->D, s, h->coefA + np, h->prev, h->coefA + 3 * np, h->tmp);   // + a^2 u_{n-1}
-        axpby(h->D, s, h->coefA + 2 * np, h->cur, h->coefA + 3 * np, h->tmp); // - a^2 u_n
-        if (h->opt.error_estimate) copy_interior(h->D, s, h->tmp, h->pred);
+        // tmp = u_n + A udot + a^2 u_{n-1} - a^2 u_n (and its copy for the
+        // error estimate)
+        bdf2_predict(h->D, s, h->coefA, h->cur, h->udot, h->prev, h->tmp,
+                     h->opt.error_estimate ? h->pred : nullptr);
         // accept per problem if positive
         std::vector<double> zero(np, 0.0), mn(np);
         HIPCHK(up(s, h->coefB, zero));
@@ -1398,11 +1392,7 @@ static nrd_status implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_sta
         buf[np + p] = -1.0 / dt[p];
     }
     HIPCHK(up(s, h->coefA, buf));
-    scale_copy(h->D, s, h->x, h->coefA, h->udot);
-    std::vector<double> one(np, 1.0);
-    HIPCHK(up(s, h->coefB, one));
-    // udot = -b/dt + udot
-    axpby(h->D, s, h->coefA + np, h->bvec, h->coefB, h->udot);
+    lincomb2(h->D, s, h->coefA, h->x, h->coefA + np, h->bvec, h->udot);
     std::swap(h->prev, h->cur);       // prev <- u_n
     std::swap(h->cur, h->x);          // cur <- u_{n+1}
     // keep ghosts/covered of the new state consistent
@@ -1948,6 +1938,8 @@ nrd_status nrd_adjoint_run(nrd_hierarchy* h, const double* dt, int32_t nsteps, i
 // residual kernel on that class's patches with every candidate shape
 // ---------------------------------------------------------------------------
 
+}  // extern "C"
+
 namespace {
 
 struct ClassKey {
@@ -1968,6 +1960,8 @@ std::string device_arch() {
 }
 
 }  // namespace
+
+extern "C" {
 
 // Tiles of every patch with the given per-patch shapes, in launch order
 // (level by level); false if some patch has no shape that fits.
@@ -2144,17 +2138,15 @@ nrd_status nrd_autotune(nrd_hierarchy* h, const char* cache_path, int32_t* timed
 static nrd_status set_udot(nrd_hierarchy* h, const double* x) {
     const int np = h->t.nprob;
     hipStream_t s = h->stream;
-    std::vector<double> buf(2 * np), one(np, 1.0);
+    std::vector<double> buf(2 * np);
     for (int p = 0; p < np; ++p) {
         buf[p] = h->c0[p] / h->dt_cur[p];
         buf[np + p] = -1.0 / h->dt_cur[p];
     }
     HIPCHK(up(s, h->coefA, buf));
     h->D.active = nullptr;
-    scale_copy(h->D, s, x, h->coefA, h->udot);
-    HIPCHK(up(s, h->coefB, one));
-    axpby(h->D, s, h->coefA + np, h->bvec, h->coefB, h->udot);
-    HIPCHK(hipStreamSynchronize(s));      // the host coefficient buffers end here
+    lincomb2(h->D, s, h->coefA, x, h->coefA + np, h->bvec, h->udot);
+    HIPCHK(hipStreamSynchronize(s));      // the host coefficient buffer ends here
     return NRD_OK;
 }
 

@@ -536,6 +536,66 @@ void axpby(const Dev& D, hipStream_t s, const double* a, const double* x, const 
     k_axpby<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.active, a, x, b, y, D.nl);
 }
 
+__global__ __launch_bounds__(kBlock) void k_lincomb2(const Tile* __restrict__ vt,
+                                                     const PatchInfo* __restrict__ P,
+                                                     const int32_t* __restrict__ active,
+                                                     const double* __restrict__ a,
+                                                     const double* __restrict__ x,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ w,
+                                                     double* __restrict__ y, int64_t nl) {
+    const Tile t = vt[blockIdx.x];
+    if (active && !active[t.prob]) return;
+    const PatchInfo& p = P[t.patch];
+    const double aa = a[t.prob], bb = b[t.prob];
+    for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+        const int c = interior_index(p, lin);
+        y[c] = bb * w[c] + aa * x[c];
+        y[c + nl] = bb * w[c + nl] + aa * x[c + nl];
+    }
+}
+
+void lincomb2(const Dev& D, hipStream_t s, const double* a, const double* x, const double* b,
+              const double* w, double* y) {
+    k_lincomb2<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.active, a, x, b, w, y, D.nl);
+}
+
+// y = u + A udot + B u_prev + C u, the terms added in that order
+__global__ __launch_bounds__(kBlock) void k_bdf2_predict(const Tile* __restrict__ vt,
+                                                         const PatchInfo* __restrict__ P,
+                                                         const int32_t* __restrict__ active,
+                                                         const double* __restrict__ cf,
+                                                         const double* __restrict__ u,
+                                                         const double* __restrict__ udot,
+                                                         const double* __restrict__ uprev,
+                                                         double* __restrict__ y,
+                                                         double* __restrict__ pred,
+                                                         int nprob, int64_t nl) {
+    const Tile t = vt[blockIdx.x];
+    if (active && !active[t.prob]) return;
+    const PatchInfo& p = P[t.patch];
+    const double A = cf[t.prob], B = cf[nprob + t.prob], C = cf[2 * nprob + t.prob];
+    for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
+        const int c = interior_index(p, lin);
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            const int64_t i = c + f * nl;
+            const double uc = u[i];
+            double v = A * udot[i] + uc;
+            v = B * uprev[i] + v;
+            v = C * uc + v;
+            y[i] = v;
+            if (pred) pred[i] = v;
+        }
+    }
+}
+
+void bdf2_predict(const Dev& D, hipStream_t s, const double* c, const double* u,
+                  const double* udot, const double* uprev, double* y, double* pred) {
+    k_bdf2_predict<<<D.nvtiles, kBlock, 0, s>>>(D.vtiles, D.patches, D.active, c, u, udot,
+                                                uprev, y, pred, D.nprob, D.nl);
+}
+
 __global__ __launch_bounds__(kBlock) void k_scale_copy(const Tile* __restrict__ vt,
                                                        const PatchInfo* __restrict__ P,
                                                        const int32_t* __restrict__ active,
