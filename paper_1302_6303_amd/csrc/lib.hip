@@ -1312,45 +1312,47 @@ static nrd_status implicit_step(nrd_hierarchy* h, const double* dt, nrd_step_sta
     if (rc) return rc;
     // initial guess: leapfrog predictor (BDF2 steps) if positive, else u_n
     h->D.active = nullptr;
-    copy_interior(h->D, s, h->cur, h->x);
     bool any2 = false;
     for (int p = 0; p < np; ++p) any2 |= h->alpha[p] > 0.0;
-    if (any2) {
-        // x = (1 - a^2) u_n + (1 + a) dt u'_n + a^2 u_{n-1}
-        std::vector<double> A(np), B(np), C(np);
+    if (!any2) {
+        copy_interior(h->D, s, h->cur, h->x);
+    } else {
+        // x = (1 - a^2) u_n + (1 + a) dt u'_n + a^2 u_{n-1}; problems taking a
+        // BDF1 step have all three coefficients 0 and get x = u_n
+        std::vector<double> buf(3 * np);
         for (int p = 0; p < np; ++p) {
             const double a = h->alpha[p];
             const bool bdf2 = a > 0.0;
-            A[p] = bdf2 ? (1.0 + a) * dt[p] : 0.0;
-            B[p] = bdf2 ? a * a : 0.0;
-            C[p] = bdf2 ? -a * a : 0.0;
-        }
-        std::vector<double> buf(3 * np);
-        for (int p = 0; p < np; ++p) {
-            buf[p] = A[p];
-            buf[np + p] = B[p];
-            buf[2 * np + p] = C[p];
+            buf[p] = bdf2 ? (1.0 + a) * dt[p] : 0.0;
+            buf[np + p] = bdf2 ? a * a : 0.0;
+            buf[2 * np + p] = bdf2 ? -a * a : 0.0;
         }
         HIPCHK(up(s, h->coefA, buf));
-        // tmp = u_n + A udot + a^2 u_{n-1} - a^2 u_n (and its copy for the
-        // error estimate)
-        bdf2_predict(h->D, s, h->coefA, h->cur, h->udot, h->prev, h->tmp,
+        // written straight into the Newton iterate, with its copy for the
+        // error estimate
+        bdf2_predict(h->D, s, h->coefA, h->cur, h->udot, h->prev, h->x,
                      h->opt.error_estimate ? h->pred : nullptr);
-        // accept per problem if positive
+        // a BDF2 problem whose predictor is not positive starts from u_n
         std::vector<double> zero(np, 0.0), mn(np);
         HIPCHK(up(s, h->coefB, zero));
-        min_positive(h->D, s, h->tmp, h->tmp, h->coefB, h->partial, h->minout);
+        min_positive(h->D, s, h->x, h->x, h->coefB, h->partial, h->minout);
         HIPCHK(hipMemcpyAsync(mn.data(), h->minout, 8 * np, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        std::vector<int32_t> use(np);
-        for (int p = 0; p < np; ++p) use[p] = (h->alpha[p] > 0.0) && mn[p] > 0.0;
-        h->host_active = use;
-        RCHK(upload_active(h));
-        h->D.active = h->active;
-        copy_interior(h->D, s, h->tmp, h->x);
-        h->host_active.assign(np, 1);
-        RCHK(upload_active(h));
-        h->D.active = nullptr;
+        std::vector<int32_t> back(np);
+        bool any_back = false;
+        for (int p = 0; p < np; ++p) {
+            back[p] = (h->alpha[p] > 0.0) && !(mn[p] > 0.0);
+            any_back |= back[p] != 0;
+        }
+        if (any_back) {
+            h->host_active = back;
+            RCHK(upload_active(h));
+            h->D.active = h->active;
+            copy_interior(h->D, s, h->cur, h->x);
+            h->host_active.assign(np, 1);
+            RCHK(upload_active(h));
+            h->D.active = nullptr;
+        }
     }
     std::vector<nrd_step_stats> st;
     rc = newton(h, st);

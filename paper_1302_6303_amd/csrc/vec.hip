@@ -575,15 +575,19 @@ __global__ __launch_bounds__(kBlock) void k_bdf2_predict(const Tile* __restrict_
     if (active && !active[t.prob]) return;
     const PatchInfo& p = P[t.patch];
     const double A = cf[t.prob], B = cf[nprob + t.prob], C = cf[2 * nprob + t.prob];
+    const bool copy = A == 0.0 && B == 0.0 && C == 0.0;      // a BDF1 step: y = u
     for (int lin = t.start + threadIdx.x; lin < t.start + t.count; lin += kBlock) {
         const int c = interior_index(p, lin);
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
             const int64_t i = c + f * nl;
             const double uc = u[i];
-            double v = A * udot[i] + uc;
-            v = B * uprev[i] + v;
-            v = C * uc + v;
+            double v = uc;
+            if (!copy) {
+                v = A * udot[i] + v;
+                v = B * uprev[i] + v;
+                v = C * uc + v;
+            }
             y[i] = v;
             if (pred) pred[i] = v;
         }
