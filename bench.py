@@ -25,7 +25,7 @@ Workloads (seeded, synthetic; --workload):
             at the second step without time-step control)
   dynamic   128^3 base, 4 levels regridded every 5 steps on |grad E|/E > 10
             or a material interface (Berger-Rigoutsos), 50 BDF steps of
-            5e-4, warm restart after each regrid; mixed batched, replayed in
+            1e-5, warm restart after each regrid; mixed batched, replayed in
             float64 batched (solution difference, Krylov counts) and for the
             first 10 steps in float64 per patch
   uniform   one 32^3 patch, dt = 1e-3
