@@ -663,6 +663,45 @@ __global__ __launch_bounds__(kBlock) void k_mg_res_restrict(const int32_t* __res
     }
 }
 
+// The same with one thread per coarse cell (the first grid, where the
+// coarse grid is large): the four children's residuals summed in the
+// order of the lane reduction above, (r_0 + r_3) + (r_5 + r_6).
+template <typename PT, bool SPLIT = false>
+__global__ __launch_bounds__(kBlock) void k_mg_res_restrict1(const int32_t* __restrict__ act,
+    const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pc,
+    const PatchInfo* __restrict__ Pf, const int32_t* __restrict__ fbox,
+    const int32_t* __restrict__ fmap,
+    const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
+    const PT* __restrict__ D, const PT* __restrict__ f, const PT* __restrict__ e, int64_t nlf,
+    PT* __restrict__ fc, int64_t nlc) {
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
+    if ((int)threadIdx.x >= t.count) return;
+    const PatchInfo& pc = Pc[t.patch];
+    const double beta = ps[t.prob].beta;
+    int id[3];
+    coords(pc, t.start + threadIdx.x, id[0], id[1], id[2]);
+    const int cc = nat(pc, id[0], id[1], id[2]);
+    const PatchInfo& pf = Pf[fmap ? fmap[cc] : fbox[t.prob]];
+    PT r0[4], r1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int child = k == 0 ? 0 : (k == 1 ? 3 : (k == 2 ? 5 : 6));
+        const int fid[3] = {2 * id[0] + (child & 1) - pf.lo[0],
+                            2 * id[1] + ((child >> 1) & 1) - pf.lo[1],
+                            2 * id[2] + (child >> 2) - pf.lo[2]};
+        const int c = nat(pf, fid[0], fid[1], fid[2]);
+        int own = c, enb[6];
+        if (SPLIT) split_stencil(pf, fid, own, enb);
+        PT dg[2], ns[2];
+        level_terms<PT, false, SPLIT>(pf, fid, c, beta, ctype, D, e, nlf, dg, ns, enb);
+        r0[k] = f[own] - (dg[0] * e[own] - ns[0]);
+        r1[k] = f[nlf + own] - (dg[1] * e[nlf + own] - ns[1]);
+    }
+    fc[cc] = ((r0[0] + r0[1]) + (r0[2] + r0[3])) * PT(0.125);
+    fc[nlc + cc] = ((r1[0] + r1[1]) + (r1[2] + r1[3])) * PT(0.125);
+}
+
 // multigrid: e_g += trilinear prolongation of e_{g+1} (copy rule at edges)
 template <typename PT>
 __global__ __launch_bounds__(kBlock) void k_mg_prolong(const int32_t* __restrict__ act, 
@@ -1122,7 +1161,11 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
             }
             if (sib) siblings(s, eg, 0);
             if (sp)
-                k_mg_res_restrict<PT, true><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active,
+                k_mg_res_restrict1<PT, true><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active,
+                    mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g], mg.l0map, d.ps, d.ctype,
+                    Dg, fg, eg, nlg, mg.fg[g + 1], mg.len[g + 1]);
+            else if (g == 0)
+                k_mg_res_restrict1<PT><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active,
                     mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g], mg.l0map, d.ps, d.ctype,
                     Dg, fg, eg, nlg, mg.fg[g + 1], mg.len[g + 1]);
             else
