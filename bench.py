@@ -71,9 +71,9 @@ HBM_PEAK_GBS = 8000.0
 # factor; the 20 full launches timed after the steps), valid for the stencil
 # source with this SHA-256 prefix; null otherwise.
 MEASURED_TRAFFIC = {"workload": "ensemble", "stencil_sha256": "c9ec114e166c8b40",
-                    "bytes_per_cell": 62.4317,
-                    "fetch_bytes_per_cell": 45.8374,
-                    "write_bytes_per_cell": 16.5944,
+                    "bytes_per_cell": 63.2710,
+                    "fetch_bytes_per_cell": 46.6790,
+                    "write_bytes_per_cell": 16.5919,
                     "fetch_scale": 2.0, "write_scale": 1.0}
 
 

@@ -107,7 +107,7 @@ struct nrd_hierarchy final : public Clock {
             mg_bprobs[kMaxMG], mg_bboxes[kMaxMG], bot_probs, bot_boxes, bot_grid, bottom_off,
             Lbuf, Xbuf, mg_l0map, ltiles;
         size_t z, z3, cur, prev, udot, bvec, x, F, s, w, tmp, tmp2, gzn, V, Z, pred;
-        size_t pc_D, pc_sigma, pc_e, pc_e2, pc_u, pc_r, pc_f, pc_shadow;
+        size_t pc_D, pc_sigma, pc_T, pc_e, pc_e2, pc_u, pc_r, pc_f, pc_shadow;
         size_t mg_D[kMaxMG], mg_e[kMaxMG], mg_f[kMaxMG];
         size_t partial, dots, h1, h2, hn2, H, cs, sn, g, rho, vscale, y, kdim, coefA, coefB,
             minout, flag, ckpt, fdF, fdw, fdsum;
@@ -296,6 +296,7 @@ static void layout(nrd_hierarchy* h) {
     const size_t es = h->mixed ? 4 : 8;
     o.pc_D = b.take(es * 6 * nl);
     o.pc_sigma = b.take(es * nl);
+    o.pc_T = b.take(es * nl);
     o.pc_e = b.take(es * 2 * nl);
     o.pc_e2 = b.take(h->opt.fac_smoother != NRD_SMOOTH_RBGS || h->opt.fac_cycle == NRD_FAC_AFACX
                          ? es * 2 * nl
@@ -401,6 +402,7 @@ static void wire_pc(nrd_hierarchy* h, PcArrays<PT>& pc) {
     pc.D = &h->D;
     pc.Dface = h->at<PT>(o.pc_D);
     pc.sigma = h->at<PT>(o.pc_sigma);
+    pc.Tp = h->at<PT>(o.pc_T);
     pc.e = h->at<PT>(o.pc_e);
     pc.e2 = h->at<PT>(o.pc_e2);
     pc.u = h->at<PT>(o.pc_u);

@@ -62,6 +62,7 @@ struct PcArrays {
     const Dev* D = nullptr;
     PT* Dface = nullptr;        // 6 * nl: (field * 3 + d) * nl
     PT* sigma = nullptr;        // nl
+    PT* Tp = nullptr;           // nl: T in PT (written by the snapshot when split0)
     PT* e = nullptr;            // 2 * nl each
     PT* u = nullptr;
     PT* r = nullptr;

@@ -37,6 +37,15 @@ __device__ __forceinline__ int nat(const PatchInfo& p, int i, int j, int k) {
 // snapshot: D_E, D_T on every face of every patch, sigma per cell
 // ---------------------------------------------------------------------------
 
+// D_T = kappa T_f^(5/2) of the face between cells of temperatures Ta, Tb
+// (symmetric in Ta, Tb); the sweeps over colour-split storage recompute it
+// from T with this same expression, so they see the snapshot's values.
+template <typename PT>
+__device__ __forceinline__ PT face_DT(PT Ta, PT Tb, PT kappa) {
+    const PT Tf = PT(0.5) * (Ta + Tb);
+    return kappa * Tf * Tf * sqrt(Tf);
+}
+
 // Face coefficients in the preconditioner's precision (the inputs are
 // rounded to PT first; in float64 mode this is the float64 formula).
 template <typename PT>
@@ -47,7 +56,7 @@ __device__ __forceinline__ void face_D(PT Ea, PT Eb, PT Ta, PT Tb, PT za, PT zb,
     const PT S = Ea + Eb;
     // D_h / (1 + lam D_h g) with D_h = 2 Tf^3 / (3 Zf), g = 2|dE| / (h S)
     DE = PT(2) * Tf3 * h * S / (PT(3) * (za + zb) * h * S + PT(4) * lam * Tf3 * fabs(Eb - Ea));
-    DT = kappa * Tf * Tf * sqrt(Tf);
+    DT = face_DT(Ta, Tb, kappa);
 }
 
 template <typename PT>
@@ -55,7 +64,8 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const int32_t* __restrict__
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const double* __restrict__ u,
     const double* __restrict__ z3, PT* __restrict__ Dface, PT* __restrict__ sigma,
-    int64_t nl) {
+    int64_t nl, PT* __restrict__ Tp) {
+    // Tp (may be NULL): T rounded to PT, read by the colour-split sweeps
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
@@ -68,6 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const int32_t* __restrict__
     const PT E = (PT)u[c], T = (PT)u[c + nl], z = (PT)z3[c];
     const PT kappa = (PT)q.kappa, lam = (PT)q.lam;
     sigma[c] = z / (T * T * T);
+    if (Tp) Tp[c] = T;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const PT h = (PT)p.h[d];
@@ -151,13 +162,18 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarsen(const int32_t* __restrict
 // Diagonal dg and neighbour sum ns of both fields at cell c = id (ZERO: the
 // iterate is taken as zero, ns = 0).
 // SPLIT: e in colour-split storage, its neighbours at enb (c indexes the
-// face coefficients and cell types, which stay native).
+// face coefficients and cell types, which stay native), and the T-field
+// coefficient of each face recomputed from Tp (T in PT, native; kappa) in
+// place of reading the three D_T arrays (a box with no siblings or coarse-
+// fine faces: every face that enters is between two of its interior cells).
 template <typename PT, bool ZERO, bool SPLIT = false>
 __device__ __forceinline__ void level_terms(const PatchInfo& p, const int id[3], int c,
                                             double beta, const uint8_t* __restrict__ ctype,
                                             const PT* __restrict__ D, const PT* __restrict__ e,
                                             int64_t nl, PT dgo[2], PT nso[2],
-                                            const int* enb = nullptr) {
+                                            const int* enb = nullptr,
+                                            const PT* __restrict__ Tp = nullptr,
+                                            PT kappa = PT(0)) {
     const int st[3] = {1, p.sy, p.sz};
     PT bh2[3];
     bool ph[6], cf[6];
@@ -185,7 +201,9 @@ __device__ __forceinline__ void level_terms(const PatchInfo& p, const int id[3],
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int fc = 2 * d + s;
-                const PT a = bh2[d] * Dd[s ? c + st[d] : c];
+                const PT a = bh2[d] * ((SPLIT && fld == 1)
+                                           ? face_DT(Tp[c], Tp[s ? c + st[d] : c - st[d]], kappa)
+                                           : Dd[s ? c + st[d] : c]);
                 const PT en = ZERO ? PT(0)
                                    : ef[SPLIT ? enb[fc] : (s ? c + st[d] : c - st[d])];
                 const bool open = !(ph[fc] || cf[fc]);
@@ -217,12 +235,12 @@ __device__ __forceinline__ void level_update(const PatchInfo& p, const int id[3]
                                              const uint8_t* __restrict__ ctype,
                                              const PT* __restrict__ D,
                                              const PT* __restrict__ f, PT* __restrict__ e,
-                                             int64_t nl) {
+                                             int64_t nl, const PT* __restrict__ Tp, PT kappa) {
     const int c = nat(p, id[0], id[1], id[2]);
     int own = c, enb[6];
     if (SPLIT) split_stencil(p, id, own, enb);
     PT dg[2], ns[2];
-    level_terms<PT, MODE == 0, SPLIT>(p, id, c, beta, ctype, D, e, nl, dg, ns, enb);
+    level_terms<PT, MODE == 0, SPLIT>(p, id, c, beta, ctype, D, e, nl, dg, ns, enb, Tp, kappa);
 #pragma unroll
     for (int fld = 0; fld < 2; ++fld) {
         const int64_t cfi = fld * nl + own;
@@ -356,7 +374,8 @@ template <typename PT, int MODE, bool REGION, bool SPLIT>
 __device__ __forceinline__ void level_cell(const PatchInfo& p, const int id[3], double beta,
                                            const uint8_t* __restrict__ ctype,
                                            const PT* __restrict__ D, const PT* __restrict__ f,
-                                           PT* __restrict__ e, int64_t nl) {
+                                           PT* __restrict__ e, int64_t nl,
+                                           const PT* __restrict__ Tp, PT kappa) {
     static_assert(!(REGION && SPLIT), "region sweeps run on native storage");
     if (REGION) {
         const int c = nat(p, id[0], id[1], id[2]);
@@ -366,7 +385,7 @@ __device__ __forceinline__ void level_cell(const PatchInfo& p, const int id[3], 
             return;
         }
     }
-    level_update<PT, MODE, SPLIT>(p, id, beta, ctype, D, f, e, nl);
+    level_update<PT, MODE, SPLIT>(p, id, beta, ctype, D, f, e, nl, Tp, kappa);
 }
 
 // One colour of a red-black sweep (MODE 0: from e = 0), kBlock / 2 threads
@@ -380,11 +399,13 @@ __global__ __launch_bounds__(kBlock) void k_level(const int32_t* __restrict__ ac
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ P,
     const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
     const PT* __restrict__ D, const PT* __restrict__ f, PT* __restrict__ e,
-    int colour, int64_t nl) {
+    int colour, int64_t nl, const PT* __restrict__ Tp = nullptr) {
+    // Tp: T in PT (SPLIT only; the T-field face coefficients)
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     const PatchInfo& p = P[t.patch];
     const double beta = ps[t.prob].beta;
+    const PT kappa = (PT)ps[t.prob].kappa;
     int id[3];
     const int lo = p.lo[0] + p.lo[1] + p.lo[2];
     if ((p.n[0] & 1) == 0) {
@@ -392,12 +413,12 @@ __global__ __launch_bounds__(kBlock) void k_level(const int32_t* __restrict__ ac
         if (a >= t.count) return;
         coords(p, t.start + a, id[0], id[1], id[2]);  // id[0] even
         id[0] += (colour + id[1] + id[2] + lo) & 1;
-        level_cell<PT, MODE, REGION, SPLIT>(p, id, beta, ctype, D, f, e, nl);
+        level_cell<PT, MODE, REGION, SPLIT>(p, id, beta, ctype, D, f, e, nl, Tp, kappa);
     } else if (!SPLIT) {
         for (int q = threadIdx.x; q < t.count; q += kBlock / 2) {
             coords(p, t.start + q, id[0], id[1], id[2]);
             if (((id[0] + id[1] + id[2] + lo) & 1) != colour) continue;
-            level_cell<PT, MODE, REGION, false>(p, id, beta, ctype, D, f, e, nl);
+            level_cell<PT, MODE, REGION, false>(p, id, beta, ctype, D, f, e, nl, Tp, kappa);
         }
     }
 }
@@ -625,11 +646,12 @@ __global__ __launch_bounds__(kBlock) void k_mg_res_restrict(const int32_t* __res
     const int32_t* __restrict__ fmap,
     const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
     const PT* __restrict__ D, const PT* __restrict__ f, const PT* __restrict__ e, int64_t nlf,
-    PT* __restrict__ fc, int64_t nlc) {
+    PT* __restrict__ fc, int64_t nlc, const PT* __restrict__ Tp = nullptr) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // uniform over the workgroup
     const PatchInfo& pc = Pc[t.patch];
     const double beta = ps[t.prob].beta;
+    const PT kappa = (PT)ps[t.prob].kappa;
     // colour-0 children (bit 0: x, 1: y, 2: z offset)
     const int lane = threadIdx.x & 3;
     const int child = lane == 0 ? 0 : (lane == 1 ? 3 : (lane == 2 ? 5 : 6));
@@ -648,7 +670,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_res_restrict(const int32_t* __res
             int own = c, enb[6];
             if (SPLIT) split_stencil(pf, fid, own, enb);
             PT dg[2], ns[2];
-            level_terms<PT, false, SPLIT>(pf, fid, c, beta, ctype, D, e, nlf, dg, ns, enb);
+            level_terms<PT, false, SPLIT>(pf, fid, c, beta, ctype, D, e, nlf, dg, ns, enb, Tp,
+                                          kappa);
             v0 = f[own] - (dg[0] * e[own] - ns[0]);
             v1 = f[nlf + own] - (dg[1] * e[nlf + own] - ns[1]);
         }
@@ -673,12 +696,13 @@ __global__ __launch_bounds__(kBlock) void k_mg_res_restrict1(const int32_t* __re
     const int32_t* __restrict__ fmap,
     const ProbScalars* __restrict__ ps, const uint8_t* __restrict__ ctype,
     const PT* __restrict__ D, const PT* __restrict__ f, const PT* __restrict__ e, int64_t nlf,
-    PT* __restrict__ fc, int64_t nlc) {
+    PT* __restrict__ fc, int64_t nlc, const PT* __restrict__ Tp = nullptr) {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
     const PatchInfo& pc = Pc[t.patch];
     const double beta = ps[t.prob].beta;
+    const PT kappa = (PT)ps[t.prob].kappa;
     int id[3];
     coords(pc, t.start + threadIdx.x, id[0], id[1], id[2]);
     const int cc = nat(pc, id[0], id[1], id[2]);
@@ -694,7 +718,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_res_restrict1(const int32_t* __re
         int own = c, enb[6];
         if (SPLIT) split_stencil(pf, fid, own, enb);
         PT dg[2], ns[2];
-        level_terms<PT, false, SPLIT>(pf, fid, c, beta, ctype, D, e, nlf, dg, ns, enb);
+        level_terms<PT, false, SPLIT>(pf, fid, c, beta, ctype, D, e, nlf, dg, ns, enb, Tp,
+                                      kappa);
         r0[k] = f[own] - (dg[0] * e[own] - ns[0]);
         r1[k] = f[nlf + own] - (dg[1] * e[nlf + own] - ns[1]);
     }
@@ -1089,7 +1114,7 @@ void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
     const Dev& d = *D;
     const int ntiles = d.level_tile0[d.nlev];
     k_snapshot<PT><<<ntiles, kBlock, 0, s>>>(d.active, d.tiles, d.patches, d.ps, u_state, d.z3, Dface,
-                                            sigma, d.nl);
+                                            sigma, d.nl, split0 ? Tp : nullptr);
     if (base_smooth) return;                   // no multigrid grids to set up
     for (int g = 1; g <= mg.G; ++g) {
         const PT* Df = (g == 1) ? Dface : mg.Dg[g - 1];
@@ -1126,10 +1151,10 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
         if (g == 0 && split0) {
             if (zero)
                 k_level<PT, 0, false, true><<<nt, kBlock / 2, 0, s>>>(
-                    d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, colour, nlg);
+                    d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, colour, nlg, Tp);
             else
                 k_level<PT, 1, false, true><<<nt, kBlock / 2, 0, s>>>(
-                    d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, colour, nlg);
+                    d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg, colour, nlg, Tp);
         } else if (zero) {
             k_level<PT, 0><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, d.ps, d.ctype, Dg, fg, eg,
                                                      colour, nlg);
@@ -1163,7 +1188,7 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
             if (sp)
                 k_mg_res_restrict1<PT, true><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active,
                     mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g], mg.l0map, d.ps, d.ctype,
-                    Dg, fg, eg, nlg, mg.fg[g + 1], mg.len[g + 1]);
+                    Dg, fg, eg, nlg, mg.fg[g + 1], mg.len[g + 1], Tp);
             else if (g == 0)
                 k_mg_res_restrict1<PT><<<mg.ntiles[g + 1], kBlock, 0, s>>>(d.active,
                     mg.tiles[g + 1], mg.box[g + 1], Pg, mg.box_of[g], mg.l0map, d.ps, d.ctype,
