@@ -769,6 +769,65 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(const int32_t* __restrict
     }
 }
 
+// The same on the colour-split base grid (even x extents, boxes at even
+// level indices), kBlock / 2 threads per tile: thread q takes the cell pair
+// (2q, 2q + 1) of a row, which shares its coarse x cell, reads the twelve
+// coarse values the two cells use once and updates both cells, each with
+// the weights and summation order above.
+template <typename PT>
+__global__ __launch_bounds__(kBlock) void k_mg_prolong2(const int32_t* __restrict__ act,
+    const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pf,
+    const PatchInfo* __restrict__ Pc, const int32_t* __restrict__ cbox,
+    const PT* __restrict__ ec, int64_t nlc, PT* __restrict__ ef, int64_t nlf) {
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    if (act && !act[t.prob]) return;           // problem not being solved
+    const int a0 = 2 * (int)threadIdx.x;       // tile starts are even
+    if (a0 >= t.count) return;
+    const PatchInfo& pf = Pf[t.patch];
+    const PatchInfo& pc = Pc[cbox[t.prob]];
+    int id[3];
+    coords(pf, t.start + a0, id[0], id[1], id[2]);    // id[0] even
+    int q[3], nbq[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int I = pf.lo[d] + id[d];
+        q[d] = I >> 1;
+        const int o = (I & 1) ? 1 : -1;
+        nbq[d] = min(max(q[d] + o, 0), pc.n[d] - 1);
+    }
+    const int xm = max(q[0] - 1, 0), xp = min(q[0] + 1, pc.n[0] - 1);
+    const int c0 = split_index(pf, id[0] + 1, id[1] + 1, id[2] + 1);
+    const int c1 = split_index(pf, id[0] + 2, id[1] + 1, id[2] + 1);
+    for (int fld = 0; fld < 2; ++fld) {
+        const PT* s = ec + fld * nlc;
+        PT R[3][2][2];                         // x: q - 1, q, q + 1; y, z: q, neighbour
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+                const int y = b ? nbq[1] : q[1], z = cc ? nbq[2] : q[2];
+                R[0][b][cc] = s[nat(pc, xm, y, z)];
+                R[1][b][cc] = s[nat(pc, q[0], y, z)];
+                R[2][b][cc] = s[nat(pc, xp, y, z)];
+            }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {          // k = 0: even fine x (neighbour q - 1)
+            PT v = PT(0);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc) {
+                        const PT w = (a ? PT(0.25) : PT(0.75)) * (b ? PT(0.25) : PT(0.75)) *
+                                     (cc ? PT(0.25) : PT(0.75));
+                        v += w * R[a ? (k ? 2 : 0) : 1][b][cc];
+                    }
+            ef[fld * nlf + (k ? c1 : c0)] += v;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // bottom solve (float64).  The coarsest grid's operator is SPD and banded:
 // setup factors it as L L^T (band Cholesky; cells numbered with the longest
@@ -1213,9 +1272,13 @@ void PcArrays<PT>::vcycle(hipStream_t s) const {
         const PT* Dg = (g == 0) ? Dface : mg.Dg[g];
         const Tile* tl = mg.smooth_tiles[g];
         const int nt = mg.nsmooth[g];
-        k_mg_prolong<PT><<<nt, kBlock, 0, s>>>(d.active, tl, Pg, mg.box[g + 1], mg.box_of[g + 1],
-                                              mg.eg[g + 1], mg.len[g + 1], eg, nlg,
-                                              (g == 0 && split0) ? 1 : 0);
+        if (g == 0 && split0)
+            k_mg_prolong2<PT><<<nt, kBlock / 2, 0, s>>>(d.active, tl, Pg, mg.box[1], mg.box_of[1],
+                                                        mg.eg[1], mg.len[1], eg, nlg);
+        else
+            k_mg_prolong<PT><<<nt, kBlock, 0, s>>>(d.active, tl, Pg, mg.box[g + 1],
+                                                  mg.box_of[g + 1], mg.eg[g + 1], mg.len[g + 1],
+                                                  eg, nlg, 0);
         const bool sib = g == 0 && mg.multi0;
         for (int it = 0; it < nu_post; ++it) {
             std::pair<hipEvent_t, hipEvent_t> tk{nullptr, nullptr};
