@@ -1134,7 +1134,8 @@ def main():
                          "avg_launch_ms": round(mixed["jvp_ms_avg"], 4)},
         "smoother_roofline": {
             "kernel": "k_level<float> (red-black sweep of the base grid, one launch per colour, "
-                      "colour-split iterate and right-hand side)",
+                      "colour-split iterate and right-hand side, T-field face coefficients "
+                      "recomputed from T)",
             "cells": base_cells, "bytes_per_cell": BYTES_PER_CELL_SWEEP,
             "achieved": gbs(BYTES_PER_CELL_SWEEP * base_cells, mixed["sweep_ms_avg"]),
             "unit": "GB/s",
