@@ -55,6 +55,7 @@ struct BottomGrids {
     const PatchInfo* P[kMaxMG] = {};
     const PT* D[kMaxMG] = {};
     int64_t nl[kMaxMG] = {};
+    const PT* T0 = nullptr;     // grid 0's T in PT when its D_T arrays are not stored
 };
 
 template <typename PT>

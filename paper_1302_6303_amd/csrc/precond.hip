@@ -65,7 +65,8 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const int32_t* __restrict__
     const ProbScalars* __restrict__ ps, const double* __restrict__ u,
     const double* __restrict__ z3, PT* __restrict__ Dface, PT* __restrict__ sigma,
     int64_t nl, PT* __restrict__ Tp) {
-    // Tp (may be NULL): T rounded to PT, read by the colour-split sweeps
+    // Tp (may be NULL): T rounded to PT; when given, the three D_T arrays
+    // are not written (every reader recomputes D_T from Tp with face_DT)
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(const int32_t* __restrict__
                     face_D<PT>(En, E, Tn, T, zn, z, h, kappa, lam, DE, DT);
             }
             Dface[(0 * 3 + d) * nl + slot] = DE;
-            Dface[(1 * 3 + d) * nl + slot] = DT;
+            if (!Tp) Dface[(1 * 3 + d) * nl + slot] = DT;
         }
     }
 }
@@ -115,7 +116,11 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarsen(const int32_t* __restrict
     const Tile* __restrict__ tiles, const PatchInfo* __restrict__ Pc,
     const PatchInfo* __restrict__ Pf, const int32_t* __restrict__ fbox,
     const int32_t* __restrict__ fmap,
-    const PT* __restrict__ Df, int64_t nlf, PT* __restrict__ Dc, int64_t nlc) {
+    const PT* __restrict__ Df, int64_t nlf, PT* __restrict__ Dc, int64_t nlc,
+    const PT* __restrict__ Tp, const ProbScalars* __restrict__ ps) {
+    // Tp (may be NULL; the first grid of a colour-split base, one box
+    // covering the domain): the fine D_T recomputed from T with face_DT,
+    // 0 on the domain boundary, as the snapshot computes them
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if (act && !act[t.prob]) return;           // problem not being solved
     if ((int)threadIdx.x >= t.count) return;
@@ -124,6 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarsen(const int32_t* __restrict
     coords(pc, t.start + threadIdx.x, id[0], id[1], id[2]);
     const int c = nat(pc, id[0], id[1], id[2]);
     const PatchInfo& pf = Pf[fmap ? fmap[c] : fbox[t.prob]];
+    const PT kappa = Tp ? (PT)ps[t.prob].kappa : PT(0);
     const int stc[3] = {1, pc.sy, pc.sz};
     const int stf[3] = {1, pf.sy, pf.sz};
     const int f0 = nat(pf, 2 * id[0] - pf.lo[0], 2 * id[1] - pf.lo[1], 2 * id[2] - pf.lo[2]);
@@ -137,9 +143,20 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarsen(const int32_t* __restrict
             const int slot = s ? c + stc[d] : c;
             const int fs = s ? f0 + 2 * stf[d] : f0;
             for (int fld = 0; fld < 2; ++fld) {
-                const PT* src = Df + (fld * 3 + d) * nlf;
-                const PT v = (src[fs] + src[fs + stf[t1]]) + (src[fs + stf[t2]] +
-                                                              src[fs + stf[t1] + stf[t2]]);
+                PT v;
+                if (fld == 1 && Tp) {
+                    // the low face of fine cell x lies between x - st and x
+                    const bool edge = s ? true : id[d] == 0;
+                    const int o = stf[d];
+                    auto dt = [&](int x) { return face_DT(Tp[x - o], Tp[x], kappa); };
+                    v = edge ? PT(0)
+                             : (dt(fs) + dt(fs + stf[t1])) +
+                                   (dt(fs + stf[t2]) + dt(fs + stf[t1] + stf[t2]));
+                } else {
+                    const PT* src = Df + (fld * 3 + d) * nlf;
+                    v = (src[fs] + src[fs + stf[t1]]) + (src[fs + stf[t2]] +
+                                                          src[fs + stf[t1] + stf[t2]]);
+                }
                 Dc[(fld * 3 + d) * nlc + slot] = v * PT(0.25);
             }
         }
@@ -902,6 +919,9 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom_setup(const int32_t* 
     const PT* __restrict__ D = G.D[g];
     const int64_t nl = G.nl[g];
     const double beta = ps[prob].beta;
+    // grid 0 without stored D_T: the T-field coefficients from T
+    const PT* __restrict__ T0 = (g == 0 && fld == 1) ? G.T0 : nullptr;
+    const PT kappa = (PT)ps[prob].kappa;
     const int N = p.ncell;                      // <= kBottomMax (checked on the host)
     const BottomOrder o = bottom_order(p);
     const int b = o.b;                          // < kBandLd (checked on the host)
@@ -920,12 +940,16 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom_setup(const int32_t* 
             const PT* Dd = D + (fld * 3 + d) * nl;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const double Dv = (double)Dd[s ? c + st[d] : c];
                 if (id[d] == (s ? p.n[d] - 1 : 0)) {        // grid covers the domain
-                    if (fld == 0 && ((p.robin >> (2 * d + s)) & 1))
+                    if (fld == 0 && ((p.robin >> (2 * d + s)) & 1)) {
+                        const double Dv = (double)Dd[s ? c + st[d] : c];
                         dg += 2.0 * beta * Dv / ((4.0 * Dv + p.h[d]) * p.h[d]);
+                    }
                     continue;
                 }
+                const int nb = s ? c + st[d] : c - st[d];
+                const double Dv = T0 ? (double)face_DT(T0[c], T0[nb], kappa)
+                                     : (double)Dd[s ? c + st[d] : c];
                 const double a = bh2 * Dv;
                 dg += a;
                 // the lower neighbour's entry; the upper one is that
@@ -1182,7 +1206,9 @@ void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
         k_mg_coarsen<PT><<<mg.ntiles[g], kBlock, 0, s>>>(d.active, mg.tiles[g], mg.box[g], Pf,
                                                          mg.box_of[g - 1],
                                                          g == 1 ? mg.l0map : nullptr, Df, nlf,
-                                                         mg.Dg[g], mg.len[g]);
+                                                         mg.Dg[g], mg.len[g],
+                                                         (g == 1 && split0) ? Tp : nullptr,
+                                                         d.ps);
     }
     // every problem's coarsest grid in one launch
     BottomGrids<PT> bg;
@@ -1190,6 +1216,7 @@ void PcArrays<PT>::setup(hipStream_t s, const double* u_state) const {
         bg.P[g] = (g == 0) ? d.patches : mg.box[g];
         bg.D[g] = (g == 0) ? Dface : mg.Dg[g];
         bg.nl[g] = (g == 0) ? d.nl : mg.len[g];
+        bg.T0 = split0 ? Tp : nullptr;
     }
     if (mg.nbot_all > 0)
         k_bottom_setup<PT><<<2 * mg.nbot_all, kBottomThreads, 0, s>>>(
