@@ -398,6 +398,46 @@ def test_precond_parity_fac_base_smoothing(name, nu):
         assert rel_err(got[sl][mm], ref[sl][mm]) < 1e-10
 
 
+def _batch(parts, name):
+    problems, boxes, z, E, T, dts = [], [], [], [], [], []
+    for p, wp in enumerate(parts):
+        problems.append(wp.problems[0])
+        b = wp.boxes[0]
+        boxes.append(I.Box(p, 0, b.lo, b.hi))
+        z.append(wp.z[0])
+        E.append(wp.E[0])
+        T.append(wp.T[0])
+        dts.append(float(wp.dt[0]))
+    return I.Workload(name, problems, boxes, z, E, T, np.array(dts))
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_colour_split_storage_is_bitwise_native(precision):
+    """The base grid's colour-split storage (single-level problems of even x
+    extent) with the T-field coefficients recomputed from T gives bit for
+    bit the preconditioner of the native storage: the same problem batched
+    beside an odd-extent problem (which turns the colour-split storage off
+    for the hierarchy) yields the same output, in float and in double."""
+    from tests.gpu_helpers import problem_slices
+    a = I.marshak_single(16, state="front")
+    b = _batch([a, odd_workload()], "split_off")
+    w_a = np.random.default_rng(14).standard_normal(2 * a.ncells())
+    outs = []
+    for w in (a, b):
+        H = make(w, precision=precision)
+        H.begin_step([float(x) for x in w.dt])
+        u = compact_state(w)
+        sl = problem_slices(w)[0]
+        wv = np.random.default_rng(15).standard_normal(u.shape)
+        wv[sl] = w_a                            # the same vector for problem 0
+        H.precond_setup(native_from_compact(H, u))
+        y = H.native()
+        H.precond_apply(native_from_compact(H, wv), y)
+        outs.append(compact_from_native(H, y)[sl])
+    assert np.array_equal(outs[0], outs[1]), \
+        np.abs(outs[0] - outs[1]).max() / np.abs(outs[1]).max()
+
+
 @pytest.mark.parametrize("wl", [boxes_workload, tiny_workload])
 def test_precond_parity_noncubic(wl):
     """Preconditioner of three non-cubic problems in one hierarchy, each
