@@ -106,7 +106,10 @@ typedef struct {
                                per patch (same kernels, same results)       */
     int32_t use_graph;      /* 1: capture each FGMRES iteration (precond,
                                Jacobian action, CGS2, Givens) as a HIP graph
-                               on first use and replay it                    */
+                               on first use and replay it on the library
+                               stream (results bitwise those of direct
+                               launches; pays off when launches dominate,
+                               e.g. a single problem of 32^3)                */
     int32_t jvp_mode;       /* analytic Jacobian action or finite difference  */
     double limiter;         /* lambda in D_h / (1 + lambda D_h |dE|/(h E_f));
                                0.5 = the printed pair (default), 1 = Wilson  */

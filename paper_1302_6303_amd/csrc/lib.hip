@@ -151,11 +151,10 @@ struct nrd_hierarchy final : public Clock {
     // point (the iterate's buffer rotates with the time-step history) and
     // Krylov index, captured on first use when use_graph is set
     std::map<std::tuple<int, const void*, int>, hipGraphExec_t> graphs;
-    hipStream_t cap_stream = nullptr;  // graphs are captured and launched here
-                                       // (the caller's stream may be the legacy
-                                       // null stream), ordered with the
-                                       // caller's stream by two events
-    hipEvent_t gev_in = nullptr, gev_out = nullptr;
+    hipStream_t cap_stream = nullptr;  // graphs are captured here (the
+                                       // library stream may be the legacy
+                                       // null stream) and replayed on the
+                                       // library stream
     void drop_graphs() {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
         graphs.clear();
@@ -1005,8 +1004,6 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
                     (transpose ? 1 : 0) + (v0_lazy ? 2 : 0), (const void*)u, j)];
                 if (!h->cap_stream) {
                     HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-                    HIPCHK(hipEventCreateWithFlags(&h->gev_in, hipEventDisableTiming));
-                    HIPCHK(hipEventCreateWithFlags(&h->gev_out, hipEventDisableTiming));
                 }
                 if (!ge) {
                     const bool timing = h->timing;
@@ -1027,11 +1024,8 @@ static nrd_status fgmres(nrd_hierarchy* h, double* u, const double* rhs, double*
                     (void)hipGraphDestroy(graph);
                     HIPCHK(ei);
                 }
-                HIPCHK(hipEventRecord(h->gev_in, s));
-                HIPCHK(hipStreamWaitEvent(h->cap_stream, h->gev_in, 0));
-                HIPCHK(hipGraphLaunch(ge, h->cap_stream));
-                HIPCHK(hipEventRecord(h->gev_out, h->cap_stream));
-                HIPCHK(hipStreamWaitEvent(s, h->gev_out, 0));
+                // captured on its own stream, replayed on the library stream
+                HIPCHK(hipGraphLaunch(ge, s));
             } else {
                 iteration();
             }
@@ -1712,8 +1706,6 @@ nrd_status nrd_hierarchy_destroy(nrd_hierarchy* h) {
     if (!h) return NRD_OK;
     h->drop_graphs();
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
-    if (h->gev_in) (void)hipEventDestroy(h->gev_in);
-    if (h->gev_out) (void)hipEventDestroy(h->gev_out);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     delete h;
     return NRD_OK;
