@@ -362,7 +362,15 @@ static bool split0_ok(const Tables& t, bool base_smooth) {
         shapes[std::make_tuple(p.n[0], p.n[1], p.n[2], p.sy, p.sz,
                                (p.lo[0] + p.lo[1] + p.lo[2]) & 1)] = true;
     }
+    // shapes already checked in this process (hierarchies are often rebuilt
+    // with the same boxes)
+    static std::mutex checked_mu;
+    static std::map<std::tuple<int, int, int, int, int, int>, bool> checked;
     for (const auto& kv : shapes) {
+        {
+            std::lock_guard<std::mutex> lk(checked_mu);
+            if (checked.count(kv.first)) continue;
+        }
         PatchInfo q;
         std::memset(&q, 0, sizeof(q));
         std::tie(q.n[0], q.n[1], q.n[2], q.sy, q.sz, q.lo[0]) = kv.first;
@@ -390,6 +398,8 @@ static bool split0_ok(const Tables& t, bool base_smooth) {
                         nb[5] != split_index(q, x, y, z + 1))
                         return false;
                 }
+        std::lock_guard<std::mutex> lk(checked_mu);
+        checked[kv.first] = true;
     }
     return true;
 }
